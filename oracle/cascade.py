@@ -1,0 +1,415 @@
+"""Plain FP64 CPU oracle for cascading-smoother multigrid (Saye, "Cascading
+Smoothers for Multigrid", arXiv 2606.12577).
+
+TEST INFRASTRUCTURE ONLY: used by tests/, the smoke check and the benchmark's
+CPU-baseline leg.  It shares no code with the HIP library.
+
+Every function writes out the definition it implements, in the paper's
+notation, with dense or scipy.sparse library products as the only building
+blocks.  Nothing is blocked, fused or reordered beyond the definitions.
+
+Conventions
+-----------
+* A is a scalar CSR matrix; block i owns scalar rows [i*n, (i+1)*n).
+* A block-diagonal Lambda is stored as an array of shape (B, n, n).
+* Vectors are (N, R) arrays: R right-hand sides side by side.
+* Structural block patterns (which blocks of E may be non-zero) are kept as
+  boolean B x B CSR matrices; numerical cancellation never removes a block
+  from a structural pattern.
+
+Readings taken where the paper leaves a choice open
+---------------------------------------------------
+* Least squares per block (Sec. 2.1, Alg. 2): the normal equations
+  Lambda_i G_i = H_i with G_i = M_i M_i^T, H_i = E_i M_i^T, M = A E, solved
+  as the minimum-norm least-squares solution (pseudo-inverse of G_i with a
+  relative cut-off of 1e-13; identical to H_i G_i^{-1} whenever G_i is SPD).
+* Prescaling (Sec. 2.3, elliptic): W = diag(a_kk^{-1/2}) over the scalar
+  diagonal of A.
+* Multiplicative construction (Sec. 2.2): every block of colour k is fitted
+  from the same E (the state before the colour-k update), then the colour-k
+  rows are updated; colours are swept in ascending id.
+* Reverse application (Sec. 2.4): the cascade is applied in the order
+  Lambda_nu^T, ..., Lambda_1^T (the index printed in the reverse formulas is
+  off by two; the supplementary symmetry section fixes this order).
+* Truncation (Alg. 2, optional step): keep the alpha blocks of largest
+  Frobenius norm in each updated block row of E; ties go to the lower block
+  column.
+"""
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+import scipy.sparse as sp
+
+PINV_RCOND = 1e-13
+
+
+# ---------------------------------------------------------------------------
+# Block helpers (pure bookkeeping)
+# ---------------------------------------------------------------------------
+
+def aggregator(N: int, n: int) -> sp.csr_matrix:
+    """B x N 0/1 matrix summing the n scalar rows of each block."""
+    return sp.csr_matrix((np.ones(N), (np.arange(N) // n, np.arange(N))), shape=(N // n, N))
+
+
+def block_pattern(X: sp.spmatrix, n: int) -> sp.csr_matrix:
+    """Structural block pattern of X (every stored entry counts)."""
+    Xs = sp.csr_matrix(X, copy=True)
+    Xs.data[:] = 1.0
+    Q = aggregator(X.shape[0], n)
+    P = (Q @ Xs @ Q.T).tocsr()
+    P.data[:] = 1.0
+    P.sort_indices()
+    return P.astype(bool)
+
+
+def pattern_product(P1: sp.csr_matrix, P2: sp.csr_matrix) -> sp.csr_matrix:
+    """Structural pattern of a product of two block-sparse matrices."""
+    R = (P1.astype(np.float64) @ P2.astype(np.float64)).tocsr()
+    R.data[:] = 1.0
+    R.sort_indices()
+    return R.astype(bool)
+
+
+def blockdiag(blocks: np.ndarray) -> sp.csr_matrix:
+    B, n, _ = blocks.shape
+    return sp.bsr_matrix((blocks, np.arange(B), np.arange(B + 1)), shape=(B * n, B * n)).tocsr()
+
+
+def blockdiag_of_product(X: sp.spmatrix, Y: sp.spmatrix, n: int) -> np.ndarray:
+    """Z[i] = X_i Y_i^T, X_i being the n x N block row i of X."""
+    X = sp.csr_matrix(X)
+    Y = sp.csr_matrix(Y)
+    B = X.shape[0] // n
+    Z = np.empty((B, n, n))
+    for r in range(n):
+        Xr = X[r::n]
+        for s in range(n):
+            Z[:, r, s] = np.asarray(Xr.multiply(Y[s::n]).sum(axis=1)).ravel()
+    return Z
+
+
+def block_rows(blocks: Sequence[int], n: int) -> np.ndarray:
+    b = np.asarray(blocks, dtype=np.int64)
+    return (b[:, None] * n + np.arange(n)[None, :]).ravel()
+
+
+# ---------------------------------------------------------------------------
+# Setup (Sec. 2.1-2.3, Alg. 2, supplementary multicoloured algorithm)
+# ---------------------------------------------------------------------------
+
+def prescale(A: sp.spmatrix):
+    """Elliptic prescaling (Sec. 2.3): W = diag(A_kk^{-1/2}); returns (w, W A W)."""
+    d = A.diagonal()
+    if np.any(d <= 0):
+        raise ValueError("elliptic prescaling needs a positive diagonal")
+    w = 1.0 / np.sqrt(d)
+    W = sp.diags(w)
+    return w, (W @ A @ W).tocsr()
+
+
+def least_squares_blocks(H: np.ndarray, G: np.ndarray) -> np.ndarray:
+    """Minimum-norm solution Lambda_i of Lambda_i M_i = E_i via its normal
+    equations Lambda_i G_i = H_i (Alg. 2, least-squares step)."""
+    out = np.empty_like(H)
+    for i in range(G.shape[0]):
+        out[i] = H[i] @ np.linalg.pinv(G[i], rcond=PINV_RCOND, hermitian=True)
+    return out
+
+
+def truncate_rows(E: sp.csr_matrix, Epat: sp.csr_matrix, n: int, alpha: int,
+                  rows: np.ndarray):
+    """Keep the alpha blocks of largest Frobenius norm in the given block rows of
+    E (ties -> lower block column); other rows are left as they are."""
+    Q = aggregator(E.shape[0], n)
+    S = (Q @ E.multiply(E) @ Q.T).tocsr()
+    Epat = Epat.tocsr()
+    keep_r, keep_c = [], []
+    rowset = np.zeros(Epat.shape[0], dtype=bool)
+    rowset[rows] = True
+    for i in range(Epat.shape[0]):
+        cols = Epat.indices[Epat.indptr[i]:Epat.indptr[i + 1]]
+        if rowset[i] and len(cols) > alpha:
+            norms = np.sqrt(np.asarray(S[i, cols].todense()).ravel())
+            order = sorted(range(len(cols)), key=lambda t: (-norms[t], cols[t]))
+            cols = np.sort(cols[order[:alpha]])
+        keep_r.append(np.full(len(cols), i))
+        keep_c.append(cols)
+    r = np.concatenate(keep_r)
+    c = np.concatenate(keep_c)
+    K = sp.csr_matrix((np.ones(len(r)), (r, c)), shape=Epat.shape)
+    K.sort_indices()
+    mask = (Q.T @ K @ Q).tocsr()
+    return E.multiply(mask).tocsr(), K.astype(bool)
+
+
+def unscale(lam_t: np.ndarray, w: np.ndarray) -> np.ndarray:
+    """Lambda <- W Lambda W (Alg. 2, final step)."""
+    B, n, _ = lam_t.shape
+    wb = w.reshape(B, n)
+    return wb[:, :, None] * lam_t * wb[:, None, :]
+
+
+def fit_additive(A: sp.spmatrix, n: int, depth: int, alpha: Optional[int] = None) -> Dict:
+    """Depth-nu additive cascade (Sec. 2.1, Alg. 2).
+
+    Lambda_l = argmin_{Lambda block-diagonal} ||(I - Lambda A~) E_{l-1}||_F,
+    E_l = (I - Lambda_l A~) E_{l-1}, E_0 = I, on the prescaled A~ = W A W.
+    Returns lam (unscaled, list over l), lam_tilde, w, and the structural block
+    patterns of E_0 .. E_{nu-1}."""
+    A = sp.csr_matrix(A)
+    N = A.shape[0]
+    B = N // n
+    w, At = prescale(A)
+    Apat = block_pattern(At, n)
+    E = sp.identity(N, format="csr")
+    Epat = sp.identity(B, format="csr", dtype=bool)
+    lam_t, pats = [], [Epat]
+    for ell in range(1, depth + 1):
+        M = (At @ E).tocsr()
+        G = blockdiag_of_product(M, M, n)
+        H = blockdiag_of_product(E, M, n)
+        Lt = least_squares_blocks(H, G)
+        lam_t.append(Lt)
+        if ell < depth:
+            E = (E - blockdiag(Lt) @ M).tocsr()
+            Epat = pattern_product(Apat, Epat)
+            if alpha:
+                E, Epat = truncate_rows(E, Epat, n, alpha, np.arange(B))
+            pats.append(Epat)
+    return dict(lam=[unscale(L, w) for L in lam_t], lam_tilde=lam_t, w=w, patterns=pats,
+                colours=None)
+
+
+def fit_multiplicative(A: sp.spmatrix, n: int, depth: int, colours: np.ndarray,
+                       alpha: Optional[int] = None) -> Dict:
+    """Depth-nu multicoloured cascade (Sec. 2.2).
+
+    For l = 1..nu and colours k in ascending order,
+    Lambda_{l,k} = argmin_{Lambda in D_k} ||(I - Lambda A~) E_{l,k-1}||_F and
+    E_{l,k} = (I - Lambda_{l,k} A~) E_{l,k-1}, continuing E across levels.
+    lam[l][i] holds the block of Lambda_{l, colour(i)}.  The returned
+    patterns are those of E after every colour step, in sweep order."""
+    A = sp.csr_matrix(A)
+    N = A.shape[0]
+    B = N // n
+    colours = np.asarray(colours, dtype=np.int64)
+    chi = int(colours.max()) + 1
+    w, At = prescale(A)
+    Apat = block_pattern(At, n)
+    E = sp.identity(N, format="csr")
+    Epat = sp.identity(B, format="csr", dtype=bool)
+    lam_t = [np.zeros((B, n, n)) for _ in range(depth)]
+    pats = [Epat]
+    for ell in range(1, depth + 1):
+        for k in range(chi):
+            blocks = np.flatnonzero(colours == k)
+            if len(blocks) == 0:
+                continue
+            sel = block_rows(blocks, n)
+            M = (At @ E).tocsr()
+            Mk, Ek = M[sel], E[sel]
+            G = blockdiag_of_product(Mk, Mk, n)
+            H = blockdiag_of_product(Ek, Mk, n)
+            Lt = least_squares_blocks(H, G)
+            lam_t[ell - 1][blocks] = Lt
+            if ell < depth or k < chi - 1:
+                D = np.zeros((B, n, n))
+                D[blocks] = Lt
+                E = (E - blockdiag(D) @ M).tocsr()
+                grown = pattern_product(Apat, Epat)
+                mask = sp.diags((colours == k).astype(np.float64))
+                keep = sp.diags((colours != k).astype(np.float64))
+                Epat = (keep @ Epat.astype(np.float64) + mask @ grown.astype(np.float64)).tocsr()
+                Epat.eliminate_zeros()
+                Epat.data[:] = 1.0
+                Epat.sort_indices()
+                Epat = Epat.astype(bool)
+                if alpha:
+                    E, Epat = truncate_rows(E, Epat, n, alpha, blocks)
+                pats.append(Epat)
+    return dict(lam=[unscale(L, w) for L in lam_t], lam_tilde=lam_t, w=w, patterns=pats,
+                colours=colours.astype(np.int32))
+
+
+def fit(A, n, depth, mode="additive", colours=None, alpha=None) -> Dict:
+    if mode == "additive":
+        return fit_additive(A, n, depth, alpha)
+    if mode == "multiplicative":
+        return fit_multiplicative(A, n, depth, colours, alpha)
+    raise ValueError(mode)
+
+
+def jacobi_smoother(A: sp.spmatrix, n: int, depth: int, omega: float = 1.0) -> Dict:
+    """Reference smoother: every Lambda_l = omega * blockdiag(A)^{-1} (Sec. 2.1:
+    nu steps of damped block Jacobi / block Gauss-Seidel)."""
+    A = sp.csr_matrix(A)
+    B = A.shape[0] // n
+    D = np.empty((B, n, n))
+    for i in range(B):
+        D[i] = np.linalg.inv(A[i * n:(i + 1) * n, i * n:(i + 1) * n].toarray())
+    return dict(lam=[omega * D for _ in range(depth)], colours=None)
+
+
+def greedy_colour(Apat: sp.csr_matrix) -> np.ndarray:
+    """Colour blocks in index order, each with the smallest colour not used by
+    an already-coloured neighbour (a proper colouring of the block graph)."""
+    Apat = sp.csr_matrix(Apat)
+    B = Apat.shape[0]
+    c = np.full(B, -1, dtype=np.int64)
+    for i in range(B):
+        used = {c[j] for j in Apat.indices[Apat.indptr[i]:Apat.indptr[i + 1]] if j < i}
+        k = 0
+        while k in used:
+            k += 1
+        c[i] = k
+    return c.astype(np.int32)
+
+
+def is_proper_colouring(Apat: sp.csr_matrix, colours: np.ndarray) -> bool:
+    C = sp.coo_matrix(Apat)
+    off = C.row != C.col
+    return bool(np.all(colours[C.row[off]] != colours[C.col[off]]))
+
+
+# ---------------------------------------------------------------------------
+# Application (Sec. 2.1 / 2.2 forward, Sec. 2.4 reverse)
+# ---------------------------------------------------------------------------
+
+def smooth(A: sp.spmatrix, sm: Dict, x: np.ndarray, b: np.ndarray, reverse: bool = False) -> np.ndarray:
+    """One application of a cascading smoother.
+
+    additive forward:  x <- x - Lambda_l (A x - b),    l = 1..nu
+    additive reverse:  x <- x - Lambda_l^T (A x - b),  l = nu..1
+    multiplicative: the same over the flattened sequence (l, k), k = 1..chi,
+    with Lambda_{l,k} zero outside colour k; reverse runs it backwards."""
+    lam = sm["lam"]
+    colours = sm.get("colours")
+    depth = len(lam)
+    if colours is None:
+        seq = [(l, None) for l in range(depth)]
+    else:
+        chi = int(np.max(colours)) + 1
+        seq = [(l, k) for l in range(depth) for k in range(chi)]
+    if reverse:
+        seq = seq[::-1]
+    for l, k in seq:
+        blocks = lam[l] if k is None else lam[l] * (colours == k)[:, None, None]
+        L = blockdiag(blocks)
+        if reverse:
+            L = L.T
+        x = x - L @ (A @ x - b)
+    return x
+
+
+def setup_hierarchy(levels, depth: int, mode: str = "additive", alpha=None) -> List[Dict]:
+    """Fit a cascade on every level except the coarsest (Sec. 2.5)."""
+    out = []
+    for lv in levels[:-1]:
+        colours = lv.colour
+        if mode == "multiplicative" and colours is None:
+            colours = greedy_colour(block_pattern(lv.A, lv.block_size))
+        out.append(fit(lv.A, lv.block_size, depth, mode, colours, alpha))
+    return out
+
+
+def vcycle(levels, smoothers: List[Dict], b: np.ndarray, order: str = "RF",
+           npre: int = 1, npost: int = 1, lvl: int = 0) -> np.ndarray:
+    """Alg. 1 applied to right-hand side b with a zero initial guess.
+
+    Pre-smoother: reverse application for RF, forward for FF; post-smoother:
+    forward.  Restriction r_scale * P^T, correction x <- x - P x_c, and a dense
+    direct solve on the bottom level."""
+    lv = levels[lvl]
+    if lvl == len(levels) - 1:
+        return np.linalg.solve(lv.A.toarray(), b)
+    x = np.zeros_like(b)
+    for _ in range(npre):
+        x = smooth(lv.A, smoothers[lvl], x, b, reverse=(order == "RF"))
+    rc = lv.r_scale * (lv.P.T @ (lv.A @ x - b))
+    xc = vcycle(levels, smoothers, rc, order, npre, npost, lvl + 1)
+    x = x - lv.P @ xc
+    for _ in range(npost):
+        x = smooth(lv.A, smoothers[lvl], x, b, reverse=False)
+    return x
+
+
+def solve(levels, smoothers, b: np.ndarray, rtol: float = 1e-10, maxit: int = 100,
+          order: str = "RF", npre: int = 1, npost: int = 1):
+    """Stationary V-cycle iteration (defect correction) in FP64:
+    x_0 = 0; r = b - A x; stop when max_j ||r_j|| <= rtol ||b_j||; x += V r.
+    Returns x and the history of max_j ||r_j|| / ||b_j||."""
+    A = levels[0].A
+    x = np.zeros_like(b)
+    bn = np.linalg.norm(b, axis=0)
+    hist = []
+    for it in range(maxit + 1):
+        r = b - A @ x
+        rel = float(np.max(np.linalg.norm(r, axis=0) / bn))
+        hist.append(rel)
+        if rel <= rtol or it == maxit:
+            break
+        x = x + vcycle(levels, smoothers, r, order, npre, npost)
+    return x, hist
+
+
+def rho_regression(hist: Sequence[float]) -> float:
+    """Convergence rate from a least-squares line through (i, log r_i),
+    i = 1..K (Sec. 3.1); r_0 is left out."""
+    h = np.asarray(hist[1:], dtype=np.float64)
+    if len(h) < 2:
+        return float(h[0] / hist[0]) if len(h) else float("nan")
+    i = np.arange(1, len(h) + 1, dtype=np.float64)
+    slope = np.polyfit(i, np.log(h), 1)[0]
+    return float(np.exp(slope))
+
+
+def eta(rho: float) -> float:
+    """Iterations per decade of residual reduction: log 0.1 / log rho (Sec. 3.1)."""
+    return float(np.log(0.1) / np.log(rho))
+
+
+def cost_model(nu: int, eta_: float, d: int) -> float:
+    """C_d(nu, eta) = eta (1 + (2 nu + 1) / (1 - 2^-d)) (Sec. 3.1)."""
+    return eta_ * (1.0 + (2 * nu + 1) / (1.0 - 2.0 ** (-d)))
+
+
+# ---------------------------------------------------------------------------
+# Local (patch) evaluation for large problems
+# ---------------------------------------------------------------------------
+
+def block_ball(Apat: sp.csr_matrix, centre: int, radius: int) -> np.ndarray:
+    seen = {centre}
+    front = [centre]
+    for _ in range(radius):
+        nxt = []
+        for i in front:
+            for j in Apat.indices[Apat.indptr[i]:Apat.indptr[i + 1]]:
+                if j not in seen:
+                    seen.add(j)
+                    nxt.append(j)
+        front = nxt
+    return np.array(sorted(seen), dtype=np.int64)
+
+
+def fit_local(A: sp.spmatrix, n: int, depth: int, centres: Sequence[int], mode: str = "additive",
+              colours: Optional[np.ndarray] = None, radius: Optional[int] = None) -> Dict[int, List[np.ndarray]]:
+    """Lambda_{l,i} for selected blocks i, each fitted on the sub-matrix of A
+    over the blocks within block-graph distance `radius` of i.
+
+    Lambda_{l,i} depends on A only through E_{l-1} on the neighbours of i,
+    which in turn reaches at most l block layers out, so radius = nu
+    (additive) or nu * chi (multiplicative) reproduces the full fit."""
+    A = sp.csr_matrix(A)
+    Apat = block_pattern(A, n)
+    if radius is None:
+        radius = depth if mode == "additive" else depth * (int(np.max(colours)) + 1)
+    out = {}
+    for c in centres:
+        S = block_ball(Apat, int(c), radius)
+        sel = block_rows(S, n)
+        sub = A[sel][:, sel]
+        pos = int(np.searchsorted(S, c))
+        res = fit(sub, n, depth, mode, None if colours is None else np.asarray(colours)[S])
+        out[int(c)] = [L[pos] for L in res["lam"]]
+    return out

@@ -1,0 +1,519 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Every test here is CPU-only.  None of them re-calls the oracle routine it
+checks to produce the expected value: expectations come from the paper's
+Table 1, closed forms (Fourier symbols, first-level least squares), textbook
+iterations written as explicit loops, dense brute-force least squares over the
+whole Frobenius objective, or invariances of the definitions.
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle as O
+from synth import fd
+from synth.rng import TEST, stream
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------------------
+# helpers (independent of the oracle)
+# ---------------------------------------------------------------------------
+
+def random_block_matrix(B, n, seed, extra_edges=2, symmetric=False):
+    """Block-sparse matrix with a positive diagonal: ring + random couplings,
+    dense random blocks, diagonally dominant diagonal blocks."""
+    rng = stream(0, TEST, seed)
+    edges = {(i, (i + 1) % B) for i in range(B)}
+    for _ in range(extra_edges * B // 2):
+        i, j = rng.integers(0, B, size=2)
+        if i != j:
+            edges.add((int(i), int(j)))
+    N = B * n
+    A = np.zeros((N, N))
+    for (i, j) in edges:
+        blk = rng.uniform(-1.0, 0.2, size=(n, n))
+        A[i * n:(i + 1) * n, j * n:(j + 1) * n] += blk
+        A[j * n:(j + 1) * n, i * n:(i + 1) * n] += blk.T if symmetric else rng.uniform(-1.0, 0.2, size=(n, n))
+    for i in range(B):
+        D = rng.uniform(-0.3, 0.3, size=(n, n))
+        if symmetric:
+            D = D + D.T
+        A[i * n:(i + 1) * n, i * n:(i + 1) * n] += D
+    rowsum = np.abs(A).sum(axis=1)
+    A[np.arange(N), np.arange(N)] = rowsum + 1.0
+    return A
+
+
+def brute_force_cascade(A, n, depth, colours=None):
+    """Solve every Frobenius problem of the cascade as ONE dense least-squares
+    problem over all block-diagonal unknowns at once (SVD lstsq), without any
+    per-block decoupling, normal equations or sparse products."""
+    N = A.shape[0]
+    B = N // n
+    w = 1.0 / np.sqrt(np.diag(A))
+    At = w[:, None] * A * w[None, :]
+    E = np.eye(N)
+    chi = 1 if colours is None else int(np.max(colours)) + 1
+    lams = [np.zeros((B, n, n)) for _ in range(depth)]
+    for l in range(depth):
+        for k in range(chi):
+            blocks = np.arange(B) if colours is None else np.flatnonzero(colours == k)
+            M = At @ E
+            cols = []
+            for i in blocks:
+                for r in range(n):
+                    for s in range(n):
+                        Z = np.zeros((N, N))
+                        Z[i * n + r, :] = M[i * n + s, :]
+                        cols.append(Z.ravel())
+            D = np.stack(cols, axis=1)
+            sol = np.linalg.lstsq(D, E.ravel(), rcond=None)[0]
+            Lfull = np.zeros((N, N))
+            t = 0
+            for i in blocks:
+                for r in range(n):
+                    for s in range(n):
+                        lams[l][i, r, s] = sol[t]
+                        Lfull[i * n + r, i * n + s] = sol[t]
+                        t += 1
+            E = E - Lfull @ M
+    return lams
+
+
+def load_table1():
+    rows = {}
+    with open(os.path.join(GOLDEN, "table1.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            parts = line.split()
+            rows[(parts[0], int(parts[1]))] = [float(v) for v in parts[2:]]
+    return rows
+
+
+# ---------------------------------------------------------------------------
+# Table 1 and Fourier closed forms
+# ---------------------------------------------------------------------------
+
+# N > 2 x (fill radius) so that no fill wraps round the torus.
+TABLE1_N = {2: 20, 3: 16}
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_table1_additive(d):
+    want = load_table1()[("additive", d)]
+    A = fd.periodic_laplacian(TABLE1_N[d], d)
+    res = O.fit_additive(A, 1, 4)
+    for l, L in enumerate(res["lam"]):
+        lam = L[:, 0, 0] * 2 * d                     # Lambda_l = lambda_l diag(A)^-1
+        assert np.ptp(lam) < 1e-12                   # scaled identity on a periodic grid
+        assert abs(lam[0] - want[l]) <= 0.005 + 1e-12, (d, l, lam[0], want[l])
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_table1_red_black(d):
+    want = load_table1()[("multiplicative", d)]
+    N = TABLE1_N[d]
+    A = fd.periodic_laplacian(N, d)
+    c = fd.periodic_parity(N, d)
+    res = O.fit_multiplicative(A, 1, 4, c)
+    for l, L in enumerate(res["lam"]):
+        for k in range(2):
+            lam = L[c == k, 0, 0] * 2 * d
+            assert np.ptp(lam) < 1e-12
+            assert abs(lam[0] - want[2 * l + k]) <= 0.005 + 1e-12, (d, l, k, lam[0])
+
+
+def fourier_lambdas(N, d, depth):
+    """lambda_l from the discrete Fourier symbol of the periodic Laplacian:
+    sigma(theta) = 1 - mean_k cos(theta_k) is the symbol of the prescaled
+    operator; by Parseval the Frobenius objective of level l is
+    sum_theta (1 - lambda sigma)^2 prod_{m<l} (1 - lambda_m sigma)^2."""
+    th = 2 * np.pi * np.arange(N) / N
+    grids = np.meshgrid(*([th] * d), indexing="ij")
+    sigma = 1.0 - sum(np.cos(g) for g in grids) / d
+    P = np.ones_like(sigma)
+    out = []
+    for _ in range(depth):
+        lam = float((sigma * P ** 2).sum() / (sigma ** 2 * P ** 2).sum())
+        out.append(lam)
+        P = P * (1.0 - lam * sigma)
+    return out
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_additive_matches_fourier_symbol(d):
+    N = TABLE1_N[d]
+    res = O.fit_additive(fd.periodic_laplacian(N, d), 1, 4)
+    want = fourier_lambdas(N, d, 4)
+    got = [L[0, 0, 0] * 2 * d for L in res["lam"]]
+    np.testing.assert_allclose(got, want, rtol=1e-12)
+
+
+def test_exact_rationals():
+    # Infinite-grid moments: 2D lambda_1 = 4/5, lambda_2 = 6/7;
+    # 3D lambda_1 = 6/7 (optimal Jacobi damping, Sec. 3.4.1), lambda_2 = 15/17.
+    r2 = O.fit_additive(fd.periodic_laplacian(12, 2), 1, 2)["lam"]
+    r3 = O.fit_additive(fd.periodic_laplacian(8, 3), 1, 2)["lam"]
+    assert abs(r2[0][0, 0, 0] * 4 - 4 / 5) < 1e-13
+    assert abs(r2[1][0, 0, 0] * 4 - 6 / 7) < 1e-13
+    assert abs(r3[0][0, 0, 0] * 6 - 6 / 7) < 1e-13
+    assert abs(r3[1][0, 0, 0] * 6 - 15 / 17) < 1e-13
+
+
+@pytest.mark.parametrize("d,mu_exact", [(2, 3 / 5), (3, 5 / 7)])
+def test_one_level_is_optimally_damped_jacobi(d, mu_exact):
+    """A depth-1 point cascade is damped Jacobi with the classical optimal
+    weight; its local Fourier smoothing factor over the high frequencies is
+    3/5 (2D) / 5/7 (3D)."""
+    lam = O.fit_additive(fd.periodic_laplacian(8, d), 1, 1)["lam"][0][0, 0, 0] * 2 * d
+    th = np.linspace(-np.pi, np.pi, 257)
+    grids = np.meshgrid(*([th] * d), indexing="ij")
+    high = np.zeros_like(grids[0], dtype=bool)
+    for g in grids:
+        high |= np.abs(g) >= np.pi / 2
+    sigma = 1.0 - sum(np.cos(g) for g in grids) / d
+    mu = np.abs(1.0 - lam * sigma)[high].max()
+    assert abs(mu - mu_exact) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# First-level closed form on a bounded problem (every row, boundary included)
+# ---------------------------------------------------------------------------
+
+def test_first_level_closed_form_dirichlet():
+    """With E_0 = I and point blocks, the level-1 least-squares problem has the
+    solution lambda~_i = a~_ii / sum_j a~_ij^2 on the prescaled matrix."""
+    p = fd.poisson2d(64)
+    A = p.levels[0].A
+    res = O.fit_additive(A, 1, 3)
+    C = sp.coo_matrix(A)
+    dg = A.diagonal()
+    at = C.data / np.sqrt(dg[C.row] * dg[C.col])
+    s2 = np.bincount(C.row, weights=at ** 2, minlength=A.shape[0])
+    lam = (1.0 / s2) / dg
+    np.testing.assert_allclose(res["lam"][0][:, 0, 0], lam, rtol=1e-14)
+    # interior rows: optimal Jacobi damping 4/5 of 1/diag
+    inner = np.flatnonzero(np.isclose(s2, 1.25))
+    assert len(inner) == 60 * 60        # rows whose neighbours are all interior too
+    np.testing.assert_allclose(res["lam"][0][inner, 0, 0] * dg[inner], 0.8, rtol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# Brute-force Frobenius minimisation on tiny matrices
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("B,n,depth,seed", [(12, 1, 3, 0), (8, 2, 3, 1), (6, 3, 2, 2), (6, 4, 2, 3)])
+def test_additive_vs_brute_force(B, n, depth, seed):
+    A = random_block_matrix(B, n, seed)
+    want = brute_force_cascade(A, n, depth)
+    got = O.fit_additive(sp.csr_matrix(A), n, depth)["lam_tilde"]
+    for l in range(depth):
+        np.testing.assert_allclose(got[l], want[l], rtol=1e-9, atol=1e-11)
+
+
+@pytest.mark.parametrize("B,n,depth,chi,seed", [(12, 1, 3, 2, 4), (9, 2, 2, 3, 5), (8, 3, 2, 2, 6)])
+def test_multiplicative_vs_brute_force(B, n, depth, chi, seed):
+    A = random_block_matrix(B, n, seed)
+    colours = np.arange(B) % chi
+    want = brute_force_cascade(A, n, depth, colours)
+    got = O.fit_multiplicative(sp.csr_matrix(A), n, depth, colours)["lam_tilde"]
+    for l in range(depth):
+        np.testing.assert_allclose(got[l], want[l], rtol=1e-9, atol=1e-11)
+
+
+def test_first_order_optimality():
+    """[(E - Lambda M) M^T]_ii = 0 for every block at every level."""
+    A = random_block_matrix(10, 3, 7)
+    n, depth = 3, 3
+    res = O.fit_additive(sp.csr_matrix(A), n, depth)
+    w = 1.0 / np.sqrt(np.diag(A))
+    At = w[:, None] * A * w[None, :]
+    E = np.eye(A.shape[0])
+    for l in range(depth):
+        M = At @ E
+        L = np.zeros_like(A)
+        for i in range(10):
+            L[i * n:(i + 1) * n, i * n:(i + 1) * n] = res["lam_tilde"][l][i]
+        R = (E - L @ M) @ M.T
+        for i in range(10):
+            blk = R[i * n:(i + 1) * n, i * n:(i + 1) * n]
+            assert np.abs(blk).max() < 1e-12 * np.abs(M).max() ** 2 * A.shape[0]
+        E = E - L @ M
+
+
+def test_one_colour_collapses_to_additive():
+    A = sp.csr_matrix(random_block_matrix(10, 2, 8))
+    a = O.fit_additive(A, 2, 3)
+    m = O.fit_multiplicative(A, 2, 3, np.zeros(10, dtype=np.int32))
+    for l in range(3):
+        np.testing.assert_array_equal(a["lam"][l], m["lam"][l])
+
+
+# ---------------------------------------------------------------------------
+# Application: block Jacobi / block Gauss-Seidel as written in textbooks
+# ---------------------------------------------------------------------------
+
+def test_inverse_diagonal_gives_block_jacobi_and_gauss_seidel():
+    n, B = 2, 9
+    A = random_block_matrix(B, n, 9, symmetric=True)
+    rng = stream(0, TEST, 10)
+    b = rng.uniform(-1, 1, size=(B * n, 2))
+    x0 = rng.uniform(-1, 1, size=(B * n, 2))
+    Ainv = [np.linalg.inv(A[i * n:(i + 1) * n, i * n:(i + 1) * n]) for i in range(B)]
+    lam = np.stack(Ainv)
+    # block Jacobi, two sweeps: x_i <- A_ii^-1 (b_i - sum_{j != i} A_ij x_j)
+    x = x0.copy()
+    for _ in range(2):
+        xn = x.copy()
+        for i in range(B):
+            s = b[i * n:(i + 1) * n].copy()
+            for j in range(B):
+                if j != i:
+                    s -= A[i * n:(i + 1) * n, j * n:(j + 1) * n] @ x[j * n:(j + 1) * n]
+            xn[i * n:(i + 1) * n] = Ainv[i] @ s
+        x = xn
+    got = O.smooth(sp.csr_matrix(A), dict(lam=[lam, lam], colours=None), x0, b)
+    np.testing.assert_allclose(got, x, rtol=1e-13, atol=1e-14)
+    # multicoloured block Gauss-Seidel (in place, colours 0,1,2 in order)
+    colours = np.arange(B) % 3
+    x = x0.copy()
+    for _ in range(2):
+        for k in range(3):
+            for i in np.flatnonzero(colours == k):
+                s = b[i * n:(i + 1) * n].copy()
+                for j in range(B):
+                    if j != i:
+                        s -= A[i * n:(i + 1) * n, j * n:(j + 1) * n] @ x[j * n:(j + 1) * n]
+                x[i * n:(i + 1) * n] = Ainv[i] @ s
+    # the in-place sweep equals the colour-restricted smoother only when no two
+    # blocks of one colour are coupled; check that first
+    Apat = O.block_pattern(sp.csr_matrix(A), n)
+    if O.is_proper_colouring(Apat, colours):
+        got = O.smooth(sp.csr_matrix(A), dict(lam=[lam, lam], colours=colours), x0, b)
+        np.testing.assert_allclose(got, x, rtol=1e-13, atol=1e-14)
+
+
+def test_gauss_seidel_proper_colouring_grid():
+    """Red-black block GS on a 5-point grid, textbook in-place loops."""
+    n_grid = 6
+    A = fd.poisson2d(n_grid).levels[0].A.toarray()
+    N = A.shape[0]
+    colours = fd.parity_colour(n_grid, 2, 1)
+    rng = stream(0, TEST, 11)
+    b = rng.uniform(-1, 1, size=(N, 1))
+    x = np.zeros((N, 1))
+    for _ in range(3):
+        for k in (0, 1):
+            for i in np.flatnonzero(colours == k):
+                x[i] = (b[i] - A[i] @ x + A[i, i] * x[i]) / A[i, i]
+    lam = (1.0 / np.diag(A)).reshape(N, 1, 1)
+    got = O.smooth(sp.csr_matrix(A), dict(lam=[lam] * 3, colours=colours), np.zeros((N, 1)), b)
+    np.testing.assert_allclose(got, x, rtol=1e-13, atol=1e-15)
+
+
+def test_forward_and_reverse_closed_forms():
+    """Supplementary V-cycle symmetry section: forward application maps
+    x0 -> (I-L_nu A)...(I-L_1 A) x0 + A^-1 [I - (I-A L_nu)...(I-A L_1)] b and
+    reverse uses L_l^T in the opposite order."""
+    n, B, depth = 2, 6, 3
+    A = random_block_matrix(B, n, 12)
+    N = A.shape[0]
+    rng = stream(0, TEST, 13)
+    lam = [rng.uniform(-0.3, 0.3, size=(B, n, n)) for _ in range(depth)]
+    Ls = []
+    for L in lam:
+        F = np.zeros((N, N))
+        for i in range(B):
+            F[i * n:(i + 1) * n, i * n:(i + 1) * n] = L[i]
+        Ls.append(F)
+    x0 = rng.uniform(-1, 1, size=(N, 1))
+    b = rng.uniform(-1, 1, size=(N, 1))
+    I = np.eye(N)
+    Ainv = np.linalg.inv(A)
+    # forward
+    T = I.copy()
+    S = I.copy()
+    for F in Ls:
+        T = (I - F @ A) @ T
+        S = (I - A @ F) @ S
+    want = T @ x0 + Ainv @ (I - S) @ b
+    got = O.smooth(sp.csr_matrix(A), dict(lam=lam, colours=None), x0, b)
+    np.testing.assert_allclose(got, want, rtol=1e-11, atol=1e-12)
+    # reverse
+    T = I.copy()
+    S = I.copy()
+    for F in reversed(Ls):
+        T = (I - F.T @ A) @ T
+        S = (I - A @ F.T) @ S
+    want = T @ x0 + Ainv @ (I - S) @ b
+    got = O.smooth(sp.csr_matrix(A), dict(lam=lam, colours=None), x0, b, reverse=True)
+    np.testing.assert_allclose(got, want, rtol=1e-11, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Invariances of the setup
+# ---------------------------------------------------------------------------
+
+def test_diagonal_scaling_invariance():
+    """Lambda(D A D) = D^-1 Lambda(A) D^-1 for positive diagonal D, and
+    Lambda(c A) = Lambda(A) / c (prescaling, Sec. 2.3)."""
+    n, B = 2, 8
+    A = random_block_matrix(B, n, 14)
+    dvec = stream(0, TEST, 15).uniform(0.1, 10.0, size=B * n)
+    base = O.fit_additive(sp.csr_matrix(A), n, 3)["lam"]
+    scaled = O.fit_additive(sp.csr_matrix(dvec[:, None] * A * dvec[None, :]), n, 3)["lam"]
+    times = O.fit_additive(sp.csr_matrix(7.5 * A), n, 3)["lam"]
+    db = dvec.reshape(B, n)
+    for l in range(3):
+        want = base[l] / db[:, :, None] / db[:, None, :]
+        np.testing.assert_allclose(scaled[l], want, rtol=1e-10)
+        np.testing.assert_allclose(times[l], base[l] / 7.5, rtol=1e-12)
+
+
+def test_permutation_equivariance():
+    n, B = 2, 10
+    A = random_block_matrix(B, n, 16)
+    perm = stream(0, TEST, 17).permutation(B)          # new block p holds old block perm[p]
+    sidx = (perm[:, None] * n + np.arange(n)[None, :]).ravel()
+    Ap = A[np.ix_(sidx, sidx)]
+    base = O.fit_additive(sp.csr_matrix(A), n, 3)["lam"]
+    got = O.fit_additive(sp.csr_matrix(Ap), n, 3)["lam"]
+    for l in range(3):
+        np.testing.assert_allclose(got[l], base[l][perm], rtol=1e-12, atol=1e-15)
+
+
+def test_additive_pattern_is_power_of_A():
+    p = fd.lognormal2d(12, n_stop=12)
+    A = p.levels[0].A
+    res = O.fit_additive(A, 1, 4)
+    S = (A.toarray() != 0).astype(np.int64)
+    Pw = np.eye(A.shape[0], dtype=np.int64)
+    for l, pat in enumerate(res["patterns"]):
+        np.testing.assert_array_equal(pat.toarray(), Pw > 0)
+        Pw = np.minimum(S @ Pw, 1)
+
+
+# ---------------------------------------------------------------------------
+# V-cycle properties
+# ---------------------------------------------------------------------------
+
+def test_periodic_ff_equals_rf():
+    """Every Lambda_l is a scaled identity on a periodic grid, so forward and
+    reverse applications coincide (footnote of Sec. 3.4.1)."""
+    N = 12
+    A = fd.periodic_laplacian(N, 2)
+    sm = O.fit_additive(A, 1, 3)
+    b = stream(0, TEST, 18).uniform(-1, 1, size=(N * N, 1))
+    f = O.smooth(A, sm, np.zeros_like(b), b)
+    r = O.smooth(A, sm, np.zeros_like(b), b, reverse=True)
+    np.testing.assert_allclose(f, r, rtol=1e-14, atol=1e-15)
+
+
+@pytest.mark.parametrize("mode", ["additive", "multiplicative"])
+def test_rf_vcycle_is_symmetric(mode):
+    p = fd.lognormal2d(16, n_stop=4)
+    for lv in p.levels:
+        lv.colour = fd.parity_colour(int(round(np.sqrt(lv.n))), 2, 1)
+    sm = O.setup_hierarchy(p.levels, 2, mode)
+    I = np.eye(p.n)
+    V = O.vcycle(p.levels, sm, I, order="RF")
+    assert np.abs(V - V.T).max() <= 1e-12 * np.abs(V).max()
+    Vf = O.vcycle(p.levels, sm, I, order="FF")
+    assert np.abs(Vf - Vf.T).max() > 1e-6 * np.abs(Vf).max()
+
+
+def test_poisson64_convergence():
+    """64^2 Dirichlet Poisson, depth-3 additive, V(2,2): monotone residual decay,
+    rho < 1, eta < 3 (the 'effective' threshold of Sec. 3.3)."""
+    p = fd.poisson2d(64)
+    sm = O.setup_hierarchy(p.levels, 3)
+    x, hist = O.solve(p.levels, sm, p.rhs, npre=2, npost=2)
+    assert hist[-1] <= 1e-10
+    assert all(b < a for a, b in zip(hist, hist[1:]))
+    rho = O.rho_regression(hist)
+    assert rho < 0.1 and O.eta(rho) < 3
+    r = p.rhs - p.levels[0].A @ x
+    assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(p.rhs)
+
+
+def test_rho_regression_geometric():
+    h = [3.0 * 0.37 ** i for i in range(9)]
+    assert abs(O.rho_regression(h) - 0.37) < 1e-12
+    assert abs(O.eta(0.1) - 1.0) < 1e-15
+    # C_d(nu=1, eta=1) in 2D: 1 + 3/(3/4) = 5
+    assert abs(O.cost_model(1, 1.0, 2) - 5.0) < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# Colouring, truncation and the local evaluation used at large sizes
+# ---------------------------------------------------------------------------
+
+def test_greedy_colouring_of_grid_is_red_black():
+    n = 9
+    A = fd.poisson2d(n, n_stop=n).levels[0].A
+    c = O.greedy_colour(O.block_pattern(A, 1))
+    np.testing.assert_array_equal(c, fd.parity_colour(n, 2, 1))
+    rnd = sp.csr_matrix(random_block_matrix(30, 1, 19, extra_edges=4))
+    pat = O.block_pattern(rnd, 1)
+    cc = O.greedy_colour(pat)
+    assert O.is_proper_colouring(pat, cc)
+    assert not O.is_proper_colouring(pat, np.zeros(30, dtype=np.int32))
+
+
+def test_truncation():
+    A = sp.csr_matrix(random_block_matrix(10, 2, 20, extra_edges=3))
+    full = O.fit_additive(A, 2, 3)
+    big = O.fit_additive(A, 2, 3, alpha=10)          # alpha >= row length: no change
+    for l in range(3):
+        np.testing.assert_allclose(full["lam"][l], big["lam"][l], rtol=1e-12, atol=1e-15)
+    one = O.fit_additive(A, 2, 2, alpha=1)
+    # with alpha = 1 each row of E_1 keeps exactly its largest block; the next
+    # fit sees that truncated E (brute force on the truncated E_1)
+    w = 1.0 / np.sqrt(A.diagonal())
+    At = (w[:, None] * A.toarray() * w[None, :])
+    lt1 = one["lam_tilde"][0]
+    L1 = np.zeros_like(At)
+    for i in range(10):
+        L1[2 * i:2 * i + 2, 2 * i:2 * i + 2] = lt1[i]
+    E1 = np.eye(20) - L1 @ At
+    Et = np.zeros_like(E1)
+    for i in range(10):
+        norms = [np.linalg.norm(E1[2 * i:2 * i + 2, 2 * j:2 * j + 2]) for j in range(10)]
+        j = int(np.argmax(norms))
+        Et[2 * i:2 * i + 2, 2 * j:2 * j + 2] = E1[2 * i:2 * i + 2, 2 * j:2 * j + 2]
+    assert one["patterns"][1].sum(axis=1).max() == 1
+    M = At @ Et
+    for i in range(10):
+        Mi, Ei = M[2 * i:2 * i + 2], Et[2 * i:2 * i + 2]
+        want = np.linalg.lstsq(Mi.T, Ei.T, rcond=None)[0].T
+        np.testing.assert_allclose(one["lam_tilde"][1][i], want, rtol=1e-9, atol=1e-12)
+
+
+def test_local_patch_fit_reproduces_full_fit():
+    p = fd.interface3d(16, nrhs=1, n_stop=16)
+    A = p.levels[0].A
+    full = O.fit_additive(A, 8, 3)["lam"]
+    centres = [0, 27, 100, 219, 511]
+    loc = O.fit_local(A, 8, 3, centres)
+    for c in centres:
+        for l in range(3):
+            np.testing.assert_allclose(loc[c][l], full[l][c], rtol=1e-11, atol=1e-14)
+    # one layer less is not enough (negative control)
+    short = O.fit_local(A, 8, 3, [219], radius=2)
+    assert np.abs(short[219][2] - full[2][219]).max() > 1e-10 * np.abs(full[2][219]).max()
+
+
+def test_local_patch_fit_multiplicative():
+    p = fd.lognormal2d(16, n_stop=16)
+    A = p.levels[0].A
+    c = fd.parity_colour(16, 2, 1)
+    full = O.fit_multiplicative(A, 1, 2, c)["lam"]
+    loc = O.fit_local(A, 1, 2, [0, 77, 136, 255], mode="multiplicative", colours=c)
+    for i, v in loc.items():
+        for l in range(2):
+            np.testing.assert_allclose(v[l], full[l][i], rtol=1e-11)

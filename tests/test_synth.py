@@ -1,0 +1,66 @@
+"""Checks of the synthetic input generators (no solver arithmetic involved)."""
+import numpy as np
+import scipy.sparse.linalg as spla
+
+from synth import fd
+
+
+def test_fd_symmetric_and_row_sums():
+    p = fd.poisson2d(16)
+    for lv in p.levels:
+        A = lv.A
+        assert abs(A - A.T).max() == 0
+        n = int(round(np.sqrt(A.shape[0])))
+        rs = np.asarray(A.sum(axis=1)).ravel().reshape(n, n)
+        assert np.abs(rs[1:-1, 1:-1]).max() < 1e-9 * A.max()   # interior rows sum to zero
+        assert rs[0, 0] > 0                                      # Dirichlet boundary rows do not
+
+
+def test_fd_second_order():
+    errs = []
+    for n in (16, 32, 64):
+        lv = fd.poisson2d(n, n_stop=n).levels[0]
+        x = (np.arange(n) + 0.5) / n
+        X, Y = np.meshgrid(x, x, indexing="ij")
+        u = np.sin(np.pi * X) * np.sin(np.pi * Y)
+        f = 2 * np.pi ** 2 * u
+        idx = fd.cell_order(n, 2, 1)
+        rhs = np.empty(n * n)
+        rhs[idx.ravel()] = f.ravel()
+        uh = spla.spsolve(lv.A.tocsc(), rhs)
+        ue = np.empty(n * n)
+        ue[idx.ravel()] = u.ravel()
+        errs.append(np.abs(uh - ue).max())
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > 1.8), rates
+
+
+def test_block_ordering_and_transfer():
+    n, bs = 8, 2
+    idx = fd.cell_order(n, 3, bs)
+    assert sorted(idx.ravel().tolist()) == list(range(n ** 3))
+    # cells of one block are contiguous
+    assert set(idx[:2, :2, :2].ravel().tolist()) == set(range(8))
+    P = fd.piecewise_constant_P(n, 3, bs, bs)
+    assert np.allclose(P @ np.ones(P.shape[1]), 1.0)          # P 1 = 1
+    assert np.all(np.asarray((P != 0).sum(axis=1)).ravel() == 1)
+    assert np.all(np.asarray(P.sum(axis=0)).ravel() == 8)
+
+
+def test_interface_problem():
+    p = fd.interface3d(32, nrhs=3)
+    c = np.array(p.meta["centre"])
+    assert np.all((c >= 0.3) & (c <= 0.7))
+    A = p.levels[0].A
+    assert abs(A - A.T).max() <= 1e-12 * abs(A).max()
+    assert A.diagonal().max() / A.diagonal().min() > 1e3       # high contrast present
+    assert [lv.n for lv in p.levels] == [32 ** 3, 16 ** 3, 8 ** 3, 4 ** 3]
+    assert p.rhs.shape == (32 ** 3, 3) and np.abs(p.rhs).max() <= 1
+
+
+def test_batch_sizes():
+    s = fd.batch_sizes(64)
+    assert np.all(s % 16 == 0) and s.min() >= 64 and s.max() <= 512
+    probs = fd.lognormal_batch(sizes=[64, 80])
+    assert probs[1].levels[-1].n == 5 * 5            # 80 -> 40 -> 20 -> 10 -> 5 (odd)
+    assert probs[0].levels[-1].n == 8 * 8            # 64 -> ... -> 8
