@@ -1,0 +1,162 @@
+/*
+ * cascade.h - C ABI of the MI355X (gfx950) cascading-smoother multigrid library.
+ *
+ * The library implements, on one GPU, the method of R. I. Saye, "Cascading
+ * Smoothers for Multigrid" (arXiv 2606.12577):
+ *   - the setup that fits each cascade level's block-diagonal smoother
+ *     Lambda_l by Frobenius-norm minimisation of the error propagator
+ *     (Sec. 2.1 additive, Sec. 2.2 multicoloured, Sec. 2.3 elliptic prescaling,
+ *     Algorithm 2 and the supplementary multicoloured algorithm);
+ *   - the geometric-multigrid V-cycle of Algorithm 1 with forward/reverse
+ *     cascade applications (Sec. 2.1 / 2.2 forward formulas, Sec. 2.4 reverse
+ *     formulas and the FF / RF solver classes), restriction r_scale * P^T,
+ *     correction x <- x - P x_c and a direct solve on the bottom level;
+ *   - a stationary solve in FP64 iterative refinement around the V-cycle.
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns cs_status (CS_OK = 0); no C++ exception crosses
+ *     the ABI.  On failure cs_last_error(ctx) holds a message and output
+ *     buffers are left unspecified unless stated otherwise.
+ *   - A context owns every device buffer it allocates and frees them in
+ *     cs_destroy.  The caller owns every pointer it passes in; the library
+ *     copies host inputs before returning and never frees caller memory.
+ *   - Work is issued on the HIP stream given to cs_create (NULL = the null
+ *     stream).  Calls on one context must not overlap; distinct contexts
+ *     may be used from distinct threads.
+ *   - Vectors (right-hand sides, solutions) are device pointers to FP64 arrays
+ *     of shape [n][nrhs]: the nrhs values of scalar unknown k are contiguous
+ *     at offset k*nrhs.
+ *   - Block i of a level owns the contiguous scalar unknowns
+ *     [i*block_size, (i+1)*block_size) (the paper's partition A_ij, Sec. 2).
+ */
+#ifndef CASCADE_H
+#define CASCADE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CS_ABI_VERSION 1
+
+typedef struct cs_ctx_s *cs_ctx;
+typedef struct cs_batch_s *cs_batch;
+
+typedef enum {
+    CS_OK = 0,
+    CS_EINVAL = -1,     /* bad argument, inconsistent sizes, non-positive diagonal */
+    CS_ENOMEM = -2,     /* device allocation failed */
+    CS_EDEVICE = -3,    /* a HIP runtime call or kernel launch failed */
+    CS_ESINGULAR = -4,  /* a normal-equation matrix had no usable pivot */
+    CS_ECOLOR = -5,     /* supplied colouring is not proper for the block graph */
+    CS_ENOCONV = -6,    /* solve stopped at maxit; x holds the last iterate */
+    CS_ESTATE = -7,     /* call out of order (e.g. vcycle before setup) */
+    CS_ENAN = -8,       /* NaN or Inf met in the solve */
+    CS_EVERSION = -9,   /* saved setup has another format version */
+    CS_EIO = -10        /* file could not be read or written */
+} cs_status;
+
+typedef enum { CS_ADDITIVE = 0, CS_MULTIPLICATIVE = 1 } cs_mode;   /* Sec. 2.1 / 2.2 */
+typedef enum { CS_FF = 0, CS_RF = 1 } cs_order;   /* pre-smoother forward / reverse; post is forward (Sec. 2.4) */
+typedef enum { CS_FP64 = 0, CS_FP32 = 1, CS_BF16 = 2 } cs_precision;  /* V-cycle working precision */
+
+/* One level of the geometric hierarchy (Sec. 2.4); levels[0] is the finest and
+ * the last level is solved directly.  All pointers are host pointers. */
+typedef struct {
+    int64_t n;                  /* scalar unknowns on this level */
+    int32_t block_size;         /* uniform block size; must divide n */
+    const int64_t *a_row_ptr;   /* [n+1] scalar CSR of A_h; column indices sorted per row */
+    const int32_t *a_col;       /* [nnz] */
+    const double *a_val;        /* [nnz] */
+    int64_t n_coarse;           /* unknowns of the next coarser level (0 on the last level) */
+    const int64_t *p_row_ptr;   /* [n+1] scalar CSR of the interpolation I_2h^h (n x n_coarse), NULL on the last level */
+    const int32_t *p_col;
+    const double *p_val;
+    double r_scale;             /* restriction R = r_scale * P^T (1 for Galerkin FE/DG, 2^-d for the FD schemes) */
+    const int32_t *colour;      /* [n/block_size] block colours 0..chi-1, or NULL (library colours greedily) */
+} cs_level;
+
+typedef struct {
+    int32_t depth;              /* cascade depth nu >= 1 */
+    int32_t mode;               /* cs_mode */
+    int32_t order;              /* cs_order */
+    int32_t n_pre, n_post;      /* cascade applications before / after the coarse correction (>= 1) */
+    int32_t trunc_alpha;        /* keep the alpha largest blocks per row of E (Alg. 2 optional step); 0 = keep all */
+    int32_t precision;          /* cs_precision of the V-cycle */
+} cs_options;
+
+typedef struct {
+    int32_t iterations;         /* V-cycles applied */
+    double rel_res;             /* final max_j ||b_j - A x_j||_2 / ||b_j||_2 */
+    double rho;                 /* convergence factor from a regression of log residuals (Sec. 3.1) */
+    double setup_ms;            /* device time of the last cs_setup */
+    double solve_ms;            /* device time of this solve */
+    int32_t singular_blocks;    /* blocks solved by the pseudo-inverse fallback in the last setup */
+} cs_info;
+
+/* Library identity. */
+int32_t cs_abi_version(void);
+const char *cs_status_string(int32_t status);
+
+/* Create a context on HIP device `device` issuing work on `stream` (a
+ * hipStream_t, may be NULL).  *out is set on success. */
+cs_status cs_create(cs_ctx *out, int32_t device, void *stream);
+void cs_destroy(cs_ctx ctx);
+/* Message of the last failing call on ctx (or of the last failed cs_create when ctx is NULL). */
+const char *cs_last_error(cs_ctx ctx);
+
+/* Copy the hierarchy to the device.  Validates sizes and that every diagonal
+ * entry of every A is positive (elliptic prescaling, Sec. 2.3.1: CS_EINVAL
+ * otherwise).  Invalidates any previous setup. */
+cs_status cs_set_hierarchy(cs_ctx ctx, int32_t n_levels, const cs_level *levels);
+
+/* Build the cascading smoothers of every level but the last (Alg. 2 /
+ * supplementary multicoloured algorithm), the working-precision copies, and the
+ * factorisation of the bottom operator.  CS_ECOLOR if a supplied colouring is
+ * improper in multiplicative mode; CS_ESINGULAR if a block's normal equations
+ * have no positive pivot and the pseudo-inverse fallback fails too. */
+cs_status cs_setup(cs_ctx ctx, const cs_options *opt);
+
+/* Change the V-cycle working precision after setup (builds missing copies). */
+cs_status cs_set_precision(cs_ctx ctx, int32_t precision);
+
+/* FP64 master smoother Lambda_ell of `level` (ell = 1..depth), unscaled, as host
+ * array [n_blocks][block_size][block_size] row-major.  In multiplicative mode
+ * block i belongs to Lambda_{ell, colour(i)}.  set_smoother replaces it (and the
+ * working-precision copies); the rest of the setup is kept. */
+cs_status cs_get_smoother(cs_ctx ctx, int32_t level, int32_t ell, double *blocks_out);
+cs_status cs_set_smoother(cs_ctx ctx, int32_t level, int32_t ell, const double *blocks);
+
+/* Structural block pattern of the residual E after fit step `step` of `level`
+ * (step 0 = identity; additive: step l = E_l; multiplicative: steps count colour
+ * sweeps), as block CSR on the host.  get_pattern_size gives the entry count. */
+cs_status cs_get_pattern_size(cs_ctx ctx, int32_t level, int32_t step, int64_t *nnzb);
+cs_status cs_get_pattern(cs_ctx ctx, int32_t level, int32_t step, int64_t *row_ptr, int32_t *col);
+/* Block colours used on `level` (multiplicative mode), host int32[n_blocks]. */
+cs_status cs_get_colours(cs_ctx ctx, int32_t level, int32_t *colours_out);
+
+/* One application of the level's cascade, x <- S(x, b), forward (reverse = 0)
+ * or reverse (reverse = 1), in the working precision (Sec. 2.1/2.2/2.4).
+ * b, x: device FP64 [n_level][nrhs]. */
+cs_status cs_smooth(cs_ctx ctx, int32_t level, int32_t reverse, const double *b, double *x, int32_t nrhs);
+
+/* x = V b: one V-cycle of Algorithm 1 with zero initial guess in the working
+ * precision; b, x: device FP64 [n][nrhs] on the finest level. */
+cs_status cs_vcycle(cs_ctx ctx, const double *b, double *x, int32_t nrhs);
+
+/* Solve A x = b by FP64 iterative refinement around the V-cycle: x_0 = 0;
+ * r = b - A x (FP64); stop when max_j ||r_j|| <= rtol ||b_j||; x += V r.
+ * history (host, may be NULL) receives maxit+1 relative residuals.  On
+ * CS_ENOCONV x holds the last iterate and info is filled. */
+cs_status cs_solve(cs_ctx ctx, const double *b, double *x, int32_t nrhs, double rtol, int32_t maxit,
+                   cs_info *info, double *history);
+
+/* Persist / restore a setup (smoothers, colours, bottom factor) for the same hierarchy. */
+cs_status cs_save_setup(cs_ctx ctx, const char *path);
+cs_status cs_load_setup(cs_ctx ctx, const char *path);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CASCADE_H */

@@ -1,0 +1,267 @@
+"""Python binding of libcascade.so (the C ABI declared in include/cascade.h).
+
+Argument marshalling only: every step of the setup and of the solve runs in the
+library's HIP kernels.  torch supplies device memory and the stream.  The
+binding refuses to work without the built library.
+"""
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcascade.so")
+
+ADDITIVE, MULTIPLICATIVE = 0, 1
+FF, RF = 0, 1
+FP64, FP32, BF16 = 0, 1, 2
+_MODES = {"additive": ADDITIVE, "multiplicative": MULTIPLICATIVE}
+_ORDERS = {"FF": FF, "RF": RF}
+_PRECS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
+
+STATUS = {0: "CS_OK", -1: "CS_EINVAL", -2: "CS_ENOMEM", -3: "CS_EDEVICE", -4: "CS_ESINGULAR",
+          -5: "CS_ECOLOR", -6: "CS_ENOCONV", -7: "CS_ESTATE", -8: "CS_ENAN", -9: "CS_EVERSION",
+          -10: "CS_EIO"}
+
+
+class CascadeError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_p = ctypes.POINTER
+
+
+class cs_level(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("block_size", ctypes.c_int32),
+                ("a_row_ptr", _p(ctypes.c_int64)), ("a_col", _p(ctypes.c_int32)), ("a_val", _p(ctypes.c_double)),
+                ("n_coarse", ctypes.c_int64),
+                ("p_row_ptr", _p(ctypes.c_int64)), ("p_col", _p(ctypes.c_int32)), ("p_val", _p(ctypes.c_double)),
+                ("r_scale", ctypes.c_double), ("colour", _p(ctypes.c_int32))]
+
+
+class cs_options(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_int32), ("mode", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("n_pre", ctypes.c_int32), ("n_post", ctypes.c_int32), ("trunc_alpha", ctypes.c_int32),
+                ("precision", ctypes.c_int32)]
+
+
+class cs_info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("rel_res", ctypes.c_double), ("rho", ctypes.c_double),
+                ("setup_ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
+                ("singular_blocks", ctypes.c_int32)]
+
+
+# every symbol declared in include/cascade.h, with its ctypes signature
+_VP, _I32, _I64, _D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+SIGNATURES = {
+    "cs_abi_version": (_I32, []),
+    "cs_status_string": (ctypes.c_char_p, [_I32]),
+    "cs_create": (_I32, [_p(_VP), _I32, _VP]),
+    "cs_destroy": (None, [_VP]),
+    "cs_last_error": (ctypes.c_char_p, [_VP]),
+    "cs_set_hierarchy": (_I32, [_VP, _I32, _p(cs_level)]),
+    "cs_setup": (_I32, [_VP, _p(cs_options)]),
+    "cs_set_precision": (_I32, [_VP, _I32]),
+    "cs_get_smoother": (_I32, [_VP, _I32, _I32, _p(_D)]),
+    "cs_set_smoother": (_I32, [_VP, _I32, _I32, _p(_D)]),
+    "cs_get_pattern_size": (_I32, [_VP, _I32, _I32, _p(_I64)]),
+    "cs_get_pattern": (_I32, [_VP, _I32, _I32, _p(_I64), _p(_I32)]),
+    "cs_get_colours": (_I32, [_VP, _I32, _p(_I32)]),
+    "cs_smooth": (_I32, [_VP, _I32, _I32, _VP, _VP, _I32]),
+    "cs_vcycle": (_I32, [_VP, _VP, _VP, _I32]),
+    "cs_solve": (_I32, [_VP, _VP, _VP, _I32, _D, _I32, _p(cs_info), _p(_D)]),
+    "cs_save_setup": (_I32, [_VP, ctypes.c_char_p]),
+    "cs_load_setup": (_I32, [_VP, ctypes.c_char_p]),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libcascade.so and declare its signatures (no GPU needed)."""
+    global _lib
+    if _lib is not None and path == LIB_PATH:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built: run `python -m paper_2606_12577_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    if path == LIB_PATH:
+        _lib = lib
+    return lib
+
+
+def _arr(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(_p(ctype))
+
+
+def _tensor_ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One hierarchy on one GPU.
+
+    levels: sequence of objects with attributes A (scipy CSR, float64),
+    block_size, P (CSR interpolation from the next coarser level or None),
+    r_scale and colour (int array per block or None); level 0 is the finest.
+    """
+
+    def __init__(self, levels: Sequence, device: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the cascade solver needs a HIP GPU")
+        self._torch = torch
+        self.device = torch.device("cuda", device)
+        self._lib = load_library()
+        self._stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        st = self._lib.cs_create(ctypes.byref(h), device, ctypes.c_void_p(self._stream.cuda_stream))
+        if st != 0:
+            raise CascadeError(st, self._lib.cs_last_error(None).decode())
+        self._h = h
+        self.n_levels = 0
+        self.sizes = []
+        self.set_hierarchy(levels)
+
+    # -- plumbing --------------------------------------------------------
+    def _check(self, st):
+        if st != 0:
+            raise CascadeError(st, self._lib.cs_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.cs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- hierarchy and setup ----------------------------------------------
+    def set_hierarchy(self, levels: Sequence):
+        keep = []
+        arr = (cs_level * len(levels))()
+        for i, lv in enumerate(levels):
+            A = lv.A.tocsr()
+            A.sort_indices()
+            ap = _arr(A.indptr, np.int64)
+            ac = _arr(A.indices, np.int32)
+            av = _arr(A.data, np.float64)
+            keep += [ap, ac, av]
+            s = arr[i]
+            s.n = A.shape[0]
+            s.block_size = int(lv.block_size)
+            s.a_row_ptr, s.a_col, s.a_val = _ptr(ap, ctypes.c_int64), _ptr(ac, ctypes.c_int32), _ptr(av, ctypes.c_double)
+            if getattr(lv, "P", None) is not None and i + 1 < len(levels):
+                P = lv.P.tocsr()
+                pp, pc, pv = _arr(P.indptr, np.int64), _arr(P.indices, np.int32), _arr(P.data, np.float64)
+                keep += [pp, pc, pv]
+                s.n_coarse = P.shape[1]
+                s.p_row_ptr, s.p_col, s.p_val = (_ptr(pp, ctypes.c_int64), _ptr(pc, ctypes.c_int32),
+                                                 _ptr(pv, ctypes.c_double))
+                s.r_scale = float(lv.r_scale)
+            col = getattr(lv, "colour", None)
+            if col is not None:
+                c = _arr(col, np.int32)
+                keep.append(c)
+                s.colour = _ptr(c, ctypes.c_int32)
+        self._check(self._lib.cs_set_hierarchy(self._h, len(levels), arr))
+        self.n_levels = len(levels)
+        self.sizes = [(int(lv.A.shape[0]), int(lv.block_size)) for lv in levels]
+
+    def setup(self, depth: int = 3, mode: str = "additive", order: str = "RF", n_pre: int = 1,
+              n_post: int = 1, alpha: int = 0, precision: str = "fp64"):
+        o = cs_options(depth, _MODES[mode], _ORDERS[order], n_pre, n_post, alpha, _PRECS[precision])
+        self.depth = depth
+        self._check(self._lib.cs_setup(self._h, ctypes.byref(o)))
+
+    def set_precision(self, precision: str):
+        self._check(self._lib.cs_set_precision(self._h, _PRECS[precision]))
+
+    def get_smoother(self, level: int, ell: int) -> np.ndarray:
+        n, nb = self.sizes[level]
+        out = np.empty((n // nb, nb, nb), dtype=np.float64)
+        self._check(self._lib.cs_get_smoother(self._h, level, ell, _ptr(out, ctypes.c_double)))
+        return out
+
+    def set_smoother(self, level: int, ell: int, blocks: np.ndarray):
+        b = _arr(blocks, np.float64)
+        n, nb = self.sizes[level]
+        if b.size != n * nb:
+            raise ValueError("smoother has the wrong size")
+        self._check(self._lib.cs_set_smoother(self._h, level, ell, _ptr(b, ctypes.c_double)))
+
+    def get_pattern(self, level: int, step: int):
+        nnz = ctypes.c_int64()
+        self._check(self._lib.cs_get_pattern_size(self._h, level, step, ctypes.byref(nnz)))
+        n, nb = self.sizes[level]
+        ptr = np.empty(n // nb + 1, dtype=np.int64)
+        col = np.empty(max(nnz.value, 1), dtype=np.int32)
+        self._check(self._lib.cs_get_pattern(self._h, level, step, _ptr(ptr, ctypes.c_int64),
+                                             _ptr(col, ctypes.c_int32)))
+        return ptr, col[:nnz.value]
+
+    def get_colours(self, level: int) -> np.ndarray:
+        n, nb = self.sizes[level]
+        out = np.empty(n // nb, dtype=np.int32)
+        self._check(self._lib.cs_get_colours(self._h, level, _ptr(out, ctypes.c_int32)))
+        return out
+
+    # -- application ----------------------------------------------------------
+    def _vec(self, b):
+        t = self._torch
+        if not isinstance(b, t.Tensor):
+            b = t.as_tensor(np.asarray(b, dtype=np.float64))
+        b = b.to(device=self.device, dtype=t.float64)
+        if b.dim() == 1:
+            b = b[:, None]
+        b = b.contiguous()
+        if b.data_ptr() % 64:
+            b = b.clone()       # the kernels load whole rows as 16-byte vectors
+        return b
+
+    def smooth(self, level: int, b, x, reverse: bool = False):
+        b = self._vec(b)
+        x = self._vec(x).clone()
+        self._check(self._lib.cs_smooth(self._h, level, int(reverse), _tensor_ptr(b), _tensor_ptr(x), b.shape[1]))
+        return x
+
+    def vcycle(self, b):
+        b = self._vec(b)
+        x = self._torch.empty_like(b)
+        self._check(self._lib.cs_vcycle(self._h, _tensor_ptr(b), _tensor_ptr(x), b.shape[1]))
+        return x
+
+    def solve(self, b, rtol: float = 1e-10, maxit: int = 100, x=None, raise_on_noconv: bool = True):
+        b = self._vec(b)
+        if x is None:
+            x = self._torch.empty_like(b)
+        info = cs_info()
+        hist = np.full(maxit + 1, np.nan)
+        st = self._lib.cs_solve(self._h, _tensor_ptr(b), _tensor_ptr(x), b.shape[1], rtol, maxit,
+                                ctypes.byref(info), _ptr(hist, ctypes.c_double))
+        if st != 0 and not (st == -6 and not raise_on_noconv):
+            self._check(st)
+        k = info.iterations
+        return x, dict(iterations=k, rel_res=info.rel_res, rho=info.rho, setup_ms=info.setup_ms,
+                       solve_ms=info.solve_ms, singular_blocks=info.singular_blocks,
+                       history=hist[:k + 1].copy(), status=st)
+
+    def save(self, path: str):
+        self._check(self._lib.cs_save_setup(self._h, path.encode()))
+
+    def load(self, path: str):
+        self._check(self._lib.cs_load_setup(self._h, path.encode()))

@@ -1,0 +1,417 @@
+// C ABI of the cascading-smoother multigrid library; see include/cascade.h.
+#include <cstdio>
+#include <exception>
+#include <fstream>
+
+#include "cs_internal.h"
+
+using cs::Ctx;
+using cs::Level;
+
+namespace {
+
+thread_local std::string g_create_err;
+
+template <class F>
+cs_status guarded(cs_ctx ctx, F &&f) {
+    if (!ctx) return CS_EINVAL;
+    Ctx &c = ctx->c;
+    try {
+        CS_HIP(hipSetDevice(c.device));
+        f(c);
+        c.err.clear();
+        return CS_OK;
+    } catch (const cs::Error &e) {
+        c.err = e.msg;
+        return e.st;
+    } catch (const std::bad_alloc &) {
+        c.err = "host allocation failed";
+        return CS_ENOMEM;
+    } catch (const std::exception &e) {
+        c.err = e.what();
+        return CS_EDEVICE;
+    }
+}
+
+void transpose_csr(int64_t n, int64_t nc, const std::vector<int64_t> &ptr, const std::vector<int32_t> &col,
+                   const std::vector<double> &val, std::vector<int32_t> &tptr, std::vector<int32_t> &tcol,
+                   std::vector<double> &tval) {
+    tptr.assign(nc + 1, 0);
+    for (int32_t c : col) tptr[c + 1]++;
+    for (int64_t i = 0; i < nc; ++i) tptr[i + 1] += tptr[i];
+    tcol.resize(col.size());
+    tval.resize(col.size());
+    std::vector<int32_t> fill(tptr.begin(), tptr.end() - 1);
+    for (int64_t r = 0; r < n; ++r)
+        for (int64_t k = ptr[r]; k < ptr[r + 1]; ++k) {
+            int32_t o = fill[col[k]]++;
+            tcol[o] = (int32_t)r;
+            tval[o] = val[k];
+        }
+}
+
+void need(bool ok, const std::string &msg, cs_status st = CS_EINVAL) {
+    if (!ok) cs::fail(st, msg);
+}
+
+void set_level(Ctx &c, Level &L, const cs_level &in, int li, int nlev, int64_t n_next) {
+    need(in.n > 0 && in.n < INT32_MAX, "level " + std::to_string(li) + ": n out of range");
+    need(in.block_size >= 1 && in.n % in.block_size == 0, "level " + std::to_string(li) + ": block size must divide n");
+    need(in.a_row_ptr && in.a_col && in.a_val, "level " + std::to_string(li) + ": A is missing");
+    L.n = in.n;
+    L.nb = in.block_size;
+    L.B = in.n / in.block_size;
+    L.h_ptr.assign(in.a_row_ptr, in.a_row_ptr + in.n + 1);
+    need(L.h_ptr[0] == 0, "A row pointer must start at 0");
+    for (int64_t r = 0; r < in.n; ++r) need(L.h_ptr[r + 1] >= L.h_ptr[r], "A row pointer must be non-decreasing");
+    L.nnz = L.h_ptr[in.n];
+    need(L.nnz < INT32_MAX, "A has too many entries for 32-bit offsets");
+    L.h_col.assign(in.a_col, in.a_col + L.nnz);
+    L.h_val.assign(in.a_val, in.a_val + L.nnz);
+    for (int64_t r = 0; r < in.n; ++r) {
+        double d = 0.0;
+        bool found = false;
+        for (int64_t k = L.h_ptr[r]; k < L.h_ptr[r + 1]; ++k) {
+            need(L.h_col[k] >= 0 && L.h_col[k] < in.n, "A column index out of range");
+            if (L.h_col[k] == r) {
+                d += L.h_val[k];
+                found = true;
+            }
+        }
+        need(found && d > 0.0, "level " + std::to_string(li) + ": diagonal entry of row " + std::to_string(r) +
+                                   " is not positive (elliptic prescaling needs a_kk > 0)");
+    }
+    L.colour_given = in.colour != nullptr;
+    L.h_colour.clear();
+    if (L.colour_given) {
+        L.h_colour.assign(in.colour, in.colour + L.B);
+        for (int32_t v : L.h_colour) need(v >= 0 && v < 4096, "colours must be in [0, 4096)");
+    }
+    if (li + 1 < nlev) {
+        need(in.n_coarse == n_next, "level " + std::to_string(li) + ": n_coarse differs from the next level's n");
+        need(in.p_row_ptr && in.p_col && in.p_val, "level " + std::to_string(li) + ": P is missing");
+        std::vector<int64_t> pp(in.p_row_ptr, in.p_row_ptr + in.n + 1);
+        need(pp[0] == 0, "P row pointer must start at 0");
+        const int64_t pn = pp[in.n];
+        std::vector<int32_t> pc(in.p_col, in.p_col + pn);
+        std::vector<double> pv(in.p_val, in.p_val + pn);
+        for (int32_t v : pc) need(v >= 0 && v < n_next, "P column index out of range");
+        L.nc = n_next;
+        L.r_scale = in.r_scale;
+        std::vector<int32_t> tp, tc;
+        std::vector<double> tv;
+        transpose_csr(in.n, n_next, pp, pc, pv, tp, tc, tv);
+        std::vector<int32_t> pp32(pp.begin(), pp.end());
+        L.p_ptr.upload(pp32.data(), pp32.size(), c.stream);
+        L.p_col.upload(pc.data(), pc.size(), c.stream);
+        L.p_val64.upload(pv.data(), pv.size(), c.stream);
+        std::vector<float> pvf(pv.begin(), pv.end());
+        L.p_val32.upload(pvf.data(), pvf.size(), c.stream);
+        L.pt_ptr.upload(tp.data(), tp.size(), c.stream);
+        L.pt_col.upload(tc.data(), tc.size(), c.stream);
+        L.pt_val64.upload(tv.data(), tv.size(), c.stream);
+        std::vector<float> tvf(tv.begin(), tv.end());
+        L.pt_val32.upload(tvf.data(), tvf.size(), c.stream);
+        CS_HIP(hipStreamSynchronize(c.stream));
+    }
+    cs::build_level_device(c, L);
+}
+
+const uint64_t SAVE_MAGIC = 0x3150555445535343ull;  // "CSSETUP1"
+const int32_t SAVE_VERSION = 1;
+
+}  // namespace
+
+extern "C" {
+
+int32_t cs_abi_version(void) { return CS_ABI_VERSION; }
+
+const char *cs_status_string(int32_t s) {
+    switch (s) {
+        case CS_OK: return "ok";
+        case CS_EINVAL: return "invalid argument";
+        case CS_ENOMEM: return "out of device memory";
+        case CS_EDEVICE: return "HIP device error";
+        case CS_ESINGULAR: return "singular normal equations";
+        case CS_ECOLOR: return "improper colouring";
+        case CS_ENOCONV: return "no convergence within maxit";
+        case CS_ESTATE: return "call out of order";
+        case CS_ENAN: return "NaN or Inf in the solve";
+        case CS_EVERSION: return "saved setup has another version";
+        case CS_EIO: return "file input/output failed";
+        default: return "unknown status";
+    }
+}
+
+cs_status cs_create(cs_ctx *out, int32_t device, void *stream) {
+    if (!out) return CS_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+        (void)hipGetLastError();
+        g_create_err = "no HIP device available";
+        return CS_EDEVICE;
+    }
+    if (device < 0 || device >= ndev) {
+        g_create_err = "device index out of range";
+        return CS_EINVAL;
+    }
+    if (hipSetDevice(device) != hipSuccess) {
+        g_create_err = "hipSetDevice failed";
+        return CS_EDEVICE;
+    }
+    cs_ctx h = new (std::nothrow) cs_ctx_s;
+    if (!h) return CS_ENOMEM;
+    h->c.device = device;
+    h->c.stream = reinterpret_cast<hipStream_t>(stream);
+    if (hipEventCreate(&h->c.ev0) != hipSuccess || hipEventCreate(&h->c.ev1) != hipSuccess) {
+        g_create_err = "hipEventCreate failed";
+        delete h;
+        return CS_EDEVICE;
+    }
+    *out = h;
+    return CS_OK;
+}
+
+void cs_destroy(cs_ctx ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->c.device);
+    (void)hipStreamSynchronize(ctx->c.stream);
+    if (ctx->c.ev0) (void)hipEventDestroy(ctx->c.ev0);
+    if (ctx->c.ev1) (void)hipEventDestroy(ctx->c.ev1);
+    delete ctx;
+}
+
+const char *cs_last_error(cs_ctx ctx) { return ctx ? ctx->c.err.c_str() : g_create_err.c_str(); }
+
+cs_status cs_set_hierarchy(cs_ctx ctx, int32_t n_levels, const cs_level *levels) {
+    return guarded(ctx, [&](Ctx &c) {
+        need(n_levels >= 1 && levels != nullptr, "need at least one level");
+        c.have_setup = false;
+        c.have_hierarchy = false;
+        c.ws_nrhs = 0;
+        c.lv.clear();
+        c.lv.resize(n_levels);
+        for (int l = 0; l < n_levels; ++l)
+            set_level(c, c.lv[l], levels[l], l, n_levels, l + 1 < n_levels ? levels[l + 1].n : 0);
+        need(c.lv.back().n <= 8192, "bottom level larger than 8192 unknowns");
+        c.have_hierarchy = true;
+    });
+}
+
+cs_status cs_setup(cs_ctx ctx, const cs_options *opt) {
+    return guarded(ctx, [&](Ctx &c) {
+        need(c.have_hierarchy, "cs_setup before cs_set_hierarchy", CS_ESTATE);
+        need(opt != nullptr, "options missing");
+        need(opt->depth >= 1 && opt->depth <= 16, "depth must be in [1, 16]");
+        need(opt->mode == CS_ADDITIVE || opt->mode == CS_MULTIPLICATIVE, "mode must be additive or multiplicative");
+        need(opt->order == CS_FF || opt->order == CS_RF, "order must be FF or RF");
+        need(opt->n_pre >= 1 && opt->n_post >= 0, "need n_pre >= 1 and n_post >= 0");
+        need(opt->trunc_alpha >= 0, "trunc_alpha must be >= 0");
+        need(opt->precision == CS_FP64 || opt->precision == CS_FP32, "precision must be FP64 or FP32");
+        c.have_setup = false;
+        c.opt = *opt;
+        c.precision = opt->precision;
+        c.ws_nrhs = 0;
+        cs::run_setup(c, *opt);
+        c.have_setup = true;
+    });
+}
+
+cs_status cs_set_precision(cs_ctx ctx, int32_t precision) {
+    return guarded(ctx, [&](Ctx &c) {
+        need(c.have_setup, "cs_set_precision before cs_setup", CS_ESTATE);
+        need(precision == CS_FP64 || precision == CS_FP32, "precision must be FP64 or FP32");
+        c.precision = precision;
+        c.opt.precision = precision;
+    });
+}
+
+cs_status cs_get_smoother(cs_ctx ctx, int32_t level, int32_t ell, double *out) {
+    return guarded(ctx, [&](Ctx &c) {
+        need(c.have_setup, "no setup", CS_ESTATE);
+        need(level >= 0 && level + 1 < (int)c.lv.size(), "level has no smoother");
+        Level &L = c.lv[level];
+        need(ell >= 1 && ell <= L.depth && out, "ell out of range");
+        const size_t nbl = L.B * L.nb * L.nb;
+        CS_HIP(hipMemcpyAsync(out, L.lam64.get() + (ell - 1) * nbl, nbl * sizeof(double), hipMemcpyDeviceToHost,
+                              c.stream));
+        CS_HIP(hipStreamSynchronize(c.stream));
+    });
+}
+
+cs_status cs_set_smoother(cs_ctx ctx, int32_t level, int32_t ell, const double *blocks) {
+    return guarded(ctx, [&](Ctx &c) {
+        need(c.have_setup, "no setup", CS_ESTATE);
+        need(level >= 0 && level + 1 < (int)c.lv.size(), "level has no smoother");
+        Level &L = c.lv[level];
+        need(ell >= 1 && ell <= L.depth && blocks, "ell out of range");
+        const size_t nbl = L.B * L.nb * L.nb;
+        CS_HIP(hipMemcpyAsync(L.lam64.get() + (ell - 1) * nbl, blocks, nbl * sizeof(double), hipMemcpyHostToDevice,
+                              c.stream));
+        cs::build_working_copies(c);
+    });
+}
+
+cs_status cs_get_pattern_size(cs_ctx ctx, int32_t level, int32_t step, int64_t *nnzb) {
+    return guarded(ctx, [&](Ctx &c) {
+        need(c.have_setup, "no setup", CS_ESTATE);
+        need(level >= 0 && level + 1 < (int)c.lv.size(), "level has no smoother");
+        Level &L = c.lv[level];
+        need(step >= 0 && step < (int)L.patterns.size() && nnzb, "step out of range");
+        *nnzb = L.patterns[step].nnzb;
+    });
+}
+
+cs_status cs_get_pattern(cs_ctx ctx, int32_t level, int32_t step, int64_t *row_ptr, int32_t *col) {
+    return guarded(ctx, [&](Ctx &c) {
+        need(c.have_setup, "no setup", CS_ESTATE);
+        need(level >= 0 && level + 1 < (int)c.lv.size(), "level has no smoother");
+        Level &L = c.lv[level];
+        need(step >= 0 && step < (int)L.patterns.size() && row_ptr && col, "step out of range");
+        const cs::BPattern &p = L.patterns[step];
+        std::vector<int32_t> hp(p.rows + 1);
+        p.ptr.download(hp.data(), p.rows + 1, c.stream);
+        p.col.download(col, p.nnzb, c.stream);
+        CS_HIP(hipStreamSynchronize(c.stream));
+        for (int64_t i = 0; i <= p.rows; ++i) row_ptr[i] = hp[i];
+    });
+}
+
+cs_status cs_get_colours(cs_ctx ctx, int32_t level, int32_t *out) {
+    return guarded(ctx, [&](Ctx &c) {
+        need(c.have_setup, "no setup", CS_ESTATE);
+        need(level >= 0 && level + 1 < (int)c.lv.size() && out, "level has no smoother");
+        Level &L = c.lv[level];
+        need(c.opt.mode == CS_MULTIPLICATIVE, "colours exist in multiplicative mode only", CS_ESTATE);
+        std::copy(L.h_colour.begin(), L.h_colour.end(), out);
+    });
+}
+
+cs_status cs_smooth(cs_ctx ctx, int32_t level, int32_t reverse, const double *b, double *x, int32_t nrhs) {
+    return guarded(ctx, [&](Ctx &c) {
+        need(c.have_setup, "no setup", CS_ESTATE);
+        need(level >= 0 && level + 1 < (int)c.lv.size(), "level has no smoother");
+        need(b && x, "null vector");
+        cs::smooth_apply(c, level, reverse != 0, b, x, nrhs);
+        CS_HIP(hipStreamSynchronize(c.stream));
+    });
+}
+
+cs_status cs_vcycle(cs_ctx ctx, const double *b, double *x, int32_t nrhs) {
+    return guarded(ctx, [&](Ctx &c) {
+        need(c.have_setup, "cs_vcycle before cs_setup", CS_ESTATE);
+        need(b && x, "null vector");
+        cs::vcycle_apply(c, b, x, nrhs);
+        CS_HIP(hipStreamSynchronize(c.stream));
+    });
+}
+
+cs_status cs_solve(cs_ctx ctx, const double *b, double *x, int32_t nrhs, double rtol, int32_t maxit, cs_info *info,
+                   double *history) {
+    cs_status st = CS_OK;
+    cs_status g = guarded(ctx, [&](Ctx &c) {
+        need(c.have_setup, "cs_solve before cs_setup", CS_ESTATE);
+        need(b && x, "null vector");
+        need(maxit >= 0 && rtol >= 0.0, "bad rtol or maxit");
+        cs::solve_ir(c, b, x, nrhs, rtol, maxit, info, history, &st);
+    });
+    if (g != CS_OK) return g;
+    if (st != CS_OK) ctx->c.err = cs_status_string(st);
+    return st;
+}
+
+cs_status cs_save_setup(cs_ctx ctx, const char *path) {
+    return guarded(ctx, [&](Ctx &c) {
+        need(c.have_setup, "no setup", CS_ESTATE);
+        need(path != nullptr, "null path");
+        std::ofstream f(path, std::ios::binary);
+        need((bool)f, std::string("cannot open ") + path, CS_EIO);
+        auto put = [&](const void *p, size_t n) { f.write(reinterpret_cast<const char *>(p), (std::streamsize)n); };
+        put(&SAVE_MAGIC, 8);
+        put(&SAVE_VERSION, 4);
+        put(&c.opt, sizeof(c.opt));
+        int32_t nl = (int32_t)c.lv.size();
+        put(&nl, 4);
+        for (size_t l = 0; l < c.lv.size(); ++l) {
+            Level &L = c.lv[l];
+            int64_t hdr[3] = {L.n, L.nb, (int64_t)L.h_colour.size()};
+            put(hdr, sizeof(hdr));
+            put(L.h_colour.data(), L.h_colour.size() * 4);
+            std::vector<double> buf;
+            if (l + 1 < c.lv.size()) {
+                buf.resize((size_t)L.depth * L.B * L.nb * L.nb);
+                L.lam64.download(buf.data(), buf.size(), c.stream);
+            } else {
+                buf.resize((size_t)L.n * L.n);
+                L.ainv.download(buf.data(), buf.size(), c.stream);
+            }
+            CS_HIP(hipStreamSynchronize(c.stream));
+            int64_t cnt = (int64_t)buf.size();
+            put(&cnt, 8);
+            put(buf.data(), buf.size() * 8);
+        }
+        need((bool)f, std::string("write failed: ") + path, CS_EIO);
+    });
+}
+
+cs_status cs_load_setup(cs_ctx ctx, const char *path) {
+    return guarded(ctx, [&](Ctx &c) {
+        need(c.have_hierarchy, "cs_load_setup before cs_set_hierarchy", CS_ESTATE);
+        need(path != nullptr, "null path");
+        std::ifstream f(path, std::ios::binary);
+        need((bool)f, std::string("cannot open ") + path, CS_EIO);
+        auto get = [&](void *p, size_t n) {
+            f.read(reinterpret_cast<char *>(p), (std::streamsize)n);
+            need((bool)f, "truncated setup file", CS_EIO);
+        };
+        uint64_t magic = 0;
+        int32_t ver = 0;
+        get(&magic, 8);
+        need(magic == SAVE_MAGIC, "not a setup file", CS_EIO);
+        get(&ver, 4);
+        need(ver == SAVE_VERSION, "setup file version mismatch", CS_EVERSION);
+        cs_options o;
+        get(&o, sizeof(o));
+        int32_t nl = 0;
+        get(&nl, 4);
+        need(nl == (int32_t)c.lv.size(), "setup file is for another hierarchy");
+        c.have_setup = false;
+        for (int l = 0; l < nl; ++l) {
+            Level &L = c.lv[l];
+            int64_t hdr[3];
+            get(hdr, sizeof(hdr));
+            need(hdr[0] == L.n && hdr[1] == L.nb, "setup file is for another hierarchy");
+            need(hdr[2] >= 0 && hdr[2] <= L.B, "bad colour count in setup file", CS_EIO);
+            L.h_colour.resize(hdr[2]);
+            get(L.h_colour.data(), hdr[2] * 4);
+            int64_t cnt = 0;
+            get(&cnt, 8);
+            std::vector<double> buf(cnt);
+            get(buf.data(), cnt * 8);
+            if (l + 1 < nl) {
+                need(cnt % (L.B * L.nb * L.nb) == 0, "bad smoother size in setup file", CS_EIO);
+                L.depth = (int)(cnt / (L.B * L.nb * L.nb));
+                L.lam64.upload(buf.data(), cnt, c.stream);
+                CS_HIP(hipStreamSynchronize(c.stream));
+                if (o.mode == CS_MULTIPLICATIVE) {
+                    need((int64_t)L.h_colour.size() == L.B, "missing colours in setup file", CS_EIO);
+                    cs::build_colour_layout(c, L);
+                }
+            } else {
+                need(cnt == L.n * L.n, "bad bottom factor in setup file", CS_EIO);
+                L.ainv.upload(buf.data(), cnt, c.stream);
+                CS_HIP(hipStreamSynchronize(c.stream));
+            }
+            L.patterns.clear();
+        }
+        CS_HIP(hipStreamSynchronize(c.stream));
+        c.opt = o;
+        c.precision = o.precision;
+        c.ws_nrhs = 0;
+        cs::build_working_copies(c);
+        c.have_setup = true;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,177 @@
+// Internal declarations of the cascading-smoother multigrid library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/cascade.h"
+
+namespace cs {
+
+struct Error {
+    cs_status st;
+    std::string msg;
+};
+
+[[noreturn]] inline void fail(cs_status st, const std::string &msg) { throw Error{st, msg}; }
+
+#define CS_HIP(call)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            ::cs::fail(CS_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+#define CS_LAUNCH_CHECK() CS_HIP(hipGetLastError())
+
+// Owning device buffer.
+template <class T>
+struct DBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DBuf() = default;
+    explicit DBuf(size_t count) { alloc(count); }
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    DBuf(DBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DBuf &operator=(DBuf &&o) noexcept {
+        if (this != &o) {
+            release();
+            p = o.p;
+            n = o.n;
+            o.p = nullptr;
+            o.n = 0;
+        }
+        return *this;
+    }
+    ~DBuf() { release(); }
+    void alloc(size_t count) {
+        release();
+        if (count == 0) return;
+        if (hipMalloc(reinterpret_cast<void **>(&p), count * sizeof(T)) != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            fail(CS_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+        }
+        n = count;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    T *get() const { return p; }
+    size_t bytes() const { return n * sizeof(T); }
+    void upload(const T *h, size_t count, hipStream_t s) {
+        if (count > n) alloc(count);
+        if (count) CS_HIP(hipMemcpyAsync(p, h, count * sizeof(T), hipMemcpyHostToDevice, s));
+    }
+    void download(T *h, size_t count, hipStream_t s) const {
+        if (count) CS_HIP(hipMemcpyAsync(h, p, count * sizeof(T), hipMemcpyDeviceToHost, s));
+    }
+};
+
+// Sliced ELLPACK (slice height 64 = one wavefront) of a scalar sparse matrix,
+// over a list of rows (rows == nullptr: rows 0..nrows-1 in order).  Entry k of
+// lane l in slice s sits at slice_ptr[s] + k*64 + l; padding entries point at
+// the row itself with value 0.
+struct Sell {
+    int64_t nrows = 0;      // valid rows
+    int64_t nslices = 0;
+    DBuf<int32_t> rows;     // [nslices*64] row ids (-1 past the end) or empty
+    DBuf<int64_t> slice_ptr;
+    DBuf<int32_t> slice_len;
+    DBuf<int32_t> col;
+    DBuf<double> val64;
+    DBuf<float> val32;
+    int64_t entries = 0;
+};
+
+// Block CSR pattern on the device (+ optional values).
+struct BPattern {
+    int64_t rows = 0, nnzb = 0;
+    DBuf<int32_t> ptr, col;
+};
+
+struct Level {
+    int64_t n = 0, nb = 1, B = 0, nnz = 0;
+    // host copies of the input (kept for layout builds and save/load)
+    std::vector<int64_t> h_ptr;
+    std::vector<int32_t> h_col;
+    std::vector<double> h_val;
+    std::vector<int32_t> h_colour;   // supplied or computed block colours
+    bool colour_given = false;
+    // device CSR of A
+    DBuf<int32_t> a_ptr, a_col;
+    DBuf<double> a_val;
+    Sell sell;                        // all rows, natural order
+    std::vector<Sell> csell;          // per-colour rows (multiplicative)
+    DBuf<int32_t> clist;              // blocks sorted by colour
+    std::vector<int64_t> cptr;        // colour offsets into clist
+    int chi = 0;
+    DBuf<int32_t> colour;             // device colours
+    // interpolation to the next coarser level
+    int64_t nc = 0;
+    double r_scale = 1.0;
+    DBuf<int32_t> p_ptr, p_col, pt_ptr, pt_col;
+    DBuf<double> p_val64, pt_val64;
+    DBuf<float> p_val32, pt_val32;
+    // prescaling and smoother
+    DBuf<double> w;
+    int depth = 0;
+    DBuf<double> lam64, lam64T;       // [depth][B][nb][nb] and per-block transposes
+    DBuf<float> lam32, lam32T;
+    std::vector<BPattern> patterns;   // E after every fit step
+    int singular = 0;
+    // bottom level: dense inverse (row-major n x n)
+    DBuf<double> ainv;
+    // V-cycle workspace (working precision), [n][nrhs]
+    DBuf<char> xb, xt, bb, rr;
+};
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    std::vector<Level> lv;
+    bool have_hierarchy = false, have_setup = false;
+    cs_options opt{};
+    int precision = CS_FP64;
+    int ws_nrhs = 0, ws_prec = -1;
+    double setup_ms = 0;
+    int singular = 0;
+    // solve workspace
+    DBuf<double> ir_partial, ir_norm;
+    DBuf<char> ir_r;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+// setup.hip
+void build_level_device(Ctx &c, Level &L);
+void run_setup(Ctx &c, const cs_options &o);
+void build_working_copies(Ctx &c);
+void factor_bottom(Ctx &c, Level &L);
+void build_colour_layout(Ctx &c, Level &L);
+
+// solve.hip
+void ensure_workspace(Ctx &c, int nrhs);
+void vcycle_apply(Ctx &c, const double *b, double *x, int nrhs);
+void smooth_apply(Ctx &c, int level, bool reverse, const double *b, double *x, int nrhs);
+void solve_ir(Ctx &c, const double *b, double *x, int nrhs, double rtol, int maxit, cs_info *info,
+              double *history, cs_status *st);
+
+// host helpers
+void build_sell(Sell &S, const std::vector<int64_t> &ptr, const std::vector<int32_t> &col,
+                const std::vector<double> &val, const std::vector<int32_t> *rows, hipStream_t s);
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace cs
+
+struct cs_ctx_s {
+    cs::Ctx c;
+};

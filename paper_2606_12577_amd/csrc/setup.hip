@@ -1,0 +1,1016 @@
+// Setup of cascading smoothers on the GPU (gfx950, wave64).
+//
+// Implements, per multigrid level, the construction of Sec. 2.1-2.3:
+//   prescale      W = diag(a_kk^{-1/2}), A~ = W A W            (Sec. 2.3.1)
+//   symbolic      pattern(M_i) = union_{j in adj(i)} pattern(E_j)
+//   row product   M_i = sum_j A~_ij E_j,:                       (Alg. 2, LS step)
+//   normal eqs    G_i = M_i M_i^T, H_i = E_i M_i^T, Lambda~_i = H_i G_i^{-1}
+//   update        E_i <- E_i - Lambda~_i M_i                     (Alg. 2, update)
+//   truncation    keep the alpha largest blocks of a row of E   (Alg. 2, option)
+//   unscale       Lambda_i = W_i Lambda~_i W_i                   (Alg. 2, last step)
+// The multicoloured variant (Sec. 2.2) runs the same fit step over the blocks of
+// one colour at a time, leaving the rows of the other colours untouched.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "cs_internal.h"
+
+namespace cs {
+
+namespace {
+
+constexpr int WG = 256;
+constexpr int UNION_CAP = 4096;   // candidate columns per row in the symbolic step
+constexpr int MATCH_CAP = 8192;   // (column, neighbour) matches cached per row
+constexpr int MAXNB = 16;
+constexpr double PIVOT_TOL = 1e-13;
+
+__device__ inline int bsearch_i32(const int32_t *a, int lo, int hi, int32_t key) {
+    // index of key in the sorted range a[lo, hi), or -1
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        int32_t v = a[mid];
+        if (v == key) return mid;
+        if (v < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return -1;
+}
+
+// ---------------------------------------------------------------------------
+// prescaling
+// ---------------------------------------------------------------------------
+__global__ void k_prescale_w(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                             const double *__restrict__ val, int64_t n, double *__restrict__ w) {
+    int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    double d = 0.0;
+    for (int k = ptr[r]; k < ptr[r + 1]; ++k)
+        if (col[k] == r) d = val[k];
+    w[r] = 1.0 / sqrt(d);
+}
+
+// A~ as dense nb x nb blocks on the block pattern of A.
+__global__ void k_scatter_blocks(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                                 const double *__restrict__ val, const double *__restrict__ w, int64_t n, int nb,
+                                 const int32_t *__restrict__ bptr, const int32_t *__restrict__ bcol,
+                                 double *__restrict__ bval) {
+    int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    int i = (int)(r / nb), lr = (int)(r % nb);
+    for (int k = ptr[r]; k < ptr[r + 1]; ++k) {
+        int c = col[k];
+        int pos = bsearch_i32(bcol, bptr[i], bptr[i + 1], c / nb);
+        if (pos < 0) continue;  // cannot happen: the block pattern covers every entry
+        bval[(int64_t)pos * nb * nb + lr * nb + (c % nb)] = val[k] * w[r] * w[c];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// symbolic union of sorted column lists (one workgroup per output row)
+// ---------------------------------------------------------------------------
+// SRC_SCALAR: candidates of block row i are the block columns of the scalar
+//             entries of its nb rows (the block pattern of A).
+// SRC_E:      candidates are the columns of E_j for j in the block row i of A.
+enum { SRC_SCALAR = 0, SRC_E = 1 };
+
+template <int SRC, bool FILL>
+__global__ __launch_bounds__(WG) void k_union(const int32_t *__restrict__ list, int nlist, int nb,
+                                              const int32_t *__restrict__ sptr, const int32_t *__restrict__ scol,
+                                              const int32_t *__restrict__ eptr, const int32_t *__restrict__ ecol,
+                                              int32_t *__restrict__ out_cnt, const int32_t *__restrict__ out_ptr,
+                                              int32_t *__restrict__ out_col, int32_t *__restrict__ err) {
+    __shared__ int32_t cand[UNION_CAP];
+    __shared__ int32_t offs[257];
+    __shared__ int32_t part[WG + 1];
+    __shared__ int32_t total_s;
+    const int li = blockIdx.x;
+    if (li >= nlist) return;
+    const int i = list ? list[li] : li;
+    const int t = threadIdx.x;
+    int total;
+    if (SRC == SRC_SCALAR) {
+        int lo = sptr[(int64_t)i * nb], hi = sptr[(int64_t)(i + 1) * nb];
+        total = hi - lo;
+        if (total > UNION_CAP) {
+            if (t == 0) err[li] = 1;
+            if (!FILL && t == 0) out_cnt[li] = 0;
+            return;
+        }
+        for (int k = t; k < total; k += WG) cand[k] = scol[lo + k] / nb;
+    } else {
+        int lo = sptr[i], hi = sptr[i + 1];
+        int deg = hi - lo;
+        if (deg > 256) {
+            if (t == 0) err[li] = 2;
+            if (!FILL && t == 0) out_cnt[li] = 0;
+            return;
+        }
+        if (t < deg) {
+            int j = scol[lo + t];
+            offs[t + 1] = eptr[j + 1] - eptr[j];
+        }
+        __syncthreads();
+        if (t == 0) {
+            offs[0] = 0;
+            for (int q = 0; q < deg; ++q) offs[q + 1] += offs[q];
+            total_s = offs[deg];
+        }
+        __syncthreads();
+        total = total_s;
+        if (total > UNION_CAP) {
+            if (t == 0) err[li] = 1;
+            if (!FILL && t == 0) out_cnt[li] = 0;
+            return;
+        }
+        for (int k = t; k < total; k += WG) {
+            int q = 0;
+            while (offs[q + 1] <= k) ++q;
+            int j = scol[lo + q];
+            cand[k] = ecol[eptr[j] + (k - offs[q])];
+        }
+    }
+    int P = 1;
+    while (P < total) P <<= 1;
+    for (int k = total + t; k < P; k += WG) cand[k] = INT32_MAX;
+    __syncthreads();
+    // bitonic sort of cand[0, P)
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int a = t; a < P; a += WG) {
+                int b = a ^ j;
+                if (b > a) {
+                    int32_t x = cand[a], y = cand[b];
+                    bool up = (a & k) == 0;
+                    if ((x > y) == up) {
+                        cand[a] = y;
+                        cand[b] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // unique: each thread owns a contiguous chunk
+    const int chunk = (P + WG - 1) / WG;
+    const int a0 = t * chunk, a1 = min(P, a0 + chunk);
+    int mine = 0;
+    for (int a = a0; a < a1; ++a) {
+        int32_t v = cand[a];
+        if (v != INT32_MAX && (a == 0 || cand[a - 1] != v)) ++mine;
+    }
+    part[t + 1] = mine;
+    __syncthreads();
+    if (t == 0) {
+        part[0] = 0;
+        for (int q = 0; q < WG; ++q) part[q + 1] += part[q];
+    }
+    __syncthreads();
+    if (!FILL) {
+        if (t == 0) out_cnt[li] = part[WG];
+    } else {
+        int o = out_ptr[li] + part[t];
+        for (int a = a0; a < a1; ++a) {
+            int32_t v = cand[a];
+            if (v != INT32_MAX && (a == 0 || cand[a - 1] != v)) out_col[o++] = v;
+        }
+    }
+}
+
+// exclusive scan of cnt[0, n) into ptr[0, n]; one workgroup of 1024 threads
+__global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ cnt, int64_t n, int32_t *__restrict__ ptr,
+                                               int64_t *__restrict__ total_out) {
+    __shared__ int64_t part[1025];
+    const int t = threadIdx.x;
+    const int64_t chunk = (n + 1023) / 1024;
+    const int64_t a0 = t * chunk, a1 = min(n, a0 + chunk);
+    int64_t s = 0;
+    for (int64_t a = a0; a < a1; ++a) s += cnt[a];
+    part[t + 1] = s;
+    __syncthreads();
+    if (t == 0) {
+        part[0] = 0;
+        for (int q = 0; q < 1024; ++q) part[q + 1] += part[q];
+        total_out[0] = part[1024];
+        ptr[n] = (int32_t)part[1024];
+    }
+    __syncthreads();
+    int64_t o = part[t];
+    for (int64_t a = a0; a < a1; ++a) {
+        ptr[a] = (int32_t)o;
+        o += cnt[a];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// numeric fit step
+// ---------------------------------------------------------------------------
+
+// M_i = sum_{j in adj(i)} A~_ij E_j,:  on pattern(M_i); one workgroup per list row.
+__global__ __launch_bounds__(WG) void k_rowprod(const int32_t *__restrict__ list, int nb,
+                                                const int32_t *__restrict__ abptr, const int32_t *__restrict__ abcol,
+                                                const double *__restrict__ abval, const int32_t *__restrict__ eptr,
+                                                const int32_t *__restrict__ ecol, const double *__restrict__ eval,
+                                                const int32_t *__restrict__ mptr, const int32_t *__restrict__ mcol,
+                                                double *__restrict__ mval) {
+    __shared__ int32_t match[MATCH_CAP];
+    const int li = blockIdx.x;
+    const int i = list[li];
+    const int t = threadIdx.x;
+    const int alo = abptr[i], deg = abptr[i + 1] - alo;
+    const int mlo = mptr[li], k = mptr[li + 1] - mlo;
+    const int nb2 = nb * nb;
+    const bool cached = (int64_t)k * deg <= MATCH_CAP;
+    if (cached) {
+        for (int e = t; e < k * deg; e += WG) {
+            int p = e / deg, jj = e % deg;
+            int j = abcol[alo + jj];
+            match[e] = bsearch_i32(ecol, eptr[j], eptr[j + 1], mcol[mlo + p]);
+        }
+        __syncthreads();
+    }
+    for (int64_t e = t; e < (int64_t)k * nb2; e += WG) {
+        int p = (int)(e / nb2), rs = (int)(e % nb2);
+        int r = rs / nb, s = rs % nb;
+        double acc = 0.0;
+        for (int jj = 0; jj < deg; ++jj) {
+            int q;
+            if (cached) q = match[p * deg + jj];
+            else {
+                int j = abcol[alo + jj];
+                q = bsearch_i32(ecol, eptr[j], eptr[j + 1], mcol[mlo + p]);
+            }
+            if (q < 0) continue;
+            const double *a = abval + (int64_t)(alo + jj) * nb2 + r * nb;
+            const double *ev = eval + (int64_t)q * nb2 + s;
+            for (int u = 0; u < nb; ++u) acc += a[u] * ev[u * nb];
+        }
+        mval[(int64_t)(mlo + p) * nb2 + rs] = acc;
+    }
+}
+
+// Symmetric Jacobi eigen-decomposition of a small SPD-or-singular matrix held in
+// g (row-major nb x nb, overwritten by the eigenvalues on its diagonal); v gets
+// the eigenvectors as columns.  Single thread.
+__device__ void jacobi_eig(double *g, double *v, int nb) {
+    for (int a = 0; a < nb; ++a)
+        for (int b = 0; b < nb; ++b) v[a * nb + b] = (a == b) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0, dia = 0.0;
+        for (int a = 0; a < nb; ++a)
+            for (int b = 0; b < nb; ++b) {
+                if (a != b) off += g[a * nb + b] * g[a * nb + b];
+                else dia += g[a * nb + a] * g[a * nb + a];
+            }
+        if (off <= 1e-30 * dia || off == 0.0) break;
+        for (int p = 0; p < nb - 1; ++p)
+            for (int q = p + 1; q < nb; ++q) {
+                double apq = g[p * nb + q];
+                if (apq == 0.0) continue;
+                double app = g[p * nb + p], aqq = g[q * nb + q];
+                double theta = (aqq - app) / (2.0 * apq);
+                double tt = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                double cth = 1.0 / sqrt(tt * tt + 1.0), sth = tt * cth;
+                for (int r = 0; r < nb; ++r) {  // columns p, q
+                    double grp = g[r * nb + p], grq = g[r * nb + q];
+                    g[r * nb + p] = cth * grp - sth * grq;
+                    g[r * nb + q] = sth * grp + cth * grq;
+                }
+                for (int r = 0; r < nb; ++r) {  // rows p, q
+                    double gpr = g[p * nb + r], gqr = g[q * nb + r];
+                    g[p * nb + r] = cth * gpr - sth * gqr;
+                    g[q * nb + r] = sth * gpr + cth * gqr;
+                }
+                for (int r = 0; r < nb; ++r) {
+                    double vrp = v[r * nb + p], vrq = v[r * nb + q];
+                    v[r * nb + p] = cth * vrp - sth * vrq;
+                    v[r * nb + q] = sth * vrp + cth * vrq;
+                }
+            }
+    }
+}
+
+// Normal equations of one block row: G = M M^T, H = E M^T, Lambda~ = H G^{-1}
+// (Cholesky; pseudo-inverse fallback).  One workgroup per list row.
+__global__ __launch_bounds__(WG) void k_gram_solve(const int32_t *__restrict__ list, int nb,
+                                                   const int32_t *__restrict__ mptr, const int32_t *__restrict__ mcol,
+                                                   const double *__restrict__ mval, const int32_t *__restrict__ eptr,
+                                                   const int32_t *__restrict__ ecol, const double *__restrict__ eval,
+                                                   double *__restrict__ lamt, int32_t *__restrict__ singular) {
+    __shared__ double pg[WG], ph[WG];
+    __shared__ double G[MAXNB * MAXNB], H[MAXNB * MAXNB], Lc[MAXNB * MAXNB], V[MAXNB * MAXNB];
+    __shared__ int bad_s;
+    const int li = blockIdx.x;
+    const int i = list[li];
+    const int t = threadIdx.x;
+    const int nb2 = nb * nb;
+    const int S = WG / nb2;
+    const int mlo = mptr[li], k = mptr[li + 1] - mlo;
+    const int elo = eptr[i], ek = eptr[i + 1] - elo;
+    double g = 0.0, h = 0.0;
+    if (t < S * nb2) {
+        const int e = t % nb2, sl = t / nb2;
+        const int r = e / nb, s = e % nb;
+        for (int p = sl; p < k; p += S) {
+            const double *mp = mval + (int64_t)(mlo + p) * nb2;
+            for (int u = 0; u < nb; ++u) g += mp[r * nb + u] * mp[s * nb + u];
+        }
+        for (int q = sl; q < ek; q += S) {
+            int p = bsearch_i32(mcol, mlo, mlo + k, ecol[elo + q]);
+            if (p < 0) continue;  // pattern(E_i) is contained in pattern(M_i)
+            const double *mp = mval + (int64_t)p * nb2;
+            const double *ep = eval + (int64_t)(elo + q) * nb2;
+            for (int u = 0; u < nb; ++u) h += ep[r * nb + u] * mp[s * nb + u];
+        }
+    }
+    pg[t] = g;
+    ph[t] = h;
+    __syncthreads();
+    if (t < nb2) {
+        double sg = 0.0, sh = 0.0;
+        for (int sl = 0; sl < S; ++sl) {
+            sg += pg[sl * nb2 + t];
+            sh += ph[sl * nb2 + t];
+        }
+        G[t] = sg;
+        H[t] = sh;
+    }
+    __syncthreads();
+    if (t == 0) {
+        // Cholesky G = L L^T
+        double dmax = 0.0;
+        for (int a = 0; a < nb; ++a) dmax = fmax(dmax, G[a * nb + a]);
+        int bad = !(dmax > 0.0);
+        for (int a = 0; a < nb && !bad; ++a) {
+            for (int b = 0; b <= a; ++b) {
+                double s = G[a * nb + b];
+                for (int u = 0; u < b; ++u) s -= Lc[a * nb + u] * Lc[b * nb + u];
+                if (a == b) {
+                    if (!(s > PIVOT_TOL * dmax)) {
+                        bad = 1;
+                        break;
+                    }
+                    Lc[a * nb + a] = sqrt(s);
+                } else {
+                    Lc[a * nb + b] = s / Lc[b * nb + b];
+                }
+            }
+        }
+        bad_s = bad;
+        singular[li] = bad;
+    }
+    __syncthreads();
+    double *out = lamt + (int64_t)i * nb2;
+    if (!bad_s) {
+        if (t < nb) {
+            // row r of Lambda~ solves G y = H[r, :]^T
+            const int r = t;
+            double y[MAXNB];
+            for (int a = 0; a < nb; ++a) {
+                double s = H[r * nb + a];
+                for (int u = 0; u < a; ++u) s -= Lc[a * nb + u] * y[u];
+                y[a] = s / Lc[a * nb + a];
+            }
+            for (int a = nb - 1; a >= 0; --a) {
+                double s = y[a];
+                for (int u = a + 1; u < nb; ++u) s -= Lc[u * nb + a] * y[u];
+                y[a] = s / Lc[a * nb + a];
+            }
+            for (int a = 0; a < nb; ++a) out[r * nb + a] = y[a];
+        }
+    } else {
+        if (t == 0) {
+            // minimum-norm solution: Lambda~ = H pinv(G), pinv by eigen-decomposition
+            for (int a = 0; a < nb2; ++a) Lc[a] = G[a];
+            jacobi_eig(Lc, V, nb);
+            double emax = 0.0;
+            for (int a = 0; a < nb; ++a) emax = fmax(emax, fabs(Lc[a * nb + a]));
+            for (int r = 0; r < nb; ++r)
+                for (int c = 0; c < nb; ++c) {
+                    double s = 0.0;
+                    for (int a = 0; a < nb; ++a) {
+                        double ev = Lc[a * nb + a];
+                        if (ev > PIVOT_TOL * emax) {
+                            double hv = 0.0;
+                            for (int u = 0; u < nb; ++u) hv += H[r * nb + u] * V[u * nb + a];
+                            s += hv * V[c * nb + a] / ev;
+                        }
+                    }
+                    out[r * nb + c] = s;
+                }
+        }
+    }
+}
+
+// E_new,i = E_old,i - Lambda~_i M_i for list rows (on pattern(M_i)); other rows
+// are copied.  One workgroup per block row.
+__global__ __launch_bounds__(WG) void k_eupdate(int B, int nb, const int32_t *__restrict__ pos_in_list,
+                                                const int32_t *__restrict__ mptr, const int32_t *__restrict__ mcol,
+                                                const double *__restrict__ mval, const int32_t *__restrict__ eptr,
+                                                const int32_t *__restrict__ ecol, const double *__restrict__ eval,
+                                                const double *__restrict__ lamt, const int32_t *__restrict__ nptr,
+                                                int32_t *__restrict__ ncol, double *__restrict__ nval) {
+    const int i = blockIdx.x;
+    if (i >= B) return;
+    const int t = threadIdx.x;
+    const int nb2 = nb * nb;
+    const int li = pos_in_list[i];
+    const int elo = eptr[i], ek = eptr[i + 1] - elo;
+    const int nlo = nptr[i];
+    if (li < 0) {
+        for (int q = t; q < ek; q += WG) ncol[nlo + q] = ecol[elo + q];
+        for (int64_t e = t; e < (int64_t)ek * nb2; e += WG)
+            nval[(int64_t)nlo * nb2 + e] = eval[(int64_t)elo * nb2 + e];
+        return;
+    }
+    const int mlo = mptr[li], k = mptr[li + 1] - mlo;
+    for (int p = t; p < k; p += WG) ncol[nlo + p] = mcol[mlo + p];
+    const double *L = lamt + (int64_t)i * nb2;
+    for (int64_t e = t; e < (int64_t)k * nb2; e += WG) {
+        int p = (int)(e / nb2), rs = (int)(e % nb2);
+        int r = rs / nb, s = rs % nb;
+        int q = bsearch_i32(ecol, elo, elo + ek, mcol[mlo + p]);
+        double v = (q >= 0) ? eval[(int64_t)q * nb2 + rs] : 0.0;
+        const double *mp = mval + (int64_t)(mlo + p) * nb2 + s;
+        double acc = 0.0;
+        for (int u = 0; u < nb; ++u) acc += L[r * nb + u] * mp[u * nb];
+        nval[(int64_t)(nlo + p) * nb2 + rs] = v - acc;
+    }
+}
+
+// Truncation: keep the alpha blocks of largest Frobenius norm of every list row
+// (ties -> lower column).  COUNT pass writes the kept count, FILL copies.
+template <bool FILL>
+__global__ __launch_bounds__(WG) void k_truncate(int B, int nb, int alpha, const int32_t *__restrict__ pos_in_list,
+                                                 const int32_t *__restrict__ eptr, const int32_t *__restrict__ ecol,
+                                                 const double *__restrict__ eval, int32_t *__restrict__ cnt,
+                                                 const int32_t *__restrict__ tptr, int32_t *__restrict__ tcol,
+                                                 double *__restrict__ tval, int32_t *__restrict__ err) {
+    __shared__ double nrm[UNION_CAP];
+    __shared__ int32_t keep[UNION_CAP];
+    const int i = blockIdx.x;
+    if (i >= B) return;
+    const int t = threadIdx.x;
+    const int nb2 = nb * nb;
+    const int elo = eptr[i], ek = eptr[i + 1] - elo;
+    const bool trunc = pos_in_list[i] >= 0 && ek > alpha;
+    if (!trunc) {
+        if (!FILL) {
+            if (t == 0) cnt[i] = ek;
+        } else {
+            const int tlo = tptr[i];
+            for (int q = t; q < ek; q += WG) tcol[tlo + q] = ecol[elo + q];
+            for (int64_t e = t; e < (int64_t)ek * nb2; e += WG)
+                tval[(int64_t)tlo * nb2 + e] = eval[(int64_t)elo * nb2 + e];
+        }
+        return;
+    }
+    if (ek > UNION_CAP) {
+        if (t == 0) {
+            err[i] = 1;
+            if (!FILL) cnt[i] = 0;
+        }
+        return;
+    }
+    if (!FILL) {
+        if (t == 0) cnt[i] = alpha;
+        return;
+    }
+    for (int q = t; q < ek; q += WG) {
+        const double *ep = eval + (int64_t)(elo + q) * nb2;
+        double s = 0.0;
+        for (int e = 0; e < nb2; ++e) s += ep[e] * ep[e];
+        nrm[q] = s;
+    }
+    __syncthreads();
+    for (int q = t; q < ek; q += WG) {
+        int rank = 0;
+        double v = nrm[q];
+        for (int u = 0; u < ek; ++u) {
+            double o = nrm[u];
+            rank += (o > v) || (o == v && u < q);
+        }
+        keep[q] = rank < alpha;
+    }
+    __syncthreads();
+    if (t == 0) {
+        int o = tptr[i], kept = 0;
+        for (int q = 0; q < ek; ++q)
+            if (keep[q] > 0 && kept < alpha) {
+                ++kept;
+                tcol[o] = ecol[elo + q];
+                keep[q] = -(o + 1);
+                ++o;
+            }
+    }
+    __syncthreads();
+    for (int64_t e = t; e < (int64_t)ek * nb2; e += WG) {
+        int q = (int)(e / nb2), rs = (int)(e % nb2);
+        int kq = keep[q];
+        if (kq < 0) tval[(int64_t)(-kq - 1) * nb2 + rs] = eval[(int64_t)(elo + q) * nb2 + rs];
+    }
+}
+
+__global__ void k_identity_E(int B, int nb, int32_t *ptr, int32_t *col, double *val) {
+    int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int64_t tot = (int64_t)B * nb * nb;
+    if (e < B) {
+        ptr[e] = (int32_t)e;
+        col[e] = (int32_t)e;
+    }
+    if (e == 0) ptr[B] = B;
+    if (e < tot) {
+        int rs = (int)(e % (nb * nb));
+        val[e] = (rs / nb == rs % nb) ? 1.0 : 0.0;
+    }
+}
+
+__global__ void k_pos_in_list(const int32_t *__restrict__ list, int nlist, int32_t *__restrict__ pos) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nlist) pos[list[t]] = t;
+}
+
+__global__ void k_iota(int32_t *a, int n) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) a[t] = t;
+}
+
+__global__ void k_fill_i32(int32_t *a, int64_t n, int32_t v) {
+    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t < n) a[t] = v;
+}
+
+__global__ void k_unscale(int64_t B, int nb, const double *__restrict__ w, const double *__restrict__ lamt,
+                          double *__restrict__ lam) {
+    int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int nb2 = nb * nb;
+    if (e >= B * nb2) return;
+    int64_t i = e / nb2;
+    int rs = (int)(e % nb2), r = rs / nb, s = rs % nb;
+    lam[e] = w[i * nb + r] * lamt[e] * w[i * nb + s];
+}
+
+// ---------------------------------------------------------------------------
+// colouring
+// ---------------------------------------------------------------------------
+
+// One round of greedy colouring in block-index order: a block takes the smallest
+// colour unused by its lower-index neighbours once all of those are coloured.
+// Produces exactly the sequential greedy colouring.
+__global__ __launch_bounds__(WG) void k_greedy_round(int B, const int32_t *__restrict__ bptr,
+                                                     const int32_t *__restrict__ bcol, int32_t *colour,
+                                                     int32_t *__restrict__ pending) {
+    const int i = blockIdx.x * WG + threadIdx.x;
+    int waiting = 0;
+    if (i < B && colour[i] < 0) {
+        uint64_t used = 0;   // colours 0..63
+        bool ready = true, overflow = false;
+        for (int k = bptr[i]; k < bptr[i + 1]; ++k) {
+            int j = bcol[k];
+            if (j >= i) continue;
+            int cj = __atomic_load_n(&colour[j], __ATOMIC_RELAXED);
+            if (cj < 0) {
+                ready = false;
+                break;
+            }
+            if (cj < 64) used |= (1ull << cj);
+            else overflow = true;
+        }
+        if (ready && !overflow) {
+            int cbit = __builtin_ctzll(~used);
+            __atomic_store_n(&colour[i], cbit, __ATOMIC_RELAXED);
+        } else {
+            waiting = 1;
+        }
+    }
+    int any = __syncthreads_or(waiting);
+    if (threadIdx.x == 0) pending[blockIdx.x] = any;
+}
+
+__global__ void k_colour_check(int B, const int32_t *__restrict__ bptr, const int32_t *__restrict__ bcol,
+                               const int32_t *__restrict__ colour, int32_t *__restrict__ bad) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= B) return;
+    int ci = colour[i], b = 0;
+    for (int k = bptr[i]; k < bptr[i + 1]; ++k) {
+        int j = bcol[k];
+        if (j != i && colour[j] == ci) b = 1;
+    }
+    bad[i] = b;
+}
+
+// ---------------------------------------------------------------------------
+// bottom level: Gauss-Jordan inversion, one pivot per launch (ping-pong)
+// ---------------------------------------------------------------------------
+__global__ void k_gauss_jordan(const double *__restrict__ in, double *__restrict__ out, int n, int k) {
+    int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= (int64_t)n * n) return;
+    int i = (int)(e / n), j = (int)(e % n);
+    double p = in[(int64_t)k * n + k];
+    double v;
+    if (i == k) v = (j == k) ? 1.0 / p : in[(int64_t)k * n + j] / p;
+    else {
+        double f = in[(int64_t)i * n + k];
+        v = (j == k) ? -f / p : in[e] - f * in[(int64_t)k * n + j] / p;
+    }
+    out[e] = v;
+}
+
+__global__ void k_transpose_blocks64(int64_t nblk, int nb, const double *__restrict__ a, double *__restrict__ at) {
+    int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int nb2 = nb * nb;
+    if (e >= nblk * nb2) return;
+    int64_t i = e / nb2;
+    int rs = (int)(e % nb2), r = rs / nb, s = rs % nb;
+    at[i * nb2 + s * nb + r] = a[e];
+}
+
+__global__ void k_cast32(int64_t n, const double *__restrict__ a, float *__restrict__ b) {
+    int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e < n) b[e] = (float)a[e];
+}
+
+inline unsigned grid_for(int64_t n, int wg = WG) { return (unsigned)ceil_div(n, wg); }
+
+struct EMat {
+    BPattern pat;
+    DBuf<double> val;
+};
+
+int64_t scan_counts(Ctx &c, const DBuf<int32_t> &cnt, int64_t n, DBuf<int32_t> &ptr, DBuf<int64_t> &tot) {
+    ptr.alloc(n + 1);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, c.stream, cnt.get(), n, ptr.get(), tot.get());
+    CS_LAUNCH_CHECK();
+    int64_t total = 0;
+    tot.download(&total, 1, c.stream);
+    CS_HIP(hipStreamSynchronize(c.stream));
+    if (total >= INT32_MAX) fail(CS_ENOMEM, "pattern too large for 32-bit offsets");
+    return total;
+}
+
+void check_flags(Ctx &c, const DBuf<int32_t> &flags, int64_t n, const char *what) {
+    std::vector<int32_t> h(n);
+    flags.download(h.data(), n, c.stream);
+    CS_HIP(hipStreamSynchronize(c.stream));
+    for (int64_t a = 0; a < n; ++a)
+        if (h[a]) fail(CS_EINVAL, std::string(what) + " exceeds the per-row capacity of the symbolic kernels");
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host-side layout builders
+// ---------------------------------------------------------------------------
+
+void build_sell(Sell &S, const std::vector<int64_t> &ptr, const std::vector<int32_t> &col,
+                const std::vector<double> &val, const std::vector<int32_t> *rows, hipStream_t s) {
+    const int64_t m = rows ? (int64_t)rows->size() : (int64_t)ptr.size() - 1;
+    S.nrows = m;
+    S.nslices = ceil_div(m, 64);
+    std::vector<int64_t> sp(S.nslices + 1, 0);
+    std::vector<int32_t> sl(S.nslices, 0);
+    for (int64_t sidx = 0; sidx < S.nslices; ++sidx) {
+        int len = 0;
+        for (int l = 0; l < 64; ++l) {
+            int64_t q = sidx * 64 + l;
+            if (q >= m) break;
+            int64_t r = rows ? (*rows)[q] : q;
+            len = std::max<int>(len, (int)(ptr[r + 1] - ptr[r]));
+        }
+        sl[sidx] = len;
+        sp[sidx + 1] = sp[sidx] + (int64_t)len * 64;
+    }
+    S.entries = sp[S.nslices];
+    std::vector<int32_t> hc(S.entries);
+    std::vector<double> hv(S.entries);
+    for (int64_t sidx = 0; sidx < S.nslices; ++sidx)
+        for (int l = 0; l < 64; ++l) {
+            int64_t q = sidx * 64 + l;
+            int64_t r = (q < m) ? (rows ? (*rows)[q] : q) : -1;
+            int64_t rl = r >= 0 ? ptr[r + 1] - ptr[r] : 0;
+            for (int k = 0; k < sl[sidx]; ++k) {
+                int64_t o = sp[sidx] + (int64_t)k * 64 + l;
+                if (k < rl) {
+                    hc[o] = col[ptr[r] + k];
+                    hv[o] = val[ptr[r] + k];
+                } else {
+                    hc[o] = r >= 0 ? (int32_t)r : 0;
+                    hv[o] = 0.0;
+                }
+            }
+        }
+    S.slice_ptr.upload(sp.data(), sp.size(), s);
+    S.slice_len.upload(sl.data(), sl.size(), s);
+    S.col.upload(hc.data(), hc.size(), s);
+    S.val64.upload(hv.data(), hv.size(), s);
+    std::vector<float> hf(hv.begin(), hv.end());
+    S.val32.upload(hf.data(), hf.size(), s);
+    if (rows) {
+        std::vector<int32_t> hr(S.nslices * 64, -1);
+        for (int64_t q = 0; q < m; ++q) hr[q] = (*rows)[q];
+        S.rows.upload(hr.data(), hr.size(), s);
+    } else {
+        S.rows.release();
+    }
+    CS_HIP(hipStreamSynchronize(s));   // host staging vectors go out of scope
+}
+
+void build_level_device(Ctx &c, Level &L) {
+    hipStream_t s = c.stream;
+    std::vector<int32_t> p32(L.h_ptr.begin(), L.h_ptr.end());
+    L.a_ptr.upload(p32.data(), p32.size(), s);
+    L.a_col.upload(L.h_col.data(), L.h_col.size(), s);
+    L.a_val.upload(L.h_val.data(), L.h_val.size(), s);
+    build_sell(L.sell, L.h_ptr, L.h_col, L.h_val, nullptr, s);
+    CS_HIP(hipStreamSynchronize(s));
+}
+
+void build_colour_layout(Ctx &c, Level &L) {
+    // blocks sorted by colour (stable), per-colour SELL over their scalar rows
+    const int chi = 1 + *std::max_element(L.h_colour.begin(), L.h_colour.end());
+    L.chi = chi;
+    L.cptr.assign(chi + 1, 0);
+    for (int32_t v : L.h_colour) L.cptr[v + 1]++;
+    for (int k = 0; k < chi; ++k) L.cptr[k + 1] += L.cptr[k];
+    std::vector<int32_t> list(L.B);
+    std::vector<int64_t> fillp(L.cptr.begin(), L.cptr.end() - 1);
+    for (int64_t i = 0; i < L.B; ++i) list[fillp[L.h_colour[i]]++] = (int32_t)i;
+    L.clist.upload(list.data(), list.size(), c.stream);
+    L.csell.clear();
+    L.csell.resize(chi);
+    for (int k = 0; k < chi; ++k) {
+        std::vector<int32_t> rows;
+        rows.reserve((L.cptr[k + 1] - L.cptr[k]) * L.nb);
+        for (int64_t q = L.cptr[k]; q < L.cptr[k + 1]; ++q)
+            for (int r = 0; r < L.nb; ++r) rows.push_back((int32_t)(list[q] * L.nb + r));
+        build_sell(L.csell[k], L.h_ptr, L.h_col, L.h_val, &rows, c.stream);
+    }
+    CS_HIP(hipStreamSynchronize(c.stream));
+}
+
+// ---------------------------------------------------------------------------
+// setup driver
+// ---------------------------------------------------------------------------
+
+namespace {
+
+void block_pattern_of_A(Ctx &c, Level &L, BPattern &ap) {
+    const int B = (int)L.B;
+    DBuf<int32_t> cnt(B), err(B);
+    DBuf<int64_t> tot(1);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(B)), dim3(WG), 0, c.stream, err.get(), (int64_t)B, 0);
+    hipLaunchKernelGGL((k_union<SRC_SCALAR, false>), dim3(B), dim3(WG), 0, c.stream, nullptr, B, (int)L.nb,
+                       L.a_ptr.get(), L.a_col.get(), nullptr, nullptr, cnt.get(), nullptr, nullptr, err.get());
+    CS_LAUNCH_CHECK();
+    check_flags(c, err, B, "block row of A");
+    ap.rows = B;
+    ap.nnzb = scan_counts(c, cnt, B, ap.ptr, tot);
+    ap.col.alloc(ap.nnzb);
+    hipLaunchKernelGGL((k_union<SRC_SCALAR, true>), dim3(B), dim3(WG), 0, c.stream, nullptr, B, (int)L.nb,
+                       L.a_ptr.get(), L.a_col.get(), nullptr, nullptr, nullptr, ap.ptr.get(), ap.col.get(), err.get());
+    CS_LAUNCH_CHECK();
+}
+
+void greedy_colouring(Ctx &c, Level &L, const BPattern &ap) {
+    const int B = (int)L.B;
+    DBuf<int32_t> col(B), pend(grid_for(B));
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(B)), dim3(WG), 0, c.stream, col.get(), (int64_t)B, -1);
+    std::vector<int32_t> hp(grid_for(B));
+    for (int round = 0; round < B + 64; round += 16) {
+        for (int q = 0; q < 16; ++q)
+            hipLaunchKernelGGL(k_greedy_round, dim3(grid_for(B)), dim3(WG), 0, c.stream, B, ap.ptr.get(),
+                               ap.col.get(), col.get(), pend.get());
+        CS_LAUNCH_CHECK();
+        pend.download(hp.data(), hp.size(), c.stream);
+        CS_HIP(hipStreamSynchronize(c.stream));
+        bool any = false;
+        for (int32_t v : hp) any |= (v != 0);
+        if (!any) break;
+    }
+    L.h_colour.resize(B);
+    col.download(L.h_colour.data(), B, c.stream);
+    CS_HIP(hipStreamSynchronize(c.stream));
+    for (int32_t v : L.h_colour)
+        if (v < 0) fail(CS_EINVAL, "greedy colouring needs more than 64 colours");
+}
+
+void fit_level(Ctx &c, Level &L, const cs_options &o) {
+    hipStream_t s = c.stream;
+    const int B = (int)L.B, nb = (int)L.nb, nb2 = nb * nb;
+    const int depth = o.depth;
+    if (nb > MAXNB) fail(CS_EINVAL, "block size above 16 is not supported");
+    // prescaling
+    L.w.alloc(L.n);
+    hipLaunchKernelGGL(k_prescale_w, dim3(grid_for(L.n)), dim3(WG), 0, s, L.a_ptr.get(), L.a_col.get(),
+                       L.a_val.get(), L.n, L.w.get());
+    CS_LAUNCH_CHECK();
+    // block pattern of A and the prescaled dense blocks
+    BPattern ap;
+    block_pattern_of_A(c, L, ap);
+    DBuf<double> abval(ap.nnzb * nb2);
+    CS_HIP(hipMemsetAsync(abval.get(), 0, abval.bytes(), s));
+    hipLaunchKernelGGL(k_scatter_blocks, dim3(grid_for(L.n)), dim3(WG), 0, s, L.a_ptr.get(), L.a_col.get(),
+                       L.a_val.get(), L.w.get(), L.n, nb, ap.ptr.get(), ap.col.get(), abval.get());
+    CS_LAUNCH_CHECK();
+    // colour lists
+    std::vector<std::vector<int32_t>> lists;
+    if (o.mode == CS_MULTIPLICATIVE) {
+        if (!L.colour_given) greedy_colouring(c, L, ap);
+        L.colour.upload(L.h_colour.data(), B, s);
+        DBuf<int32_t> bad(B);
+        hipLaunchKernelGGL(k_colour_check, dim3(grid_for(B)), dim3(WG), 0, s, B, ap.ptr.get(), ap.col.get(),
+                           L.colour.get(), bad.get());
+        CS_LAUNCH_CHECK();
+        std::vector<int32_t> hb(B);
+        bad.download(hb.data(), B, s);
+        CS_HIP(hipStreamSynchronize(s));
+        for (int32_t v : hb)
+            if (v) fail(CS_ECOLOR, "colouring is not proper: two coupled blocks share a colour");
+        build_colour_layout(c, L);
+        std::vector<int32_t> hl(L.B);
+        L.clist.download(hl.data(), B, s);
+        CS_HIP(hipStreamSynchronize(s));
+        for (int k = 0; k < L.chi; ++k) lists.emplace_back(hl.begin() + L.cptr[k], hl.begin() + L.cptr[k + 1]);
+    } else {
+        L.chi = 1;
+        lists.emplace_back(B);
+        std::iota(lists[0].begin(), lists[0].end(), 0);
+    }
+    // E_0 = I
+    EMat E;
+    E.pat.rows = B;
+    E.pat.nnzb = B;
+    E.pat.ptr.alloc(B + 1);
+    E.pat.col.alloc(B);
+    E.val.alloc((size_t)B * nb2);
+    hipLaunchKernelGGL(k_identity_E, dim3(grid_for((int64_t)B * nb2)), dim3(WG), 0, s, B, nb, E.pat.ptr.get(),
+                       E.pat.col.get(), E.val.get());
+    CS_LAUNCH_CHECK();
+    auto keep_pattern = [&](const BPattern &p) {
+        BPattern q;
+        q.rows = p.rows;
+        q.nnzb = p.nnzb;
+        q.ptr.alloc(p.rows + 1);
+        q.col.alloc(std::max<int64_t>(p.nnzb, 1));
+        CS_HIP(hipMemcpyAsync(q.ptr.get(), p.ptr.get(), (p.rows + 1) * 4, hipMemcpyDeviceToDevice, s));
+        if (p.nnzb) CS_HIP(hipMemcpyAsync(q.col.get(), p.col.get(), p.nnzb * 4, hipMemcpyDeviceToDevice, s));
+        L.patterns.push_back(std::move(q));
+    };
+    L.patterns.clear();
+    keep_pattern(E.pat);
+    DBuf<double> lamt((size_t)depth * B * nb2);
+    DBuf<int32_t> pos(B), dlist, sing, cnt, err(B);
+    DBuf<int64_t> tot(1);
+    L.singular = 0;
+    const int nsteps = depth * (int)lists.size();
+    int step = 0;
+    for (int ell = 1; ell <= depth; ++ell) {
+        for (size_t kcol = 0; kcol < lists.size(); ++kcol, ++step) {
+            const std::vector<int32_t> &list = lists[kcol];
+            const int nl = (int)list.size();
+            if (nl == 0) continue;
+            dlist.upload(list.data(), nl, s);
+            hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(B)), dim3(WG), 0, s, pos.get(), (int64_t)B, -1);
+            hipLaunchKernelGGL(k_pos_in_list, dim3(grid_for(nl)), dim3(WG), 0, s, dlist.get(), nl, pos.get());
+            hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(B)), dim3(WG), 0, s, err.get(), (int64_t)B, 0);
+            // symbolic: pattern(M_i) for the list rows
+            cnt.alloc(nl);
+            BPattern mp;
+            mp.rows = nl;
+            hipLaunchKernelGGL((k_union<SRC_E, false>), dim3(nl), dim3(WG), 0, s, dlist.get(), nl, nb, ap.ptr.get(),
+                               ap.col.get(), E.pat.ptr.get(), E.pat.col.get(), cnt.get(), nullptr, nullptr, err.get());
+            CS_LAUNCH_CHECK();
+            check_flags(c, err, nl, "fill of a residual row");
+            mp.nnzb = scan_counts(c, cnt, nl, mp.ptr, tot);
+            mp.col.alloc(mp.nnzb);
+            hipLaunchKernelGGL((k_union<SRC_E, true>), dim3(nl), dim3(WG), 0, s, dlist.get(), nl, nb, ap.ptr.get(),
+                               ap.col.get(), E.pat.ptr.get(), E.pat.col.get(), nullptr, mp.ptr.get(), mp.col.get(),
+                               err.get());
+            CS_LAUNCH_CHECK();
+            // numeric: M, normal equations, Lambda~
+            DBuf<double> mval((size_t)mp.nnzb * nb2);
+            hipLaunchKernelGGL(k_rowprod, dim3(nl), dim3(WG), 0, s, dlist.get(), nb, ap.ptr.get(), ap.col.get(),
+                               abval.get(), E.pat.ptr.get(), E.pat.col.get(), E.val.get(), mp.ptr.get(),
+                               mp.col.get(), mval.get());
+            CS_LAUNCH_CHECK();
+            sing.alloc(nl);
+            double *lam_l = lamt.get() + (size_t)(ell - 1) * B * nb2;
+            hipLaunchKernelGGL(k_gram_solve, dim3(nl), dim3(WG), 0, s, dlist.get(), nb, mp.ptr.get(), mp.col.get(),
+                               mval.get(), E.pat.ptr.get(), E.pat.col.get(), E.val.get(), lam_l, sing.get());
+            CS_LAUNCH_CHECK();
+            {
+                std::vector<int32_t> hs(nl);
+                sing.download(hs.data(), nl, s);
+                CS_HIP(hipStreamSynchronize(s));
+                for (int32_t v : hs) L.singular += v;
+            }
+            if (step + 1 == nsteps) break;   // the last residual is never needed
+            // E update on pattern(M) for list rows, copy for others
+            {
+                DBuf<int32_t> ncnt(B);
+                std::vector<int32_t> hc(B);
+                // counts: list rows take |M_i|, others keep |E_i|
+                std::vector<int32_t> mp_h(nl + 1), ep_h(B + 1);
+                mp.ptr.download(mp_h.data(), nl + 1, s);
+                E.pat.ptr.download(ep_h.data(), B + 1, s);
+                CS_HIP(hipStreamSynchronize(s));
+                for (int i = 0; i < B; ++i) hc[i] = ep_h[i + 1] - ep_h[i];
+                for (int q = 0; q < nl; ++q) hc[list[q]] = mp_h[q + 1] - mp_h[q];
+                ncnt.upload(hc.data(), B, s);
+                EMat N;
+                N.pat.rows = B;
+                N.pat.nnzb = scan_counts(c, ncnt, B, N.pat.ptr, tot);
+                N.pat.col.alloc(N.pat.nnzb);
+                N.val.alloc((size_t)N.pat.nnzb * nb2);
+                hipLaunchKernelGGL(k_eupdate, dim3(B), dim3(WG), 0, s, B, nb, pos.get(), mp.ptr.get(), mp.col.get(),
+                                   mval.get(), E.pat.ptr.get(), E.pat.col.get(), E.val.get(), lam_l, N.pat.ptr.get(),
+                                   N.pat.col.get(), N.val.get());
+                CS_LAUNCH_CHECK();
+                mval.release();
+                if (o.trunc_alpha > 0) {
+                    DBuf<int32_t> tcnt(B);
+                    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(B)), dim3(WG), 0, s, err.get(), (int64_t)B, 0);
+                    hipLaunchKernelGGL((k_truncate<false>), dim3(B), dim3(WG), 0, s, B, nb, o.trunc_alpha, pos.get(),
+                                       N.pat.ptr.get(), N.pat.col.get(), N.val.get(), tcnt.get(), nullptr, nullptr,
+                                       nullptr, err.get());
+                    CS_LAUNCH_CHECK();
+                    check_flags(c, err, B, "truncated residual row");
+                    EMat T;
+                    T.pat.rows = B;
+                    T.pat.nnzb = scan_counts(c, tcnt, B, T.pat.ptr, tot);
+                    T.pat.col.alloc(T.pat.nnzb);
+                    T.val.alloc((size_t)T.pat.nnzb * nb2);
+                    hipLaunchKernelGGL((k_truncate<true>), dim3(B), dim3(WG), 0, s, B, nb, o.trunc_alpha, pos.get(),
+                                       N.pat.ptr.get(), N.pat.col.get(), N.val.get(), nullptr, T.pat.ptr.get(),
+                                       T.pat.col.get(), T.val.get(), err.get());
+                    CS_LAUNCH_CHECK();
+                    N = std::move(T);
+                }
+                E = std::move(N);
+                keep_pattern(E.pat);
+            }
+        }
+    }
+    // unscale into the FP64 master
+    L.depth = depth;
+    L.lam64.alloc((size_t)depth * B * nb2);
+    for (int ell = 0; ell < depth; ++ell)
+        hipLaunchKernelGGL(k_unscale, dim3(grid_for((int64_t)B * nb2)), dim3(WG), 0, s, (int64_t)B, nb, L.w.get(),
+                           lamt.get() + (size_t)ell * B * nb2, L.lam64.get() + (size_t)ell * B * nb2);
+    CS_LAUNCH_CHECK();
+    CS_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace
+
+void factor_bottom(Ctx &c, Level &L) {
+    const int n = (int)L.n;
+    std::vector<double> dense((size_t)n * n, 0.0);
+    for (int r = 0; r < n; ++r)
+        for (int64_t k = L.h_ptr[r]; k < L.h_ptr[r + 1]; ++k) dense[(size_t)r * n + L.h_col[k]] += L.h_val[k];
+    DBuf<double> a((size_t)n * n), b((size_t)n * n);
+    a.upload(dense.data(), dense.size(), c.stream);
+    for (int k = 0; k < n; ++k) {
+        hipLaunchKernelGGL(k_gauss_jordan, dim3(grid_for((int64_t)n * n)), dim3(WG), 0, c.stream, a.get(), b.get(), n,
+                           k);
+        std::swap(a, b);
+    }
+    CS_LAUNCH_CHECK();
+    L.ainv = std::move(a);
+    CS_HIP(hipStreamSynchronize(c.stream));
+}
+
+void build_working_copies(Ctx &c) {
+    for (size_t l = 0; l + 1 < c.lv.size(); ++l) {
+        Level &L = c.lv[l];
+        const int64_t tot = (int64_t)L.depth * L.B * L.nb * L.nb;
+        L.lam64T.alloc(tot);
+        hipLaunchKernelGGL(k_transpose_blocks64, dim3(grid_for(tot)), dim3(WG), 0, c.stream, (int64_t)L.depth * L.B,
+                           (int)L.nb, L.lam64.get(), L.lam64T.get());
+        L.lam32.alloc(tot);
+        L.lam32T.alloc(tot);
+        hipLaunchKernelGGL(k_cast32, dim3(grid_for(tot)), dim3(WG), 0, c.stream, tot, L.lam64.get(), L.lam32.get());
+        hipLaunchKernelGGL(k_cast32, dim3(grid_for(tot)), dim3(WG), 0, c.stream, tot, L.lam64T.get(), L.lam32T.get());
+        CS_LAUNCH_CHECK();
+    }
+    CS_HIP(hipStreamSynchronize(c.stream));
+}
+
+void run_setup(Ctx &c, const cs_options &o) {
+    CS_HIP(hipEventRecord(c.ev0, c.stream));
+    c.singular = 0;
+    for (size_t l = 0; l + 1 < c.lv.size(); ++l) {
+        fit_level(c, c.lv[l], o);
+        c.singular += c.lv[l].singular;
+    }
+    factor_bottom(c, c.lv.back());
+    build_working_copies(c);
+    CS_HIP(hipEventRecord(c.ev1, c.stream));
+    CS_HIP(hipEventSynchronize(c.ev1));
+    float ms = 0;
+    CS_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
+    c.setup_ms = ms;
+}
+
+}  // namespace cs

@@ -1,0 +1,633 @@
+// V-cycle and iterative-refinement solve (gfx950, wave64).
+//
+// Hot path of every solve:
+//   sweep      x_out = x_in - Lambda_l (A x_in - b)     additive, Sec. 2.1
+//              x_i  <- x_i - Lambda_{l,k,i} (A x - b)_i  colour k in place, Sec. 2.2
+//              reverse applications use Lambda^T in the reversed order, Sec. 2.4
+//   residual   r = A x - b, restriction b_c = r_scale P^T r         (Alg. 1)
+//   correction x <- x - P x_c                                          (Alg. 1)
+//   bottom     x_c = A_c^{-1} b_c (dense FP64 inverse)                 (Alg. 1)
+//   refinement FP64 residual b - A x, x += V r                         (solve)
+//
+// Layout: vectors are [n][R] (the R right-hand sides of one unknown are
+// contiguous), A streams as 64-row sliced ELLPACK so that a wavefront reads one
+// coalesced column of a slice per step, and Lambda is [B][nb][nb] row-major; the
+// forward sweep reads rows of Lambda_l, the reverse sweep rows of the stored
+// transposes.  Block residuals are exchanged through LDS inside a workgroup.
+#include <algorithm>
+#include <cmath>
+#include <type_traits>
+
+#include "cs_internal.h"
+
+namespace cs {
+
+namespace {
+
+constexpr int WG = 256;
+
+template <typename T, int R>
+__device__ __forceinline__ void vload(const T *p, T (&o)[R]) {
+    constexpr int BYTES = (int)sizeof(T) * R;
+    if constexpr (BYTES % 16 == 0) {
+        const uint4 *q = reinterpret_cast<const uint4 *>(p);
+#pragma unroll
+        for (int k = 0; k < BYTES / 16; ++k) {
+            uint4 u = q[k];
+            __builtin_memcpy(&o[k * (16 / sizeof(T))], &u, 16);
+        }
+    } else if constexpr (BYTES == 8) {
+        uint2 u = *reinterpret_cast<const uint2 *>(p);
+        __builtin_memcpy(&o[0], &u, 8);
+    } else {
+#pragma unroll
+        for (int k = 0; k < R; ++k) o[k] = p[k];
+    }
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void vstore(T *p, const T (&o)[R]) {
+    constexpr int BYTES = (int)sizeof(T) * R;
+    if constexpr (BYTES % 16 == 0) {
+        uint4 *q = reinterpret_cast<uint4 *>(p);
+#pragma unroll
+        for (int k = 0; k < BYTES / 16; ++k) {
+            uint4 u;
+            __builtin_memcpy(&u, &o[k * (16 / sizeof(T))], 16);
+            q[k] = u;
+        }
+    } else if constexpr (BYTES == 8) {
+        uint2 u;
+        __builtin_memcpy(&u, &o[0], 8);
+        *reinterpret_cast<uint2 *>(p) = u;
+    } else {
+#pragma unroll
+        for (int k = 0; k < R; ++k) p[k] = o[k];
+    }
+}
+
+// Map the hardware workgroup id to a logical tile so that each of the 8 XCDs
+// (which receive workgroups round-robin) works on one contiguous range of
+// rows, keeping gathered x in that XCD's L2.
+__device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t G) {
+    const int64_t xcd = bid & 7, idx = bid >> 3;
+    const int64_t per = G >> 3, rem = G & 7;
+    return xcd * per + (xcd < rem ? xcd : rem) + idx;
+}
+
+// One cascade sweep over 4 SELL slices (256 rows) per workgroup.
+//   ZERO:   x_in = 0, so x_out = Lambda b (A is not read)
+//   ROWMAP: rows come from a colour list and x is updated in place
+template <typename T, int NB, int R, bool ZERO, bool ROWMAP>
+__global__ __launch_bounds__(WG) void k_sweep(int64_t nrows, int64_t nslices, const int32_t *__restrict__ rows,
+                                              const int64_t *__restrict__ sptr, const int32_t *__restrict__ slen,
+                                              const int32_t *__restrict__ scol, const T *__restrict__ sval,
+                                              const T *__restrict__ lam, const T *__restrict__ b, const T *xin,
+                                              T *xout) {
+    __shared__ T red[NB > 1 ? WG * R : 1];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t slice = tile * 4 + wv;
+    const int64_t q = slice * 64 + lane;
+    const bool valid = slice < nslices && q < nrows;
+    int64_t row = 0;
+    if (valid) row = ROWMAP ? (int64_t)rows[q] : q;
+    T res[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) res[k] = T(0);
+    if (valid) {
+        T bb[R];
+        vload<T, R>(b + row * R, bb);
+#pragma unroll
+        for (int k = 0; k < R; ++k) res[k] = -bb[k];
+        if constexpr (!ZERO) {
+            const int len = slen[slice];
+            const int64_t off = sptr[slice] + lane;
+            for (int e = 0; e < len; ++e) {
+                const int c = scol[off + (int64_t)e * 64];
+                const T a = sval[off + (int64_t)e * 64];
+                T xv[R];
+                vload<T, R>(xin + (int64_t)c * R, xv);
+#pragma unroll
+                for (int k = 0; k < R; ++k) res[k] += a * xv[k];
+            }
+        }
+    }
+    if constexpr (NB == 1) {
+        if (valid) {
+            const T l = lam[row];
+            T xo[R];
+            if constexpr (ZERO) {
+#pragma unroll
+                for (int k = 0; k < R; ++k) xo[k] = T(0);
+            } else {
+                vload<T, R>(xin + row * R, xo);
+            }
+#pragma unroll
+            for (int k = 0; k < R; ++k) xo[k] -= l * res[k];
+            vstore<T, R>(xout + row * R, xo);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < R; ++k) red[threadIdx.x * R + k] = res[k];
+        __syncthreads();
+        if (valid) {
+            const int rloc = lane % NB;
+            const int base = threadIdx.x - rloc;
+            const T *lrow = lam + (row / NB) * (NB * NB) + rloc * NB;
+            T lr[NB];
+            vload<T, NB>(lrow, lr);
+            T xo[R];
+            if constexpr (ZERO) {
+#pragma unroll
+                for (int k = 0; k < R; ++k) xo[k] = T(0);
+            } else {
+                vload<T, R>(xin + row * R, xo);
+            }
+#pragma unroll
+            for (int cc = 0; cc < NB; ++cc) {
+#pragma unroll
+                for (int k = 0; k < R; ++k) xo[k] -= lr[cc] * red[(base + cc) * R + k];
+            }
+            vstore<T, R>(xout + row * R, xo);
+        }
+    }
+}
+
+// r = A x - b over SELL rows (natural order)
+template <typename T, int R>
+__global__ __launch_bounds__(WG) void k_residual(int64_t nrows, int64_t nslices, const int64_t *__restrict__ sptr,
+                                                 const int32_t *__restrict__ slen, const int32_t *__restrict__ scol,
+                                                 const T *__restrict__ sval, const T *__restrict__ b,
+                                                 const T *__restrict__ x, T *__restrict__ r) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t slice = xcd_tile(blockIdx.x, gridDim.x) * 4 + wv;
+    const int64_t row = slice * 64 + lane;
+    if (slice >= nslices || row >= nrows) return;
+    T acc[R];
+    vload<T, R>(b + row * R, acc);
+#pragma unroll
+    for (int k = 0; k < R; ++k) acc[k] = -acc[k];
+    const int len = slen[slice];
+    const int64_t off = sptr[slice] + lane;
+    for (int e = 0; e < len; ++e) {
+        const int c = scol[off + (int64_t)e * 64];
+        const T a = sval[off + (int64_t)e * 64];
+        T xv[R];
+        vload<T, R>(x + (int64_t)c * R, xv);
+#pragma unroll
+        for (int k = 0; k < R; ++k) acc[k] += a * xv[k];
+    }
+    vstore<T, R>(r + row * R, acc);
+}
+
+// b_c = r_scale * P^T r  (gather through the stored transpose)
+template <typename T, int R>
+__global__ void k_restrict(int64_t nc, const int32_t *__restrict__ ptp, const int32_t *__restrict__ ptc,
+                           const T *__restrict__ ptv, T r_scale, const T *__restrict__ r, T *__restrict__ bc) {
+    const int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (I >= nc) return;
+    T acc[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) acc[k] = T(0);
+    for (int e = ptp[I]; e < ptp[I + 1]; ++e) {
+        const T v = ptv[e];
+        T rv[R];
+        vload<T, R>(r + (int64_t)ptc[e] * R, rv);
+#pragma unroll
+        for (int k = 0; k < R; ++k) acc[k] += v * rv[k];
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) acc[k] *= r_scale;
+    vstore<T, R>(bc + I * R, acc);
+}
+
+// x <- x - P x_c
+template <typename T, int R>
+__global__ void k_prolong(int64_t n, const int32_t *__restrict__ pp, const int32_t *__restrict__ pc,
+                          const T *__restrict__ pv, const T *__restrict__ xc, T *__restrict__ x) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    T acc[R];
+    vload<T, R>(x + i * R, acc);
+    for (int e = pp[i]; e < pp[i + 1]; ++e) {
+        const T v = pv[e];
+        T cv[R];
+        vload<T, R>(xc + (int64_t)pc[e] * R, cv);
+#pragma unroll
+        for (int k = 0; k < R; ++k) acc[k] -= v * cv[k];
+    }
+    vstore<T, R>(x + i * R, acc);
+}
+
+// bottom level: x = A^{-1} b with the FP64 inverse
+template <typename T, int R>
+__global__ void k_coarse(int n, const double *__restrict__ ainv, const T *__restrict__ b, T *__restrict__ x) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) acc[k] = 0.0;
+    const double *row = ainv + (int64_t)i * n;
+    for (int j = 0; j < n; ++j) {
+        const double a = row[j];
+#pragma unroll
+        for (int k = 0; k < R; ++k) acc[k] += a * (double)b[(int64_t)j * R + k];
+    }
+    T o[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) o[k] = (T)acc[k];
+    vstore<T, R>(x + (int64_t)i * R, o);
+}
+
+// FP64 refinement residual r = b - A x; writes r in the working precision and
+// per-workgroup partial sums of r^2 for every right-hand side.  With x == null
+// it computes the partial sums of b^2.
+template <typename T, int R>
+__global__ __launch_bounds__(WG) void k_ir_residual(int64_t nrows, int64_t nslices, const int64_t *__restrict__ sptr,
+                                                    const int32_t *__restrict__ slen, const int32_t *__restrict__ scol,
+                                                    const double *__restrict__ sval, const double *__restrict__ b,
+                                                    const double *__restrict__ x, T *__restrict__ rt,
+                                                    double *__restrict__ partial) {
+    __shared__ double red[WG * R];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t slice = (int64_t)blockIdx.x * 4 + wv;
+    const int64_t row = slice * 64 + lane;
+    double acc[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) acc[k] = 0.0;
+    if (slice < nslices && row < nrows) {
+        vload<double, R>(b + row * R, acc);
+        if (x) {
+            const int len = slen[slice];
+            const int64_t off = sptr[slice] + lane;
+            for (int e = 0; e < len; ++e) {
+                const int c = scol[off + (int64_t)e * 64];
+                const double a = sval[off + (int64_t)e * 64];
+                double xv[R];
+                vload<double, R>(x + (int64_t)c * R, xv);
+#pragma unroll
+                for (int k = 0; k < R; ++k) acc[k] -= a * xv[k];
+            }
+        }
+        if (rt) {
+            T o[R];
+#pragma unroll
+            for (int k = 0; k < R; ++k) o[k] = (T)acc[k];
+            vstore<T, R>(rt + row * R, o);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) red[threadIdx.x * R + k] = acc[k] * acc[k];
+    __syncthreads();
+    for (int s = WG / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+#pragma unroll
+            for (int k = 0; k < R; ++k) red[threadIdx.x * R + k] += red[(threadIdx.x + s) * R + k];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < R) partial[(int64_t)blockIdx.x * R + threadIdx.x] = red[threadIdx.x];
+}
+
+// Fixed-order sum of the partials: out[k] = sum_g partial[g][k]
+__global__ __launch_bounds__(WG) void k_reduce_partials(int64_t G, int R, const double *__restrict__ partial,
+                                                        double *__restrict__ out) {
+    __shared__ double red[WG];
+    for (int k = 0; k < R; ++k) {
+        double s = 0.0;
+        for (int64_t g = threadIdx.x; g < G; g += WG) s += partial[g * R + k];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int h = WG / 2; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[k] = red[0];
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ void k_add_to64(int64_t n, const T *__restrict__ d, double *__restrict__ x) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e < n) x[e] += (double)d[e];
+}
+
+template <typename A, typename B>
+__global__ void k_convert(int64_t n, const A *__restrict__ a, B *__restrict__ b) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e < n) b[e] = (B)a[e];
+}
+
+template <typename T>
+__global__ void k_zero(int64_t n, T *__restrict__ a) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e < n) a[e] = T(0);
+}
+
+inline unsigned grid_for(int64_t n, int wg = WG) { return (unsigned)ceil_div(n, wg); }
+
+template <class F>
+void dispatch_nb(int nb, F &&f) {
+    switch (nb) {
+        case 1: f(std::integral_constant<int, 1>{}); break;
+        case 2: f(std::integral_constant<int, 2>{}); break;
+        case 4: f(std::integral_constant<int, 4>{}); break;
+        case 8: f(std::integral_constant<int, 8>{}); break;
+        case 16: f(std::integral_constant<int, 16>{}); break;
+        default: fail(CS_EINVAL, "block size must be 1, 2, 4, 8 or 16");
+    }
+}
+
+template <class F>
+void dispatch_r(int r, F &&f) {
+    switch (r) {
+        case 1: f(std::integral_constant<int, 1>{}); break;
+        case 2: f(std::integral_constant<int, 2>{}); break;
+        case 4: f(std::integral_constant<int, 4>{}); break;
+        case 8: f(std::integral_constant<int, 8>{}); break;
+        default: fail(CS_EINVAL, "nrhs must be 1, 2, 4 or 8");
+    }
+}
+
+template <typename T>
+const T *sell_val(const Sell &S);
+template <>
+const double *sell_val<double>(const Sell &S) { return S.val64.get(); }
+template <>
+const float *sell_val<float>(const Sell &S) { return S.val32.get(); }
+
+template <typename T>
+const T *lam_ptr(const Level &L, bool transposed);
+template <>
+const double *lam_ptr<double>(const Level &L, bool tr) { return tr ? L.lam64T.get() : L.lam64.get(); }
+template <>
+const float *lam_ptr<float>(const Level &L, bool tr) { return tr ? L.lam32T.get() : L.lam32.get(); }
+
+template <typename T>
+const T *pval(const Level &L, bool transposed);
+template <>
+const double *pval<double>(const Level &L, bool tr) { return tr ? L.pt_val64.get() : L.p_val64.get(); }
+template <>
+const float *pval<float>(const Level &L, bool tr) { return tr ? L.pt_val32.get() : L.p_val32.get(); }
+
+template <typename T, int R>
+void launch_sweep(Ctx &c, const Level &L, const Sell &S, bool rowmap, bool zero, const T *lam, const T *b,
+                  const T *xin, T *xout) {
+    const unsigned G = grid_for(S.nslices, 4);
+    if (G == 0) return;
+    dispatch_nb(L.nb, [&](auto nbc) {
+        constexpr int NB = decltype(nbc)::value;
+        if (rowmap) {
+            if (zero)
+                hipLaunchKernelGGL((k_sweep<T, NB, R, true, true>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
+                                   S.rows.get(), S.slice_ptr.get(), S.slice_len.get(), S.col.get(), sell_val<T>(S),
+                                   lam, b, xin, xout);
+            else
+                hipLaunchKernelGGL((k_sweep<T, NB, R, false, true>), dim3(G), dim3(WG), 0, c.stream, S.nrows,
+                                   S.nslices, S.rows.get(), S.slice_ptr.get(), S.slice_len.get(), S.col.get(),
+                                   sell_val<T>(S), lam, b, xin, xout);
+        } else {
+            if (zero)
+                hipLaunchKernelGGL((k_sweep<T, NB, R, true, false>), dim3(G), dim3(WG), 0, c.stream, S.nrows,
+                                   S.nslices, nullptr, S.slice_ptr.get(), S.slice_len.get(), S.col.get(),
+                                   sell_val<T>(S), lam, b, xin, xout);
+            else
+                hipLaunchKernelGGL((k_sweep<T, NB, R, false, false>), dim3(G), dim3(WG), 0, c.stream, S.nrows,
+                                   S.nslices, nullptr, S.slice_ptr.get(), S.slice_len.get(), S.col.get(),
+                                   sell_val<T>(S), lam, b, xin, xout);
+        }
+    });
+    CS_LAUNCH_CHECK();
+}
+
+// One application of the cascade of level L: x <- S(x, b).  Returns the buffer
+// holding the result (additive sweeps alternate between x and alt).
+template <typename T, int R>
+T *apply_cascade(Ctx &c, const Level &L, bool reverse, bool zero_start, const T *b, T *x, T *alt) {
+    const int64_t nbl = L.B * L.nb * L.nb;
+    const int depth = L.depth;
+    if (c.opt.mode == CS_ADDITIVE) {
+        T *cur = x, *nxt = alt;
+        for (int s = 0; s < depth; ++s) {
+            const int ell = reverse ? depth - 1 - s : s;
+            const T *lam = lam_ptr<T>(L, reverse) + (int64_t)ell * nbl;
+            launch_sweep<T, R>(c, L, L.sell, false, zero_start && s == 0, lam, b, cur, nxt);
+            std::swap(cur, nxt);
+        }
+        return cur;
+    }
+    // multiplicative: flattened (l, k) sequence, in place
+    if (zero_start) {
+        hipLaunchKernelGGL(k_zero<T>, dim3(grid_for(L.n * R)), dim3(WG), 0, c.stream, L.n * R, x);
+        CS_LAUNCH_CHECK();
+    }
+    const int chi = L.chi;
+    const int nsteps = depth * chi;
+    for (int s = 0; s < nsteps; ++s) {
+        const int f = reverse ? nsteps - 1 - s : s;
+        const int ell = f / chi, k = f % chi;
+        const Sell &S = L.csell[k];
+        if (S.nrows == 0) continue;
+        const T *lam = lam_ptr<T>(L, reverse) + (int64_t)ell * nbl;
+        launch_sweep<T, R>(c, L, S, true, zero_start && s == 0, lam, b, x, x);
+    }
+    return x;
+}
+
+template <typename T, int R>
+void vcycle_level(Ctx &c, int l) {
+    Level &L = c.lv[l];
+    T *xb = reinterpret_cast<T *>(L.xb.get());
+    T *xt = reinterpret_cast<T *>(L.xt.get());
+    T *bb = reinterpret_cast<T *>(L.bb.get());
+    T *rr = reinterpret_cast<T *>(L.rr.get());
+    if (l + 1 == (int)c.lv.size()) {
+        hipLaunchKernelGGL((k_coarse<T, R>), dim3(grid_for(L.n, 64)), dim3(64), 0, c.stream, (int)L.n, L.ainv.get(), bb,
+                           xb);
+        CS_LAUNCH_CHECK();
+        return;
+    }
+    Level &C = c.lv[l + 1];
+    T *x = xb, *alt = xt;
+    const bool rf = c.opt.order == CS_RF;
+    for (int a = 0; a < c.opt.n_pre; ++a) {
+        T *res = apply_cascade<T, R>(c, L, rf, a == 0, bb, x, alt);
+        if (res != x) std::swap(x, alt);
+    }
+    // restricted residual
+    hipLaunchKernelGGL((k_residual<T, R>), dim3(grid_for(L.sell.nslices, 4)), dim3(WG), 0, c.stream, L.sell.nrows,
+                       L.sell.nslices, L.sell.slice_ptr.get(), L.sell.slice_len.get(), L.sell.col.get(),
+                       sell_val<T>(L.sell), bb, x, rr);
+    hipLaunchKernelGGL((k_restrict<T, R>), dim3(grid_for(L.nc)), dim3(WG), 0, c.stream, L.nc, L.pt_ptr.get(),
+                       L.pt_col.get(), pval<T>(L, true), (T)L.r_scale, rr, reinterpret_cast<T *>(C.bb.get()));
+    CS_LAUNCH_CHECK();
+    vcycle_level<T, R>(c, l + 1);
+    hipLaunchKernelGGL((k_prolong<T, R>), dim3(grid_for(L.n)), dim3(WG), 0, c.stream, L.n, L.p_ptr.get(),
+                       L.p_col.get(), pval<T>(L, false), reinterpret_cast<const T *>(C.xb.get()), x);
+    CS_LAUNCH_CHECK();
+    for (int a = 0; a < c.opt.n_post; ++a) {
+        T *res = apply_cascade<T, R>(c, L, false, false, bb, x, alt);
+        if (res != x) std::swap(x, alt);
+    }
+    if (x != xb) {
+        CS_HIP(hipMemcpyAsync(xb, x, L.n * R * sizeof(T), hipMemcpyDeviceToDevice, c.stream));
+    }
+}
+
+template <class F>
+void dispatch_prec(int prec, F &&f) {
+    if (prec == CS_FP64) f((double *)nullptr);
+    else f((float *)nullptr);
+}
+
+}  // namespace
+
+void ensure_workspace(Ctx &c, int nrhs) {
+    const int prec = c.precision;
+    if (c.ws_nrhs == nrhs && c.ws_prec == prec) return;
+    const size_t es = prec == CS_FP64 ? sizeof(double) : sizeof(float);
+    for (Level &L : c.lv) {
+        const size_t bytes = (size_t)L.n * nrhs * es;
+        L.xb.alloc(bytes);
+        L.xt.alloc(bytes);
+        L.bb.alloc(bytes);
+        L.rr.alloc(bytes);
+    }
+    const int64_t G = ceil_div(c.lv[0].sell.nslices, 4);
+    c.ir_partial.alloc(std::max<int64_t>(G, 1) * nrhs);
+    c.ir_norm.alloc(2 * nrhs);
+    c.ws_nrhs = nrhs;
+    c.ws_prec = prec;
+}
+
+void vcycle_apply(Ctx &c, const double *b, double *x, int nrhs) {
+    ensure_workspace(c, nrhs);
+    Level &L0 = c.lv[0];
+    const int64_t n = L0.n * nrhs;
+    dispatch_prec(c.precision, [&](auto tp) {
+        using T = std::remove_pointer_t<decltype(tp)>;
+        hipLaunchKernelGGL((k_convert<double, T>), dim3(grid_for(n)), dim3(WG), 0, c.stream, n, b,
+                           reinterpret_cast<T *>(L0.bb.get()));
+        dispatch_r(nrhs, [&](auto rc) { vcycle_level<T, decltype(rc)::value>(c, 0); });
+        hipLaunchKernelGGL((k_convert<T, double>), dim3(grid_for(n)), dim3(WG), 0, c.stream, n,
+                           reinterpret_cast<const T *>(L0.xb.get()), x);
+        CS_LAUNCH_CHECK();
+    });
+}
+
+void smooth_apply(Ctx &c, int level, bool reverse, const double *b, double *x, int nrhs) {
+    ensure_workspace(c, nrhs);
+    Level &L = c.lv[level];
+    const int64_t n = L.n * nrhs;
+    dispatch_prec(c.precision, [&](auto tp) {
+        using T = std::remove_pointer_t<decltype(tp)>;
+        T *bb = reinterpret_cast<T *>(L.bb.get());
+        T *xb = reinterpret_cast<T *>(L.xb.get());
+        T *xt = reinterpret_cast<T *>(L.xt.get());
+        hipLaunchKernelGGL((k_convert<double, T>), dim3(grid_for(n)), dim3(WG), 0, c.stream, n, b, bb);
+        hipLaunchKernelGGL((k_convert<double, T>), dim3(grid_for(n)), dim3(WG), 0, c.stream, n, (const double *)x, xb);
+        T *res = nullptr;
+        dispatch_r(nrhs, [&](auto rc) {
+            res = apply_cascade<T, decltype(rc)::value>(c, L, reverse, false, bb, xb, xt);
+        });
+        hipLaunchKernelGGL((k_convert<T, double>), dim3(grid_for(n)), dim3(WG), 0, c.stream, n, (const T *)res, x);
+        CS_LAUNCH_CHECK();
+    });
+}
+
+void solve_ir(Ctx &c, const double *b, double *x, int nrhs, double rtol, int maxit, cs_info *info,
+              double *history, cs_status *st) {
+    ensure_workspace(c, nrhs);
+    Level &L0 = c.lv[0];
+    const Sell &S = L0.sell;
+    const int64_t n = L0.n * nrhs;
+    const int64_t G = ceil_div(S.nslices, 4);
+    std::vector<double> hn(2 * nrhs);
+    *st = CS_OK;
+    CS_HIP(hipEventRecord(c.ev0, c.stream));
+    dispatch_prec(c.precision, [&](auto tp) {
+        using T = std::remove_pointer_t<decltype(tp)>;
+        dispatch_r(nrhs, [&](auto rc) {
+            constexpr int R = decltype(rc)::value;
+            // ||b||^2
+            hipLaunchKernelGGL((k_ir_residual<T, R>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
+                               S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), b, nullptr,
+                               (T *)nullptr, c.ir_partial.get());
+            hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(WG), 0, c.stream, G, R, c.ir_partial.get(),
+                               c.ir_norm.get() + R);
+            hipLaunchKernelGGL(k_zero<double>, dim3(grid_for(n)), dim3(WG), 0, c.stream, n, x);
+            CS_LAUNCH_CHECK();
+            std::vector<double> hist;
+            double bn2[8];
+            int it = 0;
+            for (;; ++it) {
+                hipLaunchKernelGGL((k_ir_residual<T, R>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
+                                   S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), b, x,
+                                   reinterpret_cast<T *>(L0.bb.get()), c.ir_partial.get());
+                hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(WG), 0, c.stream, G, R, c.ir_partial.get(),
+                                   c.ir_norm.get());
+                CS_LAUNCH_CHECK();
+                c.ir_norm.download(hn.data(), 2 * R, c.stream);
+                CS_HIP(hipStreamSynchronize(c.stream));
+                if (it == 0)
+                    for (int k = 0; k < R; ++k) bn2[k] = hn[R + k] > 0 ? hn[R + k] : 1.0;
+                double rel = 0.0;
+                bool bad = false;
+                for (int k = 0; k < R; ++k) {
+                    double v = std::sqrt(hn[k] / bn2[k]);
+                    if (!std::isfinite(v)) bad = true;
+                    rel = std::max(rel, v);
+                }
+                hist.push_back(bad ? NAN : rel);
+                if (bad) {
+                    *st = CS_ENAN;
+                    break;
+                }
+                if (rel <= rtol) break;
+                if (it == maxit) {
+                    *st = CS_ENOCONV;
+                    break;
+                }
+                vcycle_level<T, R>(c, 0);
+                hipLaunchKernelGGL((k_add_to64<T>), dim3(grid_for(n)), dim3(WG), 0, c.stream, n,
+                                   reinterpret_cast<const T *>(L0.xb.get()), x);
+                CS_LAUNCH_CHECK();
+            }
+            CS_HIP(hipEventRecord(c.ev1, c.stream));
+            CS_HIP(hipEventSynchronize(c.ev1));
+            float ms = 0;
+            CS_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
+            if (history)
+                for (size_t q = 0; q < hist.size(); ++q) history[q] = hist[q];
+            if (info) {
+                info->iterations = it;
+                info->rel_res = hist.back();
+                info->solve_ms = ms;
+                info->setup_ms = c.setup_ms;
+                info->singular_blocks = c.singular;
+                // least-squares slope of log r_i over i = 1..K
+                const int K = (int)hist.size() - 1;
+                double rho = NAN;
+                if (K >= 2) {
+                    double si = 0, sy = 0, sii = 0, siy = 0;
+                    for (int q = 1; q <= K; ++q) {
+                        double y = std::log(hist[q]);
+                        si += q;
+                        sy += y;
+                        sii += (double)q * q;
+                        siy += q * y;
+                    }
+                    double slope = (K * siy - si * sy) / (K * sii - si * si);
+                    rho = std::exp(slope);
+                } else if (K == 1) {
+                    rho = hist[1] / hist[0];
+                }
+                info->rho = rho;
+            }
+        });
+    });
+}
+
+}  // namespace cs
