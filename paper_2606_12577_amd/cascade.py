@@ -73,6 +73,8 @@ SIGNATURES = {
     "cs_smooth": (_I32, [_VP, _I32, _I32, _VP, _VP, _I32]),
     "cs_vcycle": (_I32, [_VP, _VP, _VP, _I32]),
     "cs_solve": (_I32, [_VP, _VP, _VP, _I32, _D, _I32, _p(cs_info), _p(_D)]),
+    "cs_trace": (_I32, [_VP, _I32]),
+    "cs_trace_read": (_I32, [_VP, _I32, _p(_D), _p(_I64), _p(_D)]),
     "cs_save_setup": (_I32, [_VP, ctypes.c_char_p]),
     "cs_load_setup": (_I32, [_VP, ctypes.c_char_p]),
 }
@@ -259,6 +261,24 @@ class Solver:
         return x, dict(iterations=k, rel_res=info.rel_res, rho=info.rho, setup_ms=info.setup_ms,
                        solve_ms=info.solve_ms, singular_blocks=info.singular_blocks,
                        history=hist[:k + 1].copy(), status=st)
+
+    TRACE_CLASSES = ("sweep", "sweep_zero", "residual", "prolong", "bottom", "refine")
+
+    def trace(self, classes=("sweep",)):
+        """Start (clearing the counters) per-kernel-class event timing of the
+        given classes; an empty sequence stops it."""
+        mask = 0
+        for name in classes:
+            mask |= 1 << self.TRACE_CLASSES.index(name)
+        self._check(self._lib.cs_trace(self._h, mask))
+
+    def trace_read(self):
+        out = {}
+        for k, name in enumerate(self.TRACE_CLASSES):
+            ms, cnt, by = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+            self._check(self._lib.cs_trace_read(self._h, k, ctypes.byref(ms), ctypes.byref(cnt), ctypes.byref(by)))
+            out[name] = dict(ms=ms.value, launches=cnt.value, bytes=by.value)
+        return out
 
     def save(self, path: str):
         self._check(self._lib.cs_save_setup(self._h, path.encode()))

@@ -97,6 +97,7 @@ void set_level(Ctx &c, Level &L, const cs_level &in, int li, int nlev, int64_t n
         std::vector<double> pv(in.p_val, in.p_val + pn);
         for (int32_t v : pc) need(v >= 0 && v < n_next, "P column index out of range");
         L.nc = n_next;
+        L.p_nnz = pn;
         L.r_scale = in.r_scale;
         std::vector<int32_t> tp, tc;
         std::vector<double> tv;
@@ -177,6 +178,7 @@ void cs_destroy(cs_ctx ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->c.device);
     (void)hipStreamSynchronize(ctx->c.stream);
+    cs::trace_release(ctx->c);
     if (ctx->c.ev0) (void)hipEventDestroy(ctx->c.ev0);
     if (ctx->c.ev1) (void)hipEventDestroy(ctx->c.ev1);
     delete ctx;
@@ -411,6 +413,89 @@ cs_status cs_load_setup(cs_ctx ctx, const char *path) {
         c.ws_nrhs = 0;
         cs::build_working_copies(c);
         c.have_setup = true;
+    });
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// tracing
+// ---------------------------------------------------------------------------
+namespace cs {
+
+int trace_begin(Ctx &c, int cls, double bytes) {
+    Trace &t = c.tr;
+    if (!t.on || !((t.mask >> cls) & 1)) return -1;
+    if (2 * t.used + 2 > t.ev.size()) {
+        hipEvent_t a, b;
+        CS_HIP(hipEventCreate(&a));
+        CS_HIP(hipEventCreate(&b));
+        t.ev.push_back(a);
+        t.ev.push_back(b);
+        t.cls.push_back(0);
+        t.cls_bytes.push_back(0.0);
+    }
+    const int slot = (int)t.used++;
+    t.cls[slot] = cls;
+    t.cls_bytes[slot] = bytes;
+    CS_HIP(hipEventRecord(t.ev[2 * slot], c.stream));
+    return slot;
+}
+
+void trace_end(Ctx &c, int slot) {
+    if (slot < 0) return;
+    CS_HIP(hipEventRecord(c.tr.ev[2 * slot + 1], c.stream));
+}
+
+void trace_flush(Ctx &c) {
+    Trace &t = c.tr;
+    if (t.used == 0) return;
+    CS_HIP(hipStreamSynchronize(c.stream));
+    for (size_t k = 0; k < t.used; ++k) {
+        float ms = 0;
+        CS_HIP(hipEventElapsedTime(&ms, t.ev[2 * k], t.ev[2 * k + 1]));
+        t.ms[t.cls[k]] += ms;
+        t.count[t.cls[k]] += 1;
+        t.bytes[t.cls[k]] += t.cls_bytes[k];
+    }
+    t.used = 0;
+}
+
+void trace_release(Ctx &c) {
+    for (hipEvent_t e : c.tr.ev) (void)hipEventDestroy(e);
+    c.tr.ev.clear();
+    c.tr.cls.clear();
+    c.tr.cls_bytes.clear();
+    c.tr.used = 0;
+}
+
+}  // namespace cs
+
+extern "C" {
+
+cs_status cs_trace(cs_ctx ctx, int32_t mask) {
+    return guarded(ctx, [&](Ctx &c) {
+        cs::trace_flush(c);
+        c.tr.mask = mask;
+        const int32_t enable = mask;
+        if (enable) {
+            for (int k = 0; k < CS_TRACE_NCLASS; ++k) {
+                c.tr.ms[k] = 0;
+                c.tr.count[k] = 0;
+                c.tr.bytes[k] = 0;
+            }
+        }
+        c.tr.on = enable != 0;
+    });
+}
+
+cs_status cs_trace_read(cs_ctx ctx, int32_t cls, double *total_ms, int64_t *launches, double *bytes) {
+    return guarded(ctx, [&](Ctx &c) {
+        need(cls >= 0 && cls < CS_TRACE_NCLASS, "trace class out of range");
+        cs::trace_flush(c);
+        if (total_ms) *total_ms = c.tr.ms[cls];
+        if (launches) *launches = c.tr.count[cls];
+        if (bytes) *bytes = c.tr.bytes[cls];
     });
 }
 

@@ -88,7 +88,8 @@ struct Sell {
     DBuf<int32_t> col;
     DBuf<double> val64;
     DBuf<float> val32;
-    int64_t entries = 0;
+    int64_t entries = 0;    // stored entries including padding
+    int64_t nnz = 0;        // structural entries of the rows
 };
 
 // Block CSR pattern on the device (+ optional values).
@@ -115,7 +116,7 @@ struct Level {
     int chi = 0;
     DBuf<int32_t> colour;             // device colours
     // interpolation to the next coarser level
-    int64_t nc = 0;
+    int64_t nc = 0, p_nnz = 0;
     double r_scale = 1.0;
     DBuf<int32_t> p_ptr, p_col, pt_ptr, pt_col;
     DBuf<double> p_val64, pt_val64;
@@ -133,6 +134,18 @@ struct Level {
     DBuf<char> xb, xt, bb, rr;
 };
 
+struct Trace {
+    bool on = false;
+    int mask = 0;                        // bit k: record class k
+    std::vector<hipEvent_t> ev;          // pairs: ev[2k] start, ev[2k+1] end
+    std::vector<int> cls;
+    std::vector<double> cls_bytes;       // per recorded launch
+    size_t used = 0;
+    double ms[CS_TRACE_NCLASS] = {0};
+    int64_t count[CS_TRACE_NCLASS] = {0};
+    double bytes[CS_TRACE_NCLASS] = {0};
+};
+
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -148,7 +161,14 @@ struct Ctx {
     DBuf<double> ir_partial, ir_norm;
     DBuf<char> ir_r;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    Trace tr;
 };
+
+// tracing helpers (api.hip)
+int trace_begin(Ctx &c, int cls, double bytes);   // returns slot or -1
+void trace_end(Ctx &c, int slot);
+void trace_flush(Ctx &c);
+void trace_release(Ctx &c);
 
 // setup.hip
 void build_level_device(Ctx &c, Level &L);

@@ -682,6 +682,11 @@ void build_sell(Sell &S, const std::vector<int64_t> &ptr, const std::vector<int3
         sp[sidx + 1] = sp[sidx] + (int64_t)len * 64;
     }
     S.entries = sp[S.nslices];
+    S.nnz = 0;
+    for (int64_t q = 0; q < m; ++q) {
+        int64_t r = rows ? (*rows)[q] : q;
+        S.nnz += ptr[r + 1] - ptr[r];
+    }
     std::vector<int32_t> hc(S.entries);
     std::vector<double> hv(S.entries);
     for (int64_t sidx = 0; sidx < S.nslices; ++sidx)

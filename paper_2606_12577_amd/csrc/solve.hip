@@ -377,6 +377,11 @@ void launch_sweep(Ctx &c, const Level &L, const Sell &S, bool rowmap, bool zero,
                   const T *xin, T *xout) {
     const unsigned G = grid_for(S.nslices, 4);
     if (G == 0) return;
+    const int cls = zero ? CS_TRACE_SWEEP_ZERO : CS_TRACE_SWEEP;
+    const double es = sizeof(T);
+    const double bytes = (zero ? 0.0 : S.nnz * (es + 4.0)) + (double)S.nrows * L.nb * es +
+                         (double)S.nrows * R * es * 2.0 + (zero ? 0.0 : (rowmap ? L.n : S.nrows) * R * es);
+    const int slot = trace_begin(c, cls, bytes);
     dispatch_nb(L.nb, [&](auto nbc) {
         constexpr int NB = decltype(nbc)::value;
         if (rowmap) {
@@ -400,6 +405,7 @@ void launch_sweep(Ctx &c, const Level &L, const Sell &S, bool rowmap, bool zero,
         }
     });
     CS_LAUNCH_CHECK();
+    trace_end(c, slot);
 }
 
 // One application of the cascade of level L: x <- S(x, b).  Returns the buffer
@@ -443,10 +449,13 @@ void vcycle_level(Ctx &c, int l) {
     T *xt = reinterpret_cast<T *>(L.xt.get());
     T *bb = reinterpret_cast<T *>(L.bb.get());
     T *rr = reinterpret_cast<T *>(L.rr.get());
+    const double es = sizeof(T);
     if (l + 1 == (int)c.lv.size()) {
+        const int slot = trace_begin(c, CS_TRACE_BOTTOM, (double)L.n * L.n * 8.0 + 2.0 * L.n * R * es);
         hipLaunchKernelGGL((k_coarse<T, R>), dim3(grid_for(L.n, 64)), dim3(64), 0, c.stream, (int)L.n, L.ainv.get(), bb,
                            xb);
         CS_LAUNCH_CHECK();
+        trace_end(c, slot);
         return;
     }
     Level &C = c.lv[l + 1];
@@ -457,16 +466,21 @@ void vcycle_level(Ctx &c, int l) {
         if (res != x) std::swap(x, alt);
     }
     // restricted residual
+    int slot = trace_begin(c, CS_TRACE_RESIDUAL,
+                           L.sell.nnz * (es + 4.0) + 3.0 * L.n * R * es + L.p_nnz * (es + 4.0) + L.nc * R * es);
     hipLaunchKernelGGL((k_residual<T, R>), dim3(grid_for(L.sell.nslices, 4)), dim3(WG), 0, c.stream, L.sell.nrows,
                        L.sell.nslices, L.sell.slice_ptr.get(), L.sell.slice_len.get(), L.sell.col.get(),
                        sell_val<T>(L.sell), bb, x, rr);
     hipLaunchKernelGGL((k_restrict<T, R>), dim3(grid_for(L.nc)), dim3(WG), 0, c.stream, L.nc, L.pt_ptr.get(),
                        L.pt_col.get(), pval<T>(L, true), (T)L.r_scale, rr, reinterpret_cast<T *>(C.bb.get()));
     CS_LAUNCH_CHECK();
+    trace_end(c, slot);
     vcycle_level<T, R>(c, l + 1);
+    slot = trace_begin(c, CS_TRACE_PROLONG, L.p_nnz * (es + 4.0) + 2.0 * L.n * R * es + L.nc * R * es);
     hipLaunchKernelGGL((k_prolong<T, R>), dim3(grid_for(L.n)), dim3(WG), 0, c.stream, L.n, L.p_ptr.get(),
                        L.p_col.get(), pval<T>(L, false), reinterpret_cast<const T *>(C.xb.get()), x);
     CS_LAUNCH_CHECK();
+    trace_end(c, slot);
     for (int a = 0; a < c.opt.n_post; ++a) {
         T *res = apply_cascade<T, R>(c, L, false, false, bb, x, alt);
         if (res != x) std::swap(x, alt);
@@ -562,13 +576,17 @@ void solve_ir(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
             std::vector<double> hist;
             double bn2[8];
             int it = 0;
+            const double ir_bytes = S.nnz * 12.0 + (double)L0.n * R * (16.0 + sizeof(T));
+            const double up_bytes = (double)L0.n * R * (16.0 + sizeof(T));
             for (;; ++it) {
+                int slot = trace_begin(c, CS_TRACE_REFINE, ir_bytes);
                 hipLaunchKernelGGL((k_ir_residual<T, R>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
                                    S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), b, x,
                                    reinterpret_cast<T *>(L0.bb.get()), c.ir_partial.get());
                 hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(WG), 0, c.stream, G, R, c.ir_partial.get(),
                                    c.ir_norm.get());
                 CS_LAUNCH_CHECK();
+                trace_end(c, slot);
                 c.ir_norm.download(hn.data(), 2 * R, c.stream);
                 CS_HIP(hipStreamSynchronize(c.stream));
                 if (it == 0)
@@ -591,10 +609,13 @@ void solve_ir(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
                     break;
                 }
                 vcycle_level<T, R>(c, 0);
+                slot = trace_begin(c, CS_TRACE_REFINE, up_bytes);
                 hipLaunchKernelGGL((k_add_to64<T>), dim3(grid_for(n)), dim3(WG), 0, c.stream, n,
                                    reinterpret_cast<const T *>(L0.xb.get()), x);
                 CS_LAUNCH_CHECK();
+                trace_end(c, slot);
             }
+            trace_flush(c);
             CS_HIP(hipEventRecord(c.ev1, c.stream));
             CS_HIP(hipEventSynchronize(c.ev1));
             float ms = 0;
