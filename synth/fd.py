@@ -140,7 +140,7 @@ def fv_hierarchy(mu: np.ndarray, bs: int = 1, n_stop: int = 4,
     for li, m in enumerate(sizes):
         b = bs if m % bs == 0 else 1
         A = assemble(faces, b)
-        lv = Level(A=A, block_size=b)
+        lv = Level(A=A, block_size=b ** d)
         if colour:
             lv.colour = parity_colour(m, d, b)
         if li + 1 < len(sizes):

@@ -64,3 +64,10 @@ def test_batch_sizes():
     probs = fd.lognormal_batch(sizes=[64, 80])
     assert probs[1].levels[-1].n == 5 * 5            # 80 -> 40 -> 20 -> 10 -> 5 (odd)
     assert probs[0].levels[-1].n == 8 * 8            # 64 -> ... -> 8
+
+
+def test_block_size_counts_unknowns_per_block():
+    p = fd.interface3d(16, nrhs=1, bs=2)
+    assert [lv.block_size for lv in p.levels] == [8, 8, 8]
+    z = np.ones((8, 8))
+    assert [lv.block_size for lv in fd.fv_hierarchy(z, bs=2, n_stop=2)] == [4, 4, 4]
