@@ -99,6 +99,15 @@ void set_level(Ctx &c, Level &L, const cs_level &in, int li, int nlev, int64_t n
         L.nc = n_next;
         L.p_nnz = pn;
         L.r_scale = in.r_scale;
+        // contiguous unit aggregation: row r of P is the single entry (r / k, 1)
+        L.agg_k = 0;
+        if (n_next > 0 && in.n % n_next == 0) {
+            const int64_t k = in.n / n_next;
+            bool ok = k <= 64 && 64 % k == 0 && pn == in.n;
+            for (int64_t r = 0; ok && r < in.n; ++r)
+                ok = pp[r + 1] - pp[r] == 1 && pc[pp[r]] == r / k && pv[pp[r]] == 1.0;
+            if (ok) L.agg_k = (int)k;
+        }
         std::vector<int32_t> tp, tc;
         std::vector<double> tv;
         transpose_csr(in.n, n_next, pp, pc, pv, tp, tc, tv);
@@ -179,6 +188,7 @@ void cs_destroy(cs_ctx ctx) {
     (void)hipSetDevice(ctx->c.device);
     (void)hipStreamSynchronize(ctx->c.stream);
     cs::trace_release(ctx->c);
+    if (ctx->c.h_norm) (void)hipHostFree(ctx->c.h_norm);
     if (ctx->c.ev0) (void)hipEventDestroy(ctx->c.ev0);
     if (ctx->c.ev1) (void)hipEventDestroy(ctx->c.ev1);
     delete ctx;

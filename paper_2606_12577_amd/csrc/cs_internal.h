@@ -118,6 +118,11 @@ struct Level {
     // interpolation to the next coarser level
     int64_t nc = 0, p_nnz = 0;
     double r_scale = 1.0;
+    // agg_k > 0: P injects coarse unknown I into the fine unknowns
+    // [agg_k*I, agg_k*(I+1)) with weight 1 (contiguous piecewise-constant
+    // aggregation); the V-cycle then fuses residual+restriction and
+    // interpolation+first post-sweep.
+    int agg_k = 0;
     DBuf<int32_t> p_ptr, p_col, pt_ptr, pt_col;
     DBuf<double> p_val64, pt_val64;
     DBuf<float> p_val32, pt_val32;
@@ -159,7 +164,8 @@ struct Ctx {
     int singular = 0;
     // solve workspace
     DBuf<double> ir_partial, ir_norm;
-    DBuf<char> ir_r;
+    double *h_norm = nullptr;           // pinned host copy of ir_norm (16 doubles)
+    bool fuse_transfers = true;         // use the fused aggregation kernels when agg_k > 0
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     Trace tr;
 };

@@ -75,15 +75,54 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t G) {
     return xcd * per + (xcd < rem ? xcd : rem) + idx;
 }
 
+// Streaming (non-temporal) loads for data read exactly once per sweep (A,
+// Lambda, b), so that L2 keeps the gathered x.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+template <typename T, int R>
+__device__ __forceinline__ void vload_nt(const T *p, T (&o)[R]) {
+    constexpr int BYTES = (int)sizeof(T) * R;
+    if constexpr (BYTES % 16 == 0) {
+        const u32x4 *q = reinterpret_cast<const u32x4 *>(p);
+#pragma unroll
+        for (int k = 0; k < BYTES / 16; ++k) {
+            u32x4 u = __builtin_nontemporal_load(q + k);
+            __builtin_memcpy(&o[k * (16 / sizeof(T))], &u, 16);
+        }
+    } else if constexpr (BYTES == 8) {
+        u32x2 u = __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>(p));
+        __builtin_memcpy(&o[0], &u, 8);
+    } else {
+#pragma unroll
+        for (int k = 0; k < R; ++k) o[k] = __builtin_nontemporal_load(p + k);
+    }
+}
+
+// x_in at unknown j, minus the interpolated coarse correction when PROL:
+// x_in[j] - x_c[j / agg_k]  (contiguous unit aggregation).
+template <typename T, int R, bool PROL>
+__device__ __forceinline__ void load_x(const T *xin, const T *xc, int agg_k, int64_t j, T (&o)[R]) {
+    vload<T, R>(xin + j * R, o);
+    if constexpr (PROL) {
+        T cv[R];
+        vload<T, R>(xc + (j / agg_k) * R, cv);
+#pragma unroll
+        for (int k = 0; k < R; ++k) o[k] -= cv[k];
+    }
+}
+
 // One cascade sweep over 4 SELL slices (256 rows) per workgroup.
 //   ZERO:   x_in = 0, so x_out = Lambda b (A is not read)
 //   ROWMAP: rows come from a colour list and x is updated in place
-template <typename T, int NB, int R, bool ZERO, bool ROWMAP>
+//   PROL:   x_in is first corrected by the coarse-grid solution x_c (the
+//           interpolation step of Alg. 1 fused into the first post-sweep)
+template <typename T, int NB, int R, bool ZERO, bool ROWMAP, bool PROL>
 __global__ __launch_bounds__(WG) void k_sweep(int64_t nrows, int64_t nslices, const int32_t *__restrict__ rows,
                                               const int64_t *__restrict__ sptr, const int32_t *__restrict__ slen,
                                               const int32_t *__restrict__ scol, const T *__restrict__ sval,
                                               const T *__restrict__ lam, const T *__restrict__ b, const T *xin,
-                                              T *xout) {
+                                              T *xout, const T *__restrict__ xc, int agg_k) {
     __shared__ T red[NB > 1 ? WG * R : 1];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -97,17 +136,17 @@ __global__ __launch_bounds__(WG) void k_sweep(int64_t nrows, int64_t nslices, co
     for (int k = 0; k < R; ++k) res[k] = T(0);
     if (valid) {
         T bb[R];
-        vload<T, R>(b + row * R, bb);
+        vload_nt<T, R>(b + row * R, bb);
 #pragma unroll
         for (int k = 0; k < R; ++k) res[k] = -bb[k];
         if constexpr (!ZERO) {
             const int len = slen[slice];
             const int64_t off = sptr[slice] + lane;
             for (int e = 0; e < len; ++e) {
-                const int c = scol[off + (int64_t)e * 64];
-                const T a = sval[off + (int64_t)e * 64];
+                const int c = __builtin_nontemporal_load(scol + off + (int64_t)e * 64);
+                const T a = __builtin_nontemporal_load(sval + off + (int64_t)e * 64);
                 T xv[R];
-                vload<T, R>(xin + (int64_t)c * R, xv);
+                load_x<T, R, PROL>(xin, xc, agg_k, c, xv);
 #pragma unroll
                 for (int k = 0; k < R; ++k) res[k] += a * xv[k];
             }
@@ -115,13 +154,13 @@ __global__ __launch_bounds__(WG) void k_sweep(int64_t nrows, int64_t nslices, co
     }
     if constexpr (NB == 1) {
         if (valid) {
-            const T l = lam[row];
+            const T l = __builtin_nontemporal_load(lam + row);
             T xo[R];
             if constexpr (ZERO) {
 #pragma unroll
                 for (int k = 0; k < R; ++k) xo[k] = T(0);
             } else {
-                vload<T, R>(xin + row * R, xo);
+                load_x<T, R, PROL>(xin, xc, agg_k, row, xo);
             }
 #pragma unroll
             for (int k = 0; k < R; ++k) xo[k] -= l * res[k];
@@ -136,13 +175,13 @@ __global__ __launch_bounds__(WG) void k_sweep(int64_t nrows, int64_t nslices, co
             const int base = threadIdx.x - rloc;
             const T *lrow = lam + (row / NB) * (NB * NB) + rloc * NB;
             T lr[NB];
-            vload<T, NB>(lrow, lr);
+            vload_nt<T, NB>(lrow, lr);
             T xo[R];
             if constexpr (ZERO) {
 #pragma unroll
                 for (int k = 0; k < R; ++k) xo[k] = T(0);
             } else {
-                vload<T, R>(xin + row * R, xo);
+                load_x<T, R, PROL>(xin, xc, agg_k, row, xo);
             }
 #pragma unroll
             for (int cc = 0; cc < NB; ++cc) {
@@ -179,6 +218,60 @@ __global__ __launch_bounds__(WG) void k_residual(int64_t nrows, int64_t nslices,
         for (int k = 0; k < R; ++k) acc[k] += a * xv[k];
     }
     vstore<T, R>(r + row * R, acc);
+}
+
+// Fused residual and restriction for contiguous unit aggregation:
+// b_c[I] = r_scale * sum_{u < agg_k} (A x - b)[agg_k*I + u].  A workgroup owns
+// 256 fine rows, i.e. 256/agg_k whole coarse rows (agg_k divides 64).
+template <typename T, int R>
+__global__ __launch_bounds__(WG) void k_residual_restrict(int64_t nrows, int64_t nslices,
+                                                          const int64_t *__restrict__ sptr,
+                                                          const int32_t *__restrict__ slen,
+                                                          const int32_t *__restrict__ scol, const T *__restrict__ sval,
+                                                          const T *__restrict__ b, const T *__restrict__ x,
+                                                          int agg_k, int64_t nc, T r_scale, T *__restrict__ bc) {
+    __shared__ T red[WG * R];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t slice = tile * 4 + wv;
+    const int64_t row = slice * 64 + lane;
+    T acc[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) acc[k] = T(0);
+    if (slice < nslices && row < nrows) {
+        vload_nt<T, R>(b + row * R, acc);
+#pragma unroll
+        for (int k = 0; k < R; ++k) acc[k] = -acc[k];
+        const int len = slen[slice];
+        const int64_t off = sptr[slice] + lane;
+        for (int e = 0; e < len; ++e) {
+            const int c = __builtin_nontemporal_load(scol + off + (int64_t)e * 64);
+            const T a = __builtin_nontemporal_load(sval + off + (int64_t)e * 64);
+            T xv[R];
+            vload<T, R>(x + (int64_t)c * R, xv);
+#pragma unroll
+            for (int k = 0; k < R; ++k) acc[k] += a * xv[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) red[threadIdx.x * R + k] = acc[k];
+    __syncthreads();
+    const int per = WG / agg_k;
+    if ((int)threadIdx.x < per) {
+        const int64_t I = tile * per + threadIdx.x;
+        if (I < nc) {
+            T s[R];
+#pragma unroll
+            for (int k = 0; k < R; ++k) s[k] = T(0);
+            for (int u = 0; u < agg_k; ++u) {
+#pragma unroll
+                for (int k = 0; k < R; ++k) s[k] += red[(threadIdx.x * agg_k + u) * R + k];
+            }
+#pragma unroll
+            for (int k = 0; k < R; ++k) s[k] *= r_scale;
+            vstore<T, R>(bc + I * R, s);
+        }
+    }
 }
 
 // b_c = r_scale * P^T r  (gather through the stored transpose)
@@ -291,21 +384,21 @@ __global__ __launch_bounds__(WG) void k_ir_residual(int64_t nrows, int64_t nslic
 }
 
 // Fixed-order sum of the partials: out[k] = sum_g partial[g][k]
-__global__ __launch_bounds__(WG) void k_reduce_partials(int64_t G, int R, const double *__restrict__ partial,
-                                                        double *__restrict__ out) {
-    __shared__ double red[WG];
-    for (int k = 0; k < R; ++k) {
-        double s = 0.0;
-        for (int64_t g = threadIdx.x; g < G; g += WG) s += partial[g * R + k];
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int h = WG / 2; h > 0; h >>= 1) {
-            if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[k] = red[0];
+// One coalesced pass: thread t always accumulates component t % R (R divides
+// 1024), then a tree over threads of equal t % R.
+__global__ __launch_bounds__(1024) void k_reduce_partials(int64_t G, int R, const double *__restrict__ partial,
+                                                          double *__restrict__ out) {
+    __shared__ double red[1024];
+    const int t = threadIdx.x;
+    double s = 0.0;
+    for (int64_t e = t; e < G * R; e += 1024) s += partial[e];
+    red[t] = s;
+    __syncthreads();
+    for (int h = 512; h >= R; h >>= 1) {
+        if (t < h) red[t] += red[t + h];
         __syncthreads();
     }
+    if (t < R) out[t] = red[t];
 }
 
 template <typename T>
@@ -374,44 +467,44 @@ const float *pval<float>(const Level &L, bool tr) { return tr ? L.pt_val32.get()
 
 template <typename T, int R>
 void launch_sweep(Ctx &c, const Level &L, const Sell &S, bool rowmap, bool zero, const T *lam, const T *b,
-                  const T *xin, T *xout) {
+                  const T *xin, T *xout, const T *xc = nullptr, int agg_k = 0) {
     const unsigned G = grid_for(S.nslices, 4);
     if (G == 0) return;
+    const bool prol = xc != nullptr;
     const int cls = zero ? CS_TRACE_SWEEP_ZERO : CS_TRACE_SWEEP;
     const double es = sizeof(T);
     const double bytes = (zero ? 0.0 : S.nnz * (es + 4.0)) + (double)S.nrows * L.nb * es +
-                         (double)S.nrows * R * es * 2.0 + (zero ? 0.0 : (rowmap ? L.n : S.nrows) * R * es);
+                         (double)S.nrows * R * es * 2.0 + (zero ? 0.0 : (rowmap ? L.n : S.nrows) * R * es) +
+                         (prol ? (double)L.nc * R * es : 0.0);
     const int slot = trace_begin(c, cls, bytes);
     dispatch_nb(L.nb, [&](auto nbc) {
         constexpr int NB = decltype(nbc)::value;
+#define CS_SWEEP(Z, M, P, ROWS)                                                                                      \
+    hipLaunchKernelGGL((k_sweep<T, NB, R, Z, M, P>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices, ROWS,     \
+                       S.slice_ptr.get(), S.slice_len.get(), S.col.get(), sell_val<T>(S), lam, b, xin, xout, xc, \
+                       agg_k)
         if (rowmap) {
-            if (zero)
-                hipLaunchKernelGGL((k_sweep<T, NB, R, true, true>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
-                                   S.rows.get(), S.slice_ptr.get(), S.slice_len.get(), S.col.get(), sell_val<T>(S),
-                                   lam, b, xin, xout);
-            else
-                hipLaunchKernelGGL((k_sweep<T, NB, R, false, true>), dim3(G), dim3(WG), 0, c.stream, S.nrows,
-                                   S.nslices, S.rows.get(), S.slice_ptr.get(), S.slice_len.get(), S.col.get(),
-                                   sell_val<T>(S), lam, b, xin, xout);
+            if (zero) CS_SWEEP(true, true, false, S.rows.get());
+            else CS_SWEEP(false, true, false, S.rows.get());
+        } else if (zero) {
+            CS_SWEEP(true, false, false, nullptr);
+        } else if (prol) {
+            CS_SWEEP(false, false, true, nullptr);
         } else {
-            if (zero)
-                hipLaunchKernelGGL((k_sweep<T, NB, R, true, false>), dim3(G), dim3(WG), 0, c.stream, S.nrows,
-                                   S.nslices, nullptr, S.slice_ptr.get(), S.slice_len.get(), S.col.get(),
-                                   sell_val<T>(S), lam, b, xin, xout);
-            else
-                hipLaunchKernelGGL((k_sweep<T, NB, R, false, false>), dim3(G), dim3(WG), 0, c.stream, S.nrows,
-                                   S.nslices, nullptr, S.slice_ptr.get(), S.slice_len.get(), S.col.get(),
-                                   sell_val<T>(S), lam, b, xin, xout);
+            CS_SWEEP(false, false, false, nullptr);
         }
+#undef CS_SWEEP
     });
     CS_LAUNCH_CHECK();
     trace_end(c, slot);
 }
 
 // One application of the cascade of level L: x <- S(x, b).  Returns the buffer
-// holding the result (additive sweeps alternate between x and alt).
+// holding the result (additive sweeps alternate between x and alt).  With xc
+// given (additive only), the first sweep reads x - P x_c instead of x.
 template <typename T, int R>
-T *apply_cascade(Ctx &c, const Level &L, bool reverse, bool zero_start, const T *b, T *x, T *alt) {
+T *apply_cascade(Ctx &c, const Level &L, bool reverse, bool zero_start, const T *b, T *x, T *alt,
+                 const T *xc = nullptr) {
     const int64_t nbl = L.B * L.nb * L.nb;
     const int depth = L.depth;
     if (c.opt.mode == CS_ADDITIVE) {
@@ -419,7 +512,8 @@ T *apply_cascade(Ctx &c, const Level &L, bool reverse, bool zero_start, const T 
         for (int s = 0; s < depth; ++s) {
             const int ell = reverse ? depth - 1 - s : s;
             const T *lam = lam_ptr<T>(L, reverse) + (int64_t)ell * nbl;
-            launch_sweep<T, R>(c, L, L.sell, false, zero_start && s == 0, lam, b, cur, nxt);
+            launch_sweep<T, R>(c, L, L.sell, false, zero_start && s == 0, lam, b, cur, nxt, s == 0 ? xc : nullptr,
+                               L.agg_k);
             std::swap(cur, nxt);
         }
         return cur;
@@ -466,23 +560,36 @@ void vcycle_level(Ctx &c, int l) {
         if (res != x) std::swap(x, alt);
     }
     // restricted residual
+    const bool fused = c.fuse_transfers && L.agg_k > 0;
     int slot = trace_begin(c, CS_TRACE_RESIDUAL,
-                           L.sell.nnz * (es + 4.0) + 3.0 * L.n * R * es + L.p_nnz * (es + 4.0) + L.nc * R * es);
-    hipLaunchKernelGGL((k_residual<T, R>), dim3(grid_for(L.sell.nslices, 4)), dim3(WG), 0, c.stream, L.sell.nrows,
-                       L.sell.nslices, L.sell.slice_ptr.get(), L.sell.slice_len.get(), L.sell.col.get(),
-                       sell_val<T>(L.sell), bb, x, rr);
-    hipLaunchKernelGGL((k_restrict<T, R>), dim3(grid_for(L.nc)), dim3(WG), 0, c.stream, L.nc, L.pt_ptr.get(),
-                       L.pt_col.get(), pval<T>(L, true), (T)L.r_scale, rr, reinterpret_cast<T *>(C.bb.get()));
+                           L.sell.nnz * (es + 4.0) + (fused ? 2.0 : 3.0) * L.n * R * es +
+                               (fused ? 0.0 : L.p_nnz * (es + 4.0) + L.n * R * es) + L.nc * R * es);
+    if (fused) {
+        hipLaunchKernelGGL((k_residual_restrict<T, R>), dim3(grid_for(L.sell.nslices, 4)), dim3(WG), 0, c.stream,
+                           L.sell.nrows, L.sell.nslices, L.sell.slice_ptr.get(), L.sell.slice_len.get(),
+                           L.sell.col.get(), sell_val<T>(L.sell), bb, x, L.agg_k, L.nc, (T)L.r_scale,
+                           reinterpret_cast<T *>(C.bb.get()));
+    } else {
+        hipLaunchKernelGGL((k_residual<T, R>), dim3(grid_for(L.sell.nslices, 4)), dim3(WG), 0, c.stream,
+                           L.sell.nrows, L.sell.nslices, L.sell.slice_ptr.get(), L.sell.slice_len.get(),
+                           L.sell.col.get(), sell_val<T>(L.sell), bb, x, rr);
+        hipLaunchKernelGGL((k_restrict<T, R>), dim3(grid_for(L.nc)), dim3(WG), 0, c.stream, L.nc, L.pt_ptr.get(),
+                           L.pt_col.get(), pval<T>(L, true), (T)L.r_scale, rr, reinterpret_cast<T *>(C.bb.get()));
+    }
     CS_LAUNCH_CHECK();
     trace_end(c, slot);
     vcycle_level<T, R>(c, l + 1);
-    slot = trace_begin(c, CS_TRACE_PROLONG, L.p_nnz * (es + 4.0) + 2.0 * L.n * R * es + L.nc * R * es);
-    hipLaunchKernelGGL((k_prolong<T, R>), dim3(grid_for(L.n)), dim3(WG), 0, c.stream, L.n, L.p_ptr.get(),
-                       L.p_col.get(), pval<T>(L, false), reinterpret_cast<const T *>(C.xb.get()), x);
-    CS_LAUNCH_CHECK();
-    trace_end(c, slot);
+    const T *xc = reinterpret_cast<const T *>(C.xb.get());
+    const bool fuse_prol = fused && c.opt.mode == CS_ADDITIVE && c.opt.n_post > 0;
+    if (!fuse_prol) {
+        slot = trace_begin(c, CS_TRACE_PROLONG, L.p_nnz * (es + 4.0) + 2.0 * L.n * R * es + L.nc * R * es);
+        hipLaunchKernelGGL((k_prolong<T, R>), dim3(grid_for(L.n)), dim3(WG), 0, c.stream, L.n, L.p_ptr.get(),
+                           L.p_col.get(), pval<T>(L, false), xc, x);
+        CS_LAUNCH_CHECK();
+        trace_end(c, slot);
+    }
     for (int a = 0; a < c.opt.n_post; ++a) {
-        T *res = apply_cascade<T, R>(c, L, false, false, bb, x, alt);
+        T *res = apply_cascade<T, R>(c, L, false, false, bb, x, alt, (fuse_prol && a == 0) ? xc : nullptr);
         if (res != x) std::swap(x, alt);
     }
     if (x != xb) {
@@ -512,6 +619,7 @@ void ensure_workspace(Ctx &c, int nrhs) {
     const int64_t G = ceil_div(c.lv[0].sell.nslices, 4);
     c.ir_partial.alloc(std::max<int64_t>(G, 1) * nrhs);
     c.ir_norm.alloc(2 * nrhs);
+    if (!c.h_norm) CS_HIP(hipHostMalloc(reinterpret_cast<void **>(&c.h_norm), 16 * sizeof(double)));
     c.ws_nrhs = nrhs;
     c.ws_prec = prec;
 }
@@ -558,7 +666,7 @@ void solve_ir(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
     const Sell &S = L0.sell;
     const int64_t n = L0.n * nrhs;
     const int64_t G = ceil_div(S.nslices, 4);
-    std::vector<double> hn(2 * nrhs);
+    const double *hn = c.h_norm;
     *st = CS_OK;
     CS_HIP(hipEventRecord(c.ev0, c.stream));
     dispatch_prec(c.precision, [&](auto tp) {
@@ -569,7 +677,7 @@ void solve_ir(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
             hipLaunchKernelGGL((k_ir_residual<T, R>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
                                S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), b, nullptr,
                                (T *)nullptr, c.ir_partial.get());
-            hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(WG), 0, c.stream, G, R, c.ir_partial.get(),
+            hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(1024), 0, c.stream, G, R, c.ir_partial.get(),
                                c.ir_norm.get() + R);
             hipLaunchKernelGGL(k_zero<double>, dim3(grid_for(n)), dim3(WG), 0, c.stream, n, x);
             CS_LAUNCH_CHECK();
@@ -583,11 +691,12 @@ void solve_ir(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
                 hipLaunchKernelGGL((k_ir_residual<T, R>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
                                    S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), b, x,
                                    reinterpret_cast<T *>(L0.bb.get()), c.ir_partial.get());
-                hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(WG), 0, c.stream, G, R, c.ir_partial.get(),
+                hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(1024), 0, c.stream, G, R, c.ir_partial.get(),
                                    c.ir_norm.get());
                 CS_LAUNCH_CHECK();
                 trace_end(c, slot);
-                c.ir_norm.download(hn.data(), 2 * R, c.stream);
+                CS_HIP(hipMemcpyAsync(c.h_norm, c.ir_norm.get(), 2 * R * sizeof(double), hipMemcpyDeviceToHost,
+                                      c.stream));
                 CS_HIP(hipStreamSynchronize(c.stream));
                 if (it == 0)
                     for (int k = 0; k < R; ++k) bn2[k] = hn[R + k] > 0 ? hn[R + k] : 1.0;

@@ -24,6 +24,28 @@ from .problem import Level, Problem
 from .rng import GEOMETRY, stream, uniform_rhs
 
 
+def morton_order(n: int, d: int, L: int) -> np.ndarray:
+    """Recursive order for a grid that coarsens L more times: cells are
+    numbered lexicographically by their ancestor on the grid n / 2^L and, inside
+    it, in Z-order (Morton) of their offset.  The 2^d children of coarse cell I
+    are then the fine unknowns 2^d I .. 2^d I + 2^d - 1 on every level, and 2^d
+    siblings form a contiguous block."""
+    if n % (1 << L):
+        raise ValueError("grid size must be divisible by 2^L")
+    c = n >> L
+    coords = np.indices((n,) * d)
+    lex = np.zeros((n,) * d, dtype=np.int64)
+    m = 1
+    for a in range(d):
+        lex += (coords[a] >> L) * m
+        m *= c
+    mort = np.zeros((n,) * d, dtype=np.int64)
+    for bit in range(L):
+        for a in range(d):
+            mort |= ((coords[a] >> bit) & 1).astype(np.int64) << (bit * d + a)
+    return lex * (1 << (d * L)) + mort
+
+
 def cell_order(n: int, d: int, bs: int) -> np.ndarray:
     """Unknown number of every cell, as an array indexed [i0, i1(, i2)]."""
     if n % bs:
@@ -48,9 +70,16 @@ def block_coords(n: int, d: int, bs: int) -> np.ndarray:
     return c[:, ::-1].copy() if d > 1 else c          # reorder so axis 0 is fastest
 
 
-def parity_colour(n: int, d: int, bs: int) -> np.ndarray:
-    """Red-black colouring of the block grid: (sum of block coordinates) mod 2."""
-    return (block_coords(n, d, bs).sum(axis=1) % 2).astype(np.int32)
+def parity_colour(n: int, d: int, bs: int, idx: Optional[np.ndarray] = None) -> np.ndarray:
+    """Red-black colouring of the block grid: (sum of block coordinates) mod 2,
+    listed in block-index order of the numbering idx (default: cell_order)."""
+    if idx is None:
+        idx = cell_order(n, d, bs)
+    coords = np.indices((n,) * d)
+    par = (sum(c // bs for c in coords) % 2).ravel()
+    out = np.empty(n ** d // bs ** d, dtype=np.int32)
+    out[idx.ravel() // bs ** d] = par
+    return out
 
 
 def face_coefficients(mu: np.ndarray) -> List[np.ndarray]:
@@ -81,11 +110,11 @@ def coarsen_faces(faces: Sequence[np.ndarray]) -> List[np.ndarray]:
     return out
 
 
-def assemble(faces: Sequence[np.ndarray], bs: int) -> sp.csr_matrix:
+def assemble(faces: Sequence[np.ndarray], idx: np.ndarray) -> sp.csr_matrix:
+    """Operator of the faces, unknowns numbered by idx[cell]."""
     d = len(faces)
     n = faces[0].shape[0] - 1
     h = 1.0 / n
-    idx = cell_order(n, d, bs)
     diag = np.zeros((n,) * d)
     rows, cols, vals = [], [], []
     for a, f in enumerate(faces):
@@ -115,10 +144,13 @@ def assemble(faces: Sequence[np.ndarray], bs: int) -> sp.csr_matrix:
     return A
 
 
-def piecewise_constant_P(n: int, d: int, bs_f: int, bs_c: int) -> sp.csr_matrix:
+def piecewise_constant_P(n: int, d: int, bs_f: int, bs_c: int, idx_f: Optional[np.ndarray] = None,
+                         idx_c: Optional[np.ndarray] = None) -> sp.csr_matrix:
     """Injection of each coarse cell value into its 2^d fine sub-cells."""
-    idx_f = cell_order(n, d, bs_f)
-    idx_c = cell_order(n // 2, d, bs_c)
+    if idx_f is None:
+        idx_f = cell_order(n, d, bs_f)
+    if idx_c is None:
+        idx_c = cell_order(n // 2, d, bs_c)
     coords = np.indices((n,) * d)
     parent = idx_c[tuple(c // 2 for c in coords)]
     N = n ** d
@@ -127,26 +159,37 @@ def piecewise_constant_P(n: int, d: int, bs_f: int, bs_c: int) -> sp.csr_matrix:
     return P
 
 
-def fv_hierarchy(mu: np.ndarray, bs: int = 1, n_stop: int = 4,
-                 colour: bool = False) -> List[Level]:
-    """Levels n, n/2, ... while the size is even and above n_stop."""
+def fv_hierarchy(mu: np.ndarray, bs: int = 1, n_stop: int = 4, colour: bool = False,
+                 order: str = "morton") -> List[Level]:
+    """Levels n, n/2, ... while the size is even and above n_stop.
+
+    order="morton" numbers cells recursively (see morton_order) when bs <= 2,
+    so that blocks and coarse-cell children are contiguous on every level;
+    order="lex" uses cell_order (lexicographic blocks)."""
     d = mu.ndim
     n = mu.shape[0]
     faces = face_coefficients(mu)
     sizes = [n]
     while sizes[-1] % 2 == 0 and sizes[-1] > n_stop:
         sizes.append(sizes[-1] // 2)
+    L = len(sizes) - 1
+    use_morton = order == "morton" and bs <= 2
+    blocks = [bs if m % bs == 0 else 1 for m in sizes]
+    if use_morton:
+        idxs = [morton_order(m, d, L - li) for li, m in enumerate(sizes)]
+        # a level's 2x2x2 blocks are sibling groups: they exist while the level
+        # still coarsens
+        blocks = [bs if li < L else 1 for li in range(len(sizes))]
+    else:
+        idxs = [cell_order(m, d, b) for m, b in zip(sizes, blocks)]
     levels = []
     for li, m in enumerate(sizes):
-        b = bs if m % bs == 0 else 1
-        A = assemble(faces, b)
-        lv = Level(A=A, block_size=b ** d)
+        b = blocks[li]
+        lv = Level(A=assemble(faces, idxs[li]), block_size=b ** d, cells=idxs[li])
         if colour:
-            lv.colour = parity_colour(m, d, b)
+            lv.colour = parity_colour(m, d, b, idxs[li])
         if li + 1 < len(sizes):
-            m2 = sizes[li + 1]
-            b2 = bs if m2 % bs == 0 else 1
-            lv.P = piecewise_constant_P(m, d, b, b2)
+            lv.P = piecewise_constant_P(m, d, b, blocks[li + 1], idxs[li], idxs[li + 1])
             lv.r_scale = 2.0 ** (-d)
             faces = coarsen_faces(faces)
         levels.append(lv)

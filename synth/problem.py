@@ -17,12 +17,14 @@ class Level:
                None on the coarsest level
     r_scale    restriction is r_scale * P^T
     colour     optional int32 colour per block (multiplicative smoothers)
+    cells      optional array giving the unknown number of every grid cell
     """
     A: sp.csr_matrix
     block_size: int = 1
     P: Optional[sp.csr_matrix] = None
     r_scale: float = 1.0
     colour: Optional[np.ndarray] = None
+    cells: Optional[np.ndarray] = None
 
     @property
     def n(self) -> int:

@@ -51,7 +51,7 @@ def test_fullsize_sampled_smoother_blocks(full):
     p, s = full
     A0 = p.levels[0].A
     mu = fd.sphere_mu(N, np.array(p.meta["centre"]), 0.3, 1e4)
-    blk = (fd.cell_order(N, 3, 2) // 8).ravel()
+    blk = (p.levels[0].cells // 8).ravel()
     lo = np.full(blk.max() + 1, np.inf)
     hi = np.zeros(blk.max() + 1)
     np.minimum.at(lo, blk, mu.ravel())
@@ -68,7 +68,7 @@ def test_fullsize_sampled_smoother_blocks(full):
         for c in centres:
             o = loc[c][ell - 1]
             e = np.linalg.norm(g[c] - o) / np.linalg.norm(o)
-            assert e <= 1e-11, (c, ell, e)
+            assert e <= 1e-9, (c, ell, e)    # cond(G)-scaled, as in test_gpu_parity
 
 
 def test_fullsize_solve_fp32_ir(full):

@@ -3,10 +3,17 @@
 Every expected value comes from the FP64 CPU oracle on the same seeded inputs.
 Tolerances:
   * integer artefacts (patterns, colours): bit-exact;
-  * FP64 smoother blocks: normwise relative 1e-11 per block (different
-    summation order and Cholesky vs eigen pseudo-inverse in the normal
-    equations; both are ~cond(G) * 1e-16 with cond(G) <= 1e3 here);
-  * FP64 smoother application and V-cycle: normwise relative 1e-12;
+  * FP64 smoother blocks: normwise relative 1e-9 per block.  G_i = M_i M_i^T
+    sums up to ~10^3 products, so the two summation orders leave ~1e-13
+    relative differences in G_i and H_i; the solve amplifies them by cond(G_i),
+    which stays below 1e4 for the non-singular blocks met here.  Blocks whose
+    G_i is exactly singular (they occur from the second cascade level on) are
+    compared through the minimum-norm solution, both sides cutting eigenvalues
+    below 1e-13 of the largest;
+  * FP64 V-cycle with the oracle's smoothers injected: normwise relative 1e-12
+    (only summation order differs);
+  * FP64 V-cycle with the GPU's own setup: 1e-10 (inherits the smoother
+    differences above);
   * FP32 V-cycle: normwise relative 1e-5 against the FP64 oracle (about
     100 x the FP32 unit round-off for the ~40 dependent sweeps of a V-cycle).
 """
@@ -21,8 +28,9 @@ from synth.rng import TEST, stream
 
 pytestmark = pytest.mark.gpu
 
-LAM_TOL = 1e-11
+LAM_TOL = 1e-9
 APPLY_TOL = 1e-12
+SETUP_APPLY_TOL = 1e-10
 FP32_TOL = 1e-5
 
 
@@ -54,6 +62,26 @@ def check_smoothers(s, sm, prob, depth):
             g = s.get_smoother(l, ell)
             o = sm[l]["lam"][ell - 1]
             assert blockwise_rel(g, o) <= LAM_TOL, (l, ell, blockwise_rel(g, o))
+
+
+def inject(s, sm):
+    """Replace the GPU's smoothers by the oracle's (every level and ell)."""
+    for l, d in enumerate(sm):
+        for ell, L in enumerate(d["lam"]):
+            s.set_smoother(l, ell + 1, L)
+
+
+def check_vcycle(s, sm, prob, order="RF", npre=1, npost=1, b=None):
+    """V b against the oracle: with the GPU's own setup, then with the oracle's
+    smoothers injected (the apply path alone)."""
+    b = prob.rhs if b is None else b
+    o = O.vcycle(prob.levels, sm, b, order, npre, npost)
+    g = s.vcycle(b).cpu().numpy()
+    assert rel(g, o) <= SETUP_APPLY_TOL, ("own setup", rel(g, o))
+    inject(s, sm)
+    g = s.vcycle(b).cpu().numpy()
+    assert rel(g, o) <= APPLY_TOL, ("injected", rel(g, o))
+    return o
 
 
 def check_patterns(s, sm, prob):
@@ -89,13 +117,12 @@ def test_poisson64_apply_and_vcycle_parity(gpu_lib, poisson64):
     s = gpu_solver(gpu_lib, p, depth=3, n_pre=2, n_post=2)
     rng = stream(1, TEST, 0)
     x0 = rng.uniform(-1, 1, size=p.rhs.shape)
+    inject(s, sm)
     for rev in (False, True):
         g = s.smooth(0, p.rhs, x0, reverse=rev).cpu().numpy()
         o = O.smooth(p.levels[0].A, sm[0], x0, p.rhs, reverse=rev)
         assert rel(g, o) <= APPLY_TOL, (rev, rel(g, o))
-    g = s.vcycle(p.rhs).cpu().numpy()
-    o = O.vcycle(p.levels, sm, p.rhs, "RF", 2, 2)
-    assert rel(g, o) <= APPLY_TOL, rel(g, o)
+    check_vcycle(s, sm, p, "RF", 2, 2)
 
 
 def test_poisson64_solve(gpu_lib, poisson64):
@@ -131,9 +158,7 @@ def test_interface_setup_parity(gpu_lib, iface32):
 def test_interface_vcycle_fp64_and_fp32(gpu_lib, iface32, order):
     p, sm = iface32
     s = gpu_solver(gpu_lib, p, depth=4, order=order)
-    o = O.vcycle(p.levels, sm, p.rhs, order)
-    g = s.vcycle(p.rhs).cpu().numpy()
-    assert rel(g, o) <= APPLY_TOL, rel(g, o)
+    o = check_vcycle(s, sm, p, order)
     s.set_precision("fp32")
     g32 = s.vcycle(p.rhs).cpu().numpy()
     err = rel(g32, o)
@@ -162,8 +187,7 @@ def test_ragged_sizes(gpu_lib):
     sm = oracle_setup(p, 3)
     s = gpu_solver(gpu_lib, p, depth=3)
     check_smoothers(s, sm, p, 3)
-    g = s.vcycle(p.rhs).cpu().numpy()
-    assert rel(g, O.vcycle(p.levels, sm, p.rhs)) <= APPLY_TOL
+    check_vcycle(s, sm, p)
 
 
 @pytest.mark.parametrize("bs", [2, 4])
@@ -176,8 +200,7 @@ def test_block_sizes_2d(gpu_lib, bs):
     s = gpu_solver(gpu_lib, p, depth=2)
     check_smoothers(s, sm, p, 2)
     check_patterns(s, sm, p)
-    g = s.vcycle(p.rhs).cpu().numpy()
-    assert rel(g, O.vcycle(p.levels, sm, p.rhs)) <= APPLY_TOL
+    check_vcycle(s, sm, p)
 
 
 # ---------------------------------------------------------------------------
@@ -188,18 +211,17 @@ def test_multiplicative_red_black_2d(gpu_lib):
     p = fd.lognormal2d(32, nrhs=2, n_stop=4)
     for lv in p.levels:
         m = int(round(np.sqrt(lv.n)))
-        lv.colour = fd.parity_colour(m, 2, 1)
+        lv.colour = fd.parity_colour(m, 2, 1, lv.cells)
     sm = oracle_setup(p, 3, "multiplicative")
     for order in ("FF", "RF"):
         s = gpu_solver(gpu_lib, p, depth=3, mode="multiplicative", order=order)
         check_smoothers(s, sm, p, 3)
         check_patterns(s, sm, p)
+        check_vcycle(s, sm, p, order)
         x0 = stream(2, TEST).uniform(-1, 1, size=p.rhs.shape)
         for rev in (False, True):
             g = s.smooth(0, p.rhs, x0, reverse=rev).cpu().numpy()
             assert rel(g, O.smooth(p.levels[0].A, sm[0], x0, p.rhs, rev)) <= APPLY_TOL
-        g = s.vcycle(p.rhs).cpu().numpy()
-        assert rel(g, O.vcycle(p.levels, sm, p.rhs, order)) <= APPLY_TOL
 
 
 def test_multiplicative_greedy_colouring_blocks(gpu_lib):
@@ -212,8 +234,7 @@ def test_multiplicative_greedy_colouring_blocks(gpu_lib):
         np.testing.assert_array_equal(s.get_colours(l), sm[l]["colours"])
     check_smoothers(s, sm, p, 2)
     check_patterns(s, sm, p)
-    g = s.vcycle(p.rhs).cpu().numpy()
-    assert rel(g, O.vcycle(p.levels, sm, p.rhs, "FF")) <= APPLY_TOL
+    check_vcycle(s, sm, p, "FF")
 
 
 def test_improper_colouring_is_rejected(gpu_lib):
@@ -242,8 +263,7 @@ def test_depth_one_and_single_level(gpu_lib):
     p = fd.lognormal2d(16, nrhs=1, n_stop=4)
     sm = oracle_setup(p, 1)
     s = gpu_solver(gpu_lib, p, depth=1, n_pre=2, n_post=3)
-    g = s.vcycle(p.rhs).cpu().numpy()
-    assert rel(g, O.vcycle(p.levels, sm, p.rhs, "RF", 2, 3)) <= APPLY_TOL
+    check_vcycle(s, sm, p, "RF", 2, 3)
     one = Problem("bottom", [Level(A=p.levels[-1].A)], stream(3, 0).uniform(-1, 1, size=(p.levels[-1].n, 1)))
     s1 = gpu_solver(gpu_lib, one, depth=1)
     g = s1.vcycle(one.rhs).cpu().numpy()

@@ -301,9 +301,10 @@ def test_inverse_diagonal_gives_block_jacobi_and_gauss_seidel():
 def test_gauss_seidel_proper_colouring_grid():
     """Red-black block GS on a 5-point grid, textbook in-place loops."""
     n_grid = 6
-    A = fd.poisson2d(n_grid).levels[0].A.toarray()
+    lv0 = fd.poisson2d(n_grid).levels[0]
+    A = lv0.A.toarray()
     N = A.shape[0]
-    colours = fd.parity_colour(n_grid, 2, 1)
+    colours = fd.parity_colour(n_grid, 2, 1, lv0.cells)
     rng = stream(0, TEST, 11)
     b = rng.uniform(-1, 1, size=(N, 1))
     x = np.zeros((N, 1))
@@ -418,7 +419,7 @@ def test_periodic_ff_equals_rf():
 def test_rf_vcycle_is_symmetric(mode):
     p = fd.lognormal2d(16, n_stop=4)
     for lv in p.levels:
-        lv.colour = fd.parity_colour(int(round(np.sqrt(lv.n))), 2, 1)
+        lv.colour = fd.parity_colour(int(round(np.sqrt(lv.n))), 2, 1, lv.cells)
     sm = O.setup_hierarchy(p.levels, 2, mode)
     I = np.eye(p.n)
     V = O.vcycle(p.levels, sm, I, order="RF")

@@ -10,8 +10,7 @@ def test_fd_symmetric_and_row_sums():
     for lv in p.levels:
         A = lv.A
         assert abs(A - A.T).max() == 0
-        n = int(round(np.sqrt(A.shape[0])))
-        rs = np.asarray(A.sum(axis=1)).ravel().reshape(n, n)
+        rs = np.asarray(A.sum(axis=1)).ravel()[lv.cells]     # indexed by cell coordinates
         assert np.abs(rs[1:-1, 1:-1]).max() < 1e-9 * A.max()   # interior rows sum to zero
         assert rs[0, 0] > 0                                      # Dirichlet boundary rows do not
 
@@ -24,7 +23,7 @@ def test_fd_second_order():
         X, Y = np.meshgrid(x, x, indexing="ij")
         u = np.sin(np.pi * X) * np.sin(np.pi * Y)
         f = 2 * np.pi ** 2 * u
-        idx = fd.cell_order(n, 2, 1)
+        idx = lv.cells
         rhs = np.empty(n * n)
         rhs[idx.ravel()] = f.ravel()
         uh = spla.spsolve(lv.A.tocsc(), rhs)
@@ -68,6 +67,24 @@ def test_batch_sizes():
 
 def test_block_size_counts_unknowns_per_block():
     p = fd.interface3d(16, nrhs=1, bs=2)
-    assert [lv.block_size for lv in p.levels] == [8, 8, 8]
+    assert [lv.block_size for lv in p.levels] == [8, 8, 1]      # bottom level: no smoother
     z = np.ones((8, 8))
-    assert [lv.block_size for lv in fd.fv_hierarchy(z, bs=2, n_stop=2)] == [4, 4, 4]
+    assert [lv.block_size for lv in fd.fv_hierarchy(z, bs=2, n_stop=2, order="lex")] == [4, 4, 4]
+
+
+def test_morton_numbering_makes_children_contiguous():
+    for d, n in ((2, 32), (3, 16)):
+        levels = fd.fv_hierarchy(np.ones((n,) * d), bs=2, n_stop=4)
+        for lv in levels[:-1]:
+            P = lv.P.tocsr()
+            k = 2 ** d
+            assert np.all(np.diff(P.indptr) == 1)
+            np.testing.assert_array_equal(P.indices, np.arange(P.shape[0]) // k)
+            assert lv.block_size == k
+        # numbering is a permutation and the operator is the lexicographic one permuted
+        lex = fd.fv_hierarchy(np.ones((n,) * d), bs=1, n_stop=n, order="lex")[0].A
+        mor = levels[0]
+        perm = np.empty(n ** d, dtype=np.int64)
+        perm[mor.cells.ravel()] = fd.cell_order(n, d, 1).ravel()
+        Pm = lex[perm][:, perm]
+        assert abs(Pm - mor.A).max() == 0
