@@ -50,6 +50,36 @@ def cpu_baseline(n: int, nrhs: int, depth: int):
                         f"solve {t_solve:.2f} s timed, setup {t_setup:.2f} s not timed"))
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_interface3d_128_traffic.md")
+
+
+def kernel_source_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("solve.hip", "cs_internal.h"):
+        with open(os.path.join(ROOT, "paper_2606_12577_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(args):
+    """HBM bytes per launch of the sweep kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain-copy calibration),
+    or None when the summary is missing, for another workload, or older than
+    the kernel source."""
+    if args.n != 128 or args.nrhs != 8 or args.precision != "fp32" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if line.startswith("traffic:"):
+            for kv in line.split()[1:]:
+                k, v = kv.split("=")
+                vals[k] = v
+    if vals.get("source") != kernel_source_digest():
+        return None
+    return int(float(vals["bytes_per_launch"]))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,6 +94,9 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-baseline", action="store_true")
+    ap.add_argument("--no-trace", action="store_true", help="do not time the sweep kernel with events")
+    ap.add_argument("--trace-period", type=int, default=8,
+                    help="time every n-th launch of the sweep kernel with HIP events")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -101,7 +134,8 @@ def main():
         log(f"warmup {w}: setup {info['setup_ms']:.1f} ms, solve {info['solve_ms']:.1f} ms, "
             f"{info['iterations']} it, rho {info['rho']:.4f}")
     torch.cuda.synchronize()
-    s.trace(("sweep",))
+    if not args.no_trace:
+        s.trace(("sweep",), period=args.trace_period)
     t0 = time.perf_counter()
     infos = []
     for k in range(args.steps):
@@ -122,10 +156,11 @@ def main():
     sw = tr["sweep"]
     avg_ms = sw["ms"] / max(sw["launches"], 1)
     bytes_per_launch = sw["bytes"] / max(sw["launches"], 1)
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                    kernel=f"k_sweep<{'float' if args.precision == 'fp32' else 'double'}, 8, {args.nrhs}, false, false>",
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    roofline = None if args.no_trace else dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(args),
+                    kernel=(f"k_sweep<{'float' if args.precision == 'fp32' else 'double'}, 8, {args.nrhs}, "
+                            "false, false, false, 256> (cascade sweep reading A, large levels)"),
                     launches=sw["launches"], avg_us=round(avg_ms * 1e3, 2),
                     algorithmic_bytes_per_launch=int(bytes_per_launch))
 

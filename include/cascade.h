@@ -154,22 +154,26 @@ cs_status cs_solve(cs_ctx ctx, const double *b, double *x, int32_t nrhs, double 
 
 /* Device timing of kernel classes with HIP events recorded on the context's
  * stream around every launch of the class (for measurement; adds one event pair
- * per launch).  cs_trace(ctx, mask) clears the counters and records the
- * classes whose bit (1 << class) is set in mask; mask 0 stops.  cs_trace_read
+ * per recorded launch).  cs_trace(ctx, mask, period) clears the counters and
+ * records every period-th launch (period >= 1) of each class whose bit
+ * (1 << class) is set in mask; mask 0 stops.  Sampling keeps the event
+ * records from perturbing the timed work.  cs_trace_read
  * returns the summed kernel time in ms, the number of launches and the
  * algorithmic bytes those launches must move (structural non-zeros of A with
  * their 32-bit column index, the Lambda blocks, and each vector read or
  * written once). */
 typedef enum {
-    CS_TRACE_SWEEP = 0,         /* cascade sweeps that read A (every level) */
+    CS_TRACE_SWEEP = 0,         /* cascade sweeps that read A on large levels (>= 2^19 unknowns) */
     CS_TRACE_SWEEP_ZERO = 1,    /* first sweep from a zero guess: x = Lambda b */
     CS_TRACE_RESIDUAL = 2,      /* residual + restriction, all levels */
-    CS_TRACE_PROLONG = 3,       /* interpolation + correction */
+    CS_TRACE_PROLONG = 3,       /* interpolation + correction (separate kernel) */
     CS_TRACE_BOTTOM = 4,        /* bottom-level solve */
     CS_TRACE_REFINE = 5,        /* FP64 refinement residual and update */
-    CS_TRACE_NCLASS = 6
+    CS_TRACE_SWEEP_PROLONG = 6, /* first post-sweep with the interpolation fused in */
+    CS_TRACE_SWEEP_SMALL = 7,   /* cascade sweeps that read A on small levels */
+    CS_TRACE_NCLASS = 8
 } cs_trace_class;
-cs_status cs_trace(cs_ctx ctx, int32_t mask);
+cs_status cs_trace(cs_ctx ctx, int32_t mask, int32_t period);
 cs_status cs_trace_read(cs_ctx ctx, int32_t cls, double *total_ms, int64_t *launches, double *bytes);
 
 /* Persist / restore a setup (smoothers, colours, bottom factor) for the same hierarchy. */

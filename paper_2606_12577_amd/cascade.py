@@ -73,7 +73,7 @@ SIGNATURES = {
     "cs_smooth": (_I32, [_VP, _I32, _I32, _VP, _VP, _I32]),
     "cs_vcycle": (_I32, [_VP, _VP, _VP, _I32]),
     "cs_solve": (_I32, [_VP, _VP, _VP, _I32, _D, _I32, _p(cs_info), _p(_D)]),
-    "cs_trace": (_I32, [_VP, _I32]),
+    "cs_trace": (_I32, [_VP, _I32, _I32]),
     "cs_trace_read": (_I32, [_VP, _I32, _p(_D), _p(_I64), _p(_D)]),
     "cs_save_setup": (_I32, [_VP, ctypes.c_char_p]),
     "cs_load_setup": (_I32, [_VP, ctypes.c_char_p]),
@@ -262,15 +262,16 @@ class Solver:
                        solve_ms=info.solve_ms, singular_blocks=info.singular_blocks,
                        history=hist[:k + 1].copy(), status=st)
 
-    TRACE_CLASSES = ("sweep", "sweep_zero", "residual", "prolong", "bottom", "refine")
+    TRACE_CLASSES = ("sweep", "sweep_zero", "residual", "prolong", "bottom", "refine", "sweep_prolong",
+                     "sweep_small")
 
-    def trace(self, classes=("sweep",)):
-        """Start (clearing the counters) per-kernel-class event timing of the
-        given classes; an empty sequence stops it."""
+    def trace(self, classes=("sweep",), period: int = 1):
+        """Start (clearing the counters) event timing of every period-th launch
+        of the given kernel classes; an empty sequence stops it."""
         mask = 0
         for name in classes:
             mask |= 1 << self.TRACE_CLASSES.index(name)
-        self._check(self._lib.cs_trace(self._h, mask))
+        self._check(self._lib.cs_trace(self._h, mask, period))
 
     def trace_read(self):
         out = {}

@@ -1,5 +1,6 @@
 // C ABI of the cascading-smoother multigrid library; see include/cascade.h.
 #include <cstdio>
+#include <cstdlib>
 #include <exception>
 #include <fstream>
 
@@ -174,7 +175,15 @@ cs_status cs_create(cs_ctx *out, int32_t device, void *stream) {
     if (!h) return CS_ENOMEM;
     h->c.device = device;
     h->c.stream = reinterpret_cast<hipStream_t>(stream);
-    if (hipEventCreate(&h->c.ev0) != hipSuccess || hipEventCreate(&h->c.ev1) != hipSuccess) {
+    if (const char *g = std::getenv("CS_SWEEP_GRID")) {   // tuning override
+        const long v = std::strtol(g, nullptr, 10);
+        if (v >= 8) h->c.sweep_grid = (v / 8) * 8;
+    }
+    if (const char *f = std::getenv("CS_FUSE_TRANSFERS")) h->c.fuse_transfers = std::atoi(f) != 0;
+    if (const char *f = std::getenv("CS_GRAPHS")) h->c.use_graphs = std::atoi(f) != 0;
+    if (hipEventCreate(&h->c.ev0) != hipSuccess || hipEventCreate(&h->c.ev1) != hipSuccess ||
+        hipEventCreateWithFlags(&h->c.ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->c.ev_out, hipEventDisableTiming) != hipSuccess) {
         g_create_err = "hipEventCreate failed";
         delete h;
         return CS_EDEVICE;
@@ -188,6 +197,13 @@ void cs_destroy(cs_ctx ctx) {
     (void)hipSetDevice(ctx->c.device);
     (void)hipStreamSynchronize(ctx->c.stream);
     cs::trace_release(ctx->c);
+    cs::graph_release(ctx->c);
+    if (ctx->c.work) {
+        (void)hipStreamSynchronize(ctx->c.work);
+        (void)hipStreamDestroy(ctx->c.work);
+    }
+    if (ctx->c.ev_in) (void)hipEventDestroy(ctx->c.ev_in);
+    if (ctx->c.ev_out) (void)hipEventDestroy(ctx->c.ev_out);
     if (ctx->c.h_norm) (void)hipHostFree(ctx->c.h_norm);
     if (ctx->c.ev0) (void)hipEventDestroy(ctx->c.ev0);
     if (ctx->c.ev1) (void)hipEventDestroy(ctx->c.ev1);
@@ -202,6 +218,8 @@ cs_status cs_set_hierarchy(cs_ctx ctx, int32_t n_levels, const cs_level *levels)
         c.have_setup = false;
         c.have_hierarchy = false;
         c.ws_nrhs = 0;
+        cs::graph_release(c);
+        c.gen++;
         c.lv.clear();
         c.lv.resize(n_levels);
         for (int l = 0; l < n_levels; ++l)
@@ -436,6 +454,17 @@ namespace cs {
 int trace_begin(Ctx &c, int cls, double bytes) {
     Trace &t = c.tr;
     if (!t.on || !((t.mask >> cls) & 1)) return -1;
+    if (t.seen[cls]++ % t.period != 0) return -1;
+    if (t.capturing) {
+        // graph slot g is returned as -(g + 2); its events come from the pool
+        // created before the capture began
+        const int g = (int)t.gcls.size();
+        if (2 * (size_t)g + 2 > t.gev.size()) fail(CS_EDEVICE, "trace event pool exhausted during graph capture");
+        t.gcls.push_back(cls);
+        t.gbytes.push_back(bytes);
+        CS_HIP(hipEventRecordWithFlags(t.gev[2 * g], c.stream, hipEventRecordExternal));
+        return -(g + 2);
+    }
     if (2 * t.used + 2 > t.ev.size()) {
         hipEvent_t a, b;
         CS_HIP(hipEventCreate(&a));
@@ -453,8 +482,42 @@ int trace_begin(Ctx &c, int cls, double bytes) {
 }
 
 void trace_end(Ctx &c, int slot) {
-    if (slot < 0) return;
+    if (slot == -1) return;
+    if (slot <= -2) {
+        const int g = -slot - 2;
+        CS_HIP(hipEventRecordWithFlags(c.tr.gev[2 * g + 1], c.stream, hipEventRecordExternal));
+        return;
+    }
     CS_HIP(hipEventRecord(c.tr.ev[2 * slot + 1], c.stream));
+}
+
+void trace_graph_accumulate(Ctx &c) {
+    Trace &t = c.tr;
+    for (size_t g = 0; g < t.gcls.size(); ++g) {
+        float ms = 0;
+        CS_HIP(hipEventElapsedTime(&ms, t.gev[2 * g], t.gev[2 * g + 1]));
+        t.ms[t.gcls[g]] += ms;
+        t.count[t.gcls[g]] += 1;
+        t.bytes[t.gcls[g]] += t.gbytes[g];
+    }
+}
+
+void graph_release(Ctx &c) {
+    if (c.gexec) (void)hipGraphExecDestroy(c.gexec);
+    if (c.graph) (void)hipGraphDestroy(c.graph);
+    c.gexec = nullptr;
+    c.graph = nullptr;
+    c.tr.gcls.clear();
+    c.tr.gbytes.clear();
+    c.gkey = Ctx::GraphKey{};
+}
+
+void trace_graph_pool(Ctx &c, size_t slots) {
+    while (c.tr.gev.size() < 2 * slots) {
+        hipEvent_t e;
+        CS_HIP(hipEventCreate(&e));
+        c.tr.gev.push_back(e);
+    }
 }
 
 void trace_flush(Ctx &c) {
@@ -472,6 +535,8 @@ void trace_flush(Ctx &c) {
 }
 
 void trace_release(Ctx &c) {
+    for (hipEvent_t e : c.tr.gev) (void)hipEventDestroy(e);
+    c.tr.gev.clear();
     for (hipEvent_t e : c.tr.ev) (void)hipEventDestroy(e);
     c.tr.ev.clear();
     c.tr.cls.clear();
@@ -483,16 +548,19 @@ void trace_release(Ctx &c) {
 
 extern "C" {
 
-cs_status cs_trace(cs_ctx ctx, int32_t mask) {
+cs_status cs_trace(cs_ctx ctx, int32_t mask, int32_t period) {
     return guarded(ctx, [&](Ctx &c) {
+        need(period >= 1, "trace period must be >= 1");
         cs::trace_flush(c);
         c.tr.mask = mask;
+        c.tr.period = period;
         const int32_t enable = mask;
         if (enable) {
             for (int k = 0; k < CS_TRACE_NCLASS; ++k) {
                 c.tr.ms[k] = 0;
                 c.tr.count[k] = 0;
                 c.tr.bytes[k] = 0;
+                c.tr.seen[k] = 0;
             }
         }
         c.tr.on = enable != 0;

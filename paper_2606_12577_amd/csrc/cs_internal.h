@@ -142,10 +142,18 @@ struct Level {
 struct Trace {
     bool on = false;
     int mask = 0;                        // bit k: record class k
+    int period = 1;                      // record every period-th launch of a class
+    int64_t seen[CS_TRACE_NCLASS] = {0};
     std::vector<hipEvent_t> ev;          // pairs: ev[2k] start, ev[2k+1] end
     std::vector<int> cls;
     std::vector<double> cls_bytes;       // per recorded launch
     size_t used = 0;
+    // launches recorded while a graph is captured: external event-record
+    // nodes, read back after every replay
+    bool capturing = false;
+    std::vector<hipEvent_t> gev;
+    std::vector<int> gcls;
+    std::vector<double> gbytes;
     double ms[CS_TRACE_NCLASS] = {0};
     int64_t count[CS_TRACE_NCLASS] = {0};
     double bytes[CS_TRACE_NCLASS] = {0};
@@ -166,9 +174,29 @@ struct Ctx {
     DBuf<double> ir_partial, ir_norm;
     double *h_norm = nullptr;           // pinned host copy of ir_norm (16 doubles)
     bool fuse_transfers = true;         // use the fused aggregation kernels when agg_k > 0
+    int64_t sweep_grid = int64_t(1) << 40;   // cap on workgroups of the tiled kernels (multiple of 8)
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     Trace tr;
+    // graph replay of one refinement iteration (on the internal work stream)
+    bool use_graphs = false;            // measured no faster than eager launches; CS_GRAPHS=1 enables
+    uint64_t gen = 0;                   // bumped whenever device buffers the graph uses change
+    hipStream_t work = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    struct GraphKey {
+        const void *b = nullptr, *x = nullptr;
+        int nrhs = 0, prec = -1, mask = 0;
+        uint64_t gen = 0;
+        bool operator==(const GraphKey &o) const {
+            return b == o.b && x == o.x && nrhs == o.nrhs && prec == o.prec && mask == o.mask && gen == o.gen;
+        }
+    } gkey;
 };
+
+void graph_release(Ctx &c);
+void trace_graph_accumulate(Ctx &c);
+void trace_graph_pool(Ctx &c, size_t slots);   // pre-create events for `slots` traced launches
 
 // tracing helpers (api.hip)
 int trace_begin(Ctx &c, int cls, double bytes);   // returns slot or -1

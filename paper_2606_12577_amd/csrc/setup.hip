@@ -987,6 +987,7 @@ void factor_bottom(Ctx &c, Level &L) {
 }
 
 void build_working_copies(Ctx &c) {
+    c.gen++;   // buffers change: captured graphs are stale
     for (size_t l = 0; l + 1 < c.lv.size(); ++l) {
         Level &L = c.lv[l];
         const int64_t tot = (int64_t)L.depth * L.B * L.nb * L.nb;

@@ -25,6 +25,8 @@ namespace cs {
 namespace {
 
 constexpr int WG = 256;
+constexpr int64_t IR_GRID = 1024;   // workgroups of the refinement residual (8 per XCD-CU group)
+constexpr int64_t SMALL_SLICES = 8192;   // below this many 64-row slices a level counts as small
 
 template <typename T, int R>
 __device__ __forceinline__ void vload(const T *p, T (&o)[R]) {
@@ -75,6 +77,20 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t G) {
     return xcd * per + (xcd < rem ? xcd : rem) + idx;
 }
 
+// Tiles (256 rows each) handled by this workgroup.  With a workgroup per tile
+// the hardware id is remapped by xcd_tile; with fewer workgroups (a multiple
+// of 8, resident all at once) each XCD sweeps one contiguous range of tiles
+// with its workgroups interleaved, so they advance through the range together.
+struct Tiles {
+    int64_t t, end, step;
+};
+__device__ __forceinline__ Tiles my_tiles(int64_t ntiles) {
+    const int64_t G = gridDim.x, b = blockIdx.x;
+    if (G >= ntiles) return Tiles{xcd_tile(b, G), ntiles, G};
+    const int64_t xcd = b & 7, j = b >> 3, gx = G >> 3;
+    return Tiles{ntiles * xcd / 8 + j, ntiles * (xcd + 1) / 8, gx};
+}
+
 // Streaming (non-temporal) loads for data read exactly once per sweep (A,
 // Lambda, b), so that L2 keeps the gathered x.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -112,21 +128,73 @@ __device__ __forceinline__ void load_x(const T *xin, const T *xc, int agg_k, int
     }
 }
 
+// acc += (A x_in)_row for the SELL row at entry offset `off` (lane included)
+// with `len` stored entries.  Column indices and values are fetched U at a
+// time before the dependent x gathers, so each wavefront keeps 2U loads and
+// then U gathers in flight instead of one chain per entry.
+// Exactly L entries, straight-line: L index/value loads, then L gathers, then
+// the FMAs, so a wavefront has all of them in flight before its first wait.
+template <typename T, int R, bool PROL, int L, typename TA>
+__device__ __forceinline__ void spmv_fixed(const int32_t *__restrict__ scol, const TA *__restrict__ sval,
+                                           int64_t off, const T *xin, const T *xc, int agg_k, T (&acc)[R]) {
+    int cc[L];
+    TA aa[L];
+#pragma unroll
+    for (int u = 0; u < L; ++u) {
+        cc[u] = __builtin_nontemporal_load(scol + off + (int64_t)u * 64);
+        aa[u] = __builtin_nontemporal_load(sval + off + (int64_t)u * 64);
+    }
+    T xv[L][R];
+#pragma unroll
+    for (int u = 0; u < L; ++u) load_x<T, R, PROL>(xin, xc, agg_k, cc[u], xv[u]);
+#pragma unroll
+    for (int u = 0; u < L; ++u) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) acc[k] += (T)aa[u] * xv[u][k];
+    }
+}
+
+// Rows are processed in straight-line chunks of U entries (U = 8 when a
+// gathered row of x is at most 32 bytes, else 4) and a fixed-length tail.
+template <typename T, int R, bool PROL, typename TA = T>
+__device__ __forceinline__ void spmv_row(const int32_t *__restrict__ scol, const TA *__restrict__ sval, int64_t off,
+                                         int len, const T *xin, const T *xc, int agg_k, T (&acc)[R]) {
+    constexpr int U = (sizeof(T) * R > 32) ? 4 : 8;
+    int e0 = 0;
+    for (; e0 + U <= len; e0 += U)
+        spmv_fixed<T, R, PROL, U>(scol, sval, off + (int64_t)e0 * 64, xin, xc, agg_k, acc);
+    const int64_t o = off + (int64_t)e0 * 64;
+    switch (len - e0) {
+        case 1: spmv_fixed<T, R, PROL, 1>(scol, sval, o, xin, xc, agg_k, acc); break;
+        case 2: spmv_fixed<T, R, PROL, 2>(scol, sval, o, xin, xc, agg_k, acc); break;
+        case 3: spmv_fixed<T, R, PROL, 3>(scol, sval, o, xin, xc, agg_k, acc); break;
+        case 4: if constexpr (U > 4) spmv_fixed<T, R, PROL, 4>(scol, sval, o, xin, xc, agg_k, acc); break;
+        case 5: if constexpr (U > 5) spmv_fixed<T, R, PROL, 5>(scol, sval, o, xin, xc, agg_k, acc); break;
+        case 6: if constexpr (U > 6) spmv_fixed<T, R, PROL, 6>(scol, sval, o, xin, xc, agg_k, acc); break;
+        case 7: if constexpr (U > 7) spmv_fixed<T, R, PROL, 7>(scol, sval, o, xin, xc, agg_k, acc); break;
+        default: break;
+    }
+}
+
 // One cascade sweep over 4 SELL slices (256 rows) per workgroup.
 //   ZERO:   x_in = 0, so x_out = Lambda b (A is not read)
 //   ROWMAP: rows come from a colour list and x is updated in place
 //   PROL:   x_in is first corrected by the coarse-grid solution x_c (the
 //           interpolation step of Alg. 1 fused into the first post-sweep)
-template <typename T, int NB, int R, bool ZERO, bool ROWMAP, bool PROL>
-__global__ __launch_bounds__(WG) void k_sweep(int64_t nrows, int64_t nslices, const int32_t *__restrict__ rows,
-                                              const int64_t *__restrict__ sptr, const int32_t *__restrict__ slen,
-                                              const int32_t *__restrict__ scol, const T *__restrict__ sval,
-                                              const T *__restrict__ lam, const T *__restrict__ b, const T *xin,
-                                              T *xout, const T *__restrict__ xc, int agg_k) {
-    __shared__ T red[NB > 1 ? WG * R : 1];
+//   WGS:    workgroup size; 256 (4 slices) on large levels, 64 (one slice per
+//           workgroup, more workgroups in flight) on small ones
+template <typename T, int NB, int R, bool ZERO, bool ROWMAP, bool PROL, int WGS>
+__global__ __launch_bounds__(WGS) void k_sweep(int64_t nrows, int64_t nslices, const int32_t *__restrict__ rows,
+                                               const int64_t *__restrict__ sptr, const int32_t *__restrict__ slen,
+                                               const int32_t *__restrict__ scol, const T *__restrict__ sval,
+                                               const T *__restrict__ lam, const T *__restrict__ b, const T *xin,
+                                               T *xout, const T *__restrict__ xc, int agg_k) {
+    constexpr int SPW = WGS / 64;
+    __shared__ T red[NB > 1 ? WGS * R : 1];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int64_t slice = tile * 4 + wv;
+    const Tiles tl = my_tiles((nslices + SPW - 1) / SPW);
+    for (int64_t tile = tl.t; tile < tl.end; tile += tl.step) {
+    const int64_t slice = tile * SPW + wv;
     const int64_t q = slice * 64 + lane;
     const bool valid = slice < nslices && q < nrows;
     int64_t row = 0;
@@ -140,16 +208,7 @@ __global__ __launch_bounds__(WG) void k_sweep(int64_t nrows, int64_t nslices, co
 #pragma unroll
         for (int k = 0; k < R; ++k) res[k] = -bb[k];
         if constexpr (!ZERO) {
-            const int len = slen[slice];
-            const int64_t off = sptr[slice] + lane;
-            for (int e = 0; e < len; ++e) {
-                const int c = __builtin_nontemporal_load(scol + off + (int64_t)e * 64);
-                const T a = __builtin_nontemporal_load(sval + off + (int64_t)e * 64);
-                T xv[R];
-                load_x<T, R, PROL>(xin, xc, agg_k, c, xv);
-#pragma unroll
-                for (int k = 0; k < R; ++k) res[k] += a * xv[k];
-            }
+            spmv_row<T, R, PROL>(scol, sval, sptr[slice] + lane, slen[slice], xin, xc, agg_k, res);
         }
     }
     if constexpr (NB == 1) {
@@ -190,6 +249,8 @@ __global__ __launch_bounds__(WG) void k_sweep(int64_t nrows, int64_t nslices, co
             }
             vstore<T, R>(xout + row * R, xo);
         }
+        __syncthreads();   // red is rewritten by the next tile
+    }
     }
 }
 
@@ -200,24 +261,18 @@ __global__ __launch_bounds__(WG) void k_residual(int64_t nrows, int64_t nslices,
                                                  const T *__restrict__ sval, const T *__restrict__ b,
                                                  const T *__restrict__ x, T *__restrict__ r) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t slice = xcd_tile(blockIdx.x, gridDim.x) * 4 + wv;
-    const int64_t row = slice * 64 + lane;
-    if (slice >= nslices || row >= nrows) return;
-    T acc[R];
-    vload<T, R>(b + row * R, acc);
+    const Tiles tl = my_tiles((nslices + 3) / 4);
+    for (int64_t tile = tl.t; tile < tl.end; tile += tl.step) {
+        const int64_t slice = tile * 4 + wv;
+        const int64_t row = slice * 64 + lane;
+        if (slice >= nslices || row >= nrows) continue;
+        T acc[R];
+        vload_nt<T, R>(b + row * R, acc);
 #pragma unroll
-    for (int k = 0; k < R; ++k) acc[k] = -acc[k];
-    const int len = slen[slice];
-    const int64_t off = sptr[slice] + lane;
-    for (int e = 0; e < len; ++e) {
-        const int c = scol[off + (int64_t)e * 64];
-        const T a = sval[off + (int64_t)e * 64];
-        T xv[R];
-        vload<T, R>(x + (int64_t)c * R, xv);
-#pragma unroll
-        for (int k = 0; k < R; ++k) acc[k] += a * xv[k];
+        for (int k = 0; k < R; ++k) acc[k] = -acc[k];
+        spmv_row<T, R, false>(scol, sval, sptr[slice] + lane, slen[slice], x, nullptr, 1, acc);
+        vstore<T, R>(r + row * R, acc);
     }
-    vstore<T, R>(r + row * R, acc);
 }
 
 // Fused residual and restriction for contiguous unit aggregation:
@@ -232,7 +287,8 @@ __global__ __launch_bounds__(WG) void k_residual_restrict(int64_t nrows, int64_t
                                                           int agg_k, int64_t nc, T r_scale, T *__restrict__ bc) {
     __shared__ T red[WG * R];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const Tiles tl = my_tiles((nslices + 3) / 4);
+    for (int64_t tile = tl.t; tile < tl.end; tile += tl.step) {
     const int64_t slice = tile * 4 + wv;
     const int64_t row = slice * 64 + lane;
     T acc[R];
@@ -242,16 +298,7 @@ __global__ __launch_bounds__(WG) void k_residual_restrict(int64_t nrows, int64_t
         vload_nt<T, R>(b + row * R, acc);
 #pragma unroll
         for (int k = 0; k < R; ++k) acc[k] = -acc[k];
-        const int len = slen[slice];
-        const int64_t off = sptr[slice] + lane;
-        for (int e = 0; e < len; ++e) {
-            const int c = __builtin_nontemporal_load(scol + off + (int64_t)e * 64);
-            const T a = __builtin_nontemporal_load(sval + off + (int64_t)e * 64);
-            T xv[R];
-            vload<T, R>(x + (int64_t)c * R, xv);
-#pragma unroll
-            for (int k = 0; k < R; ++k) acc[k] += a * xv[k];
-        }
+        spmv_row<T, R, false>(scol, sval, sptr[slice] + lane, slen[slice], x, nullptr, 1, acc);
     }
 #pragma unroll
     for (int k = 0; k < R; ++k) red[threadIdx.x * R + k] = acc[k];
@@ -271,6 +318,8 @@ __global__ __launch_bounds__(WG) void k_residual_restrict(int64_t nrows, int64_t
             for (int k = 0; k < R; ++k) s[k] *= r_scale;
             vstore<T, R>(bc + I * R, s);
         }
+    }
+    __syncthreads();   // red is rewritten by the next tile
     }
 }
 
@@ -313,24 +362,35 @@ __global__ void k_prolong(int64_t n, const int32_t *__restrict__ pp, const int32
     vstore<T, R>(x + i * R, acc);
 }
 
-// bottom level: x = A^{-1} b with the FP64 inverse
+// bottom level: x = A^{-1} b with the FP64 inverse.  One thread per (row,
+// right-hand side); b is staged in LDS when it fits (n*R <= 4096).
 template <typename T, int R>
-__global__ void k_coarse(int n, const double *__restrict__ ainv, const T *__restrict__ b, T *__restrict__ x) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double acc[R];
-#pragma unroll
-    for (int k = 0; k < R; ++k) acc[k] = 0.0;
-    const double *row = ainv + (int64_t)i * n;
-    for (int j = 0; j < n; ++j) {
-        const double a = row[j];
-#pragma unroll
-        for (int k = 0; k < R; ++k) acc[k] += a * (double)b[(int64_t)j * R + k];
+__global__ __launch_bounds__(WG) void k_coarse(int n, const double *__restrict__ ainv, const T *__restrict__ b,
+                                               T *__restrict__ x) {
+    __shared__ double bs[4096];
+    const bool staged = n * R <= 4096;
+    if (staged) {
+        for (int e = threadIdx.x; e < n * R; e += WG) bs[e] = (double)b[e];
+        __syncthreads();
     }
-    T o[R];
-#pragma unroll
-    for (int k = 0; k < R; ++k) o[k] = (T)acc[k];
-    vstore<T, R>(x + (int64_t)i * R, o);
+    const int t = blockIdx.x * WG + threadIdx.x;
+    if (t >= n * R) return;
+    const int i = t / R, k = t % R;
+    const double *row = ainv + (int64_t)i * n;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int j = 0;
+    if (staged) {
+        for (; j + 4 <= n; j += 4) {
+            a0 += row[j] * bs[j * R + k];
+            a1 += row[j + 1] * bs[(j + 1) * R + k];
+            a2 += row[j + 2] * bs[(j + 2) * R + k];
+            a3 += row[j + 3] * bs[(j + 3) * R + k];
+        }
+        for (; j < n; ++j) a0 += row[j] * bs[j * R + k];
+    } else {
+        for (; j < n; ++j) a0 += row[j] * (double)b[(int64_t)j * R + k];
+    }
+    x[t] = (T)((a0 + a1) + (a2 + a3));
 }
 
 // FP64 refinement residual r = b - A x; writes r in the working precision and
@@ -344,24 +404,25 @@ __global__ __launch_bounds__(WG) void k_ir_residual(int64_t nrows, int64_t nslic
                                                     double *__restrict__ partial) {
     __shared__ double red[WG * R];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t slice = (int64_t)blockIdx.x * 4 + wv;
-    const int64_t row = slice * 64 + lane;
-    double acc[R];
+    const int64_t ntiles = (nslices + 3) / 4;
+    double sq[R];
 #pragma unroll
-    for (int k = 0; k < R; ++k) acc[k] = 0.0;
-    if (slice < nslices && row < nrows) {
-        vload<double, R>(b + row * R, acc);
+    for (int k = 0; k < R; ++k) sq[k] = 0.0;
+    // grid-stride over 256-row tiles; partial sums stay in registers
+    const Tiles tl = my_tiles(ntiles);
+    for (int64_t tile = tl.t; tile < tl.end; tile += tl.step) {
+        const int64_t slice = tile * 4 + wv;
+        const int64_t row = slice * 64 + lane;
+        if (slice >= nslices || row >= nrows) continue;
+        double acc[R];
+        vload_nt<double, R>(b + row * R, acc);
         if (x) {
-            const int len = slen[slice];
-            const int64_t off = sptr[slice] + lane;
-            for (int e = 0; e < len; ++e) {
-                const int c = scol[off + (int64_t)e * 64];
-                const double a = sval[off + (int64_t)e * 64];
-                double xv[R];
-                vload<double, R>(x + (int64_t)c * R, xv);
+            double ax[R];
 #pragma unroll
-                for (int k = 0; k < R; ++k) acc[k] -= a * xv[k];
-            }
+            for (int k = 0; k < R; ++k) ax[k] = 0.0;
+            spmv_row<double, R, false>(scol, sval, sptr[slice] + lane, slen[slice], x, nullptr, 1, ax);
+#pragma unroll
+            for (int k = 0; k < R; ++k) acc[k] -= ax[k];
         }
         if (rt) {
             T o[R];
@@ -369,9 +430,11 @@ __global__ __launch_bounds__(WG) void k_ir_residual(int64_t nrows, int64_t nslic
             for (int k = 0; k < R; ++k) o[k] = (T)acc[k];
             vstore<T, R>(rt + row * R, o);
         }
+#pragma unroll
+        for (int k = 0; k < R; ++k) sq[k] += acc[k] * acc[k];
     }
 #pragma unroll
-    for (int k = 0; k < R; ++k) red[threadIdx.x * R + k] = acc[k] * acc[k];
+    for (int k = 0; k < R; ++k) red[threadIdx.x * R + k] = sq[k];
     __syncthreads();
     for (int s = WG / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) {
@@ -421,6 +484,13 @@ __global__ void k_zero(int64_t n, T *__restrict__ a) {
 
 inline unsigned grid_for(int64_t n, int wg = WG) { return (unsigned)ceil_div(n, wg); }
 
+// Workgroups for a tiled (256-row) kernel: one per tile up to the resident
+// limit c.sweep_grid (a multiple of 8), beyond which workgroups loop over tiles.
+inline unsigned tile_grid(const Ctx &c, int64_t nslices) {
+    const int64_t ntiles = ceil_div(nslices, 4);
+    return (unsigned)(ntiles <= c.sweep_grid ? ntiles : c.sweep_grid);
+}
+
 template <class F>
 void dispatch_nb(int nb, F &&f) {
     switch (nb) {
@@ -468,10 +538,13 @@ const float *pval<float>(const Level &L, bool tr) { return tr ? L.pt_val32.get()
 template <typename T, int R>
 void launch_sweep(Ctx &c, const Level &L, const Sell &S, bool rowmap, bool zero, const T *lam, const T *b,
                   const T *xin, T *xout, const T *xc = nullptr, int agg_k = 0) {
-    const unsigned G = grid_for(S.nslices, 4);
+    // levels below SMALL_SLICES slices run one 64-row slice per workgroup
+    const bool small = S.nslices < SMALL_SLICES;
+    const unsigned G = small ? (unsigned)std::min<int64_t>(S.nslices, c.sweep_grid) : tile_grid(c, S.nslices);
     if (G == 0) return;
     const bool prol = xc != nullptr;
-    const int cls = zero ? CS_TRACE_SWEEP_ZERO : CS_TRACE_SWEEP;
+    const int cls = zero ? CS_TRACE_SWEEP_ZERO
+                         : (xc ? CS_TRACE_SWEEP_PROLONG : (small ? CS_TRACE_SWEEP_SMALL : CS_TRACE_SWEEP));
     const double es = sizeof(T);
     const double bytes = (zero ? 0.0 : S.nnz * (es + 4.0)) + (double)S.nrows * L.nb * es +
                          (double)S.nrows * R * es * 2.0 + (zero ? 0.0 : (rowmap ? L.n : S.nrows) * R * es) +
@@ -479,10 +552,17 @@ void launch_sweep(Ctx &c, const Level &L, const Sell &S, bool rowmap, bool zero,
     const int slot = trace_begin(c, cls, bytes);
     dispatch_nb(L.nb, [&](auto nbc) {
         constexpr int NB = decltype(nbc)::value;
-#define CS_SWEEP(Z, M, P, ROWS)                                                                                      \
-    hipLaunchKernelGGL((k_sweep<T, NB, R, Z, M, P>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices, ROWS,     \
-                       S.slice_ptr.get(), S.slice_len.get(), S.col.get(), sell_val<T>(S), lam, b, xin, xout, xc, \
-                       agg_k)
+#define CS_SWEEP(Z, M, P, ROWS)                                                                                     \
+    do {                                                                                                            \
+        if (small)                                                                                                  \
+            hipLaunchKernelGGL((k_sweep<T, NB, R, Z, M, P, 64>), dim3(G), dim3(64), 0, c.stream, S.nrows,          \
+                               S.nslices, ROWS, S.slice_ptr.get(), S.slice_len.get(), S.col.get(), sell_val<T>(S), \
+                               lam, b, xin, xout, xc, agg_k);                                                       \
+        else                                                                                                        \
+            hipLaunchKernelGGL((k_sweep<T, NB, R, Z, M, P, WG>), dim3(G), dim3(WG), 0, c.stream, S.nrows,          \
+                               S.nslices, ROWS, S.slice_ptr.get(), S.slice_len.get(), S.col.get(), sell_val<T>(S), \
+                               lam, b, xin, xout, xc, agg_k);                                                       \
+    } while (0)
         if (rowmap) {
             if (zero) CS_SWEEP(true, true, false, S.rows.get());
             else CS_SWEEP(false, true, false, S.rows.get());
@@ -546,8 +626,8 @@ void vcycle_level(Ctx &c, int l) {
     const double es = sizeof(T);
     if (l + 1 == (int)c.lv.size()) {
         const int slot = trace_begin(c, CS_TRACE_BOTTOM, (double)L.n * L.n * 8.0 + 2.0 * L.n * R * es);
-        hipLaunchKernelGGL((k_coarse<T, R>), dim3(grid_for(L.n, 64)), dim3(64), 0, c.stream, (int)L.n, L.ainv.get(), bb,
-                           xb);
+        hipLaunchKernelGGL((k_coarse<T, R>), dim3(grid_for(L.n * R)), dim3(WG), 0, c.stream, (int)L.n, L.ainv.get(),
+                           bb, xb);
         CS_LAUNCH_CHECK();
         trace_end(c, slot);
         return;
@@ -565,12 +645,12 @@ void vcycle_level(Ctx &c, int l) {
                            L.sell.nnz * (es + 4.0) + (fused ? 2.0 : 3.0) * L.n * R * es +
                                (fused ? 0.0 : L.p_nnz * (es + 4.0) + L.n * R * es) + L.nc * R * es);
     if (fused) {
-        hipLaunchKernelGGL((k_residual_restrict<T, R>), dim3(grid_for(L.sell.nslices, 4)), dim3(WG), 0, c.stream,
+        hipLaunchKernelGGL((k_residual_restrict<T, R>), dim3(tile_grid(c, L.sell.nslices)), dim3(WG), 0, c.stream,
                            L.sell.nrows, L.sell.nslices, L.sell.slice_ptr.get(), L.sell.slice_len.get(),
                            L.sell.col.get(), sell_val<T>(L.sell), bb, x, L.agg_k, L.nc, (T)L.r_scale,
                            reinterpret_cast<T *>(C.bb.get()));
     } else {
-        hipLaunchKernelGGL((k_residual<T, R>), dim3(grid_for(L.sell.nslices, 4)), dim3(WG), 0, c.stream,
+        hipLaunchKernelGGL((k_residual<T, R>), dim3(tile_grid(c, L.sell.nslices)), dim3(WG), 0, c.stream,
                            L.sell.nrows, L.sell.nslices, L.sell.slice_ptr.get(), L.sell.slice_len.get(),
                            L.sell.col.get(), sell_val<T>(L.sell), bb, x, rr);
         hipLaunchKernelGGL((k_restrict<T, R>), dim3(grid_for(L.nc)), dim3(WG), 0, c.stream, L.nc, L.pt_ptr.get(),
@@ -616,11 +696,12 @@ void ensure_workspace(Ctx &c, int nrhs) {
         L.bb.alloc(bytes);
         L.rr.alloc(bytes);
     }
-    const int64_t G = ceil_div(c.lv[0].sell.nslices, 4);
+    const int64_t G = std::min<int64_t>(ceil_div(c.lv[0].sell.nslices, 4), IR_GRID);
     c.ir_partial.alloc(std::max<int64_t>(G, 1) * nrhs);
     c.ir_norm.alloc(2 * nrhs);
     if (!c.h_norm) CS_HIP(hipHostMalloc(reinterpret_cast<void **>(&c.h_norm), 16 * sizeof(double)));
     c.ws_nrhs = nrhs;
+    c.gen++;
     c.ws_prec = prec;
 }
 
@@ -665,29 +746,40 @@ void solve_ir(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
     Level &L0 = c.lv[0];
     const Sell &S = L0.sell;
     const int64_t n = L0.n * nrhs;
-    const int64_t G = ceil_div(S.nslices, 4);
+    const int64_t G = std::min<int64_t>(ceil_div(S.nslices, 4), IR_GRID);
     const double *hn = c.h_norm;
     *st = CS_OK;
+    // With graphs the solve runs on the context's own (capturable) stream,
+    // ordered after the caller's stream and followed by it.
+    // (event tracing runs eagerly: timing nodes are not available in graphs here)
+    const bool graphs = c.use_graphs && !c.tr.on;
+    const hipStream_t user = c.stream;
+    if (graphs) {
+        if (!c.work) CS_HIP(hipStreamCreateWithFlags(&c.work, hipStreamNonBlocking));
+        CS_HIP(hipEventRecord(c.ev_in, user));
+        CS_HIP(hipStreamWaitEvent(c.work, c.ev_in, 0));
+        c.stream = c.work;
+    }
+    struct Restore {
+        Ctx &c;
+        hipStream_t user;
+        bool on;
+        ~Restore() {
+            if (!on) return;
+            (void)hipEventRecord(c.ev_out, c.stream);
+            (void)hipStreamWaitEvent(user, c.ev_out, 0);
+            c.stream = user;
+        }
+    } restore{c, user, graphs};
     CS_HIP(hipEventRecord(c.ev0, c.stream));
     dispatch_prec(c.precision, [&](auto tp) {
         using T = std::remove_pointer_t<decltype(tp)>;
         dispatch_r(nrhs, [&](auto rc) {
             constexpr int R = decltype(rc)::value;
-            // ||b||^2
-            hipLaunchKernelGGL((k_ir_residual<T, R>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
-                               S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), b, nullptr,
-                               (T *)nullptr, c.ir_partial.get());
-            hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(1024), 0, c.stream, G, R, c.ir_partial.get(),
-                               c.ir_norm.get() + R);
-            hipLaunchKernelGGL(k_zero<double>, dim3(grid_for(n)), dim3(WG), 0, c.stream, n, x);
-            CS_LAUNCH_CHECK();
-            std::vector<double> hist;
-            double bn2[8];
-            int it = 0;
             const double ir_bytes = S.nnz * 12.0 + (double)L0.n * R * (16.0 + sizeof(T));
             const double up_bytes = (double)L0.n * R * (16.0 + sizeof(T));
-            for (;; ++it) {
-                int slot = trace_begin(c, CS_TRACE_REFINE, ir_bytes);
+            auto residual = [&]() {
+                const int slot = trace_begin(c, CS_TRACE_REFINE, ir_bytes);
                 hipLaunchKernelGGL((k_ir_residual<T, R>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
                                    S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), b, x,
                                    reinterpret_cast<T *>(L0.bb.get()), c.ir_partial.get());
@@ -695,9 +787,34 @@ void solve_ir(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
                                    c.ir_norm.get());
                 CS_LAUNCH_CHECK();
                 trace_end(c, slot);
+            };
+            // one refinement iteration after the check: d = V r, x += d, r = b - A x
+            auto iteration = [&]() {
+                vcycle_level<T, R>(c, 0);
+                const int slot = trace_begin(c, CS_TRACE_REFINE, up_bytes);
+                hipLaunchKernelGGL((k_add_to64<T>), dim3(grid_for(n)), dim3(WG), 0, c.stream, n,
+                                   reinterpret_cast<const T *>(L0.xb.get()), x);
+                CS_LAUNCH_CHECK();
+                trace_end(c, slot);
+                residual();
+            };
+            // ||b||^2, x = 0, first residual
+            hipLaunchKernelGGL((k_ir_residual<T, R>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
+                               S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), b, nullptr,
+                               (T *)nullptr, c.ir_partial.get());
+            hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(1024), 0, c.stream, G, R, c.ir_partial.get(),
+                               c.ir_norm.get() + R);
+            hipLaunchKernelGGL(k_zero<double>, dim3(grid_for(n)), dim3(WG), 0, c.stream, n, x);
+            CS_LAUNCH_CHECK();
+            residual();
+            std::vector<double> hist;
+            double bn2[8];
+            int it = 0;
+            for (;; ++it) {
                 CS_HIP(hipMemcpyAsync(c.h_norm, c.ir_norm.get(), 2 * R * sizeof(double), hipMemcpyDeviceToHost,
                                       c.stream));
                 CS_HIP(hipStreamSynchronize(c.stream));
+                if (graphs && it > 0) trace_graph_accumulate(c);
                 if (it == 0)
                     for (int k = 0; k < R; ++k) bn2[k] = hn[R + k] > 0 ? hn[R + k] : 1.0;
                 double rel = 0.0;
@@ -717,12 +834,38 @@ void solve_ir(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
                     *st = CS_ENOCONV;
                     break;
                 }
-                vcycle_level<T, R>(c, 0);
-                slot = trace_begin(c, CS_TRACE_REFINE, up_bytes);
-                hipLaunchKernelGGL((k_add_to64<T>), dim3(grid_for(n)), dim3(WG), 0, c.stream, n,
-                                   reinterpret_cast<const T *>(L0.xb.get()), x);
-                CS_LAUNCH_CHECK();
-                trace_end(c, slot);
+                if (graphs) {
+                    const Ctx::GraphKey key{b, x, R, c.precision, c.tr.on ? c.tr.mask : 0, c.gen};
+                    if (!c.gexec || !(key == c.gkey)) {
+                        trace_flush(c);
+                        graph_release(c);
+                        if (c.tr.on) {
+                            size_t bound = 8;
+                            for (const Level &L : c.lv)
+                                bound += (size_t)(c.opt.n_pre + c.opt.n_post) * std::max(L.depth, 1) *
+                                             std::max(L.chi, 1) + 4;
+                            trace_graph_pool(c, bound);
+                        }
+                        c.tr.capturing = true;
+                        CS_HIP(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
+                        try {
+                            iteration();
+                        } catch (...) {
+                            hipGraph_t junk = nullptr;
+                            (void)hipStreamEndCapture(c.stream, &junk);
+                            if (junk) (void)hipGraphDestroy(junk);
+                            c.tr.capturing = false;
+                            throw;
+                        }
+                        c.tr.capturing = false;
+                        CS_HIP(hipStreamEndCapture(c.stream, &c.graph));
+                        CS_HIP(hipGraphInstantiate(&c.gexec, c.graph, nullptr, nullptr, 0));
+                        c.gkey = key;
+                    }
+                    CS_HIP(hipGraphLaunch(c.gexec, c.stream));
+                } else {
+                    iteration();
+                }
             }
             trace_flush(c);
             CS_HIP(hipEventRecord(c.ev1, c.stream));
