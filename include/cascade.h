@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define CS_ABI_VERSION 1
+#define CS_ABI_VERSION 2
 
 typedef struct cs_ctx_s *cs_ctx;
 typedef struct cs_batch_s *cs_batch;
@@ -75,6 +75,16 @@ typedef struct {
     const double *p_val;
     double r_scale;             /* restriction R = r_scale * P^T (1 for Galerkin FE/DG, 2^-d for the FD schemes) */
     const int32_t *colour;      /* [n/block_size] block colours 0..chi-1, or NULL (library colours greedily) */
+    /* Direct segments: the trailing rows [direct_seg_ptr[0], n) of the level,
+     * cut into n_direct_seg independent segments [direct_seg_ptr[k],
+     * direct_seg_ptr[k+1]), are solved directly (FP64 dense inverse per
+     * segment, at most 8192 rows each) instead of being smoothed and coarsened
+     * - the bottom of Alg. 1 for systems that end on this level while others
+     * continue.  Rows of a segment couple only with their segment, the other
+     * rows never couple to them, and P has no entries in them.  n_direct_seg =
+     * 0: no direct rows (the last level is then one segment of all rows). */
+    int32_t n_direct_seg;
+    const int64_t *direct_seg_ptr;   /* [n_direct_seg+1], increasing, ending at n */
 } cs_level;
 
 typedef struct {
@@ -167,7 +177,7 @@ typedef enum {
     CS_TRACE_SWEEP_ZERO = 1,    /* first sweep from a zero guess: x = Lambda b */
     CS_TRACE_RESIDUAL = 2,      /* residual + restriction, all levels */
     CS_TRACE_PROLONG = 3,       /* interpolation + correction (separate kernel) */
-    CS_TRACE_BOTTOM = 4,        /* bottom-level solve */
+    CS_TRACE_BOTTOM = 4,        /* direct solves: the bottom level and direct segments */
     CS_TRACE_REFINE = 5,        /* FP64 refinement residual and update */
     CS_TRACE_SWEEP_PROLONG = 6, /* first post-sweep with the interpolation fused in */
     CS_TRACE_SWEEP_SMALL = 7,   /* cascade sweeps that read A on small levels */
@@ -175,6 +185,15 @@ typedef enum {
 } cs_trace_class;
 cs_status cs_trace(cs_ctx ctx, int32_t mask, int32_t period);
 cs_status cs_trace_read(cs_ctx ctx, int32_t cls, double *total_ms, int64_t *launches, double *bytes);
+
+/* Independent systems sharing one hierarchy (a batch): row_ptr[0..nsys] cuts
+ * the finest level into the systems' row ranges (host array, increasing, 0 to
+ * n).  cs_solve then measures every (system, right-hand side) residual
+ * separately and stops when all of them reach rtol; cs_get_system_stats
+ * reports, per system, the V-cycles after which it first converged (or maxit)
+ * and its final max relative residual.  nsys = 1 restores one system. */
+cs_status cs_set_systems(cs_ctx ctx, int32_t nsys, const int64_t *row_ptr);
+cs_status cs_get_system_stats(cs_ctx ctx, int32_t *iterations, double *rel_res);
 
 /* Persist / restore a setup (smoothers, colours, bottom factor) for the same hierarchy. */
 cs_status cs_save_setup(cs_ctx ctx, const char *path);

@@ -39,7 +39,8 @@ class cs_level(ctypes.Structure):
                 ("a_row_ptr", _p(ctypes.c_int64)), ("a_col", _p(ctypes.c_int32)), ("a_val", _p(ctypes.c_double)),
                 ("n_coarse", ctypes.c_int64),
                 ("p_row_ptr", _p(ctypes.c_int64)), ("p_col", _p(ctypes.c_int32)), ("p_val", _p(ctypes.c_double)),
-                ("r_scale", ctypes.c_double), ("colour", _p(ctypes.c_int32))]
+                ("r_scale", ctypes.c_double), ("colour", _p(ctypes.c_int32)),
+                ("n_direct_seg", ctypes.c_int32), ("direct_seg_ptr", _p(ctypes.c_int64))]
 
 
 class cs_options(ctypes.Structure):
@@ -75,6 +76,8 @@ SIGNATURES = {
     "cs_solve": (_I32, [_VP, _VP, _VP, _I32, _D, _I32, _p(cs_info), _p(_D)]),
     "cs_trace": (_I32, [_VP, _I32, _I32]),
     "cs_trace_read": (_I32, [_VP, _I32, _p(_D), _p(_I64), _p(_D)]),
+    "cs_set_systems": (_I32, [_VP, _I32, _p(_I64)]),
+    "cs_get_system_stats": (_I32, [_VP, _p(_I32), _p(_D)]),
     "cs_save_setup": (_I32, [_VP, ctypes.c_char_p]),
     "cs_load_setup": (_I32, [_VP, ctypes.c_char_p]),
 }
@@ -116,7 +119,8 @@ class Solver:
 
     levels: sequence of objects with attributes A (scipy CSR, float64),
     block_size, P (CSR interpolation from the next coarser level or None),
-    r_scale and colour (int array per block or None); level 0 is the finest.
+    r_scale, colour (int array per block or None) and optionally direct_seg
+    (row offsets of trailing segments solved directly); level 0 is the finest.
     """
 
     def __init__(self, levels: Sequence, device: int = 0):
@@ -180,8 +184,15 @@ class Solver:
                 c = _arr(col, np.int32)
                 keep.append(c)
                 s.colour = _ptr(c, ctypes.c_int32)
+            seg = getattr(lv, "direct_seg", None)
+            if seg is not None and len(seg) > 1:
+                sp = _arr(seg, np.int64)
+                keep.append(sp)
+                s.n_direct_seg = len(sp) - 1
+                s.direct_seg_ptr = _ptr(sp, ctypes.c_int64)
         self._check(self._lib.cs_set_hierarchy(self._h, len(levels), arr))
         self.n_levels = len(levels)
+        self.n_systems = 1
         self.sizes = [(int(lv.A.shape[0]), int(lv.block_size)) for lv in levels]
 
     def setup(self, depth: int = 3, mode: str = "additive", order: str = "RF", n_pre: int = 1,
@@ -261,6 +272,26 @@ class Solver:
         return x, dict(iterations=k, rel_res=info.rel_res, rho=info.rho, setup_ms=info.setup_ms,
                        solve_ms=info.solve_ms, singular_blocks=info.singular_blocks,
                        history=hist[:k + 1].copy(), status=st)
+
+    def set_systems(self, row_ptr=None):
+        """Declare the finest level a batch of independent systems with row
+        ranges [row_ptr[s], row_ptr[s+1]); None restores one system."""
+        if row_ptr is None:
+            self._check(self._lib.cs_set_systems(self._h, 1, None))
+            self.n_systems = 1
+            return
+        rp = _arr(row_ptr, np.int64)
+        self._check(self._lib.cs_set_systems(self._h, len(rp) - 1, _ptr(rp, ctypes.c_int64)))
+        self.n_systems = len(rp) - 1
+
+    def system_stats(self):
+        """Per system of the last solve: V-cycles to convergence and final
+        max relative residual."""
+        ns = getattr(self, "n_systems", 1)
+        it = np.empty(ns, dtype=np.int32)
+        rel = np.empty(ns, dtype=np.float64)
+        self._check(self._lib.cs_get_system_stats(self._h, _ptr(it, ctypes.c_int32), _ptr(rel, ctypes.c_double)))
+        return it, rel
 
     TRACE_CLASSES = ("sweep", "sweep_zero", "residual", "prolong", "bottom", "refine", "sweep_prolong",
                      "sweep_small")

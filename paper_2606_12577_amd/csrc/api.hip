@@ -88,7 +88,33 @@ void set_level(Ctx &c, Level &L, const cs_level &in, int li, int nlev, int64_t n
         L.h_colour.assign(in.colour, in.colour + L.B);
         for (int32_t v : L.h_colour) need(v >= 0 && v < 4096, "colours must be in [0, 4096)");
     }
+    // direct segments (trailing rows solved directly); the last level is all direct
+    const std::string lvs = "level " + std::to_string(li) + ": ";
+    L.dseg.clear();
+    if (in.n_direct_seg > 0) {
+        need(in.direct_seg_ptr != nullptr, lvs + "direct_seg_ptr missing");
+        L.dseg.assign(in.direct_seg_ptr, in.direct_seg_ptr + in.n_direct_seg + 1);
+        need(L.dseg.back() == in.n, lvs + "direct segments must end at n");
+        for (int k = 0; k < in.n_direct_seg; ++k)
+            need(L.dseg[k + 1] > L.dseg[k] && L.dseg[k + 1] - L.dseg[k] <= 8192,
+                 lvs + "direct segments must be non-empty and at most 8192 rows");
+        need(L.dseg[0] >= 0 && L.dseg[0] % in.block_size == 0, lvs + "direct segments must start on a block");
+        if (li + 1 == nlev) need(L.dseg[0] == 0, lvs + "the last level must be solved directly in full");
+    } else if (li + 1 == nlev) {
+        need(in.n <= 8192, "bottom level larger than 8192 unknowns");
+        L.dseg = {0, in.n};
+    }
+    L.n_active = L.dseg.empty() ? in.n : L.dseg[0];
+    for (size_t k = 0; k + 1 < L.dseg.size(); ++k)
+        for (int64_t r = L.dseg[k]; r < L.dseg[k + 1]; ++r)
+            for (int64_t e = L.h_ptr[r]; e < L.h_ptr[r + 1]; ++e)
+                need(L.h_col[e] >= L.dseg[k] && L.h_col[e] < L.dseg[k + 1],
+                     lvs + "a direct segment couples to rows outside it");
+    for (int64_t r = 0; r < L.n_active; ++r)
+        for (int64_t e = L.h_ptr[r]; e < L.h_ptr[r + 1]; ++e)
+            need(L.h_col[e] < L.n_active, lvs + "an active row couples to a direct segment");
     if (li + 1 < nlev) {
+        need(L.n_active > 0, lvs + "no active rows on a level that is not the last");
         need(in.n_coarse == n_next, "level " + std::to_string(li) + ": n_coarse differs from the next level's n");
         need(in.p_row_ptr && in.p_col && in.p_val, "level " + std::to_string(li) + ": P is missing");
         std::vector<int64_t> pp(in.p_row_ptr, in.p_row_ptr + in.n + 1);
@@ -97,15 +123,17 @@ void set_level(Ctx &c, Level &L, const cs_level &in, int li, int nlev, int64_t n
         std::vector<int32_t> pc(in.p_col, in.p_col + pn);
         std::vector<double> pv(in.p_val, in.p_val + pn);
         for (int32_t v : pc) need(v >= 0 && v < n_next, "P column index out of range");
+        for (int64_t r = L.n_active; r < in.n; ++r) need(pp[r + 1] == pp[r], lvs + "P has entries in a direct row");
         L.nc = n_next;
         L.p_nnz = pn;
         L.r_scale = in.r_scale;
-        // contiguous unit aggregation: row r of P is the single entry (r / k, 1)
+        // contiguous unit aggregation over the active rows: row r of P is the
+        // single entry (r / k, 1)
         L.agg_k = 0;
-        if (n_next > 0 && in.n % n_next == 0) {
-            const int64_t k = in.n / n_next;
-            bool ok = k <= 64 && 64 % k == 0 && pn == in.n;
-            for (int64_t r = 0; ok && r < in.n; ++r)
+        if (n_next > 0 && L.n_active % n_next == 0) {
+            const int64_t k = L.n_active / n_next;
+            bool ok = k <= 64 && 64 % k == 0 && pn == L.n_active;
+            for (int64_t r = 0; ok && r < L.n_active; ++r)
                 ok = pp[r + 1] - pp[r] == 1 && pc[pp[r]] == r / k && pv[pp[r]] == 1.0;
             if (ok) L.agg_k = (int)k;
         }
@@ -129,7 +157,7 @@ void set_level(Ctx &c, Level &L, const cs_level &in, int li, int nlev, int64_t n
 }
 
 const uint64_t SAVE_MAGIC = 0x3150555445535343ull;  // "CSSETUP1"
-const int32_t SAVE_VERSION = 1;
+const int32_t SAVE_VERSION = 2;
 
 }  // namespace
 
@@ -224,7 +252,7 @@ cs_status cs_set_hierarchy(cs_ctx ctx, int32_t n_levels, const cs_level *levels)
         c.lv.resize(n_levels);
         for (int l = 0; l < n_levels; ++l)
             set_level(c, c.lv[l], levels[l], l, n_levels, l + 1 < n_levels ? levels[l + 1].n : 0);
-        need(c.lv.back().n <= 8192, "bottom level larger than 8192 unknowns");
+        c.sys_ptr.clear();
         c.have_hierarchy = true;
     });
 }
@@ -372,14 +400,16 @@ cs_status cs_save_setup(cs_ctx ctx, const char *path) {
             if (l + 1 < c.lv.size()) {
                 buf.resize((size_t)L.depth * L.B * L.nb * L.nb);
                 L.lam64.download(buf.data(), buf.size(), c.stream);
-            } else {
-                buf.resize((size_t)L.n * L.n);
-                L.ainv.download(buf.data(), buf.size(), c.stream);
             }
+            std::vector<double> dbuf(L.dinv.n);
+            L.dinv.download(dbuf.data(), dbuf.size(), c.stream);
             CS_HIP(hipStreamSynchronize(c.stream));
             int64_t cnt = (int64_t)buf.size();
             put(&cnt, 8);
             put(buf.data(), buf.size() * 8);
+            cnt = (int64_t)dbuf.size();
+            put(&cnt, 8);
+            put(dbuf.data(), dbuf.size() * 8);
         }
         need((bool)f, std::string("write failed: ") + path, CS_EIO);
     });
@@ -420,7 +450,7 @@ cs_status cs_load_setup(cs_ctx ctx, const char *path) {
             std::vector<double> buf(cnt);
             get(buf.data(), cnt * 8);
             if (l + 1 < nl) {
-                need(cnt % (L.B * L.nb * L.nb) == 0, "bad smoother size in setup file", CS_EIO);
+                need(cnt > 0 && cnt % (L.B * L.nb * L.nb) == 0, "bad smoother size in setup file", CS_EIO);
                 L.depth = (int)(cnt / (L.B * L.nb * L.nb));
                 L.lam64.upload(buf.data(), cnt, c.stream);
                 CS_HIP(hipStreamSynchronize(c.stream));
@@ -428,11 +458,13 @@ cs_status cs_load_setup(cs_ctx ctx, const char *path) {
                     need((int64_t)L.h_colour.size() == L.B, "missing colours in setup file", CS_EIO);
                     cs::build_colour_layout(c, L);
                 }
-            } else {
-                need(cnt == L.n * L.n, "bad bottom factor in setup file", CS_EIO);
-                L.ainv.upload(buf.data(), cnt, c.stream);
-                CS_HIP(hipStreamSynchronize(c.stream));
             }
+            get(&cnt, 8);
+            need(cnt == (int64_t)L.dinv.n, "bad direct-segment inverses in setup file", CS_EIO);
+            buf.resize(cnt);
+            get(buf.data(), cnt * 8);
+            L.dinv.upload(buf.data(), cnt, c.stream);
+            CS_HIP(hipStreamSynchronize(c.stream));
             L.patterns.clear();
         }
         CS_HIP(hipStreamSynchronize(c.stream));
@@ -574,6 +606,52 @@ cs_status cs_trace_read(cs_ctx ctx, int32_t cls, double *total_ms, int64_t *laun
         if (total_ms) *total_ms = c.tr.ms[cls];
         if (launches) *launches = c.tr.count[cls];
         if (bytes) *bytes = c.tr.bytes[cls];
+    });
+}
+
+}  // extern "C"
+
+extern "C" {
+
+cs_status cs_set_systems(cs_ctx ctx, int32_t nsys, const int64_t *row_ptr) {
+    return guarded(ctx, [&](Ctx &c) {
+        need(c.have_hierarchy, "cs_set_systems before cs_set_hierarchy", CS_ESTATE);
+        need(nsys >= 1, "need at least one system");
+        std::vector<int64_t> p;
+        if (nsys == 1 && row_ptr == nullptr) {
+            p = {0, c.lv[0].n};
+        } else {
+            need(row_ptr != nullptr, "row_ptr missing");
+            p.assign(row_ptr, row_ptr + nsys + 1);
+        }
+        need(p.front() == 0 && p.back() == c.lv[0].n, "systems must cover the finest level");
+        for (int s = 0; s < nsys; ++s) need(p[s + 1] > p[s], "systems must be non-empty");
+        c.sys_ptr = nsys > 1 ? p : std::vector<int64_t>{};
+        c.n_het = 0;
+        if (nsys > 1) {
+            c.sys_ptr_d.upload(c.sys_ptr.data(), c.sys_ptr.size(), c.stream);
+            // 64-row slices of the finest level that hold rows of several systems
+            const int64_t n = c.lv[0].n, ns = cs::ceil_div(n, 64);
+            std::vector<int32_t> het(ns, -1);
+            int q = 0;
+            for (int64_t k = 0; k < ns; ++k) {
+                const int64_t first = 64 * k, last = std::min(first + 64, n) - 1;
+                while (p[q + 1] <= first) ++q;
+                if (last >= p[q + 1]) het[k] = (int32_t)c.n_het++;
+            }
+            c.sys_het.upload(het.data(), het.size(), c.stream);
+        }
+        CS_HIP(hipStreamSynchronize(c.stream));
+        c.ws_nrhs = 0;   // workspace depends on the system count
+    });
+}
+
+cs_status cs_get_system_stats(cs_ctx ctx, int32_t *iterations, double *rel_res) {
+    return guarded(ctx, [&](Ctx &c) {
+        need(!c.sys_iters.empty(), "no solve with systems has run", CS_ESTATE);
+        need(iterations && rel_res, "null output");
+        std::copy(c.sys_iters.begin(), c.sys_iters.end(), iterations);
+        std::copy(c.sys_rel.begin(), c.sys_rel.end(), rel_res);
     });
 }
 

@@ -133,8 +133,15 @@ struct Level {
     DBuf<float> lam32, lam32T;
     std::vector<BPattern> patterns;   // E after every fit step
     int singular = 0;
-    // bottom level: dense inverse (row-major n x n)
-    DBuf<double> ainv;
+    // direct segments: rows [n_active, n) solved with dense FP64 inverses (the
+    // whole last level; trailing systems that end on this level in a batch)
+    int64_t n_active = 0;
+    int64_t act_slices = 0;           // SELL slices covering the active rows
+    int64_t act_nnz = 0;              // entries of A in the active rows
+    std::vector<int64_t> dseg;        // absolute row offsets, size ndseg + 1
+    DBuf<int64_t> dseg_d, dinv_off;   // device copies: offsets and inverse offsets
+    DBuf<double> dinv;                // concatenated row-major inverses
+    int64_t dseg_max = 0;
     // V-cycle workspace (working precision), [n][nrhs]
     DBuf<char> xb, xt, bb, rr;
 };
@@ -170,9 +177,21 @@ struct Ctx {
     int ws_nrhs = 0, ws_prec = -1;
     double setup_ms = 0;
     int singular = 0;
+    // independent systems on the finest level (a batch)
+    std::vector<int64_t> sys_ptr;       // size nsys + 1
+    DBuf<int64_t> sys_ptr_d;
+    // batch residual norms: per-slice sums over slices inside one system, and
+    // per-row squares of the n_het slices that straddle a system boundary
+    DBuf<int32_t> sys_het;              // [nslices]: -1, or index of a straddling slice
+    int64_t n_het = 0;
+    DBuf<double> sys_spart;             // [nslices][R]
+    DBuf<double> rn2;                   // [n_het*64][R]
+    std::vector<int32_t> sys_iters;
+    std::vector<double> sys_rel;
     // solve workspace
     DBuf<double> ir_partial, ir_norm;
-    double *h_norm = nullptr;           // pinned host copy of ir_norm (16 doubles)
+    double *h_norm = nullptr;           // pinned host copy of ir_norm
+    size_t h_norm_cap = 0;
     bool fuse_transfers = true;         // use the fused aggregation kernels when agg_k > 0
     int64_t sweep_grid = int64_t(1) << 40;   // cap on workgroups of the tiled kernels (multiple of 8)
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -208,7 +227,7 @@ void trace_release(Ctx &c);
 void build_level_device(Ctx &c, Level &L);
 void run_setup(Ctx &c, const cs_options &o);
 void build_working_copies(Ctx &c);
-void factor_bottom(Ctx &c, Level &L);
+void factor_direct(Ctx &c, Level &L);   // dense inverses of the direct segments
 void build_colour_layout(Ctx &c, Level &L);
 
 // solve.hip

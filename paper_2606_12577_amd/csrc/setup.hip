@@ -617,6 +617,36 @@ __global__ void k_gauss_jordan(const double *__restrict__ in, double *__restrict
     out[e] = v;
 }
 
+// One Gauss-Jordan pivot step k applied to every segment's dense matrix at
+// once; segments already past their size are copied unchanged.
+__global__ void k_gauss_jordan_seg(const double *__restrict__ in, double *__restrict__ out, int64_t tot, int nseg,
+                                   const int64_t *__restrict__ off, int k) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= tot) return;
+    int lo = 0, hi = nseg;   // segment q with off[q] <= e < off[q+1]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= e) lo = mid;
+        else hi = mid;
+    }
+    const int64_t base = off[lo];
+    const int64_t m = (int64_t)llround(sqrt((double)(off[lo + 1] - base)));
+    if (k >= m) {
+        out[e] = in[e];
+        return;
+    }
+    const int64_t loc = e - base, i = loc / m, j = loc % m;
+    const double *a = in + base;
+    const double p = a[k * m + k];
+    double v;
+    if (i == k) v = (j == k) ? 1.0 / p : a[k * m + j] / p;
+    else {
+        const double f = a[i * m + k];
+        v = (j == k) ? -f / p : a[loc] - f * a[k * m + j] / p;
+    }
+    out[e] = v;
+}
+
 __global__ void k_transpose_blocks64(int64_t nblk, int nb, const double *__restrict__ a, double *__restrict__ at) {
     int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     int nb2 = nb * nb;
@@ -728,6 +758,25 @@ void build_level_device(Ctx &c, Level &L) {
     L.a_col.upload(L.h_col.data(), L.h_col.size(), s);
     L.a_val.upload(L.h_val.data(), L.h_val.size(), s);
     build_sell(L.sell, L.h_ptr, L.h_col, L.h_val, nullptr, s);
+    L.act_slices = ceil_div(L.n_active, 64);
+    L.act_nnz = L.h_ptr[L.n_active];
+    // direct segments: offsets of their dense inverses in dinv
+    const int nseg = (int)L.dseg.size() - 1;
+    if (nseg > 0) {
+        std::vector<int64_t> off(nseg + 1, 0);
+        L.dseg_max = 0;
+        for (int k = 0; k < nseg; ++k) {
+            const int64_t m = L.dseg[k + 1] - L.dseg[k];
+            off[k + 1] = off[k] + m * m;
+            L.dseg_max = std::max(L.dseg_max, m);
+        }
+        L.dseg_d.upload(L.dseg.data(), L.dseg.size(), s);
+        L.dinv_off.upload(off.data(), off.size(), s);
+        L.dinv.alloc(off[nseg]);
+    } else {
+        L.dseg_max = 0;
+        L.dinv.release();
+    }
     CS_HIP(hipStreamSynchronize(s));
 }
 
@@ -748,7 +797,8 @@ void build_colour_layout(Ctx &c, Level &L) {
         std::vector<int32_t> rows;
         rows.reserve((L.cptr[k + 1] - L.cptr[k]) * L.nb);
         for (int64_t q = L.cptr[k]; q < L.cptr[k + 1]; ++q)
-            for (int r = 0; r < L.nb; ++r) rows.push_back((int32_t)(list[q] * L.nb + r));
+            if (list[q] * L.nb < L.n_active)   // rows of direct segments are not smoothed
+                for (int r = 0; r < L.nb; ++r) rows.push_back((int32_t)(list[q] * L.nb + r));
         build_sell(L.csell[k], L.h_ptr, L.h_col, L.h_val, &rows, c.stream);
     }
     CS_HIP(hipStreamSynchronize(c.stream));
@@ -803,6 +853,7 @@ void greedy_colouring(Ctx &c, Level &L, const BPattern &ap) {
 void fit_level(Ctx &c, Level &L, const cs_options &o) {
     hipStream_t s = c.stream;
     const int B = (int)L.B, nb = (int)L.nb, nb2 = nb * nb;
+    const int B_act = (int)(L.n_active / nb);   // blocks that are smoothed (the rest are solved directly)
     const int depth = o.depth;
     if (nb > MAXNB) fail(CS_EINVAL, "block size above 16 is not supported");
     // prescaling
@@ -836,10 +887,14 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
         std::vector<int32_t> hl(L.B);
         L.clist.download(hl.data(), B, s);
         CS_HIP(hipStreamSynchronize(s));
-        for (int k = 0; k < L.chi; ++k) lists.emplace_back(hl.begin() + L.cptr[k], hl.begin() + L.cptr[k + 1]);
+        for (int k = 0; k < L.chi; ++k) {
+            lists.emplace_back();
+            for (int64_t q = L.cptr[k]; q < L.cptr[k + 1]; ++q)
+                if (hl[q] < B_act) lists.back().push_back(hl[q]);
+        }
     } else {
         L.chi = 1;
-        lists.emplace_back(B);
+        lists.emplace_back(B_act);
         std::iota(lists[0].begin(), lists[0].end(), 0);
     }
     // E_0 = I
@@ -865,6 +920,7 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
     L.patterns.clear();
     keep_pattern(E.pat);
     DBuf<double> lamt((size_t)depth * B * nb2);
+    CS_HIP(hipMemsetAsync(lamt.get(), 0, lamt.bytes(), s));   // rows of direct segments get no smoother
     DBuf<int32_t> pos(B), dlist, sing, cnt, err(B);
     DBuf<int64_t> tot(1);
     L.singular = 0;
@@ -969,20 +1025,29 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
 
 }  // namespace
 
-void factor_bottom(Ctx &c, Level &L) {
-    const int n = (int)L.n;
-    std::vector<double> dense((size_t)n * n, 0.0);
-    for (int r = 0; r < n; ++r)
-        for (int64_t k = L.h_ptr[r]; k < L.h_ptr[r + 1]; ++k) dense[(size_t)r * n + L.h_col[k]] += L.h_val[k];
-    DBuf<double> a((size_t)n * n), b((size_t)n * n);
+void factor_direct(Ctx &c, Level &L) {
+    const int nseg = (int)L.dseg.size() - 1;
+    if (nseg <= 0) return;
+    // dense copies of the segment diagonal blocks of A, concatenated
+    std::vector<double> dense(L.dinv.n, 0.0);
+    size_t off = 0;
+    for (int q = 0; q < nseg; ++q) {
+        const int64_t r0 = L.dseg[q], m = L.dseg[q + 1] - r0;
+        for (int64_t r = r0; r < r0 + m; ++r)
+            for (int64_t e = L.h_ptr[r]; e < L.h_ptr[r + 1]; ++e)
+                dense[off + (size_t)(r - r0) * m + (L.h_col[e] - r0)] += L.h_val[e];
+        off += (size_t)m * m;
+    }
+    DBuf<double> a(L.dinv.n), b(L.dinv.n);
     a.upload(dense.data(), dense.size(), c.stream);
-    for (int k = 0; k < n; ++k) {
-        hipLaunchKernelGGL(k_gauss_jordan, dim3(grid_for((int64_t)n * n)), dim3(WG), 0, c.stream, a.get(), b.get(), n,
-                           k);
+    const int64_t tot = (int64_t)L.dinv.n;
+    for (int k = 0; k < L.dseg_max; ++k) {
+        hipLaunchKernelGGL(k_gauss_jordan_seg, dim3(grid_for(tot)), dim3(WG), 0, c.stream, a.get(), b.get(), tot,
+                           nseg, L.dinv_off.get(), k);
         std::swap(a, b);
     }
     CS_LAUNCH_CHECK();
-    L.ainv = std::move(a);
+    CS_HIP(hipMemcpyAsync(L.dinv.get(), a.get(), tot * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
     CS_HIP(hipStreamSynchronize(c.stream));
 }
 
@@ -1010,7 +1075,7 @@ void run_setup(Ctx &c, const cs_options &o) {
         fit_level(c, c.lv[l], o);
         c.singular += c.lv[l].singular;
     }
-    factor_bottom(c, c.lv.back());
+    for (Level &L : c.lv) factor_direct(c, L);
     build_working_copies(c);
     CS_HIP(hipEventRecord(c.ev1, c.stream));
     CS_HIP(hipEventSynchronize(c.ev1));

@@ -362,47 +362,67 @@ __global__ void k_prolong(int64_t n, const int32_t *__restrict__ pp, const int32
     vstore<T, R>(x + i * R, acc);
 }
 
-// bottom level: x = A^{-1} b with the FP64 inverse.  One thread per (row,
-// right-hand side); b is staged in LDS when it fits (n*R <= 4096).
+// Direct segments: x[i] = sum_j inv_q[i - s_q][j] b[s_q + j] for the rows
+// [n_active, n), with inv_q the FP64 inverse of the diagonal block of segment q
+// (the whole bottom level, or trailing systems of a batch that end on this
+// level).  One wavefront per row: the lanes stream the inverse row coalesced,
+// accumulate all right-hand sides in FP64 and reduce across the wavefront.
 template <typename T, int R>
-__global__ __launch_bounds__(WG) void k_coarse(int n, const double *__restrict__ ainv, const T *__restrict__ b,
-                                               T *__restrict__ x) {
-    __shared__ double bs[4096];
-    const bool staged = n * R <= 4096;
-    if (staged) {
-        for (int e = threadIdx.x; e < n * R; e += WG) bs[e] = (double)b[e];
-        __syncthreads();
+__global__ __launch_bounds__(WG) void k_direct_seg(int64_t n_active, int64_t n, int nseg,
+                                                   const int64_t *__restrict__ seg, const int64_t *__restrict__ inv_off,
+                                                   const double *__restrict__ inv, const T *__restrict__ b,
+                                                   T *__restrict__ x) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = n_active + (int64_t)blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
+    if (i >= n) return;   // uniform per wavefront
+    int lo = 0, hi = nseg - 1;   // segment q with seg[q] <= i < seg[q+1]
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (seg[mid] <= i) lo = mid;
+        else hi = mid - 1;
     }
-    const int t = blockIdx.x * WG + threadIdx.x;
-    if (t >= n * R) return;
-    const int i = t / R, k = t % R;
-    const double *row = ainv + (int64_t)i * n;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int j = 0;
-    if (staged) {
-        for (; j + 4 <= n; j += 4) {
-            a0 += row[j] * bs[j * R + k];
-            a1 += row[j + 1] * bs[(j + 1) * R + k];
-            a2 += row[j + 2] * bs[(j + 2) * R + k];
-            a3 += row[j + 3] * bs[(j + 3) * R + k];
-        }
-        for (; j < n; ++j) a0 += row[j] * bs[j * R + k];
-    } else {
-        for (; j < n; ++j) a0 += row[j] * (double)b[(int64_t)j * R + k];
+    const int64_t s = seg[lo], m = seg[lo + 1] - s;
+    const double *row = inv + inv_off[lo] + (i - s) * m;
+    double acc[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) acc[k] = 0.0;
+    for (int64_t j = lane; j < m; j += 64) {
+        const double a = row[j];
+        T bv[R];
+        vload<T, R>(b + (s + j) * R, bv);
+#pragma unroll
+        for (int k = 0; k < R; ++k) acc[k] += a * (double)bv[k];
     }
-    x[t] = (T)((a0 + a1) + (a2 + a3));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) acc[k] += __shfl_xor(acc[k], off, 64);
+    }
+    if (lane == 0) {
+        T o[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) o[k] = (T)acc[k];
+        vstore<T, R>(x + i * R, o);
+    }
 }
 
 // FP64 refinement residual r = b - A x; writes r in the working precision and
 // per-workgroup partial sums of r^2 for every right-hand side.  With x == null
 // it computes the partial sums of b^2.
-template <typename T, int R>
+//
+// SYS (a batch of independent systems): the squares are summed per 64-row
+// slice instead.  het[s] < 0 marks a slice whose rows all belong to one
+// system: its sums go to spart[s][R] (wavefront reduction).  The few slices
+// that straddle a system boundary keep their per-row squares in
+// rn2[(het[s]*64 + lane)][R] for the per-system reduction.
+template <typename T, int R, bool SYS>
 __global__ __launch_bounds__(WG) void k_ir_residual(int64_t nrows, int64_t nslices, const int64_t *__restrict__ sptr,
                                                     const int32_t *__restrict__ slen, const int32_t *__restrict__ scol,
                                                     const double *__restrict__ sval, const double *__restrict__ b,
                                                     const double *__restrict__ x, T *__restrict__ rt,
-                                                    double *__restrict__ partial) {
-    __shared__ double red[WG * R];
+                                                    double *__restrict__ partial, const int32_t *__restrict__ het,
+                                                    double *__restrict__ spart, double *__restrict__ rn2) {
+    __shared__ double red[SYS ? 1 : WG * R];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t ntiles = (nslices + 3) / 4;
     double sq[R];
@@ -413,26 +433,50 @@ __global__ __launch_bounds__(WG) void k_ir_residual(int64_t nrows, int64_t nslic
     for (int64_t tile = tl.t; tile < tl.end; tile += tl.step) {
         const int64_t slice = tile * 4 + wv;
         const int64_t row = slice * 64 + lane;
-        if (slice >= nslices || row >= nrows) continue;
+        if (slice >= nslices) continue;   // uniform per wavefront
+        const bool valid = row < nrows;
+        if (!SYS && !valid) continue;
         double acc[R];
-        vload_nt<double, R>(b + row * R, acc);
-        if (x) {
-            double ax[R];
 #pragma unroll
-            for (int k = 0; k < R; ++k) ax[k] = 0.0;
-            spmv_row<double, R, false>(scol, sval, sptr[slice] + lane, slen[slice], x, nullptr, 1, ax);
+        for (int k = 0; k < R; ++k) acc[k] = 0.0;
+        if (valid) {
+            vload_nt<double, R>(b + row * R, acc);
+            if (x) {
+                double ax[R];
 #pragma unroll
-            for (int k = 0; k < R; ++k) acc[k] -= ax[k];
+                for (int k = 0; k < R; ++k) ax[k] = 0.0;
+                spmv_row<double, R, false>(scol, sval, sptr[slice] + lane, slen[slice], x, nullptr, 1, ax);
+#pragma unroll
+                for (int k = 0; k < R; ++k) acc[k] -= ax[k];
+            }
+            if (rt) {
+                T o[R];
+#pragma unroll
+                for (int k = 0; k < R; ++k) o[k] = (T)acc[k];
+                vstore<T, R>(rt + row * R, o);
+            }
         }
-        if (rt) {
-            T o[R];
+        if constexpr (SYS) {
+            double o[R];
 #pragma unroll
-            for (int k = 0; k < R; ++k) o[k] = (T)acc[k];
-            vstore<T, R>(rt + row * R, o);
+            for (int k = 0; k < R; ++k) o[k] = acc[k] * acc[k];
+            const int h = het[slice];
+            if (h < 0) {
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+                    for (int k = 0; k < R; ++k) o[k] += __shfl_xor(o[k], off, 64);
+                }
+                if (lane == 0) vstore<double, R>(spart + slice * R, o);
+            } else {
+                vstore<double, R>(rn2 + ((int64_t)h * 64 + lane) * R, o);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < R; ++k) sq[k] += acc[k] * acc[k];
         }
-#pragma unroll
-        for (int k = 0; k < R; ++k) sq[k] += acc[k] * acc[k];
     }
+    if constexpr (SYS) return;
 #pragma unroll
     for (int k = 0; k < R; ++k) red[threadIdx.x * R + k] = sq[k];
     __syncthreads();
@@ -462,6 +506,47 @@ __global__ __launch_bounds__(1024) void k_reduce_partials(int64_t G, int R, cons
         __syncthreads();
     }
     if (t < R) out[t] = red[t];
+}
+
+// Per-system squared norms from the slice sums of k_ir_residual<SYS>:
+// out[s][k] = sum over the whole slices of system s (spart) + sum over its rows
+// in straddling slices (rn2).  One workgroup per system, fixed order.  System
+// s owns rows [r0, r1); its whole slices are [fs, fe), the rest of its rows sit
+// in straddling slices.
+__global__ __launch_bounds__(256) void k_sys_norms(int R, int64_t n, const int64_t *__restrict__ sys_ptr,
+                                                   const int32_t *__restrict__ het,
+                                                   const double *__restrict__ spart,
+                                                   const double *__restrict__ rn2, double *__restrict__ out) {
+    __shared__ double red[256];
+    const int t = threadIdx.x;
+    const int64_t r0 = sys_ptr[blockIdx.x], r1 = sys_ptr[blockIdx.x + 1];
+    const int64_t fs = (r0 + 63) / 64;
+    const int64_t fe = (r1 % 64 == 0 || r1 == n) ? (r1 + 63) / 64 : r1 / 64;
+    double s = 0.0;
+    // R divides 256 and every range starts at a multiple of R: thread t always
+    // sums component t % R
+    if (fs < fe) {
+        for (int64_t e = fs * R + t; e < fe * R; e += 256) s += spart[e];
+    }
+    auto rows = [&](int64_t a, int64_t b) {
+        for (int64_t e = a * R + t; e < b * R; e += 256) {
+            const int64_t r = e / R;
+            s += rn2[((int64_t)het[r / 64] * 64 + r % 64) * R + e % R];
+        }
+    };
+    if (fs < fe) {
+        rows(r0, fs * 64);
+        rows(fe * 64 < r1 ? fe * 64 : r1, r1);
+    } else {
+        rows(r0, r1);
+    }
+    red[t] = s;
+    __syncthreads();
+    for (int h = 128; h >= R; h >>= 1) {
+        if (t < h) red[t] += red[t + h];
+        __syncthreads();
+    }
+    if (t < R) out[(int64_t)blockIdx.x * R + t] = red[t];
 }
 
 template <typename T>
@@ -538,16 +623,21 @@ const float *pval<float>(const Level &L, bool tr) { return tr ? L.pt_val32.get()
 template <typename T, int R>
 void launch_sweep(Ctx &c, const Level &L, const Sell &S, bool rowmap, bool zero, const T *lam, const T *b,
                   const T *xin, T *xout, const T *xc = nullptr, int agg_k = 0) {
+    // the natural-order layout is swept over the active rows only (rows of
+    // direct segments are solved exactly after the sweeps)
+    const int64_t nrows = rowmap ? S.nrows : L.n_active;
+    const int64_t nslices = rowmap ? S.nslices : L.act_slices;
+    const int64_t nnz = rowmap ? S.nnz : L.act_nnz;
     // levels below SMALL_SLICES slices run one 64-row slice per workgroup
-    const bool small = S.nslices < SMALL_SLICES;
-    const unsigned G = small ? (unsigned)std::min<int64_t>(S.nslices, c.sweep_grid) : tile_grid(c, S.nslices);
+    const bool small = nslices < SMALL_SLICES;
+    const unsigned G = small ? (unsigned)std::min<int64_t>(nslices, c.sweep_grid) : tile_grid(c, nslices);
     if (G == 0) return;
     const bool prol = xc != nullptr;
     const int cls = zero ? CS_TRACE_SWEEP_ZERO
                          : (xc ? CS_TRACE_SWEEP_PROLONG : (small ? CS_TRACE_SWEEP_SMALL : CS_TRACE_SWEEP));
     const double es = sizeof(T);
-    const double bytes = (zero ? 0.0 : S.nnz * (es + 4.0)) + (double)S.nrows * L.nb * es +
-                         (double)S.nrows * R * es * 2.0 + (zero ? 0.0 : (rowmap ? L.n : S.nrows) * R * es) +
+    const double bytes = (zero ? 0.0 : nnz * (es + 4.0)) + (double)nrows * L.nb * es +
+                         (double)nrows * R * es * 2.0 + (zero ? 0.0 : (rowmap ? L.n : nrows) * R * es) +
                          (prol ? (double)L.nc * R * es : 0.0);
     const int slot = trace_begin(c, cls, bytes);
     dispatch_nb(L.nb, [&](auto nbc) {
@@ -555,12 +645,12 @@ void launch_sweep(Ctx &c, const Level &L, const Sell &S, bool rowmap, bool zero,
 #define CS_SWEEP(Z, M, P, ROWS)                                                                                     \
     do {                                                                                                            \
         if (small)                                                                                                  \
-            hipLaunchKernelGGL((k_sweep<T, NB, R, Z, M, P, 64>), dim3(G), dim3(64), 0, c.stream, S.nrows,          \
-                               S.nslices, ROWS, S.slice_ptr.get(), S.slice_len.get(), S.col.get(), sell_val<T>(S), \
+            hipLaunchKernelGGL((k_sweep<T, NB, R, Z, M, P, 64>), dim3(G), dim3(64), 0, c.stream, nrows,            \
+                               nslices, ROWS, S.slice_ptr.get(), S.slice_len.get(), S.col.get(), sell_val<T>(S), \
                                lam, b, xin, xout, xc, agg_k);                                                       \
         else                                                                                                        \
-            hipLaunchKernelGGL((k_sweep<T, NB, R, Z, M, P, WG>), dim3(G), dim3(WG), 0, c.stream, S.nrows,          \
-                               S.nslices, ROWS, S.slice_ptr.get(), S.slice_len.get(), S.col.get(), sell_val<T>(S), \
+            hipLaunchKernelGGL((k_sweep<T, NB, R, Z, M, P, WG>), dim3(G), dim3(WG), 0, c.stream, nrows,            \
+                               nslices, ROWS, S.slice_ptr.get(), S.slice_len.get(), S.col.get(), sell_val<T>(S), \
                                lam, b, xin, xout, xc, agg_k);                                                       \
     } while (0)
         if (rowmap) {
@@ -600,7 +690,7 @@ T *apply_cascade(Ctx &c, const Level &L, bool reverse, bool zero_start, const T 
     }
     // multiplicative: flattened (l, k) sequence, in place
     if (zero_start) {
-        hipLaunchKernelGGL(k_zero<T>, dim3(grid_for(L.n * R)), dim3(WG), 0, c.stream, L.n * R, x);
+        hipLaunchKernelGGL(k_zero<T>, dim3(grid_for(L.n_active * R)), dim3(WG), 0, c.stream, L.n_active * R, x);
         CS_LAUNCH_CHECK();
     }
     const int chi = L.chi;
@@ -616,6 +706,22 @@ T *apply_cascade(Ctx &c, const Level &L, bool reverse, bool zero_start, const T 
     return x;
 }
 
+// x_d = A_dd^{-1} b_d on the rows of the direct segments of level L
+template <typename T, int R>
+void direct_solve(Ctx &c, const Level &L, const T *b, T *x) {
+    const int nseg = (int)L.dseg.size() - 1;
+    if (nseg <= 0) return;
+    const double es = sizeof(T);
+    const int slot = trace_begin(c, CS_TRACE_BOTTOM, (double)L.dinv.n * 8.0 + 2.0 * (L.n - L.n_active) * R * es);
+    hipLaunchKernelGGL((k_direct_seg<T, R>), dim3(grid_for(L.n - L.n_active, WG / 64)), dim3(WG), 0, c.stream,
+                       L.n_active, L.n, nseg, L.dseg_d.get(), L.dinv_off.get(), L.dinv.get(), b, x);
+    CS_LAUNCH_CHECK();
+    trace_end(c, slot);
+}
+
+// V-cycle (Alg. 1) from level l down: x_l = V(b_l) from the zero guess, with
+// b_l in bb and the result in xb.  Only the active rows are smoothed and
+// transferred; the direct segments of every level are solved exactly.
 template <typename T, int R>
 void vcycle_level(Ctx &c, int l) {
     Level &L = c.lv[l];
@@ -625,14 +731,11 @@ void vcycle_level(Ctx &c, int l) {
     T *rr = reinterpret_cast<T *>(L.rr.get());
     const double es = sizeof(T);
     if (l + 1 == (int)c.lv.size()) {
-        const int slot = trace_begin(c, CS_TRACE_BOTTOM, (double)L.n * L.n * 8.0 + 2.0 * L.n * R * es);
-        hipLaunchKernelGGL((k_coarse<T, R>), dim3(grid_for(L.n * R)), dim3(WG), 0, c.stream, (int)L.n, L.ainv.get(),
-                           bb, xb);
-        CS_LAUNCH_CHECK();
-        trace_end(c, slot);
+        direct_solve<T, R>(c, L, bb, xb);
         return;
     }
     Level &C = c.lv[l + 1];
+    const int64_t na = L.n_active;
     T *x = xb, *alt = xt;
     const bool rf = c.opt.order == CS_RF;
     for (int a = 0; a < c.opt.n_pre; ++a) {
@@ -642,17 +745,17 @@ void vcycle_level(Ctx &c, int l) {
     // restricted residual
     const bool fused = c.fuse_transfers && L.agg_k > 0;
     int slot = trace_begin(c, CS_TRACE_RESIDUAL,
-                           L.sell.nnz * (es + 4.0) + (fused ? 2.0 : 3.0) * L.n * R * es +
-                               (fused ? 0.0 : L.p_nnz * (es + 4.0) + L.n * R * es) + L.nc * R * es);
+                           L.act_nnz * (es + 4.0) + (fused ? 2.0 : 3.0) * na * R * es +
+                               (fused ? 0.0 : L.p_nnz * (es + 4.0) + na * R * es) + L.nc * R * es);
     if (fused) {
-        hipLaunchKernelGGL((k_residual_restrict<T, R>), dim3(tile_grid(c, L.sell.nslices)), dim3(WG), 0, c.stream,
-                           L.sell.nrows, L.sell.nslices, L.sell.slice_ptr.get(), L.sell.slice_len.get(),
-                           L.sell.col.get(), sell_val<T>(L.sell), bb, x, L.agg_k, L.nc, (T)L.r_scale,
+        hipLaunchKernelGGL((k_residual_restrict<T, R>), dim3(tile_grid(c, L.act_slices)), dim3(WG), 0, c.stream, na,
+                           L.act_slices, L.sell.slice_ptr.get(), L.sell.slice_len.get(), L.sell.col.get(),
+                           sell_val<T>(L.sell), bb, x, L.agg_k, L.nc, (T)L.r_scale,
                            reinterpret_cast<T *>(C.bb.get()));
     } else {
-        hipLaunchKernelGGL((k_residual<T, R>), dim3(tile_grid(c, L.sell.nslices)), dim3(WG), 0, c.stream,
-                           L.sell.nrows, L.sell.nslices, L.sell.slice_ptr.get(), L.sell.slice_len.get(),
-                           L.sell.col.get(), sell_val<T>(L.sell), bb, x, rr);
+        hipLaunchKernelGGL((k_residual<T, R>), dim3(tile_grid(c, L.act_slices)), dim3(WG), 0, c.stream, na,
+                           L.act_slices, L.sell.slice_ptr.get(), L.sell.slice_len.get(), L.sell.col.get(),
+                           sell_val<T>(L.sell), bb, x, rr);
         hipLaunchKernelGGL((k_restrict<T, R>), dim3(grid_for(L.nc)), dim3(WG), 0, c.stream, L.nc, L.pt_ptr.get(),
                            L.pt_col.get(), pval<T>(L, true), (T)L.r_scale, rr, reinterpret_cast<T *>(C.bb.get()));
     }
@@ -662,8 +765,8 @@ void vcycle_level(Ctx &c, int l) {
     const T *xc = reinterpret_cast<const T *>(C.xb.get());
     const bool fuse_prol = fused && c.opt.mode == CS_ADDITIVE && c.opt.n_post > 0;
     if (!fuse_prol) {
-        slot = trace_begin(c, CS_TRACE_PROLONG, L.p_nnz * (es + 4.0) + 2.0 * L.n * R * es + L.nc * R * es);
-        hipLaunchKernelGGL((k_prolong<T, R>), dim3(grid_for(L.n)), dim3(WG), 0, c.stream, L.n, L.p_ptr.get(),
+        slot = trace_begin(c, CS_TRACE_PROLONG, L.p_nnz * (es + 4.0) + 2.0 * na * R * es + L.nc * R * es);
+        hipLaunchKernelGGL((k_prolong<T, R>), dim3(grid_for(na)), dim3(WG), 0, c.stream, na, L.p_ptr.get(),
                            L.p_col.get(), pval<T>(L, false), xc, x);
         CS_LAUNCH_CHECK();
         trace_end(c, slot);
@@ -673,8 +776,9 @@ void vcycle_level(Ctx &c, int l) {
         if (res != x) std::swap(x, alt);
     }
     if (x != xb) {
-        CS_HIP(hipMemcpyAsync(xb, x, L.n * R * sizeof(T), hipMemcpyDeviceToDevice, c.stream));
+        CS_HIP(hipMemcpyAsync(xb, x, na * R * sizeof(T), hipMemcpyDeviceToDevice, c.stream));
     }
+    direct_solve<T, R>(c, L, bb, xb);
 }
 
 template <class F>
@@ -698,8 +802,22 @@ void ensure_workspace(Ctx &c, int nrhs) {
     }
     const int64_t G = std::min<int64_t>(ceil_div(c.lv[0].sell.nslices, 4), IR_GRID);
     c.ir_partial.alloc(std::max<int64_t>(G, 1) * nrhs);
-    c.ir_norm.alloc(2 * nrhs);
-    if (!c.h_norm) CS_HIP(hipHostMalloc(reinterpret_cast<void **>(&c.h_norm), 16 * sizeof(double)));
+    const int64_t nsys = c.sys_ptr.empty() ? 1 : (int64_t)c.sys_ptr.size() - 1;
+    c.ir_norm.alloc(2 * nsys * nrhs);
+    if (nsys > 1) {
+        c.sys_spart.alloc((size_t)c.lv[0].sell.nslices * nrhs);
+        c.rn2.alloc((size_t)std::max<int64_t>(c.n_het, 1) * 64 * nrhs);
+    } else {
+        c.sys_spart.release();
+        c.rn2.release();
+    }
+    if ((size_t)(2 * nsys * nrhs) > c.h_norm_cap) {
+        if (c.h_norm) CS_HIP(hipHostFree(c.h_norm));
+        c.h_norm = nullptr;
+        c.h_norm_cap = 0;
+        CS_HIP(hipHostMalloc(reinterpret_cast<void **>(&c.h_norm), 2 * nsys * nrhs * sizeof(double)));
+        c.h_norm_cap = 2 * nsys * nrhs;
+    }
     c.ws_nrhs = nrhs;
     c.gen++;
     c.ws_prec = prec;
@@ -735,6 +853,11 @@ void smooth_apply(Ctx &c, int level, bool reverse, const double *b, double *x, i
         dispatch_r(nrhs, [&](auto rc) {
             res = apply_cascade<T, decltype(rc)::value>(c, L, reverse, false, bb, xb, xt);
         });
+        // rows of direct segments are not smoothed: they keep their input values
+        if (res != xb && L.n_active < L.n) {
+            const int64_t off = L.n_active * nrhs;
+            CS_HIP(hipMemcpyAsync(res + off, xb + off, (n - off) * sizeof(T), hipMemcpyDeviceToDevice, c.stream));
+        }
         hipLaunchKernelGGL((k_convert<T, double>), dim3(grid_for(n)), dim3(WG), 0, c.stream, n, (const T *)res, x);
         CS_LAUNCH_CHECK();
     });
@@ -747,6 +870,7 @@ void solve_ir(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
     const Sell &S = L0.sell;
     const int64_t n = L0.n * nrhs;
     const int64_t G = std::min<int64_t>(ceil_div(S.nslices, 4), IR_GRID);
+    const int nsys = c.sys_ptr.empty() ? 1 : (int)c.sys_ptr.size() - 1;
     const double *hn = c.h_norm;
     *st = CS_OK;
     // With graphs the solve runs on the context's own (capturable) stream,
@@ -778,14 +902,28 @@ void solve_ir(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
             constexpr int R = decltype(rc)::value;
             const double ir_bytes = S.nnz * 12.0 + (double)L0.n * R * (16.0 + sizeof(T));
             const double up_bytes = (double)L0.n * R * (16.0 + sizeof(T));
+            // squared norms of r (and of b, at offset nsys*R): per system in a batch
+            const bool batch = nsys > 1;
+            auto norms = [&](const double *xx, T *rt, double *out) {
+                if (batch) {
+                    hipLaunchKernelGGL((k_ir_residual<T, R, true>), dim3(G), dim3(WG), 0, c.stream, S.nrows,
+                                       S.nslices, S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), b,
+                                       xx, rt, (double *)nullptr, c.sys_het.get(), c.sys_spart.get(), c.rn2.get());
+                    hipLaunchKernelGGL(k_sys_norms, dim3(nsys), dim3(256), 0, c.stream, R, S.nrows,
+                                       c.sys_ptr_d.get(), c.sys_het.get(), c.sys_spart.get(), c.rn2.get(), out);
+                } else {
+                    hipLaunchKernelGGL((k_ir_residual<T, R, false>), dim3(G), dim3(WG), 0, c.stream, S.nrows,
+                                       S.nslices, S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), b,
+                                       xx, rt, c.ir_partial.get(), (const int32_t *)nullptr, (double *)nullptr,
+                                       (double *)nullptr);
+                    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(1024), 0, c.stream, G, R, c.ir_partial.get(),
+                                       out);
+                }
+                CS_LAUNCH_CHECK();
+            };
             auto residual = [&]() {
                 const int slot = trace_begin(c, CS_TRACE_REFINE, ir_bytes);
-                hipLaunchKernelGGL((k_ir_residual<T, R>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
-                                   S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), b, x,
-                                   reinterpret_cast<T *>(L0.bb.get()), c.ir_partial.get());
-                hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(1024), 0, c.stream, G, R, c.ir_partial.get(),
-                                   c.ir_norm.get());
-                CS_LAUNCH_CHECK();
+                norms(x, reinterpret_cast<T *>(L0.bb.get()), c.ir_norm.get());
                 trace_end(c, slot);
             };
             // one refinement iteration after the check: d = V r, x += d, r = b - A x
@@ -799,30 +937,34 @@ void solve_ir(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
                 residual();
             };
             // ||b||^2, x = 0, first residual
-            hipLaunchKernelGGL((k_ir_residual<T, R>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
-                               S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), b, nullptr,
-                               (T *)nullptr, c.ir_partial.get());
-            hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(1024), 0, c.stream, G, R, c.ir_partial.get(),
-                               c.ir_norm.get() + R);
+            norms(nullptr, (T *)nullptr, c.ir_norm.get() + nsys * R);
             hipLaunchKernelGGL(k_zero<double>, dim3(grid_for(n)), dim3(WG), 0, c.stream, n, x);
             CS_LAUNCH_CHECK();
             residual();
-            std::vector<double> hist;
-            double bn2[8];
+            std::vector<double> hist, bn2(nsys * R);
+            c.sys_iters.assign(nsys, -1);
+            c.sys_rel.assign(nsys, NAN);
             int it = 0;
             for (;; ++it) {
-                CS_HIP(hipMemcpyAsync(c.h_norm, c.ir_norm.get(), 2 * R * sizeof(double), hipMemcpyDeviceToHost,
-                                      c.stream));
+                CS_HIP(hipMemcpyAsync(c.h_norm, c.ir_norm.get(), 2 * nsys * R * sizeof(double),
+                                      hipMemcpyDeviceToHost, c.stream));
                 CS_HIP(hipStreamSynchronize(c.stream));
                 if (graphs && it > 0) trace_graph_accumulate(c);
                 if (it == 0)
-                    for (int k = 0; k < R; ++k) bn2[k] = hn[R + k] > 0 ? hn[R + k] : 1.0;
+                    for (int e = 0; e < nsys * R; ++e) bn2[e] = hn[nsys * R + e] > 0 ? hn[nsys * R + e] : 1.0;
+                // every system converges on its own: max over systems of max over RHS
                 double rel = 0.0;
                 bool bad = false;
-                for (int k = 0; k < R; ++k) {
-                    double v = std::sqrt(hn[k] / bn2[k]);
-                    if (!std::isfinite(v)) bad = true;
-                    rel = std::max(rel, v);
+                for (int q = 0; q < nsys; ++q) {
+                    double rq = 0.0;
+                    for (int k = 0; k < R; ++k) {
+                        const double v = std::sqrt(hn[q * R + k] / bn2[q * R + k]);
+                        if (!std::isfinite(v)) bad = true;
+                        rq = std::max(rq, v);
+                    }
+                    c.sys_rel[q] = rq;
+                    if (c.sys_iters[q] < 0 && rq <= rtol) c.sys_iters[q] = it;
+                    rel = std::max(rel, rq);
                 }
                 hist.push_back(bad ? NAN : rel);
                 if (bad) {
@@ -867,6 +1009,8 @@ void solve_ir(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
                     iteration();
                 }
             }
+            for (int q = 0; q < nsys; ++q)
+                if (c.sys_iters[q] < 0) c.sys_iters[q] = it;
             trace_flush(c);
             CS_HIP(hipEventRecord(c.ev1, c.stream));
             CS_HIP(hipEventSynchronize(c.ev1));

@@ -88,3 +88,36 @@ def test_morton_numbering_makes_children_contiguous():
         perm[mor.cells.ravel()] = fd.cell_order(n, d, 1).ravel()
         Pm = lex[perm][:, perm]
         assert abs(Pm - mor.A).max() == 0
+
+
+def test_batch_concatenation_layout():
+    """Stacked levels are block diagonal over the present systems (deepest
+    first); systems that end on a level are its trailing direct segments; P
+    is block diagonal over the continuing systems with empty direct rows."""
+    import scipy.sparse as sp
+    from synth.batch import concatenate
+    sizes = [16, 32, 8, 24]
+    probs = fd.lognormal_batch(len(sizes), nrhs=2, sizes=sizes, config_id=14)
+    bt = concatenate(probs)
+    nlev = [len(p.levels) for p in probs]
+    assert [nlev[s] for s in bt.order] == sorted(nlev, reverse=True)
+    for l, lv in enumerate(bt.levels):
+        present = [s for s in bt.order if nlev[s] > l]
+        ref = sp.block_diag([probs[s].levels[l].A for s in present], format="csr")
+        assert (lv.A != ref).nnz == 0
+        ends = [s for s in present if nlev[s] == l + 1]
+        if ends:
+            seg = np.asarray(lv.direct_seg)
+            assert seg[-1] == lv.n and np.array_equal(np.diff(seg), [probs[s].levels[l].n for s in ends])
+        else:
+            assert lv.direct_seg is None
+        if lv.P is not None:
+            n_act = lv.n if lv.direct_seg is None else lv.direct_seg[0]
+            assert lv.P.shape == (lv.n, bt.levels[l + 1].n)
+            assert lv.P[n_act:].nnz == 0
+    assert bt.levels[-1].direct_seg[0] == 0
+    xs = [np.arange(p.n * 2, dtype=float).reshape(p.n, 2) + 1000 * i for i, p in enumerate(probs)]
+    back = bt.split(bt.stack(xs))
+    for a, b in zip(xs, back):
+        np.testing.assert_array_equal(a, b)
+    assert bt.sys_ptr[-1] == bt.levels[0].n and np.array_equal(bt.split(bt.rhs)[1], probs[1].rhs)
