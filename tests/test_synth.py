@@ -1,4 +1,5 @@
 """Checks of the synthetic input generators (no solver arithmetic involved)."""
+import pytest
 import numpy as np
 import scipy.sparse.linalg as spla
 
@@ -121,3 +122,33 @@ def test_batch_concatenation_layout():
     for a, b in zip(xs, back):
         np.testing.assert_array_equal(a, b)
     assert bt.sys_ptr[-1] == bt.levels[0].n and np.array_equal(bt.split(bt.rhs)[1], probs[1].rhs)
+
+
+def test_q1_multiphase_generator():
+    """Q1 FE: exact element stiffness, symmetric positive definite global
+    matrix, zero row sums away from the Dirichlet faces, Galerkin coarse
+    operator equal to the rediscretisation on the coarse mesh, phases at the
+    1/3 and 2/3 quantiles."""
+    from synth import fe
+    K = fe.q1_stiffness()
+    np.testing.assert_allclose(K.sum(axis=1), 0, atol=1e-15)
+    assert K[0, 0] == pytest.approx(1.0 / 3.0)       # diagonal of the unit-cube Q1 Laplacian
+    n = 8
+    mu = fe.grf_phases(n, config_id=99)
+    assert sorted(np.unique(mu)) == [1.0, 1e3, 1e6]
+    assert all(abs(np.mean(mu == v) - 1 / 3) < 0.01 for v in (1.0, 1e3, 1e6))
+    A = fe.assemble(mu)
+    assert abs(A - A.T).max() < 1e-9 * abs(A).max()
+    order = fe.node_order(n)
+    kk, jj, ii = np.indices((n, n, n))
+    interior = (ii < n - 1) & (jj < n - 1) & (kk < n - 1)     # no Dirichlet neighbour
+    rs = np.asarray(A.sum(axis=1)).ravel()
+    assert np.all(np.abs(rs[order[interior]]) <= 1e-9 * abs(A).max())
+    assert np.all(rs[order[~interior]] > 0)
+    assert np.linalg.eigvalsh(A.toarray()).min() > 0
+    for m in (8, 12):
+        P = fe.trilinear_P(m)
+        Ac = P.T @ fe.assemble(np.ones((m,) * 3)) @ P
+        assert abs(Ac - fe.assemble(np.ones((m // 2,) * 3))).max() < 1e-14
+    lv = fe.galerkin_hierarchy(A, n, n_stop=2)
+    assert [l.n for l in lv] == [512, 64, 8] and all(l.block_size == 8 for l in lv)
