@@ -78,6 +78,23 @@ SIGNATURES = {
     "cs_trace_read": (_I32, [_VP, _I32, _p(_D), _p(_I64), _p(_D)]),
     "cs_set_systems": (_I32, [_VP, _I32, _p(_I64)]),
     "cs_get_system_stats": (_I32, [_VP, _p(_I32), _p(_D)]),
+    # learned setup (cascade_learned.h)
+    "cs_mlp_create": (_I32, [_p(_VP), _I32, _VP, _I32, _I32, _I32]),
+    "cs_mlp_destroy": (None, [_VP]),
+    "cs_mlp_last_error": (ctypes.c_char_p, [_VP]),
+    "cs_mlp_param_count": (_I32, [_VP, _p(_I64)]),
+    "cs_mlp_set_params": (_I32, [_VP, _p(ctypes.c_float)]),
+    "cs_mlp_get_params": (_I32, [_VP, _p(ctypes.c_float)]),
+    "cs_mlp_set_scaling": (_I32, [_VP, _p(ctypes.c_float), _p(ctypes.c_float)]),
+    "cs_mlp_get_scaling": (_I32, [_VP, _p(ctypes.c_float), _p(ctypes.c_float)]),
+    "cs_mlp_fit_scaling": (_I32, [_VP, _VP, _VP, _I64]),
+    "cs_mlp_gradient": (_I32, [_VP, _VP, _VP, _VP, _I64, _p(ctypes.c_float), _p(_D)]),
+    "cs_mlp_loss": (_I32, [_VP, _VP, _VP, _VP, _I64, _p(_D)]),
+    "cs_mlp_train": (_I32, [_VP, _VP, _VP, _VP, _I64, _I32, _I32, _D, _D, _p(_D)]),
+    "cs_mlp_forward": (_I32, [_VP, _VP, _I64, _VP]),
+    "cs_fe_block_features": (_I32, [_VP, _VP, _I32, _VP]),
+    "cs_get_prescaled_blocks": (_I32, [_VP, _I32, _VP]),
+    "cs_setup_learned": (_I32, [_VP, _p(cs_options), _VP, _VP]),
     "cs_save_setup": (_I32, [_VP, ctypes.c_char_p]),
     "cs_load_setup": (_I32, [_VP, ctypes.c_char_p]),
 }
@@ -272,6 +289,22 @@ class Solver:
         return x, dict(iterations=k, rel_res=info.rel_res, rho=info.rho, setup_ms=info.setup_ms,
                        solve_ms=info.solve_ms, singular_blocks=info.singular_blocks,
                        history=hist[:k + 1].copy(), status=st)
+
+    def get_prescaled_blocks(self, level: int = 0):
+        """Lambda~ of a level as a device tensor [n_blocks, depth, nb, nb] (FP32)."""
+        n, nb = self.sizes[level]
+        out = self._torch.empty((n // nb, self.depth, nb, nb), dtype=self._torch.float32, device=self.device)
+        self._check(self._lib.cs_get_prescaled_blocks(self._h, level, _tensor_ptr(out)))
+        return out
+
+    def setup_learned(self, net, features, depth: int = 2, order: str = "RF", n_pre: int = 1, n_post: int = 1,
+                      precision: str = "fp64"):
+        """Finest-level cascade from the network's prediction for `features`
+        (device FP32 [n_blocks, n_in]); Frobenius fit on coarser levels."""
+        X = features.contiguous()
+        o = cs_options(depth, _MODES["additive"], _ORDERS[order], n_pre, n_post, 0, _PRECS[precision])
+        self.depth = depth
+        self._check(self._lib.cs_setup_learned(self._h, ctypes.byref(o), net._h, _tensor_ptr(X)))
 
     def set_systems(self, row_ptr=None):
         """Declare the finest level a batch of independent systems with row

@@ -5,6 +5,7 @@
 #include <fstream>
 
 #include "cs_internal.h"
+#include "mlp_internal.h"
 
 using cs::Ctx;
 using cs::Level;
@@ -273,6 +274,47 @@ cs_status cs_setup(cs_ctx ctx, const cs_options *opt) {
         c.ws_nrhs = 0;
         cs::run_setup(c, *opt);
         c.have_setup = true;
+    });
+}
+
+cs_status cs_setup_learned(cs_ctx ctx, const cs_options *opt, cs_mlp mlp, const float *X) {
+    return guarded(ctx, [&](Ctx &c) {
+        need(c.have_hierarchy, "cs_setup_learned before cs_set_hierarchy", CS_ESTATE);
+        need(opt != nullptr && mlp != nullptr && X != nullptr, "options, network or features missing");
+        need(opt->depth >= 1 && opt->depth <= 16, "depth must be in [1, 16]");
+        need(opt->mode == CS_ADDITIVE, "the learned setup fits additive cascades");
+        need(opt->order == CS_FF || opt->order == CS_RF, "order must be FF or RF");
+        need(opt->n_pre >= 1 && opt->n_post >= 0, "need n_pre >= 1 and n_post >= 0");
+        need(opt->precision == CS_FP64 || opt->precision == CS_FP32, "precision must be FP64 or FP32");
+        need(c.lv.size() >= 2, "the hierarchy has no smoothed level");
+        Level &L0 = c.lv[0];
+        cs::Mlp &m = mlp->m;
+        need(m.device == c.device, "network and context live on different devices");
+        need(m.n_out == opt->depth * L0.nb * L0.nb, "network outputs must equal depth * block_size^2");
+        need(L0.n_active == L0.n, "the finest level must not hold direct segments");
+        c.have_setup = false;
+        c.opt = *opt;
+        c.precision = opt->precision;
+        c.ws_nrhs = 0;
+        cs::DBuf<float> lt((size_t)L0.B * m.n_out);
+        CS_HIP(hipEventRecord(c.ev0, c.stream));
+        cs::mlp_predict(m, c.stream, X, L0.B, lt.get());
+        cs::run_setup_learned(c, *opt, lt.get());
+        CS_HIP(hipEventRecord(c.ev1, c.stream));
+        CS_HIP(hipEventSynchronize(c.ev1));
+        float ms = 0;
+        CS_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
+        c.setup_ms = ms;
+        c.have_setup = true;
+    });
+}
+
+cs_status cs_get_prescaled_blocks(cs_ctx ctx, int32_t level, float *out) {
+    return guarded(ctx, [&](Ctx &c) {
+        need(c.have_setup, "no setup", CS_ESTATE);
+        need(level >= 0 && level + 1 < (int)c.lv.size(), "level has no smoother");
+        need(out != nullptr, "null output");
+        cs::prescaled_blocks(c, c.lv[level], out);
     });
 }
 

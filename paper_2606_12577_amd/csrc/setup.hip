@@ -551,6 +551,33 @@ __global__ void k_unscale(int64_t B, int nb, const double *__restrict__ w, const
     lam[e] = w[i * nb + r] * lamt[e] * w[i * nb + s];
 }
 
+// Lambda[ell][i] = W_i Lambda~[i][ell] W_i from the network's FP32 layout
+// [B][depth][nb][nb] into the FP64 master [depth][B][nb][nb]
+__global__ void k_unscale_learned(int64_t B, int nb, int depth, const double *__restrict__ w,
+                                  const float *__restrict__ lt, double *__restrict__ lam) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int nb2 = nb * nb;
+    if (e >= (int64_t)depth * B * nb2) return;
+    const int ell = (int)(e / (B * nb2));
+    const int64_t rem = e % (B * nb2);
+    const int64_t i = rem / nb2;
+    const int rs = (int)(rem % nb2), r = rs / nb, c = rs % nb;
+    lam[e] = w[i * nb + r] * (double)lt[(i * depth + ell) * nb2 + rs] * w[i * nb + c];
+}
+
+// Lambda~ = W^-1 Lambda W^-1 in the network's layout [B][depth][nb][nb]
+__global__ void k_prescaled_export(int64_t B, int nb, int depth, const double *__restrict__ w,
+                                   const double *__restrict__ lam, float *__restrict__ out) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int nb2 = nb * nb;
+    if (e >= (int64_t)depth * B * nb2) return;
+    const int64_t i = e / ((int64_t)depth * nb2);
+    const int64_t rem = e % ((int64_t)depth * nb2);
+    const int ell = (int)(rem / nb2);
+    const int rs = (int)(rem % nb2), r = rs / nb, c = rs % nb;
+    out[e] = (float)(lam[((int64_t)ell * B + i) * nb2 + rs] / (w[i * nb + r] * w[i * nb + c]));
+}
+
 // ---------------------------------------------------------------------------
 // colouring
 // ---------------------------------------------------------------------------
@@ -1082,6 +1109,49 @@ void run_setup(Ctx &c, const cs_options &o) {
     float ms = 0;
     CS_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
     c.setup_ms = ms;
+}
+
+namespace {
+void level_prescaling(Ctx &c, Level &L) {
+    if (L.w.n == (size_t)L.n) return;
+    L.w.alloc(L.n);
+    hipLaunchKernelGGL(k_prescale_w, dim3(grid_for(L.n)), dim3(WG), 0, c.stream, L.a_ptr.get(), L.a_col.get(),
+                       L.a_val.get(), L.n, L.w.get());
+    CS_LAUNCH_CHECK();
+}
+}  // namespace
+
+void prescaled_blocks(Ctx &c, Level &L, float *out) {
+    level_prescaling(c, L);
+    const int64_t tot = (int64_t)L.depth * L.B * L.nb * L.nb;
+    hipLaunchKernelGGL(k_prescaled_export, dim3(grid_for(tot)), dim3(WG), 0, c.stream, L.B, (int)L.nb, L.depth,
+                       L.w.get(), L.lam64.get(), out);
+    CS_LAUNCH_CHECK();
+    CS_HIP(hipStreamSynchronize(c.stream));
+}
+
+void run_setup_learned(Ctx &c, const cs_options &o, const float *lam_t) {
+    // lam_t is produced on c.stream before this call; timing covers it
+    Level &L0 = c.lv[0];
+    const int nb2 = (int)(L0.nb * L0.nb);
+    L0.w.release();
+    level_prescaling(c, L0);
+    L0.depth = o.depth;
+    L0.lam64.alloc((size_t)o.depth * L0.B * nb2);
+    const int64_t tot = (int64_t)o.depth * L0.B * nb2;
+    hipLaunchKernelGGL(k_unscale_learned, dim3(grid_for(tot)), dim3(WG), 0, c.stream, L0.B, (int)L0.nb, o.depth,
+                       L0.w.get(), lam_t, L0.lam64.get());
+    CS_LAUNCH_CHECK();
+    L0.patterns.clear();
+    L0.singular = 0;
+    L0.chi = 1;
+    c.singular = 0;
+    for (size_t l = 1; l + 1 < c.lv.size(); ++l) {
+        fit_level(c, c.lv[l], o);
+        c.singular += c.lv[l].singular;
+    }
+    for (Level &L : c.lv) factor_direct(c, L);
+    build_working_copies(c);
 }
 
 }  // namespace cs

@@ -7,11 +7,11 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "cascade.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("cascade.h", "cascade_learned.h")]
 
 
 def declared_functions():
-    text = open(HEADER).read()
+    text = "".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(cs_[a-z_0-9]+)\s*\(", text)))
 
