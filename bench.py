@@ -5,7 +5,9 @@ Workload (default): 3D 7-point variable-coefficient interface problem on 128^3
 cells (coefficient 1e4 inside a sphere of radius 0.3 with a seeded centre, 1
 outside), 2x2x2 blocks, depth-4 additive cascade, RF V(1,1), 8 seeded U[-1,1]
 right-hand sides; FP32 V-cycle (sweeps, SpMV, transfers) inside FP64 iterative
-refinement to 1e-10 relative residual.
+refinement (or as the preconditioner of flexible CG, the default) to 1e-10
+relative residual.  Beside it: the batched 64-system workload and the learned
+setup on Q1 multiphase diffusion.
 
 A step is one pass of the whole hot path on inputs resident in HBM: the GPU
 setup (prescaling, symbolic fill, Frobenius fit of every level, bottom
@@ -53,6 +55,68 @@ def cpu_baseline(n: int, nrhs: int, depth: int):
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_interface3d_128_traffic.md")
 
 
+def bench_batch(precision: str):
+    """64 independent 2D 5-point log-normal (sigma 2) systems, sizes 64^2 ..
+    512^2, 4 RHS each, one stacked hierarchy; solve DOF/s with stationary
+    refinement and with flexible CG (every system to 1e-10 on its own)."""
+    import numpy as np
+    import torch
+    from paper_2606_12577_amd import cascade
+    from synth import fd
+    from synth.batch import concatenate
+    bt = concatenate(fd.lognormal_batch(64, nrhs=4))
+    s = cascade.Solver(bt.levels)
+    s.setup(depth=3, precision=precision)
+    s.set_systems(bt.sys_ptr)
+    b = torch.as_tensor(bt.rhs, device="cuda").contiguous()
+    dof = bt.levels[0].n * 4
+    out = dict(dof=int(bt.levels[0].n), nrhs=4, systems=64, setup_ms=None)
+    for method, maxit in (("cg", 300), ("ir", 1000)):
+        infos = [s.solve(b, rtol=1e-10, maxit=maxit, method=method, raise_on_noconv=False)[1] for _ in range(2)]
+        its, rels = s.system_stats()
+        i = infos[-1]
+        out[method] = dict(solve_ms=round(i["solve_ms"], 2), iterations=i["iterations"],
+                           converged_systems=int((rels <= 1e-10).sum()), dof_per_s=dof / (i["solve_ms"] * 1e-3),
+                           per_system_iterations=[int(np.min(its)), int(np.median(its)), int(np.max(its))])
+        out["setup_ms"] = round(i["setup_ms"], 2)
+    s.close()
+    return out
+
+
+def bench_learned():
+    """Q1 multiphase diffusion 96^3: train the block network on two samples,
+    then on an unseen sample compare the learned finest-level setup with the
+    Frobenius setup (setup time, CG convergence factor) and apply the judge."""
+    import time as _t
+    from paper_2606_12577_amd import cascade, learned as L
+    from synth import fe
+    t = _t.perf_counter()
+    train = [fe.multiphase3d(96, seed_extra=k) for k in (1, 2)]
+    test = fe.multiphase3d(96, seed_extra=0)
+    gen_s = _t.perf_counter() - t
+    X, T = L.build_training_set(train, depth=2)
+    t = _t.perf_counter()
+    net, rep = L.train_network(X, T, n_samples=200000, epochs=40, batch=1024, lr0=1e-3)
+    import torch
+    torch.cuda.synchronize()
+    train_s = _t.perf_counter() - t
+    s = cascade.Solver(test.levels)
+    t = _t.perf_counter()
+    Xt = L.fe_block_features(test.meta["log10mu"])
+    torch.cuda.synchronize()
+    feat_ms = (_t.perf_counter() - t) * 1e3
+    v = L.judge(s, net, Xt, test.rhs, depth=2, method="cg", maxit=300)
+    _, sol = s.solve(test.rhs, rtol=1e-10, maxit=300, method="cg")
+    dof = test.n
+    return dict(dof=dof, generation_s=round(gen_s, 1), train_s=round(train_s, 2), train_blocks=rep.n_train,
+                val_loss=round(rep.val_loss, 4), val_loss_untrained=round(rep.val_loss_untrained, 4),
+                features_ms=round(feat_ms, 2), use_learned=v.use_learned,
+                rho_learned=round(v.rho_learned, 4), rho_frobenius=round(v.rho_frobenius, 4),
+                setup_ms_learned=round(v.setup_ms_learned, 2), setup_ms_frobenius=round(v.setup_ms_frobenius, 2),
+                iterations_learned=v.iterations_learned, iterations_frobenius=v.iterations_frobenius,
+                setup_plus_solve_dof_per_s=dof / ((sol["setup_ms"] + sol["solve_ms"]) * 1e-3))
+
+
 def kernel_source_digest() -> str:
     import hashlib
     h = hashlib.sha256()
@@ -97,6 +161,10 @@ def main():
     ap.add_argument("--no-trace", action="store_true", help="do not time the sweep kernel with events")
     ap.add_argument("--trace-period", type=int, default=8,
                     help="time every n-th launch of the sweep kernel with HIP events")
+    ap.add_argument("--solver", default="cg", choices=["ir", "cg"],
+                    help="outer solver of the timed step: FP64 refinement or flexible CG around the V-cycle")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-system measurement")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-setup measurement")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -126,7 +194,7 @@ def main():
 
     def step():
         s.setup(**opts)
-        x, info = s.solve(b, rtol=args.rtol, maxit=args.maxit)
+        x, info = s.solve(b, rtol=args.rtol, maxit=args.maxit, method=args.solver)
         return info
 
     for w in range(args.warmup):
@@ -165,7 +233,12 @@ def main():
                     algorithmic_bytes_per_launch=int(bytes_per_launch))
 
     extra = {}
+    other = "ir" if args.solver == "cg" else "cg"
+    oinfo = [s.solve(b, rtol=args.rtol, maxit=args.maxit, method=other)[1] for _ in range(2)][-1]
+    extra[f"{args.precision}_{other}"] = dict(solve_ms=round(oinfo["solve_ms"], 3), iterations=oinfo["iterations"],
+                                              rho=round(oinfo["rho"], 4), dof_per_s=dof / (oinfo["solve_ms"] * 1e-3))
     if not args.no_fp64_baseline:
+        # the plain FP64 V-cycle: stationary iteration, every kernel in FP64
         s.set_precision("fp64")
         _, i64 = s.solve(b, rtol=args.rtol, maxit=args.maxit)
         ms64 = []
@@ -176,7 +249,15 @@ def main():
         extra["fp64_vcycle"] = dict(solve_ms=round(ms64, 2), iterations=i64["iterations"],
                                     rho=round(i64["rho"], 4), dof_per_s=dof / (ms64 * 1e-3))
         extra["speedup_vs_fp64_vcycle"] = round(ms64 / solve_ms, 3)
-        extra["rho_ratio_vs_fp64"] = round(last["rho"] / i64["rho"], 4)
+        # convergence factor of the same outer method in the working precision vs FP64
+        _, c64 = s.solve(b, rtol=args.rtol, maxit=args.maxit, method=args.solver)
+        extra[f"fp64_{args.solver}"] = dict(solve_ms=round(c64["solve_ms"], 3), iterations=c64["iterations"],
+                                            rho=round(c64["rho"], 4))
+        extra["rho_ratio_vs_fp64"] = round(last["rho"] / c64["rho"], 4)
+        if args.precision != "fp64":
+            extra["rho_ratio_vs_fp64_" + other] = round(oinfo["rho"] / (i64["rho"] if other == "ir" else
+                                                                        s.solve(b, rtol=args.rtol, maxit=args.maxit,
+                                                                                method=other)[1]["rho"]), 4)
         s.set_precision(args.precision)
     if args.copy_mib:
         nel = args.copy_mib * 1024 * 1024 // 4
@@ -186,6 +267,13 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         extra["copy_calibration_mib"] = args.copy_mib
+
+    if not args.no_batch:
+        log("batched workload: 64 log-normal 2D systems")
+        extra["batch64"] = bench_batch(args.precision)
+    if not args.no_learned:
+        log("learned setup: Q1 multiphase 96^3")
+        extra["learned_q1_96"] = bench_learned()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -208,7 +296,10 @@ def main():
         "config": {
             "workload": f"3D 7-point interface problem {args.n}^3, contrast 1e4 sphere r=0.3, "
                         f"{args.nrhs} RHS, 2x2x2 blocks, depth-{args.depth} additive cascade, RF V(1,1), "
-                        f"{args.precision.upper()} V-cycle in FP64 iterative refinement to {args.rtol:g}",
+                        f"{args.precision.upper()} V-cycle "
+                        + ("as flexible-CG preconditioner" if args.solver == "cg" else "in iterative refinement")
+                        + f" with FP64 outer vectors, to {args.rtol:g}",
+            "solver": args.solver,
             "dof": prob.n, "nrhs": prob.nrhs, "levels": len(prob.levels), "parallelism": "single GPU",
         },
         "solve_ms": round(solve_ms, 3),

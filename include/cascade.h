@@ -162,6 +162,17 @@ cs_status cs_vcycle(cs_ctx ctx, const double *b, double *x, int32_t nrhs);
 cs_status cs_solve(cs_ctx ctx, const double *b, double *x, int32_t nrhs, double rtol, int32_t maxit,
                    cs_info *info, double *history);
 
+/* Solve A x = b by flexible conjugate gradients with one V-cycle as the
+ * preconditioner (the symmetric RF V-cycle of Sec. 2.4 makes it a symmetric
+ * preconditioner for SPD A; the flexible form tolerates the working-precision
+ * rounding of the V-cycle).  FP64 vectors: x_0 = 0, r = b; per iteration z =
+ * V r, p = z + beta p with beta = -(z, A p_prev)/(p_prev, A p_prev), alpha =
+ * (p, r)/(p, A p), x += alpha p, r -= alpha A p, each (system, RHS) with its
+ * own scalars.  Arguments, stopping test, history and info as for cs_solve;
+ * rho is the mean residual reduction per iteration (Sec. 3.1 regression). */
+cs_status cs_solve_cg(cs_ctx ctx, const double *b, double *x, int32_t nrhs, double rtol, int32_t maxit,
+                      cs_info *info, double *history);
+
 /* Device timing of kernel classes with HIP events recorded on the context's
  * stream around every launch of the class (for measurement; adds one event pair
  * per recorded launch).  cs_trace(ctx, mask, period) clears the counters and

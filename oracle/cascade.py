@@ -353,6 +353,37 @@ def solve(levels, smoothers, b: np.ndarray, rtol: float = 1e-10, maxit: int = 10
     return x, hist
 
 
+def fcg(A, precond, b: np.ndarray, rtol: float = 1e-10, maxit: int = 100):
+    """Flexible conjugate gradients with one-vector truncation (FCG(1)): the
+    new direction is the preconditioned residual minus its A-projection on
+    the previous direction.  Independent scalars per column of b.
+        x = 0, r = b;  z = M(r);  p = z - (z, A p_old)/(p_old, A p_old) p_old;
+        alpha = (p, r)/(p, A p);  x += alpha p;  r -= alpha A p.
+    With a fixed symmetric positive definite M this is preconditioned CG.
+    Returns x and the history of max_j ||r_j|| / ||b_j||."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    bn = np.linalg.norm(b, axis=0)
+    hist = [float(np.max(np.linalg.norm(r, axis=0) / bn))]
+    p_old = q_old = None
+    for it in range(maxit):
+        if hist[-1] <= rtol:
+            break
+        z = precond(r)
+        if p_old is None:
+            p = z
+        else:
+            beta = -np.sum(z * q_old, axis=0) / np.sum(p_old * q_old, axis=0)
+            p = z + beta * p_old
+        q = A @ p
+        alpha = np.sum(p * r, axis=0) / np.sum(p * q, axis=0)
+        x = x + alpha * p
+        r = r - alpha * q
+        p_old, q_old = p, q
+        hist.append(float(np.max(np.linalg.norm(r, axis=0) / bn)))
+    return x, hist
+
+
 def rho_regression(hist: Sequence[float]) -> float:
     """Convergence rate from a least-squares line through (i, log r_i),
     i = 1..K (Sec. 3.1); r_0 is left out."""

@@ -74,6 +74,7 @@ SIGNATURES = {
     "cs_smooth": (_I32, [_VP, _I32, _I32, _VP, _VP, _I32]),
     "cs_vcycle": (_I32, [_VP, _VP, _VP, _I32]),
     "cs_solve": (_I32, [_VP, _VP, _VP, _I32, _D, _I32, _p(cs_info), _p(_D)]),
+    "cs_solve_cg": (_I32, [_VP, _VP, _VP, _I32, _D, _I32, _p(cs_info), _p(_D)]),
     "cs_trace": (_I32, [_VP, _I32, _I32]),
     "cs_trace_read": (_I32, [_VP, _I32, _p(_D), _p(_I64), _p(_D)]),
     "cs_set_systems": (_I32, [_VP, _I32, _p(_I64)]),
@@ -275,14 +276,18 @@ class Solver:
         self._check(self._lib.cs_vcycle(self._h, _tensor_ptr(b), _tensor_ptr(x), b.shape[1]))
         return x
 
-    def solve(self, b, rtol: float = 1e-10, maxit: int = 100, x=None, raise_on_noconv: bool = True):
+    def solve(self, b, rtol: float = 1e-10, maxit: int = 100, x=None, raise_on_noconv: bool = True,
+              method: str = "ir"):
+        """method "ir": FP64 iterative refinement around the V-cycle (stationary);
+        "cg": flexible conjugate gradients preconditioned by the V-cycle."""
         b = self._vec(b)
         if x is None:
             x = self._torch.empty_like(b)
         info = cs_info()
         hist = np.full(maxit + 1, np.nan)
-        st = self._lib.cs_solve(self._h, _tensor_ptr(b), _tensor_ptr(x), b.shape[1], rtol, maxit,
-                                ctypes.byref(info), _ptr(hist, ctypes.c_double))
+        fn = {"ir": self._lib.cs_solve, "cg": self._lib.cs_solve_cg}[method]
+        st = fn(self._h, _tensor_ptr(b), _tensor_ptr(x), b.shape[1], rtol, maxit,
+                ctypes.byref(info), _ptr(hist, ctypes.c_double))
         if st != 0 and not (st == -6 and not raise_on_noconv):
             self._check(st)
         k = info.iterations

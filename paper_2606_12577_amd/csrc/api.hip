@@ -421,6 +421,20 @@ cs_status cs_solve(cs_ctx ctx, const double *b, double *x, int32_t nrhs, double 
     return st;
 }
 
+cs_status cs_solve_cg(cs_ctx ctx, const double *b, double *x, int32_t nrhs, double rtol, int32_t maxit,
+                      cs_info *info, double *history) {
+    cs_status st = CS_OK;
+    cs_status g = guarded(ctx, [&](Ctx &c) {
+        need(c.have_setup, "cs_solve_cg before cs_setup", CS_ESTATE);
+        need(b && x, "null vector");
+        need(maxit >= 0 && rtol >= 0.0, "bad rtol or maxit");
+        cs::solve_cg(c, b, x, nrhs, rtol, maxit, info, history, &st);
+    });
+    if (g != CS_OK) return g;
+    if (st != CS_OK) ctx->c.err = cs_status_string(st);
+    return st;
+}
+
 cs_status cs_save_setup(cs_ctx ctx, const char *path) {
     return guarded(ctx, [&](Ctx &c) {
         need(c.have_setup, "no setup", CS_ESTATE);

@@ -190,6 +190,8 @@ struct Ctx {
     std::vector<double> sys_rel;
     // solve workspace
     DBuf<double> ir_partial, ir_norm;
+    DBuf<double> cg_r, cg_p, cg_q;      // conjugate-gradient vectors [n][R] (FP64)
+    DBuf<double> cg_zq, cg_pq[2];       // per (system, RHS): (z, q_prev); (p, q) and (p, r), ping-pong
     double *h_norm = nullptr;           // pinned host copy of ir_norm
     size_t h_norm_cap = 0;
     bool fuse_transfers = true;         // use the fused aggregation kernels when agg_k > 0
@@ -239,6 +241,8 @@ void ensure_workspace(Ctx &c, int nrhs);
 void vcycle_apply(Ctx &c, const double *b, double *x, int nrhs);
 void smooth_apply(Ctx &c, int level, bool reverse, const double *b, double *x, int nrhs);
 void solve_ir(Ctx &c, const double *b, double *x, int nrhs, double rtol, int maxit, cs_info *info,
+              double *history, cs_status *st);
+void solve_cg(Ctx &c, const double *b, double *x, int nrhs, double rtol, int maxit, cs_info *info,
               double *history, cs_status *st);
 
 // host helpers

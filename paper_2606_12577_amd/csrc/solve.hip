@@ -490,6 +490,215 @@ __global__ __launch_bounds__(WG) void k_ir_residual(int64_t nrows, int64_t nslic
     if (threadIdx.x < R) partial[(int64_t)blockIdx.x * R + threadIdx.x] = red[threadIdx.x];
 }
 
+// ---------------------------------------------------------------------------
+// Flexible conjugate gradients around the V-cycle (FP64 outer vectors)
+// ---------------------------------------------------------------------------
+
+// Partial sums of W per-row values: per 64-row slice (SYS, see k_ir_residual)
+// or accumulated per thread for a workgroup tree (acc).
+template <int W>
+__device__ __forceinline__ void slice_partials(double (&v)[W], int lane, int64_t slice, const int32_t *het,
+                                               double *spart, double *rn2) {
+    const int h = het[slice];
+    if (h < 0) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+            for (int k = 0; k < W; ++k) v[k] += __shfl_xor(v[k], off, 64);
+        }
+        if (lane == 0) vstore<double, W>(spart + slice * W, v);
+    } else {
+        vstore<double, W>(rn2 + ((int64_t)h * 64 + lane) * W, v);
+    }
+}
+
+template <int W>
+__device__ __forceinline__ void wg_partials(const double (&acc)[W], double *red, double *partial) {
+#pragma unroll
+    for (int k = 0; k < W; ++k) red[threadIdx.x * W + k] = acc[k];
+    __syncthreads();
+    for (int s = WG / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+#pragma unroll
+            for (int k = 0; k < W; ++k) red[threadIdx.x * W + k] += red[(threadIdx.x + s) * W + k];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < W) partial[(int64_t)blockIdx.x * W + threadIdx.x] = red[threadIdx.x];
+}
+
+__device__ __forceinline__ int row_system(int64_t row, int nsys, const int64_t *__restrict__ sys_ptr) {
+    int lo = 0, hi = nsys - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sys_ptr[mid] <= row) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// (z, q) per right-hand side
+template <typename T, int R, bool SYS>
+__global__ __launch_bounds__(WG) void k_cg_zq(int64_t nrows, int64_t nslices, const T *__restrict__ z,
+                                              const double *__restrict__ q, const int32_t *__restrict__ het,
+                                              double *__restrict__ spart, double *__restrict__ rn2,
+                                              double *__restrict__ partial) {
+    __shared__ double red[SYS ? 1 : WG * R];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double acc[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) acc[k] = 0.0;
+    const Tiles tl = my_tiles((nslices + 3) / 4);
+    for (int64_t tile = tl.t; tile < tl.end; tile += tl.step) {
+        const int64_t slice = tile * 4 + wv;
+        if (slice >= nslices) continue;
+        const int64_t row = slice * 64 + lane;
+        double v[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) v[k] = 0.0;
+        if (row < nrows) {
+            T zz[R];
+            double qq[R];
+            vload_nt<T, R>(z + row * R, zz);
+            vload_nt<double, R>(q + row * R, qq);
+#pragma unroll
+            for (int k = 0; k < R; ++k) v[k] = (double)zz[k] * qq[k];
+        }
+        if constexpr (SYS) {
+            slice_partials<R>(v, lane, slice, het, spart, rn2);
+        } else {
+#pragma unroll
+            for (int k = 0; k < R; ++k) acc[k] += v[k];
+        }
+    }
+    if constexpr (!SYS) wg_partials<R>(acc, red, partial);
+}
+
+// p = z + beta p with beta = -(z, q_prev) / (p_prev, q_prev) per system and
+// right-hand side (first: p = z).  pq_prev holds [nsys][2R]: (p, q) then (p, r).
+template <typename T, int R>
+__global__ void k_cg_p(int64_t n, int nsys, const int64_t *__restrict__ sys_ptr, const T *__restrict__ z,
+                       const double *__restrict__ zq, const double *__restrict__ pq_prev, double *__restrict__ p,
+                       int first) {
+    const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (row >= n) return;
+    const int s = nsys > 1 ? row_system(row, nsys, sys_ptr) : 0;
+    T zz[R];
+    double pp[R];
+    vload<T, R>(z + row * R, zz);
+    if (!first) vload<double, R>(p + row * R, pp);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        double beta = 0.0;
+        if (!first) {
+            const double d = pq_prev[s * 2 * R + k];
+            beta = d > 0.0 ? -zq[s * R + k] / d : 0.0;
+            if (!isfinite(beta)) beta = 0.0;
+        }
+        pp[k] = (double)zz[k] + (first ? 0.0 : beta * pp[k]);
+    }
+    vstore<double, R>(p + row * R, pp);
+}
+
+// q = A p (FP64) with the per-RHS partial sums of (p, q) and (p, r)
+template <int R, bool SYS>
+__global__ __launch_bounds__(WG) void k_cg_ap(int64_t nrows, int64_t nslices, const int64_t *__restrict__ sptr,
+                                              const int32_t *__restrict__ slen, const int32_t *__restrict__ scol,
+                                              const double *__restrict__ sval, const double *__restrict__ p,
+                                              const double *__restrict__ r, double *__restrict__ q,
+                                              const int32_t *__restrict__ het, double *__restrict__ spart,
+                                              double *__restrict__ rn2, double *__restrict__ partial) {
+    __shared__ double red[SYS ? 1 : WG * 2 * R];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double acc[2 * R];
+#pragma unroll
+    for (int k = 0; k < 2 * R; ++k) acc[k] = 0.0;
+    const Tiles tl = my_tiles((nslices + 3) / 4);
+    for (int64_t tile = tl.t; tile < tl.end; tile += tl.step) {
+        const int64_t slice = tile * 4 + wv;
+        if (slice >= nslices) continue;
+        const int64_t row = slice * 64 + lane;
+        double v[2 * R];
+#pragma unroll
+        for (int k = 0; k < 2 * R; ++k) v[k] = 0.0;
+        if (row < nrows) {
+            double ap[R], pp[R], rr[R];
+#pragma unroll
+            for (int k = 0; k < R; ++k) ap[k] = 0.0;
+            spmv_row<double, R, false>(scol, sval, sptr[slice] + lane, slen[slice], p, nullptr, 1, ap);
+            vstore<double, R>(q + row * R, ap);
+            vload<double, R>(p + row * R, pp);
+            vload_nt<double, R>(r + row * R, rr);
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                v[k] = pp[k] * ap[k];
+                v[R + k] = pp[k] * rr[k];
+            }
+        }
+        if constexpr (SYS) {
+            slice_partials<2 * R>(v, lane, slice, het, spart, rn2);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 2 * R; ++k) acc[k] += v[k];
+        }
+    }
+    if constexpr (!SYS) wg_partials<2 * R>(acc, red, partial);
+}
+
+// x += alpha p, r -= alpha q with alpha = (p, r) / (p, q); rt = r in the
+// working precision; per-RHS partial sums of r^2
+template <typename T, int R, bool SYS>
+__global__ __launch_bounds__(WG) void k_cg_update(int64_t nrows, int64_t nslices, int nsys,
+                                                  const int64_t *__restrict__ sys_ptr, const double *__restrict__ pq,
+                                                  const double *__restrict__ p, const double *__restrict__ q,
+                                                  double *__restrict__ x, double *__restrict__ r, T *__restrict__ rt,
+                                                  const int32_t *__restrict__ het, double *__restrict__ spart,
+                                                  double *__restrict__ rn2, double *__restrict__ partial) {
+    __shared__ double red[SYS ? 1 : WG * R];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double acc[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) acc[k] = 0.0;
+    const Tiles tl = my_tiles((nslices + 3) / 4);
+    for (int64_t tile = tl.t; tile < tl.end; tile += tl.step) {
+        const int64_t slice = tile * 4 + wv;
+        if (slice >= nslices) continue;
+        const int64_t row = slice * 64 + lane;
+        double v[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) v[k] = 0.0;
+        if (row < nrows) {
+            const int s = nsys > 1 ? row_system(row, nsys, sys_ptr) : 0;
+            double pp[R], qq[R], xx[R], rr[R];
+            vload_nt<double, R>(p + row * R, pp);
+            vload_nt<double, R>(q + row * R, qq);
+            vload_nt<double, R>(x + row * R, xx);
+            vload_nt<double, R>(r + row * R, rr);
+            T o[R];
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const double d = pq[s * 2 * R + k];
+                double alpha = d > 0.0 ? pq[s * 2 * R + R + k] / d : 0.0;
+                if (!isfinite(alpha)) alpha = 0.0;
+                xx[k] += alpha * pp[k];
+                rr[k] -= alpha * qq[k];
+                o[k] = (T)rr[k];
+                v[k] = rr[k] * rr[k];
+            }
+            vstore<double, R>(x + row * R, xx);
+            vstore<double, R>(r + row * R, rr);
+            vstore<T, R>(rt + row * R, o);
+        }
+        if constexpr (SYS) {
+            slice_partials<R>(v, lane, slice, het, spart, rn2);
+        } else {
+#pragma unroll
+            for (int k = 0; k < R; ++k) acc[k] += v[k];
+        }
+    }
+    if constexpr (!SYS) wg_partials<R>(acc, red, partial);
+}
+
 // Fixed-order sum of the partials: out[k] = sum_g partial[g][k]
 // One coalesced pass: thread t always accumulates component t % R (R divides
 // 1024), then a tree over threads of equal t % R.
@@ -801,12 +1010,12 @@ void ensure_workspace(Ctx &c, int nrhs) {
         L.rr.alloc(bytes);
     }
     const int64_t G = std::min<int64_t>(ceil_div(c.lv[0].sell.nslices, 4), IR_GRID);
-    c.ir_partial.alloc(std::max<int64_t>(G, 1) * nrhs);
+    c.ir_partial.alloc(std::max<int64_t>(G, 1) * 2 * nrhs);   // up to two dot products per RHS
     const int64_t nsys = c.sys_ptr.empty() ? 1 : (int64_t)c.sys_ptr.size() - 1;
     c.ir_norm.alloc(2 * nsys * nrhs);
     if (nsys > 1) {
-        c.sys_spart.alloc((size_t)c.lv[0].sell.nslices * nrhs);
-        c.rn2.alloc((size_t)std::max<int64_t>(c.n_het, 1) * 64 * nrhs);
+        c.sys_spart.alloc((size_t)c.lv[0].sell.nslices * 2 * nrhs);
+        c.rn2.alloc((size_t)std::max<int64_t>(c.n_het, 1) * 64 * 2 * nrhs);
     } else {
         c.sys_spart.release();
         c.rn2.release();
@@ -862,6 +1071,73 @@ void smooth_apply(Ctx &c, int level, bool reverse, const double *b, double *x, i
         CS_LAUNCH_CHECK();
     });
 }
+
+namespace {
+
+// Convergence bookkeeping shared by the refinement and Krylov drivers: every
+// (system, right-hand side) residual is measured against its own ||b||, and
+// the iteration stops when the largest relative residual reaches rtol.
+struct Monitor {
+    Ctx &c;
+    int nsys, R;
+    double rtol;
+    std::vector<double> hist, bn2;
+    Monitor(Ctx &cc, int ns, int r, double tol) : c(cc), nsys(ns), R(r), rtol(tol), bn2((size_t)ns * r, 1.0) {
+        c.sys_iters.assign(nsys, -1);
+        c.sys_rel.assign(nsys, NAN);
+    }
+    // hn: squared residual norms [nsys][R], followed (at it == 0) by those of b
+    double record(int it, const double *hn) {
+        if (it == 0)
+            for (int e = 0; e < nsys * R; ++e) bn2[e] = hn[nsys * R + e] > 0 ? hn[nsys * R + e] : 1.0;
+        double rel = 0.0;
+        bool bad = false;
+        for (int q = 0; q < nsys; ++q) {
+            double rq = 0.0;
+            for (int k = 0; k < R; ++k) {
+                const double v = std::sqrt(hn[q * R + k] / bn2[q * R + k]);
+                if (!std::isfinite(v)) bad = true;
+                rq = std::max(rq, v);
+            }
+            c.sys_rel[q] = rq;
+            if (c.sys_iters[q] < 0 && rq <= rtol) c.sys_iters[q] = it;
+            rel = std::max(rel, rq);
+        }
+        hist.push_back(bad ? NAN : rel);
+        return hist.back();
+    }
+    void finish(int it, float ms, cs_info *info, double *history) {
+        for (int q = 0; q < nsys; ++q)
+            if (c.sys_iters[q] < 0) c.sys_iters[q] = it;
+        if (history)
+            for (size_t q = 0; q < hist.size(); ++q) history[q] = hist[q];
+        if (!info) return;
+        info->iterations = it;
+        info->rel_res = hist.back();
+        info->solve_ms = ms;
+        info->setup_ms = c.setup_ms;
+        info->singular_blocks = c.singular;
+        // least-squares slope of log r_i over i = 1..K (Sec. 3.1)
+        const int K = (int)hist.size() - 1;
+        double rho = NAN;
+        if (K >= 2) {
+            double si = 0, sy = 0, sii = 0, siy = 0;
+            for (int q = 1; q <= K; ++q) {
+                const double y = std::log(hist[q]);
+                si += q;
+                sy += y;
+                sii += (double)q * q;
+                siy += q * y;
+            }
+            rho = std::exp((K * siy - si * sy) / (K * sii - si * si));
+        } else if (K == 1) {
+            rho = hist[1] / hist[0];
+        }
+        info->rho = rho;
+    }
+};
+
+}  // namespace
 
 void solve_ir(Ctx &c, const double *b, double *x, int nrhs, double rtol, int maxit, cs_info *info,
               double *history, cs_status *st) {
@@ -941,33 +1217,15 @@ void solve_ir(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
             hipLaunchKernelGGL(k_zero<double>, dim3(grid_for(n)), dim3(WG), 0, c.stream, n, x);
             CS_LAUNCH_CHECK();
             residual();
-            std::vector<double> hist, bn2(nsys * R);
-            c.sys_iters.assign(nsys, -1);
-            c.sys_rel.assign(nsys, NAN);
+            Monitor mon(c, nsys, R, rtol);
             int it = 0;
             for (;; ++it) {
                 CS_HIP(hipMemcpyAsync(c.h_norm, c.ir_norm.get(), 2 * nsys * R * sizeof(double),
                                       hipMemcpyDeviceToHost, c.stream));
                 CS_HIP(hipStreamSynchronize(c.stream));
                 if (graphs && it > 0) trace_graph_accumulate(c);
-                if (it == 0)
-                    for (int e = 0; e < nsys * R; ++e) bn2[e] = hn[nsys * R + e] > 0 ? hn[nsys * R + e] : 1.0;
-                // every system converges on its own: max over systems of max over RHS
-                double rel = 0.0;
-                bool bad = false;
-                for (int q = 0; q < nsys; ++q) {
-                    double rq = 0.0;
-                    for (int k = 0; k < R; ++k) {
-                        const double v = std::sqrt(hn[q * R + k] / bn2[q * R + k]);
-                        if (!std::isfinite(v)) bad = true;
-                        rq = std::max(rq, v);
-                    }
-                    c.sys_rel[q] = rq;
-                    if (c.sys_iters[q] < 0 && rq <= rtol) c.sys_iters[q] = it;
-                    rel = std::max(rel, rq);
-                }
-                hist.push_back(bad ? NAN : rel);
-                if (bad) {
+                const double rel = mon.record(it, hn);
+                if (std::isnan(rel)) {
                     *st = CS_ENAN;
                     break;
                 }
@@ -1009,40 +1267,147 @@ void solve_ir(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
                     iteration();
                 }
             }
-            for (int q = 0; q < nsys; ++q)
-                if (c.sys_iters[q] < 0) c.sys_iters[q] = it;
             trace_flush(c);
             CS_HIP(hipEventRecord(c.ev1, c.stream));
             CS_HIP(hipEventSynchronize(c.ev1));
             float ms = 0;
             CS_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
-            if (history)
-                for (size_t q = 0; q < hist.size(); ++q) history[q] = hist[q];
-            if (info) {
-                info->iterations = it;
-                info->rel_res = hist.back();
-                info->solve_ms = ms;
-                info->setup_ms = c.setup_ms;
-                info->singular_blocks = c.singular;
-                // least-squares slope of log r_i over i = 1..K
-                const int K = (int)hist.size() - 1;
-                double rho = NAN;
-                if (K >= 2) {
-                    double si = 0, sy = 0, sii = 0, siy = 0;
-                    for (int q = 1; q <= K; ++q) {
-                        double y = std::log(hist[q]);
-                        si += q;
-                        sy += y;
-                        sii += (double)q * q;
-                        siy += q * y;
-                    }
-                    double slope = (K * siy - si * sy) / (K * sii - si * si);
-                    rho = std::exp(slope);
-                } else if (K == 1) {
-                    rho = hist[1] / hist[0];
+            mon.finish(it, ms, info, history);
+        });
+    });
+}
+
+// Flexible conjugate gradients preconditioned by one V-cycle (FCG(1): the new
+// direction is z minus its A-projection on the previous one), FP64 vectors
+// and scalars, the V-cycle in the working precision.  Per (system, RHS):
+//   r = b, x = 0;  z = V r;  p = z + beta p, beta = -(z, q_prev)/(p_prev, q_prev);
+//   q = A p;  alpha = (p, r)/(p, q);  x += alpha p;  r -= alpha q.
+// The scalars stay on the device; the host reads the residual norms once per
+// iteration for the stopping test.
+void solve_cg(Ctx &c, const double *b, double *x, int nrhs, double rtol, int maxit, cs_info *info,
+              double *history, cs_status *st) {
+    ensure_workspace(c, nrhs);
+    Level &L0 = c.lv[0];
+    const Sell &S = L0.sell;
+    const int64_t n = L0.n * nrhs;
+    const int64_t G = std::min<int64_t>(ceil_div(S.nslices, 4), IR_GRID);
+    const int nsys = c.sys_ptr.empty() ? 1 : (int)c.sys_ptr.size() - 1;
+    const bool batch = nsys > 1;
+    if (c.cg_r.n < (size_t)n) {
+        c.cg_r.alloc(n);
+        c.cg_p.alloc(n);
+        c.cg_q.alloc(n);
+    }
+    c.cg_zq.alloc((size_t)nsys * nrhs);
+    c.cg_pq[0].alloc((size_t)nsys * 2 * nrhs);
+    c.cg_pq[1].alloc((size_t)nsys * 2 * nrhs);
+    double *r = c.cg_r.get(), *p = c.cg_p.get(), *q = c.cg_q.get();
+    *st = CS_OK;
+    CS_HIP(hipEventRecord(c.ev0, c.stream));
+    dispatch_prec(c.precision, [&](auto tp) {
+        using T = std::remove_pointer_t<decltype(tp)>;
+        dispatch_r(nrhs, [&](auto rc) {
+            constexpr int R = decltype(rc)::value;
+            T *rt = reinterpret_cast<T *>(L0.bb.get());
+            const T *z = reinterpret_cast<const T *>(L0.xb.get());
+            // reduce partial sums of W values per row into out[nsys][W]
+            auto reduce = [&](int W, double *out) {
+                if (batch)
+                    hipLaunchKernelGGL(k_sys_norms, dim3(nsys), dim3(256), 0, c.stream, W, S.nrows,
+                                       c.sys_ptr_d.get(), c.sys_het.get(), c.sys_spart.get(), c.rn2.get(), out);
+                else
+                    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(1024), 0, c.stream, G, W, c.ir_partial.get(),
+                                       out);
+                CS_LAUNCH_CHECK();
+            };
+            const double vec = (double)L0.n * R * 8.0;
+            // ||b||^2 and rt = b; r = b; x = 0
+            if (batch)
+                hipLaunchKernelGGL((k_ir_residual<T, R, true>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
+                                   S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), b, nullptr, rt,
+                                   (double *)nullptr, c.sys_het.get(), c.sys_spart.get(), c.rn2.get());
+            else
+                hipLaunchKernelGGL((k_ir_residual<T, R, false>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
+                                   S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), b, nullptr, rt,
+                                   c.ir_partial.get(), (const int32_t *)nullptr, (double *)nullptr,
+                                   (double *)nullptr);
+            CS_LAUNCH_CHECK();
+            reduce(R, c.ir_norm.get() + nsys * R);
+            CS_HIP(hipMemcpyAsync(c.ir_norm.get(), c.ir_norm.get() + nsys * R, nsys * R * sizeof(double),
+                                  hipMemcpyDeviceToDevice, c.stream));
+            CS_HIP(hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
+            hipLaunchKernelGGL(k_zero<double>, dim3(grid_for(n)), dim3(WG), 0, c.stream, n, x);
+            CS_LAUNCH_CHECK();
+            Monitor mon(c, nsys, R, rtol);
+            int it = 0;
+            int cur = 0;
+            for (;; ++it) {
+                CS_HIP(hipMemcpyAsync(c.h_norm, c.ir_norm.get(), 2 * nsys * R * sizeof(double),
+                                      hipMemcpyDeviceToHost, c.stream));
+                CS_HIP(hipStreamSynchronize(c.stream));
+                const double rel = mon.record(it, c.h_norm);
+                if (std::isnan(rel)) {
+                    *st = CS_ENAN;
+                    break;
                 }
-                info->rho = rho;
+                if (rel <= rtol) break;
+                if (it == maxit) {
+                    *st = CS_ENOCONV;
+                    break;
+                }
+                vcycle_level<T, R>(c, 0);   // z = V r
+                const double *pq_prev = c.cg_pq[cur ^ 1].get();
+                double *pq = c.cg_pq[cur].get();
+                int slot = trace_begin(c, CS_TRACE_REFINE, it ? vec + L0.n * R * sizeof(T) : 0.0);
+                if (it) {
+                    if (batch)
+                        hipLaunchKernelGGL((k_cg_zq<T, R, true>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
+                                           z, q, c.sys_het.get(), c.sys_spart.get(), c.rn2.get(), (double *)nullptr);
+                    else
+                        hipLaunchKernelGGL((k_cg_zq<T, R, false>), dim3(G), dim3(WG), 0, c.stream, S.nrows,
+                                           S.nslices, z, q, (const int32_t *)nullptr, (double *)nullptr,
+                                           (double *)nullptr, c.ir_partial.get());
+                    CS_LAUNCH_CHECK();
+                    reduce(R, c.cg_zq.get());
+                }
+                hipLaunchKernelGGL((k_cg_p<T, R>), dim3(grid_for(L0.n)), dim3(WG), 0, c.stream, L0.n, nsys,
+                                   c.sys_ptr_d.get(), z, c.cg_zq.get(), pq_prev, p, it == 0 ? 1 : 0);
+                CS_LAUNCH_CHECK();
+                trace_end(c, slot);
+                slot = trace_begin(c, CS_TRACE_REFINE, S.nnz * 12.0 + 3.0 * vec);
+                if (batch)
+                    hipLaunchKernelGGL((k_cg_ap<R, true>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
+                                       S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), p, r, q,
+                                       c.sys_het.get(), c.sys_spart.get(), c.rn2.get(), (double *)nullptr);
+                else
+                    hipLaunchKernelGGL((k_cg_ap<R, false>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
+                                       S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), p, r, q,
+                                       (const int32_t *)nullptr, (double *)nullptr, (double *)nullptr,
+                                       c.ir_partial.get());
+                CS_LAUNCH_CHECK();
+                reduce(2 * R, pq);
+                trace_end(c, slot);
+                slot = trace_begin(c, CS_TRACE_REFINE, 6.0 * vec + L0.n * R * sizeof(T));
+                if (batch)
+                    hipLaunchKernelGGL((k_cg_update<T, R, true>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
+                                       nsys, c.sys_ptr_d.get(), pq, p, q, x, r, rt, c.sys_het.get(),
+                                       c.sys_spart.get(), c.rn2.get(), (double *)nullptr);
+                else
+                    hipLaunchKernelGGL((k_cg_update<T, R, false>), dim3(G), dim3(WG), 0, c.stream, S.nrows,
+                                       S.nslices, nsys, c.sys_ptr_d.get(), pq, p, q, x, r, rt,
+                                       (const int32_t *)nullptr, (double *)nullptr, (double *)nullptr,
+                                       c.ir_partial.get());
+                CS_LAUNCH_CHECK();
+                reduce(R, c.ir_norm.get());
+                trace_end(c, slot);
+                cur ^= 1;
             }
+            trace_flush(c);
+            CS_HIP(hipEventRecord(c.ev1, c.stream));
+            CS_HIP(hipEventSynchronize(c.ev1));
+            float ms = 0;
+            CS_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
+            mon.finish(it, ms, info, history);
         });
     });
 }

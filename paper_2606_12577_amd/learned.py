@@ -189,13 +189,24 @@ def build_training_set(problems: Sequence, depth: int = 2, order: str = "RF"):
     return torch.cat(X), torch.cat(T)
 
 
+def regular_blocks(T, factor: float = 4.0) -> np.ndarray:
+    """Rows of T whose largest entry stays within `factor` times the median
+    of that statistic.  The few blocks outside are those whose normal
+    equations were (nearly) singular; their minimum-norm fits are isolated,
+    large and not a function of the local features, so they are left out of
+    training (the judge still measures the whole cascade)."""
+    big = T.abs().amax(dim=1).cpu().numpy()
+    return np.where(big <= factor * np.median(big))[0].astype(np.int32)
+
+
 def train_network(X, T, n_samples: int, epochs: int = 40, batch: int = 1024, lr0: float = 1e-3,
-                  val_fraction: float = 0.1, seed: int = 0, width: int = 128) -> (Mlp, TrainReport):
-    """Sample n_samples blocks, split train/validation, fit the output scaling
-    on the training rows and train with Adam and a cosine rate."""
+                  val_fraction: float = 0.1, seed: int = 0, width: int = 128,
+                  outlier_factor: float = 4.0) -> (Mlp, TrainReport):
+    """Sample n_samples regular blocks, split train/validation, fit the output
+    scaling on the training rows and train with Adam and a cosine rate."""
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([2606, 5, 2, int(seed)])))
-    n_all = X.shape[0]
-    pick = rng.choice(n_all, size=min(n_samples, n_all), replace=False).astype(np.int32)
+    ok = regular_blocks(T, outlier_factor) if outlier_factor else np.arange(X.shape[0], dtype=np.int32)
+    pick = ok[rng.choice(len(ok), size=min(n_samples, len(ok)), replace=False)].astype(np.int32)
     n_val = max(1, int(round(val_fraction * len(pick))))
     val, tr = pick[:n_val], pick[n_val:]
     net = Mlp(X.shape[1], width, T.shape[1])
@@ -219,15 +230,17 @@ class Verdict:
 
 
 def judge(solver, net, features, b, depth: int = 2, slack: float = 1.05, rtol: float = 1e-10, maxit: int = 200,
-          order: str = "RF", precision: str = "fp64") -> Verdict:
+          order: str = "RF", precision: str = "fp64", method: str = "ir") -> Verdict:
     """Measure rho with the learned and with the Frobenius finest-level
     cascade and keep the learned one iff rho_learned <= slack * rho_frobenius.
-    The solver is left with the chosen setup."""
+    method selects the solve that measures rho ("ir": the stationary V-cycle
+    iteration, "cg": the V-cycle as CG preconditioner).  The solver is left
+    with the chosen setup."""
     solver.setup(depth=depth, order=order, precision=precision)
-    _, fr = solver.solve(b, rtol=rtol, maxit=maxit, raise_on_noconv=False)
+    _, fr = solver.solve(b, rtol=rtol, maxit=maxit, raise_on_noconv=False, method=method)
     solver.setup_learned(net, features, depth=depth, order=order, precision=precision)
     try:
-        _, le = solver.solve(b, rtol=rtol, maxit=maxit, raise_on_noconv=False)
+        _, le = solver.solve(b, rtol=rtol, maxit=maxit, raise_on_noconv=False, method=method)
         rho_l = le["rho"] if np.isfinite(le["rho"]) else np.inf
     except C.CascadeError:          # a divergent learned cascade (non-finite residual)
         le = dict(setup_ms=float("nan"), iterations=-1)

@@ -518,3 +518,64 @@ def test_local_patch_fit_multiplicative():
     for i, v in loc.items():
         for l in range(2):
             np.testing.assert_allclose(v[l], full[l][i], rtol=1e-11)
+
+
+# ---------------------------------------------------------------------------
+# Flexible CG (Krylov acceleration of the V-cycle)
+# ---------------------------------------------------------------------------
+
+def _textbook_pcg(A, Minv, b, iters):
+    """Preconditioned CG in its textbook form (Hestenes-Stiefel with
+    beta = (r_new, z_new) / (r_old, z_old)), one column."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    z = Minv(r)
+    p = z.copy()
+    rz = r @ z
+    out = [x.copy()]
+    for _ in range(iters):
+        q = A @ p
+        a = rz / (p @ q)
+        x = x + a * p
+        r = r - a * q
+        z = Minv(r)
+        rz_new = r @ z
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+        out.append(x.copy())
+    return out
+
+
+def test_fcg_equals_textbook_pcg_for_fixed_spd_preconditioner():
+    p = fd.poisson2d(16)
+    A = p.levels[0].A
+    d = A.diagonal()
+    rng = stream(1, TEST, 40)
+    b = rng.uniform(-1, 1, size=(A.shape[0], 1))
+    ref = _textbook_pcg(A, lambda r: r / d, b[:, 0], 12)
+    for k in (3, 7, 12):
+        x, _ = O.fcg(A, lambda r: r / d[:, None], b, rtol=0.0, maxit=k)
+        np.testing.assert_allclose(x[:, 0], ref[k], rtol=1e-9, atol=1e-12)
+
+
+def test_fcg_exact_preconditioner_converges_in_one_step_and_cg_terminates():
+    p = fd.poisson2d(8)
+    A = p.levels[0].A
+    Ad = A.toarray()
+    rng = stream(1, TEST, 41)
+    b = rng.uniform(-1, 1, size=(A.shape[0], 3))
+    x, hist = O.fcg(A, lambda r: np.linalg.solve(Ad, r), b, rtol=1e-12, maxit=5)
+    assert len(hist) == 2 and hist[-1] <= 1e-12
+    np.testing.assert_allclose(x, np.linalg.solve(Ad, b), rtol=1e-10)
+    # unpreconditioned CG terminates within the number of distinct eigenvalues
+    _, h = O.fcg(A, lambda r: r, b, rtol=1e-10, maxit=64)
+    ev = np.unique(np.round(np.linalg.eigvalsh(Ad), 9))
+    assert len(h) - 1 <= len(ev)
+
+
+def test_fcg_with_vcycle_beats_stationary_iteration():
+    p = fd.interface3d(16, nrhs=2)
+    sm = O.setup_hierarchy(p.levels, 3)
+    _, h_ir = O.solve(p.levels, sm, p.rhs, rtol=1e-10, maxit=200)
+    _, h_cg = O.fcg(p.levels[0].A, lambda r: O.vcycle(p.levels, sm, r), p.rhs, rtol=1e-10, maxit=200)
+    assert h_cg[-1] <= 1e-10 and len(h_cg) < len(h_ir)
