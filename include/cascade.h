@@ -59,7 +59,11 @@ typedef enum {
 
 typedef enum { CS_ADDITIVE = 0, CS_MULTIPLICATIVE = 1 } cs_mode;   /* Sec. 2.1 / 2.2 */
 typedef enum { CS_FF = 0, CS_RF = 1 } cs_order;   /* pre-smoother forward / reverse; post is forward (Sec. 2.4) */
-typedef enum { CS_FP64 = 0, CS_FP32 = 1, CS_BF16 = 2 } cs_precision;  /* V-cycle working precision */
+/* V-cycle working precision.  CS_BF16: FP32 vectors and arithmetic, with A and
+ * Lambda of 16x16-block levels stored in BF16 and applied on the matrix cores
+ * (FP32 accumulation) in the multicoloured sweeps and the residual when the
+ * solve has one right-hand side; everything else as CS_FP32. */
+typedef enum { CS_FP64 = 0, CS_FP32 = 1, CS_BF16 = 2 } cs_precision;
 
 /* One level of the geometric hierarchy (Sec. 2.4); levels[0] is the finest and
  * the last level is solved directly.  All pointers are host pointers. */
@@ -103,6 +107,7 @@ typedef struct {
     double setup_ms;            /* device time of the last cs_setup */
     double solve_ms;            /* device time of this solve */
     int32_t singular_blocks;    /* blocks solved by the pseudo-inverse fallback in the last setup */
+    int32_t precision;          /* cs_precision the solve finished in (raised on divergence) */
 } cs_info;
 
 /* Library identity. */
@@ -157,6 +162,9 @@ cs_status cs_vcycle(cs_ctx ctx, const double *b, double *x, int32_t nrhs);
 
 /* Solve A x = b by FP64 iterative refinement around the V-cycle: x_0 = 0;
  * r = b - A x (FP64); stop when max_j ||r_j|| <= rtol ||b_j||; x += V r.
+ * A residual that becomes non-finite or grows beyond 1e6 ||b|| ends the solve
+ * with CS_ENAN; a reduced-precision context then raises its working precision
+ * (BF16 -> FP32 -> FP64) for the current setup and solves again.
  * history (host, may be NULL) receives maxit+1 relative residuals.  On
  * CS_ENOCONV x holds the last iterate and info is filled. */
 cs_status cs_solve(cs_ctx ctx, const double *b, double *x, int32_t nrhs, double rtol, int32_t maxit,

@@ -117,6 +117,20 @@ def least_squares_blocks(H: np.ndarray, G: np.ndarray) -> np.ndarray:
     return out
 
 
+def gram_condition(G: np.ndarray) -> np.ndarray:
+    """Spectral condition number of every G_i restricted to the eigenvalues the
+    least-squares step keeps (those above PINV_RCOND times the largest).  The
+    solve of Lambda_i G_i = H_i loses about that factor of relative accuracy,
+    which bounds how closely two implementations can agree on Lambda_i."""
+    out = np.empty(G.shape[0])
+    for i in range(G.shape[0]):
+        ev = np.linalg.eigvalsh(G[i])
+        top = ev[-1]
+        kept = ev[ev > PINV_RCOND * top]
+        out[i] = top / kept[0] if top > 0 else 1.0
+    return out
+
+
 def truncate_rows(E: sp.csr_matrix, Epat: sp.csr_matrix, n: int, alpha: int,
                   rows: np.ndarray):
     """Keep the alpha blocks of largest Frobenius norm in the given block rows of
@@ -165,11 +179,13 @@ def fit_additive(A: sp.spmatrix, n: int, depth: int, alpha: Optional[int] = None
     E = sp.identity(N, format="csr")
     Epat = sp.identity(B, format="csr", dtype=bool)
     lam_t, pats = [], [Epat]
+    cond = []
     for ell in range(1, depth + 1):
         M = (At @ E).tocsr()
         G = blockdiag_of_product(M, M, n)
         H = blockdiag_of_product(E, M, n)
         Lt = least_squares_blocks(H, G)
+        cond.append(gram_condition(G))
         lam_t.append(Lt)
         if ell < depth:
             E = (E - blockdiag(Lt) @ M).tocsr()
@@ -178,7 +194,7 @@ def fit_additive(A: sp.spmatrix, n: int, depth: int, alpha: Optional[int] = None
                 E, Epat = truncate_rows(E, Epat, n, alpha, np.arange(B))
             pats.append(Epat)
     return dict(lam=[unscale(L, w) for L in lam_t], lam_tilde=lam_t, w=w, patterns=pats,
-                colours=None)
+                colours=None, gram_cond=cond)
 
 
 def fit_multiplicative(A: sp.spmatrix, n: int, depth: int, colours: np.ndarray,
@@ -200,6 +216,7 @@ def fit_multiplicative(A: sp.spmatrix, n: int, depth: int, colours: np.ndarray,
     E = sp.identity(N, format="csr")
     Epat = sp.identity(B, format="csr", dtype=bool)
     lam_t = [np.zeros((B, n, n)) for _ in range(depth)]
+    cond = [np.ones(B) for _ in range(depth)]
     pats = [Epat]
     for ell in range(1, depth + 1):
         for k in range(chi):
@@ -213,6 +230,7 @@ def fit_multiplicative(A: sp.spmatrix, n: int, depth: int, colours: np.ndarray,
             H = blockdiag_of_product(Ek, Mk, n)
             Lt = least_squares_blocks(H, G)
             lam_t[ell - 1][blocks] = Lt
+            cond[ell - 1][blocks] = gram_condition(G)
             if ell < depth or k < chi - 1:
                 D = np.zeros((B, n, n))
                 D[blocks] = Lt
@@ -229,7 +247,7 @@ def fit_multiplicative(A: sp.spmatrix, n: int, depth: int, colours: np.ndarray,
                     E, Epat = truncate_rows(E, Epat, n, alpha, blocks)
                 pats.append(Epat)
     return dict(lam=[unscale(L, w) for L in lam_t], lam_tilde=lam_t, w=w, patterns=pats,
-                colours=colours.astype(np.int32))
+                colours=colours.astype(np.int32), gram_cond=cond)
 
 
 def fit(A, n, depth, mode="additive", colours=None, alpha=None) -> Dict:

@@ -52,7 +52,7 @@ class cs_options(ctypes.Structure):
 class cs_info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("rel_res", ctypes.c_double), ("rho", ctypes.c_double),
                 ("setup_ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
-                ("singular_blocks", ctypes.c_int32)]
+                ("singular_blocks", ctypes.c_int32), ("precision", ctypes.c_int32)]
 
 
 # every symbol declared in include/cascade.h, with its ctypes signature
@@ -293,6 +293,7 @@ class Solver:
         k = info.iterations
         return x, dict(iterations=k, rel_res=info.rel_res, rho=info.rho, setup_ms=info.setup_ms,
                        solve_ms=info.solve_ms, singular_blocks=info.singular_blocks,
+                       precision={v: k for k, v in _PRECS.items()}.get(info.precision),
                        history=hist[:k + 1].copy(), status=st)
 
     def get_prescaled_blocks(self, level: int = 0):

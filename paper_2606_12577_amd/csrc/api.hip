@@ -162,6 +162,35 @@ const int32_t SAVE_VERSION = 2;
 
 }  // namespace
 
+namespace {
+
+// Run a solve; a reduced-precision V-cycle that diverges (non-finite or
+// exploding residual) is escalated (BF16 -> FP32 -> FP64) for this setup and
+// the solve repeated.
+template <class F>
+cs_status solve_escalating(cs_ctx ctx, const double *b, double *x, int32_t maxit, double rtol, cs_info *info,
+                           F &&run) {
+    cs_status st = CS_OK;
+    cs_status g = guarded(ctx, [&](Ctx &c) {
+        need(c.have_setup, "solve before cs_setup", CS_ESTATE);
+        need(b && x, "null vector");
+        need(maxit >= 0 && rtol >= 0.0, "bad rtol or maxit");
+        run(c, &st);
+        while (st == CS_ENAN && c.precision != CS_FP64) {
+            c.precision = c.precision == CS_BF16 ? CS_FP32 : CS_FP64;
+            c.opt.precision = c.precision;
+            st = CS_OK;
+            run(c, &st);
+        }
+        if (info) info->precision = c.precision;
+    });
+    if (g != CS_OK) return g;
+    if (st != CS_OK) ctx->c.err = cs_status_string(st);
+    return st;
+}
+
+}  // namespace
+
 extern "C" {
 
 int32_t cs_abi_version(void) { return CS_ABI_VERSION; }
@@ -267,7 +296,8 @@ cs_status cs_setup(cs_ctx ctx, const cs_options *opt) {
         need(opt->order == CS_FF || opt->order == CS_RF, "order must be FF or RF");
         need(opt->n_pre >= 1 && opt->n_post >= 0, "need n_pre >= 1 and n_post >= 0");
         need(opt->trunc_alpha >= 0, "trunc_alpha must be >= 0");
-        need(opt->precision == CS_FP64 || opt->precision == CS_FP32, "precision must be FP64 or FP32");
+        need(opt->precision == CS_FP64 || opt->precision == CS_FP32 || opt->precision == CS_BF16,
+             "precision must be FP64, FP32 or BF16");
         c.have_setup = false;
         c.opt = *opt;
         c.precision = opt->precision;
@@ -285,7 +315,8 @@ cs_status cs_setup_learned(cs_ctx ctx, const cs_options *opt, cs_mlp mlp, const 
         need(opt->mode == CS_ADDITIVE, "the learned setup fits additive cascades");
         need(opt->order == CS_FF || opt->order == CS_RF, "order must be FF or RF");
         need(opt->n_pre >= 1 && opt->n_post >= 0, "need n_pre >= 1 and n_post >= 0");
-        need(opt->precision == CS_FP64 || opt->precision == CS_FP32, "precision must be FP64 or FP32");
+        need(opt->precision == CS_FP64 || opt->precision == CS_FP32 || opt->precision == CS_BF16,
+             "precision must be FP64, FP32 or BF16");
         need(c.lv.size() >= 2, "the hierarchy has no smoothed level");
         Level &L0 = c.lv[0];
         cs::Mlp &m = mlp->m;
@@ -321,7 +352,8 @@ cs_status cs_get_prescaled_blocks(cs_ctx ctx, int32_t level, float *out) {
 cs_status cs_set_precision(cs_ctx ctx, int32_t precision) {
     return guarded(ctx, [&](Ctx &c) {
         need(c.have_setup, "cs_set_precision before cs_setup", CS_ESTATE);
-        need(precision == CS_FP64 || precision == CS_FP32, "precision must be FP64 or FP32");
+        need(precision == CS_FP64 || precision == CS_FP32 || precision == CS_BF16,
+             "precision must be FP64, FP32 or BF16");
         c.precision = precision;
         c.opt.precision = precision;
     });
@@ -409,30 +441,16 @@ cs_status cs_vcycle(cs_ctx ctx, const double *b, double *x, int32_t nrhs) {
 
 cs_status cs_solve(cs_ctx ctx, const double *b, double *x, int32_t nrhs, double rtol, int32_t maxit, cs_info *info,
                    double *history) {
-    cs_status st = CS_OK;
-    cs_status g = guarded(ctx, [&](Ctx &c) {
-        need(c.have_setup, "cs_solve before cs_setup", CS_ESTATE);
-        need(b && x, "null vector");
-        need(maxit >= 0 && rtol >= 0.0, "bad rtol or maxit");
-        cs::solve_ir(c, b, x, nrhs, rtol, maxit, info, history, &st);
+    return solve_escalating(ctx, b, x, maxit, rtol, info, [&](Ctx &c, cs_status *st) {
+        cs::solve_ir(c, b, x, nrhs, rtol, maxit, info, history, st);
     });
-    if (g != CS_OK) return g;
-    if (st != CS_OK) ctx->c.err = cs_status_string(st);
-    return st;
 }
 
 cs_status cs_solve_cg(cs_ctx ctx, const double *b, double *x, int32_t nrhs, double rtol, int32_t maxit,
                       cs_info *info, double *history) {
-    cs_status st = CS_OK;
-    cs_status g = guarded(ctx, [&](Ctx &c) {
-        need(c.have_setup, "cs_solve_cg before cs_setup", CS_ESTATE);
-        need(b && x, "null vector");
-        need(maxit >= 0 && rtol >= 0.0, "bad rtol or maxit");
-        cs::solve_cg(c, b, x, nrhs, rtol, maxit, info, history, &st);
+    return solve_escalating(ctx, b, x, maxit, rtol, info, [&](Ctx &c, cs_status *st) {
+        cs::solve_cg(c, b, x, nrhs, rtol, maxit, info, history, st);
     });
-    if (g != CS_OK) return g;
-    if (st != CS_OK) ctx->c.err = cs_status_string(st);
-    return st;
 }
 
 cs_status cs_save_setup(cs_ctx ctx, const char *path) {

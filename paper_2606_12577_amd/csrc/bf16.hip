@@ -1,0 +1,235 @@
+// BF16 block kernels for 16x16 blocks (tensor Q3 DG elements): the
+// multicoloured cascade sweep and the residual with A and Lambda stored in
+// BF16 and applied on the matrix cores (v_mfma_f32_16x16x16bf16) with FP32
+// accumulation; vectors FP32.
+//
+// A block product y = M v (16x16 times a 16-vector) is one MFMA whose B
+// operand holds v in every column: lane l supplies M[l%16][4(l/16)+t] and
+// v[4(l/16)+t] (t = 0..3) and receives y[4(l/16)+r] (r = 0..3) in every
+// column.  The received rows are exactly the k-slots a lane supplies as a B
+// operand, so a residual computed by one MFMA feeds the Lambda product of the
+// next without data movement.  FP32 vectors enter as a BF16 pair hi + lo
+// (hi = bf16(v), lo = bf16(v - hi)): two MFMAs per block carry v to about 16
+// significant bits, leaving the BF16 rounding of A and Lambda as the only
+// reduced-precision step.
+//
+// Blocks are stored in that operand order: entry (i, k) of a block sits at
+// 4 (i + 16 (k/4)) + k%4, so every lane reads its four values as one 8-byte
+// load and a wavefront reads a block as one contiguous 512-byte segment.
+#include <algorithm>
+
+#include "cs_internal.h"
+
+namespace cs {
+namespace {
+
+constexpr int WG = 256;
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short f2bf(float f) {   // round to nearest even
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ void split(const float (&v)[4], bf16x4 &hi, bf16x4 &lo) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const unsigned short h = f2bf(v[t]);
+        hi[t] = (short)h;
+        lo[t] = (short)f2bf(v[t] - bf2f(h));
+    }
+}
+
+__device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// acc = sum over the blocks of row i of A_ij x_j (rows 4 kg .. 4 kg + 3)
+__device__ __forceinline__ f32x4 block_row_product(int i, int lane, const int32_t *__restrict__ bptr,
+                                                   const int32_t *__restrict__ bcol,
+                                                   const unsigned short *__restrict__ aval,
+                                                   const float *__restrict__ x) {
+    const int kg = lane >> 4;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int e = bptr[i]; e < bptr[i + 1]; ++e) {
+        const int64_t j = bcol[e];
+        const bf16x4 a = *reinterpret_cast<const bf16x4 *>(aval + (int64_t)e * 256 + lane * 4);
+        const float4 xv = *reinterpret_cast<const float4 *>(x + j * 16 + kg * 4);
+        const float v[4] = {xv.x, xv.y, xv.z, xv.w};
+        bf16x4 hi, lo;
+        split(v, hi, lo);
+        acc = mfma(a, hi, acc);
+        acc = mfma(a, lo, acc);
+    }
+    return acc;
+}
+
+// Multiplicative cascade step on the blocks blist[0..nblk) (one colour):
+// x_i <- x_i - Lambda_i (sum_j A_ij x_j - b_i), in place; ZERO: x = 0 before
+// the step, so x_i = Lambda_i b_i.  One wavefront per block row.
+template <bool ZERO>
+__global__ __launch_bounds__(WG) void k_bsr16_sweep(int64_t nblk, const int32_t *__restrict__ blist,
+                                                    const int32_t *__restrict__ bptr,
+                                                    const int32_t *__restrict__ bcol,
+                                                    const unsigned short *__restrict__ aval,
+                                                    const unsigned short *__restrict__ lam,
+                                                    const float *__restrict__ b, float *x) {
+    const int lane = threadIdx.x & 63;
+    const int64_t w = (int64_t)blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
+    if (w >= nblk) return;   // whole wavefront
+    const int i = blist[w];
+    const int kg = lane >> 4;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    if constexpr (!ZERO) acc = block_row_product(i, lane, bptr, bcol, aval, x);
+    const float4 bv = *reinterpret_cast<const float4 *>(b + (int64_t)i * 16 + kg * 4);
+    const float r[4] = {acc[0] - bv.x, acc[1] - bv.y, acc[2] - bv.z, acc[3] - bv.w};
+    bf16x4 hi, lo;
+    split(r, hi, lo);
+    const bf16x4 l = *reinterpret_cast<const bf16x4 *>(lam + (int64_t)i * 256 + lane * 4);
+    f32x4 y = {0.f, 0.f, 0.f, 0.f};
+    y = mfma(l, hi, y);
+    y = mfma(l, lo, y);
+    if ((lane & 15) == 0) {
+        float4 *xp = reinterpret_cast<float4 *>(x + (int64_t)i * 16 + kg * 4);
+        float4 xo = ZERO ? float4{0.f, 0.f, 0.f, 0.f} : *xp;
+        xo.x -= y[0];
+        xo.y -= y[1];
+        xo.z -= y[2];
+        xo.w -= y[3];
+        *xp = xo;
+    }
+}
+
+// r = A x - b on block rows 0..nblk-1
+__global__ __launch_bounds__(WG) void k_bsr16_residual(int64_t nblk, const int32_t *__restrict__ bptr,
+                                                       const int32_t *__restrict__ bcol,
+                                                       const unsigned short *__restrict__ aval,
+                                                       const float *__restrict__ b, const float *__restrict__ x,
+                                                       float *__restrict__ r) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
+    if (i >= nblk) return;
+    const int kg = lane >> 4;
+    const f32x4 acc = block_row_product((int)i, lane, bptr, bcol, aval, x);
+    if ((lane & 15) == 0) {
+        const float4 bv = *reinterpret_cast<const float4 *>(b + i * 16 + kg * 4);
+        *reinterpret_cast<float4 *>(r + i * 16 + kg * 4) =
+            float4{acc[0] - bv.x, acc[1] - bv.y, acc[2] - bv.z, acc[3] - bv.w};
+    }
+}
+
+__device__ __forceinline__ int64_t op_pos(int i, int k) { return 4 * (i + 16 * (k >> 2)) + (k & 3); }
+
+// BF16 copy of A's 16x16 blocks in operand order (blocks of the block-CSR
+// pattern bptr/bcol, zero-filled beforehand); one thread per scalar row
+__global__ void k_pack_a16(int64_t n, const int32_t *__restrict__ ap, const int32_t *__restrict__ ac,
+                           const double *__restrict__ av, const int32_t *__restrict__ bptr,
+                           const int32_t *__restrict__ bcol, unsigned short *__restrict__ out) {
+    const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (row >= n) return;
+    const int64_t I = row / 16;
+    const int i = (int)(row % 16);
+    for (int e = ap[row]; e < ap[row + 1]; ++e) {
+        const int c = ac[e];
+        int p = bptr[I];
+        while (p < bptr[I + 1] - 1 && bcol[p] != c / 16) ++p;
+        out[(int64_t)p * 256 + op_pos(i, c % 16)] = f2bf((float)av[e]);
+    }
+}
+
+// Lambda blocks [depth][B][16][16] (FP64) -> operand order, plain and transposed
+__global__ void k_pack_lam16(int64_t nblocks, const double *__restrict__ lam, unsigned short *__restrict__ out,
+                             unsigned short *__restrict__ out_t) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= nblocks * 256) return;
+    const int64_t blk = e / 256;
+    const int i = (int)(e % 256) / 16, k = (int)(e % 16);
+    const unsigned short v = f2bf((float)lam[e]);
+    out[blk * 256 + op_pos(i, k)] = v;
+    out_t[blk * 256 + op_pos(k, i)] = v;
+}
+
+__global__ void k_zero16(int64_t n, unsigned short *__restrict__ a) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e < n) a[e] = 0;
+}
+
+inline unsigned gdim(int64_t n, int wg = WG) { return (unsigned)ceil_div(n, wg); }
+
+}  // namespace
+
+void build_bf16_level(Ctx &c, Level &L) {
+    L.bsr_ptr.release();
+    L.bsr_col.release();
+    L.a16.release();
+    if (L.nb != 16) return;
+    // block-CSR pattern of A over all block rows (host, from the scalar CSR)
+    const int64_t B = L.B;
+    std::vector<int32_t> bp(B + 1, 0), bc;
+    std::vector<int32_t> cols;
+    for (int64_t I = 0; I < B; ++I) {
+        cols.clear();
+        for (int64_t r = I * 16; r < I * 16 + 16; ++r)
+            for (int64_t e = L.h_ptr[r]; e < L.h_ptr[r + 1]; ++e) cols.push_back(L.h_col[e] / 16);
+        std::sort(cols.begin(), cols.end());
+        cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+        bc.insert(bc.end(), cols.begin(), cols.end());
+        bp[I + 1] = (int32_t)bc.size();
+    }
+    L.bsr_ptr.upload(bp.data(), bp.size(), c.stream);
+    L.bsr_col.upload(bc.data(), bc.size(), c.stream);
+    const int64_t tot = (int64_t)bc.size() * 256;
+    L.a16.alloc(tot);
+    hipLaunchKernelGGL(k_zero16, dim3(gdim(tot)), dim3(WG), 0, c.stream, tot, L.a16.get());
+    hipLaunchKernelGGL(k_pack_a16, dim3(gdim(L.n)), dim3(WG), 0, c.stream, L.n, L.a_ptr.get(), L.a_col.get(),
+                       L.a_val.get(), L.bsr_ptr.get(), L.bsr_col.get(), L.a16.get());
+    CS_LAUNCH_CHECK();
+    L.bsr_nnzb = (int64_t)bc.size();
+    CS_HIP(hipStreamSynchronize(c.stream));
+}
+
+void build_bf16_smoother(Ctx &c, Level &L) {
+    L.lam16.release();
+    L.lam16T.release();
+    if (L.nb != 16 || L.depth == 0) return;
+    const int64_t nbl = (int64_t)L.depth * L.B;
+    L.lam16.alloc(nbl * 256);
+    L.lam16T.alloc(nbl * 256);
+    hipLaunchKernelGGL(k_pack_lam16, dim3(gdim(nbl * 256)), dim3(WG), 0, c.stream, nbl, L.lam64.get(), L.lam16.get(),
+                       L.lam16T.get());
+    CS_LAUNCH_CHECK();
+}
+
+bool use_bf16(const Ctx &c, const Level &L) {
+    return c.precision == CS_BF16 && L.nb == 16 && L.a16.get() != nullptr;
+}
+
+void bf16_sweep(Ctx &c, const Level &L, int ell, int colour, bool reverse, bool zero, const float *b, float *x) {
+    const int64_t k0 = L.cblk_ptr[colour], nblk = L.cblk_ptr[colour + 1] - k0;
+    if (nblk == 0) return;
+    const unsigned short *lam = (reverse ? L.lam16T.get() : L.lam16.get()) + (int64_t)ell * L.B * 256;
+    const int slot = trace_begin(c, zero ? CS_TRACE_SWEEP_ZERO : (L.n >= (1 << 19) ? CS_TRACE_SWEEP
+                                                                                    : CS_TRACE_SWEEP_SMALL),
+                                 (zero ? 0.0 : (double)L.bsr_nnzb * 512.0 * nblk / std::max<int64_t>(L.B, 1)) +
+                                     nblk * (512.0 + 16 * 4 * (zero ? 2.0 : 3.0)));
+    if (zero)
+        hipLaunchKernelGGL(k_bsr16_sweep<true>, dim3(gdim(nblk, WG / 64)), dim3(WG), 0, c.stream, nblk,
+                           L.cblk.get() + k0, L.bsr_ptr.get(), L.bsr_col.get(), L.a16.get(), lam, b, x);
+    else
+        hipLaunchKernelGGL(k_bsr16_sweep<false>, dim3(gdim(nblk, WG / 64)), dim3(WG), 0, c.stream, nblk,
+                           L.cblk.get() + k0, L.bsr_ptr.get(), L.bsr_col.get(), L.a16.get(), lam, b, x);
+    CS_LAUNCH_CHECK();
+    trace_end(c, slot);
+}
+
+void bf16_residual(Ctx &c, const Level &L, const float *b, const float *x, float *r) {
+    const int64_t nblk = L.n_active / 16;
+    hipLaunchKernelGGL(k_bsr16_residual, dim3(gdim(nblk, WG / 64)), dim3(WG), 0, c.stream, nblk, L.bsr_ptr.get(),
+                       L.bsr_col.get(), L.a16.get(), b, x, r);
+    CS_LAUNCH_CHECK();
+}
+
+}  // namespace cs

@@ -142,6 +142,12 @@ struct Level {
     DBuf<int64_t> dseg_d, dinv_off;   // device copies: offsets and inverse offsets
     DBuf<double> dinv;                // concatenated row-major inverses
     int64_t dseg_max = 0;
+    // BF16 block copies for 16x16 blocks (MFMA operand order), block-CSR of A
+    DBuf<int32_t> bsr_ptr, bsr_col;
+    int64_t bsr_nnzb = 0;
+    DBuf<unsigned short> a16, lam16, lam16T;
+    DBuf<int32_t> cblk;               // active blocks grouped by colour
+    std::vector<int64_t> cblk_ptr;    // colour offsets into cblk
     // V-cycle workspace (working precision), [n][nrhs]
     DBuf<char> xb, xt, bb, rr;
 };
@@ -235,6 +241,13 @@ void build_colour_layout(Ctx &c, Level &L);
 void run_setup_learned(Ctx &c, const cs_options &o, const float *lam_t);
 // Lambda~ of a level in the layout [B][depth][nb][nb] (FP32, device)
 void prescaled_blocks(Ctx &c, Level &L, float *out);
+
+// bf16.hip: 16x16 blocks in BF16 on the matrix cores
+void build_bf16_level(Ctx &c, Level &L);
+void build_bf16_smoother(Ctx &c, Level &L);
+bool use_bf16(const Ctx &c, const Level &L);
+void bf16_sweep(Ctx &c, const Level &L, int ell, int colour, bool reverse, bool zero, const float *b, float *x);
+void bf16_residual(Ctx &c, const Level &L, const float *b, const float *x, float *r);
 
 // solve.hip
 void ensure_workspace(Ctx &c, int nrhs);

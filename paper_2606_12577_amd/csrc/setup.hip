@@ -805,6 +805,7 @@ void build_level_device(Ctx &c, Level &L) {
         L.dinv.release();
     }
     CS_HIP(hipStreamSynchronize(s));
+    build_bf16_level(c, L);
 }
 
 void build_colour_layout(Ctx &c, Level &L) {
@@ -820,6 +821,14 @@ void build_colour_layout(Ctx &c, Level &L) {
     L.clist.upload(list.data(), list.size(), c.stream);
     L.csell.clear();
     L.csell.resize(chi);
+    std::vector<int32_t> act;                 // active blocks by colour
+    L.cblk_ptr.assign(chi + 1, 0);
+    for (int k = 0; k < chi; ++k) {
+        for (int64_t q = L.cptr[k]; q < L.cptr[k + 1]; ++q)
+            if (list[q] * L.nb < L.n_active) act.push_back(list[q]);
+        L.cblk_ptr[k + 1] = (int64_t)act.size();
+    }
+    L.cblk.upload(act.data(), act.size(), c.stream);
     for (int k = 0; k < chi; ++k) {
         std::vector<int32_t> rows;
         rows.reserve((L.cptr[k + 1] - L.cptr[k]) * L.nb);
@@ -1091,6 +1100,7 @@ void build_working_copies(Ctx &c) {
         hipLaunchKernelGGL(k_cast32, dim3(grid_for(tot)), dim3(WG), 0, c.stream, tot, L.lam64.get(), L.lam32.get());
         hipLaunchKernelGGL(k_cast32, dim3(grid_for(tot)), dim3(WG), 0, c.stream, tot, L.lam64T.get(), L.lam32T.get());
         CS_LAUNCH_CHECK();
+        build_bf16_smoother(c, L);
     }
     CS_HIP(hipStreamSynchronize(c.stream));
 }

@@ -904,9 +904,17 @@ T *apply_cascade(Ctx &c, const Level &L, bool reverse, bool zero_start, const T 
     }
     const int chi = L.chi;
     const int nsteps = depth * chi;
+    bool bf16 = false;
+    if constexpr (std::is_same<T, float>::value && R == 1) bf16 = use_bf16(c, L);
     for (int s = 0; s < nsteps; ++s) {
         const int f = reverse ? nsteps - 1 - s : s;
         const int ell = f / chi, k = f % chi;
+        if constexpr (std::is_same<T, float>::value && R == 1) {
+            if (bf16) {
+                bf16_sweep(c, L, ell, k, reverse, zero_start && s == 0, b, x);
+                continue;
+            }
+        }
         const Sell &S = L.csell[k];
         if (S.nrows == 0) continue;
         const T *lam = lam_ptr<T>(L, reverse) + (int64_t)ell * nbl;
@@ -962,9 +970,15 @@ void vcycle_level(Ctx &c, int l) {
                            sell_val<T>(L.sell), bb, x, L.agg_k, L.nc, (T)L.r_scale,
                            reinterpret_cast<T *>(C.bb.get()));
     } else {
-        hipLaunchKernelGGL((k_residual<T, R>), dim3(tile_grid(c, L.act_slices)), dim3(WG), 0, c.stream, na,
-                           L.act_slices, L.sell.slice_ptr.get(), L.sell.slice_len.get(), L.sell.col.get(),
-                           sell_val<T>(L.sell), bb, x, rr);
+        bool bf16 = false;
+        if constexpr (std::is_same<T, float>::value && R == 1) {
+            bf16 = use_bf16(c, L);
+            if (bf16) bf16_residual(c, L, bb, x, rr);
+        }
+        if (!bf16)
+            hipLaunchKernelGGL((k_residual<T, R>), dim3(tile_grid(c, L.act_slices)), dim3(WG), 0, c.stream, na,
+                               L.act_slices, L.sell.slice_ptr.get(), L.sell.slice_len.get(), L.sell.col.get(),
+                               sell_val<T>(L.sell), bb, x, rr);
         hipLaunchKernelGGL((k_restrict<T, R>), dim3(grid_for(L.nc)), dim3(WG), 0, c.stream, L.nc, L.pt_ptr.get(),
                            L.pt_col.get(), pval<T>(L, true), (T)L.r_scale, rr, reinterpret_cast<T *>(C.bb.get()));
     }
@@ -1096,7 +1110,7 @@ struct Monitor {
             double rq = 0.0;
             for (int k = 0; k < R; ++k) {
                 const double v = std::sqrt(hn[q * R + k] / bn2[q * R + k]);
-                if (!std::isfinite(v)) bad = true;
+                if (!std::isfinite(v) || v > 1e6) bad = true;   // diverged
                 rq = std::max(rq, v);
             }
             c.sys_rel[q] = rq;

@@ -579,3 +579,13 @@ def test_fcg_with_vcycle_beats_stationary_iteration():
     _, h_ir = O.solve(p.levels, sm, p.rhs, rtol=1e-10, maxit=200)
     _, h_cg = O.fcg(p.levels[0].A, lambda r: O.vcycle(p.levels, sm, r), p.rhs, rtol=1e-10, maxit=200)
     assert h_cg[-1] <= 1e-10 and len(h_cg) < len(h_ir)
+
+
+def test_gram_condition_closed_form():
+    G = np.stack([np.diag([4.0, 2.0, 1.0]), np.diag([5.0, 1e-20, 0.5]),
+                  np.zeros((3, 3))])
+    Q, _ = np.linalg.qr(stream(1, TEST, 42).normal(size=(3, 3)))
+    G[0] = Q @ G[0] @ Q.T
+    c = O.gram_condition(G)
+    np.testing.assert_allclose(c[:2], [4.0, 10.0], rtol=1e-12)   # 1e-20 is below the cut-off
+    assert c[2] == 1.0

@@ -1,6 +1,7 @@
 """Checks of the synthetic input generators (no solver arithmetic involved)."""
 import pytest
 import numpy as np
+import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from synth import fd
@@ -152,3 +153,42 @@ def test_q1_multiphase_generator():
         assert abs(Ac - fe.assemble(np.ones((m // 2,) * 3))).max() < 1e-14
     lv = fe.galerkin_hierarchy(A, n, n_stop=2)
     assert [l.n for l in lv] == [512, 64, 8] and all(l.block_size == 8 for l in lv)
+
+
+def test_sipg_q3_generator():
+    """SIPG Q3 on the jittered mesh: symmetric, O(h^4) L2 convergence for a
+    manufactured solution, exact child projections (sum of M_c^T M_c = 4 I,
+    constants map to constants), proper 4-colouring of the block graph."""
+    import scipy.sparse.linalg as spla
+    from numpy.polynomial import legendre as npl
+    from synth import dg
+    f = lambda x, y: 2 * np.pi ** 2 * np.sin(np.pi * x) * np.sin(np.pi * y)
+    u = lambda x, y: np.sin(np.pi * x) * np.sin(np.pi * y)
+    errs = []
+    for n in (4, 8, 16):
+        v = dg.jittered_vertices(n)
+        A, b = dg.assemble(v, rhs_fn=f)
+        A = A.tocsr()
+        assert abs(A - A.T).max() < 1e-12 * abs(A).max()
+        x = spla.spsolve(A.tocsc(), b)
+        gq, gw = npl.leggauss(6)
+        xi, eta = np.meshgrid(gq, gq, indexing="xy")
+        X, J = dg._geometry(dg._corners(v, n), xi.ravel(), eta.ravel())
+        wdet = np.linalg.det(J) * np.outer(gw, gw).ravel()
+        val, _ = dg.basis2d(xi.ravel(), eta.ravel())
+        uh = x.reshape(-1, 16) @ val.T
+        errs.append(np.sqrt((wdet * (uh - u(X[..., 0], X[..., 1])) ** 2).sum()))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > 3.7), rates
+    M = dg.child_matrices()
+    np.testing.assert_allclose(sum(m.T @ m for m in M), 4 * np.eye(16), atol=1e-13)
+    np.testing.assert_allclose(M[:, 0, 0], 1.0, rtol=1e-14)
+    np.testing.assert_allclose(M[:, 1:, 0], 0.0, atol=1e-14)
+    p = dg.sipg_q3(8)
+    assert [l.n for l in p.levels] == [1024, 256] and p.levels[0].block_size == 16
+    Ab = abs(p.levels[0].A).tocsr()
+    B = sp.csr_matrix((np.ones(Ab.nnz), Ab.indices // 16, Ab.indptr), shape=(1024, 64))
+    col = p.levels[0].colour
+    for i in range(64):
+        nbrs = np.unique(B[i * 16:(i + 1) * 16].indices)
+        assert all(col[j] != col[i] for j in nbrs if j != i)
