@@ -699,6 +699,118 @@ __global__ __launch_bounds__(WG) void k_cg_update(int64_t nrows, int64_t nslices
     if constexpr (!SYS) wg_partials<R>(acc, red, partial);
 }
 
+// Single-system forms of the vector steps: the [n][R] vectors are streamed as
+// flat arrays, two doubles per thread per step (a thread always meets the same
+// two right-hand sides, since the grid stride is a multiple of R), which keeps
+// registers low and many loads in flight.  Partial sums per workgroup [G][R].
+template <int R>
+__device__ __forceinline__ void flat_partials(const double (&v)[2], double *red, double *partial) {
+    constexpr int K2 = R > 1 ? R / 2 : 1;   // distinct pair positions
+    red[threadIdx.x * 2] = v[0];
+    red[threadIdx.x * 2 + 1] = v[1];
+    __syncthreads();
+    for (int h = WG / 2; h >= K2; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            red[threadIdx.x * 2] += red[(threadIdx.x + h) * 2];
+            red[threadIdx.x * 2 + 1] += red[(threadIdx.x + h) * 2 + 1];
+        }
+        __syncthreads();
+    }
+    if ((int)threadIdx.x < K2) {
+        if constexpr (R == 1) {
+            partial[blockIdx.x] = red[0] + red[1];
+        } else {
+            partial[(int64_t)blockIdx.x * R + 2 * threadIdx.x] = red[threadIdx.x * 2];
+            partial[(int64_t)blockIdx.x * R + 2 * threadIdx.x + 1] = red[threadIdx.x * 2 + 1];
+        }
+    }
+}
+
+// (z, q) per right-hand side
+template <typename T, int R>
+__global__ __launch_bounds__(WG) void k_cg_zq_flat(int64_t npairs, const T *__restrict__ z,
+                                                   const double *__restrict__ q, double *__restrict__ partial) {
+    __shared__ double red[2 * WG];
+    double v[2] = {0.0, 0.0};
+    const int64_t stride = (int64_t)gridDim.x * WG;
+    for (int64_t e2 = blockIdx.x * (int64_t)WG + threadIdx.x; e2 < npairs; e2 += stride) {
+        T zz[2];
+        double qq[2];
+        vload_nt<T, 2>(z + 2 * e2, zz);
+        vload_nt<double, 2>(q + 2 * e2, qq);
+        v[0] += (double)zz[0] * qq[0];
+        v[1] += (double)zz[1] * qq[1];
+    }
+    flat_partials<R>(v, red, partial);
+}
+
+// p = z + beta p (first: p = z), beta = -(z, q_prev) / (p_prev, q_prev)
+template <typename T, int R>
+__global__ __launch_bounds__(WG) void k_cg_p_flat(int64_t npairs, const T *__restrict__ z,
+                                                  const double *__restrict__ zq, const double *__restrict__ pq_prev,
+                                                  double *__restrict__ p, int first) {
+    const int64_t stride = (int64_t)gridDim.x * WG;
+    const int64_t e2_0 = blockIdx.x * (int64_t)WG + threadIdx.x;
+    double beta[2] = {0.0, 0.0};
+    if (!first) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int k = (int)((2 * e2_0 + u) % R);
+            const double d = pq_prev[k];
+            beta[u] = d > 0.0 ? -zq[k] / d : 0.0;
+            if (!isfinite(beta[u])) beta[u] = 0.0;
+        }
+    }
+    for (int64_t e2 = e2_0; e2 < npairs; e2 += stride) {
+        T zz[2];
+        vload_nt<T, 2>(z + 2 * e2, zz);
+        double pp[2] = {0.0, 0.0};
+        if (!first) vload_nt<double, 2>(p + 2 * e2, pp);
+        pp[0] = (double)zz[0] + beta[0] * pp[0];
+        pp[1] = (double)zz[1] + beta[1] * pp[1];
+        vstore<double, 2>(p + 2 * e2, pp);
+    }
+}
+
+// x += alpha p, r -= alpha q, rt = r (working precision), partial r^2
+template <typename T, int R>
+__global__ __launch_bounds__(WG) void k_cg_update_flat(int64_t npairs, const double *__restrict__ pq,
+                                                       const double *__restrict__ p, const double *__restrict__ q,
+                                                       double *__restrict__ x, double *__restrict__ r,
+                                                       T *__restrict__ rt, double *__restrict__ partial) {
+    __shared__ double red[2 * WG];
+    const int64_t stride = (int64_t)gridDim.x * WG;
+    const int64_t e2_0 = blockIdx.x * (int64_t)WG + threadIdx.x;
+    double alpha[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int k = (int)((2 * e2_0 + u) % R);
+        const double d = pq[k];
+        alpha[u] = d > 0.0 ? pq[R + k] / d : 0.0;
+        if (!isfinite(alpha[u])) alpha[u] = 0.0;
+    }
+    double v[2] = {0.0, 0.0};
+    for (int64_t e2 = e2_0; e2 < npairs; e2 += stride) {
+        double pp[2], qq[2], xx[2], rr[2];
+        vload_nt<double, 2>(p + 2 * e2, pp);
+        vload_nt<double, 2>(q + 2 * e2, qq);
+        vload_nt<double, 2>(x + 2 * e2, xx);
+        vload_nt<double, 2>(r + 2 * e2, rr);
+        T o[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            xx[u] += alpha[u] * pp[u];
+            rr[u] -= alpha[u] * qq[u];
+            o[u] = (T)rr[u];
+            v[u] += rr[u] * rr[u];
+        }
+        vstore<double, 2>(x + 2 * e2, xx);
+        vstore<double, 2>(r + 2 * e2, rr);
+        vstore<T, 2>(rt + 2 * e2, o);
+    }
+    flat_partials<R>(v, red, partial);
+}
+
 // Fixed-order sum of the partials: out[k] = sum_g partial[g][k]
 // One coalesced pass: thread t always accumulates component t % R (R divides
 // 1024), then a tree over threads of equal t % R.
@@ -1335,6 +1447,8 @@ void solve_cg(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
                 CS_LAUNCH_CHECK();
             };
             const double vec = (double)L0.n * R * 8.0;
+            const int64_t npairs = L0.n * R / 2;
+            const bool flat = !batch && (L0.n * R) % 2 == 0;   // flat pair streaming (one system, even length)
             // ||b||^2 and rt = b; r = b; x = 0
             if (batch)
                 hipLaunchKernelGGL((k_ir_residual<T, R, true>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
@@ -1377,6 +1491,9 @@ void solve_cg(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
                     if (batch)
                         hipLaunchKernelGGL((k_cg_zq<T, R, true>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
                                            z, q, c.sys_het.get(), c.sys_spart.get(), c.rn2.get(), (double *)nullptr);
+                    else if (flat)
+                        hipLaunchKernelGGL((k_cg_zq_flat<T, R>), dim3(G), dim3(WG), 0, c.stream, npairs, z, q,
+                                           c.ir_partial.get());
                     else
                         hipLaunchKernelGGL((k_cg_zq<T, R, false>), dim3(G), dim3(WG), 0, c.stream, S.nrows,
                                            S.nslices, z, q, (const int32_t *)nullptr, (double *)nullptr,
@@ -1384,8 +1501,12 @@ void solve_cg(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
                     CS_LAUNCH_CHECK();
                     reduce(R, c.cg_zq.get());
                 }
-                hipLaunchKernelGGL((k_cg_p<T, R>), dim3(grid_for(L0.n)), dim3(WG), 0, c.stream, L0.n, nsys,
-                                   c.sys_ptr_d.get(), z, c.cg_zq.get(), pq_prev, p, it == 0 ? 1 : 0);
+                if (!flat)
+                    hipLaunchKernelGGL((k_cg_p<T, R>), dim3(grid_for(L0.n)), dim3(WG), 0, c.stream, L0.n, nsys,
+                                       c.sys_ptr_d.get(), z, c.cg_zq.get(), pq_prev, p, it == 0 ? 1 : 0);
+                else
+                    hipLaunchKernelGGL((k_cg_p_flat<T, R>), dim3(G), dim3(WG), 0, c.stream, npairs, z, c.cg_zq.get(),
+                                       pq_prev, p, it == 0 ? 1 : 0);
                 CS_LAUNCH_CHECK();
                 trace_end(c, slot);
                 slot = trace_begin(c, CS_TRACE_REFINE, S.nnz * 12.0 + 3.0 * vec);
@@ -1406,6 +1527,9 @@ void solve_cg(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
                     hipLaunchKernelGGL((k_cg_update<T, R, true>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
                                        nsys, c.sys_ptr_d.get(), pq, p, q, x, r, rt, c.sys_het.get(),
                                        c.sys_spart.get(), c.rn2.get(), (double *)nullptr);
+                else if (flat)
+                    hipLaunchKernelGGL((k_cg_update_flat<T, R>), dim3(G), dim3(WG), 0, c.stream, npairs, pq, p, q, x,
+                                       r, rt, c.ir_partial.get());
                 else
                     hipLaunchKernelGGL((k_cg_update<T, R, false>), dim3(G), dim3(WG), 0, c.stream, S.nrows,
                                        S.nslices, nsys, c.sys_ptr_d.get(), pq, p, q, x, r, rt,
