@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <numeric>
+#include <type_traits>
 
 #include "cs_internal.h"
 
@@ -247,6 +248,68 @@ __global__ __launch_bounds__(WG) void k_rowprod(const int32_t *__restrict__ list
             for (int u = 0; u < nb; ++u) acc += a[u] * ev[u * nb];
         }
         mval[(int64_t)(mlo + p) * nb2 + rs] = acc;
+    }
+}
+
+// The same product with the A~_ij blocks of the row staged in LDS and one
+// thread per (block column p, column s) of M_i computing all NB rows: every
+// E entry is read from memory once per (p, j) instead of NB times, and the
+// A~ values come from LDS as wavefront broadcasts.
+constexpr int AS_CAP = 2048;   // doubles of A~ staged per row (deg * NB^2)
+constexpr int MATCH_NB = 4096; // (column, neighbour) matches cached per row
+
+template <int NB>
+__global__ __launch_bounds__(WG) void k_rowprod_nb(const int32_t *__restrict__ list,
+                                                   const int32_t *__restrict__ abptr,
+                                                   const int32_t *__restrict__ abcol,
+                                                   const double *__restrict__ abval,
+                                                   const int32_t *__restrict__ eptr, const int32_t *__restrict__ ecol,
+                                                   const double *__restrict__ eval, const int32_t *__restrict__ mptr,
+                                                   const int32_t *__restrict__ mcol, double *__restrict__ mval) {
+    constexpr int NB2 = NB * NB;
+    __shared__ int32_t match[MATCH_NB];
+    __shared__ double As[AS_CAP];
+    const int li = blockIdx.x;
+    const int i = list[li];
+    const int t = threadIdx.x;
+    const int alo = abptr[i], deg = abptr[i + 1] - alo;
+    const int mlo = mptr[li], k = mptr[li + 1] - mlo;
+    const bool cached = (int64_t)k * deg <= MATCH_NB;   // uniform per workgroup
+    const bool staged = deg * NB2 <= AS_CAP;
+    if (cached)
+        for (int e = t; e < k * deg; e += WG) {
+            const int p = e / deg, jj = e % deg;
+            const int j = abcol[alo + jj];
+            match[e] = bsearch_i32(ecol, eptr[j], eptr[j + 1], mcol[mlo + p]);
+        }
+    if (staged)
+        for (int e = t; e < deg * NB2; e += WG) As[e] = abval[(int64_t)alo * NB2 + e];
+    __syncthreads();
+    for (int w = t; w < k * NB; w += WG) {
+        const int p = w / NB, sc = w % NB;
+        double acc[NB];
+#pragma unroll
+        for (int r = 0; r < NB; ++r) acc[r] = 0.0;
+        for (int jj = 0; jj < deg; ++jj) {
+            int q;
+            if (cached) {
+                q = match[p * deg + jj];
+            } else {
+                const int j = abcol[alo + jj];
+                q = bsearch_i32(ecol, eptr[j], eptr[j + 1], mcol[mlo + p]);
+            }
+            if (q < 0) continue;
+            const double *ev = eval + (int64_t)q * NB2 + sc;
+            const double *a = staged ? As + jj * NB2 : abval + (int64_t)(alo + jj) * NB2;
+#pragma unroll 2
+            for (int u = 0; u < NB; ++u) {
+                const double e = ev[u * NB];
+#pragma unroll
+                for (int r = 0; r < NB; ++r) acc[r] += a[r * NB + u] * e;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < NB; ++r) mval[(int64_t)(mlo + p) * NB2 + r * NB + sc] = acc[r];
     }
 }
 
@@ -886,6 +949,25 @@ void greedy_colouring(Ctx &c, Level &L, const BPattern &ap) {
         if (v < 0) fail(CS_EINVAL, "greedy colouring needs more than 64 colours");
 }
 
+// register-blocked M = A~ E for the common block sizes; false: use k_rowprod
+bool rowprod_nb(hipStream_t s, int nb, int nl, const int32_t *list, const BPattern &ap, const double *abval,
+                const EMat &E, const BPattern &mp, double *mval) {
+    auto go = [&](auto nbc) {
+        constexpr int NB = decltype(nbc)::value;
+        hipLaunchKernelGGL((k_rowprod_nb<NB>), dim3(nl), dim3(WG), 0, s, list, ap.ptr.get(), ap.col.get(), abval,
+                           E.pat.ptr.get(), E.pat.col.get(), E.val.get(), mp.ptr.get(), mp.col.get(), mval);
+        return true;
+    };
+    switch (nb) {
+        case 1: return go(std::integral_constant<int, 1>{});
+        case 2: return go(std::integral_constant<int, 2>{});
+        case 4: return go(std::integral_constant<int, 4>{});
+        case 8: return go(std::integral_constant<int, 8>{});
+        case 16: return go(std::integral_constant<int, 16>{});
+        default: return false;
+    }
+}
+
 void fit_level(Ctx &c, Level &L, const cs_options &o) {
     hipStream_t s = c.stream;
     const int B = (int)L.B, nb = (int)L.nb, nb2 = nb * nb;
@@ -987,9 +1069,10 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
             CS_LAUNCH_CHECK();
             // numeric: M, normal equations, Lambda~
             DBuf<double> mval((size_t)mp.nnzb * nb2);
-            hipLaunchKernelGGL(k_rowprod, dim3(nl), dim3(WG), 0, s, dlist.get(), nb, ap.ptr.get(), ap.col.get(),
-                               abval.get(), E.pat.ptr.get(), E.pat.col.get(), E.val.get(), mp.ptr.get(),
-                               mp.col.get(), mval.get());
+            if (!rowprod_nb(s, nb, nl, dlist.get(), ap, abval.get(), E, mp, mval.get()))
+                hipLaunchKernelGGL(k_rowprod, dim3(nl), dim3(WG), 0, s, dlist.get(), nb, ap.ptr.get(), ap.col.get(),
+                                   abval.get(), E.pat.ptr.get(), E.pat.col.get(), E.val.get(), mp.ptr.get(),
+                                   mp.col.get(), mval.get());
             CS_LAUNCH_CHECK();
             sing.alloc(nl);
             double *lam_l = lamt.get() + (size_t)(ell - 1) * B * nb2;
