@@ -110,6 +110,9 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built: run `python -m paper_2606_12577_amd.build`")
+    # load torch's HIP runtime first, so that the library binds to the same one
+    # (a second runtime loaded ahead of torch cannot see the device afterwards)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

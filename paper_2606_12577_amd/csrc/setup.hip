@@ -313,47 +313,6 @@ __global__ __launch_bounds__(WG) void k_rowprod_nb(const int32_t *__restrict__ l
     }
 }
 
-// Symmetric Jacobi eigen-decomposition of a small SPD-or-singular matrix held in
-// g (row-major nb x nb, overwritten by the eigenvalues on its diagonal); v gets
-// the eigenvectors as columns.  Single thread.
-__device__ void jacobi_eig(double *g, double *v, int nb) {
-    for (int a = 0; a < nb; ++a)
-        for (int b = 0; b < nb; ++b) v[a * nb + b] = (a == b) ? 1.0 : 0.0;
-    for (int sweep = 0; sweep < 60; ++sweep) {
-        double off = 0.0, dia = 0.0;
-        for (int a = 0; a < nb; ++a)
-            for (int b = 0; b < nb; ++b) {
-                if (a != b) off += g[a * nb + b] * g[a * nb + b];
-                else dia += g[a * nb + a] * g[a * nb + a];
-            }
-        if (off <= 1e-30 * dia || off == 0.0) break;
-        for (int p = 0; p < nb - 1; ++p)
-            for (int q = p + 1; q < nb; ++q) {
-                double apq = g[p * nb + q];
-                if (apq == 0.0) continue;
-                double app = g[p * nb + p], aqq = g[q * nb + q];
-                double theta = (aqq - app) / (2.0 * apq);
-                double tt = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-                double cth = 1.0 / sqrt(tt * tt + 1.0), sth = tt * cth;
-                for (int r = 0; r < nb; ++r) {  // columns p, q
-                    double grp = g[r * nb + p], grq = g[r * nb + q];
-                    g[r * nb + p] = cth * grp - sth * grq;
-                    g[r * nb + q] = sth * grp + cth * grq;
-                }
-                for (int r = 0; r < nb; ++r) {  // rows p, q
-                    double gpr = g[p * nb + r], gqr = g[q * nb + r];
-                    g[p * nb + r] = cth * gpr - sth * gqr;
-                    g[q * nb + r] = sth * gpr + cth * gqr;
-                }
-                for (int r = 0; r < nb; ++r) {
-                    double vrp = v[r * nb + p], vrq = v[r * nb + q];
-                    v[r * nb + p] = cth * vrp - sth * vrq;
-                    v[r * nb + q] = sth * vrp + cth * vrq;
-                }
-            }
-    }
-}
-
 // Normal equations of one block row: G = M M^T, H = E M^T, Lambda~ = H G^{-1}
 // (Cholesky; pseudo-inverse fallback).  One workgroup per list row.
 __global__ __launch_bounds__(WG) void k_gram_solve(const int32_t *__restrict__ list, int nb,
@@ -361,110 +320,245 @@ __global__ __launch_bounds__(WG) void k_gram_solve(const int32_t *__restrict__ l
                                                    const double *__restrict__ mval, const int32_t *__restrict__ eptr,
                                                    const int32_t *__restrict__ ecol, const double *__restrict__ eval,
                                                    double *__restrict__ lamt, int32_t *__restrict__ singular) {
-    __shared__ double pg[WG], ph[WG];
     __shared__ double G[MAXNB * MAXNB], H[MAXNB * MAXNB], Lc[MAXNB * MAXNB], V[MAXNB * MAXNB];
-    __shared__ int bad_s;
+    __shared__ int32_t epos[UNION_CAP];   // position in pattern(M_i) of every block of E_i
     const int li = blockIdx.x;
     const int i = list[li];
     const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
     const int nb2 = nb * nb;
-    const int S = WG / nb2;
     const int mlo = mptr[li], k = mptr[li + 1] - mlo;
     const int elo = eptr[i], ek = eptr[i + 1] - elo;
-    double g = 0.0, h = 0.0;
-    if (t < S * nb2) {
-        const int e = t % nb2, sl = t / nb2;
-        const int r = e / nb, s = e % nb;
-        for (int p = sl; p < k; p += S) {
-            const double *mp = mval + (int64_t)(mlo + p) * nb2;
-            for (int u = 0; u < nb; ++u) g += mp[r * nb + u] * mp[s * nb + u];
+    const bool epos_cached = ek <= UNION_CAP;
+    if (epos_cached)
+        for (int q = t; q < ek; q += WG) epos[q] = bsearch_i32(mcol, mlo, mlo + k, ecol[elo + q]);
+    __syncthreads();
+    // G = M M^T and H = E M^T as sums of column outer products: wavefront w owns
+    // 4x4 tiles w, w+4, ... of G and H, its lanes split the columns, and the
+    // tile sums are reduced across the lanes at the end.  Every lane reads
+    // 4 + 4 entries of a column for 16 products of each matrix.
+    const int ntd = (nb + 3) / 4;
+    for (int tile = wave; tile < ntd * ntd; tile += WG / 64) {
+        const int tr = (tile / ntd) * 4, tc = (tile % ntd) * 4;
+        double ga[4][4], ha[4][4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) ga[x][y] = ha[x][y] = 0.0;
+        for (int j = lane; j < k * nb; j += 64) {
+            const int pb = j / nb, u = j % nb;
+            const double *mp = mval + (int64_t)(mlo + pb) * nb2 + u;
+            double av[4], bv[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                av[x] = tr + x < nb ? mp[(tr + x) * nb] : 0.0;
+                bv[x] = tc + x < nb ? mp[(tc + x) * nb] : 0.0;
+            }
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) ga[x][y] += av[x] * bv[y];
         }
-        for (int q = sl; q < ek; q += S) {
-            int p = bsearch_i32(mcol, mlo, mlo + k, ecol[elo + q]);
-            if (p < 0) continue;  // pattern(E_i) is contained in pattern(M_i)
-            const double *mp = mval + (int64_t)p * nb2;
-            const double *ep = eval + (int64_t)(elo + q) * nb2;
-            for (int u = 0; u < nb; ++u) h += ep[r * nb + u] * mp[s * nb + u];
+        for (int j = lane; j < ek * nb; j += 64) {
+            const int qb = j / nb, u = j % nb;
+            const int pb = epos_cached ? epos[qb] : bsearch_i32(mcol, mlo, mlo + k, ecol[elo + qb]);
+            if (pb < 0) continue;   // pattern(E_i) is contained in pattern(M_i)
+            const double *ep = eval + (int64_t)(elo + qb) * nb2 + u;
+            const double *mp = mval + (int64_t)pb * nb2 + u;
+            double av[4], bv[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                av[x] = tr + x < nb ? ep[(tr + x) * nb] : 0.0;
+                bv[x] = tc + x < nb ? mp[(tc + x) * nb] : 0.0;
+            }
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) ha[x][y] += av[x] * bv[y];
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) {
+                    ga[x][y] += __shfl_xor(ga[x][y], off, 64);
+                    ha[x][y] += __shfl_xor(ha[x][y], off, 64);
+                }
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y)
+                    if (tr + x < nb && tc + y < nb) {
+                        G[(tr + x) * nb + tc + y] = ga[x][y];
+                        H[(tr + x) * nb + tc + y] = ha[x][y];
+                    }
         }
     }
-    pg[t] = g;
-    ph[t] = h;
+    __syncthreads();
+    // Lambda~ G = H.  Regular G: Gauss-Jordan inverse of [G | I] (G is SPD:
+    // no pivoting; the pivots are the Cholesky pivots squared, with the same
+    // cut-off), one thread per entry, two barriers per step.  A pivot below
+    // PIVOT_TOL max diag(G) marks G as (numerically) singular: then the
+    // minimum-norm solution through a parallel cyclic Jacobi eigen-decomposition.
+    __shared__ double Aug[MAXNB * 2 * MAXNB];
+    const int w2 = 2 * nb;
+    double dmax = 0.0;
+    for (int q = 0; q < nb; ++q) dmax = fmax(dmax, G[q * nb + q]);
+    bool bad = !(dmax > 0.0);
+    for (int e = t; e < nb * w2; e += WG) {
+        const int r = e / w2, c = e % w2;
+        Aug[e] = c < nb ? G[r * nb + c] : (c - nb == r ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    constexpr int PER = (MAXNB * 2 * MAXNB + WG - 1) / WG;
+    for (int q = 0; q < nb && !bad; ++q) {
+        const double piv = Aug[q * w2 + q];
+        if (!(piv > PIVOT_TOL * dmax)) {   // same value in every thread: uniform
+            bad = true;
+            break;
+        }
+        double f[PER], g[PER];
+#pragma unroll
+        for (int k2 = 0; k2 < PER; ++k2) {
+            const int e = t + k2 * WG;
+            if (e < nb * w2) {
+                f[k2] = Aug[(e / w2) * w2 + q];
+                g[k2] = Aug[q * w2 + e % w2];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k2 = 0; k2 < PER; ++k2) {
+            const int e = t + k2 * WG;
+            if (e < nb * w2) Aug[e] = (e / w2 == q) ? g[k2] / piv : Aug[e] - f[k2] * g[k2] / piv;
+        }
+        __syncthreads();
+    }
+    if (t == 0) singular[li] = bad ? 1 : 0;
+    double *out = lamt + (int64_t)i * nb2;
+    if (!bad) {
+        if (t < nb2) {
+            const int r = t / nb, c = t % nb;
+            double acc = 0.0;
+            for (int u = 0; u < nb; ++u) acc += H[r * nb + u] * Aug[u * w2 + nb + c];
+            out[t] = acc;
+        }
+        return;
+    }
+    // ---- (near-)singular G: Lambda~ = H V diag(1/ev, ev kept) V^T
+    const int m = nb + (nb & 1);   // even order for the round-robin pairing (zero padding)
+    __shared__ int pp_s[MAXNB / 2], pq_s[MAXNB / 2], pair_of[MAXNB], side_of[MAXNB];
+    __shared__ double rc_s[MAXNB / 2], rs_s[MAXNB / 2], off_s[WG], dia_s[WG];
+    for (int e = t; e < m * m; e += WG) {
+        const int r = e / m, c = e % m;
+        Lc[e] = (r < nb && c < nb) ? G[r * nb + c] : 0.0;
+        V[e] = r == c ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        double off = 0.0, dia = 0.0;
+        for (int e = t; e < m * m; e += WG) {
+            const double v = Lc[e];
+            if (e / m == e % m) dia += v * v;
+            else off += v * v;
+        }
+        off_s[t] = off;
+        dia_s[t] = dia;
+        __syncthreads();
+        for (int h = WG / 2; h > 0; h >>= 1) {
+            if (t < h) {
+                off_s[t] += off_s[t + h];
+                dia_s[t] += dia_s[t + h];
+            }
+            __syncthreads();
+        }
+        const double offt = off_s[0], diat = dia_s[0];
+        __syncthreads();
+        if (offt <= 1e-30 * diat || offt == 0.0) break;   // uniform
+        for (int k = 0; k < m - 1; ++k) {
+            // circle-method pairing: (m-1, k) and ((k+j) mod (m-1), (k-j) mod (m-1))
+            if (t < m / 2) {
+                int a1, b1;
+                if (t == 0) {
+                    a1 = m - 1;
+                    b1 = k;
+                } else {
+                    a1 = (k + t) % (m - 1);
+                    b1 = (k - t + (m - 1)) % (m - 1);
+                }
+                const int pp = min(a1, b1), qq = max(a1, b1);
+                pp_s[t] = pp;
+                pq_s[t] = qq;
+                pair_of[pp] = t;
+                side_of[pp] = 0;
+                pair_of[qq] = t;
+                side_of[qq] = 1;
+                const double apq = Lc[pp * m + qq];
+                double c = 1.0, sn = 0.0;
+                if (apq != 0.0) {
+                    const double tau = (Lc[qq * m + qq] - Lc[pp * m + pp]) / (2.0 * apq);
+                    const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                    c = 1.0 / sqrt(1.0 + tt * tt);
+                    sn = tt * c;
+                }
+                rc_s[t] = c;
+                rs_s[t] = sn;
+            }
+            __syncthreads();
+            // rows: Lc <- J^T Lc
+            double nv[(MAXNB * MAXNB + WG - 1) / WG];
+            for (int e = t, k2 = 0; e < m * m; e += WG, ++k2) {
+                const int r = e / m, c2 = e % m, pr = pair_of[r];
+                const double c = rc_s[pr], sn = rs_s[pr];
+                const double vp = Lc[pp_s[pr] * m + c2], vq = Lc[pq_s[pr] * m + c2];
+                nv[k2] = side_of[r] == 0 ? c * vp - sn * vq : sn * vp + c * vq;
+            }
+            __syncthreads();
+            for (int e = t, k2 = 0; e < m * m; e += WG, ++k2) Lc[e] = nv[k2];
+            __syncthreads();
+            // columns: Lc <- Lc J, V <- V J
+            double nw[(MAXNB * MAXNB + WG - 1) / WG];
+            for (int e = t, k2 = 0; e < m * m; e += WG, ++k2) {
+                const int r = e / m, c2 = e % m, pr = pair_of[c2];
+                const double c = rc_s[pr], sn = rs_s[pr];
+                const int p0 = pp_s[pr], q0 = pq_s[pr];
+                const double lp = Lc[r * m + p0], lq = Lc[r * m + q0];
+                const double vp = V[r * m + p0], vq = V[r * m + q0];
+                nv[k2] = side_of[c2] == 0 ? c * lp - sn * lq : sn * lp + c * lq;
+                nw[k2] = side_of[c2] == 0 ? c * vp - sn * vq : sn * vp + c * vq;
+            }
+            __syncthreads();
+            for (int e = t, k2 = 0; e < m * m; e += WG, ++k2) {
+                Lc[e] = nv[k2];
+                V[e] = nw[k2];
+            }
+            __syncthreads();
+        }
+    }
+    double emax = 0.0;
+    for (int q = 0; q < nb; ++q) emax = fmax(emax, fabs(Lc[q * m + q]));
+    // HV[r][a] = sum_u H[r][u] V[u][a] (into Aug)
+    if (t < nb2) {
+        const int r = t / nb, a2 = t % nb;
+        double acc = 0.0;
+        for (int u = 0; u < nb; ++u) acc += H[r * nb + u] * V[u * m + a2];
+        Aug[t] = acc;
+    }
     __syncthreads();
     if (t < nb2) {
-        double sg = 0.0, sh = 0.0;
-        for (int sl = 0; sl < S; ++sl) {
-            sg += pg[sl * nb2 + t];
-            sh += ph[sl * nb2 + t];
+        const int r = t / nb, c = t % nb;
+        double acc = 0.0;
+        for (int a2 = 0; a2 < nb; ++a2) {
+            const double ev = Lc[a2 * m + a2];
+            if (ev > PIVOT_TOL * emax) acc += Aug[r * nb + a2] * V[c * m + a2] / ev;
         }
-        G[t] = sg;
-        H[t] = sh;
-    }
-    __syncthreads();
-    if (t == 0) {
-        // Cholesky G = L L^T
-        double dmax = 0.0;
-        for (int a = 0; a < nb; ++a) dmax = fmax(dmax, G[a * nb + a]);
-        int bad = !(dmax > 0.0);
-        for (int a = 0; a < nb && !bad; ++a) {
-            for (int b = 0; b <= a; ++b) {
-                double s = G[a * nb + b];
-                for (int u = 0; u < b; ++u) s -= Lc[a * nb + u] * Lc[b * nb + u];
-                if (a == b) {
-                    if (!(s > PIVOT_TOL * dmax)) {
-                        bad = 1;
-                        break;
-                    }
-                    Lc[a * nb + a] = sqrt(s);
-                } else {
-                    Lc[a * nb + b] = s / Lc[b * nb + b];
-                }
-            }
-        }
-        bad_s = bad;
-        singular[li] = bad;
-    }
-    __syncthreads();
-    double *out = lamt + (int64_t)i * nb2;
-    if (!bad_s) {
-        if (t < nb) {
-            // row r of Lambda~ solves G y = H[r, :]^T
-            const int r = t;
-            double y[MAXNB];
-            for (int a = 0; a < nb; ++a) {
-                double s = H[r * nb + a];
-                for (int u = 0; u < a; ++u) s -= Lc[a * nb + u] * y[u];
-                y[a] = s / Lc[a * nb + a];
-            }
-            for (int a = nb - 1; a >= 0; --a) {
-                double s = y[a];
-                for (int u = a + 1; u < nb; ++u) s -= Lc[u * nb + a] * y[u];
-                y[a] = s / Lc[a * nb + a];
-            }
-            for (int a = 0; a < nb; ++a) out[r * nb + a] = y[a];
-        }
-    } else {
-        if (t == 0) {
-            // minimum-norm solution: Lambda~ = H pinv(G), pinv by eigen-decomposition
-            for (int a = 0; a < nb2; ++a) Lc[a] = G[a];
-            jacobi_eig(Lc, V, nb);
-            double emax = 0.0;
-            for (int a = 0; a < nb; ++a) emax = fmax(emax, fabs(Lc[a * nb + a]));
-            for (int r = 0; r < nb; ++r)
-                for (int c = 0; c < nb; ++c) {
-                    double s = 0.0;
-                    for (int a = 0; a < nb; ++a) {
-                        double ev = Lc[a * nb + a];
-                        if (ev > PIVOT_TOL * emax) {
-                            double hv = 0.0;
-                            for (int u = 0; u < nb; ++u) hv += H[r * nb + u] * V[u * nb + a];
-                            s += hv * V[c * nb + a] / ev;
-                        }
-                    }
-                    out[r * nb + c] = s;
-                }
-        }
+        out[t] = acc;
     }
 }
+
 
 // E_new,i = E_old,i - Lambda~_i M_i for list rows (on pattern(M_i)); other rows
 // are copied.  One workgroup per block row.
