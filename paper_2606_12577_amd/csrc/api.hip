@@ -84,6 +84,7 @@ void set_level(Ctx &c, Level &L, const cs_level &in, int li, int nlev, int64_t n
                                    " is not positive (elliptic prescaling needs a_kk > 0)");
     }
     L.colour_given = in.colour != nullptr;
+    L.layout_colour.clear();   // A changed: any colour layout is stale
     L.h_colour.clear();
     if (L.colour_given) {
         L.h_colour.assign(in.colour, in.colour + L.B);
@@ -246,6 +247,7 @@ cs_status cs_create(cs_ctx *out, int32_t device, void *stream) {
         delete h;
         return CS_EDEVICE;
     }
+    cs::pool_user(+1);
     *out = h;
     return CS_OK;
 }
@@ -266,6 +268,7 @@ void cs_destroy(cs_ctx ctx) {
     if (ctx->c.ev0) (void)hipEventDestroy(ctx->c.ev0);
     if (ctx->c.ev1) (void)hipEventDestroy(ctx->c.ev1);
     delete ctx;
+    cs::pool_user(-1);
 }
 
 const char *cs_last_error(cs_ctx ctx) { return ctx ? ctx->c.err.c_str() : g_create_err.c_str(); }
@@ -531,6 +534,7 @@ cs_status cs_load_setup(cs_ctx ctx, const char *path) {
                 if (o.mode == CS_MULTIPLICATIVE) {
                     need((int64_t)L.h_colour.size() == L.B, "missing colours in setup file", CS_EIO);
                     cs::build_colour_layout(c, L);
+                    L.layout_colour = L.h_colour;
                 }
             }
             get(&cnt, 8);

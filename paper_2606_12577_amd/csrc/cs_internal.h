@@ -28,6 +28,12 @@ struct Error {
 
 #define CS_LAUNCH_CHECK() CS_HIP(hipGetLastError())
 
+// Device memory cache (pool.hip): blocks are reused across allocations; a
+// freed block is released to the cache after a device synchronisation.
+void *pool_alloc(size_t bytes);   // throws CS_ENOMEM
+void pool_free(void *p);
+void pool_user(int delta);        // contexts alive; the cache is emptied when none are
+
 // Owning device buffer.
 template <class T>
 struct DBuf {
@@ -52,15 +58,11 @@ struct DBuf {
     void alloc(size_t count) {
         release();
         if (count == 0) return;
-        if (hipMalloc(reinterpret_cast<void **>(&p), count * sizeof(T)) != hipSuccess) {
-            p = nullptr;
-            (void)hipGetLastError();
-            fail(CS_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
-        }
+        p = static_cast<T *>(pool_alloc(count * sizeof(T)));
         n = count;
     }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) pool_free(p);
         p = nullptr;
         n = 0;
     }
@@ -112,6 +114,7 @@ struct Level {
     Sell sell;                        // all rows, natural order
     std::vector<Sell> csell;          // per-colour rows (multiplicative)
     DBuf<int32_t> clist;              // blocks sorted by colour
+    std::vector<int32_t> layout_colour;   // colours the colour layout was built for
     std::vector<int64_t> cptr;        // colour offsets into clist
     int chi = 0;
     DBuf<int32_t> colour;             // device colours

@@ -445,6 +445,7 @@ cs_status cs_mlp_create(cs_mlp *out, int32_t device, void *stream, int32_t n_in,
         delete h;
         return st;
     }
+    cs::pool_user(+1);
     *out = h;
     return CS_OK;
 }
@@ -454,6 +455,7 @@ void cs_mlp_destroy(cs_mlp h) {
     (void)hipSetDevice(h->m.device);
     if (h->m.h_acc) (void)hipHostFree(h->m.h_acc);
     delete h;
+    cs::pool_user(-1);
 }
 
 const char *cs_mlp_last_error(cs_mlp h) { return h ? h->m.err.c_str() : g_create_err.c_str(); }

@@ -1095,7 +1095,10 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
         CS_HIP(hipStreamSynchronize(s));
         for (int32_t v : hb)
             if (v) fail(CS_ECOLOR, "colouring is not proper: two coupled blocks share a colour");
-        build_colour_layout(c, L);
+        if (L.layout_colour != L.h_colour) {   // colours and A unchanged: keep the layout
+            build_colour_layout(c, L);
+            L.layout_colour = L.h_colour;
+        }
         std::vector<int32_t> hl(L.B);
         L.clist.download(hl.data(), B, s);
         CS_HIP(hipStreamSynchronize(s));
