@@ -201,6 +201,8 @@ struct Ctx {
     DBuf<double> ir_partial, ir_norm;
     DBuf<double> cg_r, cg_p, cg_q;      // conjugate-gradient vectors [n][R] (FP64)
     DBuf<double> cg_zq, cg_pq[2];       // per (system, RHS): (z, q_prev); (p, q) and (p, r), ping-pong
+    DBuf<int32_t> cg_sys_wg;            // batch: first workgroup of every system in the flat kernels
+    DBuf<double> cg_partial;            // batch: flat-kernel partial sums [workgroups][R]
     double *h_norm = nullptr;           // pinned host copy of ir_norm
     size_t h_norm_cap = 0;
     bool fuse_transfers = true;         // use the fused aggregation kernels when agg_k > 0

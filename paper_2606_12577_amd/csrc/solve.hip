@@ -726,14 +726,42 @@ __device__ __forceinline__ void flat_partials(const double (&v)[2], double *red,
     }
 }
 
+// Pair range of this workgroup.  One system: a grid-stride over all pairs.
+// A batch (sys_wg != null): workgroup b belongs to the system s with
+// sys_wg[s] <= b < sys_wg[s+1] and covers a chunk of that system's pairs only,
+// so its partial sums and scalars are those of one system.
+constexpr int64_t SYS_CHUNK = 4 * WG;   // pairs per workgroup in a batch
+
+struct PairRange {
+    int64_t begin, end, stride;
+    int sys;
+};
+
+template <int R>
+__device__ __forceinline__ PairRange pair_range(int64_t npairs, int nsys, const int32_t *__restrict__ sys_wg,
+                                                const int64_t *__restrict__ sys_ptr) {
+    if (!sys_wg) return {blockIdx.x * (int64_t)WG + threadIdx.x, npairs, (int64_t)gridDim.x * WG, 0};
+    int lo = 0, hi = nsys - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sys_wg[mid] <= (int)blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    const int64_t p0 = sys_ptr[lo] * R / 2, p1 = sys_ptr[lo + 1] * R / 2;
+    const int64_t b = blockIdx.x - sys_wg[lo];
+    const int64_t e = p0 + (b + 1) * SYS_CHUNK;
+    return {p0 + b * SYS_CHUNK + threadIdx.x, e < p1 ? e : p1, (int64_t)WG, lo};
+}
+
 // (z, q) per right-hand side
 template <typename T, int R>
-__global__ __launch_bounds__(WG) void k_cg_zq_flat(int64_t npairs, const T *__restrict__ z,
+__global__ __launch_bounds__(WG) void k_cg_zq_flat(int64_t npairs, int nsys, const int32_t *__restrict__ sys_wg,
+                                                   const int64_t *__restrict__ sys_ptr, const T *__restrict__ z,
                                                    const double *__restrict__ q, double *__restrict__ partial) {
     __shared__ double red[2 * WG];
     double v[2] = {0.0, 0.0};
-    const int64_t stride = (int64_t)gridDim.x * WG;
-    for (int64_t e2 = blockIdx.x * (int64_t)WG + threadIdx.x; e2 < npairs; e2 += stride) {
+    const PairRange pr = pair_range<R>(npairs, nsys, sys_wg, sys_ptr);
+    for (int64_t e2 = pr.begin; e2 < pr.end; e2 += pr.stride) {
         T zz[2];
         double qq[2];
         vload_nt<T, 2>(z + 2 * e2, zz);
@@ -746,22 +774,22 @@ __global__ __launch_bounds__(WG) void k_cg_zq_flat(int64_t npairs, const T *__re
 
 // p = z + beta p (first: p = z), beta = -(z, q_prev) / (p_prev, q_prev)
 template <typename T, int R>
-__global__ __launch_bounds__(WG) void k_cg_p_flat(int64_t npairs, const T *__restrict__ z,
+__global__ __launch_bounds__(WG) void k_cg_p_flat(int64_t npairs, int nsys, const int32_t *__restrict__ sys_wg,
+                                                  const int64_t *__restrict__ sys_ptr, const T *__restrict__ z,
                                                   const double *__restrict__ zq, const double *__restrict__ pq_prev,
                                                   double *__restrict__ p, int first) {
-    const int64_t stride = (int64_t)gridDim.x * WG;
-    const int64_t e2_0 = blockIdx.x * (int64_t)WG + threadIdx.x;
+    const PairRange pr = pair_range<R>(npairs, nsys, sys_wg, sys_ptr);
     double beta[2] = {0.0, 0.0};
     if (!first) {
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            const int k = (int)((2 * e2_0 + u) % R);
-            const double d = pq_prev[k];
-            beta[u] = d > 0.0 ? -zq[k] / d : 0.0;
+            const int k = (int)((2 * pr.begin + u) % R);
+            const double d = pq_prev[pr.sys * 2 * R + k];
+            beta[u] = d > 0.0 ? -zq[pr.sys * R + k] / d : 0.0;
             if (!isfinite(beta[u])) beta[u] = 0.0;
         }
     }
-    for (int64_t e2 = e2_0; e2 < npairs; e2 += stride) {
+    for (int64_t e2 = pr.begin; e2 < pr.end; e2 += pr.stride) {
         T zz[2];
         vload_nt<T, 2>(z + 2 * e2, zz);
         double pp[2] = {0.0, 0.0};
@@ -774,23 +802,24 @@ __global__ __launch_bounds__(WG) void k_cg_p_flat(int64_t npairs, const T *__res
 
 // x += alpha p, r -= alpha q, rt = r (working precision), partial r^2
 template <typename T, int R>
-__global__ __launch_bounds__(WG) void k_cg_update_flat(int64_t npairs, const double *__restrict__ pq,
-                                                       const double *__restrict__ p, const double *__restrict__ q,
-                                                       double *__restrict__ x, double *__restrict__ r,
-                                                       T *__restrict__ rt, double *__restrict__ partial) {
+__global__ __launch_bounds__(WG) void k_cg_update_flat(int64_t npairs, int nsys, const int32_t *__restrict__ sys_wg,
+                                                       const int64_t *__restrict__ sys_ptr,
+                                                       const double *__restrict__ pq, const double *__restrict__ p,
+                                                       const double *__restrict__ q, double *__restrict__ x,
+                                                       double *__restrict__ r, T *__restrict__ rt,
+                                                       double *__restrict__ partial) {
     __shared__ double red[2 * WG];
-    const int64_t stride = (int64_t)gridDim.x * WG;
-    const int64_t e2_0 = blockIdx.x * (int64_t)WG + threadIdx.x;
+    const PairRange pr = pair_range<R>(npairs, nsys, sys_wg, sys_ptr);
     double alpha[2];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-        const int k = (int)((2 * e2_0 + u) % R);
-        const double d = pq[k];
-        alpha[u] = d > 0.0 ? pq[R + k] / d : 0.0;
+        const int k = (int)((2 * pr.begin + u) % R);
+        const double d = pq[pr.sys * 2 * R + k];
+        alpha[u] = d > 0.0 ? pq[pr.sys * 2 * R + R + k] / d : 0.0;
         if (!isfinite(alpha[u])) alpha[u] = 0.0;
     }
     double v[2] = {0.0, 0.0};
-    for (int64_t e2 = e2_0; e2 < npairs; e2 += stride) {
+    for (int64_t e2 = pr.begin; e2 < pr.end; e2 += pr.stride) {
         double pp[2], qq[2], xx[2], rr[2];
         vload_nt<double, 2>(p + 2 * e2, pp);
         vload_nt<double, 2>(q + 2 * e2, qq);
@@ -809,6 +838,24 @@ __global__ __launch_bounds__(WG) void k_cg_update_flat(int64_t npairs, const dou
         vstore<T, 2>(rt + 2 * e2, o);
     }
     flat_partials<R>(v, red, partial);
+}
+
+// Per-system sums of per-workgroup partials: out[s][k] = sum over the
+// workgroups b of system s (sys_wg[s] <= b < sys_wg[s+1]) of partial[b][k].
+__global__ __launch_bounds__(256) void k_wg_to_sys(int W, const int32_t *__restrict__ sys_wg,
+                                                   const double *__restrict__ partial, double *__restrict__ out) {
+    __shared__ double red[256];
+    const int t = threadIdx.x;
+    const int64_t e0 = (int64_t)sys_wg[blockIdx.x] * W, e1 = (int64_t)sys_wg[blockIdx.x + 1] * W;
+    double s = 0.0;
+    for (int64_t e = e0 + t; e < e1; e += 256) s += partial[e];   // W divides 256: component t % W
+    red[t] = s;
+    __syncthreads();
+    for (int h = 128; h >= W; h >>= 1) {
+        if (t < h) red[t] += red[t + h];
+        __syncthreads();
+    }
+    if (t < W) out[(int64_t)blockIdx.x * W + t] = red[t];
 }
 
 // Fixed-order sum of the partials: out[k] = sum_g partial[g][k]
@@ -1448,7 +1495,28 @@ void solve_cg(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
             };
             const double vec = (double)L0.n * R * 8.0;
             const int64_t npairs = L0.n * R / 2;
-            const bool flat = !batch && (L0.n * R) % 2 == 0;   // flat pair streaming (one system, even length)
+            // flat pair streaming: one system of even length, or a batch with R even
+            // (pairs then never straddle two systems)
+            const bool flat = batch ? R % 2 == 0 : (L0.n * R) % 2 == 0;
+            int64_t Gf = G;                      // workgroups of the flat kernels
+            const int32_t *sys_wg = nullptr;
+            if (batch && flat) {
+                std::vector<int32_t> wg(nsys + 1, 0);
+                for (int q2 = 0; q2 < nsys; ++q2)
+                    wg[q2 + 1] = wg[q2] + (int32_t)ceil_div((c.sys_ptr[q2 + 1] - c.sys_ptr[q2]) * R / 2, SYS_CHUNK);
+                c.cg_sys_wg.upload(wg.data(), wg.size(), c.stream);
+                Gf = wg[nsys];
+                sys_wg = c.cg_sys_wg.get();
+                if (c.cg_partial.n < (size_t)(Gf * R)) c.cg_partial.alloc(Gf * R);
+            }
+            double *fpart = sys_wg ? c.cg_partial.get() : c.ir_partial.get();
+            auto reduce_flat = [&](double *out) {   // flat-kernel partials [Gf][R] -> out[nsys][R]
+                if (sys_wg)
+                    hipLaunchKernelGGL(k_wg_to_sys, dim3(nsys), dim3(256), 0, c.stream, R, sys_wg, fpart, out);
+                else
+                    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(1024), 0, c.stream, Gf, R, fpart, out);
+                CS_LAUNCH_CHECK();
+            };
             // ||b||^2 and rt = b; r = b; x = 0
             if (batch)
                 hipLaunchKernelGGL((k_ir_residual<T, R, true>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
@@ -1488,25 +1556,30 @@ void solve_cg(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
                 double *pq = c.cg_pq[cur].get();
                 int slot = trace_begin(c, CS_TRACE_REFINE, it ? vec + L0.n * R * sizeof(T) : 0.0);
                 if (it) {
-                    if (batch)
-                        hipLaunchKernelGGL((k_cg_zq<T, R, true>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
-                                           z, q, c.sys_het.get(), c.sys_spart.get(), c.rn2.get(), (double *)nullptr);
-                    else if (flat)
-                        hipLaunchKernelGGL((k_cg_zq_flat<T, R>), dim3(G), dim3(WG), 0, c.stream, npairs, z, q,
-                                           c.ir_partial.get());
-                    else
-                        hipLaunchKernelGGL((k_cg_zq<T, R, false>), dim3(G), dim3(WG), 0, c.stream, S.nrows,
-                                           S.nslices, z, q, (const int32_t *)nullptr, (double *)nullptr,
-                                           (double *)nullptr, c.ir_partial.get());
-                    CS_LAUNCH_CHECK();
-                    reduce(R, c.cg_zq.get());
+                    if (flat) {
+                        hipLaunchKernelGGL((k_cg_zq_flat<T, R>), dim3(Gf), dim3(WG), 0, c.stream, npairs, nsys, sys_wg,
+                                           c.sys_ptr_d.get(), z, q, fpart);
+                        CS_LAUNCH_CHECK();
+                        reduce_flat(c.cg_zq.get());
+                    } else {
+                        if (batch)
+                            hipLaunchKernelGGL((k_cg_zq<T, R, true>), dim3(G), dim3(WG), 0, c.stream, S.nrows,
+                                               S.nslices, z, q, c.sys_het.get(), c.sys_spart.get(), c.rn2.get(),
+                                               (double *)nullptr);
+                        else
+                            hipLaunchKernelGGL((k_cg_zq<T, R, false>), dim3(G), dim3(WG), 0, c.stream, S.nrows,
+                                               S.nslices, z, q, (const int32_t *)nullptr, (double *)nullptr,
+                                               (double *)nullptr, c.ir_partial.get());
+                        CS_LAUNCH_CHECK();
+                        reduce(R, c.cg_zq.get());
+                    }
                 }
                 if (!flat)
                     hipLaunchKernelGGL((k_cg_p<T, R>), dim3(grid_for(L0.n)), dim3(WG), 0, c.stream, L0.n, nsys,
                                        c.sys_ptr_d.get(), z, c.cg_zq.get(), pq_prev, p, it == 0 ? 1 : 0);
                 else
-                    hipLaunchKernelGGL((k_cg_p_flat<T, R>), dim3(G), dim3(WG), 0, c.stream, npairs, z, c.cg_zq.get(),
-                                       pq_prev, p, it == 0 ? 1 : 0);
+                    hipLaunchKernelGGL((k_cg_p_flat<T, R>), dim3(Gf), dim3(WG), 0, c.stream, npairs, nsys, sys_wg,
+                                       c.sys_ptr_d.get(), z, c.cg_zq.get(), pq_prev, p, it == 0 ? 1 : 0);
                 CS_LAUNCH_CHECK();
                 trace_end(c, slot);
                 slot = trace_begin(c, CS_TRACE_REFINE, S.nnz * 12.0 + 3.0 * vec);
@@ -1523,20 +1596,24 @@ void solve_cg(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
                 reduce(2 * R, pq);
                 trace_end(c, slot);
                 slot = trace_begin(c, CS_TRACE_REFINE, 6.0 * vec + L0.n * R * sizeof(T));
-                if (batch)
-                    hipLaunchKernelGGL((k_cg_update<T, R, true>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
-                                       nsys, c.sys_ptr_d.get(), pq, p, q, x, r, rt, c.sys_het.get(),
-                                       c.sys_spart.get(), c.rn2.get(), (double *)nullptr);
-                else if (flat)
-                    hipLaunchKernelGGL((k_cg_update_flat<T, R>), dim3(G), dim3(WG), 0, c.stream, npairs, pq, p, q, x,
-                                       r, rt, c.ir_partial.get());
-                else
-                    hipLaunchKernelGGL((k_cg_update<T, R, false>), dim3(G), dim3(WG), 0, c.stream, S.nrows,
-                                       S.nslices, nsys, c.sys_ptr_d.get(), pq, p, q, x, r, rt,
-                                       (const int32_t *)nullptr, (double *)nullptr, (double *)nullptr,
-                                       c.ir_partial.get());
-                CS_LAUNCH_CHECK();
-                reduce(R, c.ir_norm.get());
+                if (flat) {
+                    hipLaunchKernelGGL((k_cg_update_flat<T, R>), dim3(Gf), dim3(WG), 0, c.stream, npairs, nsys, sys_wg,
+                                       c.sys_ptr_d.get(), pq, p, q, x, r, rt, fpart);
+                    CS_LAUNCH_CHECK();
+                    reduce_flat(c.ir_norm.get());
+                } else {
+                    if (batch)
+                        hipLaunchKernelGGL((k_cg_update<T, R, true>), dim3(G), dim3(WG), 0, c.stream, S.nrows,
+                                           S.nslices, nsys, c.sys_ptr_d.get(), pq, p, q, x, r, rt, c.sys_het.get(),
+                                           c.sys_spart.get(), c.rn2.get(), (double *)nullptr);
+                    else
+                        hipLaunchKernelGGL((k_cg_update<T, R, false>), dim3(G), dim3(WG), 0, c.stream, S.nrows,
+                                           S.nslices, nsys, c.sys_ptr_d.get(), pq, p, q, x, r, rt,
+                                           (const int32_t *)nullptr, (double *)nullptr, (double *)nullptr,
+                                           c.ir_partial.get());
+                    CS_LAUNCH_CHECK();
+                    reduce(R, c.ir_norm.get());
+                }
                 trace_end(c, slot);
                 cur ^= 1;
             }
