@@ -402,6 +402,92 @@ def fcg(A, precond, b: np.ndarray, rtol: float = 1e-10, maxit: int = 100):
     return x, hist
 
 
+def gmres(A, precond, b: np.ndarray, restart: int = 30, rtol: float = 1e-10, maxit: int = 200,
+          flexible: bool = False, inner: float = 0.0):
+    """Restarted GMRES(m) around a preconditioner M (Sec. 3.1 uses the V-cycle
+    as a left preconditioner).  Independent Krylov spaces per column of b.
+
+    left (flexible=False): minimise ||M(b - A x)|| over x in
+        x_0 + K_k(M A, M r_0); the monitored residual is ||M(b - A x_k)||, the
+        norm Sec. 3.1 regresses rho on.
+    flexible (right): z_j = M(v_j), w = A z_j, x = x_0 + Z y; the monitored
+        residual is ||b - A x_k|| (M may change from step to step).
+
+    Arnoldi with modified Gram-Schmidt; y minimises ||beta e_1 - Hbar y||
+    (dense least squares).  The columns advance in lockstep: a column whose
+    estimate reaches rtol ||u_0|| (or inner times the cycle's starting norm,
+    inner > 0) or breaks down stops growing its basis, and the cycle ends when
+    every column has stopped or after `restart` steps.  Then x is updated,
+    the monitored residual is recomputed explicitly (it replaces the estimate
+    of the last step), and columns still above rtol start a new cycle.
+    Returns x and the history of max_j u_j(x_k) / u_j(x_0)."""
+    n, R = b.shape
+    x = np.zeros_like(b)
+
+    def monitored(xx):
+        r = b - A @ xx
+        return r if flexible else precond(r)
+
+    u = monitored(x)
+    res = np.linalg.norm(u, axis=0)
+    beta0 = np.where(res > 0, res, 1.0)
+    hist = [float(np.max(res / beta0))]
+    done = res <= rtol * beta0
+    it = 0
+    while not np.all(done) and it < maxit:
+        start = res.copy()
+        V = [np.where(start > 0, u / np.where(start > 0, start, 1.0), 0.0)]
+        Z = []
+        H = np.zeros((restart + 1, restart, R))
+        steps = np.zeros(R, dtype=int)
+        est = res.copy()
+        growing = ~done
+        for j in range(restart):
+            if it == maxit:
+                break
+            if flexible:
+                z = precond(V[j])
+                Z.append(z)
+                w = A @ z
+            else:
+                w = precond(A @ V[j])
+            for i in range(j + 1):
+                h = np.sum(w * V[i], axis=0)
+                H[i, j] = h
+                w = w - h * V[i]
+            hn = np.linalg.norm(w, axis=0)
+            H[j + 1, j] = hn
+            V.append(np.where(hn > 0, w / np.where(hn > 0, hn, 1.0), 0.0))
+            it += 1
+            for c in np.flatnonzero(growing):
+                Hb = H[: j + 2, : j + 1, c]
+                g = np.zeros(j + 2)
+                g[0] = start[c]
+                y = np.linalg.lstsq(Hb, g, rcond=None)[0]
+                steps[c] = j + 1
+                est[c] = np.linalg.norm(g - Hb @ y)
+                if est[c] <= max(rtol * beta0[c], inner * start[c]) or hn[c] == 0:
+                    growing[c] = False
+            hist.append(float(np.max(est / beta0)))
+            if not np.any(growing):
+                break
+        basis = Z if flexible else V
+        for c in np.flatnonzero(~done):
+            k = steps[c]
+            if k == 0:
+                continue
+            g = np.zeros(k + 1)
+            g[0] = start[c]
+            y = np.linalg.lstsq(H[: k + 1, :k, c], g, rcond=None)[0]
+            for i in range(k):
+                x[:, c] += y[i] * basis[i][:, c]
+        u = monitored(x)
+        res = np.linalg.norm(u, axis=0)
+        done = res <= rtol * beta0
+        hist[-1] = float(np.max(res / beta0))
+    return x, hist
+
+
 def rho_regression(hist: Sequence[float]) -> float:
     """Convergence rate from a least-squares line through (i, log r_i),
     i = 1..K (Sec. 3.1); r_0 is left out."""

@@ -589,3 +589,103 @@ def test_gram_condition_closed_form():
     c = O.gram_condition(G)
     np.testing.assert_allclose(c[:2], [4.0, 10.0], rtol=1e-12)   # 1e-20 is below the cut-off
     assert c[2] == 1.0
+
+
+# ---------------------------------------------------------------------------
+# GMRES (Sec. 3.1 driver): pinned to the minimisation property by brute force
+# over an explicit Krylov basis, to closed forms and to finite termination.
+# ---------------------------------------------------------------------------
+
+def _convdiff(n, peclet=0.7):
+    """Nonsymmetric tridiagonal test matrix (upwinded convection-diffusion)."""
+    return sp.diags([np.full(n - 1, -1.0 - peclet), np.full(n, 2.0 + peclet), np.full(n - 1, -1.0)],
+                    [-1, 0, 1]).tocsr()
+
+
+def _krylov(Op, v, k):
+    K = [v]
+    for _ in range(k - 1):
+        K.append(Op @ K[-1])
+    return np.stack(K, axis=1)
+
+
+def test_gmres_left_minimises_preconditioned_residual():
+    n = 14
+    A = _convdiff(n)
+    rng = stream(1, TEST, 60)
+    M = np.linalg.inv(A.toarray() + np.diag(rng.uniform(0.5, 1.5, n)))   # fixed, nonsymmetric
+    b = rng.uniform(-1, 1, size=(n, 1))
+    MA = M @ A.toarray()
+    Mb = M @ b[:, 0]
+    for k in range(1, 6):
+        x, hist = O.gmres(A, lambda r: M @ r, b, restart=20, rtol=0.0, maxit=k)
+        K = _krylov(MA, Mb, k)
+        y = np.linalg.lstsq(MA @ K, Mb, rcond=None)[0]
+        best = np.linalg.norm(Mb - MA @ K @ y)
+        assert len(hist) == k + 1
+        np.testing.assert_allclose(hist[-1] * np.linalg.norm(Mb), best, rtol=1e-8)
+        np.testing.assert_allclose(x[:, 0], K @ y, rtol=1e-8, atol=1e-12)
+
+
+def test_gmres_flexible_with_fixed_preconditioner_is_right_preconditioned_gmres():
+    n = 14
+    A = _convdiff(n, 1.3)
+    rng = stream(1, TEST, 61)
+    M = np.linalg.inv(A.toarray() + np.diag(rng.uniform(0.5, 1.5, n)))
+    b = rng.uniform(-1, 1, size=(n, 1))
+    AM = A.toarray() @ M
+    for k in range(1, 6):
+        x, hist = O.gmres(A, lambda r: M @ r, b, restart=20, rtol=0.0, maxit=k, flexible=True)
+        K = _krylov(AM, b[:, 0], k)
+        y = np.linalg.lstsq(AM @ K, b[:, 0], rcond=None)[0]
+        best = np.linalg.norm(b[:, 0] - AM @ K @ y)
+        np.testing.assert_allclose(hist[-1] * np.linalg.norm(b), best, rtol=1e-8)
+        np.testing.assert_allclose(x[:, 0], M @ K @ y, rtol=1e-8, atol=1e-12)
+
+
+def test_gmres_restart_one_is_the_minimal_residual_iteration():
+    n = 12
+    A = _convdiff(n)
+    rng = stream(1, TEST, 62)
+    b = rng.uniform(-1, 1, size=(n, 2))
+    x, hist = O.gmres(A, lambda r: r, b, restart=1, rtol=0.0, maxit=5)
+    xr = np.zeros_like(b)
+    for _ in range(5):
+        r = b - A @ xr
+        Ar = A @ r
+        xr = xr + np.sum(r * Ar, axis=0) / np.sum(Ar * Ar, axis=0) * r
+    np.testing.assert_allclose(x, xr, rtol=1e-10)
+    rn = np.linalg.norm(b - A @ xr, axis=0) / np.linalg.norm(b, axis=0)
+    np.testing.assert_allclose(hist[-1], np.max(rn), rtol=1e-10)
+
+
+def test_gmres_terminates_within_n_steps_and_columns_are_independent():
+    n = 10
+    A = _convdiff(n, 2.0)
+    rng = stream(1, TEST, 63)
+    b = rng.uniform(-1, 1, size=(n, 3))
+    b[:, 2] = A @ np.ones(n)   # another right-hand side
+    x, hist = O.gmres(A, lambda r: r, b, restart=30, rtol=1e-12, maxit=30)
+    assert len(hist) - 1 <= n and hist[-1] <= 1e-12
+    np.testing.assert_allclose(x, np.linalg.solve(A.toarray(), b), rtol=1e-9)
+    # without a restart every column follows its own Krylov space
+    for c in range(3):
+        xc, _ = O.gmres(A, lambda r: r, b[:, c:c + 1], restart=30, rtol=0.0, maxit=4)
+        xa, _ = O.gmres(A, lambda r: r, b, restart=30, rtol=0.0, maxit=4)
+        np.testing.assert_allclose(xa[:, c], xc[:, 0], rtol=1e-12, atol=1e-15)
+
+
+def test_gmres_with_vcycle_left_and_flexible():
+    p = fd.interface3d(16, nrhs=2)
+    sm = O.setup_hierarchy(p.levels, 3)
+    pre = lambda r: O.vcycle(p.levels, sm, r, "FF")
+    A = p.levels[0].A
+    x, h = O.gmres(A, pre, p.rhs, rtol=1e-10, maxit=60)
+    assert h[-1] <= 1e-10
+    # the left residual is ||V(b - A x)||: the true residual follows within the V-cycle's conditioning
+    r = p.rhs - A @ x
+    assert np.max(np.linalg.norm(r, axis=0) / np.linalg.norm(p.rhs, axis=0)) <= 1e-8
+    xf, hf = O.gmres(A, pre, p.rhs, rtol=1e-10, maxit=60, flexible=True)
+    r = p.rhs - A @ xf
+    np.testing.assert_allclose(hf[-1], np.max(np.linalg.norm(r, axis=0) / np.linalg.norm(p.rhs, axis=0)), rtol=1e-9)
+    assert hf[-1] <= 1e-10 and abs(len(hf) - len(h)) <= 2
