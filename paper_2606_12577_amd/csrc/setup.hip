@@ -179,29 +179,191 @@ __global__ __launch_bounds__(WG) void k_union(const int32_t *__restrict__ list, 
     }
 }
 
-// exclusive scan of cnt[0, n) into ptr[0, n]; one workgroup of 1024 threads
-__global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ cnt, int64_t n, int32_t *__restrict__ ptr,
-                                               int64_t *__restrict__ total_out) {
-    __shared__ int64_t part[1025];
+// The same union, one wavefront per output row, for rows of at most 64 K
+// candidates (and, for SRC_E, at most 64 neighbours): the candidates sit in K
+// registers per lane (element e = 64 r + lane), are sorted by a bitonic network
+// of register exchanges (distance >= 64) and lane shuffles (distance < 64), and
+// the distinct values are compacted with ballots.  The host picks K from an
+// upper bound of the candidate count; a row above it sets err (cannot happen).
+template <int K, int SRC, bool FILL>
+__global__ __launch_bounds__(WG) void k_union_wave(const int32_t *__restrict__ list, int nlist, int nb,
+                                                   const int32_t *__restrict__ sptr,
+                                                   const int32_t *__restrict__ scol,
+                                                   const int32_t *__restrict__ eptr,
+                                                   const int32_t *__restrict__ ecol, int32_t *__restrict__ out_cnt,
+                                                   const int32_t *__restrict__ out_ptr, int32_t *__restrict__ out_col,
+                                                   int32_t *__restrict__ err) {
+    constexpr int P = 64 * K;
+    __shared__ int32_t offs_s[WG / 64][65], start_s[WG / 64][64];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int li = blockIdx.x * (WG / 64) + wv;
+    const bool live = li < nlist;
+    const int i = live ? (list ? list[li] : li) : 0;
+    int total = 0, lo = 0, deg = 0;
+    if (SRC == SRC_SCALAR) {
+        if (live) {
+            lo = sptr[(int64_t)i * nb];
+            total = sptr[(int64_t)(i + 1) * nb] - lo;
+        }
+    } else {
+        if (live) {
+            lo = sptr[i];
+            deg = sptr[i + 1] - lo;
+        }
+        int len = 0;
+        if (lane < deg) {
+            const int j = scol[lo + lane];
+            start_s[wv][lane] = eptr[j];
+            len = eptr[j + 1] - eptr[j];
+        }
+        int inc = len;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += y;
+        }
+        offs_s[wv][lane + 1] = inc;
+        if (lane == 0) offs_s[wv][0] = 0;
+        total = __shfl(inc, 63, 64);
+        if (deg > 64) total = P + 1;
+    }
+    __syncthreads();   // every wavefront reaches it: offs_s and start_s are visible
+    if (total > P) {
+        if (lane == 0) {
+            err[li] = 1;
+            if (!FILL) out_cnt[li] = 0;
+        }
+        return;
+    }
+    int32_t v[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        const int e = r * 64 + lane;
+        v[r] = INT32_MAX;
+        if (e < total) {
+            if (SRC == SRC_SCALAR) {
+                v[r] = scol[lo + e] / nb;
+            } else {
+                int a = 0, b = deg;   // offs[a] <= e < offs[b]
+                while (b - a > 1) {
+                    const int m = (a + b) >> 1;
+                    if (offs_s[wv][m] <= e) a = m;
+                    else b = m;
+                }
+                v[r] = ecol[start_s[wv][a] + (e - offs_s[wv][a])];
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 2; k <= P; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= 64) {
+#pragma unroll
+                for (int r = 0; r < K; ++r) {
+                    const int rp = r ^ (j >> 6);
+                    if (rp > r) {
+                        const bool up = ((r * 64 + lane) & k) == 0;
+                        const int32_t x = v[r], y = v[rp];
+                        if ((x > y) == up) {
+                            v[r] = y;
+                            v[rp] = x;
+                        }
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < K; ++r) {
+                    const int32_t y = __shfl_xor(v[r], j, 64);
+                    const bool up = ((r * 64 + lane) & k) == 0;
+                    const bool lower = (lane & j) == 0;
+                    v[r] = (lower == up) ? min(v[r], y) : max(v[r], y);
+                }
+            }
+        }
+    }
+    int base = live ? (FILL ? out_ptr[li] : 0) : 0;
+    int count = 0;
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        // element e - 1: lane - 1 of register r, or lane 63 of register r - 1
+        const int32_t up1 = __shfl_up(v[r], 1, 64);
+        const int32_t last = r > 0 ? __shfl(v[r > 0 ? r - 1 : 0], 63, 64) : INT32_MIN;
+        const int32_t prev = lane == 0 ? last : up1;
+        const bool keep = v[r] != INT32_MAX && prev != v[r];
+        const uint64_t mask = __ballot(keep);
+        if (FILL && keep) {
+            const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+            out_col[base + count + below] = v[r];
+        }
+        count += __popcll(mask);
+    }
+    if (!FILL && live && lane == 0) out_cnt[li] = count;
+}
+
+// Exclusive prefix sum of n counts in three passes: every workgroup scans 1024
+// counts and records its total, one workgroup scans the totals, and the
+// offsets are added (coalesced; the totals are exact in 64 bits).
+constexpr int SCAN_TILE = 1024;
+
+__device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t *sh, int64_t &total) {
+    // 256 threads, Hillis-Steele in LDS
     const int t = threadIdx.x;
-    const int64_t chunk = (n + 1023) / 1024;
-    const int64_t a0 = t * chunk, a1 = min(n, a0 + chunk);
-    int64_t s = 0;
-    for (int64_t a = a0; a < a1; ++a) s += cnt[a];
-    part[t + 1] = s;
+    sh[t] = v;
     __syncthreads();
-    if (t == 0) {
-        part[0] = 0;
-        for (int q = 0; q < 1024; ++q) part[q + 1] += part[q];
-        total_out[0] = part[1024];
-        ptr[n] = (int32_t)part[1024];
+    for (int o = 1; o < 256; o <<= 1) {
+        const int64_t add = t >= o ? sh[t - o] : 0;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
     }
+    total = sh[255];
+    const int64_t incl = sh[t];
     __syncthreads();
-    int64_t o = part[t];
-    for (int64_t a = a0; a < a1; ++a) {
-        ptr[a] = (int32_t)o;
-        o += cnt[a];
+    return incl - v;
+}
+
+__global__ __launch_bounds__(256) void k_scan_tiles(const int32_t *__restrict__ cnt, int64_t n,
+                                                    int32_t *__restrict__ ptr, int64_t *__restrict__ tile_sum) {
+    __shared__ int64_t sh[256];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x * 4;
+    int64_t v[4], local = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        v[u] = base + u < n ? cnt[base + u] : 0;
+        local += v[u];
     }
+    int64_t total;
+    int64_t o = block_exclusive_scan(local, sh, total);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        if (base + u < n) ptr[base + u] = (int32_t)o;
+        o += v[u];
+    }
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(256) void k_scan_sums(int64_t ntiles, int64_t *__restrict__ tile_sum,
+                                                   int64_t *__restrict__ total_out) {
+    __shared__ int64_t sh[256];
+    int64_t carry = 0;
+    for (int64_t b0 = 0; b0 < ntiles; b0 += 256) {
+        const int64_t b = b0 + threadIdx.x;
+        const int64_t v = b < ntiles ? tile_sum[b] : 0;
+        int64_t total;
+        const int64_t o = block_exclusive_scan(v, sh, total);
+        if (b < ntiles) tile_sum[b] = carry + o;
+        carry += total;
+    }
+    if (threadIdx.x == 0) total_out[0] = carry;
+}
+
+__global__ __launch_bounds__(256) void k_scan_add(int64_t n, const int64_t *__restrict__ tile_off,
+                                                  const int64_t *__restrict__ total, int32_t *__restrict__ ptr) {
+    const int64_t a = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (a < n) ptr[a] += (int32_t)tile_off[a / SCAN_TILE];
+    if (a == 0) ptr[n] = (int32_t)total[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -560,6 +722,64 @@ __global__ __launch_bounds__(WG) void k_gram_solve(const int32_t *__restrict__ l
 }
 
 
+// Point blocks (n = 1): one wavefront per list row, four rows per workgroup.
+// M_i[p] = sum_j a~_ij E_j[col p]; Lambda~_i = H_i / G_i with G_i = sum M_i^2,
+// H_i = sum E_i M_i (0 when G_i = 0, the minimum-norm solution).  Lane striding
+// and the reduction order are those of the blocked kernels.
+__global__ __launch_bounds__(WG) void k_rowprod_point(int nl, const int32_t *__restrict__ list,
+                                                      const int32_t *__restrict__ abptr,
+                                                      const int32_t *__restrict__ abcol,
+                                                      const double *__restrict__ abval,
+                                                      const int32_t *__restrict__ eptr,
+                                                      const int32_t *__restrict__ ecol,
+                                                      const double *__restrict__ eval,
+                                                      const int32_t *__restrict__ mptr,
+                                                      const int32_t *__restrict__ mcol, double *__restrict__ mval) {
+    const int w = blockIdx.x * (WG / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (w >= nl) return;
+    const int i = list[w];
+    const int alo = abptr[i], deg = abptr[i + 1] - alo;
+    const int mlo = mptr[w], k = mptr[w + 1] - mlo;
+    for (int p = lane; p < k; p += 64) {
+        const int col = mcol[mlo + p];
+        double acc = 0.0;
+        for (int jj = 0; jj < deg; ++jj) {
+            const int j = abcol[alo + jj];
+            const int q = bsearch_i32(ecol, eptr[j], eptr[j + 1], col);
+            if (q >= 0) acc += abval[alo + jj] * eval[q];
+        }
+        mval[mlo + p] = acc;
+    }
+}
+
+__global__ __launch_bounds__(WG) void k_gram_point(int nl, const int32_t *__restrict__ list,
+                                                   const int32_t *__restrict__ mptr, const int32_t *__restrict__ mcol,
+                                                   const double *__restrict__ mval, const int32_t *__restrict__ eptr,
+                                                   const int32_t *__restrict__ ecol, const double *__restrict__ eval,
+                                                   double *__restrict__ lamt, int32_t *__restrict__ singular) {
+    const int w = blockIdx.x * (WG / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (w >= nl) return;
+    const int i = list[w];
+    const int mlo = mptr[w], k = mptr[w + 1] - mlo;
+    const int elo = eptr[i], ek = eptr[i + 1] - elo;
+    double g = 0.0, h = 0.0;
+    for (int p = lane; p < k; p += 64) g += mval[mlo + p] * mval[mlo + p];
+    for (int q = lane; q < ek; q += 64) {
+        const int pb = bsearch_i32(mcol, mlo, mlo + k, ecol[elo + q]);
+        if (pb >= 0) h += eval[elo + q] * mval[pb];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        g += __shfl_xor(g, off, 64);
+        h += __shfl_xor(h, off, 64);
+    }
+    if (lane == 0) {
+        const bool bad = !(g > 0.0);
+        singular[w] = bad ? 1 : 0;
+        lamt[i] = bad ? 0.0 : h / g;
+    }
+}
+
 // E_new,i = E_old,i - Lambda~_i M_i for list rows (on pattern(M_i)); other rows
 // are copied.  One workgroup per block row.
 __global__ __launch_bounds__(WG) void k_eupdate(int B, int nb, const int32_t *__restrict__ pos_in_list,
@@ -696,6 +916,53 @@ __global__ void k_iota(int32_t *a, int n) {
 __global__ void k_fill_i32(int32_t *a, int64_t n, int32_t v) {
     int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t < n) a[t] = v;
+}
+
+// max over r < n of ptr[(r + 1) stride] - ptr[r stride] (out starts at 0)
+__global__ __launch_bounds__(WG) void k_max_span(int64_t n, int stride, const int32_t *__restrict__ ptr,
+                                                 int32_t *__restrict__ out) {
+    __shared__ int32_t red[WG / 64];
+    const int64_t r = blockIdx.x * (int64_t)WG + threadIdx.x;
+    int32_t m = r < n ? ptr[(r + 1) * stride] - ptr[r * stride] : 0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < WG / 64; ++w) m = max(m, red[w]);
+        atomicMax(out, m);
+    }
+}
+
+// out += sum (SUM) or out = max(out, max) (!SUM) of a[0, n) (out starts at 0)
+template <bool SUM>
+__global__ __launch_bounds__(WG) void k_reduce_i32(int64_t n, const int32_t *__restrict__ a,
+                                                   int32_t *__restrict__ out) {
+    __shared__ int32_t red[WG / 64];
+    int32_t m = 0;
+    for (int64_t r = blockIdx.x * (int64_t)WG + threadIdx.x; r < n; r += (int64_t)gridDim.x * WG)
+        m = SUM ? m + a[r] : max(m, a[r]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const int32_t y = __shfl_xor(m, off, 64);
+        m = SUM ? m + y : max(m, y);
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < WG / 64; ++w) m = SUM ? m + red[w] : max(m, red[w]);
+        if (SUM) atomicAdd(out, m);
+        else atomicMax(out, m);
+    }
+}
+
+// block-row lengths of the updated E: list rows take |pattern(M_i)|, the others keep |pattern(E_i)|
+__global__ void k_ecount(int B, const int32_t *__restrict__ pos, const int32_t *__restrict__ mptr,
+                         const int32_t *__restrict__ eptr, int32_t *__restrict__ cnt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= B) return;
+    const int q = pos[i];
+    cnt[i] = q >= 0 ? mptr[q + 1] - mptr[q] : eptr[i + 1] - eptr[i];
 }
 
 __global__ void k_unscale(int64_t B, int nb, const double *__restrict__ w, const double *__restrict__ lamt,
@@ -854,7 +1121,13 @@ struct EMat {
 
 int64_t scan_counts(Ctx &c, const DBuf<int32_t> &cnt, int64_t n, DBuf<int32_t> &ptr, DBuf<int64_t> &tot) {
     ptr.alloc(n + 1);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, c.stream, cnt.get(), n, ptr.get(), tot.get());
+    const int64_t ntiles = std::max<int64_t>(ceil_div(n, SCAN_TILE), 1);
+    DBuf<int64_t> tiles(ntiles);
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(256), 0, c.stream, cnt.get(), n, ptr.get(),
+                       tiles.get());
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, c.stream, ntiles, tiles.get(), tot.get());
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)ceil_div(n + 1, 256)), dim3(256), 0, c.stream, n, tiles.get(),
+                       tot.get(), ptr.get());
     CS_LAUNCH_CHECK();
     int64_t total = 0;
     tot.download(&total, 1, c.stream);
@@ -863,12 +1136,23 @@ int64_t scan_counts(Ctx &c, const DBuf<int32_t> &cnt, int64_t n, DBuf<int32_t> &
     return total;
 }
 
-void check_flags(Ctx &c, const DBuf<int32_t> &flags, int64_t n, const char *what) {
-    std::vector<int32_t> h(n);
-    flags.download(h.data(), n, c.stream);
+// sum (or max) of n device ints, on the host
+int32_t reduce_i32(Ctx &c, const int32_t *a, int64_t n, bool sum) {
+    DBuf<int32_t> m(1);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(WG), 0, c.stream, m.get(), (int64_t)1, 0);
+    const unsigned g = (unsigned)std::min<int64_t>(std::max<int64_t>(ceil_div(n, WG), 1), 4096);
+    if (sum) hipLaunchKernelGGL(k_reduce_i32<true>, dim3(g), dim3(WG), 0, c.stream, n, a, m.get());
+    else hipLaunchKernelGGL(k_reduce_i32<false>, dim3(g), dim3(WG), 0, c.stream, n, a, m.get());
+    CS_LAUNCH_CHECK();
+    int32_t h = 0;
+    m.download(&h, 1, c.stream);
     CS_HIP(hipStreamSynchronize(c.stream));
-    for (int64_t a = 0; a < n; ++a)
-        if (h[a]) fail(CS_EINVAL, std::string(what) + " exceeds the per-row capacity of the symbolic kernels");
+    return h;
+}
+
+void check_flags(Ctx &c, const DBuf<int32_t> &flags, int64_t n, const char *what) {
+    if (reduce_i32(c, flags.get(), n, false))
+        fail(CS_EINVAL, std::string(what) + " exceeds the per-row capacity of the symbolic kernels");
 }
 
 }  // namespace
@@ -1003,20 +1287,58 @@ void build_colour_layout(Ctx &c, Level &L) {
 
 namespace {
 
+int max_span(Ctx &c, int64_t n, int stride, const int32_t *ptr) {
+    DBuf<int32_t> m(1);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(WG), 0, c.stream, m.get(), (int64_t)1, 0);
+    hipLaunchKernelGGL(k_max_span, dim3(grid_for(std::max<int64_t>(n, 1))), dim3(WG), 0, c.stream, n, stride, ptr,
+                       m.get());
+    CS_LAUNCH_CHECK();
+    int32_t h = 0;
+    m.download(&h, 1, c.stream);
+    CS_HIP(hipStreamSynchronize(c.stream));
+    return h;
+}
+
+// Union of sorted column lists for nl rows: one wavefront per row when every
+// row has at most 512 candidates (the bound is an upper bound of the candidate
+// count), else one workgroup per row.
+template <int SRC, bool FILL>
+void launch_union(hipStream_t s, int64_t bound, const int32_t *list, int nl, int nb, const int32_t *sptr,
+                  const int32_t *scol, const int32_t *eptr, const int32_t *ecol, int32_t *cnt, const int32_t *optr,
+                  int32_t *ocol, int32_t *err) {
+    const dim3 gw((unsigned)ceil_div(nl, WG / 64));
+    if (bound <= 64)
+        hipLaunchKernelGGL((k_union_wave<1, SRC, FILL>), gw, dim3(WG), 0, s, list, nl, nb, sptr, scol, eptr, ecol,
+                           cnt, optr, ocol, err);
+    else if (bound <= 128)
+        hipLaunchKernelGGL((k_union_wave<2, SRC, FILL>), gw, dim3(WG), 0, s, list, nl, nb, sptr, scol, eptr, ecol,
+                           cnt, optr, ocol, err);
+    else if (bound <= 256)
+        hipLaunchKernelGGL((k_union_wave<4, SRC, FILL>), gw, dim3(WG), 0, s, list, nl, nb, sptr, scol, eptr, ecol,
+                           cnt, optr, ocol, err);
+    else if (bound <= 512)
+        hipLaunchKernelGGL((k_union_wave<8, SRC, FILL>), gw, dim3(WG), 0, s, list, nl, nb, sptr, scol, eptr, ecol,
+                           cnt, optr, ocol, err);
+    else
+        hipLaunchKernelGGL((k_union<SRC, FILL>), dim3(nl), dim3(WG), 0, s, list, nl, nb, sptr, scol, eptr, ecol, cnt,
+                           optr, ocol, err);
+}
+
 void block_pattern_of_A(Ctx &c, Level &L, BPattern &ap) {
     const int B = (int)L.B;
     DBuf<int32_t> cnt(B), err(B);
     DBuf<int64_t> tot(1);
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(B)), dim3(WG), 0, c.stream, err.get(), (int64_t)B, 0);
-    hipLaunchKernelGGL((k_union<SRC_SCALAR, false>), dim3(B), dim3(WG), 0, c.stream, nullptr, B, (int)L.nb,
-                       L.a_ptr.get(), L.a_col.get(), nullptr, nullptr, cnt.get(), nullptr, nullptr, err.get());
+    const int64_t bound = max_span(c, B, (int)L.nb, L.a_ptr.get());
+    launch_union<SRC_SCALAR, false>(c.stream, bound, nullptr, B, (int)L.nb, L.a_ptr.get(), L.a_col.get(), nullptr,
+                                    nullptr, cnt.get(), nullptr, nullptr, err.get());
     CS_LAUNCH_CHECK();
     check_flags(c, err, B, "block row of A");
     ap.rows = B;
     ap.nnzb = scan_counts(c, cnt, B, ap.ptr, tot);
     ap.col.alloc(ap.nnzb);
-    hipLaunchKernelGGL((k_union<SRC_SCALAR, true>), dim3(B), dim3(WG), 0, c.stream, nullptr, B, (int)L.nb,
-                       L.a_ptr.get(), L.a_col.get(), nullptr, nullptr, nullptr, ap.ptr.get(), ap.col.get(), err.get());
+    launch_union<SRC_SCALAR, true>(c.stream, bound, nullptr, B, (int)L.nb, L.a_ptr.get(), L.a_col.get(), nullptr,
+                                   nullptr, nullptr, ap.ptr.get(), ap.col.get(), err.get());
     CS_LAUNCH_CHECK();
 }
 
@@ -1082,7 +1404,10 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
                        L.a_val.get(), L.w.get(), L.n, nb, ap.ptr.get(), ap.col.get(), abval.get());
     CS_LAUNCH_CHECK();
     // colour lists
-    std::vector<std::vector<int32_t>> lists;
+    // fit lists: the active blocks of one colour at a time (multiplicative), or all
+    // active blocks at once (additive)
+    std::vector<std::pair<const int32_t *, int>> lists;
+    DBuf<int32_t> all_blocks;
     if (o.mode == CS_MULTIPLICATIVE) {
         if (!L.colour_given) greedy_colouring(c, L, ap);
         L.colour.upload(L.h_colour.data(), B, s);
@@ -1099,18 +1424,14 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
             build_colour_layout(c, L);
             L.layout_colour = L.h_colour;
         }
-        std::vector<int32_t> hl(L.B);
-        L.clist.download(hl.data(), B, s);
-        CS_HIP(hipStreamSynchronize(s));
-        for (int k = 0; k < L.chi; ++k) {
-            lists.emplace_back();
-            for (int64_t q = L.cptr[k]; q < L.cptr[k + 1]; ++q)
-                if (hl[q] < B_act) lists.back().push_back(hl[q]);
-        }
+        for (int k = 0; k < L.chi; ++k)
+            lists.emplace_back(L.cblk.get() + L.cblk_ptr[k], (int)(L.cblk_ptr[k + 1] - L.cblk_ptr[k]));
     } else {
         L.chi = 1;
-        lists.emplace_back(B_act);
-        std::iota(lists[0].begin(), lists[0].end(), 0);
+        all_blocks.alloc(std::max(B_act, 1));
+        hipLaunchKernelGGL(k_iota, dim3(grid_for(std::max(B_act, 1))), dim3(WG), 0, s, all_blocks.get(), B_act);
+        CS_LAUNCH_CHECK();
+        lists.emplace_back(all_blocks.get(), B_act);
     }
     // E_0 = I
     EMat E;
@@ -1136,65 +1457,64 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
     keep_pattern(E.pat);
     DBuf<double> lamt((size_t)depth * B * nb2);
     CS_HIP(hipMemsetAsync(lamt.get(), 0, lamt.bytes(), s));   // rows of direct segments get no smoother
-    DBuf<int32_t> pos(B), dlist, sing, cnt, err(B);
+    DBuf<int32_t> pos(B), sing, cnt, err(B);
     DBuf<int64_t> tot(1);
+    const int maxdeg = max_span(c, B, 1, ap.ptr.get());
     L.singular = 0;
     const int nsteps = depth * (int)lists.size();
     int step = 0;
     for (int ell = 1; ell <= depth; ++ell) {
         for (size_t kcol = 0; kcol < lists.size(); ++kcol, ++step) {
-            const std::vector<int32_t> &list = lists[kcol];
-            const int nl = (int)list.size();
+            const int32_t *dlist = lists[kcol].first;
+            const int nl = lists[kcol].second;
             if (nl == 0) continue;
-            dlist.upload(list.data(), nl, s);
             hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(B)), dim3(WG), 0, s, pos.get(), (int64_t)B, -1);
-            hipLaunchKernelGGL(k_pos_in_list, dim3(grid_for(nl)), dim3(WG), 0, s, dlist.get(), nl, pos.get());
+            hipLaunchKernelGGL(k_pos_in_list, dim3(grid_for(nl)), dim3(WG), 0, s, dlist, nl, pos.get());
             hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(B)), dim3(WG), 0, s, err.get(), (int64_t)B, 0);
             // symbolic: pattern(M_i) for the list rows
             cnt.alloc(nl);
             BPattern mp;
             mp.rows = nl;
-            hipLaunchKernelGGL((k_union<SRC_E, false>), dim3(nl), dim3(WG), 0, s, dlist.get(), nl, nb, ap.ptr.get(),
-                               ap.col.get(), E.pat.ptr.get(), E.pat.col.get(), cnt.get(), nullptr, nullptr, err.get());
+            const int64_t bound = maxdeg <= 64 ? (int64_t)maxdeg * max_span(c, B, 1, E.pat.ptr.get()) : INT64_MAX;
+            launch_union<SRC_E, false>(s, bound, dlist, nl, nb, ap.ptr.get(), ap.col.get(), E.pat.ptr.get(),
+                                       E.pat.col.get(), cnt.get(), nullptr, nullptr, err.get());
             CS_LAUNCH_CHECK();
             check_flags(c, err, nl, "fill of a residual row");
             mp.nnzb = scan_counts(c, cnt, nl, mp.ptr, tot);
             mp.col.alloc(mp.nnzb);
-            hipLaunchKernelGGL((k_union<SRC_E, true>), dim3(nl), dim3(WG), 0, s, dlist.get(), nl, nb, ap.ptr.get(),
-                               ap.col.get(), E.pat.ptr.get(), E.pat.col.get(), nullptr, mp.ptr.get(), mp.col.get(),
-                               err.get());
+            launch_union<SRC_E, true>(s, bound, dlist, nl, nb, ap.ptr.get(), ap.col.get(), E.pat.ptr.get(),
+                                      E.pat.col.get(), nullptr, mp.ptr.get(), mp.col.get(), err.get());
             CS_LAUNCH_CHECK();
             // numeric: M, normal equations, Lambda~
             DBuf<double> mval((size_t)mp.nnzb * nb2);
-            if (!rowprod_nb(s, nb, nl, dlist.get(), ap, abval.get(), E, mp, mval.get()))
-                hipLaunchKernelGGL(k_rowprod, dim3(nl), dim3(WG), 0, s, dlist.get(), nb, ap.ptr.get(), ap.col.get(),
+            if (nb == 1)
+                hipLaunchKernelGGL(k_rowprod_point, dim3((unsigned)ceil_div(nl, WG / 64)), dim3(WG), 0, s, nl,
+                                   dlist, ap.ptr.get(), ap.col.get(), abval.get(), E.pat.ptr.get(),
+                                   E.pat.col.get(), E.val.get(), mp.ptr.get(), mp.col.get(), mval.get());
+            else if (!rowprod_nb(s, nb, nl, dlist, ap, abval.get(), E, mp, mval.get()))
+                hipLaunchKernelGGL(k_rowprod, dim3(nl), dim3(WG), 0, s, dlist, nb, ap.ptr.get(), ap.col.get(),
                                    abval.get(), E.pat.ptr.get(), E.pat.col.get(), E.val.get(), mp.ptr.get(),
                                    mp.col.get(), mval.get());
             CS_LAUNCH_CHECK();
             sing.alloc(nl);
             double *lam_l = lamt.get() + (size_t)(ell - 1) * B * nb2;
-            hipLaunchKernelGGL(k_gram_solve, dim3(nl), dim3(WG), 0, s, dlist.get(), nb, mp.ptr.get(), mp.col.get(),
-                               mval.get(), E.pat.ptr.get(), E.pat.col.get(), E.val.get(), lam_l, sing.get());
+            if (nb == 1)
+                hipLaunchKernelGGL(k_gram_point, dim3((unsigned)ceil_div(nl, WG / 64)), dim3(WG), 0, s, nl,
+                                   dlist, mp.ptr.get(), mp.col.get(), mval.get(), E.pat.ptr.get(),
+                                   E.pat.col.get(), E.val.get(), lam_l, sing.get());
+            else
+                hipLaunchKernelGGL(k_gram_solve, dim3(nl), dim3(WG), 0, s, dlist, nb, mp.ptr.get(),
+                                   mp.col.get(), mval.get(), E.pat.ptr.get(), E.pat.col.get(), E.val.get(), lam_l,
+                                   sing.get());
             CS_LAUNCH_CHECK();
-            {
-                std::vector<int32_t> hs(nl);
-                sing.download(hs.data(), nl, s);
-                CS_HIP(hipStreamSynchronize(s));
-                for (int32_t v : hs) L.singular += v;
-            }
+            L.singular += reduce_i32(c, sing.get(), nl, true);
             if (step + 1 == nsteps) break;   // the last residual is never needed
             // E update on pattern(M) for list rows, copy for others
             {
                 DBuf<int32_t> ncnt(B);
-                std::vector<int32_t> hc(B);
-                // counts: list rows take |M_i|, others keep |E_i|
-                std::vector<int32_t> mp_h(nl + 1), ep_h(B + 1);
-                mp.ptr.download(mp_h.data(), nl + 1, s);
-                E.pat.ptr.download(ep_h.data(), B + 1, s);
-                CS_HIP(hipStreamSynchronize(s));
-                for (int i = 0; i < B; ++i) hc[i] = ep_h[i + 1] - ep_h[i];
-                for (int q = 0; q < nl; ++q) hc[list[q]] = mp_h[q + 1] - mp_h[q];
-                ncnt.upload(hc.data(), B, s);
+                hipLaunchKernelGGL(k_ecount, dim3(grid_for(B)), dim3(WG), 0, s, B, pos.get(), mp.ptr.get(),
+                                   E.pat.ptr.get(), ncnt.get());
+                CS_LAUNCH_CHECK();
                 EMat N;
                 N.pat.rows = B;
                 N.pat.nnzb = scan_counts(c, ncnt, B, N.pat.ptr, tot);
