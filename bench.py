@@ -161,8 +161,9 @@ def main():
     ap.add_argument("--no-trace", action="store_true", help="do not time the sweep kernel with events")
     ap.add_argument("--trace-period", type=int, default=8,
                     help="time every n-th launch of the sweep kernel with HIP events")
-    ap.add_argument("--solver", default="cg", choices=["ir", "cg"],
-                    help="outer solver of the timed step: FP64 refinement or flexible CG around the V-cycle")
+    ap.add_argument("--solver", default="cg", choices=["ir", "cg", "gmres", "fgmres"],
+                    help="outer solver of the timed step: FP64 refinement, flexible CG, left-preconditioned "
+                         "GMRES or flexible GMRES around the V-cycle")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-system measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-setup measurement")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -233,10 +234,18 @@ def main():
                     algorithmic_bytes_per_launch=int(bytes_per_launch))
 
     extra = {}
-    other = "ir" if args.solver == "cg" else "cg"
+    other = "ir" if args.solver != "ir" else "cg"
     oinfo = [s.solve(b, rtol=args.rtol, maxit=args.maxit, method=other)[1] for _ in range(2)][-1]
     extra[f"{args.precision}_{other}"] = dict(solve_ms=round(oinfo["solve_ms"], 3), iterations=oinfo["iterations"],
                                               rho=round(oinfo["rho"], 4), dof_per_s=dof / (oinfo["solve_ms"] * 1e-3))
+    # the paper's driver (left-preconditioned GMRES, residual ||V(b - Ax)||) and flexible GMRES
+    for gm in ("gmres", "fgmres"):
+        if gm == args.solver:
+            continue
+        ginfo = [s.solve(b, rtol=args.rtol, maxit=args.maxit, method=gm)[1] for _ in range(2)][-1]
+        extra[f"{args.precision}_{gm}"] = dict(solve_ms=round(ginfo["solve_ms"], 3), iterations=ginfo["iterations"],
+                                               rho=round(ginfo["rho"], 4), rel_res=ginfo["rel_res"],
+                                               dof_per_s=dof / (ginfo["solve_ms"] * 1e-3))
     if not args.no_fp64_baseline:
         # the plain FP64 V-cycle: stationary iteration, every kernel in FP64
         s.set_precision("fp64")
@@ -297,7 +306,9 @@ def main():
             "workload": f"3D 7-point interface problem {args.n}^3, contrast 1e4 sphere r=0.3, "
                         f"{args.nrhs} RHS, 2x2x2 blocks, depth-{args.depth} additive cascade, RF V(1,1), "
                         f"{args.precision.upper()} V-cycle "
-                        + ("as flexible-CG preconditioner" if args.solver == "cg" else "in iterative refinement")
+                        + {"cg": "as flexible-CG preconditioner", "ir": "in iterative refinement",
+                           "gmres": "as left GMRES(30) preconditioner",
+                           "fgmres": "as flexible GMRES(30) preconditioner"}[args.solver]
                         + f" with FP64 outer vectors, to {args.rtol:g}",
             "solver": args.solver,
             "dof": prob.n, "nrhs": prob.nrhs, "levels": len(prob.levels), "parallelism": "single GPU",

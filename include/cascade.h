@@ -181,6 +181,35 @@ cs_status cs_solve(cs_ctx ctx, const double *b, double *x, int32_t nrhs, double 
 cs_status cs_solve_cg(cs_ctx ctx, const double *b, double *x, int32_t nrhs, double rtol, int32_t maxit,
                       cs_info *info, double *history);
 
+/* Solve A x = b by restarted GMRES(restart) with one V-cycle as the
+ * preconditioner: the Sec. 3.1 driver.  FP64 Krylov vectors, the V-cycle in the
+ * working precision, independent Krylov spaces per (system, RHS), x_0 = 0.
+ *   flexible = 0: left preconditioning (the paper's form); the monitored
+ *     residual is ||V (b - A x)||, and the stop is max_j ||V(b_j - A x_j)|| <=
+ *     rtol ||V b_j||; history and rho refer to this norm (Sec. 3.1).
+ *   flexible = 1: right preconditioning with the preconditioned vectors kept
+ *     (flexible GMRES, exact for a V-cycle in reduced precision); the
+ *     monitored residual is ||b - A x||, stop as for cs_solve.
+ * restart: 1..31 basis vectors per cycle; maxit counts V-cycles inside the
+ * Arnoldi steps (the restart checks add one more per cycle).  Memory:
+ * (restart + 3) FP64 vectors of n x nrhs (flexible: 2 restart + 3), allocated on
+ * the first call and kept.  Errors, history and info as for cs_solve; a
+ * diverging reduced-precision V-cycle is escalated the same way. */
+cs_status cs_solve_gmres(cs_ctx ctx, const double *b, double *x, int32_t nrhs, double rtol, int32_t maxit,
+                         int32_t restart, int32_t flexible, cs_info *info, double *history);
+
+/* Pick the launch schedule of every level's cascade sweeps by measurement
+ * (needs a setup): for the current working precision and nrhs, one cascade
+ * application per level is timed for each candidate schedule (64 or 256 rows
+ * per workgroup; a workgroup per tile, or a capped grid of 1024, 2048 or 4096
+ * workgroups that loop over the tiles) and the fastest is kept for later
+ * solves, until the level is replaced.  Results are identical under every
+ * schedule.  Outputs per level (host arrays of n_levels, each may be NULL):
+ * rows per workgroup (0 for a level without sweeps), workgroup cap (0 = none)
+ * and the best time in ms.  The workspace vectors of every level are
+ * overwritten. */
+cs_status cs_autotune(cs_ctx ctx, int32_t nrhs, int32_t *wgs, int64_t *grid, double *ms);
+
 /* Device timing of kernel classes with HIP events recorded on the context's
  * stream around every launch of the class (for measurement; adds one event pair
  * per recorded launch).  cs_trace(ctx, mask, period) clears the counters and

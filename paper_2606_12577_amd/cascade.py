@@ -75,6 +75,8 @@ SIGNATURES = {
     "cs_vcycle": (_I32, [_VP, _VP, _VP, _I32]),
     "cs_solve": (_I32, [_VP, _VP, _VP, _I32, _D, _I32, _p(cs_info), _p(_D)]),
     "cs_solve_cg": (_I32, [_VP, _VP, _VP, _I32, _D, _I32, _p(cs_info), _p(_D)]),
+    "cs_solve_gmres": (_I32, [_VP, _VP, _VP, _I32, _D, _I32, _I32, _I32, _p(cs_info), _p(_D)]),
+    "cs_autotune": (_I32, [_VP, _I32, _p(_I32), _p(_I64), _p(_D)]),
     "cs_trace": (_I32, [_VP, _I32, _I32]),
     "cs_trace_read": (_I32, [_VP, _I32, _p(_D), _p(_I64), _p(_D)]),
     "cs_set_systems": (_I32, [_VP, _I32, _p(_I64)]),
@@ -280,17 +282,23 @@ class Solver:
         return x
 
     def solve(self, b, rtol: float = 1e-10, maxit: int = 100, x=None, raise_on_noconv: bool = True,
-              method: str = "ir"):
+              method: str = "ir", restart: int = 30):
         """method "ir": FP64 iterative refinement around the V-cycle (stationary);
-        "cg": flexible conjugate gradients preconditioned by the V-cycle."""
+        "cg": flexible conjugate gradients preconditioned by the V-cycle;
+        "gmres": restarted GMRES with the V-cycle as left preconditioner (the
+        history is ||V(b - Ax)|| / ||Vb||); "fgmres": flexible (right) GMRES."""
         b = self._vec(b)
         if x is None:
             x = self._torch.empty_like(b)
         info = cs_info()
         hist = np.full(maxit + 1, np.nan)
-        fn = {"ir": self._lib.cs_solve, "cg": self._lib.cs_solve_cg}[method]
-        st = fn(self._h, _tensor_ptr(b), _tensor_ptr(x), b.shape[1], rtol, maxit,
-                ctypes.byref(info), _ptr(hist, ctypes.c_double))
+        args = (self._h, _tensor_ptr(b), _tensor_ptr(x), b.shape[1], rtol, maxit)
+        tail = (ctypes.byref(info), _ptr(hist, ctypes.c_double))
+        if method in ("gmres", "fgmres"):
+            st = self._lib.cs_solve_gmres(*args, restart, int(method == "fgmres"), *tail)
+        else:
+            fn = {"ir": self._lib.cs_solve, "cg": self._lib.cs_solve_cg}[method]
+            st = fn(*args, *tail)
         if st != 0 and not (st == -6 and not raise_on_noconv):
             self._check(st)
         k = info.iterations
@@ -337,6 +345,15 @@ class Solver:
 
     TRACE_CLASSES = ("sweep", "sweep_zero", "residual", "prolong", "bottom", "refine", "sweep_prolong",
                      "sweep_small")
+
+    def autotune(self, nrhs: int):
+        """Time the candidate sweep schedules of every level (current precision,
+        nrhs right-hand sides) and keep the fastest; returns per level
+        (rows per workgroup, workgroup cap, best ms per cascade application)."""
+        L = len(self.sizes)
+        wgs, grid, ms = np.zeros(L, np.int32), np.zeros(L, np.int64), np.zeros(L)
+        self._check(self._lib.cs_autotune(self._h, nrhs, _ptr(wgs, _I32), _ptr(grid, _I64), _ptr(ms, _D)))
+        return [(int(w), int(g), float(t)) for w, g, t in zip(wgs, grid, ms)]
 
     def trace(self, classes=("sweep",), period: int = 1):
         """Start (clearing the counters) event timing of every period-th launch

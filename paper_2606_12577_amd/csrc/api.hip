@@ -265,6 +265,7 @@ void cs_destroy(cs_ctx ctx) {
     if (ctx->c.ev_in) (void)hipEventDestroy(ctx->c.ev_in);
     if (ctx->c.ev_out) (void)hipEventDestroy(ctx->c.ev_out);
     if (ctx->c.h_norm) (void)hipHostFree(ctx->c.h_norm);
+    if (ctx->c.gm_host) (void)hipHostFree(ctx->c.gm_host);
     if (ctx->c.ev0) (void)hipEventDestroy(ctx->c.ev0);
     if (ctx->c.ev1) (void)hipEventDestroy(ctx->c.ev1);
     delete ctx;
@@ -453,6 +454,25 @@ cs_status cs_solve_cg(cs_ctx ctx, const double *b, double *x, int32_t nrhs, doub
                       cs_info *info, double *history) {
     return solve_escalating(ctx, b, x, maxit, rtol, info, [&](Ctx &c, cs_status *st) {
         cs::solve_cg(c, b, x, nrhs, rtol, maxit, info, history, st);
+    });
+}
+
+cs_status cs_autotune(cs_ctx ctx, int32_t nrhs, int32_t *wgs, int64_t *grid, double *ms) {
+    return guarded(ctx, [&](Ctx &c) {
+        need(c.have_setup, "autotune before cs_setup", CS_ESTATE);
+        need(nrhs == 1 || nrhs == 2 || nrhs == 4 || nrhs == 8, "nrhs must be 1, 2, 4 or 8");
+        cs::autotune(c, nrhs, ms);
+        for (size_t l = 0; l < c.lv.size(); ++l) {
+            if (wgs) wgs[l] = c.lv[l].tune_wgs;
+            if (grid) grid[l] = c.lv[l].tune_grid;
+        }
+    });
+}
+
+cs_status cs_solve_gmres(cs_ctx ctx, const double *b, double *x, int32_t nrhs, double rtol, int32_t maxit,
+                         int32_t restart, int32_t flexible, cs_info *info, double *history) {
+    return solve_escalating(ctx, b, x, maxit, rtol, info, [&](Ctx &c, cs_status *st) {
+        cs::solve_gmres(c, b, x, nrhs, rtol, maxit, restart, flexible != 0, info, history, st);
     });
 }
 

@@ -115,6 +115,9 @@ struct Level {
     std::vector<Sell> csell;          // per-colour rows (multiplicative)
     DBuf<int32_t> clist;              // blocks sorted by colour
     std::vector<int32_t> layout_colour;   // colours the colour layout was built for
+    // sweep launch schedule picked by the autotuner (0: the size rule)
+    int tune_wgs = 0;                 // rows per workgroup: 64 or 256
+    int64_t tune_grid = 0;            // workgroups (the kernels loop over the remaining tiles)
     std::vector<int64_t> cptr;        // colour offsets into clist
     int chi = 0;
     DBuf<int32_t> colour;             // device colours
@@ -205,6 +208,14 @@ struct Ctx {
     DBuf<double> cg_partial;            // batch: flat-kernel partial sums [workgroups][R]
     double *h_norm = nullptr;           // pinned host copy of ir_norm
     size_t h_norm_cap = 0;
+    // GMRES: unnormalised basis [m+1][n][R], preconditioned vectors (flexible)
+    // [m][n][R], two work vectors, reciprocal basis norms [m+1][nsys][R],
+    // Hessenberg columns of two Gram-Schmidt passes and the new norm, the
+    // least-squares solution [nsys][R][m], partial sums, batch workgroup table
+    DBuf<double> gm_V, gm_Z, gm_w, gm_sc, gm_h, gm_y, gm_partial;
+    DBuf<int32_t> gm_sys_wg;
+    double *gm_host = nullptr;          // pinned host copy of gm_h
+    size_t gm_host_cap = 0;
     bool fuse_transfers = true;         // use the fused aggregation kernels when agg_k > 0
     int64_t sweep_grid = int64_t(1) << 40;   // cap on workgroups of the tiled kernels (multiple of 8)
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -262,6 +273,9 @@ void solve_ir(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
               double *history, cs_status *st);
 void solve_cg(Ctx &c, const double *b, double *x, int nrhs, double rtol, int maxit, cs_info *info,
               double *history, cs_status *st);
+void autotune(Ctx &c, int nrhs, double *ms_out);
+void solve_gmres(Ctx &c, const double *b, double *x, int nrhs, double rtol, int maxit, int restart, bool flexible,
+                 cs_info *info, double *history, cs_status *st);
 
 // host helpers
 void build_sell(Sell &S, const std::vector<int64_t> &ptr, const std::vector<int32_t> &col,

@@ -840,6 +840,228 @@ __global__ __launch_bounds__(WG) void k_cg_update_flat(int64_t npairs, int nsys,
     flat_partials<R>(v, red, partial);
 }
 
+// ---------------------------------------------------------------------------
+// GMRES vector kernels.  The Krylov basis is kept unnormalised: basis vector i
+// is sc[i][col] * vt_i with vt_i stored ([n][R] FP64, leading dimension ld)
+// and sc the reciprocal norms, col = system * R + right-hand side.  Vectors
+// stream one element per thread and step; a thread always meets the same
+// right-hand side (R divides the stride), and in a batch a workgroup covers a
+// chunk of one system only, so each thread has one column.
+// ---------------------------------------------------------------------------
+constexpr int GM_MAXV = 32;             // basis vectors per kernel (restart + 1)
+constexpr int64_t GM_CHUNK = 4 * WG;    // elements per workgroup in a batch
+
+struct ElemRange {
+    int64_t begin, end, stride;
+    int sys;
+};
+
+template <int R>
+__device__ __forceinline__ ElemRange elem_range(int64_t nel, int nsys, const int32_t *__restrict__ sys_wg,
+                                                const int64_t *__restrict__ sys_ptr) {
+    if (!sys_wg) return {blockIdx.x * (int64_t)WG + threadIdx.x, nel, (int64_t)gridDim.x * WG, 0};
+    int lo = 0, hi = nsys - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sys_wg[mid] <= (int)blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    const int64_t e0 = sys_ptr[lo] * R, e1 = sys_ptr[lo + 1] * R;
+    const int64_t a = e0 + (int64_t)(blockIdx.x - sys_wg[lo]) * GM_CHUNK;
+    return {a + threadIdx.x, a + GM_CHUNK < e1 ? a + GM_CHUNK : e1, (int64_t)WG, lo};
+}
+
+// Workgroup partial sums of NV values per thread, reduced over the threads of
+// one right-hand side (t mod R): partial[blockIdx][i][R].
+template <int R>
+__device__ __forceinline__ void gm_partials(const double (&acc)[GM_MAXV], int nv, double *red,
+                                            double *__restrict__ partial) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < GM_MAXV; ++i) {
+        if (i < nv) {   // uniform
+            double v = acc[i];
+#pragma unroll
+            for (int off = 32; off >= R; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane < R) red[(wv * GM_MAXV + i) * R + lane] = v;
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nv * R; e += WG) {
+        const int i = e / R, k = e % R;
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < WG / 64; ++w) s += red[(w * GM_MAXV + i) * R + k];
+        partial[(int64_t)blockIdx.x * nv * R + e] = s;
+    }
+}
+
+// h_i = (v_i, w) for i < nv
+template <typename W, int R>
+__global__ __launch_bounds__(WG) void k_gm_dots(int64_t nel, int nsys, const int32_t *__restrict__ sys_wg,
+                                                const int64_t *__restrict__ sys_ptr, int nv,
+                                                const double *__restrict__ vt, int64_t ld,
+                                                const double *__restrict__ sc, const W *__restrict__ w,
+                                                double *__restrict__ partial) {
+    __shared__ double red[(WG / 64) * GM_MAXV * R];
+    const ElemRange er = elem_range<R>(nel, nsys, sys_wg, sys_ptr);
+    const int col = er.sys * R + (int)(threadIdx.x % R);
+    double acc[GM_MAXV];
+#pragma unroll
+    for (int i = 0; i < GM_MAXV; ++i) acc[i] = 0.0;
+    for (int64_t e = er.begin; e < er.end; e += er.stride) {
+        const double we = (double)w[e];
+#pragma unroll
+        for (int i = 0; i < GM_MAXV; ++i)
+            if (i < nv) acc[i] += __builtin_nontemporal_load(vt + i * ld + e) * we;
+    }
+#pragma unroll
+    for (int i = 0; i < GM_MAXV; ++i)
+        if (i < nv) acc[i] *= sc[(int64_t)i * nsys * R + col];
+    gm_partials<R>(acc, nv, red, partial);
+}
+
+// w' = w - sum_i h_i v_i (h[sys][i][R] from the reduction), stored in FP64;
+// with DOTS the partial sums of (v_i, w') for i < nv, else of (w', w').
+// nv = 0 copies w (converted) and sums its squares.
+template <typename W, int R, bool DOTS>
+__global__ __launch_bounds__(WG) void k_gm_update(int64_t nel, int nsys, const int32_t *__restrict__ sys_wg,
+                                                  const int64_t *__restrict__ sys_ptr, int nv,
+                                                  const double *__restrict__ vt, int64_t ld,
+                                                  const double *__restrict__ sc, const double *__restrict__ h,
+                                                  const W *__restrict__ w, double *__restrict__ wout,
+                                                  double *__restrict__ partial) {
+    __shared__ double red[(WG / 64) * GM_MAXV * R];
+    const ElemRange er = elem_range<R>(nel, nsys, sys_wg, sys_ptr);
+    const int k = (int)(threadIdx.x % R), col = er.sys * R + k;
+    double coef[GM_MAXV], acc[GM_MAXV];
+#pragma unroll
+    for (int i = 0; i < GM_MAXV; ++i) {
+        acc[i] = 0.0;
+        coef[i] = i < nv ? h[((int64_t)er.sys * nv + i) * R + k] * sc[(int64_t)i * nsys * R + col] : 0.0;
+    }
+    for (int64_t e = er.begin; e < er.end; e += er.stride) {
+        double v[GM_MAXV];
+        double we = (double)w[e];
+#pragma unroll
+        for (int i = 0; i < GM_MAXV; ++i)
+            if (i < nv) {
+                v[i] = __builtin_nontemporal_load(vt + i * ld + e);
+                we -= coef[i] * v[i];
+            }
+        wout[e] = we;
+        if constexpr (DOTS) {
+#pragma unroll
+            for (int i = 0; i < GM_MAXV; ++i)
+                if (i < nv) acc[i] += v[i] * we;
+        } else {
+            acc[0] += we * we;
+        }
+    }
+    if constexpr (DOTS) {
+#pragma unroll
+        for (int i = 0; i < GM_MAXV; ++i)
+            if (i < nv) acc[i] *= sc[(int64_t)i * nsys * R + col];
+    }
+    gm_partials<R>(acc, DOTS ? nv : 1, red, partial);
+}
+
+// x += sum_{i < nv} y[col][i] * basis_i, basis_i = sc_i vt_i (sc != null) or
+// the stored preconditioned vectors (sc == null); y is [ncol][ystride]
+template <typename B, int R>
+__global__ __launch_bounds__(WG) void k_gm_xupdate(int64_t nel, int nsys, const int32_t *__restrict__ sys_wg,
+                                                   const int64_t *__restrict__ sys_ptr, int nv,
+                                                   const B *__restrict__ basis, int64_t ld,
+                                                   const double *__restrict__ sc, const double *__restrict__ y,
+                                                   int ystride, double *__restrict__ x) {
+    const ElemRange er = elem_range<R>(nel, nsys, sys_wg, sys_ptr);
+    const int col = er.sys * R + (int)(threadIdx.x % R);
+    double coef[GM_MAXV];
+#pragma unroll
+    for (int i = 0; i < GM_MAXV; ++i)
+        coef[i] = i < nv ? y[(int64_t)col * ystride + i] * (sc ? sc[(int64_t)i * nsys * R + col] : 1.0) : 0.0;
+    for (int64_t e = er.begin; e < er.end; e += er.stride) {
+        double xe = x[e];
+#pragma unroll
+        for (int i = 0; i < GM_MAXV; ++i)
+            if (i < nv) xe += coef[i] * (double)__builtin_nontemporal_load(basis + i * ld + e);
+        x[e] = xe;
+    }
+}
+
+// Per-system sums of GMRES partials: out[s][c] = sum over the workgroups of
+// system s of partial[b][c], c < W.  Workgroup (s, c-block of 64): wavefront
+// w sums every fourth workgroup, then the four wavefronts are added in order.
+__global__ __launch_bounds__(256) void k_gm_reduce(int W, int64_t G, const int32_t *__restrict__ sys_wg,
+                                                   const double *__restrict__ partial, double *__restrict__ out) {
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int s = blockIdx.y;
+    const int c = blockIdx.x * 64 + lane;
+    const int64_t b0 = sys_wg ? sys_wg[s] : 0, b1 = sys_wg ? sys_wg[s + 1] : G;
+    double v = 0.0;
+    if (c < W)
+        for (int64_t b = b0 + wv; b < b1; b += 4) v += partial[b * W + c];
+    red[wv][lane] = v;
+    __syncthreads();
+    if (wv == 0 && c < W) out[(int64_t)s * W + c] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+}
+
+// sc[col] = 1 / sqrt(n2[col]) (0 for a zero or non-finite norm)
+__global__ void k_gm_rscale(int ncol, const double *__restrict__ n2, double *__restrict__ sc) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncol) return;
+    const double v = n2[c];
+    sc[c] = (v > 0.0 && isfinite(v)) ? 1.0 / sqrt(v) : 0.0;
+}
+
+// out = sc * (A vt) (left GMRES: the V-cycle input, in the working precision)
+// or out = b - A x (sc == null, b != null) or A x (both null), FP64 A.
+template <typename TO, int R>
+__global__ __launch_bounds__(WG) void k_gm_spmv(int64_t nrows, int64_t nslices, const int64_t *__restrict__ sptr,
+                                                const int32_t *__restrict__ slen, const int32_t *__restrict__ scol,
+                                                const double *__restrict__ sval, const double *__restrict__ x,
+                                                const double *__restrict__ b, const double *__restrict__ sc, int nsys,
+                                                const int64_t *__restrict__ sys_ptr, TO *__restrict__ out) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const Tiles tl = my_tiles((nslices + 3) / 4);
+    for (int64_t tile = tl.t; tile < tl.end; tile += tl.step) {
+        const int64_t slice = tile * 4 + wv;
+        if (slice >= nslices) continue;
+        const int64_t row = slice * 64 + lane;
+        if (row >= nrows) continue;
+        double ax[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) ax[k] = 0.0;
+        spmv_row<double, R, false>(scol, sval, sptr[slice] + lane, slen[slice], x, nullptr, 1, ax);
+        if (sc) {
+            const int s = nsys > 1 ? row_system(row, nsys, sys_ptr) : 0;
+#pragma unroll
+            for (int k = 0; k < R; ++k) ax[k] *= sc[s * R + k];
+        } else if (b) {
+            double bb[R];
+            vload_nt<double, R>(b + row * R, bb);
+#pragma unroll
+            for (int k = 0; k < R; ++k) ax[k] = bb[k] - ax[k];
+        }
+        TO o[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) o[k] = (TO)ax[k];
+        vstore<TO, R>(out + row * R, o);
+    }
+}
+
+// out = T(sc * vt) (flexible GMRES: the V-cycle input)
+template <typename T, int R>
+__global__ __launch_bounds__(WG) void k_gm_scale_cast(int64_t nel, int nsys, const int32_t *__restrict__ sys_wg,
+                                                      const int64_t *__restrict__ sys_ptr,
+                                                      const double *__restrict__ vt, const double *__restrict__ sc,
+                                                      T *__restrict__ out) {
+    const ElemRange er = elem_range<R>(nel, nsys, sys_wg, sys_ptr);
+    const double f = sc[er.sys * R + (int)(threadIdx.x % R)];
+    for (int64_t e = er.begin; e < er.end; e += er.stride) out[e] = (T)(f * vt[e]);
+}
+
 // Per-system sums of per-workgroup partials: out[s][k] = sum over the
 // workgroups b of system s (sys_wg[s] <= b < sys_wg[s+1]) of partial[b][k].
 __global__ __launch_bounds__(256) void k_wg_to_sys(int W, const int32_t *__restrict__ sys_wg,
@@ -996,9 +1218,11 @@ void launch_sweep(Ctx &c, const Level &L, const Sell &S, bool rowmap, bool zero,
     const int64_t nrows = rowmap ? S.nrows : L.n_active;
     const int64_t nslices = rowmap ? S.nslices : L.act_slices;
     const int64_t nnz = rowmap ? S.nnz : L.act_nnz;
-    // levels below SMALL_SLICES slices run one 64-row slice per workgroup
-    const bool small = nslices < SMALL_SLICES;
-    const unsigned G = small ? (unsigned)std::min<int64_t>(nslices, c.sweep_grid) : tile_grid(c, nslices);
+    // levels below SMALL_SLICES slices run one 64-row slice per workgroup,
+    // unless the autotuner picked a schedule for the level
+    const bool small = L.tune_wgs ? L.tune_wgs == 64 : nslices < SMALL_SLICES;
+    unsigned G = small ? (unsigned)std::min<int64_t>(nslices, c.sweep_grid) : tile_grid(c, nslices);
+    if (L.tune_grid > 0 && (int64_t)G > L.tune_grid) G = (unsigned)L.tune_grid;
     if (G == 0) return;
     const bool prol = xc != nullptr;
     const int cls = zero ? CS_TRACE_SWEEP_ZERO
@@ -1218,6 +1442,81 @@ void vcycle_apply(Ctx &c, const double *b, double *x, int nrhs) {
                            reinterpret_cast<const T *>(L0.xb.get()), x);
         CS_LAUNCH_CHECK();
     });
+}
+
+// Sweep launch schedules per level, picked by measurement: one application of
+// the level's cascade (its real operator, smoothers and colour layout) is
+// timed with HIP events for every candidate schedule, 64 or 256 rows per
+// workgroup with a workgroup per tile or a capped, looping grid (caps are
+// multiples of 8 so that every XCD sweeps whole tile ranges); the median of
+// five applications decides.  ms[l] receives the best time of level l.
+void autotune(Ctx &c, int nrhs, double *ms) {
+    ensure_workspace(c, nrhs);
+    const bool tr = c.tr.on;
+    c.tr.on = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    CS_HIP(hipEventCreate(&e0));
+    CS_HIP(hipEventCreate(&e1));
+    struct Cand {
+        int wgs;
+        int64_t grid;
+    };
+    try {
+        dispatch_prec(c.precision, [&](auto tp) {
+            using T = std::remove_pointer_t<decltype(tp)>;
+            dispatch_r(nrhs, [&](auto rc) {
+                constexpr int R = decltype(rc)::value;
+                for (size_t l = 0; l < c.lv.size(); ++l) {
+                    Level &L = c.lv[l];
+                    if (ms) ms[l] = 0.0;
+                    if (L.depth <= 0 || L.n_active == 0 || l + 1 == c.lv.size()) continue;
+                    const int64_t n = L.n * R;
+                    T *b = reinterpret_cast<T *>(L.bb.get()), *x = reinterpret_cast<T *>(L.xb.get()),
+                      *alt = reinterpret_cast<T *>(L.xt.get());
+                    hipLaunchKernelGGL(k_zero<T>, dim3(grid_for(n)), dim3(WG), 0, c.stream, n, b);
+                    hipLaunchKernelGGL(k_zero<T>, dim3(grid_for(n)), dim3(WG), 0, c.stream, n, x);
+                    CS_LAUNCH_CHECK();
+                    const int64_t ns = std::max<int64_t>(L.act_slices, 1), nt = ceil_div(ns, 4);
+                    std::vector<Cand> cands{{64, 0}, {256, 0}};
+                    for (int64_t g : {1024, 2048, 4096})
+                        for (int w : {64, 256})
+                            if (g < (w == 64 ? ns : nt)) cands.push_back({w, g});
+                    double best = 1e30;
+                    Cand pick{0, 0};
+                    for (const Cand &cd : cands) {
+                        L.tune_wgs = cd.wgs;
+                        L.tune_grid = cd.grid;
+                        (void)apply_cascade<T, R>(c, L, false, false, b, x, alt);   // warm-up
+                        std::vector<float> t(5);
+                        for (float &v : t) {
+                            CS_HIP(hipEventRecord(e0, c.stream));
+                            (void)apply_cascade<T, R>(c, L, false, false, b, x, alt);
+                            CS_HIP(hipEventRecord(e1, c.stream));
+                            CS_HIP(hipEventSynchronize(e1));
+                            CS_HIP(hipEventElapsedTime(&v, e0, e1));
+                        }
+                        std::sort(t.begin(), t.end());
+                        if (t[2] < best) {
+                            best = t[2];
+                            pick = cd;
+                        }
+                    }
+                    L.tune_wgs = pick.wgs;
+                    L.tune_grid = pick.grid;
+                    if (ms) ms[l] = best;
+                }
+            });
+        });
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        c.tr.on = tr;
+        throw;
+    }
+    CS_HIP(hipEventDestroy(e0));
+    CS_HIP(hipEventDestroy(e1));
+    c.tr.on = tr;
+    c.gen++;   // captured graphs hold the old launch shapes
 }
 
 void smooth_apply(Ctx &c, int level, bool reverse, const double *b, double *x, int nrhs) {
@@ -1617,6 +1916,291 @@ void solve_cg(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
                 trace_end(c, slot);
                 cur ^= 1;
             }
+            trace_flush(c);
+            CS_HIP(hipEventRecord(c.ev1, c.stream));
+            CS_HIP(hipEventSynchronize(c.ev1));
+            float ms = 0;
+            CS_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
+            mon.finish(it, ms, info, history);
+        });
+    });
+}
+
+}  // namespace cs
+
+namespace cs {
+
+// Restarted GMRES(m) with the V-cycle as preconditioner (Sec. 3.1), FP64
+// Krylov vectors, the V-cycle in the working precision.  Left (flexible =
+// false): the Krylov space of V A and the monitored residual ||V (b - A x)||,
+// the norm Sec. 3.1 regresses rho on.  Flexible (right): z_j = V v_j is kept,
+// w = A z_j, x = x_0 + Z y, and the monitored residual is ||b - A x||.
+// Arnoldi orthogonalises by classical Gram-Schmidt applied twice (two passes
+// over the basis per step instead of j + 1); the Hessenberg columns go to the
+// host, which applies Givens rotations per (system, RHS) column.  A column
+// stops growing once its estimate reaches rtol ||u_0|| (or, with a left
+// preconditioner in reduced precision, 1e-5 times the cycle's starting norm,
+// below which the rounding of V makes the Arnoldi estimate unreliable) or on
+// breakdown; the cycle ends when every column has stopped or after m steps.
+// Then x is updated, the monitored residual is recomputed, and columns still
+// above rtol start another cycle.
+void solve_gmres(Ctx &c, const double *b, double *x, int nrhs, double rtol, int maxit, int restart, bool flexible,
+                 cs_info *info, double *history, cs_status *st) {
+    if (restart < 1 || restart > GM_MAXV - 1) fail(CS_EINVAL, "restart must be between 1 and 31");
+    ensure_workspace(c, nrhs);
+    Level &L0 = c.lv[0];
+    const Sell &S = L0.sell;
+    const int64_t nel = L0.n * nrhs;
+    const int nsys = c.sys_ptr.empty() ? 1 : (int)c.sys_ptr.size() - 1;
+    const bool batch = nsys > 1;
+    const int ncol = nsys * nrhs;
+    const int m = restart;
+    const double inner = (!flexible && c.precision != CS_FP64) ? 1e-5 : 0.0;
+    if (c.gm_V.n < (size_t)((m + 1) * nel)) c.gm_V.alloc((m + 1) * nel);
+    if (flexible && c.gm_Z.n < (size_t)(m * nel)) c.gm_Z.alloc(m * nel);
+    if (c.gm_w.n < (size_t)(2 * nel)) c.gm_w.alloc(2 * nel);
+    c.gm_sc.alloc((size_t)(m + 1) * ncol);
+    c.gm_h.alloc((size_t)(2 * (m + 1) + 1) * ncol);
+    c.gm_y.alloc((size_t)ncol * m);
+    int64_t Gp = std::min<int64_t>(std::max<int64_t>(ceil_div(nel, 4 * WG), 1), IR_GRID);
+    const int32_t *sys_wg = nullptr;
+    if (batch) {
+        std::vector<int32_t> wg(nsys + 1, 0);
+        for (int q = 0; q < nsys; ++q)
+            wg[q + 1] = wg[q] + (int32_t)std::max<int64_t>(ceil_div((c.sys_ptr[q + 1] - c.sys_ptr[q]) * nrhs, GM_CHUNK), 1);
+        c.gm_sys_wg.upload(wg.data(), wg.size(), c.stream);
+        Gp = wg[nsys];
+        sys_wg = c.gm_sys_wg.get();
+    }
+    if (c.gm_partial.n < (size_t)(Gp * (m + 1) * nrhs)) c.gm_partial.alloc(Gp * (m + 1) * nrhs);
+    const size_t hcap = (size_t)(2 * (m + 1) + 1) * ncol;
+    if (hcap > c.gm_host_cap) {
+        if (c.gm_host) CS_HIP(hipHostFree(c.gm_host));
+        c.gm_host = nullptr;
+        c.gm_host_cap = 0;
+        CS_HIP(hipHostMalloc(reinterpret_cast<void **>(&c.gm_host), hcap * sizeof(double)));
+        c.gm_host_cap = hcap;
+    }
+    double *V = c.gm_V.get(), *Z = flexible ? c.gm_Z.get() : nullptr;
+    double *w1 = c.gm_w.get(), *w2 = c.gm_w.get() + nel;
+    double *sc = c.gm_sc.get(), *dh = c.gm_h.get(), *part = c.gm_partial.get();
+    const int64_t *sysp = c.sys_ptr_d.get();
+    const int64_t G = std::min<int64_t>(ceil_div(S.nslices, 4), IR_GRID);
+    *st = CS_OK;
+    CS_HIP(hipEventRecord(c.ev0, c.stream));
+    dispatch_prec(c.precision, [&](auto tp) {
+        using T = std::remove_pointer_t<decltype(tp)>;
+        dispatch_r(nrhs, [&](auto rc) {
+            constexpr int R = decltype(rc)::value;
+            T *bb = reinterpret_cast<T *>(L0.bb.get());
+            const T *xb = reinterpret_cast<const T *>(L0.xb.get());
+            auto reduce = [&](int W, double *out) {
+                hipLaunchKernelGGL(k_gm_reduce, dim3((unsigned)ceil_div(W, 64), (unsigned)nsys), dim3(256), 0,
+                                   c.stream, W, Gp, sys_wg, part, out);
+                CS_LAUNCH_CHECK();
+            };
+            const dim3 gg((unsigned)Gp);
+            // monitored residual u of the current x into basis slot 0, its squared
+            // norms into n2 and sc_0 = 1 / ||u||
+            auto monitored = [&](double *n2) {
+                if (!flexible) {
+                    hipLaunchKernelGGL((k_gm_spmv<T, R>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
+                                       S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), x, b,
+                                       (const double *)nullptr, nsys, sysp, bb);
+                    CS_LAUNCH_CHECK();
+                    vcycle_level<T, R>(c, 0);
+                    hipLaunchKernelGGL((k_gm_update<T, R, false>), gg, dim3(WG), 0, c.stream, nel, nsys, sys_wg, sysp,
+                                       0, V, nel, sc, dh, xb, V, part);
+                } else {
+                    hipLaunchKernelGGL((k_gm_spmv<double, R>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
+                                       S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), x, b,
+                                       (const double *)nullptr, nsys, sysp, w1);
+                    hipLaunchKernelGGL((k_gm_update<double, R, false>), gg, dim3(WG), 0, c.stream, nel, nsys, sys_wg,
+                                       sysp, 0, V, nel, sc, dh, (const double *)w1, V, part);
+                }
+                CS_LAUNCH_CHECK();
+                reduce(R, n2);
+                hipLaunchKernelGGL(k_gm_rscale, dim3((unsigned)ceil_div(ncol, 256)), dim3(256), 0, c.stream, ncol,
+                                   n2, sc);
+                CS_LAUNCH_CHECK();
+                CS_HIP(hipMemcpyAsync(c.gm_host, n2, ncol * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+                CS_HIP(hipStreamSynchronize(c.stream));
+            };
+            hipLaunchKernelGGL(k_zero<double>, dim3(grid_for(nel)), dim3(WG), 0, c.stream, nel, x);
+            CS_LAUNCH_CHECK();
+            monitored(dh);
+            std::vector<double> res(ncol), beta0(ncol), hn(2 * (size_t)ncol);
+            for (int q = 0; q < ncol; ++q) {
+                res[q] = std::sqrt(std::max(c.gm_host[q], 0.0));
+                beta0[q] = res[q] > 0 ? res[q] : 1.0;
+                hn[q] = res[q] * res[q];
+                hn[ncol + q] = beta0[q] * beta0[q];
+            }
+            Monitor mon(c, nsys, R, rtol);
+            int it = 0;
+            double rel = mon.record(0, hn.data());
+            std::vector<char> done(ncol);
+            for (int q = 0; q < ncol; ++q) done[q] = res[q] <= rtol * beta0[q];
+            // per column: Hessenberg (rotated in place), rotations, rhs g
+            std::vector<double> H((size_t)ncol * (m + 1) * m), cs_(ncol * (size_t)m), sn_(ncol * (size_t)m),
+                g(ncol * (size_t)(m + 1)), est(ncol), start(ncol), y((size_t)ncol * m);
+            std::vector<int> steps(ncol);
+            std::vector<char> growing(ncol);
+            auto Hc = [&](int q, int i, int j) -> double & { return H[((size_t)q * (m + 1) + i) * m + j]; };
+            while (!std::isnan(rel)) {
+                bool all_done = true;
+                for (int q = 0; q < ncol; ++q) all_done &= done[q] != 0;
+                if (all_done) break;
+                if (it == maxit) {
+                    *st = CS_ENOCONV;
+                    break;
+                }
+                for (int q = 0; q < ncol; ++q) {
+                    start[q] = res[q];
+                    est[q] = res[q];
+                    steps[q] = 0;
+                    growing[q] = !done[q];
+                    std::fill(&g[(size_t)q * (m + 1)], &g[(size_t)q * (m + 1)] + m + 1, 0.0);
+                    g[(size_t)q * (m + 1)] = res[q];
+                }
+                int j = 0;
+                for (; j < m && it < maxit; ++j) {
+                    const int nv = j + 1;
+                    double *h1 = dh, *h2 = dh + (size_t)nv * ncol, *n2 = dh + (size_t)2 * nv * ncol;
+                    double *vj = V + (int64_t)j * nel, *vn = V + (int64_t)(j + 1) * nel;
+                    int slot = trace_begin(c, CS_TRACE_REFINE, S.nnz * 12.0 + (double)nel * (8.0 + sizeof(T)));
+                    if (!flexible) {
+                        hipLaunchKernelGGL((k_gm_spmv<T, R>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
+                                           S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), vj,
+                                           (const double *)nullptr, sc + (int64_t)j * ncol, nsys, sysp, bb);
+                        CS_LAUNCH_CHECK();
+                        trace_end(c, slot);
+                        vcycle_level<T, R>(c, 0);
+                    } else {
+                        hipLaunchKernelGGL((k_gm_scale_cast<T, R>), gg, dim3(WG), 0, c.stream, nel, nsys, sys_wg,
+                                           sysp, vj, sc + (int64_t)j * ncol, bb);
+                        CS_LAUNCH_CHECK();
+                        trace_end(c, slot);
+                        vcycle_level<T, R>(c, 0);
+                        slot = trace_begin(c, CS_TRACE_REFINE, S.nnz * 12.0 + (double)nel * (16.0 + sizeof(T)));
+                        double *zj = Z + (int64_t)j * nel;
+                        hipLaunchKernelGGL((k_convert<T, double>), dim3(grid_for(nel)), dim3(WG), 0, c.stream, nel,
+                                           xb, zj);
+                        hipLaunchKernelGGL((k_gm_spmv<double, R>), dim3(G), dim3(WG), 0, c.stream, S.nrows,
+                                           S.nslices, S.slice_ptr.get(), S.slice_len.get(), S.col.get(),
+                                           S.val64.get(), zj, (const double *)nullptr, (const double *)nullptr, nsys,
+                                           sysp, w2);
+                        CS_LAUNCH_CHECK();
+                        trace_end(c, slot);
+                    }
+                    // two Gram-Schmidt passes: h1 = V^T w, w1 = w - V h1; h2 = V^T w1, v_{j+1} = w1 - V h2
+                    slot = trace_begin(c, CS_TRACE_REFINE, (3.0 * nv + 4.0) * nel * 8.0);
+                    if (!flexible) {
+                        hipLaunchKernelGGL((k_gm_dots<T, R>), gg, dim3(WG), 0, c.stream, nel, nsys, sys_wg, sysp, nv,
+                                           V, nel, sc, xb, part);
+                        CS_LAUNCH_CHECK();
+                        reduce(nv * R, h1);
+                        hipLaunchKernelGGL((k_gm_update<T, R, true>), gg, dim3(WG), 0, c.stream, nel, nsys, sys_wg,
+                                           sysp, nv, V, nel, sc, h1, xb, w1, part);
+                    } else {
+                        hipLaunchKernelGGL((k_gm_dots<double, R>), gg, dim3(WG), 0, c.stream, nel, nsys, sys_wg,
+                                           sysp, nv, V, nel, sc, (const double *)w2, part);
+                        CS_LAUNCH_CHECK();
+                        reduce(nv * R, h1);
+                        hipLaunchKernelGGL((k_gm_update<double, R, true>), gg, dim3(WG), 0, c.stream, nel, nsys,
+                                           sys_wg, sysp, nv, V, nel, sc, h1, (const double *)w2, w1, part);
+                    }
+                    CS_LAUNCH_CHECK();
+                    reduce(nv * R, h2);
+                    hipLaunchKernelGGL((k_gm_update<double, R, false>), gg, dim3(WG), 0, c.stream, nel, nsys, sys_wg,
+                                       sysp, nv, V, nel, sc, h2, (const double *)w1, vn, part);
+                    CS_LAUNCH_CHECK();
+                    reduce(R, n2);
+                    hipLaunchKernelGGL(k_gm_rscale, dim3((unsigned)ceil_div(ncol, 256)), dim3(256), 0, c.stream, ncol,
+                                       n2, sc + (int64_t)(j + 1) * ncol);
+                    CS_LAUNCH_CHECK();
+                    CS_HIP(hipMemcpyAsync(c.gm_host, dh, (size_t)(2 * nv + 1) * ncol * sizeof(double),
+                                          hipMemcpyDeviceToHost, c.stream));
+                    CS_HIP(hipStreamSynchronize(c.stream));
+                    trace_end(c, slot);
+                    ++it;
+                    const double *hh1 = c.gm_host, *hh2 = c.gm_host + (size_t)nv * ncol,
+                                 *hn2 = c.gm_host + (size_t)2 * nv * ncol;
+                    bool any = false;
+                    for (int q = 0; q < ncol; ++q) {
+                        if (!growing[q]) continue;
+                        const int s = q / R, k = q % R;
+                        for (int i = 0; i < nv; ++i)
+                            Hc(q, i, j) = hh1[((size_t)s * nv + i) * R + k] + hh2[((size_t)s * nv + i) * R + k];
+                        const double hnext = std::sqrt(std::max(hn2[q], 0.0));
+                        // previous rotations, then the one that annihilates H(j+1, j)
+                        for (int i = 0; i < j; ++i) {
+                            const double a = Hc(q, i, j), bq = Hc(q, i + 1, j);
+                            Hc(q, i, j) = cs_[q * (size_t)m + i] * a + sn_[q * (size_t)m + i] * bq;
+                            Hc(q, i + 1, j) = -sn_[q * (size_t)m + i] * a + cs_[q * (size_t)m + i] * bq;
+                        }
+                        const double a = Hc(q, j, j);
+                        const double r = std::hypot(a, hnext);
+                        const double cj = r > 0 ? a / r : 1.0, sj = r > 0 ? hnext / r : 0.0;
+                        cs_[q * (size_t)m + j] = cj;
+                        sn_[q * (size_t)m + j] = sj;
+                        Hc(q, j, j) = r;
+                        Hc(q, j + 1, j) = 0.0;
+                        double *gq = &g[(size_t)q * (m + 1)];
+                        gq[j + 1] = -sj * gq[j];
+                        gq[j] = cj * gq[j];
+                        est[q] = std::fabs(gq[j + 1]);
+                        steps[q] = j + 1;
+                        if (!(est[q] > std::max(rtol * beta0[q], inner * start[q])) || !(hnext > 0.0))
+                            growing[q] = 0;
+                        any |= growing[q] != 0;
+                    }
+                    for (int q = 0; q < ncol; ++q) hn[q] = est[q] * est[q];
+                    rel = mon.record(it, hn.data());
+                    if (std::isnan(rel) || !any) {
+                        ++j;
+                        break;
+                    }
+                }
+                if (std::isnan(rel)) break;
+                // y from the rotated triangle, x += basis y
+                int kmax = 0;
+                std::fill(y.begin(), y.end(), 0.0);
+                for (int q = 0; q < ncol; ++q) {
+                    if (done[q]) continue;
+                    const int kq = steps[q];
+                    kmax = std::max(kmax, kq);
+                    for (int i = kq - 1; i >= 0; --i) {
+                        double v = g[(size_t)q * (m + 1) + i];
+                        for (int l = i + 1; l < kq; ++l) v -= Hc(q, i, l) * y[(size_t)q * m + l];
+                        const double d = Hc(q, i, i);
+                        y[(size_t)q * m + i] = d != 0.0 ? v / d : 0.0;
+                    }
+                }
+                if (kmax > 0) {
+                    c.gm_y.upload(y.data(), y.size(), c.stream);
+                    if (!flexible)
+                        hipLaunchKernelGGL((k_gm_xupdate<double, R>), gg, dim3(WG), 0, c.stream, nel, nsys, sys_wg,
+                                           sysp, kmax, (const double *)V, nel, (const double *)sc,
+                                           (const double *)c.gm_y.get(), m, x);
+                    else
+                        hipLaunchKernelGGL((k_gm_xupdate<double, R>), gg, dim3(WG), 0, c.stream, nel, nsys, sys_wg,
+                                           sysp, kmax, (const double *)Z, nel, (const double *)nullptr,
+                                           (const double *)c.gm_y.get(), m, x);
+                    CS_LAUNCH_CHECK();
+                }
+                // the monitored residual of the new x replaces the last estimate
+                monitored(dh);
+                for (int q = 0; q < ncol; ++q) {
+                    res[q] = std::sqrt(std::max(c.gm_host[q], 0.0));
+                    if (!std::isfinite(c.gm_host[q])) res[q] = NAN;
+                    hn[q] = res[q] * res[q];
+                    done[q] = res[q] <= rtol * beta0[q];
+                }
+                mon.hist.pop_back();
+                rel = mon.record(it, hn.data());
+            }
+            if (std::isnan(rel)) *st = CS_ENAN;
             trace_flush(c);
             CS_HIP(hipEventRecord(c.ev1, c.stream));
             CS_HIP(hipEventSynchronize(c.ev1));

@@ -81,3 +81,87 @@ def test_batched_cg_runs_every_system_as_if_alone(gpu_lib):
         if abs(np.log(h[k] / rtol)) > 1e-3 and (k == 0 or abs(np.log(h[k - 1] / rtol)) > 1e-3):
             assert its[q] == k, (q, its[q], k)
     assert info["iterations"] == its.max()
+
+
+# ---------------------------------------------------------------------------
+# GMRES (cs_solve_gmres) against the oracle's GMRES: FP64, injected smoothers,
+# short restarts so that several cycles run.  Classical Gram-Schmidt applied
+# twice (GPU) and modified Gram-Schmidt (oracle) agree to rounding; histories
+# to 1e-6 relative (1e-13 absolute for the explicitly recomputed residuals),
+# iterates to 1e-8.
+# ---------------------------------------------------------------------------
+
+GM_CASES = [("poisson64", lambda: fd.poisson2d(64, nrhs=2), 3, "FF", 4),
+            ("interface24", lambda: fd.interface3d(24, nrhs=4), 3, "RF", 3),
+            ("lognormal48", lambda: fd.lognormal2d(48, 2.0, 1), 2, "FF", 30)]
+
+
+@pytest.mark.parametrize("flexible", [False, True])
+@pytest.mark.parametrize("name,make,depth,order,restart", GM_CASES)
+def test_gmres_matches_oracle(gpu_lib, name, make, depth, order, restart, flexible):
+    p = make()
+    sm = O.setup_hierarchy(p.levels, depth)
+    s = gpu_lib.Solver(p.levels)
+    s.setup(depth=depth, order=order)
+    inject(s, sm)
+    pre = lambda r: O.vcycle(p.levels, sm, r, order)
+    xo, ho = O.gmres(p.levels[0].A, pre, p.rhs, restart=restart, rtol=1e-10, maxit=100, flexible=flexible)
+    x, info = s.solve(p.rhs, rtol=1e-10, maxit=100, method="fgmres" if flexible else "gmres", restart=restart)
+    assert info["iterations"] == len(ho) - 1, (info["iterations"], len(ho) - 1)
+    # a residual recomputed at a restart carries rounding of order u ||A|| ||x|| / ||b||
+    # (absolute, in the history's relative units; the 1e4 contrast makes ||A|| ||x||
+    # large), and the next cycle starts from it: 1e-13 absolute beside 1e-6 relative
+    np.testing.assert_allclose(info["history"], ho, rtol=1e-6, atol=1e-13)
+    assert rel(x.cpu().numpy(), xo) <= 1e-8
+    r = p.rhs - p.levels[0].A @ x.cpu().numpy()
+    true = np.max(np.linalg.norm(r, axis=0) / np.linalg.norm(p.rhs, axis=0))
+    assert true <= (1e-10 if flexible else 1e-7)
+
+
+def test_gmres_fp32_vcycle_reaches_fp64_accuracy(gpu_lib):
+    p = fd.interface3d(32, nrhs=8)
+    s = gpu_lib.Solver(p.levels)
+    s.setup(depth=4, order="FF")
+    _, g64 = s.solve(p.rhs, rtol=1e-10, maxit=100, method="fgmres")
+    s.set_precision("fp32")
+    for method in ("gmres", "fgmres"):
+        x, g = s.solve(p.rhs, rtol=1e-10, maxit=100, method=method)
+        assert g["precision"] == "fp32" and g["rel_res"] <= 1e-10, (method, g["rel_res"])
+        assert g["iterations"] <= g64["iterations"] + 5, (method, g["iterations"], g64["iterations"])
+        r = p.rhs - p.levels[0].A @ x.cpu().numpy()
+        true = np.max(np.linalg.norm(r, axis=0) / np.linalg.norm(p.rhs, axis=0))
+        assert true <= (1e-10 if method == "fgmres" else 1e-8), (method, true)
+
+
+def test_gmres_maxit_and_restart_limits(gpu_lib):
+    p = fd.poisson2d(32, nrhs=1)
+    s = gpu_lib.Solver(p.levels)
+    s.setup(depth=1)
+    x, info = s.solve(p.rhs, rtol=1e-14, maxit=3, method="gmres", restart=2, raise_on_noconv=False)
+    assert info["status"] == -6 and info["iterations"] == 3 and len(info["history"]) == 4
+    with pytest.raises(gpu_lib.CascadeError):
+        s.solve(p.rhs, method="gmres", restart=32)
+
+
+def test_batched_gmres_runs_every_system_as_if_alone(gpu_lib):
+    sizes = [48, 64, 80, 16, 112, 32, 8, 20, 12]
+    probs = fd.lognormal_batch(len(sizes), nrhs=2, sizes=sizes, config_id=16)
+    bt = concatenate(probs)
+    sms = [O.setup_hierarchy(p.levels, 3) for p in probs]
+    s = gpu_lib.Solver(bt.levels)
+    s.setup(depth=3, order="FF")
+    s.set_systems(bt.sys_ptr)
+    rtol = 1e-10
+    for flexible in (False, True):
+        x, info = s.solve(bt.rhs, rtol=rtol, maxit=200, method="fgmres" if flexible else "gmres", restart=30)
+        its, rels = s.system_stats()
+        xs = bt.split(x.cpu().numpy())
+        for q, si in enumerate(bt.order):
+            p = probs[si]
+            pre = lambda v: O.vcycle(p.levels, sms[si], v, "FF")
+            xo, h = O.gmres(p.levels[0].A, pre, p.rhs, restart=30, rtol=rtol, maxit=200, flexible=flexible)
+            assert rel(xs[si], xo) <= 1e-7, (q, flexible, rel(xs[si], xo))
+            k = next(i for i, v in enumerate(h) if v <= rtol)
+            if abs(np.log(h[k] / rtol)) > 1e-3 and (k == 0 or abs(np.log(h[k - 1] / rtol)) > 1e-3):
+                assert its[q] == k, (q, flexible, its[q], k)
+        assert info["iterations"] == its.max()

@@ -330,3 +330,21 @@ def test_injected_smoother_vcycle(gpu_lib):
         sm.append(dict(lam=lams, colours=None))
     g = s.vcycle(p.rhs).cpu().numpy()
     assert rel(g, O.vcycle(p.levels, sm, p.rhs)) <= APPLY_TOL
+
+
+@pytest.mark.parametrize("mode", ["additive", "multiplicative"])
+def test_autotuned_schedules_give_identical_results(gpu_lib, mode):
+    """Sweep schedules change only the launch shape: solves are bit-identical."""
+    p = fd.interface3d(24, nrhs=4) if mode == "additive" else fd.poisson2d(128, nrhs=4)
+    s = gpu_lib.Solver(p.levels)
+    s.setup(depth=3, mode=mode, precision="fp32")
+    x0, i0 = s.solve(p.rhs, rtol=1e-10, maxit=100, method="cg")
+    x0 = x0.cpu().numpy()
+    sched = s.autotune(4)
+    assert len(sched) == len(p.levels)
+    for l, (w, g, ms) in enumerate(sched[:-1]):
+        assert w in (64, 256) and g in (0, 1024, 2048, 4096) and ms > 0, (l, w, g, ms)
+    assert sched[-1][0] == 0
+    x1, i1 = s.solve(p.rhs, rtol=1e-10, maxit=100, method="cg")
+    assert i1["iterations"] == i0["iterations"]
+    np.testing.assert_array_equal(x1.cpu().numpy(), x0)
