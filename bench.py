@@ -118,11 +118,16 @@ def bench_learned():
 
 
 def kernel_source_digest() -> str:
+    """Digest of the source that decides the sweep kernel's memory traffic: the
+    device code from the x loads through k_sweep, and its launcher."""
     import hashlib
+    src = open(os.path.join(ROOT, "paper_2606_12577_amd", "csrc", "solve.hip")).read()
+    spans = [("// x_in at unknown j", "// r = A x - b over SELL rows"),
+             ("template <typename T, int R>\nvoid launch_sweep(", "// One application of the cascade of level L")]
     h = hashlib.sha256()
-    for name in ("solve.hip", "cs_internal.h"):
-        with open(os.path.join(ROOT, "paper_2606_12577_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+    for a, b in spans:
+        i, j = src.find(a), src.find(b)
+        h.update((src[i:j] if 0 <= i < j else src).encode())
     return h.hexdigest()[:16]
 
 

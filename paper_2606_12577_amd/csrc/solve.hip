@@ -183,6 +183,72 @@ __device__ __forceinline__ void spmv_row(const int32_t *__restrict__ scol, const
 //           interpolation step of Alg. 1 fused into the first post-sweep)
 //   WGS:    workgroup size; 256 (4 slices) on large levels, 64 (one slice per
 //           workgroup, more workgroups in flight) on small ones
+// SpMV of a natural-order row of an NB-block level (NB a power of two, so a
+// block's rows sit in NB consecutive lanes of the slice): entries inside the
+// row's own block take x from the lanes that hold those rows (shuffles of the
+// x rows they loaded anyway), only the others are gathered.  For the 7-point
+// stencil on 2x2x2 blocks this removes four of the seven gathers per row.
+template <typename T, int R, bool PROL, int NB, int L>
+__device__ __forceinline__ void spmv_fixed_blk(const int32_t *__restrict__ scol, const T *__restrict__ sval,
+                                               int64_t off, const T *xin, const T *xc, int agg_k, int64_t row,
+                                               int lane, const T (&xo)[R], T (&acc)[R]) {
+    int cc[L];
+    T aa[L];
+#pragma unroll
+    for (int u = 0; u < L; ++u) {
+        cc[u] = __builtin_nontemporal_load(scol + off + (int64_t)u * 64);
+        aa[u] = __builtin_nontemporal_load(sval + off + (int64_t)u * 64);
+    }
+    const int64_t blk = row / NB;
+    const int lbase = lane & ~(NB - 1);
+    T xv[L][R];
+#pragma unroll
+    for (int u = 0; u < L; ++u) {
+        const int src = lbase | (cc[u] & (NB - 1));
+#pragma unroll
+        for (int k = 0; k < R; ++k) xv[u][k] = __shfl(xo[k], src, 64);
+        if ((int64_t)(cc[u] / NB) != blk) load_x<T, R, PROL>(xin, xc, agg_k, cc[u], xv[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < L; ++u) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) acc[k] += aa[u] * xv[u][k];
+    }
+}
+
+template <typename T, int R, bool PROL, int NB>
+__device__ __forceinline__ void spmv_row_blk(const int32_t *__restrict__ scol, const T *__restrict__ sval,
+                                             int64_t off, int len, const T *xin, const T *xc, int agg_k,
+                                             int64_t row, int lane, const T (&xo)[R], T (&acc)[R]) {
+    constexpr int U = (sizeof(T) * R > 32) ? 4 : 8;
+    int e0 = 0;
+    for (; e0 + U <= len; e0 += U)
+        spmv_fixed_blk<T, R, PROL, NB, U>(scol, sval, off + (int64_t)e0 * 64, xin, xc, agg_k, row, lane, xo, acc);
+    const int64_t o = off + (int64_t)e0 * 64;
+    switch (len - e0) {
+        case 1: spmv_fixed_blk<T, R, PROL, NB, 1>(scol, sval, o, xin, xc, agg_k, row, lane, xo, acc); break;
+        case 2: spmv_fixed_blk<T, R, PROL, NB, 2>(scol, sval, o, xin, xc, agg_k, row, lane, xo, acc); break;
+        case 3: spmv_fixed_blk<T, R, PROL, NB, 3>(scol, sval, o, xin, xc, agg_k, row, lane, xo, acc); break;
+        case 4: if constexpr (U > 4) spmv_fixed_blk<T, R, PROL, NB, 4>(scol, sval, o, xin, xc, agg_k, row, lane, xo, acc); break;
+        case 5: if constexpr (U > 5) spmv_fixed_blk<T, R, PROL, NB, 5>(scol, sval, o, xin, xc, agg_k, row, lane, xo, acc); break;
+        case 6: if constexpr (U > 6) spmv_fixed_blk<T, R, PROL, NB, 6>(scol, sval, o, xin, xc, agg_k, row, lane, xo, acc); break;
+        case 7: if constexpr (U > 7) spmv_fixed_blk<T, R, PROL, NB, 7>(scol, sval, o, xin, xc, agg_k, row, lane, xo, acc); break;
+        default: break;
+    }
+}
+
+// Natural-order SpMV row of a level with NB-blocks: the in-block shuffle form
+// for NB > 1 (xo: the row's own x, already loaded), else plain gathers.
+template <typename T, int R, bool PROL, int NB>
+__device__ __forceinline__ void spmv_row_nb(const int32_t *__restrict__ scol, const T *__restrict__ sval, int64_t off,
+                                            int len, const T *xin, const T *xc, int agg_k, int64_t row, int lane,
+                                            const T (&xo)[R], T (&acc)[R]) {
+    if constexpr (NB > 1)
+        spmv_row_blk<T, R, PROL, NB>(scol, sval, off, len, xin, xc, agg_k, row, lane, xo, acc);
+    else
+        spmv_row<T, R, PROL>(scol, sval, off, len, xin, xc, agg_k, acc);
+}
+
 template <typename T, int NB, int R, bool ZERO, bool ROWMAP, bool PROL, int WGS>
 __global__ __launch_bounds__(WGS) void k_sweep(int64_t nrows, int64_t nslices, const int32_t *__restrict__ rows,
                                                const int64_t *__restrict__ sptr, const int32_t *__restrict__ slen,
@@ -202,13 +268,31 @@ __global__ __launch_bounds__(WGS) void k_sweep(int64_t nrows, int64_t nslices, c
     T res[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) res[k] = T(0);
+    // block levels: the row of Lambda and the row's own x_in are loaded first;
+    // x_in feeds the in-block part of the SpMV through lane shuffles
+    T lr[NB], xo[R];
+    if constexpr (NB > 1) {
+        if (valid) {
+            vload_nt<T, NB>(lam + (row / NB) * (NB * NB) + (lane % NB) * NB, lr);
+            if constexpr (ZERO) {
+#pragma unroll
+                for (int k = 0; k < R; ++k) xo[k] = T(0);
+            } else {
+                load_x<T, R, PROL>(xin, xc, agg_k, row, xo);
+            }
+        }
+    }
     if (valid) {
         T bb[R];
         vload_nt<T, R>(b + row * R, bb);
 #pragma unroll
         for (int k = 0; k < R; ++k) res[k] = -bb[k];
         if constexpr (!ZERO) {
-            spmv_row<T, R, PROL>(scol, sval, sptr[slice] + lane, slen[slice], xin, xc, agg_k, res);
+            if constexpr (NB > 1 && !ROWMAP)
+                spmv_row_blk<T, R, PROL, NB>(scol, sval, sptr[slice] + lane, slen[slice], xin, xc, agg_k, row,
+                                             lane, xo, res);
+            else
+                spmv_row<T, R, PROL>(scol, sval, sptr[slice] + lane, slen[slice], xin, xc, agg_k, res);
         }
     }
     if constexpr (NB == 1) {
@@ -232,16 +316,6 @@ __global__ __launch_bounds__(WGS) void k_sweep(int64_t nrows, int64_t nslices, c
         if (valid) {
             const int rloc = lane % NB;
             const int base = threadIdx.x - rloc;
-            const T *lrow = lam + (row / NB) * (NB * NB) + rloc * NB;
-            T lr[NB];
-            vload_nt<T, NB>(lrow, lr);
-            T xo[R];
-            if constexpr (ZERO) {
-#pragma unroll
-                for (int k = 0; k < R; ++k) xo[k] = T(0);
-            } else {
-                load_x<T, R, PROL>(xin, xc, agg_k, row, xo);
-            }
 #pragma unroll
             for (int cc = 0; cc < NB; ++cc) {
 #pragma unroll
@@ -278,7 +352,7 @@ __global__ __launch_bounds__(WG) void k_residual(int64_t nrows, int64_t nslices,
 // Fused residual and restriction for contiguous unit aggregation:
 // b_c[I] = r_scale * sum_{u < agg_k} (A x - b)[agg_k*I + u].  A workgroup owns
 // 256 fine rows, i.e. 256/agg_k whole coarse rows (agg_k divides 64).
-template <typename T, int R>
+template <typename T, int R, int NB = 1>
 __global__ __launch_bounds__(WG) void k_residual_restrict(int64_t nrows, int64_t nslices,
                                                           const int64_t *__restrict__ sptr,
                                                           const int32_t *__restrict__ slen,
@@ -295,10 +369,12 @@ __global__ __launch_bounds__(WG) void k_residual_restrict(int64_t nrows, int64_t
 #pragma unroll
     for (int k = 0; k < R; ++k) acc[k] = T(0);
     if (slice < nslices && row < nrows) {
+        T xo[R];
+        if constexpr (NB > 1) vload<T, R>(x + row * R, xo);
         vload_nt<T, R>(b + row * R, acc);
 #pragma unroll
         for (int k = 0; k < R; ++k) acc[k] = -acc[k];
-        spmv_row<T, R, false>(scol, sval, sptr[slice] + lane, slen[slice], x, nullptr, 1, acc);
+        spmv_row_nb<T, R, false, NB>(scol, sval, sptr[slice] + lane, slen[slice], x, nullptr, 1, row, lane, xo, acc);
     }
 #pragma unroll
     for (int k = 0; k < R; ++k) red[threadIdx.x * R + k] = acc[k];
@@ -415,7 +491,7 @@ __global__ __launch_bounds__(WG) void k_direct_seg(int64_t n_active, int64_t n, 
 // system: its sums go to spart[s][R] (wavefront reduction).  The few slices
 // that straddle a system boundary keep their per-row squares in
 // rn2[(het[s]*64 + lane)][R] for the per-system reduction.
-template <typename T, int R, bool SYS>
+template <typename T, int R, bool SYS, int NB = 1>
 __global__ __launch_bounds__(WG) void k_ir_residual(int64_t nrows, int64_t nslices, const int64_t *__restrict__ sptr,
                                                     const int32_t *__restrict__ slen, const int32_t *__restrict__ scol,
                                                     const double *__restrict__ sval, const double *__restrict__ b,
@@ -442,10 +518,12 @@ __global__ __launch_bounds__(WG) void k_ir_residual(int64_t nrows, int64_t nslic
         if (valid) {
             vload_nt<double, R>(b + row * R, acc);
             if (x) {
-                double ax[R];
+                double ax[R], xo[R];
 #pragma unroll
                 for (int k = 0; k < R; ++k) ax[k] = 0.0;
-                spmv_row<double, R, false>(scol, sval, sptr[slice] + lane, slen[slice], x, nullptr, 1, ax);
+                if constexpr (NB > 1) vload<double, R>(x + row * R, xo);
+                spmv_row_nb<double, R, false, NB>(scol, sval, sptr[slice] + lane, slen[slice], x, nullptr, 1, row,
+                                                  lane, xo, ax);
 #pragma unroll
                 for (int k = 0; k < R; ++k) acc[k] -= ax[k];
             }
@@ -601,7 +679,7 @@ __global__ void k_cg_p(int64_t n, int nsys, const int64_t *__restrict__ sys_ptr,
 }
 
 // q = A p (FP64) with the per-RHS partial sums of (p, q) and (p, r)
-template <int R, bool SYS>
+template <int R, bool SYS, int NB = 1>
 __global__ __launch_bounds__(WG) void k_cg_ap(int64_t nrows, int64_t nslices, const int64_t *__restrict__ sptr,
                                               const int32_t *__restrict__ slen, const int32_t *__restrict__ scol,
                                               const double *__restrict__ sval, const double *__restrict__ p,
@@ -625,9 +703,10 @@ __global__ __launch_bounds__(WG) void k_cg_ap(int64_t nrows, int64_t nslices, co
             double ap[R], pp[R], rr[R];
 #pragma unroll
             for (int k = 0; k < R; ++k) ap[k] = 0.0;
-            spmv_row<double, R, false>(scol, sval, sptr[slice] + lane, slen[slice], p, nullptr, 1, ap);
-            vstore<double, R>(q + row * R, ap);
             vload<double, R>(p + row * R, pp);
+            spmv_row_nb<double, R, false, NB>(scol, sval, sptr[slice] + lane, slen[slice], p, nullptr, 1, row, lane,
+                                              pp, ap);
+            vstore<double, R>(q + row * R, ap);
             vload_nt<double, R>(r + row * R, rr);
 #pragma unroll
             for (int k = 0; k < R; ++k) {
@@ -1017,7 +1096,7 @@ __global__ void k_gm_rscale(int ncol, const double *__restrict__ n2, double *__r
 
 // out = sc * (A vt) (left GMRES: the V-cycle input, in the working precision)
 // or out = b - A x (sc == null, b != null) or A x (both null), FP64 A.
-template <typename TO, int R>
+template <typename TO, int R, int NB = 1>
 __global__ __launch_bounds__(WG) void k_gm_spmv(int64_t nrows, int64_t nslices, const int64_t *__restrict__ sptr,
                                                 const int32_t *__restrict__ slen, const int32_t *__restrict__ scol,
                                                 const double *__restrict__ sval, const double *__restrict__ x,
@@ -1030,10 +1109,12 @@ __global__ __launch_bounds__(WG) void k_gm_spmv(int64_t nrows, int64_t nslices, 
         if (slice >= nslices) continue;
         const int64_t row = slice * 64 + lane;
         if (row >= nrows) continue;
-        double ax[R];
+        double ax[R], xo[R];
 #pragma unroll
         for (int k = 0; k < R; ++k) ax[k] = 0.0;
-        spmv_row<double, R, false>(scol, sval, sptr[slice] + lane, slen[slice], x, nullptr, 1, ax);
+        if constexpr (NB > 1) vload<double, R>(x + row * R, xo);
+        spmv_row_nb<double, R, false, NB>(scol, sval, sptr[slice] + lane, slen[slice], x, nullptr, 1, row, lane, xo,
+                                          ax);
         if (sc) {
             const int s = nsys > 1 ? row_system(row, nsys, sys_ptr) : 0;
 #pragma unroll
@@ -1348,10 +1429,13 @@ void vcycle_level(Ctx &c, int l) {
                            L.act_nnz * (es + 4.0) + (fused ? 2.0 : 3.0) * na * R * es +
                                (fused ? 0.0 : L.p_nnz * (es + 4.0) + na * R * es) + L.nc * R * es);
     if (fused) {
-        hipLaunchKernelGGL((k_residual_restrict<T, R>), dim3(tile_grid(c, L.act_slices)), dim3(WG), 0, c.stream, na,
-                           L.act_slices, L.sell.slice_ptr.get(), L.sell.slice_len.get(), L.sell.col.get(),
-                           sell_val<T>(L.sell), bb, x, L.agg_k, L.nc, (T)L.r_scale,
-                           reinterpret_cast<T *>(C.bb.get()));
+        dispatch_nb((int)L.nb, [&](auto nbc) {
+            constexpr int NB = decltype(nbc)::value;
+            hipLaunchKernelGGL((k_residual_restrict<T, R, NB>), dim3(tile_grid(c, L.act_slices)), dim3(WG), 0, c.stream, na,
+                               L.act_slices, L.sell.slice_ptr.get(), L.sell.slice_len.get(), L.sell.col.get(),
+                               sell_val<T>(L.sell), bb, x, L.agg_k, L.nc, (T)L.r_scale,
+                               reinterpret_cast<T *>(C.bb.get()));
+        });
     } else {
         bool bf16 = false;
         if constexpr (std::is_same<T, float>::value && R == 1) {
@@ -1654,16 +1738,22 @@ void solve_ir(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
             const bool batch = nsys > 1;
             auto norms = [&](const double *xx, T *rt, double *out) {
                 if (batch) {
-                    hipLaunchKernelGGL((k_ir_residual<T, R, true>), dim3(G), dim3(WG), 0, c.stream, S.nrows,
-                                       S.nslices, S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), b,
-                                       xx, rt, (double *)nullptr, c.sys_het.get(), c.sys_spart.get(), c.rn2.get());
+                    dispatch_nb((int)L0.nb, [&](auto nbc) {
+                        constexpr int NB = decltype(nbc)::value;
+                        hipLaunchKernelGGL((k_ir_residual<T, R, true, NB>), dim3(G), dim3(WG), 0, c.stream, S.nrows,
+                                           S.nslices, S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), b,
+                                           xx, rt, (double *)nullptr, c.sys_het.get(), c.sys_spart.get(), c.rn2.get());
+                    });
                     hipLaunchKernelGGL(k_sys_norms, dim3(nsys), dim3(256), 0, c.stream, R, S.nrows,
                                        c.sys_ptr_d.get(), c.sys_het.get(), c.sys_spart.get(), c.rn2.get(), out);
                 } else {
-                    hipLaunchKernelGGL((k_ir_residual<T, R, false>), dim3(G), dim3(WG), 0, c.stream, S.nrows,
-                                       S.nslices, S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), b,
-                                       xx, rt, c.ir_partial.get(), (const int32_t *)nullptr, (double *)nullptr,
-                                       (double *)nullptr);
+                    dispatch_nb((int)L0.nb, [&](auto nbc) {
+                        constexpr int NB = decltype(nbc)::value;
+                        hipLaunchKernelGGL((k_ir_residual<T, R, false, NB>), dim3(G), dim3(WG), 0, c.stream, S.nrows,
+                                           S.nslices, S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), b,
+                                           xx, rt, c.ir_partial.get(), (const int32_t *)nullptr, (double *)nullptr,
+                                           (double *)nullptr);
+                    });
                     hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(1024), 0, c.stream, G, R, c.ir_partial.get(),
                                        out);
                 }
@@ -1883,14 +1973,20 @@ void solve_cg(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
                 trace_end(c, slot);
                 slot = trace_begin(c, CS_TRACE_REFINE, S.nnz * 12.0 + 3.0 * vec);
                 if (batch)
-                    hipLaunchKernelGGL((k_cg_ap<R, true>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
-                                       S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), p, r, q,
-                                       c.sys_het.get(), c.sys_spart.get(), c.rn2.get(), (double *)nullptr);
+                    dispatch_nb((int)L0.nb, [&](auto nbc) {
+                        constexpr int NB = decltype(nbc)::value;
+                        hipLaunchKernelGGL((k_cg_ap<R, true, NB>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
+                                           S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), p, r, q,
+                                           c.sys_het.get(), c.sys_spart.get(), c.rn2.get(), (double *)nullptr);
+                    });
                 else
-                    hipLaunchKernelGGL((k_cg_ap<R, false>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
-                                       S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), p, r, q,
-                                       (const int32_t *)nullptr, (double *)nullptr, (double *)nullptr,
-                                       c.ir_partial.get());
+                    dispatch_nb((int)L0.nb, [&](auto nbc) {
+                        constexpr int NB = decltype(nbc)::value;
+                        hipLaunchKernelGGL((k_cg_ap<R, false, NB>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
+                                           S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), p, r, q,
+                                           (const int32_t *)nullptr, (double *)nullptr, (double *)nullptr,
+                                           c.ir_partial.get());
+                    });
                 CS_LAUNCH_CHECK();
                 reduce(2 * R, pq);
                 trace_end(c, slot);
@@ -2004,17 +2100,23 @@ void solve_gmres(Ctx &c, const double *b, double *x, int nrhs, double rtol, int 
             // norms into n2 and sc_0 = 1 / ||u||
             auto monitored = [&](double *n2) {
                 if (!flexible) {
-                    hipLaunchKernelGGL((k_gm_spmv<T, R>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
-                                       S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), x, b,
-                                       (const double *)nullptr, nsys, sysp, bb);
+                    dispatch_nb((int)L0.nb, [&](auto nbc) {
+                        constexpr int NB = decltype(nbc)::value;
+                        hipLaunchKernelGGL((k_gm_spmv<T, R, NB>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
+                                           S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), x, b,
+                                           (const double *)nullptr, nsys, sysp, bb);
+                    });
                     CS_LAUNCH_CHECK();
                     vcycle_level<T, R>(c, 0);
                     hipLaunchKernelGGL((k_gm_update<T, R, false>), gg, dim3(WG), 0, c.stream, nel, nsys, sys_wg, sysp,
                                        0, V, nel, sc, dh, xb, V, part);
                 } else {
-                    hipLaunchKernelGGL((k_gm_spmv<double, R>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
-                                       S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), x, b,
-                                       (const double *)nullptr, nsys, sysp, w1);
+                    dispatch_nb((int)L0.nb, [&](auto nbc) {
+                        constexpr int NB = decltype(nbc)::value;
+                        hipLaunchKernelGGL((k_gm_spmv<double, R, NB>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
+                                           S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), x, b,
+                                           (const double *)nullptr, nsys, sysp, w1);
+                    });
                     hipLaunchKernelGGL((k_gm_update<double, R, false>), gg, dim3(WG), 0, c.stream, nel, nsys, sys_wg,
                                        sysp, 0, V, nel, sc, dh, (const double *)w1, V, part);
                 }
@@ -2070,9 +2172,12 @@ void solve_gmres(Ctx &c, const double *b, double *x, int nrhs, double rtol, int 
                     double *vj = V + (int64_t)j * nel, *vn = V + (int64_t)(j + 1) * nel;
                     int slot = trace_begin(c, CS_TRACE_REFINE, S.nnz * 12.0 + (double)nel * (8.0 + sizeof(T)));
                     if (!flexible) {
-                        hipLaunchKernelGGL((k_gm_spmv<T, R>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
-                                           S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), vj,
-                                           (const double *)nullptr, sc + (int64_t)j * ncol, nsys, sysp, bb);
+                        dispatch_nb((int)L0.nb, [&](auto nbc) {
+                            constexpr int NB = decltype(nbc)::value;
+                            hipLaunchKernelGGL((k_gm_spmv<T, R, NB>), dim3(G), dim3(WG), 0, c.stream, S.nrows, S.nslices,
+                                               S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), vj,
+                                               (const double *)nullptr, sc + (int64_t)j * ncol, nsys, sysp, bb);
+                        });
                         CS_LAUNCH_CHECK();
                         trace_end(c, slot);
                         vcycle_level<T, R>(c, 0);
@@ -2086,10 +2191,13 @@ void solve_gmres(Ctx &c, const double *b, double *x, int nrhs, double rtol, int 
                         double *zj = Z + (int64_t)j * nel;
                         hipLaunchKernelGGL((k_convert<T, double>), dim3(grid_for(nel)), dim3(WG), 0, c.stream, nel,
                                            xb, zj);
-                        hipLaunchKernelGGL((k_gm_spmv<double, R>), dim3(G), dim3(WG), 0, c.stream, S.nrows,
-                                           S.nslices, S.slice_ptr.get(), S.slice_len.get(), S.col.get(),
-                                           S.val64.get(), zj, (const double *)nullptr, (const double *)nullptr, nsys,
-                                           sysp, w2);
+                        dispatch_nb((int)L0.nb, [&](auto nbc) {
+                            constexpr int NB = decltype(nbc)::value;
+                            hipLaunchKernelGGL((k_gm_spmv<double, R, NB>), dim3(G), dim3(WG), 0, c.stream, S.nrows,
+                                               S.nslices, S.slice_ptr.get(), S.slice_len.get(), S.col.get(),
+                                               S.val64.get(), zj, (const double *)nullptr, (const double *)nullptr, nsys,
+                                               sysp, w2);
+                        });
                         CS_LAUNCH_CHECK();
                         trace_end(c, slot);
                     }
