@@ -930,6 +930,15 @@ __global__ __launch_bounds__(WG) void k_cg_update_flat(int64_t npairs, int nsys,
 constexpr int GM_MAXV = 32;             // basis vectors per kernel (restart + 1)
 constexpr int64_t GM_CHUNK = 4 * WG;    // elements per workgroup in a batch
 
+// register-array size of the GMRES vector kernels for nv basis vectors
+template <class F>
+void dispatch_mv(int nv, F &&f) {
+    if (nv <= 4) f(std::integral_constant<int, 4>{});
+    else if (nv <= 8) f(std::integral_constant<int, 8>{});
+    else if (nv <= 16) f(std::integral_constant<int, 16>{});
+    else f(std::integral_constant<int, GM_MAXV>{});
+}
+
 struct ElemRange {
     int64_t begin, end, stride;
     int sys;
@@ -952,17 +961,17 @@ __device__ __forceinline__ ElemRange elem_range(int64_t nel, int nsys, const int
 
 // Workgroup partial sums of NV values per thread, reduced over the threads of
 // one right-hand side (t mod R): partial[blockIdx][i][R].
-template <int R>
-__device__ __forceinline__ void gm_partials(const double (&acc)[GM_MAXV], int nv, double *red,
+template <int R, int MV>
+__device__ __forceinline__ void gm_partials(const double (&acc)[MV], int nv, double *red,
                                             double *__restrict__ partial) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-    for (int i = 0; i < GM_MAXV; ++i) {
+    for (int i = 0; i < MV; ++i) {
         if (i < nv) {   // uniform
             double v = acc[i];
 #pragma unroll
             for (int off = 32; off >= R; off >>= 1) v += __shfl_xor(v, off, 64);
-            if (lane < R) red[(wv * GM_MAXV + i) * R + lane] = v;
+            if (lane < R) red[(wv * MV + i) * R + lane] = v;
         }
     }
     __syncthreads();
@@ -970,60 +979,60 @@ __device__ __forceinline__ void gm_partials(const double (&acc)[GM_MAXV], int nv
         const int i = e / R, k = e % R;
         double s = 0.0;
 #pragma unroll
-        for (int w = 0; w < WG / 64; ++w) s += red[(w * GM_MAXV + i) * R + k];
+        for (int w = 0; w < WG / 64; ++w) s += red[(w * MV + i) * R + k];
         partial[(int64_t)blockIdx.x * nv * R + e] = s;
     }
 }
 
 // h_i = (v_i, w) for i < nv
-template <typename W, int R>
+template <typename W, int R, int MV>
 __global__ __launch_bounds__(WG) void k_gm_dots(int64_t nel, int nsys, const int32_t *__restrict__ sys_wg,
                                                 const int64_t *__restrict__ sys_ptr, int nv,
                                                 const double *__restrict__ vt, int64_t ld,
                                                 const double *__restrict__ sc, const W *__restrict__ w,
                                                 double *__restrict__ partial) {
-    __shared__ double red[(WG / 64) * GM_MAXV * R];
+    __shared__ double red[(WG / 64) * MV * R];
     const ElemRange er = elem_range<R>(nel, nsys, sys_wg, sys_ptr);
     const int col = er.sys * R + (int)(threadIdx.x % R);
-    double acc[GM_MAXV];
+    double acc[MV];
 #pragma unroll
-    for (int i = 0; i < GM_MAXV; ++i) acc[i] = 0.0;
+    for (int i = 0; i < MV; ++i) acc[i] = 0.0;
     for (int64_t e = er.begin; e < er.end; e += er.stride) {
         const double we = (double)w[e];
 #pragma unroll
-        for (int i = 0; i < GM_MAXV; ++i)
+        for (int i = 0; i < MV; ++i)
             if (i < nv) acc[i] += __builtin_nontemporal_load(vt + i * ld + e) * we;
     }
 #pragma unroll
-    for (int i = 0; i < GM_MAXV; ++i)
+    for (int i = 0; i < MV; ++i)
         if (i < nv) acc[i] *= sc[(int64_t)i * nsys * R + col];
-    gm_partials<R>(acc, nv, red, partial);
+    gm_partials<R, MV>(acc, nv, red, partial);
 }
 
 // w' = w - sum_i h_i v_i (h[sys][i][R] from the reduction), stored in FP64;
 // with DOTS the partial sums of (v_i, w') for i < nv, else of (w', w').
 // nv = 0 copies w (converted) and sums its squares.
-template <typename W, int R, bool DOTS>
+template <typename W, int R, bool DOTS, int MV>
 __global__ __launch_bounds__(WG) void k_gm_update(int64_t nel, int nsys, const int32_t *__restrict__ sys_wg,
                                                   const int64_t *__restrict__ sys_ptr, int nv,
                                                   const double *__restrict__ vt, int64_t ld,
                                                   const double *__restrict__ sc, const double *__restrict__ h,
                                                   const W *__restrict__ w, double *__restrict__ wout,
                                                   double *__restrict__ partial) {
-    __shared__ double red[(WG / 64) * GM_MAXV * R];
+    __shared__ double red[(WG / 64) * MV * R];
     const ElemRange er = elem_range<R>(nel, nsys, sys_wg, sys_ptr);
     const int k = (int)(threadIdx.x % R), col = er.sys * R + k;
-    double coef[GM_MAXV], acc[GM_MAXV];
+    double coef[MV], acc[MV];
 #pragma unroll
-    for (int i = 0; i < GM_MAXV; ++i) {
+    for (int i = 0; i < MV; ++i) {
         acc[i] = 0.0;
         coef[i] = i < nv ? h[((int64_t)er.sys * nv + i) * R + k] * sc[(int64_t)i * nsys * R + col] : 0.0;
     }
     for (int64_t e = er.begin; e < er.end; e += er.stride) {
-        double v[GM_MAXV];
+        double v[MV];
         double we = (double)w[e];
 #pragma unroll
-        for (int i = 0; i < GM_MAXV; ++i)
+        for (int i = 0; i < MV; ++i)
             if (i < nv) {
                 v[i] = __builtin_nontemporal_load(vt + i * ld + e);
                 we -= coef[i] * v[i];
@@ -1031,7 +1040,7 @@ __global__ __launch_bounds__(WG) void k_gm_update(int64_t nel, int nsys, const i
         wout[e] = we;
         if constexpr (DOTS) {
 #pragma unroll
-            for (int i = 0; i < GM_MAXV; ++i)
+            for (int i = 0; i < MV; ++i)
                 if (i < nv) acc[i] += v[i] * we;
         } else {
             acc[0] += we * we;
@@ -1039,15 +1048,15 @@ __global__ __launch_bounds__(WG) void k_gm_update(int64_t nel, int nsys, const i
     }
     if constexpr (DOTS) {
 #pragma unroll
-        for (int i = 0; i < GM_MAXV; ++i)
+        for (int i = 0; i < MV; ++i)
             if (i < nv) acc[i] *= sc[(int64_t)i * nsys * R + col];
     }
-    gm_partials<R>(acc, DOTS ? nv : 1, red, partial);
+    gm_partials<R, MV>(acc, DOTS ? nv : 1, red, partial);
 }
 
 // x += sum_{i < nv} y[col][i] * basis_i, basis_i = sc_i vt_i (sc != null) or
 // the stored preconditioned vectors (sc == null); y is [ncol][ystride]
-template <typename B, int R>
+template <typename B, int R, int MV>
 __global__ __launch_bounds__(WG) void k_gm_xupdate(int64_t nel, int nsys, const int32_t *__restrict__ sys_wg,
                                                    const int64_t *__restrict__ sys_ptr, int nv,
                                                    const B *__restrict__ basis, int64_t ld,
@@ -1055,14 +1064,14 @@ __global__ __launch_bounds__(WG) void k_gm_xupdate(int64_t nel, int nsys, const 
                                                    int ystride, double *__restrict__ x) {
     const ElemRange er = elem_range<R>(nel, nsys, sys_wg, sys_ptr);
     const int col = er.sys * R + (int)(threadIdx.x % R);
-    double coef[GM_MAXV];
+    double coef[MV];
 #pragma unroll
-    for (int i = 0; i < GM_MAXV; ++i)
+    for (int i = 0; i < MV; ++i)
         coef[i] = i < nv ? y[(int64_t)col * ystride + i] * (sc ? sc[(int64_t)i * nsys * R + col] : 1.0) : 0.0;
     for (int64_t e = er.begin; e < er.end; e += er.stride) {
         double xe = x[e];
 #pragma unroll
-        for (int i = 0; i < GM_MAXV; ++i)
+        for (int i = 0; i < MV; ++i)
             if (i < nv) xe += coef[i] * (double)__builtin_nontemporal_load(basis + i * ld + e);
         x[e] = xe;
     }
@@ -1070,20 +1079,34 @@ __global__ __launch_bounds__(WG) void k_gm_xupdate(int64_t nel, int nsys, const 
 
 // Per-system sums of GMRES partials: out[s][c] = sum over the workgroups of
 // system s of partial[b][c], c < W.  Workgroup (s, c-block of 64): wavefront
-// w sums every fourth workgroup, then the four wavefronts are added in order.
-__global__ __launch_bounds__(256) void k_gm_reduce(int W, int64_t G, const int32_t *__restrict__ sys_wg,
-                                                   const double *__restrict__ partial, double *__restrict__ out) {
-    __shared__ double red[4][64];
+// w of 16 sums every 16th workgroup with four independent accumulators (loads
+// in flight), then the wavefronts are added in order.  Fixed order throughout.
+__global__ __launch_bounds__(1024) void k_gm_reduce(int W, int64_t G, const int32_t *__restrict__ sys_wg,
+                                                    const double *__restrict__ partial, double *__restrict__ out) {
+    __shared__ double red[16][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int s = blockIdx.y;
     const int c = blockIdx.x * 64 + lane;
     const int64_t b0 = sys_wg ? sys_wg[s] : 0, b1 = sys_wg ? sys_wg[s + 1] : G;
-    double v = 0.0;
-    if (c < W)
-        for (int64_t b = b0 + wv; b < b1; b += 4) v += partial[b * W + c];
-    red[wv][lane] = v;
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+    if (c < W) {
+        int64_t b = b0 + wv;
+        for (; b + 48 < b1; b += 64) {
+            v0 += partial[b * W + c];
+            v1 += partial[(b + 16) * W + c];
+            v2 += partial[(b + 32) * W + c];
+            v3 += partial[(b + 48) * W + c];
+        }
+        for (; b < b1; b += 16) v0 += partial[b * W + c];
+    }
+    red[wv][lane] = (v0 + v1) + (v2 + v3);
     __syncthreads();
-    if (wv == 0 && c < W) out[(int64_t)s * W + c] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+    if (wv == 0 && c < W) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < 16; ++w) t += red[w][lane];
+        out[(int64_t)s * W + c] = t;
+    }
 }
 
 // sc[col] = 1 / sqrt(n2[col]) (0 for a zero or non-finite norm)
@@ -2091,7 +2114,7 @@ void solve_gmres(Ctx &c, const double *b, double *x, int nrhs, double rtol, int 
             T *bb = reinterpret_cast<T *>(L0.bb.get());
             const T *xb = reinterpret_cast<const T *>(L0.xb.get());
             auto reduce = [&](int W, double *out) {
-                hipLaunchKernelGGL(k_gm_reduce, dim3((unsigned)ceil_div(W, 64), (unsigned)nsys), dim3(256), 0,
+                hipLaunchKernelGGL(k_gm_reduce, dim3((unsigned)ceil_div(W, 64), (unsigned)nsys), dim3(1024), 0,
                                    c.stream, W, Gp, sys_wg, part, out);
                 CS_LAUNCH_CHECK();
             };
@@ -2108,8 +2131,11 @@ void solve_gmres(Ctx &c, const double *b, double *x, int nrhs, double rtol, int 
                     });
                     CS_LAUNCH_CHECK();
                     vcycle_level<T, R>(c, 0);
-                    hipLaunchKernelGGL((k_gm_update<T, R, false>), gg, dim3(WG), 0, c.stream, nel, nsys, sys_wg, sysp,
-                                       0, V, nel, sc, dh, xb, V, part);
+                    dispatch_mv(0, [&](auto mvc) {
+                        constexpr int MV = decltype(mvc)::value;
+                        hipLaunchKernelGGL((k_gm_update<T, R, false, MV>), gg, dim3(WG), 0, c.stream, nel, nsys, sys_wg, sysp,
+                                           0, V, nel, sc, dh, xb, V, part);
+                    });
                 } else {
                     dispatch_nb((int)L0.nb, [&](auto nbc) {
                         constexpr int NB = decltype(nbc)::value;
@@ -2117,8 +2143,11 @@ void solve_gmres(Ctx &c, const double *b, double *x, int nrhs, double rtol, int 
                                            S.slice_ptr.get(), S.slice_len.get(), S.col.get(), S.val64.get(), x, b,
                                            (const double *)nullptr, nsys, sysp, w1);
                     });
-                    hipLaunchKernelGGL((k_gm_update<double, R, false>), gg, dim3(WG), 0, c.stream, nel, nsys, sys_wg,
-                                       sysp, 0, V, nel, sc, dh, (const double *)w1, V, part);
+                    dispatch_mv(0, [&](auto mvc) {
+                        constexpr int MV = decltype(mvc)::value;
+                        hipLaunchKernelGGL((k_gm_update<double, R, false, MV>), gg, dim3(WG), 0, c.stream, nel, nsys, sys_wg,
+                                           sysp, 0, V, nel, sc, dh, (const double *)w1, V, part);
+                    });
                 }
                 CS_LAUNCH_CHECK();
                 reduce(R, n2);
@@ -2204,24 +2233,39 @@ void solve_gmres(Ctx &c, const double *b, double *x, int nrhs, double rtol, int 
                     // two Gram-Schmidt passes: h1 = V^T w, w1 = w - V h1; h2 = V^T w1, v_{j+1} = w1 - V h2
                     slot = trace_begin(c, CS_TRACE_REFINE, (3.0 * nv + 4.0) * nel * 8.0);
                     if (!flexible) {
-                        hipLaunchKernelGGL((k_gm_dots<T, R>), gg, dim3(WG), 0, c.stream, nel, nsys, sys_wg, sysp, nv,
-                                           V, nel, sc, xb, part);
+                        dispatch_mv(nv, [&](auto mvc) {
+                            constexpr int MV = decltype(mvc)::value;
+                            hipLaunchKernelGGL((k_gm_dots<T, R, MV>), gg, dim3(WG), 0, c.stream, nel, nsys, sys_wg, sysp, nv,
+                                               V, nel, sc, xb, part);
+                        });
                         CS_LAUNCH_CHECK();
                         reduce(nv * R, h1);
-                        hipLaunchKernelGGL((k_gm_update<T, R, true>), gg, dim3(WG), 0, c.stream, nel, nsys, sys_wg,
-                                           sysp, nv, V, nel, sc, h1, xb, w1, part);
+                        dispatch_mv(nv, [&](auto mvc) {
+                            constexpr int MV = decltype(mvc)::value;
+                            hipLaunchKernelGGL((k_gm_update<T, R, true, MV>), gg, dim3(WG), 0, c.stream, nel, nsys, sys_wg,
+                                               sysp, nv, V, nel, sc, h1, xb, w1, part);
+                        });
                     } else {
-                        hipLaunchKernelGGL((k_gm_dots<double, R>), gg, dim3(WG), 0, c.stream, nel, nsys, sys_wg,
-                                           sysp, nv, V, nel, sc, (const double *)w2, part);
+                        dispatch_mv(nv, [&](auto mvc) {
+                            constexpr int MV = decltype(mvc)::value;
+                            hipLaunchKernelGGL((k_gm_dots<double, R, MV>), gg, dim3(WG), 0, c.stream, nel, nsys, sys_wg,
+                                               sysp, nv, V, nel, sc, (const double *)w2, part);
+                        });
                         CS_LAUNCH_CHECK();
                         reduce(nv * R, h1);
-                        hipLaunchKernelGGL((k_gm_update<double, R, true>), gg, dim3(WG), 0, c.stream, nel, nsys,
-                                           sys_wg, sysp, nv, V, nel, sc, h1, (const double *)w2, w1, part);
+                        dispatch_mv(nv, [&](auto mvc) {
+                            constexpr int MV = decltype(mvc)::value;
+                            hipLaunchKernelGGL((k_gm_update<double, R, true, MV>), gg, dim3(WG), 0, c.stream, nel, nsys,
+                                               sys_wg, sysp, nv, V, nel, sc, h1, (const double *)w2, w1, part);
+                        });
                     }
                     CS_LAUNCH_CHECK();
                     reduce(nv * R, h2);
-                    hipLaunchKernelGGL((k_gm_update<double, R, false>), gg, dim3(WG), 0, c.stream, nel, nsys, sys_wg,
-                                       sysp, nv, V, nel, sc, h2, (const double *)w1, vn, part);
+                    dispatch_mv(nv, [&](auto mvc) {
+                        constexpr int MV = decltype(mvc)::value;
+                        hipLaunchKernelGGL((k_gm_update<double, R, false, MV>), gg, dim3(WG), 0, c.stream, nel, nsys, sys_wg,
+                                           sysp, nv, V, nel, sc, h2, (const double *)w1, vn, part);
+                    });
                     CS_LAUNCH_CHECK();
                     reduce(R, n2);
                     hipLaunchKernelGGL(k_gm_rscale, dim3((unsigned)ceil_div(ncol, 256)), dim3(256), 0, c.stream, ncol,
@@ -2288,13 +2332,19 @@ void solve_gmres(Ctx &c, const double *b, double *x, int nrhs, double rtol, int 
                 if (kmax > 0) {
                     c.gm_y.upload(y.data(), y.size(), c.stream);
                     if (!flexible)
-                        hipLaunchKernelGGL((k_gm_xupdate<double, R>), gg, dim3(WG), 0, c.stream, nel, nsys, sys_wg,
-                                           sysp, kmax, (const double *)V, nel, (const double *)sc,
-                                           (const double *)c.gm_y.get(), m, x);
+                        dispatch_mv(kmax, [&](auto mvc) {
+                            constexpr int MV = decltype(mvc)::value;
+                            hipLaunchKernelGGL((k_gm_xupdate<double, R, MV>), gg, dim3(WG), 0, c.stream, nel, nsys, sys_wg,
+                                               sysp, kmax, (const double *)V, nel, (const double *)sc,
+                                               (const double *)c.gm_y.get(), m, x);
+                        });
                     else
-                        hipLaunchKernelGGL((k_gm_xupdate<double, R>), gg, dim3(WG), 0, c.stream, nel, nsys, sys_wg,
-                                           sysp, kmax, (const double *)Z, nel, (const double *)nullptr,
-                                           (const double *)c.gm_y.get(), m, x);
+                        dispatch_mv(kmax, [&](auto mvc) {
+                            constexpr int MV = decltype(mvc)::value;
+                            hipLaunchKernelGGL((k_gm_xupdate<double, R, MV>), gg, dim3(WG), 0, c.stream, nel, nsys, sys_wg,
+                                               sysp, kmax, (const double *)Z, nel, (const double *)nullptr,
+                                               (const double *)c.gm_y.get(), m, x);
+                        });
                     CS_LAUNCH_CHECK();
                 }
                 // the monitored residual of the new x replaces the last estimate
