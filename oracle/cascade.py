@@ -250,6 +250,53 @@ def fit_multiplicative(A: sp.spmatrix, n: int, depth: int, colours: np.ndarray,
                 colours=colours.astype(np.int32), gram_cond=cond)
 
 
+def fit_sketched(A: sp.spmatrix, n: int, depth: int, S: np.ndarray, mode: str = "additive",
+                 colours: Optional[np.ndarray] = None) -> Dict:
+    """Sketched cascade construction (Sec. 4, Concluding Remarks, proposed there as
+    future work).
+
+    The square residual E_{l-1} is replaced by the tall-and-narrow sketch
+    T_{l-1} = E_{l-1} S, S an N x s matrix of random error modes (given):
+        Lambda_l = argmin_{Lambda block-diagonal} ||(I - Lambda A~) T_{l-1}||_F,
+        T_l = (I - Lambda_l A~) T_{l-1},  T_0 = S,
+    on the prescaled A~ = W A W, block by block through the normal equations
+    Lambda_i G_i = H_i with M = A~ T, G_i = M_i M_i^T, H_i = T_i M_i^T (the
+    same minimum-norm solve as the exact fit).  With S = I it is the exact fit.
+    Multiplicative: the blocks of colour k are fitted from the current T, then
+    their rows of T are updated, colours ascending (Sec. 2.2)."""
+    A = sp.csr_matrix(A)
+    N = A.shape[0]
+    B = N // n
+    w, At = prescale(A)
+    T = np.array(S, dtype=np.float64, copy=True)
+    s = T.shape[1]
+    if mode == "additive":
+        groups = [np.arange(B)]
+    elif mode == "multiplicative":
+        colours = np.asarray(colours, dtype=np.int64)
+        groups = [np.flatnonzero(colours == k) for k in range(int(colours.max()) + 1)]
+    else:
+        raise ValueError(mode)
+    lam_t = [np.zeros((B, n, n)) for _ in range(depth)]
+    cond = [np.ones(B) for _ in range(depth)]
+    for ell in range(1, depth + 1):
+        for blocks in groups:
+            if len(blocks) == 0:
+                continue
+            M = At @ T
+            rows = block_rows(blocks, n)
+            Mb = M[rows].reshape(len(blocks), n, s)
+            Tb = T[rows].reshape(len(blocks), n, s)
+            G = Mb @ Mb.transpose(0, 2, 1)
+            H = Tb @ Mb.transpose(0, 2, 1)
+            Lt = least_squares_blocks(H, G)
+            lam_t[ell - 1][blocks] = Lt
+            cond[ell - 1][blocks] = gram_condition(G)
+            T[rows] = (Tb - Lt @ Mb).reshape(-1, s)
+    return dict(lam=[unscale(L, w) for L in lam_t], lam_tilde=lam_t, w=w,
+                colours=None if mode == "additive" else colours.astype(np.int32), gram_cond=cond)
+
+
 def fit(A, n, depth, mode="additive", colours=None, alpha=None) -> Dict:
     if mode == "additive":
         return fit_additive(A, n, depth, alpha)

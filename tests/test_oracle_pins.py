@@ -689,3 +689,68 @@ def test_gmres_with_vcycle_left_and_flexible():
     r = p.rhs - A @ xf
     np.testing.assert_allclose(hf[-1], np.max(np.linalg.norm(r, axis=0) / np.linalg.norm(p.rhs, axis=0)), rtol=1e-9)
     assert hf[-1] <= 1e-10 and abs(len(hf) - len(h)) <= 2
+
+
+# ---------------------------------------------------------------------------
+# Sketched construction (Sec. 4): pinned to the exact fit (S = I), to brute-force
+# least squares per block and to the invariances of the sketch.
+# ---------------------------------------------------------------------------
+
+def _small_interface():
+    p = fd.interface3d(8, nrhs=1)
+    return p.levels[0].A, p.levels[0].block_size
+
+
+@pytest.mark.parametrize("mode", ["additive", "multiplicative"])
+def test_sketch_with_identity_is_the_exact_fit(mode):
+    if mode == "additive":
+        A, n = _small_interface()
+        colours = None
+        exact = O.fit_additive(A, n, 3)
+    else:
+        A = fd.poisson2d(12).levels[0].A
+        n = 1
+        colours = O.greedy_colour(O.block_pattern(A, 1))
+        exact = O.fit_multiplicative(A, n, 3, colours)
+    sk = O.fit_sketched(A, n, 3, np.eye(A.shape[0]), mode=mode, colours=colours)
+    for L1, L2 in zip(sk["lam"], exact["lam"]):
+        np.testing.assert_allclose(L1, L2, rtol=1e-10, atol=1e-14)
+
+
+def test_sketch_first_level_is_blockwise_least_squares():
+    A, n = _small_interface()
+    rng = stream(1, TEST, 70)
+    S = rng.choice([-1.0, 1.0], size=(A.shape[0], 24))
+    sk = O.fit_sketched(A, n, 1, S)
+    w, At = O.prescale(A)
+    M = At @ S
+    for i in range(0, A.shape[0] // n, 7):
+        r = slice(i * n, (i + 1) * n)
+        # Lambda_i = argmin ||S_i - Lambda M_i||_F  <=>  M_i^T Lambda^T = S_i^T
+        Lt = np.linalg.lstsq(M[r].T, S[r].T, rcond=None)[0].T
+        np.testing.assert_allclose(sk["lam_tilde"][0][i], Lt, rtol=1e-9, atol=1e-12)
+
+
+def test_sketch_is_invariant_to_scaling_sign_flips_and_column_order():
+    A, n = _small_interface()
+    rng = stream(1, TEST, 71)
+    S = rng.choice([-1.0, 1.0], size=(A.shape[0], 16))
+    ref = O.fit_sketched(A, n, 3, S)
+    signs = rng.choice([-1.0, 1.0], size=16)
+    perm = rng.permutation(16)
+    for S2 in (3.7 * S, S * signs, S[:, perm]):
+        got = O.fit_sketched(A, n, 3, S2)
+        for L1, L2 in zip(got["lam"], ref["lam"]):
+            np.testing.assert_allclose(L1, L2, rtol=1e-9, atol=1e-13)
+
+
+def test_wider_sketch_approaches_the_exact_fit():
+    A, n = _small_interface()
+    exact = O.fit_additive(A, n, 2)
+    rng = stream(1, TEST, 72)
+    errs = []
+    for s in (16, 64, 256):
+        S = rng.choice([-1.0, 1.0], size=(A.shape[0], s))
+        sk = O.fit_sketched(A, n, 2, S)
+        errs.append(np.linalg.norm(sk["lam"][0] - exact["lam"][0]) / np.linalg.norm(exact["lam"][0]))
+    assert errs[0] > errs[1] > errs[2], errs
