@@ -198,6 +198,20 @@ cs_status cs_solve_cg(cs_ctx ctx, const double *b, double *x, int32_t nrhs, doub
 cs_status cs_solve_gmres(cs_ctx ctx, const double *b, double *x, int32_t nrhs, double rtol, int32_t maxit,
                          int32_t restart, int32_t flexible, cs_info *info, double *history);
 
+/* Sketched construction (Sec. 4, Concluding Remarks, proposed there): every
+ * cascade level is fitted against a tall sketch T = E S of the residual instead
+ * of the square E, Lambda~_l = argmin ||(I - Lambda A~) T_{l-1}||_F,
+ * T_l = (I - Lambda~_l A~) T_{l-1}, T_0 = S, on the prescaled A~ = W A W, block by
+ * block through the same normal equations as cs_setup (multicoloured: colour by
+ * colour, Sec. 2.2).  With S = I it reproduces cs_setup.  The memory is 2-3
+ * N x s arrays per level instead of the fill-in of E.
+ *   S: device FP64, the sketches of all smoothed levels one after the other
+ *      (level l: n_l x s, row-major, at offset s * (n_0 + ... + n_{l-1})); the
+ *      caller draws them (e.g. Rademacher +-1); only their span matters.
+ *   s: sketch width, 1..64.  opt: as cs_setup; trunc_alpha must be 0.
+ * Residual patterns (cs_get_pattern) are not available after this setup. */
+cs_status cs_setup_sketched(cs_ctx ctx, const cs_options *opt, int32_t s, const double *S);
+
 /* Pick the launch schedule of every level's cascade sweeps by measurement
  * (needs a setup): for the current working precision and nrhs, one cascade
  * application per level is timed for each candidate schedule (64 or 256 rows

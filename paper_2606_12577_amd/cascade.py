@@ -77,6 +77,7 @@ SIGNATURES = {
     "cs_solve_cg": (_I32, [_VP, _VP, _VP, _I32, _D, _I32, _p(cs_info), _p(_D)]),
     "cs_solve_gmres": (_I32, [_VP, _VP, _VP, _I32, _D, _I32, _I32, _I32, _p(cs_info), _p(_D)]),
     "cs_autotune": (_I32, [_VP, _I32, _p(_I32), _p(_I64), _p(_D)]),
+    "cs_setup_sketched": (_I32, [_VP, _p(cs_options), _I32, _VP]),
     "cs_trace": (_I32, [_VP, _I32, _I32]),
     "cs_trace_read": (_I32, [_VP, _I32, _p(_D), _p(_I64), _p(_D)]),
     "cs_set_systems": (_I32, [_VP, _I32, _p(_I64)]),
@@ -223,6 +224,26 @@ class Solver:
         o = cs_options(depth, _MODES[mode], _ORDERS[order], n_pre, n_post, alpha, _PRECS[precision])
         self.depth = depth
         self._check(self._lib.cs_setup(self._h, ctypes.byref(o)))
+
+    def setup_sketched(self, width: int = 32, seed: int = 0, sketch=None, depth: int = 3, mode: str = "additive",
+                       order: str = "RF", n_pre: int = 1, n_post: int = 1, precision: str = "fp64"):
+        """Sketched cascade construction: every level is fitted against `width`
+        random error modes.  `sketch` (device or host, (sum of the smoothed
+        levels' sizes) x width) gives them; otherwise Rademacher +-1 modes are
+        drawn on the device from `seed`.  Returns the sketch used."""
+        total = sum(n for n, _ in self.sizes[:-1])
+        if sketch is None:
+            g = self._torch.Generator(device=self.device)
+            g.manual_seed(int(seed))
+            sketch = self._torch.randint(0, 2, (total, width), generator=g, device=self.device)
+            sketch = (2.0 * sketch - 1.0).to(self._torch.float64)
+        S = self._torch.as_tensor(sketch, dtype=self._torch.float64, device=self.device).contiguous()
+        if tuple(S.shape) != (total, width):
+            raise ValueError(f"sketch must be {total} x {width}")
+        o = cs_options(depth, _MODES[mode], _ORDERS[order], n_pre, n_post, 0, _PRECS[precision])
+        self.depth = depth
+        self._check(self._lib.cs_setup_sketched(self._h, ctypes.byref(o), width, _tensor_ptr(S)))
+        return S
 
     def set_precision(self, precision: str):
         self._check(self._lib.cs_set_precision(self._h, _PRECS[precision]))

@@ -311,6 +311,27 @@ cs_status cs_setup(cs_ctx ctx, const cs_options *opt) {
     });
 }
 
+cs_status cs_setup_sketched(cs_ctx ctx, const cs_options *opt, int32_t s, const double *S) {
+    return guarded(ctx, [&](Ctx &c) {
+        need(c.have_hierarchy, "cs_setup_sketched before cs_set_hierarchy", CS_ESTATE);
+        need(opt != nullptr && S != nullptr, "options or sketch missing");
+        need(s >= 1 && s <= 64, "the sketch width must be in [1, 64]");
+        need(opt->depth >= 1 && opt->depth <= 16, "depth must be in [1, 16]");
+        need(opt->mode == CS_ADDITIVE || opt->mode == CS_MULTIPLICATIVE, "mode must be additive or multiplicative");
+        need(opt->order == CS_FF || opt->order == CS_RF, "order must be FF or RF");
+        need(opt->n_pre >= 1 && opt->n_post >= 0, "need n_pre >= 1 and n_post >= 0");
+        need(opt->trunc_alpha == 0, "truncation applies to the exact fit only");
+        need(opt->precision == CS_FP64 || opt->precision == CS_FP32 || opt->precision == CS_BF16,
+             "precision must be FP64, FP32 or BF16");
+        c.have_setup = false;
+        c.opt = *opt;
+        c.precision = opt->precision;
+        c.ws_nrhs = 0;
+        cs::run_setup_sketched(c, *opt, s, S);
+        c.have_setup = true;
+    });
+}
+
 cs_status cs_setup_learned(cs_ctx ctx, const cs_options *opt, cs_mlp mlp, const float *X) {
     return guarded(ctx, [&](Ctx &c) {
         need(c.have_hierarchy, "cs_setup_learned before cs_set_hierarchy", CS_ESTATE);

@@ -254,6 +254,7 @@ void build_working_copies(Ctx &c);
 void factor_direct(Ctx &c, Level &L);   // dense inverses of the direct segments
 void build_colour_layout(Ctx &c, Level &L);
 // learned level-0 cascade from Lambda~ [B][depth][nb][nb] (FP32, device; additive)
+void run_setup_sketched(Ctx &c, const cs_options &o, int sk, const double *S);
 void run_setup_learned(Ctx &c, const cs_options &o, const float *lam_t);
 // Lambda~ of a level in the layout [B][depth][nb][nb] (FP32, device)
 void prescaled_blocks(Ctx &c, Level &L, float *out);

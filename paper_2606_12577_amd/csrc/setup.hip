@@ -475,91 +475,13 @@ __global__ __launch_bounds__(WG) void k_rowprod_nb(const int32_t *__restrict__ l
     }
 }
 
-// Normal equations of one block row: G = M M^T, H = E M^T, Lambda~ = H G^{-1}
-// (Cholesky; pseudo-inverse fallback).  One workgroup per list row.
-__global__ __launch_bounds__(WG) void k_gram_solve(const int32_t *__restrict__ list, int nb,
-                                                   const int32_t *__restrict__ mptr, const int32_t *__restrict__ mcol,
-                                                   const double *__restrict__ mval, const int32_t *__restrict__ eptr,
-                                                   const int32_t *__restrict__ ecol, const double *__restrict__ eval,
-                                                   double *__restrict__ lamt, int32_t *__restrict__ singular) {
-    __shared__ double G[MAXNB * MAXNB], H[MAXNB * MAXNB], Lc[MAXNB * MAXNB], V[MAXNB * MAXNB];
-    __shared__ int32_t epos[UNION_CAP];   // position in pattern(M_i) of every block of E_i
-    const int li = blockIdx.x;
-    const int i = list[li];
+// Lambda~ G = H for one block (G, H: nb x nb in LDS, row-major), by the whole
+// workgroup; Lc and V are LDS scratch of MAXNB^2 doubles.  Writes Lambda~ to out
+// and, from thread 0, whether G was (numerically) singular to *singular.
+__device__ void normal_solve(const double *G, const double *H, double *Lc, double *V, int nb,
+                             double *__restrict__ out, int32_t *__restrict__ singular) {
     const int t = threadIdx.x;
-    const int lane = t & 63, wave = t >> 6;
     const int nb2 = nb * nb;
-    const int mlo = mptr[li], k = mptr[li + 1] - mlo;
-    const int elo = eptr[i], ek = eptr[i + 1] - elo;
-    const bool epos_cached = ek <= UNION_CAP;
-    if (epos_cached)
-        for (int q = t; q < ek; q += WG) epos[q] = bsearch_i32(mcol, mlo, mlo + k, ecol[elo + q]);
-    __syncthreads();
-    // G = M M^T and H = E M^T as sums of column outer products: wavefront w owns
-    // 4x4 tiles w, w+4, ... of G and H, its lanes split the columns, and the
-    // tile sums are reduced across the lanes at the end.  Every lane reads
-    // 4 + 4 entries of a column for 16 products of each matrix.
-    const int ntd = (nb + 3) / 4;
-    for (int tile = wave; tile < ntd * ntd; tile += WG / 64) {
-        const int tr = (tile / ntd) * 4, tc = (tile % ntd) * 4;
-        double ga[4][4], ha[4][4];
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-            for (int y = 0; y < 4; ++y) ga[x][y] = ha[x][y] = 0.0;
-        for (int j = lane; j < k * nb; j += 64) {
-            const int pb = j / nb, u = j % nb;
-            const double *mp = mval + (int64_t)(mlo + pb) * nb2 + u;
-            double av[4], bv[4];
-#pragma unroll
-            for (int x = 0; x < 4; ++x) {
-                av[x] = tr + x < nb ? mp[(tr + x) * nb] : 0.0;
-                bv[x] = tc + x < nb ? mp[(tc + x) * nb] : 0.0;
-            }
-#pragma unroll
-            for (int x = 0; x < 4; ++x)
-#pragma unroll
-                for (int y = 0; y < 4; ++y) ga[x][y] += av[x] * bv[y];
-        }
-        for (int j = lane; j < ek * nb; j += 64) {
-            const int qb = j / nb, u = j % nb;
-            const int pb = epos_cached ? epos[qb] : bsearch_i32(mcol, mlo, mlo + k, ecol[elo + qb]);
-            if (pb < 0) continue;   // pattern(E_i) is contained in pattern(M_i)
-            const double *ep = eval + (int64_t)(elo + qb) * nb2 + u;
-            const double *mp = mval + (int64_t)pb * nb2 + u;
-            double av[4], bv[4];
-#pragma unroll
-            for (int x = 0; x < 4; ++x) {
-                av[x] = tr + x < nb ? ep[(tr + x) * nb] : 0.0;
-                bv[x] = tc + x < nb ? mp[(tc + x) * nb] : 0.0;
-            }
-#pragma unroll
-            for (int x = 0; x < 4; ++x)
-#pragma unroll
-                for (int y = 0; y < 4; ++y) ha[x][y] += av[x] * bv[y];
-        }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-#pragma unroll
-            for (int x = 0; x < 4; ++x)
-#pragma unroll
-                for (int y = 0; y < 4; ++y) {
-                    ga[x][y] += __shfl_xor(ga[x][y], off, 64);
-                    ha[x][y] += __shfl_xor(ha[x][y], off, 64);
-                }
-        }
-        if (lane == 0) {
-#pragma unroll
-            for (int x = 0; x < 4; ++x)
-#pragma unroll
-                for (int y = 0; y < 4; ++y)
-                    if (tr + x < nb && tc + y < nb) {
-                        G[(tr + x) * nb + tc + y] = ga[x][y];
-                        H[(tr + x) * nb + tc + y] = ha[x][y];
-                    }
-        }
-    }
-    __syncthreads();
     // Lambda~ G = H.  Regular G: Gauss-Jordan inverse of [G | I] (G is SPD:
     // no pivoting; the pivots are the Cholesky pivots squared, with the same
     // cut-off), one thread per entry, two barriers per step.  A pivot below
@@ -599,8 +521,7 @@ __global__ __launch_bounds__(WG) void k_gram_solve(const int32_t *__restrict__ l
         }
         __syncthreads();
     }
-    if (t == 0) singular[li] = bad ? 1 : 0;
-    double *out = lamt + (int64_t)i * nb2;
+    if (t == 0) *singular = bad ? 1 : 0;
     if (!bad) {
         if (t < nb2) {
             const int r = t / nb, c = t % nb;
@@ -721,6 +642,93 @@ __global__ __launch_bounds__(WG) void k_gram_solve(const int32_t *__restrict__ l
     }
 }
 
+// Normal equations of one block row: G = M M^T, H = E M^T, Lambda~ = H G^{-1}
+// (Cholesky; pseudo-inverse fallback).  One workgroup per list row.
+__global__ __launch_bounds__(WG) void k_gram_solve(const int32_t *__restrict__ list, int nb,
+                                                   const int32_t *__restrict__ mptr, const int32_t *__restrict__ mcol,
+                                                   const double *__restrict__ mval, const int32_t *__restrict__ eptr,
+                                                   const int32_t *__restrict__ ecol, const double *__restrict__ eval,
+                                                   double *__restrict__ lamt, int32_t *__restrict__ singular) {
+    __shared__ double G[MAXNB * MAXNB], H[MAXNB * MAXNB], Lc[MAXNB * MAXNB], V[MAXNB * MAXNB];
+    __shared__ int32_t epos[UNION_CAP];   // position in pattern(M_i) of every block of E_i
+    const int li = blockIdx.x;
+    const int i = list[li];
+    const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
+    const int nb2 = nb * nb;
+    const int mlo = mptr[li], k = mptr[li + 1] - mlo;
+    const int elo = eptr[i], ek = eptr[i + 1] - elo;
+    const bool epos_cached = ek <= UNION_CAP;
+    if (epos_cached)
+        for (int q = t; q < ek; q += WG) epos[q] = bsearch_i32(mcol, mlo, mlo + k, ecol[elo + q]);
+    __syncthreads();
+    // G = M M^T and H = E M^T as sums of column outer products: wavefront w owns
+    // 4x4 tiles w, w+4, ... of G and H, its lanes split the columns, and the
+    // tile sums are reduced across the lanes at the end.  Every lane reads
+    // 4 + 4 entries of a column for 16 products of each matrix.
+    const int ntd = (nb + 3) / 4;
+    for (int tile = wave; tile < ntd * ntd; tile += WG / 64) {
+        const int tr = (tile / ntd) * 4, tc = (tile % ntd) * 4;
+        double ga[4][4], ha[4][4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) ga[x][y] = ha[x][y] = 0.0;
+        for (int j = lane; j < k * nb; j += 64) {
+            const int pb = j / nb, u = j % nb;
+            const double *mp = mval + (int64_t)(mlo + pb) * nb2 + u;
+            double av[4], bv[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                av[x] = tr + x < nb ? mp[(tr + x) * nb] : 0.0;
+                bv[x] = tc + x < nb ? mp[(tc + x) * nb] : 0.0;
+            }
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) ga[x][y] += av[x] * bv[y];
+        }
+        for (int j = lane; j < ek * nb; j += 64) {
+            const int qb = j / nb, u = j % nb;
+            const int pb = epos_cached ? epos[qb] : bsearch_i32(mcol, mlo, mlo + k, ecol[elo + qb]);
+            if (pb < 0) continue;   // pattern(E_i) is contained in pattern(M_i)
+            const double *ep = eval + (int64_t)(elo + qb) * nb2 + u;
+            const double *mp = mval + (int64_t)pb * nb2 + u;
+            double av[4], bv[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                av[x] = tr + x < nb ? ep[(tr + x) * nb] : 0.0;
+                bv[x] = tc + x < nb ? mp[(tc + x) * nb] : 0.0;
+            }
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) ha[x][y] += av[x] * bv[y];
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) {
+                    ga[x][y] += __shfl_xor(ga[x][y], off, 64);
+                    ha[x][y] += __shfl_xor(ha[x][y], off, 64);
+                }
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y)
+                    if (tr + x < nb && tc + y < nb) {
+                        G[(tr + x) * nb + tc + y] = ga[x][y];
+                        H[(tr + x) * nb + tc + y] = ha[x][y];
+                    }
+        }
+    }
+    __syncthreads();
+    normal_solve(G, H, Lc, V, nb, lamt + (int64_t)i * nb2, singular + li);
+}
 
 // Point blocks (n = 1): one wavefront per list row, four rows per workgroup.
 // M_i[p] = sum_j a~_ij E_j[col p]; Lambda~_i = H_i / G_i with G_i = sum M_i^2,
@@ -777,6 +785,136 @@ __global__ __launch_bounds__(WG) void k_gram_point(int nl, const int32_t *__rest
         const bool bad = !(g > 0.0);
         singular[w] = bad ? 1 : 0;
         lamt[i] = bad ? 0.0 : h / g;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// sketched construction (Sec. 4): the residual E_{l-1} is replaced by the
+// N x s sketch T = E_{l-1} S (row-major, s <= 64).  One wavefront per list
+// block, lane c = sketch column c; the rows of A are read through the scalar
+// CSR (uniform per wavefront) and T rows are gathered whole (coalesced).
+// ---------------------------------------------------------------------------
+constexpr int SK_MAX = 64;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// m[r] = (A~ T)[i n + r][c], t[r] = T[i n + r][c] with A~ = W A W
+template <int NB>
+__device__ __forceinline__ void sk_rows(int i, int lane, int s, const int32_t *__restrict__ aptr,
+                                        const int32_t *__restrict__ acol, const double *__restrict__ aval,
+                                        const double *__restrict__ w, const double *__restrict__ T,
+                                        double (&m)[NB], double (&t)[NB]) {
+    const bool on = lane < s;
+#pragma unroll
+    for (int r = 0; r < NB; ++r) {
+        const int64_t row = (int64_t)i * NB + r;
+        double acc = 0.0;
+        for (int e = aptr[row]; e < aptr[row + 1]; ++e) {
+            const int k = acol[e];
+            const double tk = on ? T[(int64_t)k * s + lane] : 0.0;
+            acc += aval[e] * w[k] * tk;
+        }
+        m[r] = w[row] * acc;
+        t[r] = on ? T[row * s + lane] : 0.0;
+    }
+}
+
+// Point blocks: Lambda~_i = (T_i, M_i) / (M_i, M_i) (0 when M_i = 0, the
+// minimum-norm solution) and T_i <- T_i - Lambda~_i M_i, written to Tout.
+__global__ __launch_bounds__(WG) void k_sk_point(int nl, const int32_t *__restrict__ list,
+                                                 const int32_t *__restrict__ aptr, const int32_t *__restrict__ acol,
+                                                 const double *__restrict__ aval, const double *__restrict__ w, int s,
+                                                 const double *T, double *Tout, double *__restrict__ lamt,
+                                                 int32_t *__restrict__ singular) {
+    const int wi = blockIdx.x * (WG / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (wi >= nl) return;   // whole wavefront
+    const int i = list[wi];
+    double m[1], t[1];
+    sk_rows<1>(i, lane, s, aptr, acol, aval, w, T, m, t);
+    const double g = wave_sum(m[0] * m[0]), h = wave_sum(t[0] * m[0]);
+    const bool bad = !(g > 0.0);
+    const double lam = bad ? 0.0 : h / g;
+    if (lane == 0) {
+        lamt[i] = lam;
+        singular[wi] = bad ? 1 : 0;
+    }
+    if (lane < s) Tout[(int64_t)i * s + lane] = t[0] - lam * m[0];
+}
+
+// Block rows: M_i to Mb[wi][NB][s], G_i = M_i M_i^T and H_i = T_i M_i^T to
+// gh[wi][2][NB][NB]
+template <int NB>
+__global__ __launch_bounds__(WG) void k_sk_gram(int nl, const int32_t *__restrict__ list,
+                                                const int32_t *__restrict__ aptr, const int32_t *__restrict__ acol,
+                                                const double *__restrict__ aval, const double *__restrict__ w, int s,
+                                                const double *__restrict__ T, double *__restrict__ Mb,
+                                                double *__restrict__ gh) {
+    const int wi = blockIdx.x * (WG / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (wi >= nl) return;
+    const int i = list[wi];
+    double m[NB], t[NB];
+    sk_rows<NB>(i, lane, s, aptr, acol, aval, w, T, m, t);
+    if (lane < s) {
+#pragma unroll
+        for (int r = 0; r < NB; ++r) Mb[((int64_t)wi * NB + r) * s + lane] = m[r];
+    }
+    double *g = gh + (int64_t)wi * 2 * NB * NB, *h = g + NB * NB;
+#pragma unroll
+    for (int p = 0; p < NB; ++p) {
+#pragma unroll
+        for (int q = 0; q <= p; ++q) {
+            const double v = wave_sum(m[p] * m[q]);
+            if (lane == 0) {
+                g[p * NB + q] = v;
+                g[q * NB + p] = v;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const double v = wave_sum(t[p] * m[q]);
+            if (lane == 0) h[p * NB + q] = v;
+        }
+    }
+}
+
+// Lambda~_i G_i = H_i per list block (the exact fit's solve), one workgroup each
+__global__ __launch_bounds__(WG) void k_sk_solve(const int32_t *__restrict__ list, int nb,
+                                                 const double *__restrict__ gh, double *__restrict__ lamt,
+                                                 int32_t *__restrict__ singular) {
+    __shared__ double G[MAXNB * MAXNB], H[MAXNB * MAXNB], Lc[MAXNB * MAXNB], V[MAXNB * MAXNB];
+    const int wi = blockIdx.x, nb2 = nb * nb;
+    const double *src = gh + (int64_t)wi * 2 * nb2;
+    for (int e = threadIdx.x; e < nb2; e += WG) {
+        G[e] = src[e];
+        H[e] = src[nb2 + e];
+    }
+    __syncthreads();
+    normal_solve(G, H, Lc, V, nb, lamt + (int64_t)list[wi] * nb2, singular + wi);
+}
+
+// T_i <- T_i - Lambda~_i M_i for the list blocks (in place: M was formed from
+// the old T before this launch)
+template <int NB>
+__global__ __launch_bounds__(WG) void k_sk_update(int nl, const int32_t *__restrict__ list, int s,
+                                                  const double *__restrict__ lamt, const double *__restrict__ Mb,
+                                                  double *__restrict__ T) {
+    const int wi = blockIdx.x * (WG / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (wi >= nl || lane >= s) return;
+    const int i = list[wi];
+    const double *lam = lamt + (int64_t)i * NB * NB;
+    double m[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) m[u] = Mb[((int64_t)wi * NB + u) * s + lane];
+#pragma unroll
+    for (int r = 0; r < NB; ++r) {
+        double v = T[((int64_t)i * NB + r) * s + lane];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) v -= lam[r * NB + u] * m[u];
+        T[((int64_t)i * NB + r) * s + lane] = v;
     }
 }
 
@@ -1384,30 +1522,25 @@ bool rowprod_nb(hipStream_t s, int nb, int nl, const int32_t *list, const BPatte
     }
 }
 
-void fit_level(Ctx &c, Level &L, const cs_options &o) {
+// Prescaling W = diag(a_kk^{-1/2}), the block pattern of A (when asked for,
+// and always for colouring), the colours (multiplicative) and the fit lists:
+// the active blocks of one colour at a time (multiplicative), or all active
+// blocks at once (additive).
+struct FitLists {
+    std::vector<std::pair<const int32_t *, int>> lists;
+    DBuf<int32_t> all_blocks;
+};
+
+void prepare_level(Ctx &c, Level &L, const cs_options &o, bool need_ap, BPattern &ap, FitLists &fl) {
     hipStream_t s = c.stream;
-    const int B = (int)L.B, nb = (int)L.nb, nb2 = nb * nb;
-    const int B_act = (int)(L.n_active / nb);   // blocks that are smoothed (the rest are solved directly)
-    const int depth = o.depth;
-    if (nb > MAXNB) fail(CS_EINVAL, "block size above 16 is not supported");
-    // prescaling
+    const int B = (int)L.B;
+    const int B_act = (int)(L.n_active / L.nb);   // blocks that are smoothed (the rest are solved directly)
+    if (L.nb > MAXNB) fail(CS_EINVAL, "block size above 16 is not supported");
     L.w.alloc(L.n);
     hipLaunchKernelGGL(k_prescale_w, dim3(grid_for(L.n)), dim3(WG), 0, s, L.a_ptr.get(), L.a_col.get(),
                        L.a_val.get(), L.n, L.w.get());
     CS_LAUNCH_CHECK();
-    // block pattern of A and the prescaled dense blocks
-    BPattern ap;
-    block_pattern_of_A(c, L, ap);
-    DBuf<double> abval(ap.nnzb * nb2);
-    CS_HIP(hipMemsetAsync(abval.get(), 0, abval.bytes(), s));
-    hipLaunchKernelGGL(k_scatter_blocks, dim3(grid_for(L.n)), dim3(WG), 0, s, L.a_ptr.get(), L.a_col.get(),
-                       L.a_val.get(), L.w.get(), L.n, nb, ap.ptr.get(), ap.col.get(), abval.get());
-    CS_LAUNCH_CHECK();
-    // colour lists
-    // fit lists: the active blocks of one colour at a time (multiplicative), or all
-    // active blocks at once (additive)
-    std::vector<std::pair<const int32_t *, int>> lists;
-    DBuf<int32_t> all_blocks;
+    if (need_ap || o.mode == CS_MULTIPLICATIVE) block_pattern_of_A(c, L, ap);
     if (o.mode == CS_MULTIPLICATIVE) {
         if (!L.colour_given) greedy_colouring(c, L, ap);
         L.colour.upload(L.h_colour.data(), B, s);
@@ -1415,24 +1548,37 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
         hipLaunchKernelGGL(k_colour_check, dim3(grid_for(B)), dim3(WG), 0, s, B, ap.ptr.get(), ap.col.get(),
                            L.colour.get(), bad.get());
         CS_LAUNCH_CHECK();
-        std::vector<int32_t> hb(B);
-        bad.download(hb.data(), B, s);
-        CS_HIP(hipStreamSynchronize(s));
-        for (int32_t v : hb)
-            if (v) fail(CS_ECOLOR, "colouring is not proper: two coupled blocks share a colour");
+        if (reduce_i32(c, bad.get(), B, false))
+            fail(CS_ECOLOR, "colouring is not proper: two coupled blocks share a colour");
         if (L.layout_colour != L.h_colour) {   // colours and A unchanged: keep the layout
             build_colour_layout(c, L);
             L.layout_colour = L.h_colour;
         }
         for (int k = 0; k < L.chi; ++k)
-            lists.emplace_back(L.cblk.get() + L.cblk_ptr[k], (int)(L.cblk_ptr[k + 1] - L.cblk_ptr[k]));
+            fl.lists.emplace_back(L.cblk.get() + L.cblk_ptr[k], (int)(L.cblk_ptr[k + 1] - L.cblk_ptr[k]));
     } else {
         L.chi = 1;
-        all_blocks.alloc(std::max(B_act, 1));
-        hipLaunchKernelGGL(k_iota, dim3(grid_for(std::max(B_act, 1))), dim3(WG), 0, s, all_blocks.get(), B_act);
+        fl.all_blocks.alloc(std::max(B_act, 1));
+        hipLaunchKernelGGL(k_iota, dim3(grid_for(std::max(B_act, 1))), dim3(WG), 0, s, fl.all_blocks.get(), B_act);
         CS_LAUNCH_CHECK();
-        lists.emplace_back(all_blocks.get(), B_act);
+        fl.lists.emplace_back(fl.all_blocks.get(), B_act);
     }
+}
+
+void fit_level(Ctx &c, Level &L, const cs_options &o) {
+    hipStream_t s = c.stream;
+    const int B = (int)L.B, nb = (int)L.nb, nb2 = nb * nb;
+    const int depth = o.depth;
+    BPattern ap;
+    FitLists fl;
+    prepare_level(c, L, o, true, ap, fl);
+    const auto &lists = fl.lists;
+    // the prescaled dense blocks of A
+    DBuf<double> abval(ap.nnzb * nb2);
+    CS_HIP(hipMemsetAsync(abval.get(), 0, abval.bytes(), s));
+    hipLaunchKernelGGL(k_scatter_blocks, dim3(grid_for(L.n)), dim3(WG), 0, s, L.a_ptr.get(), L.a_col.get(),
+                       L.a_val.get(), L.w.get(), L.n, nb, ap.ptr.get(), ap.col.get(), abval.get());
+    CS_LAUNCH_CHECK();
     // E_0 = I
     EMat E;
     E.pat.rows = B;
@@ -1559,6 +1705,76 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
     CS_HIP(hipStreamSynchronize(s));
 }
 
+// Sketched fit of one level (Sec. 4): T_0 = S (N x s, device, row-major),
+// then for every cascade level and fit list: M = A~ T on the list blocks, the
+// normal equations of min ||T_i - Lambda~_i M_i||_F, T_i <- T_i - Lambda~_i M_i.
+void fit_level_sketched(Ctx &c, Level &L, const cs_options &o, const double *S, int sk) {
+    hipStream_t s = c.stream;
+    const int B = (int)L.B, nb = (int)L.nb, nb2 = nb * nb;
+    const int depth = o.depth;
+    BPattern ap;
+    FitLists fl;
+    prepare_level(c, L, o, false, ap, fl);
+    L.patterns.clear();   // no residual patterns: the sketch is dense
+    const size_t nT = (size_t)L.n * sk;
+    // point blocks update T inside the fitting kernel: additive steps write a
+    // second buffer (every block reads its neighbours' old rows), colour steps
+    // update in place (a proper colouring couples no two blocks of one colour)
+    const bool pingpong = nb == 1 && o.mode == CS_ADDITIVE;
+    DBuf<double> T0(std::max<size_t>(nT, 1)), T1(pingpong ? std::max<size_t>(nT, 1) : 1);
+    CS_HIP(hipMemcpyAsync(T0.get(), S, nT * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (pingpong) CS_HIP(hipMemcpyAsync(T1.get(), S, nT * sizeof(double), hipMemcpyDeviceToDevice, s));
+    double *Tin = T0.get(), *Tout = pingpong ? T1.get() : T0.get();
+    DBuf<double> lamt((size_t)depth * B * nb2);
+    CS_HIP(hipMemsetAsync(lamt.get(), 0, lamt.bytes(), s));   // rows of direct segments get no smoother
+    int maxl = 1;
+    for (const auto &pr : fl.lists) maxl = std::max(maxl, pr.second);
+    DBuf<int32_t> sing(maxl);
+    DBuf<double> Mb(nb > 1 ? (size_t)maxl * nb * sk : 1), gh(nb > 1 ? (size_t)maxl * 2 * nb2 : 1);
+    L.singular = 0;
+    for (int ell = 1; ell <= depth; ++ell) {
+        double *lam_l = lamt.get() + (size_t)(ell - 1) * B * nb2;
+        for (const auto &pr : fl.lists) {
+            const int32_t *list = pr.first;
+            const int nl = pr.second;
+            if (nl == 0) continue;
+            const dim3 gw((unsigned)ceil_div(nl, WG / 64));
+            if (nb == 1) {
+                hipLaunchKernelGGL(k_sk_point, gw, dim3(WG), 0, s, nl, list, L.a_ptr.get(), L.a_col.get(),
+                                   L.a_val.get(), L.w.get(), sk, Tin, Tout, lam_l, sing.get());
+                CS_LAUNCH_CHECK();
+                if (pingpong) std::swap(Tin, Tout);
+            } else {
+                auto go = [&](auto nbc) {
+                    constexpr int NB = decltype(nbc)::value;
+                    hipLaunchKernelGGL(k_sk_gram<NB>, gw, dim3(WG), 0, s, nl, list, L.a_ptr.get(), L.a_col.get(),
+                                       L.a_val.get(), L.w.get(), sk, (const double *)Tin, Mb.get(), gh.get());
+                    hipLaunchKernelGGL(k_sk_solve, dim3((unsigned)nl), dim3(WG), 0, s, list, nb,
+                                       (const double *)gh.get(), lam_l, sing.get());
+                    hipLaunchKernelGGL(k_sk_update<NB>, gw, dim3(WG), 0, s, nl, list, sk, (const double *)lam_l,
+                                       (const double *)Mb.get(), Tin);
+                };
+                switch (nb) {
+                    case 2: go(std::integral_constant<int, 2>{}); break;
+                    case 4: go(std::integral_constant<int, 4>{}); break;
+                    case 8: go(std::integral_constant<int, 8>{}); break;
+                    case 16: go(std::integral_constant<int, 16>{}); break;
+                    default: fail(CS_EINVAL, "the sketched setup supports block sizes 1, 2, 4, 8 and 16");
+                }
+                CS_LAUNCH_CHECK();
+            }
+            L.singular += reduce_i32(c, sing.get(), nl, true);
+        }
+    }
+    L.depth = depth;
+    L.lam64.alloc((size_t)depth * B * nb2);
+    for (int ell = 0; ell < depth; ++ell)
+        hipLaunchKernelGGL(k_unscale, dim3(grid_for((int64_t)B * nb2)), dim3(WG), 0, s, (int64_t)B, nb, L.w.get(),
+                           lamt.get() + (size_t)ell * B * nb2, L.lam64.get() + (size_t)ell * B * nb2);
+    CS_LAUNCH_CHECK();
+    CS_HIP(hipStreamSynchronize(s));
+}
+
 }  // namespace
 
 void factor_direct(Ctx &c, Level &L) {
@@ -1610,6 +1826,24 @@ void run_setup(Ctx &c, const cs_options &o) {
     c.singular = 0;
     for (size_t l = 0; l + 1 < c.lv.size(); ++l) {
         fit_level(c, c.lv[l], o);
+        c.singular += c.lv[l].singular;
+    }
+    for (Level &L : c.lv) factor_direct(c, L);
+    build_working_copies(c);
+    CS_HIP(hipEventRecord(c.ev1, c.stream));
+    CS_HIP(hipEventSynchronize(c.ev1));
+    float ms = 0;
+    CS_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
+    c.setup_ms = ms;
+}
+
+void run_setup_sketched(Ctx &c, const cs_options &o, int sk, const double *S) {
+    CS_HIP(hipEventRecord(c.ev0, c.stream));
+    c.singular = 0;
+    size_t off = 0;
+    for (size_t l = 0; l + 1 < c.lv.size(); ++l) {
+        fit_level_sketched(c, c.lv[l], o, S + off, sk);
+        off += (size_t)c.lv[l].n * sk;
         c.singular += c.lv[l].singular;
     }
     for (Level &L : c.lv) factor_direct(c, L);
