@@ -79,6 +79,15 @@ def bench_batch(precision: str):
                            converged_systems=int((rels <= 1e-10).sum()), dof_per_s=dof / (i["solve_ms"] * 1e-3),
                            per_system_iterations=[int(np.min(its)), int(np.median(its)), int(np.max(its))])
         out["setup_ms"] = round(i["setup_ms"], 2)
+    # sketched construction (64 Rademacher modes per level) instead of the exact fit
+    for _ in range(2):
+        s.setup_sketched(width=64, seed=0, depth=3, precision=precision)
+    infos = [s.solve(b, rtol=1e-10, maxit=300, method="cg", raise_on_noconv=False)[1] for _ in range(2)]
+    its, rels = s.system_stats()
+    i = infos[-1]
+    out["sketched_s64_cg"] = dict(setup_ms=round(i["setup_ms"], 2), solve_ms=round(i["solve_ms"], 2),
+                                  iterations=i["iterations"], converged_systems=int((rels <= 1e-10).sum()),
+                                  setup_plus_solve_dof_per_s=dof / ((i["setup_ms"] + i["solve_ms"]) * 1e-3))
     s.close()
     return out
 
@@ -169,6 +178,8 @@ def main():
     ap.add_argument("--solver", default="cg", choices=["ir", "cg", "gmres", "fgmres"],
                     help="outer solver of the timed step: FP64 refinement, flexible CG, left-preconditioned "
                          "GMRES or flexible GMRES around the V-cycle")
+    ap.add_argument("--sketch-width", type=int, default=32,
+                    help="also measure the sketched setup with this many modes (0: skip)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-system measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-setup measurement")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -273,6 +284,18 @@ def main():
                                                                         s.solve(b, rtol=args.rtol, maxit=args.maxit,
                                                                                 method=other)[1]["rho"]), 4)
         s.set_precision(args.precision)
+    # sketched construction (32 Rademacher modes per level) instead of the exact fit, same solve
+    if args.sketch_width > 0:
+        sks = []
+        for _ in range(2):
+            s.setup_sketched(width=args.sketch_width, seed=0, depth=args.depth, precision=args.precision)
+            sks.append(s.solve(b, rtol=args.rtol, maxit=args.maxit, method=args.solver, raise_on_noconv=False)[1])
+        sk = sks[-1]
+        extra[f"sketched_s{args.sketch_width}_{args.solver}"] = dict(
+            setup_ms=round(sk["setup_ms"], 2), solve_ms=round(sk["solve_ms"], 3), iterations=sk["iterations"],
+            rho=round(sk["rho"], 4), rel_res=sk["rel_res"],
+            setup_plus_solve_dof_per_s=dof / ((sk["setup_ms"] + sk["solve_ms"]) * 1e-3),
+            setup_speedup_vs_exact=round(setup_ms / sk["setup_ms"], 2))
     if args.copy_mib:
         nel = args.copy_mib * 1024 * 1024 // 4
         src = torch.ones(nel, device=dev, dtype=torch.float32)
