@@ -208,7 +208,9 @@ cs_status cs_solve_gmres(cs_ctx ctx, const double *b, double *x, int32_t nrhs, d
  *   S: device FP64, the sketches of all smoothed levels one after the other
  *      (level l: n_l x s, row-major, at offset s * (n_0 + ... + n_{l-1})); the
  *      caller draws them (e.g. Rademacher +-1); only their span matters.
- *   s: sketch width, 1..64.  opt: as cs_setup; trunc_alpha must be 0.
+ *   s: sketch width, 1..64, and above the block size when depth > 1 (with
+ *      s <= n the first level fits every column exactly, T_1 = 0).
+ *   opt: as cs_setup; trunc_alpha must be 0.
  * Residual patterns (cs_get_pattern) are not available after this setup. */
 cs_status cs_setup_sketched(cs_ctx ctx, const cs_options *opt, int32_t s, const double *S);
 

@@ -321,6 +321,11 @@ cs_status cs_setup_sketched(cs_ctx ctx, const cs_options *opt, int32_t s, const 
         need(opt->order == CS_FF || opt->order == CS_RF, "order must be FF or RF");
         need(opt->n_pre >= 1 && opt->n_post >= 0, "need n_pre >= 1 and n_post >= 0");
         need(opt->trunc_alpha == 0, "truncation applies to the exact fit only");
+        int64_t nbmax = 1;
+        for (const Level &L : c.lv) nbmax = std::max<int64_t>(nbmax, L.nb);
+        // with s <= n the first level fits every sketch column exactly: T_1 = 0
+        // and every later level would fit rounding noise
+        need(opt->depth == 1 || s > nbmax, "a deeper sketched cascade needs more sketch columns than the block size");
         need(opt->precision == CS_FP64 || opt->precision == CS_FP32 || opt->precision == CS_BF16,
              "precision must be FP64, FP32 or BF16");
         c.have_setup = false;

@@ -165,3 +165,23 @@ def test_batched_gmres_runs_every_system_as_if_alone(gpu_lib):
             if abs(np.log(h[k] / rtol)) > 1e-3 and (k == 0 or abs(np.log(h[k - 1] / rtol)) > 1e-3):
                 assert its[q] == k, (q, flexible, its[q], k)
         assert info["iterations"] == its.max()
+
+
+@pytest.mark.parametrize("nrhs", [1, 2, 8])
+def test_gmres_rhs_counts_and_ragged_batch(gpu_lib, nrhs):
+    """Every RHS count, and a batch with odd sizes whose systems end on
+    different levels (ragged direct segments)."""
+    sizes = [20, 12, 36, 10, 6, 20]
+    probs = fd.lognormal_batch(len(sizes), nrhs=nrhs, sizes=sizes, config_id=18)
+    bt = concatenate(probs)
+    sms = [O.setup_hierarchy(p.levels, 2) for p in probs]
+    s = gpu_lib.Solver(bt.levels)
+    s.setup(depth=2, order="FF")
+    s.set_systems(bt.sys_ptr)
+    for flexible in (False, True):
+        x, info = s.solve(bt.rhs, rtol=1e-10, maxit=200, method="fgmres" if flexible else "gmres", restart=7)
+        xs = bt.split(x.cpu().numpy())
+        for si, p in enumerate(probs):
+            pre = lambda v: O.vcycle(p.levels, sms[si], v, "FF")
+            xo, _ = O.gmres(p.levels[0].A, pre, p.rhs, restart=7, rtol=1e-10, maxit=200, flexible=flexible)
+            assert rel(xs[si], xo) <= 1e-7, (si, flexible, rel(xs[si], xo))
