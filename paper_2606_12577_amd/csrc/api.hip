@@ -637,6 +637,29 @@ int trace_begin(Ctx &c, int cls, double bytes) {
     return slot;
 }
 
+int trace_begin_launch(Ctx &c, int cls, double bytes, hipEvent_t *start, hipEvent_t *stop) {
+    *start = *stop = nullptr;
+    Trace &t = c.tr;
+    if (t.capturing) return trace_begin(c, cls, bytes);   // event nodes around the launch
+    if (!t.on || !((t.mask >> cls) & 1)) return -1;
+    if (t.seen[cls]++ % t.period != 0) return -1;
+    if (2 * t.used + 2 > t.ev.size()) {
+        hipEvent_t a, b;
+        CS_HIP(hipEventCreate(&a));
+        CS_HIP(hipEventCreate(&b));
+        t.ev.push_back(a);
+        t.ev.push_back(b);
+        t.cls.push_back(0);
+        t.cls_bytes.push_back(0.0);
+    }
+    const int slot = (int)t.used++;
+    t.cls[slot] = cls;
+    t.cls_bytes[slot] = bytes;
+    *start = t.ev[2 * slot];
+    *stop = t.ev[2 * slot + 1];
+    return slot;
+}
+
 void trace_end(Ctx &c, int slot) {
     if (slot == -1) return;
     if (slot <= -2) {

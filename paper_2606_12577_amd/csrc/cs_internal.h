@@ -243,6 +243,11 @@ void trace_graph_pool(Ctx &c, size_t slots);   // pre-create events for `slots` 
 
 // tracing helpers (api.hip)
 int trace_begin(Ctx &c, int cls, double bytes);   // returns slot or -1
+// For one launch that records its own start and end (hipExtLaunchKernelGGL with
+// *start / *stop, null when the launch is not sampled): the kernel's duration
+// without event-packet overhead.  Under graph capture it falls back to event
+// nodes, and the caller then ends the slot with trace_end (slot <= -2).
+int trace_begin_launch(Ctx &c, int cls, double bytes, hipEvent_t *start, hipEvent_t *stop);
 void trace_end(Ctx &c, int slot);
 void trace_flush(Ctx &c);
 void trace_release(Ctx &c);

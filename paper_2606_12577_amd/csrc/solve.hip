@@ -18,6 +18,8 @@
 #include <cmath>
 #include <type_traits>
 
+#include <hip/hip_ext.h>
+
 #include "cs_internal.h"
 
 namespace cs {
@@ -1335,19 +1337,20 @@ void launch_sweep(Ctx &c, const Level &L, const Sell &S, bool rowmap, bool zero,
     const double bytes = (zero ? 0.0 : nnz * (es + 4.0)) + (double)nrows * L.nb * es +
                          (double)nrows * R * es * 2.0 + (zero ? 0.0 : (rowmap ? L.n : nrows) * R * es) +
                          (prol ? (double)L.nc * R * es : 0.0);
-    const int slot = trace_begin(c, cls, bytes);
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;   // set for a sampled launch: it times itself
+    const int slot = trace_begin_launch(c, cls, bytes, &ev0, &ev1);
     dispatch_nb(L.nb, [&](auto nbc) {
         constexpr int NB = decltype(nbc)::value;
 #define CS_SWEEP(Z, M, P, ROWS)                                                                                     \
     do {                                                                                                            \
         if (small)                                                                                                  \
-            hipLaunchKernelGGL((k_sweep<T, NB, R, Z, M, P, 64>), dim3(G), dim3(64), 0, c.stream, nrows,            \
-                               nslices, ROWS, S.slice_ptr.get(), S.slice_len.get(), S.col.get(), sell_val<T>(S), \
-                               lam, b, xin, xout, xc, agg_k);                                                       \
+            hipExtLaunchKernelGGL((k_sweep<T, NB, R, Z, M, P, 64>), dim3(G), dim3(64), 0, c.stream, ev0, ev1, 0,   \
+                                  nrows, nslices, ROWS, S.slice_ptr.get(), S.slice_len.get(), S.col.get(),         \
+                                  sell_val<T>(S), lam, b, xin, xout, xc, agg_k);                                   \
         else                                                                                                        \
-            hipLaunchKernelGGL((k_sweep<T, NB, R, Z, M, P, WG>), dim3(G), dim3(WG), 0, c.stream, nrows,            \
-                               nslices, ROWS, S.slice_ptr.get(), S.slice_len.get(), S.col.get(), sell_val<T>(S), \
-                               lam, b, xin, xout, xc, agg_k);                                                       \
+            hipExtLaunchKernelGGL((k_sweep<T, NB, R, Z, M, P, WG>), dim3(G), dim3(WG), 0, c.stream, ev0, ev1, 0,   \
+                                  nrows, nslices, ROWS, S.slice_ptr.get(), S.slice_len.get(), S.col.get(),         \
+                                  sell_val<T>(S), lam, b, xin, xout, xc, agg_k);                                   \
     } while (0)
         if (rowmap) {
             if (zero) CS_SWEEP(true, true, false, S.rows.get());
@@ -1362,7 +1365,7 @@ void launch_sweep(Ctx &c, const Level &L, const Sell &S, bool rowmap, bool zero,
 #undef CS_SWEEP
     });
     CS_LAUNCH_CHECK();
-    trace_end(c, slot);
+    if (slot <= -2) trace_end(c, slot);
 }
 
 // One application of the cascade of level L: x <- S(x, b).  Returns the buffer
