@@ -98,12 +98,44 @@ def block_rows(blocks: Sequence[int], n: int) -> np.ndarray:
 # Setup (Sec. 2.1-2.3, Alg. 2, supplementary multicoloured algorithm)
 # ---------------------------------------------------------------------------
 
-def prescale(A: sp.spmatrix):
-    """Elliptic prescaling (Sec. 2.3): W = diag(A_kk^{-1/2}); returns (w, W A W)."""
-    d = A.diagonal()
-    if np.any(d <= 0):
-        raise ValueError("elliptic prescaling needs a positive diagonal")
-    w = 1.0 / np.sqrt(d)
+def prescale(A: sp.spmatrix, kind: Optional[np.ndarray] = None, norm: str = "max"):
+    """Symmetric diagonal prescaling W, returns (w, W A W) (Sec. 2.3).
+
+    kind None (elliptic, Sec. 2.3.1): W = diag(A_kk^{-1/2}).
+    kind given (Stokes, Sec. 2.3.2): per unknown 0 velocity, 1 pressure (2: an
+    inert unknown, scaled as a velocity).  With the viscous block V = A[vel, vel]
+    and the constraint block D = A[pres, vel]:
+      velocity: w_i chosen so that (W V W)_ii = ||V_i,:||_1 / V_ii, i.e.
+                w_i = sqrt(||V_i,:||_1) / V_ii;
+      pressure: every row of diag(w_p) D diag(w_u) has unit max-norm
+                (norm "max") or unit 1-norm (norm "l1", the MAC variant)."""
+    A = sp.csr_matrix(A)
+    if kind is None:
+        d = A.diagonal()
+        if np.any(d <= 0):
+            raise ValueError("elliptic prescaling needs a positive diagonal")
+        w = 1.0 / np.sqrt(d)
+    else:
+        kind = np.asarray(kind)
+        vel = kind != 1
+        pre = kind == 1
+        V = A[vel][:, vel]
+        dv = V.diagonal()
+        if np.any(dv <= 0):
+            raise ValueError("Stokes prescaling needs a positive viscous diagonal")
+        l1 = np.asarray(abs(V).sum(axis=1)).ravel()
+        w = np.empty(A.shape[0])
+        w[vel] = np.sqrt(l1) / dv
+        D = sp.csr_matrix(A[pre][:, vel] @ sp.diags(w[vel]))
+        if norm == "max":
+            m = np.asarray(abs(D).max(axis=1).todense()).ravel()
+        elif norm == "l1":
+            m = np.asarray(abs(D).sum(axis=1)).ravel()
+        else:
+            raise ValueError(norm)
+        if np.any(m <= 0):
+            raise ValueError("a constraint row couples to no velocity")
+        w[pre] = 1.0 / m
     W = sp.diags(w)
     return w, (W @ A @ W).tocsr()
 
@@ -164,7 +196,8 @@ def unscale(lam_t: np.ndarray, w: np.ndarray) -> np.ndarray:
     return wb[:, :, None] * lam_t * wb[:, None, :]
 
 
-def fit_additive(A: sp.spmatrix, n: int, depth: int, alpha: Optional[int] = None) -> Dict:
+def fit_additive(A: sp.spmatrix, n: int, depth: int, alpha: Optional[int] = None,
+                 kind: Optional[np.ndarray] = None, norm: str = "max") -> Dict:
     """Depth-nu additive cascade (Sec. 2.1, Alg. 2).
 
     Lambda_l = argmin_{Lambda block-diagonal} ||(I - Lambda A~) E_{l-1}||_F,
@@ -174,7 +207,7 @@ def fit_additive(A: sp.spmatrix, n: int, depth: int, alpha: Optional[int] = None
     A = sp.csr_matrix(A)
     N = A.shape[0]
     B = N // n
-    w, At = prescale(A)
+    w, At = prescale(A, kind, norm)
     Apat = block_pattern(At, n)
     E = sp.identity(N, format="csr")
     Epat = sp.identity(B, format="csr", dtype=bool)
@@ -198,7 +231,7 @@ def fit_additive(A: sp.spmatrix, n: int, depth: int, alpha: Optional[int] = None
 
 
 def fit_multiplicative(A: sp.spmatrix, n: int, depth: int, colours: np.ndarray,
-                       alpha: Optional[int] = None) -> Dict:
+                       alpha: Optional[int] = None, kind: Optional[np.ndarray] = None, norm: str = "max") -> Dict:
     """Depth-nu multicoloured cascade (Sec. 2.2).
 
     For l = 1..nu and colours k in ascending order,
@@ -211,7 +244,7 @@ def fit_multiplicative(A: sp.spmatrix, n: int, depth: int, colours: np.ndarray,
     B = N // n
     colours = np.asarray(colours, dtype=np.int64)
     chi = int(colours.max()) + 1
-    w, At = prescale(A)
+    w, At = prescale(A, kind, norm)
     Apat = block_pattern(At, n)
     E = sp.identity(N, format="csr")
     Epat = sp.identity(B, format="csr", dtype=bool)
@@ -251,7 +284,8 @@ def fit_multiplicative(A: sp.spmatrix, n: int, depth: int, colours: np.ndarray,
 
 
 def fit_sketched(A: sp.spmatrix, n: int, depth: int, S: np.ndarray, mode: str = "additive",
-                 colours: Optional[np.ndarray] = None) -> Dict:
+                 colours: Optional[np.ndarray] = None, kind: Optional[np.ndarray] = None,
+                 norm: str = "max") -> Dict:
     """Sketched cascade construction (Sec. 4, Concluding Remarks, proposed there as
     future work).
 
@@ -267,7 +301,7 @@ def fit_sketched(A: sp.spmatrix, n: int, depth: int, S: np.ndarray, mode: str = 
     A = sp.csr_matrix(A)
     N = A.shape[0]
     B = N // n
-    w, At = prescale(A)
+    w, At = prescale(A, kind, norm)
     T = np.array(S, dtype=np.float64, copy=True)
     s = T.shape[1]
     if mode == "additive":
@@ -297,11 +331,11 @@ def fit_sketched(A: sp.spmatrix, n: int, depth: int, S: np.ndarray, mode: str = 
                 colours=None if mode == "additive" else colours.astype(np.int32), gram_cond=cond)
 
 
-def fit(A, n, depth, mode="additive", colours=None, alpha=None) -> Dict:
+def fit(A, n, depth, mode="additive", colours=None, alpha=None, kind=None, norm="max") -> Dict:
     if mode == "additive":
-        return fit_additive(A, n, depth, alpha)
+        return fit_additive(A, n, depth, alpha, kind, norm)
     if mode == "multiplicative":
-        return fit_multiplicative(A, n, depth, colours, alpha)
+        return fit_multiplicative(A, n, depth, colours, alpha, kind, norm)
     raise ValueError(mode)
 
 
@@ -367,14 +401,16 @@ def smooth(A: sp.spmatrix, sm: Dict, x: np.ndarray, b: np.ndarray, reverse: bool
     return x
 
 
-def setup_hierarchy(levels, depth: int, mode: str = "additive", alpha=None) -> List[Dict]:
-    """Fit a cascade on every level except the coarsest (Sec. 2.5)."""
+def setup_hierarchy(levels, depth: int, mode: str = "additive", alpha=None, norm: str = "max") -> List[Dict]:
+    """Fit a cascade on every level except the coarsest (Sec. 2.5); a level
+    with a `kind` array (velocity / pressure per unknown) is prescaled as a
+    Stokes problem (Sec. 2.3.2) with the given constraint-row norm."""
     out = []
     for lv in levels[:-1]:
         colours = lv.colour
         if mode == "multiplicative" and colours is None:
             colours = greedy_colour(block_pattern(lv.A, lv.block_size))
-        out.append(fit(lv.A, lv.block_size, depth, mode, colours, alpha))
+        out.append(fit(lv.A, lv.block_size, depth, mode, colours, alpha, getattr(lv, "kind", None), norm))
     return out
 
 

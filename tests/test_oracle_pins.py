@@ -754,3 +754,72 @@ def test_wider_sketch_approaches_the_exact_fit():
         sk = O.fit_sketched(A, n, 2, S)
         errs.append(np.linalg.norm(sk["lam"][0] - exact["lam"][0]) / np.linalg.norm(exact["lam"][0]))
     assert errs[0] > errs[1] > errs[2], errs
+
+
+# ---------------------------------------------------------------------------
+# Stokes prescaling (Sec. 2.3.2) on the MAC grid: closed-form weights, the
+# invariance that motivates it, inert slots, and convergence of the cascade.
+# ---------------------------------------------------------------------------
+
+from synth import stokes as _stokes
+
+
+def test_stokes_prescaling_closed_form_on_the_mac_grid():
+    n = 8
+    h = 1.0 / n
+    A = _stokes.operator(n)
+    kind = _stokes.kinds(n)
+    for norm, wp_int in (("l1", 1.0 / (2.0 * np.sqrt(2.0))), ("max", np.sqrt(2.0))):
+        w, _ = O.prescale(A, kind, norm)
+        # u at the face between cells (3, 4) and (4, 4): away from every wall
+        u_int = 4 * (3 + n * 4) + 0
+        np.testing.assert_allclose(w[u_int], h / np.sqrt(2.0), rtol=1e-14)
+        # u next to the bottom wall (ghost mirror: diagonal 5/h^2, |row| 8/h^2)
+        u_wall = 4 * (3 + n * 0) + 0
+        np.testing.assert_allclose(w[u_wall], 2.0 * np.sqrt(2.0) * h / 5.0, rtol=1e-14)
+        # pressure of a cell whose four faces are interior faces
+        p_int = 4 * (4 + n * 4) + 2
+        np.testing.assert_allclose(w[p_int], wp_int, rtol=1e-14)
+        assert np.all(w[kind == 2] == 1.0)
+
+
+def test_stokes_prescaling_is_invariant_to_viscosity_and_constraint_scale():
+    A = _stokes.operator(8)
+    kind = _stokes.kinds(8)
+    vel = (kind != 1).astype(float)
+    pre = (kind == 1).astype(float)
+    Dv, Dp = sp.diags(vel), sp.diags(pre)
+    V = Dv @ A @ Dv
+    G = Dv @ A @ Dp
+    Dm = Dp @ A @ Dv
+    _, ref = O.prescale(A, kind, "l1")
+    for c, a in ((1e-3, 1.0), (37.0, 1.0), (1.0, 1e2), (5.0, 1e-2)):
+        # inert slots keep their unit diagonal
+        Vc = c * V + (1.0 - c) * sp.diags((kind == 2).astype(float))
+        A2 = (Vc + a * G + a * Dm).tocsr()
+        _, got = O.prescale(A2, kind, "l1")
+        np.testing.assert_allclose(got.toarray(), ref.toarray(), rtol=1e-12, atol=1e-14)
+
+
+def test_inert_slots_decouple_in_the_fit():
+    p = _stokes.mac2d(8)
+    lv = p.levels[0]
+    sm = O.fit_additive(lv.A, 4, 3, kind=lv.kind, norm="l1")
+    L1 = sm["lam"][0]
+    inert = np.flatnonzero(lv.kind == 2)
+    for s in inert:
+        b, r = divmod(int(s), 4)
+        e = np.zeros(4)
+        e[r] = 1.0
+        np.testing.assert_allclose(L1[b][r], e, atol=1e-14)
+        np.testing.assert_allclose(L1[b][:, r], e, atol=1e-14)
+
+
+def test_stokes_cascade_converges_under_gmres():
+    p = _stokes.mac2d(16)
+    sm = O.setup_hierarchy(p.levels, 4, norm="l1")
+    pre = lambda r: O.vcycle(p.levels, sm, r, "FF")
+    x, h = O.gmres(p.levels[0].A, pre, p.rhs, restart=30, rtol=1e-10, maxit=60)
+    assert h[-1] <= 1e-10 and O.rho_regression(h) < 0.2
+    r = p.rhs - p.levels[0].A @ x
+    assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(p.rhs)

@@ -192,3 +192,28 @@ def test_sipg_q3_generator():
     for i in range(64):
         nbrs = np.unique(B[i * 16:(i + 1) * 16].indices)
         assert all(col[j] != col[i] for j in nbrs if j != i)
+
+
+def test_mac_stokes_operator_and_hierarchy():
+    from synth import stokes
+    p = stokes.mac2d(16)
+    for lv in p.levels:
+        A = lv.A
+        assert abs(A - A.T).max() == 0.0
+        assert lv.block_size == 4 and len(lv.kind) == A.shape[0]
+        # inert slots: unit diagonal, nothing else in their row
+        for s in np.flatnonzero(lv.kind == 2):
+            row = A.getrow(s)
+            assert row.nnz == 1 and row.indices[0] == s and row.data[0] == 1.0
+        # constraint rows have a zero diagonal and couple to velocities only
+        for s in np.flatnonzero(lv.kind == 1)[:20]:
+            row = A.getrow(s)
+            assert A[s, s] == 0.0 and np.all(lv.kind[row.indices] == 0)
+    d = np.linalg.eigvalsh(p.levels[-1].A.toarray())
+    assert np.min(np.abs(d)) > 1e-8 and (d < 0).sum() == (p.levels[-1].kind == 1).sum()
+    # the interpolation reproduces a constant pressure away from the pinned cell
+    lv = p.levels[0]
+    pc = np.where(p.levels[1].kind == 1, 1.0, 0.0)
+    pf = lv.P @ pc
+    fine_p = np.flatnonzero(lv.kind == 1)
+    assert np.mean(pf[fine_p] == 1.0) > 0.9
