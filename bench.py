@@ -92,6 +92,33 @@ def bench_batch(precision: str):
     return out
 
 
+def bench_stokes(precision: str):
+    """2D Stokes on a 256^2 MAC staggered grid (cell blocks of velocity and
+    pressure, Stokes prescaling with 1-norm constraint rows), depth-4 additive
+    FF cascade; the V-cycle preconditions GMRES(30), left (the paper's driver)
+    and flexible."""
+    import time as _t
+    import numpy as np
+    import torch
+    from paper_2606_12577_amd import cascade
+    from synth import stokes
+    t = _t.perf_counter()
+    p = stokes.mac2d(256)
+    gen_s = _t.perf_counter() - t
+    s = cascade.Solver(p.levels)
+    b = torch.as_tensor(p.rhs, device="cuda").contiguous()
+    out = dict(cells=256 * 256, unknowns=int(p.n), generation_s=round(gen_s, 1))
+    for _ in range(2):
+        s.setup(depth=4, order="FF", precision=precision)
+    for method in ("gmres", "fgmres"):
+        i = [s.solve(b, rtol=1e-10, maxit=300, method=method, raise_on_noconv=False)[1] for _ in range(2)][-1]
+        out[method] = dict(solve_ms=round(i["solve_ms"], 2), iterations=i["iterations"], rho=round(i["rho"], 4),
+                           rel_res=i["rel_res"], setup_ms=round(i["setup_ms"], 2),
+                           dof_per_s=3 * 256 * 256 / (i["solve_ms"] * 1e-3))
+    s.close()
+    return out
+
+
 def bench_learned():
     """Q1 multiphase diffusion 96^3: train the block network on two samples,
     then on an unseen sample compare the learned finest-level setup with the
@@ -182,6 +209,7 @@ def main():
                     help="also measure the sketched setup with this many modes (0: skip)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-system measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-setup measurement")
+    ap.add_argument("--no-stokes", action="store_true", help="skip the Stokes (MAC) measurement")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -308,6 +336,9 @@ def main():
     if not args.no_batch:
         log("batched workload: 64 log-normal 2D systems")
         extra["batch64"] = bench_batch(args.precision)
+    if not args.no_stokes:
+        log("Stokes: MAC 256^2")
+        extra["stokes_mac_256"] = bench_stokes(args.precision)
     if not args.no_learned:
         log("learned setup: Q1 multiphase 96^3")
         extra["learned_q1_96"] = bench_learned()

@@ -121,9 +121,10 @@ void cs_destroy(cs_ctx ctx);
 /* Message of the last failing call on ctx (or of the last failed cs_create when ctx is NULL). */
 const char *cs_last_error(cs_ctx ctx);
 
-/* Copy the hierarchy to the device.  Validates sizes and that every diagonal
- * entry of every A is positive (elliptic prescaling, Sec. 2.3.1: CS_EINVAL
- * otherwise).  Invalidates any previous setup. */
+/* Copy the hierarchy to the device.  Validates sizes and column indices;
+ * invalidates any previous setup.  The setup checks the diagonals its
+ * prescaling needs (CS_EINVAL): a_kk > 0 for elliptic levels (Sec. 2.3.1), a
+ * positive viscous diagonal on saddle-point levels (cs_set_saddle_point). */
 cs_status cs_set_hierarchy(cs_ctx ctx, int32_t n_levels, const cs_level *levels);
 
 /* Build the cascading smoothers of every level but the last (Alg. 2 /
@@ -213,6 +214,20 @@ cs_status cs_solve_gmres(cs_ctx ctx, const double *b, double *x, int32_t nrhs, d
  *   opt: as cs_setup; trunc_alpha must be 0.
  * Residual patterns (cs_get_pattern) are not available after this setup. */
 cs_status cs_setup_sketched(cs_ctx ctx, const cs_options *opt, int32_t s, const double *S);
+
+/* Declare `level` a saddle-point (Stokes) level, Sec. 2.3.2: kind (host
+ * int32[n_level]) marks every unknown 0 velocity, 1 pressure (constraint row),
+ * 2 inert (a decoupled padding unknown; prescaled as a velocity).  The setup
+ * then prescales with W = diag(w_u, w_p): w_u so that the prescaled viscous
+ * block (the non-pressure columns of the velocity rows) has diagonal
+ * ||row||_1 / diagonal, and w_p so that every prescaled constraint row has unit
+ * max-norm (l1 = 0) or unit 1-norm (l1 = 1, the staggered-grid variant).  The
+ * cascade fit, V-cycle and Krylov drivers are unchanged (the operator is
+ * indefinite: use cs_solve_gmres).  kind = NULL restores elliptic prescaling.
+ * Call after cs_set_hierarchy; the next setup uses it.  CS_EINVAL for a kind
+ * outside 0..2, a level without pressures, and, at setup, a velocity row
+ * without a positive diagonal or a pressure row coupled to no velocity. */
+cs_status cs_set_saddle_point(cs_ctx ctx, int32_t level, const int32_t *kind, int32_t l1);
 
 /* Pick the launch schedule of every level's cascade sweeps by measurement
  * (needs a setup): for the current working precision and nrhs, one cascade

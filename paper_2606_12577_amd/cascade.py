@@ -78,6 +78,7 @@ SIGNATURES = {
     "cs_solve_gmres": (_I32, [_VP, _VP, _VP, _I32, _D, _I32, _I32, _I32, _p(cs_info), _p(_D)]),
     "cs_autotune": (_I32, [_VP, _I32, _p(_I32), _p(_I64), _p(_D)]),
     "cs_setup_sketched": (_I32, [_VP, _p(cs_options), _I32, _VP]),
+    "cs_set_saddle_point": (_I32, [_VP, _I32, _p(_I32), _I32]),
     "cs_trace": (_I32, [_VP, _I32, _I32]),
     "cs_trace_read": (_I32, [_VP, _I32, _p(_D), _p(_I64), _p(_D)]),
     "cs_set_systems": (_I32, [_VP, _I32, _p(_I64)]),
@@ -218,6 +219,21 @@ class Solver:
         self.n_levels = len(levels)
         self.n_systems = 1
         self.sizes = [(int(lv.A.shape[0]), int(lv.block_size)) for lv in levels]
+        # saddle-point levels (a `kind` array: 0 velocity, 1 pressure, 2 inert)
+        for i, lv in enumerate(levels):
+            kind = getattr(lv, "kind", None)
+            if kind is not None:
+                self.set_saddle_point(i, kind, l1=True)
+
+    def set_saddle_point(self, level: int, kind=None, l1: bool = True):
+        """Stokes prescaling for a level (Sec. 2.3.2): kind per unknown, 0
+        velocity, 1 pressure, 2 inert; constraint rows normalised by the 1-norm
+        (l1, the staggered-grid choice) or the max-norm.  None: elliptic."""
+        if kind is None:
+            self._check(self._lib.cs_set_saddle_point(self._h, level, None, 0))
+            return
+        k = _arr(kind, np.int32)
+        self._check(self._lib.cs_set_saddle_point(self._h, level, _ptr(k, _I32), int(bool(l1))))
 
     def setup(self, depth: int = 3, mode: str = "additive", order: str = "RF", n_pre: int = 1,
               n_post: int = 1, alpha: int = 0, precision: str = "fp64"):

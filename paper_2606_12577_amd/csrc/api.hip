@@ -70,19 +70,11 @@ void set_level(Ctx &c, Level &L, const cs_level &in, int li, int nlev, int64_t n
     need(L.nnz < INT32_MAX, "A has too many entries for 32-bit offsets");
     L.h_col.assign(in.a_col, in.a_col + L.nnz);
     L.h_val.assign(in.a_val, in.a_val + L.nnz);
-    for (int64_t r = 0; r < in.n; ++r) {
-        double d = 0.0;
-        bool found = false;
-        for (int64_t k = L.h_ptr[r]; k < L.h_ptr[r + 1]; ++k) {
+    // (the diagonal is checked by the prescaling at setup: elliptic levels need
+    // a_kk > 0, saddle-point levels a positive viscous diagonal)
+    for (int64_t r = 0; r < in.n; ++r)
+        for (int64_t k = L.h_ptr[r]; k < L.h_ptr[r + 1]; ++k)
             need(L.h_col[k] >= 0 && L.h_col[k] < in.n, "A column index out of range");
-            if (L.h_col[k] == r) {
-                d += L.h_val[k];
-                found = true;
-            }
-        }
-        need(found && d > 0.0, "level " + std::to_string(li) + ": diagonal entry of row " + std::to_string(r) +
-                                   " is not positive (elliptic prescaling needs a_kk > 0)");
-    }
     L.colour_given = in.colour != nullptr;
     L.layout_colour.clear();   // A changed: any colour layout is stale
     L.h_colour.clear();
@@ -480,6 +472,30 @@ cs_status cs_solve_cg(cs_ctx ctx, const double *b, double *x, int32_t nrhs, doub
                       cs_info *info, double *history) {
     return solve_escalating(ctx, b, x, maxit, rtol, info, [&](Ctx &c, cs_status *st) {
         cs::solve_cg(c, b, x, nrhs, rtol, maxit, info, history, st);
+    });
+}
+
+cs_status cs_set_saddle_point(cs_ctx ctx, int32_t level, const int32_t *kind, int32_t l1) {
+    return guarded(ctx, [&](Ctx &c) {
+        need(c.have_hierarchy, "cs_set_saddle_point before cs_set_hierarchy", CS_ESTATE);
+        need(level >= 0 && level < (int32_t)c.lv.size(), "level out of range");
+        need(l1 == 0 || l1 == 1, "l1 must be 0 (max-norm) or 1 (1-norm)");
+        Level &L = c.lv[level];
+        c.have_setup = false;
+        L.w.release();
+        if (!kind) {
+            L.kind.release();
+            return;
+        }
+        bool any_p = false;
+        for (int64_t i = 0; i < L.n; ++i) {
+            need(kind[i] >= 0 && kind[i] <= 2, "kind must be 0 (velocity), 1 (pressure) or 2 (inert)");
+            any_p |= kind[i] == 1;
+        }
+        need(any_p, "a saddle-point level needs pressure unknowns");
+        L.kind.upload(kind, L.n, c.stream);
+        L.stokes_l1 = l1;
+        CS_HIP(hipStreamSynchronize(c.stream));
     });
 }
 

@@ -115,6 +115,10 @@ struct Level {
     std::vector<Sell> csell;          // per-colour rows (multiplicative)
     DBuf<int32_t> clist;              // blocks sorted by colour
     std::vector<int32_t> layout_colour;   // colours the colour layout was built for
+    // saddle-point level (Stokes prescaling): kind per unknown, 0 velocity,
+    // 1 pressure, 2 inert (scaled as a velocity); empty for an elliptic level
+    DBuf<int32_t> kind;
+    int stokes_l1 = 0;                // constraint rows normalised by the 1-norm (else max-norm)
     // sweep launch schedule picked by the autotuner (0: the size rule)
     int tune_wgs = 0;                 // rows per workgroup: 64 or 256
     int64_t tune_grid = 0;            // workgroups (the kernels loop over the remaining tiles)

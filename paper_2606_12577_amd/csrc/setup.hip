@@ -42,14 +42,55 @@ __device__ inline int bsearch_i32(const int32_t *a, int lo, int hi, int32_t key)
 // ---------------------------------------------------------------------------
 // prescaling
 // ---------------------------------------------------------------------------
+// Elliptic prescaling (Sec. 2.3.1): w = a_kk^{-1/2}; bad[k] = 1 for a diagonal
+// that is not positive.
 __global__ void k_prescale_w(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
-                             const double *__restrict__ val, int64_t n, double *__restrict__ w) {
+                             const double *__restrict__ val, int64_t n, double *__restrict__ w,
+                             int32_t *__restrict__ bad) {
     int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (r >= n) return;
     double d = 0.0;
     for (int k = ptr[r]; k < ptr[r + 1]; ++k)
         if (col[k] == r) d = val[k];
-    w[r] = 1.0 / sqrt(d);
+    bad[r] = d > 0.0 ? 0 : 1;
+    w[r] = d > 0.0 ? 1.0 / sqrt(d) : 1.0;
+}
+
+// Stokes prescaling (Sec. 2.3.2), velocity (and inert) rows: with the viscous
+// block V (columns that are not pressures), w = sqrt(||V_r,:||_1) / V_rr, so
+// that the prescaled diagonal is ||V_r,:||_1 / V_rr.
+__global__ void k_prescale_stokes_v(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                                    const double *__restrict__ val, const int32_t *__restrict__ kind, int64_t n,
+                                    double *__restrict__ w, int32_t *__restrict__ bad) {
+    int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= n || kind[r] == 1) return;
+    double d = 0.0, l1 = 0.0;
+    for (int k = ptr[r]; k < ptr[r + 1]; ++k) {
+        const int c = col[k];
+        if (kind[c] == 1) continue;
+        l1 += fabs(val[k]);
+        if (c == r) d = val[k];
+    }
+    bad[r] = d > 0.0 ? 0 : 1;
+    w[r] = d > 0.0 ? sqrt(l1) / d : 1.0;
+}
+
+// pressure rows: every row of diag(w_p) D diag(w_u) gets unit max-norm
+// (l1 = 0) or unit 1-norm (l1 = 1)
+__global__ void k_prescale_stokes_p(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                                    const double *__restrict__ val, const int32_t *__restrict__ kind, int64_t n,
+                                    int l1, double *__restrict__ w, int32_t *__restrict__ bad) {
+    int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= n || kind[r] != 1) return;
+    double m = 0.0;
+    for (int k = ptr[r]; k < ptr[r + 1]; ++k) {
+        const int c = col[k];
+        if (kind[c] == 1) continue;
+        const double v = fabs(val[k] * w[c]);
+        m = l1 ? m + v : fmax(m, v);
+    }
+    bad[r] = m > 0.0 ? 0 : 1;
+    w[r] = m > 0.0 ? 1.0 / m : 1.0;
 }
 
 // A~ as dense nb x nb blocks on the block pattern of A.
@@ -1526,6 +1567,30 @@ bool rowprod_nb(hipStream_t s, int nb, int nl, const int32_t *list, const BPatte
 // and always for colouring), the colours (multiplicative) and the fit lists:
 // the active blocks of one colour at a time (multiplicative), or all active
 // blocks at once (additive).
+// W of the level: elliptic, or Stokes when the level carries unknown kinds
+void compute_prescaling(Ctx &c, Level &L) {
+    hipStream_t s = c.stream;
+    L.w.alloc(L.n);
+    DBuf<int32_t> bad(std::max<int64_t>(L.n, 1));
+    if (L.kind.n == (size_t)L.n && L.n > 0) {
+        hipLaunchKernelGGL(k_prescale_stokes_v, dim3(grid_for(L.n)), dim3(WG), 0, s, L.a_ptr.get(), L.a_col.get(),
+                           L.a_val.get(), L.kind.get(), L.n, L.w.get(), bad.get());
+        hipLaunchKernelGGL(k_prescale_stokes_p, dim3(grid_for(L.n)), dim3(WG), 0, s, L.a_ptr.get(), L.a_col.get(),
+                           L.a_val.get(), L.kind.get(), L.n, L.stokes_l1, L.w.get(), bad.get());
+        CS_LAUNCH_CHECK();
+        if (reduce_i32(c, bad.get(), L.n, false))
+            fail(CS_EINVAL, "Stokes prescaling: a velocity row without a positive diagonal or a pressure row "
+                            "without velocity couplings");
+    } else {
+        hipLaunchKernelGGL(k_prescale_w, dim3(grid_for(L.n)), dim3(WG), 0, s, L.a_ptr.get(), L.a_col.get(),
+                           L.a_val.get(), L.n, L.w.get(), bad.get());
+        CS_LAUNCH_CHECK();
+        if (reduce_i32(c, bad.get(), L.n, false))
+            fail(CS_EINVAL, "elliptic prescaling needs a positive diagonal (declare the unknown kinds of a "
+                            "saddle-point level)");
+    }
+}
+
 struct FitLists {
     std::vector<std::pair<const int32_t *, int>> lists;
     DBuf<int32_t> all_blocks;
@@ -1536,10 +1601,7 @@ void prepare_level(Ctx &c, Level &L, const cs_options &o, bool need_ap, BPattern
     const int B = (int)L.B;
     const int B_act = (int)(L.n_active / L.nb);   // blocks that are smoothed (the rest are solved directly)
     if (L.nb > MAXNB) fail(CS_EINVAL, "block size above 16 is not supported");
-    L.w.alloc(L.n);
-    hipLaunchKernelGGL(k_prescale_w, dim3(grid_for(L.n)), dim3(WG), 0, s, L.a_ptr.get(), L.a_col.get(),
-                       L.a_val.get(), L.n, L.w.get());
-    CS_LAUNCH_CHECK();
+    compute_prescaling(c, L);
     if (need_ap || o.mode == CS_MULTIPLICATIVE) block_pattern_of_A(c, L, ap);
     if (o.mode == CS_MULTIPLICATIVE) {
         if (!L.colour_given) greedy_colouring(c, L, ap);
@@ -1858,10 +1920,7 @@ void run_setup_sketched(Ctx &c, const cs_options &o, int sk, const double *S) {
 namespace {
 void level_prescaling(Ctx &c, Level &L) {
     if (L.w.n == (size_t)L.n) return;
-    L.w.alloc(L.n);
-    hipLaunchKernelGGL(k_prescale_w, dim3(grid_for(L.n)), dim3(WG), 0, c.stream, L.a_ptr.get(), L.a_col.get(),
-                       L.a_val.get(), L.n, L.w.get());
-    CS_LAUNCH_CHECK();
+    compute_prescaling(c, L);
 }
 }  // namespace
 

@@ -283,9 +283,10 @@ def test_state_and_argument_errors(gpu_lib):
     A = bad.levels[0].A.tolil()
     A[3, 3] = -1.0
     bad.levels[0].A = A.tocsr()
+    sb = gpu_lib.Solver(bad.levels)      # the diagonal is checked by the prescaling at setup
     with pytest.raises(gpu_lib.CascadeError) as e:
-        gpu_lib.Solver(bad.levels)
-    assert e.value.status == -1
+        sb.setup(depth=2)
+    assert e.value.status == -1 and "positive diagonal" in str(e.value)
     s.setup(depth=2)
     with pytest.raises(gpu_lib.CascadeError) as e:
         s.vcycle(np.zeros((p.n, 3)))

@@ -1,0 +1,95 @@
+"""Stokes (saddle-point) levels: Stokes prescaling on the GPU, cascade fit,
+V-cycle and GMRES on the MAC staggered grid, against the oracle.
+
+Lambda blocks: 1e-9 + 1e-12 cond(G_i) per block as for the elliptic fits (the
+normal equations are the same; only W differs).  V-cycle with the oracle's
+smoothers injected: 1e-12.  GMRES histories: 1e-6 relative, 1e-13 absolute
+(recomputed residuals at restarts), iterates 1e-8.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import stokes
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def check(s, sm, depth):
+    for l, d in enumerate(sm):
+        for ell in range(1, depth + 1):
+            g, o = s.get_smoother(l, ell), d["lam"][ell - 1]
+            num = np.linalg.norm((g - o).reshape(len(g), -1), axis=1)
+            den = np.maximum(np.linalg.norm(o.reshape(len(o), -1), axis=1), 1e-300)
+            worst = max(np.max(d["gram_cond"][e]) for e in range(ell))
+            ratio = float(np.max(num / den) / (1e-9 + 1e-12 * worst))
+            assert ratio <= 1.0, (l, ell, ratio)
+
+
+@pytest.fixture(scope="module")
+def mac16():
+    return stokes.mac2d(16, nrhs=2)
+
+
+@pytest.mark.parametrize("l1", [True, False])
+def test_stokes_setup_parity(gpu_lib, mac16, l1):
+    p = mac16
+    s = gpu_lib.Solver(p.levels)
+    for i, lv in enumerate(p.levels):
+        s.set_saddle_point(i, lv.kind, l1=l1)
+    s.setup(depth=3)
+    sm = O.setup_hierarchy(p.levels, 3, norm="l1" if l1 else "max")
+    check(s, sm, 3)
+
+
+def test_stokes_vcycle_and_gmres_parity(gpu_lib, mac16):
+    p = mac16
+    s = gpu_lib.Solver(p.levels)
+    s.setup(depth=4, order="FF")
+    sm = O.setup_hierarchy(p.levels, 4, norm="l1")
+    for l, d in enumerate(sm):
+        for ell, L in enumerate(d["lam"]):
+            s.set_smoother(l, ell + 1, L)
+    expect = O.vcycle(p.levels, sm, p.rhs, "FF", 1, 1)
+    assert rel(s.vcycle(p.rhs).cpu().numpy(), expect) <= 1e-12
+    pre = lambda r: O.vcycle(p.levels, sm, r, "FF")
+    for flexible in (False, True):
+        xo, ho = O.gmres(p.levels[0].A, pre, p.rhs, restart=30, rtol=1e-10, maxit=100, flexible=flexible)
+        x, info = s.solve(p.rhs, rtol=1e-10, maxit=100, method="fgmres" if flexible else "gmres")
+        assert info["iterations"] == len(ho) - 1
+        np.testing.assert_allclose(info["history"], ho, rtol=1e-6, atol=1e-13)
+        assert rel(x.cpu().numpy(), xo) <= 1e-8
+
+
+def test_stokes_fp32_gmres_and_sketch(gpu_lib):
+    p = stokes.mac2d(64, nrhs=4)
+    s = gpu_lib.Solver(p.levels)
+    s.setup(depth=4, order="FF", precision="fp32")
+    for method in ("gmres", "fgmres"):
+        x, info = s.solve(p.rhs, rtol=1e-10, maxit=200, method=method)
+        assert info["precision"] == "fp32" and info["rel_res"] <= 1e-10
+        r = p.rhs - p.levels[0].A @ x.cpu().numpy()
+        true = np.max(np.linalg.norm(r, axis=0) / np.linalg.norm(p.rhs, axis=0))
+        assert true <= (1e-10 if method == "fgmres" else 1e-7), (method, true)
+        print(f"mac64 {method}: {info['iterations']} it, rho {info['rho']:.3f}")
+    S = s.setup_sketched(width=32, seed=4, depth=3, order="FF").cpu().numpy()
+    off, sm = 0, []
+    for lv in p.levels[:-1]:
+        sm.append(O.fit_sketched(lv.A, 4, 3, S[off:off + lv.n], kind=lv.kind, norm="l1"))
+        off += lv.n
+    check(s, sm, 3)
+
+
+def test_saddle_point_needs_its_kinds(gpu_lib, mac16):
+    s = gpu_lib.Solver(mac16.levels)
+    s.set_saddle_point(0, None)            # level 0 back to elliptic: zero pressure diagonal
+    with pytest.raises(gpu_lib.CascadeError):
+        s.setup(depth=2)
+    bad = mac16.levels[0].kind.copy()
+    bad[5] = 7
+    with pytest.raises(gpu_lib.CascadeError):
+        s.set_saddle_point(0, bad)
