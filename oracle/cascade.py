@@ -331,6 +331,76 @@ def fit_sketched(A: sp.spmatrix, n: int, depth: int, S: np.ndarray, mode: str = 
                 colours=None if mode == "additive" else colours.astype(np.int32), gram_cond=cond)
 
 
+def replication(nodes: np.ndarray, N: int):
+    """Theta (Sec. 3.5.2): the tall binary matrix that copies nodal values into
+    the slots of overlapping blocks (nodes[i][s] = node of slot s of block i,
+    -1 for an unused slot, which gets a zero row), and theta = its column sums,
+    the multiplicity of every node."""
+    nodes = np.asarray(nodes)
+    nblk, m = nodes.shape
+    r = np.flatnonzero(nodes.ravel() >= 0)
+    Th = sp.csr_matrix((np.ones(len(r)), (r, nodes.ravel()[r])), shape=(nblk * m, N))
+    theta = np.asarray(Th.sum(axis=0)).ravel()
+    return Th, theta
+
+
+def fit_overlapping(A: sp.spmatrix, nodes: np.ndarray, depth: int, S: Optional[np.ndarray] = None,
+                    kind: Optional[np.ndarray] = None, norm: str = "max") -> Dict:
+    """Overlapping-block additive cascade (Sec. 3.5.2), on the prescaled A~:
+        Lambda_l = argmin_{Lambda block-diagonal over the slots}
+                   ||(Theta - Lambda Theta A~) E_{l-1}||_F,
+        E_l = diag(theta)^{-1} Theta^T (Theta - Lambda_l Theta A~) E_{l-1},
+    E_0 = I, or E_0 = S for the sketched form (Sec. 4).  Blockwise through the
+    normal equations Lambda_i G_i = H_i, G_i = M_i M_i^T, H_i = T_i M_i^T with
+    M = Theta A~ E and T = Theta E (unused slots: zero rows, and the
+    minimum-norm solution leaves their rows and columns zero).  Every node must
+    lie in some block.  Unscaled: Lambda_i <- W_i Lambda~_i W_i with W_i the
+    weights of the block's nodes.  Returns lam[l] of shape (nblk, m, m)."""
+    A = sp.csr_matrix(A)
+    N = A.shape[0]
+    nodes = np.asarray(nodes)
+    nblk, m = nodes.shape
+    w, At = prescale(A, kind, norm)
+    Th, theta = replication(nodes, N)
+    if np.any(theta == 0):
+        raise ValueError("every node must belong to a block")
+    Dinv = sp.diags(1.0 / theta)
+    E = sp.identity(N, format="csr") if S is None else np.array(S, dtype=np.float64)
+    lam_t, cond = [], []
+    for ell in range(1, depth + 1):
+        M = Th @ (At @ E)
+        T = Th @ E
+        if sp.issparse(M):
+            G = blockdiag_of_product(M, M, m)
+            H = blockdiag_of_product(T, M, m)
+        else:
+            Mb = M.reshape(nblk, m, -1)
+            Tb = T.reshape(nblk, m, -1)
+            G = Mb @ Mb.transpose(0, 2, 1)
+            H = Tb @ Mb.transpose(0, 2, 1)
+        Lt = least_squares_blocks(H, G)
+        lam_t.append(Lt)
+        cond.append(gram_condition(G))
+        if ell < depth:
+            E = Dinv @ (Th.T @ (T - blockdiag(Lt) @ M))
+            if sp.issparse(E):
+                E = sp.csr_matrix(E)
+    wr = (Th @ w).reshape(nblk, m)
+    lam = [wr[:, :, None] * L * wr[:, None, :] for L in lam_t]
+    return dict(lam=lam, lam_tilde=lam_t, w=w, nodes=nodes, theta=theta, gram_cond=cond)
+
+
+def smooth_overlapping(A: sp.spmatrix, sm: Dict, x: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """One forward application of an overlapping-block additive cascade
+    (Sec. 3.5.2): x <- x - diag(theta)^{-1} Theta^T Lambda_l Theta (A x - b),
+    l = 1..nu."""
+    Th, theta = replication(sm["nodes"], A.shape[0])
+    Dinv = sp.diags(1.0 / theta)
+    for L in sm["lam"]:
+        x = x - Dinv @ (Th.T @ (blockdiag(L) @ (Th @ (A @ x - b))))
+    return x
+
+
 def fit(A, n, depth, mode="additive", colours=None, alpha=None, kind=None, norm="max") -> Dict:
     if mode == "additive":
         return fit_additive(A, n, depth, alpha, kind, norm)
@@ -425,6 +495,18 @@ def vcycle(levels, smoothers: List[Dict], b: np.ndarray, order: str = "RF",
     if lvl == len(levels) - 1:
         return np.linalg.solve(lv.A.toarray(), b)
     x = np.zeros_like(b)
+    sm = smoothers[lvl]
+    if "nodes" in sm:        # overlapping blocks: forward applications only (FF)
+        if order != "FF":
+            raise ValueError("overlapping-block cascades are applied forward (FF)")
+        for _ in range(npre):
+            x = smooth_overlapping(lv.A, sm, x, b)
+        rc = lv.r_scale * (lv.P.T @ (lv.A @ x - b))
+        xc = vcycle(levels, smoothers, rc, order, npre, npost, lvl + 1)
+        x = x - lv.P @ xc
+        for _ in range(npost):
+            x = smooth_overlapping(lv.A, sm, x, b)
+        return x
     for _ in range(npre):
         x = smooth(lv.A, smoothers[lvl], x, b, reverse=(order == "RF"))
     rc = lv.r_scale * (lv.P.T @ (lv.A @ x - b))

@@ -200,6 +200,27 @@ def hierarchy(n: int, n_stop: int = 4) -> List[Level]:
     return levels
 
 
+def vanka_nodes(n: int) -> np.ndarray:
+    """Overlapping cell patches (the Vanka layout): every cell's pressure with
+    its four face velocities, [u_left, u_right, v_bottom, v_top, p] (-1 where a
+    face is a wall or the pressure is pinned), then one single-slot block for
+    every inert unknown so that every unknown lies in some block."""
+    kind = kinds(n)
+    blocks = []
+    for j in range(n):
+        for i in range(n):
+            c = i + n * j
+            uL = 4 * (c - 1) if i > 0 else -1
+            uR = 4 * c if kind[4 * c] == 0 else -1
+            vB = 4 * (c - n) + 1 if j > 0 else -1
+            vT = 4 * c + 1 if kind[4 * c + 1] == 0 else -1
+            p = 4 * c + 2 if kind[4 * c + 2] == 1 else -1
+            blocks.append([uL, uR, vB, vT, p])
+    for s in np.flatnonzero(kind == 2):
+        blocks.append([int(s), -1, -1, -1, -1])
+    return np.array(blocks, dtype=np.int32)
+
+
 def mac2d(n: int = 64, nrhs: int = 1, config_id: int = 6) -> Problem:
     """Enclosed 2D Stokes flow on n x n cells; RHS U[-1,1] on the momentum and
     constraint rows, zero on inert slots."""

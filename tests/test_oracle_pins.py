@@ -823,3 +823,72 @@ def test_stokes_cascade_converges_under_gmres():
     assert h[-1] <= 1e-10 and O.rho_regression(h) < 0.2
     r = p.rhs - p.levels[0].A @ x
     assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(p.rhs)
+
+
+# ---------------------------------------------------------------------------
+# Overlapping-block cascades (Sec. 3.5.2)
+# ---------------------------------------------------------------------------
+
+def test_overlapping_with_a_partition_is_the_additive_cascade():
+    p = fd.interface3d(8, nrhs=1)
+    A, n = p.levels[0].A, 8
+    nodes = np.arange(A.shape[0]).reshape(-1, n)
+    a = O.fit_additive(A, n, 3)
+    o = O.fit_overlapping(A, nodes, 3)
+    for L1, L2 in zip(o["lam"], a["lam"]):
+        np.testing.assert_allclose(L1, L2, rtol=1e-12, atol=1e-15)
+    x0 = stream(1, TEST, 80).uniform(-1, 1, size=(A.shape[0], 2))
+    b = stream(1, TEST, 81).uniform(-1, 1, size=(A.shape[0], 2))
+    ya, yo = O.smooth(A, a, x0, b), O.smooth_overlapping(A, o, x0, b)
+    assert np.linalg.norm(yo - ya) <= 1e-13 * np.linalg.norm(ya)
+
+
+def test_overlapping_levels_are_blockwise_least_squares():
+    """Vanka patches on a small MAC grid: every level's blocks against dense
+    least squares on the explicitly formed replicated residual."""
+    n = 4
+    p = _stokes.mac2d(n)
+    lv = p.levels[0]
+    nodes = _stokes.vanka_nodes(n)
+    sm = O.fit_overlapping(lv.A, nodes, 2, kind=lv.kind, norm="l1")
+    w, At = O.prescale(lv.A, lv.kind, "l1")
+    N = lv.A.shape[0]
+    At = At.toarray()
+    nblk, m = nodes.shape
+    Th = np.zeros((nblk * m, N))
+    for i in range(nblk):
+        for s_ in range(m):
+            if nodes[i, s_] >= 0:
+                Th[i * m + s_, nodes[i, s_]] = 1.0
+    theta = Th.sum(axis=0)
+    E = np.eye(N)
+    for ell in range(2):
+        M, T = Th @ At @ E, Th @ E
+        L = np.zeros((nblk, m, m))
+        for i in range(nblk):
+            r = slice(i * m, (i + 1) * m)
+            # min ||T_i - Lambda M_i||_F  <=>  M_i^T Lambda^T = T_i^T (minimum norm)
+            L[i] = np.linalg.lstsq(M[r].T, T[r].T, rcond=1e-13)[0].T
+        np.testing.assert_allclose(sm["lam_tilde"][ell], L, rtol=1e-8, atol=1e-11)
+        Lbig = np.zeros((nblk * m, nblk * m))
+        for i in range(nblk):
+            Lbig[i * m:(i + 1) * m, i * m:(i + 1) * m] = L[i]
+        E = np.diag(1.0 / theta) @ Th.T @ (T - Lbig @ M)
+
+
+def test_overlapping_identity_sketch_and_convergence():
+    p = _stokes.mac2d(8)
+    lv = p.levels[0]
+    nodes = _stokes.vanka_nodes(8)
+    ex = O.fit_overlapping(lv.A, nodes, 2, kind=lv.kind, norm="l1")
+    sk = O.fit_overlapping(lv.A, nodes, 2, S=np.eye(lv.n), kind=lv.kind, norm="l1")
+    for L1, L2 in zip(sk["lam"], ex["lam"]):
+        np.testing.assert_allclose(L1, L2, rtol=1e-10, atol=1e-12)
+    p = _stokes.mac2d(16)
+    sm, m = [], 16
+    for lv in p.levels[:-1]:
+        sm.append(O.fit_overlapping(lv.A, _stokes.vanka_nodes(m), 2, kind=lv.kind, norm="l1"))
+        m //= 2
+    x, h = O.gmres(p.levels[0].A, lambda r: O.vcycle(p.levels, sm, r, "FF"), p.rhs, restart=30, rtol=1e-10,
+                   maxit=60)
+    assert h[-1] <= 1e-10 and O.rho_regression(h) < 0.15
