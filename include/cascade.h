@@ -215,6 +215,20 @@ cs_status cs_solve_gmres(cs_ctx ctx, const double *b, double *x, int32_t nrhs, d
  * Residual patterns (cs_get_pattern) are not available after this setup. */
 cs_status cs_setup_sketched(cs_ctx ctx, const cs_options *opt, int32_t s, const double *S);
 
+/* Overlapping blocks for `level` (Sec. 3.5.2): n_blocks blocks of m slots
+ * (1 <= m <= 16); nodes (host int32[n_blocks][m]) names the unknown of every
+ * slot, -1 for an unused slot; every unknown must lie in at least one block
+ * (theta = its multiplicity).  The level's cascade becomes
+ *   x <- x - diag(theta)^{-1} Theta^T Lambda_l Theta (A x - b),  l = 1..nu,
+ * with Lambda_l block-diagonal over the replicated slots, fitted by
+ * cs_setup_sketched (additive, FF) against
+ *   min ||(Theta - Lambda Theta A~) E_{l-1}||_F,
+ *   E_l = diag(theta)^{-1} Theta^T (Theta - Lambda_l Theta A~) E_{l-1}, E_0 = S.
+ * cs_get_smoother / cs_set_smoother then move [n_blocks][m][m].  nodes = NULL
+ * restores the partition into block rows.  The level must not hold direct
+ * segments.  Invalidates the setup. */
+cs_status cs_set_overlapping_blocks(cs_ctx ctx, int32_t level, int64_t n_blocks, int32_t m, const int32_t *nodes);
+
 /* Declare `level` a saddle-point (Stokes) level, Sec. 2.3.2: kind (host
  * int32[n_level]) marks every unknown 0 velocity, 1 pressure (constraint row),
  * 2 inert (a decoupled padding unknown; prescaled as a velocity).  The setup

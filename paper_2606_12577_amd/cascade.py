@@ -79,6 +79,7 @@ SIGNATURES = {
     "cs_autotune": (_I32, [_VP, _I32, _p(_I32), _p(_I64), _p(_D)]),
     "cs_setup_sketched": (_I32, [_VP, _p(cs_options), _I32, _VP]),
     "cs_set_saddle_point": (_I32, [_VP, _I32, _p(_I32), _I32]),
+    "cs_set_overlapping_blocks": (_I32, [_VP, _I32, _I64, _I32, _p(_I32)]),
     "cs_trace": (_I32, [_VP, _I32, _I32]),
     "cs_trace_read": (_I32, [_VP, _I32, _p(_D), _p(_I64), _p(_D)]),
     "cs_set_systems": (_I32, [_VP, _I32, _p(_I64)]),
@@ -219,11 +220,31 @@ class Solver:
         self.n_levels = len(levels)
         self.n_systems = 1
         self.sizes = [(int(lv.A.shape[0]), int(lv.block_size)) for lv in levels]
+        self.ovl = {}
         # saddle-point levels (a `kind` array: 0 velocity, 1 pressure, 2 inert)
         for i, lv in enumerate(levels):
             kind = getattr(lv, "kind", None)
             if kind is not None:
                 self.set_saddle_point(i, kind, l1=True)
+
+    def set_overlapping_blocks(self, level: int, nodes=None):
+        """Overlapping blocks for a level (Sec. 3.5.2): nodes[i][s] is the
+        unknown of slot s of block i (-1 unused); None restores the partition.
+        Such levels are fitted by setup_sketched (additive, FF)."""
+        if nodes is None:
+            self._check(self._lib.cs_set_overlapping_blocks(self._h, level, 0, 0, None))
+            self.ovl.pop(level, None)
+            return
+        nd = _arr(nodes, np.int32)
+        self._check(self._lib.cs_set_overlapping_blocks(self._h, level, nd.shape[0], nd.shape[1], _ptr(nd, _I32)))
+        self.ovl[level] = (int(nd.shape[0]), int(nd.shape[1]))
+
+    def _lam_shape(self, level: int):
+        if level in self.ovl:
+            nblk, m = self.ovl[level]
+            return (nblk, m, m)
+        n, nb = self.sizes[level]
+        return (n // nb, nb, nb)
 
     def set_saddle_point(self, level: int, kind=None, l1: bool = True):
         """Stokes prescaling for a level (Sec. 2.3.2): kind per unknown, 0
@@ -265,15 +286,13 @@ class Solver:
         self._check(self._lib.cs_set_precision(self._h, _PRECS[precision]))
 
     def get_smoother(self, level: int, ell: int) -> np.ndarray:
-        n, nb = self.sizes[level]
-        out = np.empty((n // nb, nb, nb), dtype=np.float64)
+        out = np.empty(self._lam_shape(level), dtype=np.float64)
         self._check(self._lib.cs_get_smoother(self._h, level, ell, _ptr(out, ctypes.c_double)))
         return out
 
     def set_smoother(self, level: int, ell: int, blocks: np.ndarray):
         b = _arr(blocks, np.float64)
-        n, nb = self.sizes[level]
-        if b.size != n * nb:
+        if b.size != int(np.prod(self._lam_shape(level))):
             raise ValueError("smoother has the wrong size")
         self._check(self._lib.cs_set_smoother(self._h, level, ell, _ptr(b, ctypes.c_double)))
 

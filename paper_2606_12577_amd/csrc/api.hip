@@ -294,6 +294,8 @@ cs_status cs_setup(cs_ctx ctx, const cs_options *opt) {
         need(opt->trunc_alpha >= 0, "trunc_alpha must be >= 0");
         need(opt->precision == CS_FP64 || opt->precision == CS_FP32 || opt->precision == CS_BF16,
              "precision must be FP64, FP32 or BF16");
+        for (const Level &L : c.lv)
+            need(L.ovl_m == 0, "levels with overlapping blocks are fitted by cs_setup_sketched");
         c.have_setup = false;
         c.opt = *opt;
         c.precision = opt->precision;
@@ -317,7 +319,14 @@ cs_status cs_setup_sketched(cs_ctx ctx, const cs_options *opt, int32_t s, const 
         for (const Level &L : c.lv) nbmax = std::max<int64_t>(nbmax, L.nb);
         // with s <= n the first level fits every sketch column exactly: T_1 = 0
         // and every later level would fit rounding noise
+        bool ovl = false;
+        for (const Level &L : c.lv) {
+            ovl |= L.ovl_m > 0;
+            if (L.ovl_m) nbmax = std::max<int64_t>(nbmax, L.ovl_m);
+        }
         need(opt->depth == 1 || s > nbmax, "a deeper sketched cascade needs more sketch columns than the block size");
+        need(!ovl || (opt->mode == CS_ADDITIVE && opt->order == CS_FF),
+             "overlapping blocks take additive cascades applied forward (FF)");
         need(opt->precision == CS_FP64 || opt->precision == CS_FP32 || opt->precision == CS_BF16,
              "precision must be FP64, FP32 or BF16");
         c.have_setup = false;
@@ -387,7 +396,7 @@ cs_status cs_get_smoother(cs_ctx ctx, int32_t level, int32_t ell, double *out) {
         need(level >= 0 && level + 1 < (int)c.lv.size(), "level has no smoother");
         Level &L = c.lv[level];
         need(ell >= 1 && ell <= L.depth && out, "ell out of range");
-        const size_t nbl = L.B * L.nb * L.nb;
+        const size_t nbl = cs::lam_count(L) * cs::lam_size(L) * cs::lam_size(L);
         CS_HIP(hipMemcpyAsync(out, L.lam64.get() + (ell - 1) * nbl, nbl * sizeof(double), hipMemcpyDeviceToHost,
                               c.stream));
         CS_HIP(hipStreamSynchronize(c.stream));
@@ -400,7 +409,7 @@ cs_status cs_set_smoother(cs_ctx ctx, int32_t level, int32_t ell, const double *
         need(level >= 0 && level + 1 < (int)c.lv.size(), "level has no smoother");
         Level &L = c.lv[level];
         need(ell >= 1 && ell <= L.depth && blocks, "ell out of range");
-        const size_t nbl = L.B * L.nb * L.nb;
+        const size_t nbl = cs::lam_count(L) * cs::lam_size(L) * cs::lam_size(L);
         CS_HIP(hipMemcpyAsync(L.lam64.get() + (ell - 1) * nbl, blocks, nbl * sizeof(double), hipMemcpyHostToDevice,
                               c.stream));
         cs::build_working_copies(c);
@@ -472,6 +481,43 @@ cs_status cs_solve_cg(cs_ctx ctx, const double *b, double *x, int32_t nrhs, doub
                       cs_info *info, double *history) {
     return solve_escalating(ctx, b, x, maxit, rtol, info, [&](Ctx &c, cs_status *st) {
         cs::solve_cg(c, b, x, nrhs, rtol, maxit, info, history, st);
+    });
+}
+
+cs_status cs_set_overlapping_blocks(cs_ctx ctx, int32_t level, int64_t n_blocks, int32_t m, const int32_t *nodes) {
+    return guarded(ctx, [&](Ctx &c) {
+        need(c.have_hierarchy, "cs_set_overlapping_blocks before cs_set_hierarchy", CS_ESTATE);
+        need(level >= 0 && level + 1 < (int32_t)c.lv.size(), "level has no smoother");
+        Level &L = c.lv[level];
+        c.have_setup = false;
+        L.depth = 0;
+        if (!nodes) {
+            L.ovl_m = 0;
+            L.ovl_nblk = 0;
+            return;
+        }
+        need(m >= 1 && m <= 16 && n_blocks >= 1, "need 1 <= m <= 16 slots and at least one block");
+        need(L.n_active == L.n, "overlapping blocks need a level without direct segments");
+        std::vector<int32_t> cnt(L.n + 1, 0);
+        for (int64_t e = 0; e < n_blocks * m; ++e) {
+            need(nodes[e] >= -1 && nodes[e] < L.n, "block node out of range");
+            if (nodes[e] >= 0) cnt[nodes[e] + 1]++;
+        }
+        for (int64_t k = 0; k < L.n; ++k) need(cnt[k + 1] > 0, "every unknown must lie in some block");
+        for (int64_t k = 0; k < L.n; ++k) cnt[k + 1] += cnt[k];
+        std::vector<int32_t> idx(cnt[L.n]), fill(cnt.begin(), cnt.end() - 1);
+        std::vector<double> rt(L.n);
+        for (int64_t e = 0; e < n_blocks * m; ++e)
+            if (nodes[e] >= 0) idx[fill[nodes[e]]++] = (int32_t)e;   // ascending (block, slot)
+        for (int64_t k = 0; k < L.n; ++k) rt[k] = 1.0 / (cnt[k + 1] - cnt[k]);
+        L.ovl_m = m;
+        L.ovl_nblk = n_blocks;
+        L.ovl_nodes.upload(nodes, n_blocks * m, c.stream);
+        L.ovl_inv_ptr.upload(cnt.data(), cnt.size(), c.stream);
+        L.ovl_inv_idx.upload(idx.data(), idx.size(), c.stream);
+        L.ovl_rtheta.upload(rt.data(), rt.size(), c.stream);
+        c.ws_nrhs = 0;
+        CS_HIP(hipStreamSynchronize(c.stream));
     });
 }
 

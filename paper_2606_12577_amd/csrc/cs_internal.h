@@ -119,6 +119,15 @@ struct Level {
     // 1 pressure, 2 inert (scaled as a velocity); empty for an elliptic level
     DBuf<int32_t> kind;
     int stokes_l1 = 0;                // constraint rows normalised by the 1-norm (else max-norm)
+    // overlapping blocks (Sec. 3.5.2): ovl_m slots per block, ovl_nodes[i][s] the
+    // unknown of slot s of block i (-1 unused), the occurrences of every unknown
+    // (CSR over block * m + slot) and 1 / multiplicity.  The smoothers of such a
+    // level are [depth][ovl_nblk][ovl_m][ovl_m] in lam64 / lam32.
+    int ovl_m = 0;
+    int64_t ovl_nblk = 0;
+    DBuf<int32_t> ovl_nodes, ovl_inv_ptr, ovl_inv_idx;
+    DBuf<double> ovl_rtheta;
+    DBuf<unsigned char> ovl_y;        // replicated workspace [nblk][m][R] (working precision)
     // sweep launch schedule picked by the autotuner (0: the size rule)
     int tune_wgs = 0;                 // rows per workgroup: 64 or 256
     int64_t tune_grid = 0;            // workgroups (the kernels loop over the remaining tiles)
@@ -292,6 +301,10 @@ void build_sell(Sell &S, const std::vector<int64_t> &ptr, const std::vector<int3
                 const std::vector<double> &val, const std::vector<int32_t> *rows, hipStream_t s);
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// blocks and block size of a level's smoothers (overlapping or not)
+inline int64_t lam_count(const Level &L) { return L.ovl_m ? L.ovl_nblk : L.B; }
+inline int64_t lam_size(const Level &L) { return L.ovl_m ? L.ovl_m : L.nb; }
 
 }  // namespace cs
 

@@ -937,6 +937,107 @@ __global__ __launch_bounds__(WG) void k_sk_solve(const int32_t *__restrict__ lis
     normal_solve(G, H, Lc, V, nb, lamt + (int64_t)list[wi] * nb2, singular + wi);
 }
 
+// ---- overlapping blocks (Sec. 3.5.2), sketched form -------------------------
+// M = A~ T on every row (one wavefront per row, lane = sketch column)
+__global__ __launch_bounds__(WG) void k_sk_rows(int64_t n, const int32_t *__restrict__ aptr,
+                                                const int32_t *__restrict__ acol, const double *__restrict__ aval,
+                                                const double *__restrict__ w, int s, const double *__restrict__ T,
+                                                double *__restrict__ M) {
+    const int64_t row = blockIdx.x * (int64_t)(WG / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= n || lane >= s) return;
+    double acc = 0.0;
+    for (int e = aptr[row]; e < aptr[row + 1]; ++e) {
+        const int k = acol[e];
+        acc += aval[e] * w[k] * T[(int64_t)k * s + lane];
+    }
+    M[row * s + lane] = w[row] * acc;
+}
+
+// G_i = M_i M_i^T, H_i = T_i M_i^T over the block's slots (unused slots: zero
+// rows) into gh[i][2][m][m]
+template <int MB>
+__global__ __launch_bounds__(WG) void k_ovl_gram(int64_t nblk, int m, const int32_t *__restrict__ nodes, int s,
+                                                 const double *__restrict__ M, const double *__restrict__ T,
+                                                 double *__restrict__ gh) {
+    const int64_t wi = blockIdx.x * (int64_t)(WG / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (wi >= nblk) return;
+    double mv[MB], tv[MB];
+#pragma unroll
+    for (int r = 0; r < MB; ++r) {
+        const int k = r < m ? nodes[wi * m + r] : -1;
+        mv[r] = (k >= 0 && lane < s) ? M[(int64_t)k * s + lane] : 0.0;
+        tv[r] = (k >= 0 && lane < s) ? T[(int64_t)k * s + lane] : 0.0;
+    }
+    double *g = gh + wi * 2 * m * m, *h = g + m * m;
+#pragma unroll
+    for (int p = 0; p < MB; ++p) {
+        if (p >= m) break;   // uniform
+#pragma unroll
+        for (int q = 0; q < MB; ++q) {
+            if (q >= m) break;
+            const double gv = q <= p ? wave_sum(mv[p] * mv[q]) : 0.0;
+            const double hv = wave_sum(tv[p] * mv[q]);
+            if (lane == 0) {
+                if (q <= p) {
+                    g[p * m + q] = gv;
+                    g[q * m + p] = gv;
+                }
+                h[p * m + q] = hv;
+            }
+        }
+    }
+}
+
+// Y[i][r][c] = sum_u Lambda~_i[r][u] M[node(i, u)][c]
+template <int MB>
+__global__ __launch_bounds__(WG) void k_ovl_y(int64_t nblk, int m, const int32_t *__restrict__ nodes, int s,
+                                              const double *__restrict__ lamt, const double *__restrict__ M,
+                                              double *__restrict__ Y) {
+    const int64_t wi = blockIdx.x * (int64_t)(WG / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (wi >= nblk || lane >= s) return;
+    double mv[MB];
+#pragma unroll
+    for (int u = 0; u < MB; ++u) {
+        const int k = u < m ? nodes[wi * m + u] : -1;
+        mv[u] = k >= 0 ? M[(int64_t)k * s + lane] : 0.0;
+    }
+    const double *lam = lamt + wi * m * m;
+    for (int r = 0; r < m; ++r) {
+        double v = 0.0;
+#pragma unroll
+        for (int u = 0; u < MB; ++u)
+            if (u < m) v += lam[r * m + u] * mv[u];
+        Y[(wi * m + r) * s + lane] = v;
+    }
+}
+
+// T[k][c] <- T[k][c] - (1 / theta_k) sum over the slots of k of Y[slot][c]
+__global__ __launch_bounds__(WG) void k_ovl_fuse_T(int64_t n, const int32_t *__restrict__ iptr,
+                                                   const int32_t *__restrict__ iidx,
+                                                   const double *__restrict__ rtheta, int s,
+                                                   const double *__restrict__ Y, double *__restrict__ T) {
+    const int64_t k = blockIdx.x * (int64_t)(WG / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (k >= n || lane >= s) return;
+    double acc = 0.0;
+    for (int q = iptr[k]; q < iptr[k + 1]; ++q) acc += Y[(int64_t)iidx[q] * s + lane];
+    T[k * s + lane] -= rtheta[k] * acc;
+}
+
+// Lambda_i = W_i Lambda~_i W_i over the block's nodes (unused slots: zero)
+__global__ void k_ovl_unscale(int64_t nblk, int m, const int32_t *__restrict__ nodes, const double *__restrict__ w,
+                              const double *__restrict__ lamt, double *__restrict__ lam) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= nblk * m * m) return;
+    const int64_t i = e / (m * m);
+    const int r = (int)(e / m % m), c = (int)(e % m);
+    const int kr = nodes[i * m + r], kc = nodes[i * m + c];
+    lam[e] = (kr >= 0 && kc >= 0) ? w[kr] * lamt[e] * w[kc] : 0.0;
+}
+
 // T_i <- T_i - Lambda~_i M_i for the list blocks (in place: M was formed from
 // the old T before this launch)
 template <int NB>
@@ -1767,10 +1868,67 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
     CS_HIP(hipStreamSynchronize(s));
 }
 
+// Sketched fit of a level with overlapping blocks (Sec. 3.5.2 with the sketch
+// of Sec. 4): per cascade level M = A~ T, the blockwise normal equations over
+// the replicated slots, then T <- diag(theta)^{-1} Theta^T (Theta T - Lambda~ Theta M),
+// i.e. T_k -= (1/theta_k) sum over the slots of k of (Lambda~ M)_slot.
+void fit_level_overlap_sketched(Ctx &c, Level &L, const cs_options &o, const double *S, int sk) {
+    hipStream_t s = c.stream;
+    const int depth = o.depth, m = L.ovl_m;
+    const int64_t nblk = L.ovl_nblk, m2 = (int64_t)m * m;
+    compute_prescaling(c, L);
+    L.patterns.clear();
+    const size_t nT = (size_t)L.n * sk;
+    DBuf<double> T(std::max<size_t>(nT, 1)), M(std::max<size_t>(nT, 1));
+    CS_HIP(hipMemcpyAsync(T.get(), S, nT * sizeof(double), hipMemcpyDeviceToDevice, s));
+    DBuf<double> lamt((size_t)depth * nblk * m2), gh((size_t)nblk * 2 * m2), Y((size_t)nblk * m * sk);
+    DBuf<int32_t> list(nblk), sing(nblk);
+    hipLaunchKernelGGL(k_iota, dim3(grid_for(nblk)), dim3(WG), 0, s, list.get(), (int)nblk);
+    CS_LAUNCH_CHECK();
+    const dim3 gr((unsigned)ceil_div(L.n, WG / 64)), gb((unsigned)ceil_div(nblk, WG / 64));
+    L.singular = 0;
+    for (int ell = 1; ell <= depth; ++ell) {
+        double *lam_l = lamt.get() + (size_t)(ell - 1) * nblk * m2;
+        hipLaunchKernelGGL(k_sk_rows, gr, dim3(WG), 0, s, L.n, L.a_ptr.get(), L.a_col.get(), L.a_val.get(),
+                           L.w.get(), sk, (const double *)T.get(), M.get());
+        auto go = [&](auto mbc) {
+            constexpr int MB = decltype(mbc)::value;
+            hipLaunchKernelGGL(k_ovl_gram<MB>, gb, dim3(WG), 0, s, nblk, m, L.ovl_nodes.get(), sk,
+                               (const double *)M.get(), (const double *)T.get(), gh.get());
+            hipLaunchKernelGGL(k_sk_solve, dim3((unsigned)nblk), dim3(WG), 0, s, list.get(), m,
+                               (const double *)gh.get(), lam_l, sing.get());
+            if (ell < depth) {
+                hipLaunchKernelGGL(k_ovl_y<MB>, gb, dim3(WG), 0, s, nblk, m, L.ovl_nodes.get(), sk,
+                                   (const double *)lam_l, (const double *)M.get(), Y.get());
+                hipLaunchKernelGGL(k_ovl_fuse_T, gr, dim3(WG), 0, s, L.n, L.ovl_inv_ptr.get(), L.ovl_inv_idx.get(),
+                                   L.ovl_rtheta.get(), sk, (const double *)Y.get(), T.get());
+            }
+        };
+        if (m <= 4) go(std::integral_constant<int, 4>{});
+        else if (m <= 8) go(std::integral_constant<int, 8>{});
+        else go(std::integral_constant<int, 16>{});
+        CS_LAUNCH_CHECK();
+        L.singular += reduce_i32(c, sing.get(), nblk, true);
+    }
+    L.depth = depth;
+    L.lam64.alloc((size_t)depth * nblk * m2);
+    hipLaunchKernelGGL(k_ovl_unscale, dim3(grid_for(nblk * m2)), dim3(WG), 0, s, nblk, m, L.ovl_nodes.get(),
+                       L.w.get(), lamt.get(), L.lam64.get());
+    for (int ell = 1; ell < depth; ++ell)
+        hipLaunchKernelGGL(k_ovl_unscale, dim3(grid_for(nblk * m2)), dim3(WG), 0, s, nblk, m, L.ovl_nodes.get(),
+                           L.w.get(), lamt.get() + (size_t)ell * nblk * m2, L.lam64.get() + (size_t)ell * nblk * m2);
+    CS_LAUNCH_CHECK();
+    CS_HIP(hipStreamSynchronize(s));
+}
+
 // Sketched fit of one level (Sec. 4): T_0 = S (N x s, device, row-major),
 // then for every cascade level and fit list: M = A~ T on the list blocks, the
 // normal equations of min ||T_i - Lambda~_i M_i||_F, T_i <- T_i - Lambda~_i M_i.
 void fit_level_sketched(Ctx &c, Level &L, const cs_options &o, const double *S, int sk) {
+    if (L.ovl_m) {
+        fit_level_overlap_sketched(c, L, o, S, sk);
+        return;
+    }
     hipStream_t s = c.stream;
     const int B = (int)L.B, nb = (int)L.nb, nb2 = nb * nb;
     const int depth = o.depth;
@@ -1869,16 +2027,17 @@ void build_working_copies(Ctx &c) {
     c.gen++;   // buffers change: captured graphs are stale
     for (size_t l = 0; l + 1 < c.lv.size(); ++l) {
         Level &L = c.lv[l];
-        const int64_t tot = (int64_t)L.depth * L.B * L.nb * L.nb;
+        const int64_t nbk = lam_count(L), bsz = lam_size(L);
+        const int64_t tot = (int64_t)L.depth * nbk * bsz * bsz;
         L.lam64T.alloc(tot);
-        hipLaunchKernelGGL(k_transpose_blocks64, dim3(grid_for(tot)), dim3(WG), 0, c.stream, (int64_t)L.depth * L.B,
-                           (int)L.nb, L.lam64.get(), L.lam64T.get());
+        hipLaunchKernelGGL(k_transpose_blocks64, dim3(grid_for(tot)), dim3(WG), 0, c.stream, (int64_t)L.depth * nbk,
+                           (int)bsz, L.lam64.get(), L.lam64T.get());
         L.lam32.alloc(tot);
         L.lam32T.alloc(tot);
         hipLaunchKernelGGL(k_cast32, dim3(grid_for(tot)), dim3(WG), 0, c.stream, tot, L.lam64.get(), L.lam32.get());
         hipLaunchKernelGGL(k_cast32, dim3(grid_for(tot)), dim3(WG), 0, c.stream, tot, L.lam64T.get(), L.lam32T.get());
         CS_LAUNCH_CHECK();
-        build_bf16_smoother(c, L);
+        if (!L.ovl_m) build_bf16_smoother(c, L);
     }
     CS_HIP(hipStreamSynchronize(c.stream));
 }

@@ -1368,6 +1368,62 @@ void launch_sweep(Ctx &c, const Level &L, const Sell &S, bool rowmap, bool zero,
     if (slot <= -2) trace_end(c, slot);
 }
 
+// Overlapping blocks (Sec. 3.5.2): y = Lambda_l Theta r over the replicated
+// slots, r = A x - b (or -b on a zero guess), one thread per (block, slot).
+template <typename T, int R>
+__global__ void k_ovl_apply(int64_t nblk, int m, const int32_t *__restrict__ nodes, const T *__restrict__ lam,
+                            const T *__restrict__ r, int negate, T *__restrict__ y) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= nblk * m) return;
+    const int64_t i = e / m;
+    const int row = (int)(e % m);
+    T acc[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) acc[k] = T(0);
+    const T *lr = lam + (i * m + row) * m;
+    for (int u = 0; u < m; ++u) {
+        const int node = nodes[i * m + u];
+        if (node < 0) continue;
+        T rv[R];
+        vload<T, R>(r + (int64_t)node * R, rv);
+        const T l = lr[u];
+#pragma unroll
+        for (int k = 0; k < R; ++k) acc[k] += l * rv[k];
+    }
+    if (negate) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) acc[k] = -acc[k];
+    }
+    vstore<T, R>(y + e * R, acc);
+}
+
+// x_out = x_in - (1 / theta) Theta^T y (x_in null: a zero guess)
+template <typename T, int R>
+__global__ void k_ovl_fuse(int64_t n, const int32_t *__restrict__ iptr, const int32_t *__restrict__ iidx,
+                           const double *__restrict__ rtheta, const T *__restrict__ y, const T *xin, T *xout) {
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    T acc[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) acc[q] = T(0);
+    for (int q = iptr[k]; q < iptr[k + 1]; ++q) {
+        T yv[R];
+        vload<T, R>(y + (int64_t)iidx[q] * R, yv);
+#pragma unroll
+        for (int j = 0; j < R; ++j) acc[j] += yv[j];
+    }
+    T xo[R];
+    if (xin) vload<T, R>(xin + k * R, xo);
+    else {
+#pragma unroll
+        for (int j = 0; j < R; ++j) xo[j] = T(0);
+    }
+    const T f = (T)rtheta[k];
+#pragma unroll
+    for (int j = 0; j < R; ++j) xo[j] -= f * acc[j];
+    vstore<T, R>(xout + k * R, xo);
+}
+
 // One application of the cascade of level L: x <- S(x, b).  Returns the buffer
 // holding the result (additive sweeps alternate between x and alt).  With xc
 // given (additive only), the first sweep reads x - P x_c instead of x.
@@ -1376,6 +1432,36 @@ T *apply_cascade(Ctx &c, const Level &L, bool reverse, bool zero_start, const T 
                  const T *xc = nullptr) {
     const int64_t nbl = L.B * L.nb * L.nb;
     const int depth = L.depth;
+    if (L.ovl_m) {
+        // overlapping blocks: forward only (the setup requires FF); residual,
+        // blockwise apply over the replicated slots, fused weighted average
+        if (reverse || xc) fail(CS_EINVAL, "overlapping-block cascades apply forward without fused interpolation");
+        const int64_t m = L.ovl_m, nblk = L.ovl_nblk, lsz = nblk * m * m;
+        T *y = reinterpret_cast<T *>(L.ovl_y.get());
+        T *rr = reinterpret_cast<T *>(L.rr.get());
+        T *cur = x, *nxt = alt;
+        for (int ell = 0; ell < depth; ++ell) {
+            const bool zero = zero_start && ell == 0;
+            const double es = sizeof(T);
+            const int slot = trace_begin(c, zero ? CS_TRACE_SWEEP_ZERO : CS_TRACE_SWEEP_SMALL,
+                                         (zero ? 0.0 : L.nnz * (es + 4.0) + 3.0 * L.n * R * es) + lsz * es +
+                                             2.0 * nblk * m * R * es + 2.0 * L.n * R * es);
+            if (!zero)
+                hipLaunchKernelGGL((k_residual<T, R>), dim3(tile_grid(c, L.sell.nslices)), dim3(WG), 0, c.stream,
+                                   L.n, L.sell.nslices, L.sell.slice_ptr.get(), L.sell.slice_len.get(),
+                                   L.sell.col.get(), sell_val<T>(L.sell), b, cur, rr);
+            hipLaunchKernelGGL((k_ovl_apply<T, R>), dim3(grid_for(nblk * m)), dim3(WG), 0, c.stream, nblk, (int)m,
+                               L.ovl_nodes.get(), lam_ptr<T>(L, false) + (int64_t)ell * lsz, zero ? b : rr,
+                               zero ? 1 : 0, y);
+            hipLaunchKernelGGL((k_ovl_fuse<T, R>), dim3(grid_for(L.n)), dim3(WG), 0, c.stream, L.n,
+                               L.ovl_inv_ptr.get(), L.ovl_inv_idx.get(), L.ovl_rtheta.get(), (const T *)y,
+                               zero ? (const T *)nullptr : (const T *)cur, nxt);
+            CS_LAUNCH_CHECK();
+            trace_end(c, slot);
+            std::swap(cur, nxt);
+        }
+        return cur;
+    }
     if (c.opt.mode == CS_ADDITIVE) {
         T *cur = x, *nxt = alt;
         for (int s = 0; s < depth; ++s) {
@@ -1515,6 +1601,7 @@ void ensure_workspace(Ctx &c, int nrhs) {
         L.xt.alloc(bytes);
         L.bb.alloc(bytes);
         L.rr.alloc(bytes);
+        if (L.ovl_m) L.ovl_y.alloc((size_t)L.ovl_nblk * L.ovl_m * nrhs * es);
     }
     const int64_t G = std::min<int64_t>(ceil_div(c.lv[0].sell.nslices, 4), IR_GRID);
     c.ir_partial.alloc(std::max<int64_t>(G, 1) * 2 * nrhs);   // up to two dot products per RHS

@@ -93,3 +93,77 @@ def test_saddle_point_needs_its_kinds(gpu_lib, mac16):
     bad[5] = 7
     with pytest.raises(gpu_lib.CascadeError):
         s.set_saddle_point(0, bad)
+
+
+# ---------------------------------------------------------------------------
+# Overlapping blocks (Vanka cell patches), sketched fit
+# ---------------------------------------------------------------------------
+
+def vanka_solver(gpu_lib, p):
+    s = gpu_lib.Solver(p.levels)
+    m = p.meta["n"]
+    for l in range(len(p.levels) - 1):
+        s.set_overlapping_blocks(l, stokes.vanka_nodes(m))
+        m //= 2
+    return s
+
+
+def oracle_vanka(p, depth, S=None, width=None):
+    sm, m, off = [], p.meta["n"], 0
+    for lv in p.levels[:-1]:
+        Sl = None if S is None else S[off:off + lv.n]
+        off += lv.n
+        sm.append(O.fit_overlapping(lv.A, stokes.vanka_nodes(m), depth, S=Sl, kind=lv.kind, norm="l1"))
+        m //= 2
+    return sm
+
+
+def test_overlapping_sketched_setup_parity(gpu_lib, mac16):
+    p = mac16
+    s = vanka_solver(gpu_lib, p)
+    S = s.setup_sketched(width=32, seed=6, depth=2, order="FF").cpu().numpy()
+    check(s, oracle_vanka(p, 2, S), 2)
+
+
+def test_overlapping_vcycle_parity_with_exact_smoothers(gpu_lib, mac16):
+    p = mac16
+    s = vanka_solver(gpu_lib, p)
+    s.setup_sketched(width=32, seed=6, depth=2, order="FF")
+    sm = oracle_vanka(p, 2)
+    for l, d in enumerate(sm):
+        for ell, L in enumerate(d["lam"]):
+            s.set_smoother(l, ell + 1, L)
+    expect = O.vcycle(p.levels, sm, p.rhs, "FF", 1, 1)
+    assert rel(s.vcycle(p.rhs).cpu().numpy(), expect) <= 1e-12
+    rng = np.random.default_rng(3)
+    x0 = rng.uniform(-1, 1, size=p.rhs.shape)
+    got = s.smooth(0, p.rhs, x0).cpu().numpy()
+    assert rel(got, O.smooth_overlapping(p.levels[0].A, sm[0], x0, p.rhs)) <= 1e-12
+
+
+def test_overlapping_partition_equals_plain_blocks(gpu_lib, mac16):
+    p = mac16
+    s = gpu_lib.Solver(p.levels)
+    S = s.setup_sketched(width=32, seed=8, depth=2, order="FF")
+    plain = [[s.get_smoother(l, e) for e in (1, 2)] for l in range(len(p.levels) - 1)]
+    for l, lv in enumerate(p.levels[:-1]):
+        s.set_overlapping_blocks(l, np.arange(lv.n).reshape(-1, 4))
+    s.setup_sketched(width=32, sketch=S, depth=2, order="FF")
+    for l in range(len(p.levels) - 1):
+        for e in (1, 2):
+            np.testing.assert_allclose(s.get_smoother(l, e), plain[l][e - 1], rtol=1e-10, atol=1e-13)
+
+
+def test_overlapping_fp32_gmres(gpu_lib):
+    p = stokes.mac2d(64, nrhs=2)
+    s = vanka_solver(gpu_lib, p)
+    s.setup_sketched(width=32, seed=1, depth=3, order="FF", precision="fp32")
+    x, info = s.solve(p.rhs, rtol=1e-10, maxit=200, method="fgmres")
+    assert info["rel_res"] <= 1e-10
+    r = p.rhs - p.levels[0].A @ x.cpu().numpy()
+    assert np.max(np.linalg.norm(r, axis=0) / np.linalg.norm(p.rhs, axis=0)) <= 1e-10
+    print(f"mac64 Vanka sketched: {info['iterations']} it, rho {info['rho']:.3f}")
+    with pytest.raises(gpu_lib.CascadeError):
+        s.setup_sketched(width=32, seed=1, depth=3, order="RF")
+    with pytest.raises(gpu_lib.CascadeError):
+        s.setup(depth=2, order="FF")
