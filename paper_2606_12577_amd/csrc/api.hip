@@ -294,8 +294,10 @@ cs_status cs_setup(cs_ctx ctx, const cs_options *opt) {
         need(opt->trunc_alpha >= 0, "trunc_alpha must be >= 0");
         need(opt->precision == CS_FP64 || opt->precision == CS_FP32 || opt->precision == CS_BF16,
              "precision must be FP64, FP32 or BF16");
-        for (const Level &L : c.lv)
-            need(L.ovl_m == 0, "levels with overlapping blocks are fitted by cs_setup_sketched");
+        bool ovl = false;
+        for (const Level &L : c.lv) ovl |= L.ovl_m > 0;
+        need(!ovl || (opt->mode == CS_ADDITIVE && opt->order == CS_FF && opt->trunc_alpha == 0),
+             "overlapping blocks take additive cascades applied forward (FF), without truncation");
         c.have_setup = false;
         c.opt = *opt;
         c.precision = opt->precision;

@@ -22,7 +22,8 @@ namespace cs {
 namespace {
 
 constexpr int WG = 256;
-constexpr int UNION_CAP = 4096;   // candidate columns per row in the symbolic step
+constexpr int UNION_CAP = 4096;   // candidate columns per row in the symbolic step (a power of two)
+constexpr int UNION_CAP_BIG = 8192;   // the same for wide rows (32 KB of LDS; a power of two: the sort pads to one)
 constexpr int MATCH_CAP = 8192;   // (column, neighbour) matches cached per row
 constexpr int MAXNB = 16;
 constexpr double PIVOT_TOL = 1e-13;
@@ -117,13 +118,13 @@ __global__ void k_scatter_blocks(const int32_t *__restrict__ ptr, const int32_t 
 // SRC_E:      candidates are the columns of E_j for j in the block row i of A.
 enum { SRC_SCALAR = 0, SRC_E = 1 };
 
-template <int SRC, bool FILL>
+template <int SRC, bool FILL, int CAP = UNION_CAP>
 __global__ __launch_bounds__(WG) void k_union(const int32_t *__restrict__ list, int nlist, int nb,
                                               const int32_t *__restrict__ sptr, const int32_t *__restrict__ scol,
                                               const int32_t *__restrict__ eptr, const int32_t *__restrict__ ecol,
                                               int32_t *__restrict__ out_cnt, const int32_t *__restrict__ out_ptr,
                                               int32_t *__restrict__ out_col, int32_t *__restrict__ err) {
-    __shared__ int32_t cand[UNION_CAP];
+    __shared__ int32_t cand[CAP];
     __shared__ int32_t offs[257];
     __shared__ int32_t part[WG + 1];
     __shared__ int32_t total_s;
@@ -135,7 +136,7 @@ __global__ __launch_bounds__(WG) void k_union(const int32_t *__restrict__ list, 
     if (SRC == SRC_SCALAR) {
         int lo = sptr[(int64_t)i * nb], hi = sptr[(int64_t)(i + 1) * nb];
         total = hi - lo;
-        if (total > UNION_CAP) {
+        if (total > CAP) {
             if (t == 0) err[li] = 1;
             if (!FILL && t == 0) out_cnt[li] = 0;
             return;
@@ -161,7 +162,7 @@ __global__ __launch_bounds__(WG) void k_union(const int32_t *__restrict__ list, 
         }
         __syncthreads();
         total = total_s;
-        if (total > UNION_CAP) {
+        if (total > CAP) {
             if (t == 0) err[li] = 1;
             if (!FILL && t == 0) out_cnt[li] = 0;
             return;
@@ -1038,6 +1039,195 @@ __global__ void k_ovl_unscale(int64_t nblk, int m, const int32_t *__restrict__ n
     lam[e] = (kr >= 0 && kc >= 0) ? w[kr] * lamt[e] * w[kc] : 0.0;
 }
 
+// ---- overlapping blocks, exact form (Sec. 3.5.2): scalar residual E ----------
+// Prescaled values of A on its own pattern: a~_jl = w_j a_jl w_l
+__global__ void k_prescaled_csr(int64_t n, const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                                const double *__restrict__ val, const double *__restrict__ w,
+                                double *__restrict__ out) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    for (int k = ptr[r]; k < ptr[r + 1]; ++k) out[k] = w[r] * val[k] * w[col[k]];
+}
+
+// value of row (ptr, col, val) at column c, 0 when absent
+__device__ __forceinline__ double row_at(const int32_t *col, const double *val, int lo, int hi, int32_t c) {
+    const int q = bsearch_i32(col, lo, hi, c);
+    return q >= 0 ? val[q] : 0.0;
+}
+
+// G_i[s][t] = M_{n(s)} . M_{n(t)},  H_i[s][t] = E_{n(s)} . M_{n(t)} (sparse rows,
+// unused slots zero), one wavefront per block; gh[i][2][m][m]
+__global__ __launch_bounds__(WG) void k_ovl_gram_sparse(int64_t nblk, int m, const int32_t *__restrict__ nodes,
+                                                        const int32_t *__restrict__ mptr,
+                                                        const int32_t *__restrict__ mcol,
+                                                        const double *__restrict__ mval,
+                                                        const int32_t *__restrict__ eptr,
+                                                        const int32_t *__restrict__ ecol,
+                                                        const double *__restrict__ eval, double *__restrict__ gh) {
+    const int64_t wi = blockIdx.x * (int64_t)(WG / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (wi >= nblk) return;
+    double *g = gh + wi * 2 * m * m, *h = g + m * m;
+    for (int sI = 0; sI < m; ++sI) {
+        const int a = nodes[wi * m + sI];
+        for (int tI = 0; tI < m; ++tI) {
+            const int bn = nodes[wi * m + tI];
+            double gv = 0.0, hv = 0.0;
+            if (a >= 0 && bn >= 0) {
+                const int b0 = mptr[bn], b1 = mptr[bn + 1];
+                if (tI >= sI)
+                    for (int q = mptr[a] + lane; q < mptr[a + 1]; q += 64)
+                        gv += mval[q] * row_at(mcol, mval, b0, b1, mcol[q]);
+                for (int q = eptr[a] + lane; q < eptr[a + 1]; q += 64)
+                    hv += eval[q] * row_at(mcol, mval, b0, b1, ecol[q]);
+            }
+            gv = wave_sum(gv);
+            hv = wave_sum(hv);
+            if (lane == 0) {
+                if (tI >= sI) {
+                    g[sI * m + tI] = gv;
+                    g[tI * m + sI] = gv;
+                }
+                h[sI * m + tI] = hv;
+            }
+        }
+    }
+}
+
+// Rows that feed node k's new residual row: E_k itself, then the M rows of
+// every node u of every block holding k.  Returns the number of segments;
+// seg_row[s] < 0 marks the E row.
+__device__ __forceinline__ int ovl_segments(int k, int m, const int32_t *__restrict__ nodes,
+                                            const int32_t *__restrict__ iptr, const int32_t *__restrict__ iidx,
+                                            int32_t *seg_row, int cap) {
+    int ns = 0;
+    seg_row[ns++] = -1;
+    for (int q = iptr[k]; q < iptr[k + 1]; ++q) {
+        const int i = iidx[q] / m;
+        for (int u = 0; u < m; ++u) {
+            const int node = nodes[(int64_t)i * m + u];
+            if (node >= 0 && ns < cap) seg_row[ns++] = node;
+        }
+    }
+    return ns;
+}
+
+// Symbolic new residual row of node k: the sorted union of the columns of its
+// segments (one workgroup per node, bitonic sort in LDS as k_union).
+template <bool FILL>
+__global__ __launch_bounds__(WG) void k_ovl_union(int64_t n, int m, const int32_t *__restrict__ nodes,
+                                                  const int32_t *__restrict__ iptr, const int32_t *__restrict__ iidx,
+                                                  const int32_t *__restrict__ eptr, const int32_t *__restrict__ ecol,
+                                                  const int32_t *__restrict__ mptr, const int32_t *__restrict__ mcol,
+                                                  int32_t *__restrict__ out_cnt, const int32_t *__restrict__ out_ptr,
+                                                  int32_t *__restrict__ out_col, int32_t *__restrict__ err) {
+    __shared__ int32_t cand[UNION_CAP_BIG];
+    __shared__ int32_t seg_row[256], offs[257];
+    __shared__ int32_t part[WG + 1];
+    __shared__ int nseg_s;
+    const int64_t k = blockIdx.x;
+    const int t = threadIdx.x;
+    if (t == 0) {
+        nseg_s = ovl_segments((int)k, m, nodes, iptr, iidx, seg_row, 256);
+        offs[0] = 0;
+        for (int q = 0; q < nseg_s; ++q) {
+            const int r = seg_row[q];
+            offs[q + 1] = offs[q] + (r < 0 ? eptr[k + 1] - eptr[k] : mptr[r + 1] - mptr[r]);
+        }
+    }
+    __syncthreads();
+    const int nseg = nseg_s, total = offs[nseg];
+    if (total > UNION_CAP_BIG) {
+        if (t == 0) {
+            err[k] = 1;
+            if (!FILL) out_cnt[k] = 0;
+        }
+        return;
+    }
+    for (int e = t; e < total; e += WG) {
+        int q = 0;
+        while (offs[q + 1] <= e) ++q;
+        const int r = seg_row[q];
+        cand[e] = r < 0 ? ecol[eptr[k] + (e - offs[q])] : mcol[mptr[r] + (e - offs[q])];
+    }
+    int P = 1;
+    while (P < total) P <<= 1;
+    for (int e = total + t; e < P; e += WG) cand[e] = INT32_MAX;
+    __syncthreads();
+    for (int kk = 2; kk <= P; kk <<= 1) {
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            for (int a = t; a < P; a += WG) {
+                const int b = a ^ j;
+                if (b > a) {
+                    const int32_t x = cand[a], y = cand[b];
+                    const bool up = (a & kk) == 0;
+                    if ((x > y) == up) {
+                        cand[a] = y;
+                        cand[b] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const int chunk = (P + WG - 1) / WG;
+    const int a0 = t * chunk, a1 = min(P, a0 + chunk);
+    int mine = 0;
+    for (int a = a0; a < a1; ++a) {
+        const int32_t v = cand[a];
+        if (v != INT32_MAX && (a == 0 || cand[a - 1] != v)) ++mine;
+    }
+    part[t + 1] = mine;
+    __syncthreads();
+    if (t == 0) {
+        part[0] = 0;
+        for (int q = 0; q < WG; ++q) part[q + 1] += part[q];
+    }
+    __syncthreads();
+    if (!FILL) {
+        if (t == 0) out_cnt[k] = part[WG];
+    } else {
+        int o = out_ptr[k] + part[t];
+        for (int a = a0; a < a1; ++a) {
+            const int32_t v = cand[a];
+            if (v != INT32_MAX && (a == 0 || cand[a - 1] != v)) out_col[o++] = v;
+        }
+    }
+}
+
+// Numeric new residual row of node k on its pattern:
+//   E_new[k][c] = E[k][c] - (1/theta_k) sum_{(i,s) holding k} sum_u Lambda~_i[s][u] M[n(i,u)][c]
+// one wavefront per node, each lane owns output positions (fixed summation order)
+__global__ __launch_bounds__(WG) void k_ovl_eupdate(int64_t n, int m, const int32_t *__restrict__ nodes,
+                                                    const int32_t *__restrict__ iptr,
+                                                    const int32_t *__restrict__ iidx,
+                                                    const double *__restrict__ rtheta,
+                                                    const double *__restrict__ lamt, const int32_t *__restrict__ eptr,
+                                                    const int32_t *__restrict__ ecol, const double *__restrict__ eval,
+                                                    const int32_t *__restrict__ mptr, const int32_t *__restrict__ mcol,
+                                                    const double *__restrict__ mval, const int32_t *__restrict__ nptr,
+                                                    const int32_t *__restrict__ ncol, double *__restrict__ nval) {
+    const int64_t k = blockIdx.x * (int64_t)(WG / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (k >= n) return;
+    const double rt = rtheta[k];
+    for (int p = nptr[k] + lane; p < nptr[k + 1]; p += 64) {
+        const int32_t c = ncol[p];
+        double v = row_at(ecol, eval, eptr[k], eptr[k + 1], c);
+        for (int q = iptr[k]; q < iptr[k + 1]; ++q) {
+            const int64_t i = iidx[q] / m;
+            const int sl = iidx[q] % m;
+            const double *lam = lamt + (i * m + sl) * m;
+            for (int u = 0; u < m; ++u) {
+                const int node = nodes[i * m + u];
+                if (node < 0) continue;
+                v -= rt * lam[u] * row_at(mcol, mval, mptr[node], mptr[node + 1], c);
+            }
+        }
+        nval[p] = v;
+    }
+}
+
 // T_i <- T_i - Lambda~_i M_i for the list blocks (in place: M was formed from
 // the old T before this launch)
 template <int NB>
@@ -1581,7 +1771,7 @@ int max_span(Ctx &c, int64_t n, int stride, const int32_t *ptr) {
 
 // Union of sorted column lists for nl rows: one wavefront per row when every
 // row has at most 512 candidates (the bound is an upper bound of the candidate
-// count), else one workgroup per row.
+// count), else one workgroup per row (with the larger LDS buffer beyond 4096).
 template <int SRC, bool FILL>
 void launch_union(hipStream_t s, int64_t bound, const int32_t *list, int nl, int nb, const int32_t *sptr,
                   const int32_t *scol, const int32_t *eptr, const int32_t *ecol, int32_t *cnt, const int32_t *optr,
@@ -1599,9 +1789,12 @@ void launch_union(hipStream_t s, int64_t bound, const int32_t *list, int nl, int
     else if (bound <= 512)
         hipLaunchKernelGGL((k_union_wave<8, SRC, FILL>), gw, dim3(WG), 0, s, list, nl, nb, sptr, scol, eptr, ecol,
                            cnt, optr, ocol, err);
-    else
+    else if (bound <= UNION_CAP)
         hipLaunchKernelGGL((k_union<SRC, FILL>), dim3(nl), dim3(WG), 0, s, list, nl, nb, sptr, scol, eptr, ecol, cnt,
                            optr, ocol, err);
+    else
+        hipLaunchKernelGGL((k_union<SRC, FILL, UNION_CAP_BIG>), dim3(nl), dim3(WG), 0, s, list, nl, nb, sptr, scol,
+                           eptr, ecol, cnt, optr, ocol, err);
 }
 
 void block_pattern_of_A(Ctx &c, Level &L, BPattern &ap) {
@@ -1728,7 +1921,13 @@ void prepare_level(Ctx &c, Level &L, const cs_options &o, bool need_ap, BPattern
     }
 }
 
+void fit_level_overlap_exact(Ctx &c, Level &L, const cs_options &o);
+
 void fit_level(Ctx &c, Level &L, const cs_options &o) {
+    if (L.ovl_m) {
+        fit_level_overlap_exact(c, L, o);
+        return;
+    }
     hipStream_t s = c.stream;
     const int B = (int)L.B, nb = (int)L.nb, nb2 = nb * nb;
     const int depth = o.depth;
@@ -1868,6 +2067,102 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
     CS_HIP(hipStreamSynchronize(s));
 }
 
+// Exact fit of a level with overlapping blocks (Sec. 3.5.2): scalar residual
+// E (CSR over nodes), per cascade level M = A~ E on every node (symbolic union
+// and the point row product), the blockwise normal equations over the slots,
+// and E_new = diag(theta)^{-1} Theta^T (Theta E - Lambda~ Theta M) row by row.
+void fit_level_overlap_exact(Ctx &c, Level &L, const cs_options &o) {
+    hipStream_t s = c.stream;
+    const int depth = o.depth, m = L.ovl_m;
+    const int64_t n = L.n, nblk = L.ovl_nblk, m2 = (int64_t)m * m;
+    compute_prescaling(c, L);
+    L.patterns.clear();
+    // A~ on the scalar pattern of A
+    BPattern ap;
+    ap.rows = n;
+    ap.nnzb = L.nnz;
+    ap.ptr.alloc(n + 1);
+    ap.col.alloc(std::max<int64_t>(L.nnz, 1));
+    CS_HIP(hipMemcpyAsync(ap.ptr.get(), L.a_ptr.get(), (n + 1) * 4, hipMemcpyDeviceToDevice, s));
+    CS_HIP(hipMemcpyAsync(ap.col.get(), L.a_col.get(), L.nnz * 4, hipMemcpyDeviceToDevice, s));
+    DBuf<double> aval(std::max<int64_t>(L.nnz, 1));
+    hipLaunchKernelGGL(k_prescaled_csr, dim3(grid_for(n)), dim3(WG), 0, s, n, L.a_ptr.get(), L.a_col.get(),
+                       L.a_val.get(), L.w.get(), aval.get());
+    // E_0 = I
+    EMat E;
+    E.pat.rows = n;
+    E.pat.nnzb = n;
+    E.pat.ptr.alloc(n + 1);
+    E.pat.col.alloc(n);
+    E.val.alloc(n);
+    hipLaunchKernelGGL(k_identity_E, dim3(grid_for(n)), dim3(WG), 0, s, (int)n, 1, E.pat.ptr.get(), E.pat.col.get(),
+                       E.val.get());
+    CS_LAUNCH_CHECK();
+    DBuf<int32_t> list(n), cnt(n), err(n), sing(nblk);
+    DBuf<int64_t> tot(1);
+    hipLaunchKernelGGL(k_iota, dim3(grid_for(n)), dim3(WG), 0, s, list.get(), (int)n);
+    DBuf<double> lamt((size_t)depth * nblk * m2), gh((size_t)nblk * 2 * m2);
+    const int maxdeg = max_span(c, n, 1, ap.ptr.get());
+    const dim3 gw((unsigned)ceil_div(n, WG / 64)), gb((unsigned)ceil_div(nblk, WG / 64));
+    L.singular = 0;
+    for (int ell = 1; ell <= depth; ++ell) {
+        // symbolic and numeric M = A~ E on every node
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n)), dim3(WG), 0, s, err.get(), n, 0);
+        BPattern mp;
+        mp.rows = n;
+        const int64_t bound = maxdeg <= 64 ? (int64_t)maxdeg * max_span(c, n, 1, E.pat.ptr.get()) : INT64_MAX;
+        launch_union<SRC_E, false>(s, bound, list.get(), (int)n, 1, ap.ptr.get(), ap.col.get(), E.pat.ptr.get(),
+                                   E.pat.col.get(), cnt.get(), nullptr, nullptr, err.get());
+        CS_LAUNCH_CHECK();
+        check_flags(c, err, n, "fill of a residual row");
+        mp.nnzb = scan_counts(c, cnt, n, mp.ptr, tot);
+        mp.col.alloc(std::max<int64_t>(mp.nnzb, 1));
+        launch_union<SRC_E, true>(s, bound, list.get(), (int)n, 1, ap.ptr.get(), ap.col.get(), E.pat.ptr.get(),
+                                  E.pat.col.get(), nullptr, mp.ptr.get(), mp.col.get(), err.get());
+        DBuf<double> mval(std::max<int64_t>(mp.nnzb, 1));
+        hipLaunchKernelGGL(k_rowprod_point, gw, dim3(WG), 0, s, (int)n, list.get(), ap.ptr.get(), ap.col.get(),
+                           aval.get(), E.pat.ptr.get(), E.pat.col.get(), E.val.get(), mp.ptr.get(), mp.col.get(),
+                           mval.get());
+        // normal equations per overlapping block
+        double *lam_l = lamt.get() + (size_t)(ell - 1) * nblk * m2;
+        hipLaunchKernelGGL(k_ovl_gram_sparse, gb, dim3(WG), 0, s, nblk, m, L.ovl_nodes.get(), mp.ptr.get(),
+                           mp.col.get(), mval.get(), E.pat.ptr.get(), E.pat.col.get(), E.val.get(), gh.get());
+        hipLaunchKernelGGL(k_sk_solve, dim3((unsigned)nblk), dim3(WG), 0, s, list.get(), m, (const double *)gh.get(),
+                           lam_l, sing.get());
+        CS_LAUNCH_CHECK();
+        L.singular += reduce_i32(c, sing.get(), nblk, true);
+        if (ell == depth) break;
+        // new residual rows
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n)), dim3(WG), 0, s, err.get(), n, 0);
+        hipLaunchKernelGGL(k_ovl_union<false>, dim3((unsigned)n), dim3(WG), 0, s, n, m, L.ovl_nodes.get(),
+                           L.ovl_inv_ptr.get(), L.ovl_inv_idx.get(), E.pat.ptr.get(), E.pat.col.get(), mp.ptr.get(),
+                           mp.col.get(), cnt.get(), nullptr, nullptr, err.get());
+        CS_LAUNCH_CHECK();
+        check_flags(c, err, n, "fill of an overlapping residual row");
+        EMat N;
+        N.pat.rows = n;
+        N.pat.nnzb = scan_counts(c, cnt, n, N.pat.ptr, tot);
+        N.pat.col.alloc(std::max<int64_t>(N.pat.nnzb, 1));
+        N.val.alloc(std::max<int64_t>(N.pat.nnzb, 1));
+        hipLaunchKernelGGL(k_ovl_union<true>, dim3((unsigned)n), dim3(WG), 0, s, n, m, L.ovl_nodes.get(),
+                           L.ovl_inv_ptr.get(), L.ovl_inv_idx.get(), E.pat.ptr.get(), E.pat.col.get(), mp.ptr.get(),
+                           mp.col.get(), nullptr, N.pat.ptr.get(), N.pat.col.get(), err.get());
+        hipLaunchKernelGGL(k_ovl_eupdate, gw, dim3(WG), 0, s, n, m, L.ovl_nodes.get(), L.ovl_inv_ptr.get(),
+                           L.ovl_inv_idx.get(), L.ovl_rtheta.get(), (const double *)lam_l, E.pat.ptr.get(),
+                           E.pat.col.get(), E.val.get(), mp.ptr.get(), mp.col.get(), mval.get(), N.pat.ptr.get(),
+                           N.pat.col.get(), N.val.get());
+        CS_LAUNCH_CHECK();
+        E = std::move(N);
+    }
+    L.depth = depth;
+    L.lam64.alloc((size_t)depth * nblk * m2);
+    for (int ell = 0; ell < depth; ++ell)
+        hipLaunchKernelGGL(k_ovl_unscale, dim3(grid_for(nblk * m2)), dim3(WG), 0, s, nblk, m, L.ovl_nodes.get(),
+                           L.w.get(), lamt.get() + (size_t)ell * nblk * m2, L.lam64.get() + (size_t)ell * nblk * m2);
+    CS_LAUNCH_CHECK();
+    CS_HIP(hipStreamSynchronize(s));
+}
+
 // Sketched fit of a level with overlapping blocks (Sec. 3.5.2 with the sketch
 // of Sec. 4): per cascade level M = A~ T, the blockwise normal equations over
 // the replicated slots, then T <- diag(theta)^{-1} Theta^T (Theta T - Lambda~ Theta M),
@@ -1912,9 +2207,7 @@ void fit_level_overlap_sketched(Ctx &c, Level &L, const cs_options &o, const dou
     }
     L.depth = depth;
     L.lam64.alloc((size_t)depth * nblk * m2);
-    hipLaunchKernelGGL(k_ovl_unscale, dim3(grid_for(nblk * m2)), dim3(WG), 0, s, nblk, m, L.ovl_nodes.get(),
-                       L.w.get(), lamt.get(), L.lam64.get());
-    for (int ell = 1; ell < depth; ++ell)
+    for (int ell = 0; ell < depth; ++ell)
         hipLaunchKernelGGL(k_ovl_unscale, dim3(grid_for(nblk * m2)), dim3(WG), 0, s, nblk, m, L.ovl_nodes.get(),
                            L.w.get(), lamt.get() + (size_t)ell * nblk * m2, L.lam64.get() + (size_t)ell * nblk * m2);
     CS_LAUNCH_CHECK();

@@ -96,7 +96,7 @@ def test_saddle_point_needs_its_kinds(gpu_lib, mac16):
 
 
 # ---------------------------------------------------------------------------
-# Overlapping blocks (Vanka cell patches), sketched fit
+# Overlapping blocks (Vanka cell patches), exact and sketched fits
 # ---------------------------------------------------------------------------
 
 def vanka_solver(gpu_lib, p):
@@ -123,6 +123,19 @@ def test_overlapping_sketched_setup_parity(gpu_lib, mac16):
     s = vanka_solver(gpu_lib, p)
     S = s.setup_sketched(width=32, seed=6, depth=2, order="FF").cpu().numpy()
     check(s, oracle_vanka(p, 2, S), 2)
+
+
+@pytest.mark.parametrize("depth", [1, 3])
+def test_overlapping_exact_setup_parity(gpu_lib, mac16, depth):
+    """The exact overlapping-block fit (scalar residual rows, blockwise normal
+    equations over the replicated slots) against the oracle's."""
+    p = mac16
+    s = vanka_solver(gpu_lib, p)
+    s.setup(depth=depth, order="FF")
+    sm = oracle_vanka(p, depth)
+    check(s, sm, depth)
+    expect = O.vcycle(p.levels, sm, p.rhs, "FF", 1, 1)
+    assert rel(s.vcycle(p.rhs).cpu().numpy(), expect) <= 1e-10
 
 
 def test_overlapping_vcycle_parity_with_exact_smoothers(gpu_lib, mac16):
@@ -166,4 +179,8 @@ def test_overlapping_fp32_gmres(gpu_lib):
     with pytest.raises(gpu_lib.CascadeError):
         s.setup_sketched(width=32, seed=1, depth=3, order="RF")
     with pytest.raises(gpu_lib.CascadeError):
-        s.setup(depth=2, order="FF")
+        s.setup(depth=2, order="RF")
+    s.setup(depth=3, order="FF", precision="fp32")
+    x, ex = s.solve(p.rhs, rtol=1e-10, maxit=200, method="fgmres")
+    assert ex["rel_res"] <= 1e-10
+    print(f"mac64 Vanka exact: {ex['iterations']} it, rho {ex['rho']:.3f}")
