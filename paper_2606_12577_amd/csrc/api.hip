@@ -145,6 +145,11 @@ void set_level(Ctx &c, Level &L, const cs_level &in, int li, int nlev, int64_t n
         L.pt_val64.upload(tv.data(), tv.size(), c.stream);
         std::vector<float> tvf(tv.begin(), tv.end());
         L.pt_val32.upload(tvf.data(), tvf.size(), c.stream);
+        // sliced ELLPACK copies for the transfer kernels (columns of P are coarse
+        // indices: pad with column 0)
+        std::vector<int64_t> pp64(pp.begin(), pp.end()), tp64(tp.begin(), tp.end());
+        cs::build_sell(L.psell, pp64, pc, pv, nullptr, c.stream, false);
+        cs::build_sell(L.ptsell, tp64, tc, tv, nullptr, c.stream, false);
         CS_HIP(hipStreamSynchronize(c.stream));
     }
     cs::build_level_device(c, L);

@@ -145,6 +145,7 @@ struct Level {
     DBuf<int32_t> p_ptr, p_col, pt_ptr, pt_col;
     DBuf<double> p_val64, pt_val64;
     DBuf<float> p_val32, pt_val32;
+    Sell psell, ptsell;               // P (fine rows) and P^T (coarse rows) as sliced ELLPACK
     // prescaling and smoother
     DBuf<double> w;
     int depth = 0;
@@ -298,7 +299,7 @@ void solve_gmres(Ctx &c, const double *b, double *x, int nrhs, double rtol, int 
 
 // host helpers
 void build_sell(Sell &S, const std::vector<int64_t> &ptr, const std::vector<int32_t> &col,
-                const std::vector<double> &val, const std::vector<int32_t> *rows, hipStream_t s);
+                const std::vector<double> &val, const std::vector<int32_t> *rows, hipStream_t s, bool pad_with_row = true);
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 

@@ -1632,7 +1632,8 @@ void check_flags(Ctx &c, const DBuf<int32_t> &flags, int64_t n, const char *what
 // ---------------------------------------------------------------------------
 
 void build_sell(Sell &S, const std::vector<int64_t> &ptr, const std::vector<int32_t> &col,
-                const std::vector<double> &val, const std::vector<int32_t> *rows, hipStream_t s) {
+                const std::vector<double> &val, const std::vector<int32_t> *rows, hipStream_t s,
+                bool pad_with_row) {
     const int64_t m = rows ? (int64_t)rows->size() : (int64_t)ptr.size() - 1;
     S.nrows = m;
     S.nslices = ceil_div(m, 64);
@@ -1667,8 +1668,8 @@ void build_sell(Sell &S, const std::vector<int64_t> &ptr, const std::vector<int3
                 if (k < rl) {
                     hc[o] = col[ptr[r] + k];
                     hv[o] = val[ptr[r] + k];
-                } else {
-                    hc[o] = r >= 0 ? (int32_t)r : 0;
+                } else {   // padding: a zero at the row's own index (square A) or at column 0
+                    hc[o] = (pad_with_row && r >= 0) ? (int32_t)r : 0;
                     hv[o] = 0.0;
                 }
             }

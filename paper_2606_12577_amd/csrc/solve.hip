@@ -401,44 +401,53 @@ __global__ __launch_bounds__(WG) void k_residual_restrict(int64_t nrows, int64_t
     }
 }
 
-// b_c = r_scale * P^T r  (gather through the stored transpose)
+// b_c = r_scale * P^T r with P^T in sliced ELLPACK (a lane per coarse row,
+// coalesced column/value streams)
 template <typename T, int R>
-__global__ void k_restrict(int64_t nc, const int32_t *__restrict__ ptp, const int32_t *__restrict__ ptc,
-                           const T *__restrict__ ptv, T r_scale, const T *__restrict__ r, T *__restrict__ bc) {
-    const int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (I >= nc) return;
-    T acc[R];
+__global__ __launch_bounds__(WG) void k_restrict_sell(int64_t nc, int64_t nslices, const int64_t *__restrict__ sptr,
+                                                      const int32_t *__restrict__ slen,
+                                                      const int32_t *__restrict__ scol, const T *__restrict__ sval,
+                                                      T r_scale, const T *__restrict__ r, T *__restrict__ bc) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const Tiles tl = my_tiles((nslices + 3) / 4);
+    for (int64_t tile = tl.t; tile < tl.end; tile += tl.step) {
+        const int64_t slice = tile * 4 + wv;
+        const int64_t row = slice * 64 + lane;
+        if (slice >= nslices || row >= nc) continue;
+        T acc[R];
 #pragma unroll
-    for (int k = 0; k < R; ++k) acc[k] = T(0);
-    for (int e = ptp[I]; e < ptp[I + 1]; ++e) {
-        const T v = ptv[e];
-        T rv[R];
-        vload<T, R>(r + (int64_t)ptc[e] * R, rv);
+        for (int k = 0; k < R; ++k) acc[k] = T(0);
+        spmv_row<T, R, false>(scol, sval, sptr[slice] + lane, slen[slice], r, nullptr, 1, acc);
 #pragma unroll
-        for (int k = 0; k < R; ++k) acc[k] += v * rv[k];
+        for (int k = 0; k < R; ++k) acc[k] *= r_scale;
+        vstore<T, R>(bc + row * R, acc);
     }
-#pragma unroll
-    for (int k = 0; k < R; ++k) acc[k] *= r_scale;
-    vstore<T, R>(bc + I * R, acc);
 }
 
-// x <- x - P x_c
+// x <- x - P x_c with P in sliced ELLPACK, rows [0, n)
 template <typename T, int R>
-__global__ void k_prolong(int64_t n, const int32_t *__restrict__ pp, const int32_t *__restrict__ pc,
-                          const T *__restrict__ pv, const T *__restrict__ xc, T *__restrict__ x) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    T acc[R];
-    vload<T, R>(x + i * R, acc);
-    for (int e = pp[i]; e < pp[i + 1]; ++e) {
-        const T v = pv[e];
-        T cv[R];
-        vload<T, R>(xc + (int64_t)pc[e] * R, cv);
+__global__ __launch_bounds__(WG) void k_prolong_sell(int64_t n, int64_t nslices, const int64_t *__restrict__ sptr,
+                                                     const int32_t *__restrict__ slen,
+                                                     const int32_t *__restrict__ scol, const T *__restrict__ sval,
+                                                     const T *__restrict__ xc, T *__restrict__ x) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const Tiles tl = my_tiles((nslices + 3) / 4);
+    for (int64_t tile = tl.t; tile < tl.end; tile += tl.step) {
+        const int64_t slice = tile * 4 + wv;
+        const int64_t row = slice * 64 + lane;
+        if (slice >= nslices || row >= n) continue;
+        T acc[R];
 #pragma unroll
-        for (int k = 0; k < R; ++k) acc[k] -= v * cv[k];
+        for (int k = 0; k < R; ++k) acc[k] = T(0);
+        spmv_row<T, R, false>(scol, sval, sptr[slice] + lane, slen[slice], xc, nullptr, 1, acc);
+        T xo[R];
+        vload<T, R>(x + row * R, xo);
+#pragma unroll
+        for (int k = 0; k < R; ++k) xo[k] -= acc[k];
+        vstore<T, R>(x + row * R, xo);
     }
-    vstore<T, R>(x + i * R, acc);
 }
+
 
 // Direct segments: x[i] = sum_j inv_q[i - s_q][j] b[s_q + j] for the rows
 // [n_active, n), with inv_q the FP64 inverse of the diagonal block of segment q
@@ -1558,8 +1567,10 @@ void vcycle_level(Ctx &c, int l) {
             hipLaunchKernelGGL((k_residual<T, R>), dim3(tile_grid(c, L.act_slices)), dim3(WG), 0, c.stream, na,
                                L.act_slices, L.sell.slice_ptr.get(), L.sell.slice_len.get(), L.sell.col.get(),
                                sell_val<T>(L.sell), bb, x, rr);
-        hipLaunchKernelGGL((k_restrict<T, R>), dim3(grid_for(L.nc)), dim3(WG), 0, c.stream, L.nc, L.pt_ptr.get(),
-                           L.pt_col.get(), pval<T>(L, true), (T)L.r_scale, rr, reinterpret_cast<T *>(C.bb.get()));
+        hipLaunchKernelGGL((k_restrict_sell<T, R>), dim3(tile_grid(c, L.ptsell.nslices)), dim3(WG), 0, c.stream,
+                           L.nc, L.ptsell.nslices, L.ptsell.slice_ptr.get(), L.ptsell.slice_len.get(),
+                           L.ptsell.col.get(), sell_val<T>(L.ptsell), (T)L.r_scale, rr,
+                           reinterpret_cast<T *>(C.bb.get()));
     }
     CS_LAUNCH_CHECK();
     trace_end(c, slot);
@@ -1568,8 +1579,9 @@ void vcycle_level(Ctx &c, int l) {
     const bool fuse_prol = fused && c.opt.mode == CS_ADDITIVE && c.opt.n_post > 0;
     if (!fuse_prol) {
         slot = trace_begin(c, CS_TRACE_PROLONG, L.p_nnz * (es + 4.0) + 2.0 * na * R * es + L.nc * R * es);
-        hipLaunchKernelGGL((k_prolong<T, R>), dim3(grid_for(na)), dim3(WG), 0, c.stream, na, L.p_ptr.get(),
-                           L.p_col.get(), pval<T>(L, false), xc, x);
+        hipLaunchKernelGGL((k_prolong_sell<T, R>), dim3(tile_grid(c, ceil_div(na, 64))), dim3(WG), 0, c.stream,
+                           na, ceil_div(na, 64), L.psell.slice_ptr.get(), L.psell.slice_len.get(), L.psell.col.get(),
+                           sell_val<T>(L.psell), xc, x);
         CS_LAUNCH_CHECK();
         trace_end(c, slot);
     }
