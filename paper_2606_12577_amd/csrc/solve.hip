@@ -240,12 +240,15 @@ __device__ __forceinline__ void spmv_row_blk(const int32_t *__restrict__ scol, c
 }
 
 // Natural-order SpMV row of a level with NB-blocks: the in-block shuffle form
-// for NB > 1 (xo: the row's own x, already loaded), else plain gathers.
+// (xo: the row's own x, already loaded) where it pays, i.e. for blocks of at
+// most 8 rows and gathered rows of at least 16 bytes (every entry costs the
+// shuffles of a whole x row, a saved gather only for in-block entries: with
+// one FP64 right-hand side, or 16 x 16 blocks, plain gathers measured faster).
 template <typename T, int R, bool PROL, int NB>
 __device__ __forceinline__ void spmv_row_nb(const int32_t *__restrict__ scol, const T *__restrict__ sval, int64_t off,
                                             int len, const T *xin, const T *xc, int agg_k, int64_t row, int lane,
                                             const T (&xo)[R], T (&acc)[R]) {
-    if constexpr (NB > 1)
+    if constexpr (NB > 1 && NB <= 8 && sizeof(T) * R >= 16)
         spmv_row_blk<T, R, PROL, NB>(scol, sval, off, len, xin, xc, agg_k, row, lane, xo, acc);
     else
         spmv_row<T, R, PROL>(scol, sval, off, len, xin, xc, agg_k, acc);
@@ -290,7 +293,7 @@ __global__ __launch_bounds__(WGS) void k_sweep(int64_t nrows, int64_t nslices, c
 #pragma unroll
         for (int k = 0; k < R; ++k) res[k] = -bb[k];
         if constexpr (!ZERO) {
-            if constexpr (NB > 1 && !ROWMAP)
+            if constexpr (NB > 1 && NB <= 8 && !ROWMAP && sizeof(T) * R >= 16)
                 spmv_row_blk<T, R, PROL, NB>(scol, sval, sptr[slice] + lane, slen[slice], xin, xc, agg_k, row,
                                              lane, xo, res);
             else
