@@ -713,3 +713,67 @@ def fit_local(A: sp.spmatrix, n: int, depth: int, centres: Sequence[int], mode: 
         res = fit(sub, n, depth, mode, None if colours is None else np.asarray(colours)[S])
         out[int(c)] = [L[pos] for L in res["lam"]]
     return out
+
+
+# ---------------------------------------------------------------------------
+# Stencil repetition (Sec. 5, caching repeated local setups on structured meshes)
+# ---------------------------------------------------------------------------
+
+def lattice_row_signatures(A: sp.spmatrix, n: int, coords: np.ndarray) -> List[bytes]:
+    """Byte signature of every block row of A seen from its own lattice point:
+    for each block column c of row k (in order of the offset coords[c] -
+    coords[k]), the offset, the n x n block A_kc and the n diagonal entries of
+    A_cc.  Two rows with equal signatures have equal prescaled rows
+    W A W (W = diag(A)^{-1/2}) under the translation of their lattice points."""
+    A = sp.csr_matrix(A)
+    A.sort_indices()
+    coords = np.asarray(coords, dtype=np.int64)
+    B = A.shape[0] // n
+    Apat = block_pattern(A, n)
+    diag = A.diagonal()
+    sig = []
+    for k in range(B):
+        cols = Apat.indices[Apat.indptr[k]:Apat.indptr[k + 1]]
+        parts = []
+        for c in cols:
+            blk = A[k * n:(k + 1) * n, c * n:(c + 1) * n].toarray()
+            off = tuple(int(v) for v in coords[c] - coords[k])
+            parts.append((off, blk.tobytes() + diag[c * n:(c + 1) * n].tobytes()))
+        parts.sort(key=lambda p: p[0])
+        sig.append(repr([p[0] for p in parts]).encode() + b"|" + b"".join(p[1] for p in parts))
+    return sig
+
+
+def lattice_classes(A: sp.spmatrix, n: int, coords: np.ndarray, radius: int) -> np.ndarray:
+    """rep[i] = the smallest block j such that translating the lattice by
+    t = coords[j] - coords[i] maps every block k within block-graph distance
+    `radius` of i onto a block k' (coords[k'] = coords[k] + t) whose row
+    signature equals that of k.  By the dependence stated in fit_local, the
+    cascade step l (Lambda_l and the residual row E_l) of every block equals
+    that of its representative at radius l - 1, up to the rounding order of
+    the sums (the columns are relabelled by the translation)."""
+    A = sp.csr_matrix(A)
+    coords = np.asarray(coords, dtype=np.int64)
+    B = A.shape[0] // n
+    Apat = block_pattern(A, n)
+    sig = lattice_row_signatures(A, n, coords)
+    at = {tuple(int(v) for v in coords[k]): k for k in range(B)}
+    if len(at) != B:
+        raise ValueError("lattice points must be distinct")
+    balls = [block_ball(Apat, i, radius) for i in range(B)]
+    rep = np.arange(B, dtype=np.int64)
+    for i in range(B):
+        for j in range(i):
+            if rep[j] != j:
+                continue
+            t = coords[j] - coords[i]
+            ok = True
+            for k in balls[i]:
+                kk = at.get(tuple(int(v) for v in coords[k] + t))
+                if kk is None or sig[kk] != sig[k]:
+                    ok = False
+                    break
+            if ok:
+                rep[i] = j
+                break
+    return rep

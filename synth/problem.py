@@ -34,6 +34,22 @@ class Level:
     def n_blocks(self) -> int:
         return self.A.shape[0] // self.block_size
 
+    def block_lattice(self) -> np.ndarray:
+        """Integer lattice point of every block, (n_blocks, d): the grid
+        coordinates of its cells divided by the block edge (cells must be set
+        and every block must be a cube of cells)."""
+        if self.cells is None:
+            raise ValueError("level has no cell numbering")
+        d = self.cells.ndim
+        edge = int(round(self.block_size ** (1.0 / d)))
+        if edge ** d != self.block_size:
+            raise ValueError("blocks are not cubes of cells")
+        coords = np.indices(self.cells.shape).reshape(d, -1).T
+        blk = self.cells.ravel() // self.block_size
+        out = np.empty((self.n_blocks, d), dtype=np.int32)
+        out[blk] = coords // edge
+        return out
+
 
 @dataclass
 class Problem:

@@ -892,3 +892,72 @@ def test_overlapping_identity_sketch_and_convergence():
     x, h = O.gmres(p.levels[0].A, lambda r: O.vcycle(p.levels, sm, r, "FF"), p.rhs, restart=30, rtol=1e-10,
                    maxit=60)
     assert h[-1] <= 1e-10 and O.rho_regression(h) < 0.15
+
+
+# ---------------------------------------------------------------------------
+# Stencil repetition (Sec. 5): translation classes of block neighbourhoods
+# ---------------------------------------------------------------------------
+
+def _disk_problem(n=48, bs=2, contrast=100.0):
+    x = (np.arange(n) + 0.5) / n
+    X, Y = np.meshgrid(x, x, indexing="ij")
+    mu = np.where((X - 0.45) ** 2 + (Y - 0.55) ** 2 < 0.2 ** 2, contrast, 1.0)
+    return fd.fv_hierarchy(mu, bs=bs, n_stop=n, order="lex")[0]
+
+
+@pytest.mark.parametrize("r", [0, 1, 2, 3])
+def test_lattice_classes_constant_poisson_closed_forms(r):
+    """5-point Dirichlet Poisson on a 16^2 grid: a cell's row differs from the
+    bulk when it or a neighbour touches the boundary (cells 0, 1, n-2, n-1 of
+    an axis), so the class of a cell at radius r is fixed by its distance to
+    each side capped at r + 2: (2r + 5)^2 classes, and the bulk class is the
+    (n - 4 - 2r)^2 cells with both coordinates in [2 + r, n - 3 - r]."""
+    n = 16
+    L = fd.poisson2d(n, n_stop=n).levels[0]
+    coords = L.block_lattice()
+    rep = O.lattice_classes(L.A, 1, coords, r)
+    assert len(np.unique(rep)) == (2 * r + 5) ** 2
+    inner = np.all((coords >= 2 + r) & (coords <= n - 3 - r), axis=1)
+    assert inner.sum() == (n - 4 - 2 * r) ** 2
+    assert len(np.unique(rep[inner])) == 1
+    assert not np.any(rep[~inner] == rep[inner][0])
+    # every representative is the smallest index of its class
+    assert np.all(rep <= np.arange(len(rep))) and np.all(rep[rep] == rep)
+
+
+def test_lattice_classes_fix_the_cascade_fit():
+    """Blocks in one class at radius l - 1 get the same Lambda_l from the plain
+    fit (the fit of a block reads the rows within l - 1 block layers, as the
+    local-patch pin above fixes); classes at radius l - 2 do not suffice."""
+    L = _disk_problem()
+    coords = L.block_lattice()
+    res = O.fit_additive(L.A, 4, 3)
+    for ell in (1, 2, 3):
+        lam = res["lam_tilde"][ell - 1]
+        rep = O.lattice_classes(L.A, 4, coords, ell - 1)
+        members = np.nonzero(rep != np.arange(len(rep)))[0]
+        assert len(members) > 100
+        scale = np.abs(lam).max()
+        assert np.abs(lam[members] - lam[rep[members]]).max() <= 1e-12 * scale
+        if ell > 1:
+            short = O.lattice_classes(L.A, 4, coords, ell - 2)
+            m2 = np.nonzero(short != np.arange(len(short)))[0]
+            assert np.abs(lam[m2] - lam[short[m2]]).max() > 1e-8 * scale
+
+
+def test_lattice_classes_independent_of_block_order():
+    """Renumbering the blocks (with their lattice points) renumbers the classes."""
+    L = fd.poisson2d(16, n_stop=16).levels[0]
+    coords = L.block_lattice()
+    B = coords.shape[0]
+    perm = stream(0, TEST, 71).permutation(B)      # new index of old block i is perm[i]
+    Pm = sp.csr_matrix((np.ones(B), (perm, np.arange(B))), shape=(B, B))
+    A2 = (Pm @ L.A @ Pm.T).tocsr()
+    c2 = np.empty_like(coords)
+    c2[perm] = coords
+    for r in (1, 3):
+        rep = O.lattice_classes(L.A, 1, coords, r)
+        rep2 = O.lattice_classes(A2, 1, c2, r)
+        same = rep[:, None] == rep[None, :]
+        same2 = rep2[perm][:, None] == rep2[perm][None, :]
+        assert np.array_equal(same, same2)
