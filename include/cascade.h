@@ -243,6 +243,33 @@ cs_status cs_set_overlapping_blocks(cs_ctx ctx, int32_t level, int64_t n_blocks,
  * without a positive diagonal or a pressure row coupled to no velocity. */
 cs_status cs_set_saddle_point(cs_ctx ctx, int32_t level, const int32_t *kind, int32_t l1);
 
+/* Stencil-repetition setup cache (Sec. 5, caching the repeated local setups of
+ * structured meshes).  coords (host int32[n_blocks][dim], dim 1..3, each
+ * coordinate in (-2^28, 2^28), bounding box at most 2^28 points) places every
+ * block of `level` at a distinct integer lattice point; the library keeps a
+ * copy.  cs_setup then sorts the smoothed blocks into translation classes: at
+ * radius r two blocks are equivalent when the lattice translation between them
+ * maps every block within r block layers of one onto a block with the same row
+ * of A (block-column offsets, stored non-zero values, diagonals of the column
+ * blocks).  Cascade step l of a block reads A within l - 1 layers, so only the
+ * smallest block of every class at radius l - 1 is fitted; the others copy its
+ * Lambda~_l and its residual row E_l with the block columns translated.  The
+ * result equals the uncached fit up to the rounding order of the row sums.
+ * Used by cs_setup for additive cascades without truncation on elliptic levels
+ * without overlapping blocks; elsewhere (and by the sketched and learned
+ * setups) every block is fitted.  coords = NULL removes the lattice.
+ * CS_EINVAL for a bad dim, coordinates out of range or repeated, or a box too
+ * large; at setup, for a residual row above 2048 blocks. */
+cs_status cs_set_lattice(cs_ctx ctx, int32_t level, int32_t dim, const int32_t *coords);
+
+/* After an exact setup (cs_setup) of `level`: fitted (host int64[depth]) = the
+ * blocks fitted at cascade step l (all smoothed blocks without a lattice);
+ * rep (host int32[depth][n_blocks], may be NULL) = the smallest block of every
+ * block's translation class at radius l - 1 (each block itself without a
+ * lattice).  CS_ESTATE when the last setup of the level was sketched, learned
+ * or over overlapping blocks. */
+cs_status cs_get_lattice_stats(cs_ctx ctx, int32_t level, int64_t *fitted, int32_t *rep);
+
 /* Pick the launch schedule of every level's cascade sweeps by measurement
  * (needs a setup): for the current working precision and nrhs, one cascade
  * application per level is timed for each candidate schedule (64 or 256 rows

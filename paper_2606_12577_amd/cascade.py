@@ -79,6 +79,8 @@ SIGNATURES = {
     "cs_autotune": (_I32, [_VP, _I32, _p(_I32), _p(_I64), _p(_D)]),
     "cs_setup_sketched": (_I32, [_VP, _p(cs_options), _I32, _VP]),
     "cs_set_saddle_point": (_I32, [_VP, _I32, _p(_I32), _I32]),
+    "cs_set_lattice": (_I32, [_VP, _I32, _I32, _p(_I32)]),
+    "cs_get_lattice_stats": (_I32, [_VP, _I32, _p(_I64), _p(_I32)]),
     "cs_set_overlapping_blocks": (_I32, [_VP, _I32, _I64, _I32, _p(_I32)]),
     "cs_trace": (_I32, [_VP, _I32, _I32]),
     "cs_trace_read": (_I32, [_VP, _I32, _p(_D), _p(_I64), _p(_D)]),
@@ -255,6 +257,28 @@ class Solver:
             return
         k = _arr(kind, np.int32)
         self._check(self._lib.cs_set_saddle_point(self._h, level, _ptr(k, _I32), int(bool(l1))))
+
+    def set_lattice(self, level: int, coords=None):
+        """Stencil-repetition cache for a level (Sec. 5): coords (n_blocks x
+        dim integer lattice points, distinct) lets the exact additive setup fit
+        one block per class of translation-equivalent neighbourhoods and copy
+        the rest.  None removes it."""
+        if coords is None:
+            self._check(self._lib.cs_set_lattice(self._h, level, 0, None))
+            return
+        c = _arr(np.asarray(coords).reshape(self.sizes[level][0] // self.sizes[level][1], -1), np.int32)
+        self._check(self._lib.cs_set_lattice(self._h, level, c.shape[1], _ptr(c, _I32)))
+
+    def lattice_stats(self, level: int, classes: bool = False):
+        """Blocks fitted per cascade step by the last exact setup of a level
+        and, with classes=True, the class representatives (depth x n_blocks,
+        radius l - 1 for step l)."""
+        depth = getattr(self, "depth", 1)   # before any setup the library reports the state error
+        fitted = np.zeros(depth, dtype=np.int64)
+        rep = np.zeros((depth, self.sizes[level][0] // self.sizes[level][1]), dtype=np.int32) if classes else None
+        self._check(self._lib.cs_get_lattice_stats(self._h, level, _ptr(fitted, _I64),
+                                                   _ptr(rep, _I32) if classes else None))
+        return (fitted, rep) if classes else fitted
 
     def setup(self, depth: int = 3, mode: str = "additive", order: str = "RF", n_pre: int = 1,
               n_post: int = 1, alpha: int = 0, precision: str = "fp64"):

@@ -552,6 +552,81 @@ cs_status cs_set_saddle_point(cs_ctx ctx, int32_t level, const int32_t *kind, in
     });
 }
 
+cs_status cs_set_lattice(cs_ctx ctx, int32_t level, int32_t dim, const int32_t *coords) {
+    return guarded(ctx, [&](Ctx &c) {
+        need(c.have_hierarchy, "cs_set_lattice before cs_set_hierarchy", CS_ESTATE);
+        need(level >= 0 && level + 1 < (int32_t)c.lv.size(), "level has no smoother");
+        Level &L = c.lv[level];
+        if (!coords) {
+            L.lat_dim = 0;
+            L.lat_xyz.release();
+            L.lat_map.release();
+            return;
+        }
+        need(dim >= 1 && dim <= 3, "lattice dimension must be 1, 2 or 3");
+        const int64_t B = L.B;
+        constexpr int32_t LIM = 1 << 28;
+        int32_t lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+        for (int d = 0; d < dim; ++d) {
+            lo[d] = INT32_MAX;
+            hi[d] = INT32_MIN;
+        }
+        for (int64_t b = 0; b < B; ++b)
+            for (int d = 0; d < dim; ++d) {
+                const int32_t v = coords[b * dim + d];
+                need(v > -LIM && v < LIM, "lattice coordinates must lie in (-2^28, 2^28)");
+                lo[d] = std::min(lo[d], v);
+                hi[d] = std::max(hi[d], v);
+            }
+        int32_t ext[3] = {1, 1, 1};
+        int64_t vol = 1;
+        for (int d = 0; d < dim; ++d) {
+            ext[d] = hi[d] - lo[d] + 1;
+            vol *= ext[d];
+            need(vol <= (int64_t)LIM, "bounding box of the lattice points above 2^28 points");
+        }
+        std::vector<int32_t> map((size_t)vol, -1), xyz((size_t)B * 3, 0);
+        for (int64_t b = 0; b < B; ++b) {
+            int64_t idx = 0;
+            for (int d = dim - 1; d >= 0; --d) {
+                const int32_t v = coords[b * dim + d];
+                xyz[(size_t)b * 3 + d] = v;
+                idx = idx * ext[d] + (v - lo[d]);
+            }
+            need(map[(size_t)idx] < 0, "lattice points must be distinct");
+            map[(size_t)idx] = (int32_t)b;
+        }
+        L.lat_xyz.upload(xyz.data(), xyz.size(), c.stream);
+        L.lat_map.upload(map.data(), map.size(), c.stream);
+        for (int d = 0; d < 3; ++d) {
+            L.lat_lo[d] = lo[d];
+            L.lat_ext[d] = ext[d];
+        }
+        L.lat_dim = dim;
+        CS_HIP(hipStreamSynchronize(c.stream));
+    });
+}
+
+cs_status cs_get_lattice_stats(cs_ctx ctx, int32_t level, int64_t *fitted, int32_t *rep) {
+    return guarded(ctx, [&](Ctx &c) {
+        need(c.have_setup, "no setup", CS_ESTATE);
+        need(level >= 0 && level + 1 < (int32_t)c.lv.size() && fitted, "level has no smoother");
+        Level &L = c.lv[level];
+        need(L.lat_fitted.size() == (size_t)L.depth, "the last setup of this level was not an exact block fit",
+             CS_ESTATE);
+        std::copy(L.lat_fitted.begin(), L.lat_fitted.end(), fitted);
+        if (!rep) return;
+        const size_t B = (size_t)L.B;
+        if (L.lat_rep.get()) {
+            L.lat_rep.download(rep, (size_t)L.depth * B, c.stream);
+            CS_HIP(hipStreamSynchronize(c.stream));
+        } else {
+            for (int e = 0; e < L.depth; ++e)
+                for (size_t b = 0; b < B; ++b) rep[e * B + b] = (int32_t)b;
+        }
+    });
+}
+
 cs_status cs_autotune(cs_ctx ctx, int32_t nrhs, int32_t *wgs, int64_t *grid, double *ms) {
     return guarded(ctx, [&](Ctx &c) {
         need(c.have_setup, "autotune before cs_setup", CS_ESTATE);

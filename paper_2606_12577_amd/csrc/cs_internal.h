@@ -128,6 +128,14 @@ struct Level {
     DBuf<int32_t> ovl_nodes, ovl_inv_ptr, ovl_inv_idx;
     DBuf<double> ovl_rtheta;
     DBuf<unsigned char> ovl_y;        // replicated workspace [nblk][m][R] (working precision)
+    // stencil-repetition cache (Sec. 5): lattice point of every block (lat_dim
+    // 0: none), the box map point -> block, and of the last exact fit the class
+    // representatives [depth][B] (radius ell - 1 for cascade step ell) and the
+    // blocks fitted per step
+    int lat_dim = 0;
+    int32_t lat_lo[3] = {0, 0, 0}, lat_ext[3] = {1, 1, 1};
+    DBuf<int32_t> lat_xyz, lat_map, lat_rep;
+    std::vector<int64_t> lat_fitted;
     // sweep launch schedule picked by the autotuner (0: the size rule)
     int tune_wgs = 0;                 // rows per workgroup: 64 or 256
     int64_t tune_grid = 0;            // workgroups (the kernels loop over the remaining tiles)

@@ -1263,6 +1263,7 @@ __global__ __launch_bounds__(WG) void k_eupdate(int B, int nb, const int32_t *__
     const int t = threadIdx.x;
     const int nb2 = nb * nb;
     const int li = pos_in_list[i];
+    if (li == -2) return;   // member of a lattice class: translated from its representative
     const int elo = eptr[i], ek = eptr[i + 1] - elo;
     const int nlo = nptr[i];
     if (li < 0) {
@@ -1427,11 +1428,14 @@ __global__ __launch_bounds__(WG) void k_reduce_i32(int64_t n, const int32_t *__r
 }
 
 // block-row lengths of the updated E: list rows take |pattern(M_i)|, the others keep |pattern(E_i)|
-__global__ void k_ecount(int B, const int32_t *__restrict__ pos, const int32_t *__restrict__ mptr,
-                         const int32_t *__restrict__ eptr, int32_t *__restrict__ cnt) {
+// (members of a lattice class, pos -2, take the length of their representative's new row)
+__global__ void k_ecount(int B, const int32_t *__restrict__ pos, const int32_t *__restrict__ rep,
+                         const int32_t *__restrict__ mptr, const int32_t *__restrict__ eptr,
+                         int32_t *__restrict__ cnt) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= B) return;
-    const int q = pos[i];
+    int q = pos[i];
+    if (q == -2) q = pos[rep[i]];
     cnt[i] = q >= 0 ? mptr[q + 1] - mptr[q] : eptr[i + 1] - eptr[i];
 }
 
@@ -1580,6 +1584,261 @@ __global__ void k_transpose_blocks64(int64_t nblk, int nb, const double *__restr
 __global__ void k_cast32(int64_t n, const double *__restrict__ a, float *__restrict__ b) {
     int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (e < n) b[e] = (float)a[e];
+}
+
+// ---------------------------------------------------------------------------
+// Stencil-repetition cache (Sec. 5): blocks at integer lattice points whose
+// neighbourhoods coincide under translation share one cascade fit.  Classes
+// are refined one block layer per round: round 0 compares the block rows of A
+// (offsets to the block columns, the stored values, the diagonals of the
+// column blocks), round r the class of the row at round r - 1 and those of
+// its neighbours, by offset.  A 64-bit key per block finds a candidate (the
+// smallest block with the same key, through an open-addressing table); the
+// candidate is then checked exactly, so a key collision only costs sharing.
+// ---------------------------------------------------------------------------
+struct LatDev {
+    const int32_t *xyz;   // [B][3] lattice points (unused axes 0)
+    const int32_t *map;   // bounding box point -> block, -1 where none
+    int32_t lo0, lo1, lo2, ex0, ex1, ex2;
+};
+
+constexpr uint64_t LAT_EMPTY = ~0ull;
+constexpr int LAT_ROW_CAP = 2048;   // blocks per residual row that the translation copy holds in LDS
+
+// SplitMix64 output mixing (Steele, Lea and Flood, 2014)
+__device__ inline uint64_t mix64(uint64_t z) {
+    z ^= z >> 30;
+    z *= 0xbf58476d1ce4e5b9ull;
+    z ^= z >> 27;
+    z *= 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__device__ inline uint64_t dbits(double v) { return (uint64_t)__double_as_longlong(v); }
+
+__device__ inline uint64_t lat_offset_key(const LatDev &L, int c, int k) {
+    const int32_t *pc = L.xyz + 3 * (int64_t)c, *pk = L.xyz + 3 * (int64_t)k;
+    return mix64(((uint64_t)(uint32_t)(pc[0] - pk[0])) ^ ((uint64_t)(uint32_t)(pc[1] - pk[1]) << 21) ^
+                 ((uint64_t)(uint32_t)(pc[2] - pk[2]) << 42));
+}
+
+// block at the lattice point of c moved by xyz[to] - xyz[from], or -1
+__device__ inline int lat_shift(const LatDev &L, int c, int from, int to) {
+    const int32_t *pc = L.xyz + 3 * (int64_t)c, *pf = L.xyz + 3 * (int64_t)from, *pt = L.xyz + 3 * (int64_t)to;
+    const int x = pc[0] - pf[0] + pt[0] - L.lo0, y = pc[1] - pf[1] + pt[1] - L.lo1, z = pc[2] - pf[2] + pt[2] - L.lo2;
+    if ((unsigned)x >= (unsigned)L.ex0 || (unsigned)y >= (unsigned)L.ex1 || (unsigned)z >= (unsigned)L.ex2) return -1;
+    return L.map[((int64_t)z * L.ex1 + y) * L.ex0 + x];
+}
+
+__device__ inline uint64_t lat_fix(uint64_t h) { return h == LAT_EMPTY ? h - 1 : h; }
+
+__device__ inline int lat_lookup(uint64_t h, int64_t T, const uint64_t *__restrict__ tk, const int32_t *__restrict__ tm) {
+    int64_t s = (int64_t)(h & (uint64_t)(T - 1));
+    while (tk[s] != h) s = (s + 1) & (T - 1);   // the key was inserted: the probe ends there
+    return tm[s];
+}
+
+__global__ void k_lat_diag(int64_t n, const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                           const double *__restrict__ val, double *__restrict__ diag) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int q = bsearch_i32(col, ptr[r], ptr[r + 1], (int32_t)r);
+    diag[r] = q >= 0 ? val[q] : 0.0;
+}
+
+// round 0 key: block columns (offset, diagonals) and stored non-zero-bit entries
+// (offset, position in the block, value); a stored +0.0 counts as absent
+__global__ void k_lat_key0(int B, int nb, const int32_t *__restrict__ bptr, const int32_t *__restrict__ bcol,
+                           const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                           const double *__restrict__ val, const double *__restrict__ diag, LatDev L,
+                           uint64_t *__restrict__ key) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= B) return;
+    uint64_t h = mix64((uint64_t)(bptr[k + 1] - bptr[k]));
+    for (int e = bptr[k]; e < bptr[k + 1]; ++e) {
+        const int c = bcol[e];
+        uint64_t t = lat_offset_key(L, c, k);
+        for (int s = 0; s < nb; ++s) t = mix64(t ^ dbits(diag[(int64_t)c * nb + s]));
+        h += t;
+    }
+    for (int q = 0; q < nb; ++q) {
+        const int64_t r = (int64_t)k * nb + q;
+        for (int e = ptr[r]; e < ptr[r + 1]; ++e) {
+            const uint64_t v = dbits(val[e]);
+            if (!v) continue;
+            const int j = col[e];
+            h += mix64(lat_offset_key(L, j / nb, k) ^ mix64(0x9e3779b97f4a7c15ull * (uint64_t)(q * nb + j % nb + 1)) ^
+                       v);
+        }
+    }
+    key[k] = lat_fix(mix64(h));
+}
+
+// round r > 0 key: own class and the classes of the neighbours, by offset
+__global__ void k_lat_key(int B, const int32_t *__restrict__ bptr, const int32_t *__restrict__ bcol, LatDev L,
+                          const int32_t *__restrict__ prev, uint64_t *__restrict__ key) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= B) return;
+    uint64_t h = mix64((uint64_t)prev[k] + 0x632be59bd9b4e019ull);
+    for (int e = bptr[k]; e < bptr[k + 1]; ++e) {
+        const int c = bcol[e];
+        h += mix64(lat_offset_key(L, c, k) ^ (uint64_t)(uint32_t)prev[c]);
+    }
+    key[k] = lat_fix(mix64(h));
+}
+
+__global__ void k_lat_clear(int64_t T, uint64_t *__restrict__ tk, int32_t *__restrict__ tm) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= T) return;
+    tk[s] = LAT_EMPTY;
+    tm[s] = INT32_MAX;
+}
+
+// T > 2B slots: a free slot is always met, so the probe ends
+__global__ void k_lat_insert(int B, const uint64_t *__restrict__ key, int64_t T, uint64_t *__restrict__ tk,
+                             int32_t *__restrict__ tm) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= B) return;
+    const uint64_t h = key[k];
+    int64_t s = (int64_t)(h & (uint64_t)(T - 1));
+    for (;;) {
+        const unsigned long long prev =
+            atomicCAS((unsigned long long *)(tk + s), (unsigned long long)LAT_EMPTY, (unsigned long long)h);
+        if (prev == LAT_EMPTY || prev == h) {
+            atomicMin(tm + s, k);
+            return;
+        }
+        s = (s + 1) & (T - 1);
+    }
+}
+
+// same block pattern under the translation k -> r (and, for rounds > 0, the same
+// classes of the neighbours)
+__device__ inline bool lat_same_blocks(int k, int r, const int32_t *__restrict__ bptr,
+                                       const int32_t *__restrict__ bcol, const LatDev &L,
+                                       const int32_t *__restrict__ prev) {
+    if (bptr[k + 1] - bptr[k] != bptr[r + 1] - bptr[r]) return false;
+    for (int e = bptr[k]; e < bptr[k + 1]; ++e) {
+        const int c = bcol[e];
+        const int c2 = lat_shift(L, c, k, r);
+        if (c2 < 0 || bsearch_i32(bcol, bptr[r], bptr[r + 1], c2) < 0) return false;
+        if (prev && prev[c] != prev[c2]) return false;
+    }
+    return true;
+}
+
+__global__ void k_lat_rep0(int B, int nb, const int32_t *__restrict__ bptr, const int32_t *__restrict__ bcol,
+                           const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                           const double *__restrict__ val, const double *__restrict__ diag, LatDev L,
+                           const uint64_t *__restrict__ key, int64_t T, const uint64_t *__restrict__ tk,
+                           const int32_t *__restrict__ tm, int32_t *__restrict__ rep) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= B) return;
+    const int r = lat_lookup(key[k], T, tk, tm);
+    bool ok = r != k && lat_same_blocks(k, r, bptr, bcol, L, nullptr);
+    for (int e = bptr[k]; ok && e < bptr[k + 1]; ++e) {
+        const int c = bcol[e], c2 = lat_shift(L, c, k, r);
+        for (int s = 0; s < nb; ++s)
+            ok = ok && dbits(diag[(int64_t)c * nb + s]) == dbits(diag[(int64_t)c2 * nb + s]);
+    }
+    for (int q = 0; ok && q < nb; ++q) {
+        const int64_t rk = (int64_t)k * nb + q, rr = (int64_t)r * nb + q;
+        int nk = 0, nr = 0;
+        for (int e = ptr[rk]; e < ptr[rk + 1]; ++e) nk += dbits(val[e]) != 0;
+        for (int e = ptr[rr]; e < ptr[rr + 1]; ++e) nr += dbits(val[e]) != 0;
+        ok = nk == nr;
+        for (int e = ptr[rk]; ok && e < ptr[rk + 1]; ++e) {
+            const uint64_t v = dbits(val[e]);
+            if (!v) continue;
+            const int j = col[e];
+            const int c2 = lat_shift(L, j / nb, k, r);
+            const int p = c2 < 0 ? -1 : bsearch_i32(col, ptr[rr], ptr[rr + 1], c2 * nb + j % nb);
+            ok = p >= 0 && dbits(val[p]) == v;
+        }
+    }
+    rep[k] = ok ? r : k;
+}
+
+__global__ void k_lat_rep(int B, const int32_t *__restrict__ bptr, const int32_t *__restrict__ bcol, LatDev L,
+                          const int32_t *__restrict__ prev, const uint64_t *__restrict__ key, int64_t T,
+                          const uint64_t *__restrict__ tk, const int32_t *__restrict__ tm,
+                          int32_t *__restrict__ rep) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= B) return;
+    const int r = lat_lookup(key[k], T, tk, tm);
+    const bool ok = r != k && prev[k] == prev[r] && lat_same_blocks(k, r, bptr, bcol, L, prev);
+    rep[k] = ok ? r : k;
+}
+
+__global__ void k_lat_flag(int B, const int32_t *__restrict__ rep, int32_t *__restrict__ flag) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < B) flag[k] = rep[k] == k;
+}
+
+__global__ void k_lat_compact(int B, const int32_t *__restrict__ rep, const int32_t *__restrict__ off,
+                              int32_t *__restrict__ list) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < B && rep[k] == k) list[off[k]] = k;
+}
+
+// members of a class (rep != self) are marked -2 in pos_in_list
+__global__ void k_lat_mark(int B, const int32_t *__restrict__ rep, int32_t *__restrict__ pos) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < B && rep[k] != k) pos[k] = -2;
+}
+
+// Lambda~ of members from their representative; msing[k] = 1 for a member whose
+// representative took the pseudo-inverse fallback
+__global__ void k_lat_copy_lam(int B, int nb2, const int32_t *__restrict__ rep, const int32_t *__restrict__ pos,
+                               const int32_t *__restrict__ sing, double *__restrict__ lam,
+                               int32_t *__restrict__ msing) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= (int64_t)B * nb2) return;
+    const int k = (int)(e / nb2), rs = (int)(e % nb2);
+    const int r = rep[k];
+    if (r == k) {
+        if (rs == 0) msing[k] = 0;
+        return;
+    }
+    lam[e] = lam[(int64_t)r * nb2 + rs];
+    if (rs == 0) msing[k] = sing[pos[r]];
+}
+
+// Residual row of a member: the representative's new row with its block
+// columns moved by the translation, re-sorted by rank.
+__global__ __launch_bounds__(WG) void k_lat_etranslate(int B, int nb, const int32_t *__restrict__ pos,
+                                                       const int32_t *__restrict__ rep, LatDev L,
+                                                       const int32_t *__restrict__ nptr, int32_t *__restrict__ ncol,
+                                                       double *__restrict__ nval, int32_t *__restrict__ err) {
+    __shared__ int32_t tc[LAT_ROW_CAP];
+    __shared__ int32_t rk[LAT_ROW_CAP];
+    const int i = blockIdx.x;
+    if (i >= B || pos[i] != -2) return;
+    const int r = rep[i];
+    const int rlo = nptr[r], k = nptr[r + 1] - rlo, ilo = nptr[i];
+    const int nb2 = nb * nb;
+    if (k > LAT_ROW_CAP || k != nptr[i + 1] - ilo) {
+        if (threadIdx.x == 0) err[i] = 1;
+        return;
+    }
+    for (int p = threadIdx.x; p < k; p += WG) {
+        const int c = lat_shift(L, ncol[rlo + p], r, i);
+        if (c < 0) err[i] = 1;
+        tc[p] = c;
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < k; p += WG) {
+        const int v = tc[p];
+        int below = 0;
+        for (int q = 0; q < k; ++q) below += tc[q] < v;
+        rk[p] = below;
+        ncol[ilo + below] = v;
+    }
+    __syncthreads();
+    for (int64_t e = threadIdx.x; e < (int64_t)k * nb2; e += WG) {
+        const int p = (int)(e / nb2), rs = (int)(e % nb2);
+        nval[(int64_t)(ilo + rk[p]) * nb2 + rs] = nval[(int64_t)(rlo + p) * nb2 + rs];
+    }
 }
 
 inline unsigned grid_for(int64_t n, int wg = WG) { return (unsigned)ceil_div(n, wg); }
@@ -1922,6 +2181,62 @@ void prepare_level(Ctx &c, Level &L, const cs_options &o, bool need_ap, BPattern
     }
 }
 
+LatDev lat_dev(const Level &L) {
+    return LatDev{L.lat_xyz.get(), L.lat_map.get(), L.lat_lo[0], L.lat_lo[1], L.lat_lo[2],
+                  L.lat_ext[0],     L.lat_ext[1],    L.lat_ext[2]};
+}
+
+// Translation classes of the smoothed blocks at radius 0 .. depth - 1 into
+// L.lat_rep ([depth][B]; other blocks are their own representative) and, per
+// radius, the representatives in ascending order.
+void lattice_classes(Ctx &c, Level &L, const BPattern &ap, int depth, std::vector<DBuf<int32_t>> &lists,
+                     std::vector<int> &sizes) {
+    hipStream_t s = c.stream;
+    const int B = (int)L.B, nb = (int)L.nb;
+    const int Ba = (int)(L.n_active / L.nb);
+    const LatDev ld = lat_dev(L);
+    DBuf<double> diag(L.n);
+    hipLaunchKernelGGL(k_lat_diag, dim3(grid_for(L.n)), dim3(WG), 0, s, L.n, L.a_ptr.get(), L.a_col.get(),
+                       L.a_val.get(), diag.get());
+    int64_t T = 1;
+    while (T < 2 * (int64_t)std::max(Ba, 1) + 1) T <<= 1;
+    DBuf<uint64_t> tk(T), key(std::max(Ba, 1));
+    DBuf<int32_t> tm(T), flag(std::max(Ba, 1)), off;
+    DBuf<int64_t> tot(1);
+    L.lat_rep.alloc((size_t)depth * B);
+    lists.clear();
+    lists.resize(depth);
+    sizes.assign(depth, 0);
+    for (int r = 0; r < depth; ++r) {
+        int32_t *rep = L.lat_rep.get() + (size_t)r * B;
+        const int32_t *prev = r ? rep - B : nullptr;
+        hipLaunchKernelGGL(k_iota, dim3(grid_for(B)), dim3(WG), 0, s, rep, B);
+        CS_LAUNCH_CHECK();
+        if (!Ba) continue;
+        if (r == 0)
+            hipLaunchKernelGGL(k_lat_key0, dim3(grid_for(Ba)), dim3(WG), 0, s, Ba, nb, ap.ptr.get(), ap.col.get(),
+                               L.a_ptr.get(), L.a_col.get(), L.a_val.get(), diag.get(), ld, key.get());
+        else
+            hipLaunchKernelGGL(k_lat_key, dim3(grid_for(Ba)), dim3(WG), 0, s, Ba, ap.ptr.get(), ap.col.get(), ld,
+                               prev, key.get());
+        hipLaunchKernelGGL(k_lat_clear, dim3(grid_for(T)), dim3(WG), 0, s, T, tk.get(), tm.get());
+        hipLaunchKernelGGL(k_lat_insert, dim3(grid_for(Ba)), dim3(WG), 0, s, Ba, key.get(), T, tk.get(), tm.get());
+        if (r == 0)
+            hipLaunchKernelGGL(k_lat_rep0, dim3(grid_for(Ba)), dim3(WG), 0, s, Ba, nb, ap.ptr.get(), ap.col.get(),
+                               L.a_ptr.get(), L.a_col.get(), L.a_val.get(), diag.get(), ld, key.get(), T,
+                               tk.get(), tm.get(), rep);
+        else
+            hipLaunchKernelGGL(k_lat_rep, dim3(grid_for(Ba)), dim3(WG), 0, s, Ba, ap.ptr.get(), ap.col.get(), ld,
+                               prev, key.get(), T, tk.get(), tm.get(), rep);
+        hipLaunchKernelGGL(k_lat_flag, dim3(grid_for(Ba)), dim3(WG), 0, s, Ba, rep, flag.get());
+        CS_LAUNCH_CHECK();
+        sizes[r] = (int)scan_counts(c, flag, Ba, off, tot);
+        lists[r].alloc(std::max(sizes[r], 1));
+        hipLaunchKernelGGL(k_lat_compact, dim3(grid_for(Ba)), dim3(WG), 0, s, Ba, rep, off.get(), lists[r].get());
+        CS_LAUNCH_CHECK();
+    }
+}
+
 void fit_level_overlap_exact(Ctx &c, Level &L, const cs_options &o);
 
 void fit_level(Ctx &c, Level &L, const cs_options &o) {
@@ -1936,6 +2251,20 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
     FitLists fl;
     prepare_level(c, L, o, true, ap, fl);
     const auto &lists = fl.lists;
+    // stencil-repetition cache: fit one block per translation class
+    const int B_act = (int)(L.n_active / L.nb);
+    const bool lattice = L.lat_dim > 0 && o.mode == CS_ADDITIVE && o.trunc_alpha == 0 && !L.kind.get();
+    std::vector<DBuf<int32_t>> lat_lists;
+    std::vector<int> lat_sizes;
+    L.lat_rep.release();
+    L.lat_fitted.assign(depth, B_act);
+    DBuf<int32_t> msing;
+    if (lattice) {
+        lattice_classes(c, L, ap, depth, lat_lists, lat_sizes);
+        for (int ell = 0; ell < depth; ++ell) L.lat_fitted[ell] = lat_sizes[ell];
+        msing.alloc(B);
+    }
+    const LatDev ld = lat_dev(L);
     // the prescaled dense blocks of A
     DBuf<double> abval(ap.nnzb * nb2);
     CS_HIP(hipMemsetAsync(abval.get(), 0, abval.bytes(), s));
@@ -1975,10 +2304,17 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
     for (int ell = 1; ell <= depth; ++ell) {
         for (size_t kcol = 0; kcol < lists.size(); ++kcol, ++step) {
             const int32_t *dlist = lists[kcol].first;
-            const int nl = lists[kcol].second;
+            int nl = lists[kcol].second;
+            const int32_t *lrep = nullptr;   // class representatives at radius ell - 1
+            if (lattice) {
+                dlist = lat_lists[ell - 1].get();
+                nl = lat_sizes[ell - 1];
+                lrep = L.lat_rep.get() + (size_t)(ell - 1) * B;
+            }
             if (nl == 0) continue;
             hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(B)), dim3(WG), 0, s, pos.get(), (int64_t)B, -1);
             hipLaunchKernelGGL(k_pos_in_list, dim3(grid_for(nl)), dim3(WG), 0, s, dlist, nl, pos.get());
+            if (lrep) hipLaunchKernelGGL(k_lat_mark, dim3(grid_for(B)), dim3(WG), 0, s, B, lrep, pos.get());
             hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(B)), dim3(WG), 0, s, err.get(), (int64_t)B, 0);
             // symbolic: pattern(M_i) for the list rows
             cnt.alloc(nl);
@@ -2017,11 +2353,17 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
                                    sing.get());
             CS_LAUNCH_CHECK();
             L.singular += reduce_i32(c, sing.get(), nl, true);
+            if (lrep) {
+                hipLaunchKernelGGL(k_lat_copy_lam, dim3(grid_for((int64_t)B * nb2)), dim3(WG), 0, s, B, nb2, lrep,
+                                   pos.get(), sing.get(), lam_l, msing.get());
+                CS_LAUNCH_CHECK();
+                L.singular += reduce_i32(c, msing.get(), B, true);
+            }
             if (step + 1 == nsteps) break;   // the last residual is never needed
             // E update on pattern(M) for list rows, copy for others
             {
                 DBuf<int32_t> ncnt(B);
-                hipLaunchKernelGGL(k_ecount, dim3(grid_for(B)), dim3(WG), 0, s, B, pos.get(), mp.ptr.get(),
+                hipLaunchKernelGGL(k_ecount, dim3(grid_for(B)), dim3(WG), 0, s, B, pos.get(), lrep, mp.ptr.get(),
                                    E.pat.ptr.get(), ncnt.get());
                 CS_LAUNCH_CHECK();
                 EMat N;
@@ -2033,6 +2375,15 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
                                    mval.get(), E.pat.ptr.get(), E.pat.col.get(), E.val.get(), lam_l, N.pat.ptr.get(),
                                    N.pat.col.get(), N.val.get());
                 CS_LAUNCH_CHECK();
+                if (lrep) {
+                    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(B)), dim3(WG), 0, s, err.get(), (int64_t)B, 0);
+                    hipLaunchKernelGGL(k_lat_etranslate, dim3(B), dim3(WG), 0, s, B, nb, pos.get(), lrep, ld,
+                                       N.pat.ptr.get(), N.pat.col.get(), N.val.get(), err.get());
+                    CS_LAUNCH_CHECK();
+                    if (reduce_i32(c, err.get(), B, false))
+                        fail(CS_EINVAL, "a residual row of a lattice class could not be translated (row above " +
+                                            std::to_string(LAT_ROW_CAP) + " blocks, or a neighbour off the lattice)");
+                }
                 mval.release();
                 if (o.trunc_alpha > 0) {
                     DBuf<int32_t> tcnt(B);
@@ -2073,6 +2424,8 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
 // and the point row product), the blockwise normal equations over the slots,
 // and E_new = diag(theta)^{-1} Theta^T (Theta E - Lambda~ Theta M) row by row.
 void fit_level_overlap_exact(Ctx &c, Level &L, const cs_options &o) {
+    L.lat_fitted.clear();
+    L.lat_rep.release();
     hipStream_t s = c.stream;
     const int depth = o.depth, m = L.ovl_m;
     const int64_t n = L.n, nblk = L.ovl_nblk, m2 = (int64_t)m * m;
@@ -2355,6 +2708,10 @@ void run_setup(Ctx &c, const cs_options &o) {
 void run_setup_sketched(Ctx &c, const cs_options &o, int sk, const double *S) {
     CS_HIP(hipEventRecord(c.ev0, c.stream));
     c.singular = 0;
+    for (Level &L : c.lv) {   // no exact block fit: no class statistics
+        L.lat_fitted.clear();
+        L.lat_rep.release();
+    }
     size_t off = 0;
     for (size_t l = 0; l + 1 < c.lv.size(); ++l) {
         fit_level_sketched(c, c.lv[l], o, S + off, sk);
@@ -2401,6 +2758,8 @@ void run_setup_learned(Ctx &c, const cs_options &o, const float *lam_t) {
     L0.patterns.clear();
     L0.singular = 0;
     L0.chi = 1;
+    L0.lat_fitted.clear();
+    L0.lat_rep.release();
     c.singular = 0;
     for (size_t l = 1; l + 1 < c.lv.size(); ++l) {
         fit_level(c, c.lv[l], o);
