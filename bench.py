@@ -221,6 +221,8 @@ def main():
                          "GMRES or flexible GMRES around the V-cycle")
     ap.add_argument("--sketch-width", type=int, default=32,
                     help="also measure the sketched setup with this many modes (0: skip)")
+    ap.add_argument("--no-lattice", action="store_true",
+                    help="skip the exact setup with the stencil-repetition cache")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-system measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-setup measurement")
     ap.add_argument("--no-stokes", action="store_true", help="skip the Stokes (MAC) measurement")
@@ -338,6 +340,25 @@ def main():
             rho=round(sk["rho"], 4), rel_res=sk["rel_res"],
             setup_plus_solve_dof_per_s=dof / ((sk["setup_ms"] + sk["solve_ms"]) * 1e-3),
             setup_speedup_vs_exact=round(setup_ms / sk["setup_ms"], 2))
+    # exact fit with the stencil-repetition cache (Sec. 5): one fit per translation class of blocks
+    if not args.no_lattice:
+        for l, lv in enumerate(prob.levels[:-1]):
+            s.set_lattice(l, lv.block_lattice())
+        lts = []
+        for _ in range(2):
+            s.setup(**opts)
+            lts.append(s.solve(b, rtol=args.rtol, maxit=args.maxit, method=args.solver)[1])
+        lt = lts[-1]
+        nblk = [lv.n_blocks for lv in prob.levels[:-1]]
+        fitted = [s.lattice_stats(l).tolist() for l in range(len(nblk))]
+        extra[f"lattice_cache_{args.solver}"] = dict(
+            setup_ms=round(lt["setup_ms"], 2), solve_ms=round(lt["solve_ms"], 3), iterations=lt["iterations"],
+            rho=round(lt["rho"], 4), rel_res=lt["rel_res"],
+            setup_plus_solve_dof_per_s=dof / ((lt["setup_ms"] + lt["solve_ms"]) * 1e-3),
+            setup_speedup_vs_exact=round(setup_ms / lt["setup_ms"], 2),
+            fitted_fraction_per_step=[[round(f / n, 4) for f in fl] for fl, n in zip(fitted, nblk)])
+        for l in range(len(nblk)):
+            s.set_lattice(l, None)
     if args.copy_mib:
         nel = args.copy_mib * 1024 * 1024 // 4
         src = torch.ones(nel, device=dev, dtype=torch.float32)

@@ -1694,21 +1694,36 @@ __global__ void k_lat_clear(int64_t T, uint64_t *__restrict__ tk, int32_t *__res
     tm[s] = INT32_MAX;
 }
 
-// T > 2B slots: a free slot is always met, so the probe ends
-__global__ void k_lat_insert(int B, const uint64_t *__restrict__ key, int64_t T, uint64_t *__restrict__ tk,
-                             int32_t *__restrict__ tm) {
+// T > 2B slots: a free slot is always met, so the probe ends.  Neighbouring
+// blocks mostly share a key, so a wavefront first reduces its lanes per key
+// and one lane inserts each distinct key with the smallest block.
+__global__ __launch_bounds__(WG) void k_lat_insert(int B, const uint64_t *__restrict__ key, int64_t T,
+                                                   uint64_t *__restrict__ tk, int32_t *__restrict__ tm) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= B) return;
-    const uint64_t h = key[k];
-    int64_t s = (int64_t)(h & (uint64_t)(T - 1));
-    for (;;) {
-        const unsigned long long prev =
-            atomicCAS((unsigned long long *)(tk + s), (unsigned long long)LAT_EMPTY, (unsigned long long)h);
-        if (prev == LAT_EMPTY || prev == h) {
-            atomicMin(tm + s, k);
-            return;
+    const int lane = threadIdx.x & 63;
+    const bool active = k < B;
+    const uint64_t h = active ? key[k] : 0;
+    uint64_t pending = __ballot(active);
+    while (pending) {   // wavefront-uniform
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const uint64_t hl = __shfl(h, leader, 64);
+        const bool mine = ((pending >> lane) & 1) && h == hl;
+        int v = mine ? k : INT32_MAX;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+        if (lane == leader) {
+            int64_t s = (int64_t)(hl & (uint64_t)(T - 1));
+            for (;;) {
+                const unsigned long long prev = atomicCAS((unsigned long long *)(tk + s),
+                                                          (unsigned long long)LAT_EMPTY, (unsigned long long)hl);
+                if (prev == LAT_EMPTY || prev == hl) {
+                    atomicMin(tm + s, v);
+                    break;
+                }
+                s = (s + 1) & (T - 1);
+            }
         }
-        s = (s + 1) & (T - 1);
+        pending &= ~__ballot(mine);
     }
 }
 
@@ -1804,10 +1819,22 @@ __global__ void k_lat_copy_lam(int B, int nb2, const int32_t *__restrict__ rep, 
     if (rs == 0) msing[k] = sing[pos[r]];
 }
 
+// need[c] = 1 for the blocks of the next step's list and their neighbours: the
+// only rows whose residual values the next step reads
+__global__ void k_lat_need(int nl, const int32_t *__restrict__ list, const int32_t *__restrict__ bptr,
+                           const int32_t *__restrict__ bcol, int32_t *__restrict__ need) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nl) return;
+    const int i = list[t];
+    for (int e = bptr[i]; e < bptr[i + 1]; ++e) need[bcol[e]] = 1;
+}
+
 // Residual row of a member: the representative's new row with its block
-// columns moved by the translation, re-sorted by rank.
+// columns moved by the translation, re-sorted by rank; the values only where
+// need[i] is set (need = NULL: everywhere).
 __global__ __launch_bounds__(WG) void k_lat_etranslate(int B, int nb, const int32_t *__restrict__ pos,
                                                        const int32_t *__restrict__ rep, LatDev L,
+                                                       const int32_t *__restrict__ need,
                                                        const int32_t *__restrict__ nptr, int32_t *__restrict__ ncol,
                                                        double *__restrict__ nval, int32_t *__restrict__ err) {
     __shared__ int32_t tc[LAT_ROW_CAP];
@@ -1817,13 +1844,17 @@ __global__ __launch_bounds__(WG) void k_lat_etranslate(int B, int nb, const int3
     const int r = rep[i];
     const int rlo = nptr[r], k = nptr[r + 1] - rlo, ilo = nptr[i];
     const int nb2 = nb * nb;
-    if (k > LAT_ROW_CAP || k != nptr[i + 1] - ilo) {
+    if (k > LAT_ROW_CAP || k != nptr[i + 1] - ilo) {   // fails the setup; keep the columns valid meanwhile
         if (threadIdx.x == 0) err[i] = 1;
+        for (int p = threadIdx.x; p < nptr[i + 1] - ilo; p += WG) ncol[ilo + p] = i;
         return;
     }
     for (int p = threadIdx.x; p < k; p += WG) {
-        const int c = lat_shift(L, ncol[rlo + p], r, i);
-        if (c < 0) err[i] = 1;
+        int c = lat_shift(L, ncol[rlo + p], r, i);
+        if (c < 0) {   // cannot happen for verified classes; keep later indexing in bounds until the check
+            err[i] = 1;
+            c = i;
+        }
         tc[p] = c;
     }
     __syncthreads();
@@ -1834,6 +1865,7 @@ __global__ __launch_bounds__(WG) void k_lat_etranslate(int B, int nb, const int3
         rk[p] = below;
         ncol[ilo + below] = v;
     }
+    if (need && !need[i]) return;   // block-uniform
     __syncthreads();
     for (int64_t e = threadIdx.x; e < (int64_t)k * nb2; e += WG) {
         const int p = (int)(e / nb2), rs = (int)(e % nb2);
@@ -1861,6 +1893,38 @@ int64_t scan_counts(Ctx &c, const DBuf<int32_t> &cnt, int64_t n, DBuf<int32_t> &
     int64_t total = 0;
     tot.download(&total, 1, c.stream);
     CS_HIP(hipStreamSynchronize(c.stream));
+    if (total >= INT32_MAX) fail(CS_ENOMEM, "pattern too large for 32-bit offsets");
+    return total;
+}
+
+// scan_counts that also brings back, in the same round trip, max(cnt[0, n))
+// (when maxc) and max(flags[0, nflags)) (when flags)
+int64_t scan_counts_ex(Ctx &c, const DBuf<int32_t> &cnt, int64_t n, DBuf<int32_t> &ptr, DBuf<int64_t> &tot,
+                       int32_t *maxc, const int32_t *flags, int64_t nflags, int32_t *flag) {
+    DBuf<int32_t> m(2);
+    hipStream_t s = c.stream;
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(WG), 0, s, m.get(), (int64_t)2, 0);
+    if (maxc && n > 0)
+        hipLaunchKernelGGL(k_reduce_i32<false>, dim3((unsigned)std::min<int64_t>(ceil_div(n, WG), 4096)), dim3(WG), 0,
+                           s, n, cnt.get(), m.get());
+    if (flags && nflags > 0)
+        hipLaunchKernelGGL(k_reduce_i32<false>, dim3((unsigned)std::min<int64_t>(ceil_div(nflags, WG), 4096)),
+                           dim3(WG), 0, s, nflags, flags, m.get() + 1);
+    ptr.alloc(n + 1);
+    const int64_t ntiles = std::max<int64_t>(ceil_div(n, SCAN_TILE), 1);
+    DBuf<int64_t> tiles(ntiles);
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(256), 0, s, cnt.get(), n, ptr.get(), tiles.get());
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, s, ntiles, tiles.get(), tot.get());
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)ceil_div(n + 1, 256)), dim3(256), 0, s, n, tiles.get(), tot.get(),
+                       ptr.get());
+    CS_LAUNCH_CHECK();
+    int64_t total = 0;
+    int32_t hm[2] = {0, 0};
+    tot.download(&total, 1, s);
+    m.download(hm, 2, s);
+    CS_HIP(hipStreamSynchronize(s));
+    if (maxc) *maxc = hm[0];
+    if (flag) *flag = hm[1];
     if (total >= INT32_MAX) fail(CS_ENOMEM, "pattern too large for 32-bit offsets");
     return total;
 }
@@ -2258,11 +2322,14 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
     std::vector<int> lat_sizes;
     L.lat_rep.release();
     L.lat_fitted.assign(depth, B_act);
-    DBuf<int32_t> msing;
+    DBuf<int32_t> msing, need, lat_acc;   // lat_acc: singular members, translation failures (read at the end)
     if (lattice) {
         lattice_classes(c, L, ap, depth, lat_lists, lat_sizes);
         for (int ell = 0; ell < depth; ++ell) L.lat_fitted[ell] = lat_sizes[ell];
         msing.alloc(B);
+        need.alloc(B);
+        lat_acc.alloc(2);
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(WG), 0, s, lat_acc.get(), (int64_t)2, 0);
     }
     const LatDev ld = lat_dev(L);
     // the prescaled dense blocks of A
@@ -2298,6 +2365,9 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
     DBuf<int32_t> pos(B), sing, cnt, err(B);
     DBuf<int64_t> tot(1);
     const int maxdeg = max_span(c, B, 1, ap.ptr.get());
+    int32_t emax = 1;   // longest block row of E (E_0 = I)
+    DBuf<int32_t> sing_acc(1);   // singular blocks of the fitted rows, read at the end
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(WG), 0, s, sing_acc.get(), (int64_t)1, 0);
     L.singular = 0;
     const int nsteps = depth * (int)lists.size();
     int step = 0;
@@ -2320,12 +2390,13 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
             cnt.alloc(nl);
             BPattern mp;
             mp.rows = nl;
-            const int64_t bound = maxdeg <= 64 ? (int64_t)maxdeg * max_span(c, B, 1, E.pat.ptr.get()) : INT64_MAX;
+            const int64_t bound = maxdeg <= 64 ? (int64_t)maxdeg * emax : INT64_MAX;
             launch_union<SRC_E, false>(s, bound, dlist, nl, nb, ap.ptr.get(), ap.col.get(), E.pat.ptr.get(),
                                        E.pat.col.get(), cnt.get(), nullptr, nullptr, err.get());
             CS_LAUNCH_CHECK();
-            check_flags(c, err, nl, "fill of a residual row");
-            mp.nnzb = scan_counts(c, cnt, nl, mp.ptr, tot);
+            int32_t overflow = 0;
+            mp.nnzb = scan_counts_ex(c, cnt, nl, mp.ptr, tot, nullptr, err.get(), nl, &overflow);
+            if (overflow) fail(CS_EINVAL, "fill of a residual row exceeds the per-row capacity of the symbolic kernels");
             mp.col.alloc(mp.nnzb);
             launch_union<SRC_E, true>(s, bound, dlist, nl, nb, ap.ptr.get(), ap.col.get(), E.pat.ptr.get(),
                                       E.pat.col.get(), nullptr, mp.ptr.get(), mp.col.get(), err.get());
@@ -2351,13 +2422,15 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
                 hipLaunchKernelGGL(k_gram_solve, dim3(nl), dim3(WG), 0, s, dlist, nb, mp.ptr.get(),
                                    mp.col.get(), mval.get(), E.pat.ptr.get(), E.pat.col.get(), E.val.get(), lam_l,
                                    sing.get());
+            hipLaunchKernelGGL(k_reduce_i32<true>, dim3(std::min<unsigned>(grid_for(nl), 4096)), dim3(WG), 0, s,
+                               (int64_t)nl, sing.get(), sing_acc.get());
             CS_LAUNCH_CHECK();
-            L.singular += reduce_i32(c, sing.get(), nl, true);
             if (lrep) {
                 hipLaunchKernelGGL(k_lat_copy_lam, dim3(grid_for((int64_t)B * nb2)), dim3(WG), 0, s, B, nb2, lrep,
                                    pos.get(), sing.get(), lam_l, msing.get());
+                hipLaunchKernelGGL(k_reduce_i32<true>, dim3(std::min<unsigned>(grid_for(B), 4096)), dim3(WG), 0, s,
+                                   (int64_t)B, msing.get(), lat_acc.get());
                 CS_LAUNCH_CHECK();
-                L.singular += reduce_i32(c, msing.get(), B, true);
             }
             if (step + 1 == nsteps) break;   // the last residual is never needed
             // E update on pattern(M) for list rows, copy for others
@@ -2368,7 +2441,7 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
                 CS_LAUNCH_CHECK();
                 EMat N;
                 N.pat.rows = B;
-                N.pat.nnzb = scan_counts(c, ncnt, B, N.pat.ptr, tot);
+                N.pat.nnzb = scan_counts_ex(c, ncnt, B, N.pat.ptr, tot, &emax, nullptr, 0, nullptr);
                 N.pat.col.alloc(N.pat.nnzb);
                 N.val.alloc((size_t)N.pat.nnzb * nb2);
                 hipLaunchKernelGGL(k_eupdate, dim3(B), dim3(WG), 0, s, B, nb, pos.get(), mp.ptr.get(), mp.col.get(),
@@ -2376,13 +2449,16 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
                                    N.pat.col.get(), N.val.get());
                 CS_LAUNCH_CHECK();
                 if (lrep) {
+                    // rows read by step ell + 1: its list (the classes at radius ell) and their neighbours
+                    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(B)), dim3(WG), 0, s, need.get(), (int64_t)B, 0);
+                    hipLaunchKernelGGL(k_lat_need, dim3(grid_for(lat_sizes[ell])), dim3(WG), 0, s, lat_sizes[ell],
+                                       lat_lists[ell].get(), ap.ptr.get(), ap.col.get(), need.get());
                     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(B)), dim3(WG), 0, s, err.get(), (int64_t)B, 0);
                     hipLaunchKernelGGL(k_lat_etranslate, dim3(B), dim3(WG), 0, s, B, nb, pos.get(), lrep, ld,
-                                       N.pat.ptr.get(), N.pat.col.get(), N.val.get(), err.get());
+                                       need.get(), N.pat.ptr.get(), N.pat.col.get(), N.val.get(), err.get());
+                    hipLaunchKernelGGL(k_reduce_i32<false>, dim3(std::min<unsigned>(grid_for(B), 4096)), dim3(WG),
+                                       0, s, (int64_t)B, err.get(), lat_acc.get() + 1);
                     CS_LAUNCH_CHECK();
-                    if (reduce_i32(c, err.get(), B, false))
-                        fail(CS_EINVAL, "a residual row of a lattice class could not be translated (row above " +
-                                            std::to_string(LAT_ROW_CAP) + " blocks, or a neighbour off the lattice)");
                 }
                 mval.release();
                 if (o.trunc_alpha > 0) {
@@ -2392,10 +2468,12 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
                                        N.pat.ptr.get(), N.pat.col.get(), N.val.get(), tcnt.get(), nullptr, nullptr,
                                        nullptr, err.get());
                     CS_LAUNCH_CHECK();
-                    check_flags(c, err, B, "truncated residual row");
+                    int32_t tover = 0;
                     EMat T;
                     T.pat.rows = B;
-                    T.pat.nnzb = scan_counts(c, tcnt, B, T.pat.ptr, tot);
+                    T.pat.nnzb = scan_counts_ex(c, tcnt, B, T.pat.ptr, tot, &emax, err.get(), B, &tover);
+                    if (tover)
+                        fail(CS_EINVAL, "truncated residual row exceeds the per-row capacity of the symbolic kernels");
                     T.pat.col.alloc(T.pat.nnzb);
                     T.val.alloc((size_t)T.pat.nnzb * nb2);
                     hipLaunchKernelGGL((k_truncate<true>), dim3(B), dim3(WG), 0, s, B, nb, o.trunc_alpha, pos.get(),
@@ -2408,6 +2486,16 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
                 keep_pattern(E.pat);
             }
         }
+    }
+    {
+        int32_t acc[2] = {0, 0}, sg = 0;
+        sing_acc.download(&sg, 1, s);
+        if (lattice) lat_acc.download(acc, 2, s);
+        CS_HIP(hipStreamSynchronize(s));
+        if (acc[1])
+            fail(CS_EINVAL, "a residual row of a lattice class could not be translated (row above " +
+                                std::to_string(LAT_ROW_CAP) + " blocks, or a neighbour off the lattice)");
+        L.singular = sg + acc[0];
     }
     // unscale into the FP64 master
     L.depth = depth;

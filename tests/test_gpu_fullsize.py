@@ -110,3 +110,35 @@ def test_fullsize_vcycle_injected_smoothers(full):
     e32 = rel(g32, o)
     print(f"[fullsize] FP32 V-cycle vs FP64 oracle: {e32:.2e}")
     assert e32 <= 1e-5
+
+
+def test_fullsize_lattice_cache(gpu_lib, full):
+    """The stencil-repetition cache at full size: every block's smoother equals
+    the uncached fit (blockwise 1e-10), and sampled members of the bulk class
+    and their representatives equal the oracle's patch fit."""
+    p, _ = full   # the shared solver holds injected smoothers by now: fit a fresh uncached one
+    s = gpu_lib.Solver(p.levels)
+    s.setup(depth=DEPTH, mode="additive", order="RF", precision="fp32")
+    t = gpu_lib.Solver(p.levels)
+    for l, lv in enumerate(p.levels[:-1]):
+        t.set_lattice(l, lv.block_lattice())
+    t.setup(depth=DEPTH, mode="additive", order="RF", precision="fp32")
+    fitted, rep = t.lattice_stats(0, classes=True)
+    B = p.levels[0].n_blocks
+    print(f"[fullsize] lattice cache: fitted per step {fitted.tolist()} of {B}", flush=True)
+    assert fitted[0] < B // 10 and np.all(np.diff(fitted) >= 0)
+    for ell in range(1, DEPTH + 1):
+        g, o = t.get_smoother(0, ell), s.get_smoother(0, ell)
+        num = np.linalg.norm((g - o).reshape(B, -1), axis=1)
+        den = np.linalg.norm(o.reshape(B, -1), axis=1)
+        assert (num / den).max() <= 1e-10, ell
+    members = np.flatnonzero(rep[DEPTH - 1] != np.arange(B))
+    rng = stream(3, TEST)
+    pick = rng.choice(members, size=3, replace=False)
+    centres = sorted({*pick.tolist(), *rep[DEPTH - 1][pick].tolist()})
+    loc = O.fit_local(p.levels[0].A, 8, DEPTH, centres)
+    for ell in range(1, DEPTH + 1):
+        g = t.get_smoother(0, ell)
+        for c in centres:
+            o = loc[c][ell - 1]
+            assert np.linalg.norm(g[c] - o) / np.linalg.norm(o) <= 1e-9, (c, ell)
