@@ -133,6 +133,32 @@ def bench_stokes(precision: str):
     return out
 
 
+def bench_dg():
+    """SIPG Q3 on a jittered 256^2 quadrilateral mesh (16 x 16 element blocks,
+    1,048,576 unknowns, 1 RHS), depth-3 four-colour multiplicative FF cascade,
+    V(1,1); FP64 V-cycle (reduced precision diverges for this cascade) in
+    flexible CG and in the stationary iteration."""
+    import time as _t
+    import torch
+    from paper_2606_12577_amd import cascade
+    from synth import dg
+    t = _t.perf_counter()
+    p = dg.sipg_q3(256)
+    gen_s = _t.perf_counter() - t
+    s = cascade.Solver(p.levels)
+    b = torch.as_tensor(p.rhs, device="cuda").contiguous()
+    out = dict(dof=int(p.n), nrhs=1, generation_s=round(gen_s, 1))
+    for _ in range(2):
+        s.setup(depth=3, mode="multiplicative", order="FF", precision="fp64")
+    for method in ("cg", "ir"):
+        i = [s.solve(b, rtol=1e-10, maxit=300, method=method, raise_on_noconv=False)[1] for _ in range(2)][-1]
+        out[method] = dict(solve_ms=round(i["solve_ms"], 2), iterations=i["iterations"], rho=round(i["rho"], 4),
+                           rel_res=i["rel_res"], setup_ms=round(i["setup_ms"], 2),
+                           dof_per_s=p.n / (i["solve_ms"] * 1e-3))
+    s.close()
+    return out
+
+
 def bench_learned():
     """Q1 multiphase diffusion 96^3: train the block network on two samples,
     then on an unseen sample compare the learned finest-level setup with the
@@ -226,6 +252,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-system measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-setup measurement")
     ap.add_argument("--no-stokes", action="store_true", help="skip the Stokes (MAC) measurement")
+    ap.add_argument("--no-dg", action="store_true", help="skip the SIPG Q3 256^2 measurement")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -374,6 +401,9 @@ def main():
     if not args.no_stokes:
         log("Stokes: MAC 256^2")
         extra["stokes_mac_256"] = bench_stokes(args.precision)
+    if not args.no_dg:
+        log("DG: SIPG Q3 256^2")
+        extra["dg_sipg_q3_256"] = bench_dg()
     if not args.no_learned:
         log("learned setup: Q1 multiphase 96^3")
         extra["learned_q1_96"] = bench_learned()

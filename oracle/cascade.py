@@ -693,18 +693,21 @@ def block_ball(Apat: sp.csr_matrix, centre: int, radius: int) -> np.ndarray:
 
 
 def fit_local(A: sp.spmatrix, n: int, depth: int, centres: Sequence[int], mode: str = "additive",
-              colours: Optional[np.ndarray] = None, radius: Optional[int] = None) -> Dict[int, List[np.ndarray]]:
+              colours: Optional[np.ndarray] = None, radius: Optional[int] = None,
+              with_cond: bool = False):
     """Lambda_{l,i} for selected blocks i, each fitted on the sub-matrix of A
     over the blocks within block-graph distance `radius` of i.
 
     Lambda_{l,i} depends on A only through E_{l-1} on the neighbours of i,
     which in turn reaches at most l block layers out, so radius = nu
-    (additive) or nu * chi (multiplicative) reproduces the full fit."""
+    (additive) or nu * chi (multiplicative) reproduces the full fit.
+    with_cond: also return, per centre, the largest condition number of the
+    normal equations met in its patch at each cascade level."""
     A = sp.csr_matrix(A)
     Apat = block_pattern(A, n)
     if radius is None:
         radius = depth if mode == "additive" else depth * (int(np.max(colours)) + 1)
-    out = {}
+    out, conds = {}, {}
     for c in centres:
         S = block_ball(Apat, int(c), radius)
         sel = block_rows(S, n)
@@ -712,7 +715,8 @@ def fit_local(A: sp.spmatrix, n: int, depth: int, centres: Sequence[int], mode: 
         pos = int(np.searchsorted(S, c))
         res = fit(sub, n, depth, mode, None if colours is None else np.asarray(colours)[S])
         out[int(c)] = [L[pos] for L in res["lam"]]
-    return out
+        conds[int(c)] = [float(np.max(g)) for g in res["gram_cond"]]
+    return (out, conds) if with_cond else out
 
 
 # ---------------------------------------------------------------------------

@@ -27,7 +27,7 @@ namespace cs {
 namespace {
 
 constexpr int WG = 256;
-constexpr int64_t IR_GRID = 1024;   // workgroups of the refinement residual (8 per XCD-CU group)
+constexpr int64_t IR_GRID = 1024;   // workgroup cap of the outer-solver kernels (4 per CU)
 constexpr int64_t SMALL_SLICES = 8192;   // below this many 64-row slices a level counts as small
 
 template <typename T, int R>
@@ -496,6 +496,27 @@ __global__ __launch_bounds__(WG) void k_direct_seg(int64_t n_active, int64_t n, 
     }
 }
 
+// Per-workgroup sums of W per-thread values into partial[blockIdx.x][W] (red:
+// (WG / 64) * W doubles): a wavefront butterfly, then the waves in order.
+template <int W>
+__device__ __forceinline__ void wg_partials(const double (&acc)[W], double *red, double *partial) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        double v = acc[k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) red[wv * W + k] = v;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < W) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < WG / 64; ++w) t += red[w * W + threadIdx.x];
+        partial[(int64_t)blockIdx.x * W + threadIdx.x] = t;
+    }
+}
+
 // FP64 refinement residual r = b - A x; writes r in the working precision and
 // per-workgroup partial sums of r^2 for every right-hand side.  With x == null
 // it computes the partial sums of b^2.
@@ -512,7 +533,7 @@ __global__ __launch_bounds__(WG) void k_ir_residual(int64_t nrows, int64_t nslic
                                                     const double *__restrict__ x, T *__restrict__ rt,
                                                     double *__restrict__ partial, const int32_t *__restrict__ het,
                                                     double *__restrict__ spart, double *__restrict__ rn2) {
-    __shared__ double red[SYS ? 1 : WG * R];
+    __shared__ double red[SYS ? 1 : (WG / 64) * R];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t ntiles = (nslices + 3) / 4;
     double sq[R];
@@ -569,17 +590,7 @@ __global__ __launch_bounds__(WG) void k_ir_residual(int64_t nrows, int64_t nslic
         }
     }
     if constexpr (SYS) return;
-#pragma unroll
-    for (int k = 0; k < R; ++k) red[threadIdx.x * R + k] = sq[k];
-    __syncthreads();
-    for (int s = WG / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) {
-#pragma unroll
-            for (int k = 0; k < R; ++k) red[threadIdx.x * R + k] += red[(threadIdx.x + s) * R + k];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x < R) partial[(int64_t)blockIdx.x * R + threadIdx.x] = red[threadIdx.x];
+    else wg_partials<R>(sq, red, partial);
 }
 
 // ---------------------------------------------------------------------------
@@ -604,20 +615,6 @@ __device__ __forceinline__ void slice_partials(double (&v)[W], int lane, int64_t
     }
 }
 
-template <int W>
-__device__ __forceinline__ void wg_partials(const double (&acc)[W], double *red, double *partial) {
-#pragma unroll
-    for (int k = 0; k < W; ++k) red[threadIdx.x * W + k] = acc[k];
-    __syncthreads();
-    for (int s = WG / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) {
-#pragma unroll
-            for (int k = 0; k < W; ++k) red[threadIdx.x * W + k] += red[(threadIdx.x + s) * W + k];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x < W) partial[(int64_t)blockIdx.x * W + threadIdx.x] = red[threadIdx.x];
-}
 
 __device__ __forceinline__ int row_system(int64_t row, int nsys, const int64_t *__restrict__ sys_ptr) {
     int lo = 0, hi = nsys - 1;
@@ -635,7 +632,7 @@ __global__ __launch_bounds__(WG) void k_cg_zq(int64_t nrows, int64_t nslices, co
                                               const double *__restrict__ q, const int32_t *__restrict__ het,
                                               double *__restrict__ spart, double *__restrict__ rn2,
                                               double *__restrict__ partial) {
-    __shared__ double red[SYS ? 1 : WG * R];
+    __shared__ double red[SYS ? 1 : (WG / 64) * R];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     double acc[R];
 #pragma unroll
@@ -700,7 +697,7 @@ __global__ __launch_bounds__(WG) void k_cg_ap(int64_t nrows, int64_t nslices, co
                                               const double *__restrict__ r, double *__restrict__ q,
                                               const int32_t *__restrict__ het, double *__restrict__ spart,
                                               double *__restrict__ rn2, double *__restrict__ partial) {
-    __shared__ double red[SYS ? 1 : WG * 2 * R];
+    __shared__ double red[SYS ? 1 : (WG / 64) * 2 * R];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     double acc[2 * R];
 #pragma unroll
@@ -747,7 +744,7 @@ __global__ __launch_bounds__(WG) void k_cg_update(int64_t nrows, int64_t nslices
                                                   double *__restrict__ x, double *__restrict__ r, T *__restrict__ rt,
                                                   const int32_t *__restrict__ het, double *__restrict__ spart,
                                                   double *__restrict__ rn2, double *__restrict__ partial) {
-    __shared__ double red[SYS ? 1 : WG * R];
+    __shared__ double red[SYS ? 1 : (WG / 64) * R];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     double acc[R];
 #pragma unroll
