@@ -686,7 +686,8 @@ __device__ void normal_solve(const double *G, const double *H, double *Lc, doubl
 
 // Normal equations of one block row: G = M M^T, H = E M^T, Lambda~ = H G^{-1}
 // (Cholesky; pseudo-inverse fallback).  One workgroup per list row.
-__global__ __launch_bounds__(WG) void k_gram_solve(const int32_t *__restrict__ list, int nb,
+template <int NBT>   // > 0: block size fixed at compile time; 0: nb_rt
+__global__ __launch_bounds__(WG) void k_gram_solve(const int32_t *__restrict__ list, int nb_rt,
                                                    const int32_t *__restrict__ mptr, const int32_t *__restrict__ mcol,
                                                    const double *__restrict__ mval, const int32_t *__restrict__ eptr,
                                                    const int32_t *__restrict__ ecol, const double *__restrict__ eval,
@@ -697,6 +698,7 @@ __global__ __launch_bounds__(WG) void k_gram_solve(const int32_t *__restrict__ l
     const int i = list[li];
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
+    const int nb = NBT > 0 ? NBT : nb_rt;
     const int nb2 = nb * nb;
     const int mlo = mptr[li], k = mptr[li + 1] - mlo;
     const int elo = eptr[i], ek = eptr[i + 1] - elo;
@@ -1252,38 +1254,106 @@ __global__ __launch_bounds__(WG) void k_sk_update(int nl, const int32_t *__restr
 
 // E_new,i = E_old,i - Lambda~_i M_i for list rows (on pattern(M_i)); other rows
 // are copied.  One workgroup per block row.
-__global__ __launch_bounds__(WG) void k_eupdate(int B, int nb, const int32_t *__restrict__ pos_in_list,
+// NBT > 0: block size fixed at compile time (Lambda row in registers, the M
+// column loads unrolled); NBT = 0: nb at run time.
+template <int NBT>
+__global__ __launch_bounds__(WG) void k_eupdate(int B, int nb_rt, const int32_t *__restrict__ pos_in_list,
                                                 const int32_t *__restrict__ mptr, const int32_t *__restrict__ mcol,
                                                 const double *__restrict__ mval, const int32_t *__restrict__ eptr,
                                                 const int32_t *__restrict__ ecol, const double *__restrict__ eval,
                                                 const double *__restrict__ lamt, const int32_t *__restrict__ nptr,
                                                 int32_t *__restrict__ ncol, double *__restrict__ nval) {
+    constexpr int QCAP = 4096;   // block positions of a row kept in LDS
+    __shared__ int32_t qpos[QCAP];
     const int i = blockIdx.x;
     if (i >= B) return;
     const int t = threadIdx.x;
+    const int nb = NBT > 0 ? NBT : nb_rt;
     const int nb2 = nb * nb;
     const int li = pos_in_list[i];
     if (li == -2) return;   // member of a lattice class: translated from its representative
     const int elo = eptr[i], ek = eptr[i + 1] - elo;
     const int nlo = nptr[i];
-    if (li < 0) {
+    if (li < 0) {   // unchanged row: copy (16-byte accesses, four in flight per thread)
         for (int q = t; q < ek; q += WG) ncol[nlo + q] = ecol[elo + q];
-        for (int64_t e = t; e < (int64_t)ek * nb2; e += WG)
-            nval[(int64_t)nlo * nb2 + e] = eval[(int64_t)elo * nb2 + e];
+        const int64_t n = (int64_t)ek * nb2;
+        const double *src = eval + (int64_t)elo * nb2;
+        double *dst = nval + (int64_t)nlo * nb2;
+        if ((nb2 & 1) == 0) {   // row starts are then 16-byte aligned
+            const double2 *s2 = reinterpret_cast<const double2 *>(src);
+            double2 *d2 = reinterpret_cast<double2 *>(dst);
+            const int64_t n2 = n / 2;
+            int64_t e = t;
+            for (; e + 3 * WG < n2; e += 4 * WG) {
+                const double2 a0 = s2[e], a1 = s2[e + WG], a2 = s2[e + 2 * WG], a3 = s2[e + 3 * WG];
+                d2[e] = a0;
+                d2[e + WG] = a1;
+                d2[e + 2 * WG] = a2;
+                d2[e + 3 * WG] = a3;
+            }
+            for (; e < n2; e += WG) d2[e] = s2[e];
+        } else {
+            for (int64_t e = t; e < n; e += WG) dst[e] = src[e];
+        }
         return;
     }
     const int mlo = mptr[li], k = mptr[li + 1] - mlo;
-    for (int p = t; p < k; p += WG) ncol[nlo + p] = mcol[mlo + p];
+    for (int p = t; p < k; p += WG) {
+        const int32_t c = mcol[mlo + p];
+        ncol[nlo + p] = c;
+        if (k <= QCAP) qpos[p] = bsearch_i32(ecol, elo, elo + ek, c);
+    }
+    __syncthreads();
     const double *L = lamt + (int64_t)i * nb2;
-    for (int64_t e = t; e < (int64_t)k * nb2; e += WG) {
-        int p = (int)(e / nb2), rs = (int)(e % nb2);
-        int r = rs / nb, s = rs % nb;
-        int q = bsearch_i32(ecol, elo, elo + ek, mcol[mlo + p]);
-        double v = (q >= 0) ? eval[(int64_t)q * nb2 + rs] : 0.0;
-        const double *mp = mval + (int64_t)(mlo + p) * nb2 + s;
-        double acc = 0.0;
-        for (int u = 0; u < nb; ++u) acc += L[r * nb + u] * mp[u * nb];
-        nval[(int64_t)(nlo + p) * nb2 + rs] = v - acc;
+    if constexpr (NBT > 0 && WG % (NBT * NBT) == 0) {
+        // each thread keeps one entry (r, sc) of the blocks and walks the blocks
+        constexpr int NB2 = NBT * NBT, PER = WG / NB2;
+        const int rs = t % NB2, r = rs / NBT, sc = rs % NBT;
+        double lr[NBT];
+#pragma unroll
+        for (int u = 0; u < NBT; ++u) lr[u] = L[r * NBT + u];
+        for (int p = t / NB2; p < k; p += PER) {
+            const int q = k <= QCAP ? qpos[p] : bsearch_i32(ecol, elo, elo + ek, mcol[mlo + p]);
+            const double v = (q >= 0) ? eval[(int64_t)q * NB2 + rs] : 0.0;
+            const double *mp = mval + (int64_t)(mlo + p) * NB2 + sc;
+            double m[NBT];
+#pragma unroll
+            for (int u = 0; u < NBT; ++u) m[u] = mp[u * NBT];
+            double acc = 0.0;
+#pragma unroll
+            for (int u = 0; u < NBT; ++u) acc += lr[u] * m[u];
+            nval[(int64_t)(nlo + p) * NB2 + rs] = v - acc;
+        }
+    } else {
+        const int total = k * nb2;
+        for (int e = t; e < total; e += WG) {
+            const int p = e / nb2, rs = e % nb2;
+            const int r = rs / nb, sc = rs % nb;
+            const int q = k <= QCAP ? qpos[p] : bsearch_i32(ecol, elo, elo + ek, mcol[mlo + p]);
+            const double v = (q >= 0) ? eval[(int64_t)q * nb2 + rs] : 0.0;
+            const double *mp = mval + (int64_t)(mlo + p) * nb2 + sc;
+            double acc = 0.0;
+            for (int u = 0; u < nb; ++u) acc += L[r * nb + u] * mp[u * nb];
+            nval[(int64_t)(nlo + p) * nb2 + rs] = v - acc;
+        }
+    }
+}
+
+void launch_eupdate(hipStream_t s, int B, int nb, const int32_t *pos, const int32_t *mptr, const int32_t *mcol,
+                    const double *mval, const int32_t *eptr, const int32_t *ecol, const double *eval,
+                    const double *lamt, const int32_t *nptr, int32_t *ncol, double *nval) {
+    auto go = [&](auto nbc) {
+        constexpr int NBT = decltype(nbc)::value;
+        hipLaunchKernelGGL((k_eupdate<NBT>), dim3(B), dim3(WG), 0, s, B, nb, pos, mptr, mcol, mval, eptr, ecol, eval,
+                           lamt, nptr, ncol, nval);
+    };
+    switch (nb) {
+        case 1: go(std::integral_constant<int, 1>{}); break;
+        case 2: go(std::integral_constant<int, 2>{}); break;
+        case 4: go(std::integral_constant<int, 4>{}); break;
+        case 8: go(std::integral_constant<int, 8>{}); break;
+        case 16: go(std::integral_constant<int, 16>{}); break;
+        default: go(std::integral_constant<int, 0>{}); break;
     }
 }
 
@@ -1867,8 +1937,13 @@ __global__ __launch_bounds__(WG) void k_lat_etranslate(int B, int nb, const int3
     }
     if (need && !need[i]) return;   // block-uniform
     __syncthreads();
-    for (int64_t e = threadIdx.x; e < (int64_t)k * nb2; e += WG) {
-        const int p = (int)(e / nb2), rs = (int)(e % nb2);
+    const bool fixed = WG % nb2 == 0;
+    const int total = k * nb2;
+    for (int e0 = 0; e0 < total; e0 += WG) {
+        const int e = e0 + (int)threadIdx.x;
+        if (e >= total) break;
+        const int p = fixed ? e0 / nb2 + (int)threadIdx.x / nb2 : e / nb2;
+        const int rs = fixed ? (int)threadIdx.x % nb2 : e % nb2;
         nval[(int64_t)(ilo + rk[p]) * nb2 + rs] = nval[(int64_t)(rlo + p) * nb2 + rs];
     }
 }
@@ -2418,10 +2493,21 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
                 hipLaunchKernelGGL(k_gram_point, dim3((unsigned)ceil_div(nl, WG / 64)), dim3(WG), 0, s, nl,
                                    dlist, mp.ptr.get(), mp.col.get(), mval.get(), E.pat.ptr.get(),
                                    E.pat.col.get(), E.val.get(), lam_l, sing.get());
-            else
-                hipLaunchKernelGGL(k_gram_solve, dim3(nl), dim3(WG), 0, s, dlist, nb, mp.ptr.get(),
-                                   mp.col.get(), mval.get(), E.pat.ptr.get(), E.pat.col.get(), E.val.get(), lam_l,
-                                   sing.get());
+            else {
+                auto go = [&](auto nbc) {
+                    constexpr int NBT = decltype(nbc)::value;
+                    hipLaunchKernelGGL((k_gram_solve<NBT>), dim3(nl), dim3(WG), 0, s, dlist, nb, mp.ptr.get(),
+                                       mp.col.get(), mval.get(), E.pat.ptr.get(), E.pat.col.get(), E.val.get(),
+                                       lam_l, sing.get());
+                };
+                switch (nb) {
+                    case 2: go(std::integral_constant<int, 2>{}); break;
+                    case 4: go(std::integral_constant<int, 4>{}); break;
+                    case 8: go(std::integral_constant<int, 8>{}); break;
+                    case 16: go(std::integral_constant<int, 16>{}); break;
+                    default: go(std::integral_constant<int, 0>{}); break;
+                }
+            }
             hipLaunchKernelGGL(k_reduce_i32<true>, dim3(std::min<unsigned>(grid_for(nl), 4096)), dim3(WG), 0, s,
                                (int64_t)nl, sing.get(), sing_acc.get());
             CS_LAUNCH_CHECK();
@@ -2444,9 +2530,8 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
                 N.pat.nnzb = scan_counts_ex(c, ncnt, B, N.pat.ptr, tot, &emax, nullptr, 0, nullptr);
                 N.pat.col.alloc(N.pat.nnzb);
                 N.val.alloc((size_t)N.pat.nnzb * nb2);
-                hipLaunchKernelGGL(k_eupdate, dim3(B), dim3(WG), 0, s, B, nb, pos.get(), mp.ptr.get(), mp.col.get(),
-                                   mval.get(), E.pat.ptr.get(), E.pat.col.get(), E.val.get(), lam_l, N.pat.ptr.get(),
-                                   N.pat.col.get(), N.val.get());
+                launch_eupdate(s, B, nb, pos.get(), mp.ptr.get(), mp.col.get(), mval.get(), E.pat.ptr.get(),
+                               E.pat.col.get(), E.val.get(), lam_l, N.pat.ptr.get(), N.pat.col.get(), N.val.get());
                 CS_LAUNCH_CHECK();
                 if (lrep) {
                     // rows read by step ell + 1: its list (the classes at radius ell) and their neighbours
