@@ -472,7 +472,7 @@ __global__ __launch_bounds__(WG) void k_rowprod_nb(const int32_t *__restrict__ l
                                                    const int32_t *__restrict__ mcol, double *__restrict__ mval) {
     constexpr int NB2 = NB * NB;
     __shared__ int32_t match[MATCH_NB];
-    __shared__ double As[AS_CAP];
+    __shared__ __align__(16) double As[AS_CAP];
     const int li = blockIdx.x;
     const int i = list[li];
     const int t = threadIdx.x;
@@ -486,8 +486,13 @@ __global__ __launch_bounds__(WG) void k_rowprod_nb(const int32_t *__restrict__ l
             const int j = abcol[alo + jj];
             match[e] = bsearch_i32(ecol, eptr[j], eptr[j + 1], mcol[mlo + p]);
         }
+    // staged blocks are stored transposed (column u of A~_ij contiguous), so one
+    // 16-byte LDS read feeds two rows of the product
     if (staged)
-        for (int e = t; e < deg * NB2; e += WG) As[e] = abval[(int64_t)alo * NB2 + e];
+        for (int e = t; e < deg * NB2; e += WG) {
+            const int jj = e / NB2, rs = e % NB2;
+            As[jj * NB2 + (rs % NB) * NB + rs / NB] = abval[(int64_t)alo * NB2 + e];
+        }
     __syncthreads();
     for (int w = t; w < k * NB; w += WG) {
         const int p = w / NB, sc = w % NB;
@@ -504,7 +509,31 @@ __global__ __launch_bounds__(WG) void k_rowprod_nb(const int32_t *__restrict__ l
             }
             if (q < 0) continue;
             const double *ev = eval + (int64_t)q * NB2 + sc;
-            const double *a = staged ? As + jj * NB2 : abval + (int64_t)(alo + jj) * NB2;
+            if constexpr (NB % 2 == 0) {
+                if (staged) {
+                    const double2 *a2 = reinterpret_cast<const double2 *>(As + jj * NB2);
+#pragma unroll 2
+                    for (int u = 0; u < NB; ++u) {
+                        const double e = ev[u * NB];
+#pragma unroll
+                        for (int r2 = 0; r2 < NB / 2; ++r2) {
+                            const double2 av = a2[u * (NB / 2) + r2];
+                            acc[2 * r2] += av.x * e;
+                            acc[2 * r2 + 1] += av.y * e;
+                        }
+                    }
+                    continue;
+                }
+            } else if (staged) {
+#pragma unroll 2
+                for (int u = 0; u < NB; ++u) {
+                    const double e = ev[u * NB];
+#pragma unroll
+                    for (int r = 0; r < NB; ++r) acc[r] += As[jj * NB2 + u * NB + r] * e;
+                }
+                continue;
+            }
+            const double *a = abval + (int64_t)(alo + jj) * NB2;
 #pragma unroll 2
             for (int u = 0; u < NB; ++u) {
                 const double e = ev[u * NB];
