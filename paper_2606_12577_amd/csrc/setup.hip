@@ -494,6 +494,45 @@ __global__ __launch_bounds__(WG) void k_rowprod_nb(const int32_t *__restrict__ l
             As[jj * NB2 + (rs % NB) * NB + rs / NB] = abval[(int64_t)alo * NB2 + e];
         }
     __syncthreads();
+    if constexpr (NB % 2 == 0) {
+        if (staged) {   // two adjacent columns of M per thread (same summation order per entry)
+            constexpr int NH = NB / 2;
+            for (int w = t; w < k * NH; w += WG) {
+                const int p = w / NH, c2 = (w % NH) * 2;
+                double a0[NB], a1[NB];
+#pragma unroll
+                for (int r = 0; r < NB; ++r) a0[r] = a1[r] = 0.0;
+                for (int jj = 0; jj < deg; ++jj) {
+                    int q;
+                    if (cached) {
+                        q = match[p * deg + jj];
+                    } else {
+                        const int j = abcol[alo + jj];
+                        q = bsearch_i32(ecol, eptr[j], eptr[j + 1], mcol[mlo + p]);
+                    }
+                    if (q < 0) continue;
+                    const double *ev = eval + (int64_t)q * NB2 + c2;
+                    const double2 *a2 = reinterpret_cast<const double2 *>(As + jj * NB2);
+#pragma unroll 2
+                    for (int u = 0; u < NB; ++u) {
+                        const double2 e = *reinterpret_cast<const double2 *>(ev + u * NB);
+#pragma unroll
+                        for (int r2 = 0; r2 < NH; ++r2) {
+                            const double2 av = a2[u * NH + r2];
+                            a0[2 * r2] += av.x * e.x;
+                            a0[2 * r2 + 1] += av.y * e.x;
+                            a1[2 * r2] += av.x * e.y;
+                            a1[2 * r2 + 1] += av.y * e.y;
+                        }
+                    }
+                }
+                double *mo = mval + (int64_t)(mlo + p) * NB2 + c2;
+#pragma unroll
+                for (int r = 0; r < NB; ++r) *reinterpret_cast<double2 *>(mo + r * NB) = make_double2(a0[r], a1[r]);
+            }
+            return;
+        }
+    }
     for (int w = t; w < k * NB; w += WG) {
         const int p = w / NB, sc = w % NB;
         double acc[NB];
@@ -509,22 +548,7 @@ __global__ __launch_bounds__(WG) void k_rowprod_nb(const int32_t *__restrict__ l
             }
             if (q < 0) continue;
             const double *ev = eval + (int64_t)q * NB2 + sc;
-            if constexpr (NB % 2 == 0) {
-                if (staged) {
-                    const double2 *a2 = reinterpret_cast<const double2 *>(As + jj * NB2);
-#pragma unroll 2
-                    for (int u = 0; u < NB; ++u) {
-                        const double e = ev[u * NB];
-#pragma unroll
-                        for (int r2 = 0; r2 < NB / 2; ++r2) {
-                            const double2 av = a2[u * (NB / 2) + r2];
-                            acc[2 * r2] += av.x * e;
-                            acc[2 * r2 + 1] += av.y * e;
-                        }
-                    }
-                    continue;
-                }
-            } else if (staged) {
+            if (staged) {   // (odd NB: the even sizes returned above)
 #pragma unroll 2
                 for (int u = 0; u < NB; ++u) {
                     const double e = ev[u * NB];
