@@ -1358,7 +1358,42 @@ __global__ __launch_bounds__(WG) void k_eupdate(int B, int nb_rt, const int32_t 
     }
     __syncthreads();
     const double *L = lamt + (int64_t)i * nb2;
-    if constexpr (NBT > 0 && WG % (NBT * NBT) == 0) {
+    if constexpr (NBT > 1 && NBT % 2 == 0) {
+        // Lambda~_i staged transposed (column u contiguous); each thread produces two
+        // adjacent columns of an output block: per entry the same sum over u
+        constexpr int NB2 = NBT * NBT, NH = NBT / 2;
+        __shared__ __align__(16) double LT[MAXNB * MAXNB];
+        for (int e = t; e < NB2; e += WG) LT[(e % NBT) * NBT + e / NBT] = L[e];
+        __syncthreads();
+        const double2 *lt2 = reinterpret_cast<const double2 *>(LT);
+        for (int w = t; w < k * NH; w += WG) {
+            const int p = w / NH, c2 = (w % NH) * 2;
+            const int q = k <= QCAP ? qpos[p] : bsearch_i32(ecol, elo, elo + ek, mcol[mlo + p]);
+            const double *mp = mval + (int64_t)(mlo + p) * NB2 + c2;
+            double a0[NBT], a1[NBT];
+#pragma unroll
+            for (int r = 0; r < NBT; ++r) a0[r] = a1[r] = 0.0;
+#pragma unroll 2
+            for (int u = 0; u < NBT; ++u) {
+                const double2 m = *reinterpret_cast<const double2 *>(mp + u * NBT);
+#pragma unroll
+                for (int r2 = 0; r2 < NH; ++r2) {
+                    const double2 lv = lt2[u * NH + r2];
+                    a0[2 * r2] += lv.x * m.x;
+                    a0[2 * r2 + 1] += lv.y * m.x;
+                    a1[2 * r2] += lv.x * m.y;
+                    a1[2 * r2 + 1] += lv.y * m.y;
+                }
+            }
+            double *no = nval + (int64_t)(nlo + p) * NB2 + c2;
+            const double *eo = eval + (int64_t)(q >= 0 ? q : 0) * NB2 + c2;   // read only when q >= 0
+#pragma unroll
+            for (int r = 0; r < NBT; ++r) {
+                const double2 v = q >= 0 ? *reinterpret_cast<const double2 *>(eo + r * NBT) : make_double2(0.0, 0.0);
+                *reinterpret_cast<double2 *>(no + r * NBT) = make_double2(v.x - a0[r], v.y - a1[r]);
+            }
+        }
+    } else if constexpr (NBT > 0 && WG % (NBT * NBT) == 0) {
         // each thread keeps one entry (r, sc) of the blocks and walks the blocks
         constexpr int NB2 = NBT * NBT, PER = WG / NB2;
         const int rs = t % NB2, r = rs / NBT, sc = rs % NBT;
