@@ -827,6 +827,71 @@ __global__ __launch_bounds__(WG) void k_gram_solve(const int32_t *__restrict__ l
     normal_solve(G, H, Lc, V, nb, lamt + (int64_t)i * nb2, singular + li);
 }
 
+// G = M M^T and H = E M^T on the matrix cores (FP64 MFMA 16x16x4) for 16x16
+// blocks.  Operand lanes: A lane l = A[l%16][l/16], B lane l = B[l/16][l%16],
+// result lane l, register i = D[4i + l/16][l%16].  With B = the next four
+// columns of M (transposed), a lane's B value is its own A value of M; two
+// chains, A = M (G) and A = E (H).  Wavefront w sums the blocks p = w, w + 4,
+// ... of the row; the four partial sums are added in LDS in wave order, then
+// the normal equations are solved as in k_gram_solve.  (For 8x8 blocks the
+// VALU kernel measured faster: half of every 16x16 product would be idle.)
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(WG) void k_gram_mfma(const int32_t *__restrict__ list,
+                                                  const int32_t *__restrict__ mptr, const int32_t *__restrict__ mcol,
+                                                  const double *__restrict__ mval, const int32_t *__restrict__ eptr,
+                                                  const int32_t *__restrict__ ecol, const double *__restrict__ eval,
+                                                  double *__restrict__ lamt, int32_t *__restrict__ singular) {
+    constexpr int NBT = 16, NB2 = NBT * NBT, QCAP = 4096;
+    __shared__ double G[MAXNB * MAXNB], H[MAXNB * MAXNB], Lc[MAXNB * MAXNB], V[MAXNB * MAXNB];
+    __shared__ double part[WG / 64][2][16][16];
+    __shared__ int32_t qpos[QCAP];   // position in E_i of every block of M_i (-1: none)
+    const int li = blockIdx.x;
+    const int i = list[li];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int mlo = mptr[li], k = mptr[li + 1] - mlo;
+    const int elo = eptr[i], ek = eptr[i + 1] - elo;
+    const bool cached = k <= QCAP;
+    if (cached)
+        for (int p = t; p < k; p += WG) qpos[p] = bsearch_i32(ecol, elo, elo + ek, mcol[mlo + p]);
+    __syncthreads();
+    const int r = lane & 15, cq = lane >> 4;   // operand row, column within the group of four
+    d4_t dg = {0.0, 0.0, 0.0, 0.0}, dh = {0.0, 0.0, 0.0, 0.0};
+    for (int p = wave; p < k; p += WG / 64) {
+        const int q = cached ? qpos[p] : bsearch_i32(ecol, elo, elo + ek, mcol[mlo + p]);
+        const double *mb = mval + (int64_t)(mlo + p) * NB2;
+        const double *eb = eval + (int64_t)(q >= 0 ? q : 0) * NB2;   // block 0 when q < 0: read, then discarded
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = 4 * j + cq;
+            const double am = mb[r * 16 + c];
+            const double ve = eb[r * 16 + c];   // eb is a valid block even when q < 0
+            const double ae = q >= 0 ? ve : 0.0;
+            dg = __builtin_amdgcn_mfma_f64_16x16x4f64(am, am, dg, 0, 0, 0);
+            dh = __builtin_amdgcn_mfma_f64_16x16x4f64(ae, am, dh, 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+        part[wave][0][4 * x + cq][r] = dg[x];
+        part[wave][1][4 * x + cq][r] = dh[x];
+    }
+    __syncthreads();
+    for (int e = t; e < NB2; e += WG) {
+        const int x = e / NBT, y = e % NBT;
+        double g = 0.0, h = 0.0;
+#pragma unroll
+        for (int w = 0; w < WG / 64; ++w) {
+            g += part[w][0][x][y];
+            h += part[w][1][x][y];
+        }
+        G[e] = g;
+        H[e] = h;
+    }
+    __syncthreads();
+    normal_solve(G, H, Lc, V, NBT, lamt + (int64_t)i * NB2, singular + li);
+}
+
 // Point blocks (n = 1): one wavefront per list row, four rows per workgroup.
 // M_i[p] = sum_j a~_ij E_j[col p]; Lambda~_i = H_i / G_i with G_i = sum M_i^2,
 // H_i = sum E_i M_i (0 when G_i = 0, the minimum-norm solution).  Lane striding
@@ -2592,7 +2657,11 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
                     case 2: go(std::integral_constant<int, 2>{}); break;
                     case 4: go(std::integral_constant<int, 4>{}); break;
                     case 8: go(std::integral_constant<int, 8>{}); break;
-                    case 16: go(std::integral_constant<int, 16>{}); break;
+                    case 16:
+                        hipLaunchKernelGGL(k_gram_mfma, dim3(nl), dim3(WG), 0, s, dlist, mp.ptr.get(),
+                                           mp.col.get(), mval.get(), E.pat.ptr.get(), E.pat.col.get(),
+                                           E.val.get(), lam_l, sing.get());
+                        break;
                     default: go(std::integral_constant<int, 0>{}); break;
                 }
             }
