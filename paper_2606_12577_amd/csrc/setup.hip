@@ -1381,7 +1381,7 @@ __global__ __launch_bounds__(WG) void k_eupdate(int B, int nb_rt, const int32_t 
                                                 const int32_t *__restrict__ ecol, const double *__restrict__ eval,
                                                 const double *__restrict__ lamt, const int32_t *__restrict__ nptr,
                                                 int32_t *__restrict__ ncol, double *__restrict__ nval) {
-    constexpr int QCAP = 4096;   // block positions of a row kept in LDS
+    constexpr int QCAP = NBT == 1 ? 256 : 4096;   // block positions of a row kept in LDS (point rows are short)
     __shared__ int32_t qpos[QCAP];
     const int i = blockIdx.x;
     if (i >= B) return;
