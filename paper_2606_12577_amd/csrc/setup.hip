@@ -1817,7 +1817,10 @@ __global__ void k_cast32(int64_t n, const double *__restrict__ a, float *__restr
 // column blocks), round r the class of the row at round r - 1 and those of
 // its neighbours, by offset.  A 64-bit key per block finds a candidate (the
 // smallest block with the same key, through an open-addressing table); the
-// candidate is then checked exactly, so a key collision only costs sharing.
+// candidate is then checked exactly, so a key collision can only make a block
+// its own representative (a lost share), never a wrong one.  The constants
+// mixed into the keys are arbitrary odd 64-bit words that keep the inputs
+// (offsets, positions, values, classes) apart.
 // ---------------------------------------------------------------------------
 struct LatDev {
     const int32_t *xyz;   // [B][3] lattice points (unused axes 0)
