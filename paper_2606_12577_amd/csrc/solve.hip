@@ -94,11 +94,12 @@ __device__ __forceinline__ Tiles my_tiles(int64_t ntiles) {
 }
 
 // Streaming (non-temporal) loads for the per-sweep data that is not worth
-// caching (Lambda, b), so that the caches keep the gathered x.  The matrix
+// caching (Lambda, b), so that the caches keep the gathered x.  FP32 matrix
 // entries (column, value) are loaded normally: every sweep of a level reads
 // the same A, which then stays in the 256 MB last-level cache between sweeps
 // (128^3 interface sweep 74.8 -> 70.5 us; caching Lambda or b as well was
-// slower: 79 us).
+// slower: 79 us).  FP64 matrices keep streaming loads: at these sizes they do
+// not fit beside the FP64 vectors (the 128^3 FP64 V-cycle was 6% slower).
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
@@ -147,8 +148,13 @@ __device__ __forceinline__ void spmv_fixed(const int32_t *__restrict__ scol, con
     TA aa[L];
 #pragma unroll
     for (int u = 0; u < L; ++u) {
-        cc[u] = scol[off + (int64_t)u * 64];
-        aa[u] = sval[off + (int64_t)u * 64];
+        if constexpr (sizeof(TA) == 4) {   // FP32 matrices: keep A in the caches (see above)
+            cc[u] = scol[off + (int64_t)u * 64];
+            aa[u] = sval[off + (int64_t)u * 64];
+        } else {
+            cc[u] = __builtin_nontemporal_load(scol + off + (int64_t)u * 64);
+            aa[u] = __builtin_nontemporal_load(sval + off + (int64_t)u * 64);
+        }
     }
     T xv[L][R];
 #pragma unroll
@@ -202,8 +208,13 @@ __device__ __forceinline__ void spmv_fixed_blk(const int32_t *__restrict__ scol,
     T aa[L];
 #pragma unroll
     for (int u = 0; u < L; ++u) {
-        cc[u] = scol[off + (int64_t)u * 64];
-        aa[u] = sval[off + (int64_t)u * 64];
+        if constexpr (sizeof(T) == 4) {   // FP32 matrices: keep A in the caches (see above)
+            cc[u] = scol[off + (int64_t)u * 64];
+            aa[u] = sval[off + (int64_t)u * 64];
+        } else {
+            cc[u] = __builtin_nontemporal_load(scol + off + (int64_t)u * 64);
+            aa[u] = __builtin_nontemporal_load(sval + off + (int64_t)u * 64);
+        }
     }
     const int64_t blk = row / NB;
     const int lbase = lane & ~(NB - 1);
