@@ -1767,23 +1767,22 @@ __global__ void k_gauss_jordan(const double *__restrict__ in, double *__restrict
 
 // One Gauss-Jordan pivot step k applied to every segment's dense matrix at
 // once; segments already past their size are copied unchanged.
-__global__ void k_gauss_jordan_seg(const double *__restrict__ in, double *__restrict__ out, int64_t tot, int nseg,
-                                   const int64_t *__restrict__ off, int k) {
+// One Gauss-Jordan step k on the segments that are still active: segments are
+// packed largest first, so the active ones are a prefix [0, nact) and their
+// entries the range [0, soff[nact]).  Segment q is m[q] x m[q], row-major.
+__global__ void k_gauss_jordan_seg(const double *__restrict__ in, double *__restrict__ out, int nact,
+                                   const int64_t *__restrict__ soff, const int32_t *__restrict__ msz, int k) {
     const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (e >= tot) return;
-    int lo = 0, hi = nseg;   // segment q with off[q] <= e < off[q+1]
+    if (e >= soff[nact]) return;
+    int lo = 0, hi = nact;   // segment q with soff[q] <= e < soff[q+1]
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (off[mid] <= e) lo = mid;
+        if (soff[mid] <= e) lo = mid;
         else hi = mid;
     }
-    const int64_t base = off[lo];
-    const int64_t m = (int64_t)llround(sqrt((double)(off[lo + 1] - base)));
-    if (k >= m) {
-        out[e] = in[e];
-        return;
-    }
-    const int64_t loc = e - base, i = loc / m, j = loc % m;
+    const int64_t base = soff[lo];
+    const int m = msz[lo];
+    const int loc = (int)(e - base), i = loc / m, j = loc % m;
     const double *a = in + base;
     const double p = a[k * m + k];
     double v;
@@ -1793,6 +1792,23 @@ __global__ void k_gauss_jordan_seg(const double *__restrict__ in, double *__rest
         v = (j == k) ? -f / p : a[loc] - f * a[k * m + j] / p;
     }
     out[e] = v;
+}
+
+// Final inverses into their places: packed segment q finished in buffer b1
+// when its size is odd (steps alternate a -> b -> a ...), else in b0.
+__global__ void k_gauss_jordan_collect(int64_t tot, int nseg, const int64_t *__restrict__ soff,
+                                       const int32_t *__restrict__ msz, const int64_t *__restrict__ dst_off,
+                                       const double *__restrict__ b0, const double *__restrict__ b1,
+                                       double *__restrict__ out) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= tot) return;
+    int lo = 0, hi = nseg;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (soff[mid] <= e) lo = mid;
+        else hi = mid;
+    }
+    out[dst_off[lo] + (e - soff[lo])] = (msz[lo] & 1) ? b1[e] : b0[e];
 }
 
 __global__ void k_transpose_blocks64(int64_t nblk, int nb, const double *__restrict__ a, double *__restrict__ at) {
@@ -2990,16 +3006,49 @@ void factor_direct(Ctx &c, Level &L) {
                 dense[off + (size_t)(r - r0) * m + (L.h_col[e] - r0)] += L.h_val[e];
         off += (size_t)m * m;
     }
-    DBuf<double> a(L.dinv.n), b(L.dinv.n);
-    a.upload(dense.data(), dense.size(), c.stream);
-    const int64_t tot = (int64_t)L.dinv.n;
-    for (int k = 0; k < L.dseg_max; ++k) {
-        hipLaunchKernelGGL(k_gauss_jordan_seg, dim3(grid_for(tot)), dim3(WG), 0, c.stream, a.get(), b.get(), tot,
-                           nseg, L.dinv_off.get(), k);
-        std::swap(a, b);
+    // pack the segments largest first: step k then works on the prefix of
+    // segments larger than k only
+    std::vector<int> ord(nseg);
+    for (int q = 0; q < nseg; ++q) ord[q] = q;
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+        return L.dseg[x + 1] - L.dseg[x] > L.dseg[y + 1] - L.dseg[y];
+    });
+    std::vector<int64_t> src_off(nseg + 1, 0), soff(nseg + 1, 0), dst_off(nseg);
+    std::vector<int32_t> msz(nseg);
+    for (int q = 0; q < nseg; ++q) {
+        const int64_t m = L.dseg[q + 1] - L.dseg[q];
+        src_off[q + 1] = src_off[q] + m * m;
     }
+    std::vector<double> packed(dense.size());
+    for (int t = 0; t < nseg; ++t) {
+        const int q = ord[t];
+        const int64_t m = L.dseg[q + 1] - L.dseg[q];
+        msz[t] = (int32_t)m;
+        dst_off[t] = src_off[q];
+        soff[t + 1] = soff[t] + m * m;
+        std::copy(dense.begin() + src_off[q], dense.begin() + src_off[q + 1], packed.begin() + soff[t]);
+    }
+    const int64_t tot = (int64_t)L.dinv.n;
+    DBuf<double> a(tot), b(tot);
+    DBuf<int64_t> soff_d, dst_d;
+    DBuf<int32_t> msz_d;
+    a.upload(packed.data(), packed.size(), c.stream);
+    soff_d.upload(soff.data(), soff.size(), c.stream);
+    dst_d.upload(dst_off.data(), dst_off.size(), c.stream);
+    msz_d.upload(msz.data(), msz.size(), c.stream);
+    // step k reads buffer (k even ? a : b) and writes the other one
+    int nact = nseg;
+    for (int k = 0; k < L.dseg_max; ++k) {
+        while (nact > 0 && msz[nact - 1] <= k) --nact;
+        const int64_t n_el = soff[nact];
+        const double *in = (k & 1) ? b.get() : a.get();
+        double *out = (k & 1) ? a.get() : b.get();
+        hipLaunchKernelGGL(k_gauss_jordan_seg, dim3(grid_for(n_el)), dim3(WG), 0, c.stream, in, out, nact,
+                           soff_d.get(), msz_d.get(), k);
+    }
+    hipLaunchKernelGGL(k_gauss_jordan_collect, dim3(grid_for(tot)), dim3(WG), 0, c.stream, tot, nseg, soff_d.get(),
+                       msz_d.get(), dst_d.get(), a.get(), b.get(), L.dinv.get());
     CS_LAUNCH_CHECK();
-    CS_HIP(hipMemcpyAsync(L.dinv.get(), a.get(), tot * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
     CS_HIP(hipStreamSynchronize(c.stream));
 }
 
