@@ -261,6 +261,7 @@ void cs_destroy(cs_ctx ctx) {
     }
     if (ctx->c.ev_in) (void)hipEventDestroy(ctx->c.ev_in);
     if (ctx->c.ev_out) (void)hipEventDestroy(ctx->c.ev_out);
+    if (ctx->c.ev_norm) (void)hipEventDestroy(ctx->c.ev_norm);
     if (ctx->c.h_norm) (void)hipHostFree(ctx->c.h_norm);
     if (ctx->c.gm_host) (void)hipHostFree(ctx->c.gm_host);
     if (ctx->c.ev0) (void)hipEventDestroy(ctx->c.ev0);

@@ -247,6 +247,11 @@ struct Ctx {
     uint64_t gen = 0;                   // bumped whenever device buffers the graph uses change
     hipStream_t work = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    // CG: the next V-cycle's first level-0 sweep is issued before the host
+    // reads the convergence norms (ev_norm marks their download); spec_pending
+    // tells the next level-0 V-cycle that this sweep is already on the stream
+    hipEvent_t ev_norm = nullptr;
+    bool spec_pending = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     struct GraphKey {

@@ -1453,7 +1453,7 @@ __global__ void k_ovl_fuse(int64_t n, const int32_t *__restrict__ iptr, const in
 // given (additive only), the first sweep reads x - P x_c instead of x.
 template <typename T, int R>
 T *apply_cascade(Ctx &c, const Level &L, bool reverse, bool zero_start, const T *b, T *x, T *alt,
-                 const T *xc = nullptr) {
+                 const T *xc = nullptr, int s_begin = 0) {
     const int64_t nbl = L.B * L.nb * L.nb;
     const int depth = L.depth;
     if (L.ovl_m) {
@@ -1487,8 +1487,10 @@ T *apply_cascade(Ctx &c, const Level &L, bool reverse, bool zero_start, const T 
         return cur;
     }
     if (c.opt.mode == CS_ADDITIVE) {
+        // s_begin = 1: step 0 (from zero, into alt) is already on the stream
         T *cur = x, *nxt = alt;
-        for (int s = 0; s < depth; ++s) {
+        if (s_begin == 1) std::swap(cur, nxt);
+        for (int s = s_begin; s < depth; ++s) {
             const int ell = reverse ? depth - 1 - s : s;
             const T *lam = lam_ptr<T>(L, reverse) + (int64_t)ell * nbl;
             launch_sweep<T, R>(c, L, L.sell, false, zero_start && s == 0, lam, b, cur, nxt, s == 0 ? xc : nullptr,
@@ -1539,6 +1541,24 @@ void direct_solve(Ctx &c, const Level &L, const T *b, T *x) {
 // V-cycle (Alg. 1) from level l down: x_l = V(b_l) from the zero guess, with
 // b_l in bb and the result in xb.  Only the active rows are smoothed and
 // transferred; the direct segments of every level are solved exactly.
+// The first sweep of the next level-0 V-cycle, issued ahead: an additive
+// cascade's first pre-smoothing step starts from zero and reads only the
+// right-hand side (L0.bb) and Lambda, so it can run while the host checks
+// convergence.  Returns whether it was issued.
+template <typename T, int R>
+bool issue_first_sweep(Ctx &c) {
+    if (c.lv.size() < 2 || c.opt.mode != CS_ADDITIVE || c.opt.n_pre < 1) return false;
+    Level &L = c.lv[0];
+    if (L.ovl_m || L.depth < 1) return false;
+    const bool reverse = c.opt.order == CS_RF;
+    const int ell = reverse ? L.depth - 1 : 0;
+    const T *lam = lam_ptr<T>(L, reverse) + (int64_t)ell * (L.B * L.nb * L.nb);
+    launch_sweep<T, R>(c, L, L.sell, false, true, lam, reinterpret_cast<const T *>(L.bb.get()),
+                       reinterpret_cast<T *>(L.xb.get()), reinterpret_cast<T *>(L.xt.get()), nullptr, L.agg_k);
+    c.spec_pending = true;
+    return true;
+}
+
 template <typename T, int R>
 void vcycle_level(Ctx &c, int l) {
     Level &L = c.lv[l];
@@ -1556,7 +1576,9 @@ void vcycle_level(Ctx &c, int l) {
     T *x = xb, *alt = xt;
     const bool rf = c.opt.order == CS_RF;
     for (int a = 0; a < c.opt.n_pre; ++a) {
-        T *res = apply_cascade<T, R>(c, L, rf, a == 0, bb, x, alt);
+        const int s0 = (l == 0 && a == 0 && c.spec_pending) ? 1 : 0;
+        if (s0) c.spec_pending = false;
+        T *res = apply_cascade<T, R>(c, L, rf, a == 0, bb, x, alt, nullptr, s0);
         if (res != x) std::swap(x, alt);
     }
     // restricted residual
@@ -2066,10 +2088,17 @@ void solve_cg(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
             Monitor mon(c, nsys, R, rtol);
             int it = 0;
             int cur = 0;
+            if (!c.ev_norm) CS_HIP(hipEventCreateWithFlags(&c.ev_norm, hipEventDisableTiming));
+            struct SpecReset {   // however the loop ends, no later V-cycle skips its first sweep
+                Ctx &c;
+                ~SpecReset() { c.spec_pending = false; }
+            } spec_reset{c};
             for (;; ++it) {
                 CS_HIP(hipMemcpyAsync(c.h_norm, c.ir_norm.get(), 2 * nsys * R * sizeof(double),
                                       hipMemcpyDeviceToHost, c.stream));
-                CS_HIP(hipStreamSynchronize(c.stream));
+                CS_HIP(hipEventRecord(c.ev_norm, c.stream));
+                if (it < maxit) issue_first_sweep<T, R>(c);   // wasted (one sweep) when this check ends the solve
+                CS_HIP(hipEventSynchronize(c.ev_norm));
                 const double rel = mon.record(it, c.h_norm);
                 if (std::isnan(rel)) {
                     *st = CS_ENAN;
