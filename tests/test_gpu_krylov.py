@@ -185,3 +185,27 @@ def test_gmres_rhs_counts_and_ragged_batch(gpu_lib, nrhs):
             pre = lambda v: O.vcycle(p.levels, sms[si], v, "FF")
             xo, _ = O.gmres(p.levels[0].A, pre, p.rhs, restart=7, rtol=1e-10, maxit=200, flexible=flexible)
             assert rel(xs[si], xo) <= 1e-7, (si, flexible, rel(xs[si], xo))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_vcycle_after_cg_is_unaffected(gpu_lib, precision):
+    """CG issues the next V-cycle's first sweep before it reads the convergence
+    norms; once a solve ends (converged or at maxit) that sweep must not leak into
+    a later V-cycle: the V-cycle equals that of a fresh solver bit for bit."""
+    p = fd.interface3d(32, nrhs=8)
+    rng = stream(9, TEST, 1)
+    v = rng.uniform(-1, 1, size=p.rhs.shape)
+    s = gpu_lib.Solver(p.levels)
+    s.setup(depth=4, precision=precision)
+    ref = gpu_lib.Solver(p.levels)
+    ref.setup(depth=4, precision=precision)
+    expect = ref.vcycle(v).cpu().numpy()
+    s.solve(p.rhs, rtol=1e-10, maxit=100, method="cg")
+    np.testing.assert_array_equal(s.vcycle(v).cpu().numpy(), expect)
+    s.solve(p.rhs, rtol=1e-30, maxit=3, method="cg", raise_on_noconv=False)
+    np.testing.assert_array_equal(s.vcycle(v).cpu().numpy(), expect)
+    # and CG itself is unchanged by a V-cycle in between
+    x1, i1 = s.solve(p.rhs, rtol=1e-10, maxit=100, method="cg")
+    x2, i2 = ref.solve(p.rhs, rtol=1e-10, maxit=100, method="cg")
+    assert i1["iterations"] == i2["iterations"]
+    np.testing.assert_array_equal(x1.cpu().numpy(), x2.cpu().numpy())
