@@ -41,7 +41,6 @@ extern "C" {
 #define CS_ABI_VERSION 2
 
 typedef struct cs_ctx_s *cs_ctx;
-typedef struct cs_batch_s *cs_batch;
 
 typedef enum {
     CS_OK = 0,
@@ -215,7 +214,7 @@ cs_status cs_solve_gmres(cs_ctx ctx, const double *b, double *x, int32_t nrhs, d
  * Residual patterns (cs_get_pattern) are not available after this setup. */
 cs_status cs_setup_sketched(cs_ctx ctx, const cs_options *opt, int32_t s, const double *S);
 
-/* Overlapping blocks for `level` (Sec. 3.5.2): n_blocks blocks of m slots
+/* Overlapping blocks for `level` (Sec. 3.6.2): n_blocks blocks of m slots
  * (1 <= m <= 16); nodes (host int32[n_blocks][m]) names the unknown of every
  * slot, -1 for an unused slot; every unknown must lie in at least one block
  * (theta = its multiplicity).  The level's cascade becomes
@@ -243,7 +242,7 @@ cs_status cs_set_overlapping_blocks(cs_ctx ctx, int32_t level, int64_t n_blocks,
  * without a positive diagonal or a pressure row coupled to no velocity. */
 cs_status cs_set_saddle_point(cs_ctx ctx, int32_t level, const int32_t *kind, int32_t l1);
 
-/* Stencil-repetition setup cache (Sec. 5, caching the repeated local setups of
+/* Stencil-repetition setup cache (Sec. 4, caching the repeated local setups of
  * structured meshes).  coords (host int32[n_blocks][dim], dim 1..3, each
  * coordinate in (-2^28, 2^28), bounding box at most 2^28 points) places every
  * block of `level` at a distinct integer lattice point; the library keeps a

@@ -332,7 +332,7 @@ def fit_sketched(A: sp.spmatrix, n: int, depth: int, S: np.ndarray, mode: str = 
 
 
 def replication(nodes: np.ndarray, N: int):
-    """Theta (Sec. 3.5.2): the tall binary matrix that copies nodal values into
+    """Theta (Sec. 3.6.2): the tall binary matrix that copies nodal values into
     the slots of overlapping blocks (nodes[i][s] = node of slot s of block i,
     -1 for an unused slot, which gets a zero row), and theta = its column sums,
     the multiplicity of every node."""
@@ -346,7 +346,7 @@ def replication(nodes: np.ndarray, N: int):
 
 def fit_overlapping(A: sp.spmatrix, nodes: np.ndarray, depth: int, S: Optional[np.ndarray] = None,
                     kind: Optional[np.ndarray] = None, norm: str = "max") -> Dict:
-    """Overlapping-block additive cascade (Sec. 3.5.2), on the prescaled A~:
+    """Overlapping-block additive cascade (Sec. 3.6.2), on the prescaled A~:
         Lambda_l = argmin_{Lambda block-diagonal over the slots}
                    ||(Theta - Lambda Theta A~) E_{l-1}||_F,
         E_l = diag(theta)^{-1} Theta^T (Theta - Lambda_l Theta A~) E_{l-1},
@@ -392,7 +392,7 @@ def fit_overlapping(A: sp.spmatrix, nodes: np.ndarray, depth: int, S: Optional[n
 
 def smooth_overlapping(A: sp.spmatrix, sm: Dict, x: np.ndarray, b: np.ndarray) -> np.ndarray:
     """One forward application of an overlapping-block additive cascade
-    (Sec. 3.5.2): x <- x - diag(theta)^{-1} Theta^T Lambda_l Theta (A x - b),
+    (Sec. 3.6.2): x <- x - diag(theta)^{-1} Theta^T Lambda_l Theta (A x - b),
     l = 1..nu."""
     Th, theta = replication(sm["nodes"], A.shape[0])
     Dinv = sp.diags(1.0 / theta)
@@ -720,7 +720,7 @@ def fit_local(A: sp.spmatrix, n: int, depth: int, centres: Sequence[int], mode: 
 
 
 # ---------------------------------------------------------------------------
-# Stencil repetition (Sec. 5, caching repeated local setups on structured meshes)
+# Stencil repetition (Sec. 4, caching repeated local setups on structured meshes)
 # ---------------------------------------------------------------------------
 
 def lattice_row_signatures(A: sp.spmatrix, n: int, coords: np.ndarray) -> List[bytes]:

@@ -230,7 +230,7 @@ class Solver:
                 self.set_saddle_point(i, kind, l1=True)
 
     def set_overlapping_blocks(self, level: int, nodes=None):
-        """Overlapping blocks for a level (Sec. 3.5.2): nodes[i][s] is the
+        """Overlapping blocks for a level (Sec. 3.6.2): nodes[i][s] is the
         unknown of slot s of block i (-1 unused); None restores the partition.
         Such levels are fitted by setup_sketched (additive, FF)."""
         if nodes is None:
@@ -259,7 +259,7 @@ class Solver:
         self._check(self._lib.cs_set_saddle_point(self._h, level, _ptr(k, _I32), int(bool(l1))))
 
     def set_lattice(self, level: int, coords=None):
-        """Stencil-repetition cache for a level (Sec. 5): coords (n_blocks x
+        """Stencil-repetition cache for a level (Sec. 4): coords (n_blocks x
         dim integer lattice points, distinct) lets the exact additive setup fit
         one block per class of translation-equivalent neighbourhoods and copy
         the rest.  None removes it."""

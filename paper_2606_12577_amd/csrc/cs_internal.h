@@ -119,7 +119,7 @@ struct Level {
     // 1 pressure, 2 inert (scaled as a velocity); empty for an elliptic level
     DBuf<int32_t> kind;
     int stokes_l1 = 0;                // constraint rows normalised by the 1-norm (else max-norm)
-    // overlapping blocks (Sec. 3.5.2): ovl_m slots per block, ovl_nodes[i][s] the
+    // overlapping blocks (Sec. 3.6.2): ovl_m slots per block, ovl_nodes[i][s] the
     // unknown of slot s of block i (-1 unused), the occurrences of every unknown
     // (CSR over block * m + slot) and 1 / multiplicity.  The smoothers of such a
     // level are [depth][ovl_nblk][ovl_m][ovl_m] in lam64 / lam32.
@@ -128,7 +128,7 @@ struct Level {
     DBuf<int32_t> ovl_nodes, ovl_inv_ptr, ovl_inv_idx;
     DBuf<double> ovl_rtheta;
     DBuf<unsigned char> ovl_y;        // replicated workspace [nblk][m][R] (working precision)
-    // stencil-repetition cache (Sec. 5): lattice point of every block (lat_dim
+    // stencil-repetition cache (Sec. 4): lattice point of every block (lat_dim
     // 0: none), the box map point -> block, and of the last exact fit the class
     // representatives [depth][B] (radius ell - 1 for cascade step ell) and the
     // blocks fitted per step

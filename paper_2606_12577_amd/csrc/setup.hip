@@ -1058,7 +1058,7 @@ __global__ __launch_bounds__(WG) void k_sk_solve(const int32_t *__restrict__ lis
     normal_solve(G, H, Lc, V, nb, lamt + (int64_t)list[wi] * nb2, singular + wi);
 }
 
-// ---- overlapping blocks (Sec. 3.5.2), sketched form -------------------------
+// ---- overlapping blocks (Sec. 3.6.2), sketched form -------------------------
 // M = A~ T on every row (one wavefront per row, lane = sketch column)
 __global__ __launch_bounds__(WG) void k_sk_rows(int64_t n, const int32_t *__restrict__ aptr,
                                                 const int32_t *__restrict__ acol, const double *__restrict__ aval,
@@ -1159,7 +1159,7 @@ __global__ void k_ovl_unscale(int64_t nblk, int m, const int32_t *__restrict__ n
     lam[e] = (kr >= 0 && kc >= 0) ? w[kr] * lamt[e] * w[kc] : 0.0;
 }
 
-// ---- overlapping blocks, exact form (Sec. 3.5.2): scalar residual E ----------
+// ---- overlapping blocks, exact form (Sec. 3.6.2): scalar residual E ----------
 // Prescaled values of A on its own pattern: a~_jl = w_j a_jl w_l
 __global__ void k_prescaled_csr(int64_t n, const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
                                 const double *__restrict__ val, const double *__restrict__ w,
@@ -1826,7 +1826,7 @@ __global__ void k_cast32(int64_t n, const double *__restrict__ a, float *__restr
 }
 
 // ---------------------------------------------------------------------------
-// Stencil-repetition cache (Sec. 5): blocks at integer lattice points whose
+// Stencil-repetition cache (Sec. 4): blocks at integer lattice points whose
 // neighbourhoods coincide under translation share one cascade fit.  Classes
 // are refined one block layer per round: round 0 compares the block rows of A
 // (offsets to the block columns, the stored values, the diagonals of the
@@ -2768,7 +2768,7 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
     CS_HIP(hipStreamSynchronize(s));
 }
 
-// Exact fit of a level with overlapping blocks (Sec. 3.5.2): scalar residual
+// Exact fit of a level with overlapping blocks (Sec. 3.6.2): scalar residual
 // E (CSR over nodes), per cascade level M = A~ E on every node (symbolic union
 // and the point row product), the blockwise normal equations over the slots,
 // and E_new = diag(theta)^{-1} Theta^T (Theta E - Lambda~ Theta M) row by row.
@@ -2866,7 +2866,7 @@ void fit_level_overlap_exact(Ctx &c, Level &L, const cs_options &o) {
     CS_HIP(hipStreamSynchronize(s));
 }
 
-// Sketched fit of a level with overlapping blocks (Sec. 3.5.2 with the sketch
+// Sketched fit of a level with overlapping blocks (Sec. 3.6.2 with the sketch
 // of Sec. 4): per cascade level M = A~ T, the blockwise normal equations over
 // the replicated slots, then T <- diag(theta)^{-1} Theta^T (Theta T - Lambda~ Theta M),
 // i.e. T_k -= (1/theta_k) sum over the slots of k of (Lambda~ M)_slot.

@@ -1392,7 +1392,7 @@ void launch_sweep(Ctx &c, const Level &L, const Sell &S, bool rowmap, bool zero,
     if (slot <= -2) trace_end(c, slot);
 }
 
-// Overlapping blocks (Sec. 3.5.2): y = Lambda_l Theta r over the replicated
+// Overlapping blocks (Sec. 3.6.2): y = Lambda_l Theta r over the replicated
 // slots, r = A x - b (or -b on a zero guess), one thread per (block, slot).
 template <typename T, int R>
 __global__ void k_ovl_apply(int64_t nblk, int m, const int32_t *__restrict__ nodes, const T *__restrict__ lam,
@@ -2022,9 +2022,10 @@ void solve_cg(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
         c.cg_p.alloc(n);
         c.cg_q.alloc(n);
     }
-    c.cg_zq.alloc((size_t)nsys * nrhs);
-    c.cg_pq[0].alloc((size_t)nsys * 2 * nrhs);
-    c.cg_pq[1].alloc((size_t)nsys * 2 * nrhs);
+    // grown only: a release would synchronise the device (the pool waits as hipFree does)
+    if (c.cg_zq.n < (size_t)nsys * nrhs) c.cg_zq.alloc((size_t)nsys * nrhs);
+    for (auto &pq : c.cg_pq)
+        if (pq.n < (size_t)nsys * 2 * nrhs) pq.alloc((size_t)nsys * 2 * nrhs);
     double *r = c.cg_r.get(), *p = c.cg_p.get(), *q = c.cg_q.get();
     *st = CS_OK;
     CS_HIP(hipEventRecord(c.ev0, c.stream));

@@ -1,4 +1,4 @@
-"""2D Stokes on a MAC staggered grid (Sec. 3.5.1 setting), closed unit box.
+"""2D Stokes on a MAC staggered grid (Sec. 3.6.1 setting), closed unit box.
 
 Unknowns per cell (i, j) (cell index c = i + n j, block of 4, scalar 4c + s):
   s = 0  u at the cell's right face  (x = (i+1) h, y = (j+1/2) h)

@@ -21,3 +21,13 @@ def gpu_lib():
         pytest.fail("GPU test collected without a visible GPU")
     from paper_2606_12577_amd import cascade
     return cascade
+
+
+def pytest_terminal_summary(terminalreporter):
+    """Print the achieved parity ratios (error / bound) the GPU tests recorded."""
+    try:
+        import parity
+    except ImportError:
+        return
+    for line in parity.summary_lines():
+        terminalreporter.write_line(line)

@@ -1,0 +1,108 @@
+"""Parity bounds shared by the GPU tests (imported by them; not collected).
+
+Smoother blocks.  The GPU and the oracle form G_i = M_i M_i^T and
+H_i = E_i M_i^T with different summation orders, so G_i and H_i differ by
+about k u relative (u = 2^-53, k the number of summands, at most a few
+thousand here).  Solving Lambda_i G_i = H_i amplifies that by cond(G_i), and
+an earlier cascade level's difference enters E and every later fit, so the
+bound of block i at level l is
+
+    C_SUM * u * max(cond(G_{l,i}), max_{e<l} max_j cond(G_{e,j}))
+
+with C_SUM = 4096 and the condition numbers the oracle reports (restricted to
+the eigenvalues its minimum-norm solve keeps).  There is no fixed floor: a
+well-conditioned block is held to ~5e-13.
+
+Vectors.  Every comparison checks the global relative 2-norm and the
+per-entry maximum relative to the largest entry, so an error confined to a
+few rows (boundary rows, a direct segment) cannot hide under the norm.
+
+Achieved ratios (error / bound) are recorded and printed in the terminal
+summary of the run.
+"""
+import numpy as np
+
+U = 2.0 ** -53
+C_SUM = 4096.0
+# FP64 V-cycle with the GPU's own setup, and with the oracle's smoothers injected
+VCYCLE_TOL = 1e-12
+
+RECORDS = []
+
+
+def record(label, err, bound):
+    ratio = float(err) / float(bound) if bound > 0 else float("inf")
+    RECORDS.append((label, float(err), float(bound), ratio))
+    return ratio
+
+
+def rel2(g, o):
+    g = np.asarray(g, dtype=np.float64)
+    o = np.asarray(o, dtype=np.float64)
+    return float(np.linalg.norm(g - o) / max(np.linalg.norm(o), 1e-300))
+
+
+def relinf(g, o):
+    g = np.asarray(g, dtype=np.float64)
+    o = np.asarray(o, dtype=np.float64)
+    return float(np.max(np.abs(g - o)) / max(np.max(np.abs(o)), 1e-300))
+
+
+def check_vec(g, o, tol, label):
+    """Global 2-norm and per-entry (max-norm) relative error, both <= tol."""
+    e2, ei = rel2(g, o), relinf(g, o)
+    r = max(record(label + " [2-norm]", e2, tol), record(label + " [max-entry]", ei, tol))
+    assert r <= 1.0, (label, e2, ei, tol)
+    return max(e2, ei)
+
+
+def level_bounds(conds, ell):
+    """Per-block bounds at cascade level ell (1-based) from the oracle's
+    per-level, per-block condition numbers conds[0..depth-1]."""
+    cur = np.asarray(conds[ell - 1], dtype=np.float64)
+    prev = max((float(np.max(c)) for c in conds[:ell - 1]), default=1.0)
+    return C_SUM * U * np.maximum(np.maximum(cur, prev), 1.0)
+
+
+def scalar_bound(conds_upto):
+    """Bound for one block given the worst condition numbers met up to its level."""
+    return C_SUM * U * max(1.0, max(conds_upto))
+
+
+def block_errors(g, o):
+    g = np.asarray(g, dtype=np.float64)
+    o = np.asarray(o, dtype=np.float64)
+    num = np.linalg.norm((g - o).reshape(len(g), -1), axis=1)
+    den = np.maximum(np.linalg.norm(o.reshape(len(o), -1), axis=1), 1e-300)
+    return num / den
+
+
+def check_blocks(g, o, bounds, label):
+    """Per-block relative Frobenius error against per-block bounds."""
+    e = block_errors(g, o)
+    bounds = np.broadcast_to(np.asarray(bounds, dtype=np.float64), e.shape)
+    k = int(np.argmax(e / bounds))
+    r = record(label, e[k], bounds[k])
+    assert r <= 1.0, (label, "block", k, float(e[k]), float(bounds[k]))
+    return r
+
+
+def check_level_smoothers(s, sm, level, depth, label, rows=None):
+    """Every Lambda_ell of one level against the oracle's fit sm (a dict with
+    lam and gram_cond); rows selects the GPU blocks that sm describes (a
+    system inside a batch), in sm's order."""
+    for ell in range(1, depth + 1):
+        g = s.get_smoother(level, ell)
+        if rows is not None:
+            g = g[rows]
+        check_blocks(g, sm["lam"][ell - 1], level_bounds(sm["gram_cond"], ell),
+                     f"{label} level {level} Lambda_{ell}")
+
+
+def summary_lines():
+    if not RECORDS:
+        return []
+    out = ["parity: achieved error / bound (largest first)"]
+    for label, err, bound, ratio in sorted(RECORDS, key=lambda t: -t[3]):
+        out.append(f"  {ratio:9.2e}  err {err:9.2e}  bound {bound:9.2e}  {label}")
+    return out

@@ -4,36 +4,27 @@ The batch is one block-diagonal hierarchy (synth.batch): systems that end on
 a level are solved there directly while deeper ones continue.  Every system
 must behave exactly as if it were solved alone, so each expected value is the
 FP64 oracle run on that system by itself.  Tolerances as in the single-system
-parity tests (the arithmetic per system is the same).
+parity tests (the arithmetic per system is the same; bounds in tests/parity.py):
+smoother blocks per block from the oracle's condition numbers of that system,
+FP64 V-cycles 1e-12 per system in the 2-norm and per entry.
 """
 import numpy as np
 import pytest
 
 import oracle as O
+from parity import VCYCLE_TOL, check_blocks, check_vec, level_bounds
 from synth import fd
 from synth.batch import concatenate
 from synth.rng import TEST, stream
 
 pytestmark = pytest.mark.gpu
 
-LAM_TOL = 1e-9
-APPLY_TOL = 1e-12
-SETUP_APPLY_TOL = 1e-10
+APPLY_TOL = VCYCLE_TOL
 FP32_TOL = 1e-5
 
 # 2D log-normal (sigma = 2) FD systems with 3, 4, 5 and 2 levels (coarsest
 # 6^2 .. 8^2), plus a one-level system (all direct on the finest level)
 SIZES = [48, 64, 80, 16, 112, 32, 80, 8]
-
-
-def rel(a, b):
-    return float(np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-300))
-
-
-def blockwise_rel(a, b):
-    num = np.linalg.norm((a - b).reshape(len(a), -1), axis=1)
-    den = np.maximum(np.linalg.norm(b.reshape(len(b), -1), axis=1), 1e-300)
-    return float((num / den).max())
 
 
 @pytest.fixture(scope="module")
@@ -57,9 +48,10 @@ def odd_batch():
     return probs, bt, sms
 
 
-def batch_smoother(bt, sms, l, ell):
+def batch_smoother(bt, sms, l, ell, bounds=False):
     """Oracle smoothers of every system present on batch level l, stacked in
-    the batch order (zeros for the blocks of direct segments)."""
+    the batch order (zeros for the blocks of direct segments); bounds=True
+    stacks the per-block parity bounds of each system's own fit instead."""
     out = []
     for s in bt.order:
         p = bt.problems[s]
@@ -67,9 +59,9 @@ def batch_smoother(bt, sms, l, ell):
             continue
         lv = p.levels[l]
         if l + 1 < len(p.levels):
-            out.append(sms[s][l]["lam"][ell - 1])
+            out.append(level_bounds(sms[s][l]["gram_cond"], ell) if bounds else sms[s][l]["lam"][ell - 1])
         else:
-            out.append(np.zeros((lv.n_blocks, lv.block_size, lv.block_size)))
+            out.append(np.ones(lv.n_blocks) if bounds else np.zeros((lv.n_blocks, lv.block_size, lv.block_size)))
     return np.concatenate(out)
 
 
@@ -96,7 +88,8 @@ def test_batch_smoother_parity(gpu_lib, small_batch):
         for ell in range(1, 4):
             g = s.get_smoother(l, ell)
             o = batch_smoother(bt, sms, l, ell)
-            assert blockwise_rel(g[:n_act], o[:n_act]) <= LAM_TOL, (l, ell)
+            bnd = batch_smoother(bt, sms, l, ell, bounds=True)
+            check_blocks(g[:n_act], o[:n_act], bnd[:n_act], f"batch level {l} Lambda_{ell}")
 
 
 @pytest.mark.parametrize("which,precision", [("small_batch", "fp64"), ("small_batch", "fp32"),
@@ -109,15 +102,14 @@ def test_batch_vcycle_matches_separate_oracle_vcycles(gpu_lib, which, precision,
     rng = stream(14, TEST, 1)
     bs = [rng.uniform(-1, 1, size=(p.n, nr)) for p in probs]
     expect = [O.vcycle(p.levels, sm, b, "RF", 1, 1) for p, sm, b in zip(probs, sms, bs)]
-    tol = SETUP_APPLY_TOL if precision == "fp64" else FP32_TOL
+    tol = APPLY_TOL if precision == "fp64" else FP32_TOL
     g = bt.split(s.vcycle(bt.stack(bs)).cpu().numpy())
     for q in range(len(probs)):
-        assert rel(g[q], expect[q]) <= tol, ("own setup", q, rel(g[q], expect[q]))
+        check_vec(g[q], expect[q], tol, f"{which} {precision} V-cycle system {q}, own setup")
     inject_batch(s, bt, sms)
     g = bt.split(s.vcycle(bt.stack(bs)).cpu().numpy())
-    tol = APPLY_TOL if precision == "fp64" else FP32_TOL
     for q in range(len(probs)):
-        assert rel(g[q], expect[q]) <= tol, ("injected", q, rel(g[q], expect[q]))
+        check_vec(g[q], expect[q], tol, f"{which} {precision} V-cycle system {q}, oracle smoothers")
 
 
 def test_batch_smooth_keeps_direct_rows(gpu_lib, small_batch):
@@ -141,7 +133,7 @@ def test_batch_smooth_keeps_direct_rows(gpu_lib, small_batch):
             continue
         m = p.levels[l].n
         o = O.smooth(p.levels[l].A, sms[q][l], x0[off:off + m], b[off:off + m], reverse=True)
-        assert rel(g[off:off + m], o) <= APPLY_TOL
+        check_vec(g[off:off + m], o, APPLY_TOL, f"batch level {l} cascade apply, system {q}")
         off += m
     assert off == n_act
 

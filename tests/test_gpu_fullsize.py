@@ -16,6 +16,7 @@ import pytest
 import scipy.sparse as sp
 
 import oracle as O
+from parity import VCYCLE_TOL, check_vec, record, scalar_bound
 from synth import fd
 from synth.rng import TEST, stream
 
@@ -62,13 +63,14 @@ def test_fullsize_sampled_smoother_blocks(full):
     rng = stream(2, TEST)
     centres = sorted({0, B - 1, 63, int(mixed[0]), int(mixed[len(mixed) // 2]), int(inside[len(inside) // 2]),
                       *rng.integers(0, B, size=3).tolist()})
-    loc = O.fit_local(A0, 8, DEPTH, centres)
+    loc, cond = O.fit_local(A0, 8, DEPTH, centres, with_cond=True)
     for ell in range(1, DEPTH + 1):
         g = s.get_smoother(0, ell)
         for c in centres:
             o = loc[c][ell - 1]
             e = np.linalg.norm(g[c] - o) / np.linalg.norm(o)
-            assert e <= 1e-9, (c, ell, e)    # cond(G)-scaled, as in test_gpu_parity
+            bound = scalar_bound(cond[c][:ell])   # from the conditioning met in the block's patch
+            assert record(f"interface3d_128 block {c} Lambda_{ell}", e, bound) <= 1.0, (c, ell, e, bound)
 
 
 def test_fullsize_solve_fp32_ir(full):
@@ -102,20 +104,20 @@ def test_fullsize_vcycle_injected_smoothers(full):
     s.set_precision("fp64")
     g = s.vcycle(p.rhs).cpu().numpy()
     o = O.vcycle(p.levels, sm, p.rhs, "RF")
-    e = rel(g, o)
+    e = check_vec(g, o, VCYCLE_TOL, "interface3d_128 FP64 V-cycle, injected smoothers")
     print(f"[fullsize] FP64 V-cycle vs oracle: {e:.2e}")
-    assert e <= 1e-12
     s.set_precision("fp32")
     g32 = s.vcycle(p.rhs).cpu().numpy()
-    e32 = rel(g32, o)
+    e32 = check_vec(g32, o, 1e-5, "interface3d_128 FP32 V-cycle vs FP64 oracle, injected smoothers")
     print(f"[fullsize] FP32 V-cycle vs FP64 oracle: {e32:.2e}")
-    assert e32 <= 1e-5
 
 
 def test_fullsize_lattice_cache(gpu_lib, full):
     """The stencil-repetition cache at full size: every block's smoother equals
-    the uncached fit (blockwise 1e-10), and sampled members of the bulk class
-    and their representatives equal the oracle's patch fit."""
+    the uncached fit (blockwise 1e-10: no oracle fit of all blocks exists at
+    this size), and sampled members of the bulk class and their
+    representatives equal the oracle's patch fit (per-block bounds from the
+    patch's conditioning)."""
     p, _ = full   # the shared solver holds injected smoothers by now: fit a fresh uncached one
     s = gpu_lib.Solver(p.levels)
     s.setup(depth=DEPTH, mode="additive", order="RF", precision="fp32")
@@ -131,14 +133,16 @@ def test_fullsize_lattice_cache(gpu_lib, full):
         g, o = t.get_smoother(0, ell), s.get_smoother(0, ell)
         num = np.linalg.norm((g - o).reshape(B, -1), axis=1)
         den = np.linalg.norm(o.reshape(B, -1), axis=1)
-        assert (num / den).max() <= 1e-10, ell
+        assert record(f"interface3d_128 lattice-cached vs uncached Lambda_{ell}", (num / den).max(), 1e-10) <= 1.0
     members = np.flatnonzero(rep[DEPTH - 1] != np.arange(B))
     rng = stream(3, TEST)
     pick = rng.choice(members, size=3, replace=False)
     centres = sorted({*pick.tolist(), *rep[DEPTH - 1][pick].tolist()})
-    loc = O.fit_local(p.levels[0].A, 8, DEPTH, centres)
+    loc, cond = O.fit_local(p.levels[0].A, 8, DEPTH, centres, with_cond=True)
     for ell in range(1, DEPTH + 1):
         g = t.get_smoother(0, ell)
         for c in centres:
             o = loc[c][ell - 1]
-            assert np.linalg.norm(g[c] - o) / np.linalg.norm(o) <= 1e-9, (c, ell)
+            e = np.linalg.norm(g[c] - o) / np.linalg.norm(o)
+            bound = scalar_bound(cond[c][:ell])
+            assert record(f"interface3d_128 lattice-cached block {c} Lambda_{ell}", e, bound) <= 1.0, (c, ell, e)

@@ -9,15 +9,12 @@ import numpy as np
 import pytest
 
 import oracle as O
+from parity import check_vec
 from synth import fd
 from synth.batch import concatenate
 from synth.rng import TEST, stream
 
 pytestmark = pytest.mark.gpu
-
-
-def rel(a, b):
-    return float(np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-300))
 
 
 def inject(s, sm):
@@ -43,7 +40,7 @@ def test_cg_matches_oracle_fcg(gpu_lib, name, make, depth, nv):
     x, info = s.solve(p.rhs, rtol=1e-10, maxit=100, method="cg")
     assert info["iterations"] == len(ho) - 1
     np.testing.assert_allclose(info["history"], ho, rtol=1e-6)
-    assert rel(x.cpu().numpy(), xo) <= 1e-8
+    check_vec(x.cpu().numpy(), xo, 1e-8, "FCG iterate vs oracle")
 
 
 def test_cg_beats_refinement_and_fp32_converges(gpu_lib):
@@ -112,7 +109,7 @@ def test_gmres_matches_oracle(gpu_lib, name, make, depth, order, restart, flexib
     # (absolute, in the history's relative units; the 1e4 contrast makes ||A|| ||x||
     # large), and the next cycle starts from it: 1e-13 absolute beside 1e-6 relative
     np.testing.assert_allclose(info["history"], ho, rtol=1e-6, atol=1e-13)
-    assert rel(x.cpu().numpy(), xo) <= 1e-8
+    check_vec(x.cpu().numpy(), xo, 1e-8, f"GMRES {name} restart={restart} flexible={flexible} iterate vs oracle")
     r = p.rhs - p.levels[0].A @ x.cpu().numpy()
     true = np.max(np.linalg.norm(r, axis=0) / np.linalg.norm(p.rhs, axis=0))
     assert true <= (1e-10 if flexible else 1e-7)
@@ -160,7 +157,7 @@ def test_batched_gmres_runs_every_system_as_if_alone(gpu_lib):
             p = probs[si]
             pre = lambda v: O.vcycle(p.levels, sms[si], v, "FF")
             xo, h = O.gmres(p.levels[0].A, pre, p.rhs, restart=30, rtol=rtol, maxit=200, flexible=flexible)
-            assert rel(xs[si], xo) <= 1e-7, (q, flexible, rel(xs[si], xo))
+            check_vec(xs[si], xo, 1e-7, f"krylov batch system {q} flexible={flexible} iterate")
             k = next(i for i, v in enumerate(h) if v <= rtol)
             if abs(np.log(h[k] / rtol)) > 1e-3 and (k == 0 or abs(np.log(h[k - 1] / rtol)) > 1e-3):
                 assert its[q] == k, (q, flexible, its[q], k)
@@ -184,7 +181,7 @@ def test_gmres_rhs_counts_and_ragged_batch(gpu_lib, nrhs):
         for si, p in enumerate(probs):
             pre = lambda v: O.vcycle(p.levels, sms[si], v, "FF")
             xo, _ = O.gmres(p.levels[0].A, pre, p.rhs, restart=7, rtol=1e-10, maxit=200, flexible=flexible)
-            assert rel(xs[si], xo) <= 1e-7, (si, flexible, rel(xs[si], xo))
+            check_vec(xs[si], xo, 1e-7, f"krylov batch system {si} flexible={flexible} iterate")
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])

@@ -1,49 +1,36 @@
 """GPU <-> oracle parity through the C ABI (MI355X).
 
 Every expected value comes from the FP64 CPU oracle on the same seeded inputs.
-Tolerances:
+Tolerances (the bounds and their derivation are in tests/parity.py):
   * integer artefacts (patterns, colours): bit-exact;
-  * FP64 smoother blocks: normwise relative 1e-9 per block.  G_i = M_i M_i^T
-    sums up to ~10^3 products, so the two summation orders leave ~1e-13
-    relative differences in G_i and H_i; the solve amplifies them by cond(G_i),
-    which stays below 1e4 for the non-singular blocks met here.  Blocks whose
-    G_i is exactly singular (they occur from the second cascade level on) are
-    compared through the minimum-norm solution, both sides cutting eigenvalues
-    below 1e-13 of the largest;
-  * FP64 V-cycle with the oracle's smoothers injected: normwise relative 1e-12
-    (only summation order differs);
-  * FP64 V-cycle with the GPU's own setup: 1e-10 (inherits the smoother
-    differences above);
-  * FP32 V-cycle: normwise relative 1e-5 against the FP64 oracle (about
-    100 x the FP32 unit round-off for the ~40 dependent sweeps of a V-cycle).
+  * FP64 smoother blocks: per block, 4096 u max(cond(G_i), the worst
+    condition met at earlier cascade levels), u = 2^-53, cond from the
+    oracle's normal equations.  Blocks whose G_i is exactly singular (from
+    the second cascade level on) compare through the minimum-norm solution,
+    both sides cutting eigenvalues below 1e-13 of the largest;
+  * FP64 V-cycle, with the GPU's own setup and with the oracle's smoothers
+    injected: 1e-12 relative, in the 2-norm and per entry;
+  * FP32 V-cycle: 1e-5 against the FP64 oracle (about 100 x the FP32 unit
+    round-off for the ~40 dependent sweeps of a V-cycle).
 """
 import numpy as np
 import pytest
 import scipy.sparse as sp
 
 import oracle as O
+from parity import VCYCLE_TOL, check_level_smoothers, check_vec, rel2
 from synth import fd
 from synth.problem import Level, Problem
 from synth.rng import TEST, stream
 
 pytestmark = pytest.mark.gpu
 
-LAM_TOL = 1e-9
-APPLY_TOL = 1e-12
-SETUP_APPLY_TOL = 1e-10
+APPLY_TOL = VCYCLE_TOL
 FP32_TOL = 1e-5
 
 
 def rel(a, b):
-    a = np.asarray(a)
-    b = np.asarray(b)
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
-
-
-def blockwise_rel(a, b):
-    num = np.linalg.norm((a - b).reshape(len(a), -1), axis=1)
-    den = np.maximum(np.linalg.norm(b.reshape(len(b), -1), axis=1), 1e-300)
-    return float((num / den).max())
+    return rel2(a, b)
 
 
 def gpu_solver(cascade, prob, **opts):
@@ -56,12 +43,10 @@ def oracle_setup(prob, depth, mode="additive", alpha=None):
     return O.setup_hierarchy(prob.levels, depth, mode, alpha)
 
 
-def check_smoothers(s, sm, prob, depth):
+def check_smoothers(s, sm, prob, depth, label=None):
+    label = label or prob.name
     for l in range(len(prob.levels) - 1):
-        for ell in range(1, depth + 1):
-            g = s.get_smoother(l, ell)
-            o = sm[l]["lam"][ell - 1]
-            assert blockwise_rel(g, o) <= LAM_TOL, (l, ell, blockwise_rel(g, o))
+        check_level_smoothers(s, sm[l], l, depth, label)
 
 
 def inject(s, sm):
@@ -77,10 +62,10 @@ def check_vcycle(s, sm, prob, order="RF", npre=1, npost=1, b=None):
     b = prob.rhs if b is None else b
     o = O.vcycle(prob.levels, sm, b, order, npre, npost)
     g = s.vcycle(b).cpu().numpy()
-    assert rel(g, o) <= SETUP_APPLY_TOL, ("own setup", rel(g, o))
+    check_vec(g, o, VCYCLE_TOL, f"{prob.name} {order} V({npre},{npost}) FP64 V-cycle, own setup")
     inject(s, sm)
     g = s.vcycle(b).cpu().numpy()
-    assert rel(g, o) <= APPLY_TOL, ("injected", rel(g, o))
+    check_vec(g, o, VCYCLE_TOL, f"{prob.name} {order} V({npre},{npost}) FP64 V-cycle, oracle smoothers")
     return o
 
 
@@ -121,7 +106,7 @@ def test_poisson64_apply_and_vcycle_parity(gpu_lib, poisson64):
     for rev in (False, True):
         g = s.smooth(0, p.rhs, x0, reverse=rev).cpu().numpy()
         o = O.smooth(p.levels[0].A, sm[0], x0, p.rhs, reverse=rev)
-        assert rel(g, o) <= APPLY_TOL, (rev, rel(g, o))
+        check_vec(g, o, APPLY_TOL, f"poisson64 cascade apply reverse={rev}")
     check_vcycle(s, sm, p, "RF", 2, 2)
 
 
@@ -134,7 +119,7 @@ def test_poisson64_solve(gpu_lib, poisson64):
     assert info["iterations"] == len(ho) - 1
     # each history entry is ||b - A x|| / ||b||: its absolute error is ~ eps * ||A|| ||x|| / ||b||
     np.testing.assert_allclose(info["history"], ho, rtol=1e-6, atol=1e-14)
-    assert rel(x.cpu().numpy(), xo) <= 1e-11
+    check_vec(x.cpu().numpy(), xo, 1e-11, "poisson64 FP64 IR solution")
 
 
 # ---------------------------------------------------------------------------
@@ -161,9 +146,7 @@ def test_interface_vcycle_fp64_and_fp32(gpu_lib, iface32, order):
     o = check_vcycle(s, sm, p, order)
     s.set_precision("fp32")
     g32 = s.vcycle(p.rhs).cpu().numpy()
-    err = rel(g32, o)
-    print(f"fp32 V-cycle error vs FP64 oracle ({order}): {err:.3e}")
-    assert err <= FP32_TOL
+    check_vec(g32, o, FP32_TOL, f"iface32 {order} FP32 V-cycle vs FP64 oracle")
 
 
 def test_interface_solve_fp32_ir_matches_oracle_rate(gpu_lib, iface32):
@@ -177,7 +160,7 @@ def test_interface_solve_fp32_ir_matches_oracle_rate(gpu_lib, iface32):
     assert all(b < a for a, b in zip(h, h[1:]))
     print(f"rho fp32+IR {info['rho']:.4f} vs oracle {rho_o:.4f}; x error {rel(x.cpu().numpy(), xo):.2e}")
     assert info["rho"] <= 1.05 * rho_o
-    assert rel(x.cpu().numpy(), xo) <= 1e-8
+    check_vec(x.cpu().numpy(), xo, 1e-8, "iface32 FP32+IR solution vs FP64 oracle")
 
 
 def test_ragged_sizes(gpu_lib):
@@ -195,7 +178,7 @@ def test_block_sizes_2d(gpu_lib, bs):
     """2D log-normal coefficients with 2x2 (nb = 4) and 4x4 (nb = 16) blocks."""
     z = stream(7, 1).standard_normal((32, 32))
     levels = fd.fv_hierarchy(np.exp(2.0 * z), bs=bs, n_stop=4)
-    p = Problem("ln2d", levels, stream(7, 0).uniform(-1, 1, size=(32 * 32, 4)))
+    p = Problem(f"ln2d-{bs}x{bs}", levels, stream(7, 0).uniform(-1, 1, size=(32 * 32, 4)))
     sm = oracle_setup(p, 2)
     s = gpu_solver(gpu_lib, p, depth=2)
     check_smoothers(s, sm, p, 2)
@@ -221,7 +204,8 @@ def test_multiplicative_red_black_2d(gpu_lib):
         x0 = stream(2, TEST).uniform(-1, 1, size=p.rhs.shape)
         for rev in (False, True):
             g = s.smooth(0, p.rhs, x0, reverse=rev).cpu().numpy()
-            assert rel(g, O.smooth(p.levels[0].A, sm[0], x0, p.rhs, rev)) <= APPLY_TOL
+            check_vec(g, O.smooth(p.levels[0].A, sm[0], x0, p.rhs, rev), APPLY_TOL,
+                      f"red-black {order} cascade apply reverse={rev}")
 
 
 def test_multiplicative_greedy_colouring_blocks(gpu_lib):
@@ -267,7 +251,7 @@ def test_depth_one_and_single_level(gpu_lib):
     one = Problem("bottom", [Level(A=p.levels[-1].A)], stream(3, 0).uniform(-1, 1, size=(p.levels[-1].n, 1)))
     s1 = gpu_solver(gpu_lib, one, depth=1)
     g = s1.vcycle(one.rhs).cpu().numpy()
-    assert rel(g, np.linalg.solve(one.levels[0].A.toarray(), one.rhs)) <= 1e-12
+    check_vec(g, np.linalg.solve(one.levels[0].A.toarray(), one.rhs), 1e-12, "single-level direct solve")
 
 
 def test_state_and_argument_errors(gpu_lib):
@@ -330,7 +314,7 @@ def test_injected_smoother_vcycle(gpu_lib):
             s.set_smoother(l, ell + 1, lams[ell])
         sm.append(dict(lam=lams, colours=None))
     g = s.vcycle(p.rhs).cpu().numpy()
-    assert rel(g, O.vcycle(p.levels, sm, p.rhs)) <= APPLY_TOL
+    check_vec(g, O.vcycle(p.levels, sm, p.rhs), APPLY_TOL, "injected damped block-Jacobi V-cycle")
 
 
 @pytest.mark.parametrize("mode", ["additive", "multiplicative"])

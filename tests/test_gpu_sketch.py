@@ -2,9 +2,9 @@
 fit_sketched on the same sketch.
 
 Tolerances: the sketched normal equations are formed from the same products
-as the exact ones, so the Lambda blocks agree to 1e-9 + 1e-12 cond(G_i)
-normwise per block (cond from the oracle, worst up to the cascade level, as
-for the exact fit), relative to the block's norm or, for blocks of rounding
+as the exact ones, so the Lambda blocks agree to the exact fit's per-block
+bound 4096 u cond(G_i) (cond from the oracle, worst up to the cascade level;
+tests/parity.py), relative to the block's norm or, for blocks of rounding
 size, to 1e-6 of the level's largest block.  With S = [I 0] the sketch is the
 exact fit.
 """
@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from parity import level_bounds, record
 from synth import fd
 from synth.batch import concatenate
 
@@ -28,8 +29,9 @@ def check_levels(s, sm_list, sizes, depth):
             # the level's scale
             no = np.linalg.norm(o.reshape(len(o), -1), axis=1)
             den = np.maximum(no, 1e-6 * max(no.max(), 1e-300))
-            worst = max(np.max(sm["gram_cond"][e]) for e in range(ell))
-            ratio = float(np.max(num / den) / (1e-9 + 1e-12 * worst))
+            bound = level_bounds(sm["gram_cond"], ell)
+            k = int(np.argmax(num / den / bound))
+            ratio = record(f"sketched level {l} Lambda_{ell}", num[k] / den[k], bound[k])
             assert ratio <= 1.0, (l, ell, ratio)
 
 

@@ -826,7 +826,7 @@ def test_stokes_cascade_converges_under_gmres():
 
 
 # ---------------------------------------------------------------------------
-# Overlapping-block cascades (Sec. 3.5.2)
+# Overlapping-block cascades (Sec. 3.6.2)
 # ---------------------------------------------------------------------------
 
 def test_overlapping_with_a_partition_is_the_additive_cascade():
@@ -895,7 +895,7 @@ def test_overlapping_identity_sketch_and_convergence():
 
 
 # ---------------------------------------------------------------------------
-# Stencil repetition (Sec. 5): translation classes of block neighbourhoods
+# Stencil repetition (Sec. 4): translation classes of block neighbourhoods
 # ---------------------------------------------------------------------------
 
 def _disk_problem(n=48, bs=2, contrast=100.0):
