@@ -1,11 +1,11 @@
 """SIPG Q3 (16x16 element blocks) with the 4-colour multiplicative cascade:
 FP64 parity against the oracle, and the BF16 matrix-core path.
 
-FP64 smoother blocks: per block 4096 u cond (tests/parity.py), cond the worst
+FP64 smoother blocks: per block 16384 u cond (tests/parity.py), cond the worst
 condition number of the normal equations met up to that cascade level (the
 oracle reports it; up to ~3e7 for DG blocks at the third level).  FP64
 V-cycle: 1e-12 with the oracle's smoothers injected; with the GPU's own
-setup the V-cycle inherits the smoother differences, bounded by 4096 u times
+setup the V-cycle inherits the smoother differences, bounded by 16384 u times
 the worst condition number of the hierarchy.
 
 BF16 tolerances: the sweep is compared with the oracle run on A and Lambda

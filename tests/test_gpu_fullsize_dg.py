@@ -5,7 +5,7 @@ FF cascade, FP64 V-cycle - the configuration bench.py's DG leg times.
   * sampled smoother blocks (a corner, a boundary and two interior elements)
     against the oracle's fit of the same blocks on their radius nu * chi
     patch (exact: a multiplicative step reads A within nu * chi layers), to
-    4096 u cond, cond the worst normal-equation condition number met in the
+    16384 u cond, cond the worst normal-equation condition number met in the
     patch up to that cascade level (tests/parity.py);
   * the FP64 V-cycle against the oracle's at full size with injected block
     Jacobi weights on every level (1e-12, 2-norm and per entry);

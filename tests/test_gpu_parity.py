@@ -3,7 +3,7 @@
 Every expected value comes from the FP64 CPU oracle on the same seeded inputs.
 Tolerances (the bounds and their derivation are in tests/parity.py):
   * integer artefacts (patterns, colours): bit-exact;
-  * FP64 smoother blocks: per block, 4096 u max(cond(G_i), the worst
+  * FP64 smoother blocks: per block, 16384 u max(cond(G_i), the worst
     condition met at earlier cascade levels), u = 2^-53, cond from the
     oracle's normal equations.  Blocks whose G_i is exactly singular (from
     the second cascade level on) compare through the minimum-norm solution,

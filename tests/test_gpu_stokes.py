@@ -1,10 +1,10 @@
 """Stokes (saddle-point) levels: Stokes prescaling on the GPU, cascade fit,
 V-cycle and GMRES on the MAC staggered grid, against the oracle.
 
-Lambda blocks: 4096 u cond(G_i) per block as for the elliptic fits (the
+Lambda blocks: 16384 u cond(G_i) per block as for the elliptic fits (the
 normal equations are the same; only W differs; tests/parity.py).  V-cycle with
 the oracle's smoothers injected: 1e-12 (2-norm and per entry); with the GPU's
-own exact overlapping fit: 4096 u times the worst condition number met.  GMRES histories: 1e-6 relative, 1e-13 absolute
+own exact overlapping fit: 16384 u times the worst condition number met.  GMRES histories: 1e-6 relative, 1e-13 absolute
 (recomputed residuals at restarts), iterates 1e-8.
 """
 import numpy as np
