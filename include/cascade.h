@@ -160,6 +160,22 @@ cs_status cs_smooth(cs_ctx ctx, int32_t level, int32_t reverse, const double *b,
  * precision; b, x: device FP64 [n][nrhs] on the finest level. */
 cs_status cs_vcycle(cs_ctx ctx, const double *b, double *x, int32_t nrhs);
 
+/* x = V b like cs_vcycle, for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, allocation-free
+ * harnesses).  The level workspace (x, its double buffer, b and r of every
+ * level in the working precision, each range 256-byte aligned: about
+ * 4 * sizeof(working type) * nrhs * (total unknowns of all levels) bytes) comes
+ * from one static device array of CS_NOALLOC_SCRATCH_MIB MiB per GPU, looked up
+ * at cs_create; the call makes no device or host allocation, records no
+ * trace events and does not synchronise: x is ready when the context's stream
+ * reaches the end of the call.  The kernels are cs_vcycle's, so the result is
+ * bit-identical to cs_vcycle's.  Every call on a GPU (any context) shares that
+ * GPU's array and leaves its contents behind; calls that overlap on one GPU
+ * race.  CS_EINVAL when the workspace would exceed the array or nrhs is not
+ * 1, 2, 4 or 8; CS_ESTATE before cs_setup. */
+#define CS_NOALLOC_SCRATCH_MIB 64
+cs_status cs_vcycle_noalloc(cs_ctx ctx, const double *b, double *x, int32_t nrhs);
+
 /* Solve A x = b by FP64 iterative refinement around the V-cycle: x_0 = 0;
  * r = b - A x (FP64); stop when max_j ||r_j|| <= rtol ||b_j||; x += V r.
  * A residual that becomes non-finite or grows beyond 1e6 ||b|| ends the solve

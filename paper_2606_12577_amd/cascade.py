@@ -73,6 +73,7 @@ SIGNATURES = {
     "cs_get_colours": (_I32, [_VP, _I32, _p(_I32)]),
     "cs_smooth": (_I32, [_VP, _I32, _I32, _VP, _VP, _I32]),
     "cs_vcycle": (_I32, [_VP, _VP, _VP, _I32]),
+    "cs_vcycle_noalloc": (_I32, [_VP, _VP, _VP, _I32]),
     "cs_solve": (_I32, [_VP, _VP, _VP, _I32, _D, _I32, _p(cs_info), _p(_D)]),
     "cs_solve_cg": (_I32, [_VP, _VP, _VP, _I32, _D, _I32, _p(cs_info), _p(_D)]),
     "cs_solve_gmres": (_I32, [_VP, _VP, _VP, _I32, _D, _I32, _I32, _I32, _p(cs_info), _p(_D)]),
@@ -359,6 +360,16 @@ class Solver:
         b = self._vec(b)
         x = self._torch.empty_like(b)
         self._check(self._lib.cs_vcycle(self._h, _tensor_ptr(b), _tensor_ptr(x), b.shape[1]))
+        return x
+
+    def vcycle_noalloc(self, b, x):
+        """cs_vcycle_noalloc: x = V b into the caller's tensor x, the workspace
+        in the library's static device array; waits for the result."""
+        b = self._vec(b)
+        if x.shape != b.shape or x.dtype != b.dtype or not x.is_contiguous() or x.device != b.device:
+            raise ValueError("x must be a contiguous tensor shaped like b on the same device")
+        self._check(self._lib.cs_vcycle_noalloc(self._h, _tensor_ptr(b), _tensor_ptr(x), b.shape[1]))
+        self._torch.cuda.synchronize(b.device)
         return x
 
     def solve(self, b, rtol: float = 1e-10, maxit: int = 100, x=None, raise_on_noconv: bool = True,

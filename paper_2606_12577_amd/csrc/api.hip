@@ -3,12 +3,18 @@
 #include <cstdlib>
 #include <exception>
 #include <fstream>
+#include <map>
+#include <mutex>
 
 #include "cs_internal.h"
 #include "mlp_internal.h"
 
 using cs::Ctx;
 using cs::Level;
+
+// Workspace of cs_vcycle_noalloc (see the comment at register_scratch).
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(CS_NOALLOC_SCRATCH_MIB) << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -155,6 +161,34 @@ void set_level(Ctx &c, Level &L, const cs_level &in, int li, int nlev, int64_t n
     cs::build_level_device(c, L);
 }
 
+// Workspace of cs_vcycle_noalloc: a fixed device array, one copy per GPU the
+// library runs on (held until the process ends).  Host code never uses the
+// array's name as an address: cs_create looks up each device's copy with
+// hipGetSymbolAddress (once per device, that device current) and keeps it.
+std::mutex g_scratch_mu;
+std::map<int, unsigned char *> g_scratch;   // device -> its scratch address
+
+// Returns false (and sets the creation error) when the lookup fails.
+bool register_scratch(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch.count(device)) return true;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        g_create_err = std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e);
+        return false;
+    }
+    g_scratch[device] = static_cast<unsigned char *>(p);
+    return true;
+}
+
+unsigned char *device_scratch(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch.find(device);
+    return it == g_scratch.end() ? nullptr : it->second;
+}
+
 const uint64_t SAVE_MAGIC = 0x3150555445535343ull;  // "CSSETUP1"
 const int32_t SAVE_VERSION = 2;
 
@@ -227,6 +261,7 @@ cs_status cs_create(cs_ctx *out, int32_t device, void *stream) {
         g_create_err = "hipSetDevice failed";
         return CS_EDEVICE;
     }
+    if (!register_scratch(device)) return CS_EDEVICE;
     cs_ctx h = new (std::nothrow) cs_ctx_s;
     if (!h) return CS_ENOMEM;
     h->c.device = device;
@@ -475,6 +510,21 @@ cs_status cs_vcycle(cs_ctx ctx, const double *b, double *x, int32_t nrhs) {
         need(b && x, "null vector");
         cs::vcycle_apply(c, b, x, nrhs);
         CS_HIP(hipStreamSynchronize(c.stream));
+    });
+}
+
+cs_status cs_vcycle_noalloc(cs_ctx ctx, const double *b, double *x, int32_t nrhs) {
+    return guarded(ctx, [&](Ctx &c) {
+        need(c.have_setup, "cs_vcycle_noalloc before cs_setup", CS_ESTATE);
+        need(b && x, "null vector");
+        need(nrhs == 1 || nrhs == 2 || nrhs == 4 || nrhs == 8, "nrhs must be 1, 2, 4 or 8");
+        const size_t want = cs::vcycle_workspace_bytes(c, nrhs);
+        need(want <= NOALLOC_SCRATCH_BYTES,
+             "cs_vcycle_noalloc needs " + std::to_string(want) + " bytes of workspace; the static scratch holds " +
+                 std::to_string(NOALLOC_SCRATCH_BYTES));
+        unsigned char *p = device_scratch(c.device);
+        need(p != nullptr, "no scratch address for this device", CS_EDEVICE);
+        cs::vcycle_apply_scratch(c, b, x, nrhs, p);
     });
 }
 

@@ -178,6 +178,10 @@ struct Level {
     std::vector<int64_t> cblk_ptr;    // colour offsets into cblk
     // V-cycle workspace (working precision), [n][nrhs]
     DBuf<char> xb, xt, bb, rr;
+    // the workspace the V-cycle kernels use: the buffers above, or ranges of
+    // the static scratch array during cs_vcycle_noalloc
+    char *w_xb = nullptr, *w_xt = nullptr, *w_bb = nullptr, *w_rr = nullptr;
+    unsigned char *w_ovl = nullptr;
 };
 
 struct Trace {
@@ -209,6 +213,7 @@ struct Ctx {
     cs_options opt{};
     int precision = CS_FP64;
     int ws_nrhs = 0, ws_prec = -1;
+    bool ws_scratch = false;            // the level workspace points into the static scratch array
     double setup_ms = 0;
     int singular = 0;
     // independent systems on the finest level (a batch)
@@ -301,6 +306,8 @@ void bf16_residual(Ctx &c, const Level &L, const float *b, const float *x, float
 // solve.hip
 void ensure_workspace(Ctx &c, int nrhs);
 void vcycle_apply(Ctx &c, const double *b, double *x, int nrhs);
+size_t vcycle_workspace_bytes(const Ctx &c, int nrhs);
+void vcycle_apply_scratch(Ctx &c, const double *b, double *x, int nrhs, unsigned char *scratch);
 void smooth_apply(Ctx &c, int level, bool reverse, const double *b, double *x, int nrhs);
 void solve_ir(Ctx &c, const double *b, double *x, int nrhs, double rtol, int maxit, cs_info *info,
               double *history, cs_status *st);

@@ -1461,8 +1461,8 @@ T *apply_cascade(Ctx &c, const Level &L, bool reverse, bool zero_start, const T 
         // blockwise apply over the replicated slots, fused weighted average
         if (reverse || xc) fail(CS_EINVAL, "overlapping-block cascades apply forward without fused interpolation");
         const int64_t m = L.ovl_m, nblk = L.ovl_nblk, lsz = nblk * m * m;
-        T *y = reinterpret_cast<T *>(L.ovl_y.get());
-        T *rr = reinterpret_cast<T *>(L.rr.get());
+        T *y = reinterpret_cast<T *>(L.w_ovl);
+        T *rr = reinterpret_cast<T *>(L.w_rr);
         T *cur = x, *nxt = alt;
         for (int ell = 0; ell < depth; ++ell) {
             const bool zero = zero_start && ell == 0;
@@ -1553,8 +1553,8 @@ bool issue_first_sweep(Ctx &c) {
     const bool reverse = c.opt.order == CS_RF;
     const int ell = reverse ? L.depth - 1 : 0;
     const T *lam = lam_ptr<T>(L, reverse) + (int64_t)ell * (L.B * L.nb * L.nb);
-    launch_sweep<T, R>(c, L, L.sell, false, true, lam, reinterpret_cast<const T *>(L.bb.get()),
-                       reinterpret_cast<T *>(L.xb.get()), reinterpret_cast<T *>(L.xt.get()), nullptr, L.agg_k);
+    launch_sweep<T, R>(c, L, L.sell, false, true, lam, reinterpret_cast<const T *>(L.w_bb),
+                       reinterpret_cast<T *>(L.w_xb), reinterpret_cast<T *>(L.w_xt), nullptr, L.agg_k);
     c.spec_pending = true;
     return true;
 }
@@ -1562,10 +1562,10 @@ bool issue_first_sweep(Ctx &c) {
 template <typename T, int R>
 void vcycle_level(Ctx &c, int l) {
     Level &L = c.lv[l];
-    T *xb = reinterpret_cast<T *>(L.xb.get());
-    T *xt = reinterpret_cast<T *>(L.xt.get());
-    T *bb = reinterpret_cast<T *>(L.bb.get());
-    T *rr = reinterpret_cast<T *>(L.rr.get());
+    T *xb = reinterpret_cast<T *>(L.w_xb);
+    T *xt = reinterpret_cast<T *>(L.w_xt);
+    T *bb = reinterpret_cast<T *>(L.w_bb);
+    T *rr = reinterpret_cast<T *>(L.w_rr);
     const double es = sizeof(T);
     if (l + 1 == (int)c.lv.size()) {
         direct_solve<T, R>(c, L, bb, xb);
@@ -1592,7 +1592,7 @@ void vcycle_level(Ctx &c, int l) {
             hipLaunchKernelGGL((k_residual_restrict<T, R, NB>), dim3(tile_grid(c, L.act_slices)), dim3(WG), 0, c.stream, na,
                                L.act_slices, L.sell.slice_ptr.get(), L.sell.slice_len.get(), L.sell.col.get(),
                                sell_val<T>(L.sell), bb, x, L.agg_k, L.nc, (T)L.r_scale,
-                               reinterpret_cast<T *>(C.bb.get()));
+                               reinterpret_cast<T *>(C.w_bb));
         });
     } else {
         bool bf16 = false;
@@ -1607,12 +1607,12 @@ void vcycle_level(Ctx &c, int l) {
         hipLaunchKernelGGL((k_restrict_sell<T, R>), dim3(tile_grid(c, L.ptsell.nslices)), dim3(WG), 0, c.stream,
                            L.nc, L.ptsell.nslices, L.ptsell.slice_ptr.get(), L.ptsell.slice_len.get(),
                            L.ptsell.col.get(), sell_val<T>(L.ptsell), (T)L.r_scale, rr,
-                           reinterpret_cast<T *>(C.bb.get()));
+                           reinterpret_cast<T *>(C.w_bb));
     }
     CS_LAUNCH_CHECK();
     trace_end(c, slot);
     vcycle_level<T, R>(c, l + 1);
-    const T *xc = reinterpret_cast<const T *>(C.xb.get());
+    const T *xc = reinterpret_cast<const T *>(C.w_xb);
     const bool fuse_prol = fused && c.opt.mode == CS_ADDITIVE && c.opt.n_post > 0;
     if (!fuse_prol) {
         slot = trace_begin(c, CS_TRACE_PROLONG, L.p_nnz * (es + 4.0) + 2.0 * na * R * es + L.nc * R * es);
@@ -1640,9 +1640,26 @@ void dispatch_prec(int prec, F &&f) {
 
 }  // namespace
 
+// Point every level's V-cycle workspace at the context's own buffers (after
+// a call that ran on the static scratch array).
+static void use_own_workspace(Ctx &c) {
+    for (Level &L : c.lv) {
+        L.w_xb = L.xb.get();
+        L.w_xt = L.xt.get();
+        L.w_bb = L.bb.get();
+        L.w_rr = L.rr.get();
+        L.w_ovl = L.ovl_y.get();
+    }
+    if (c.ws_scratch) c.gen++;   // captured graphs hold the scratch addresses
+    c.ws_scratch = false;
+}
+
 void ensure_workspace(Ctx &c, int nrhs) {
     const int prec = c.precision;
-    if (c.ws_nrhs == nrhs && c.ws_prec == prec) return;
+    if (c.ws_nrhs == nrhs && c.ws_prec == prec) {
+        if (c.ws_scratch) use_own_workspace(c);
+        return;
+    }
     const size_t es = prec == CS_FP64 ? sizeof(double) : sizeof(float);
     for (Level &L : c.lv) {
         const size_t bytes = (size_t)L.n * nrhs * es;
@@ -1652,6 +1669,8 @@ void ensure_workspace(Ctx &c, int nrhs) {
         L.rr.alloc(bytes);
         if (L.ovl_m) L.ovl_y.alloc((size_t)L.ovl_nblk * L.ovl_m * nrhs * es);
     }
+    c.ws_scratch = true;   // forces the pointer update below
+    use_own_workspace(c);
     const int64_t G = std::min<int64_t>(ceil_div(c.lv[0].sell.nslices, 4), IR_GRID);
     c.ir_partial.alloc(std::max<int64_t>(G, 1) * 2 * nrhs);   // up to two dot products per RHS
     const int64_t nsys = c.sys_ptr.empty() ? 1 : (int64_t)c.sys_ptr.size() - 1;
@@ -1675,19 +1694,71 @@ void ensure_workspace(Ctx &c, int nrhs) {
     c.ws_prec = prec;
 }
 
-void vcycle_apply(Ctx &c, const double *b, double *x, int nrhs) {
-    ensure_workspace(c, nrhs);
+static void vcycle_run(Ctx &c, const double *b, double *x, int nrhs) {
     Level &L0 = c.lv[0];
     const int64_t n = L0.n * nrhs;
     dispatch_prec(c.precision, [&](auto tp) {
         using T = std::remove_pointer_t<decltype(tp)>;
         hipLaunchKernelGGL((k_convert<double, T>), dim3(grid_for(n)), dim3(WG), 0, c.stream, n, b,
-                           reinterpret_cast<T *>(L0.bb.get()));
+                           reinterpret_cast<T *>(L0.w_bb));
         dispatch_r(nrhs, [&](auto rc) { vcycle_level<T, decltype(rc)::value>(c, 0); });
         hipLaunchKernelGGL((k_convert<T, double>), dim3(grid_for(n)), dim3(WG), 0, c.stream, n,
-                           reinterpret_cast<const T *>(L0.xb.get()), x);
+                           reinterpret_cast<const T *>(L0.w_xb), x);
         CS_LAUNCH_CHECK();
     });
+}
+
+void vcycle_apply(Ctx &c, const double *b, double *x, int nrhs) {
+    ensure_workspace(c, nrhs);
+    vcycle_run(c, b, x, nrhs);
+}
+
+// Bytes of V-cycle workspace for nrhs right-hand sides in the working
+// precision: x, its double buffer, b and r of every level (+ the replicated
+// slots of overlapping-block levels), each range 256-byte aligned.
+size_t vcycle_workspace_bytes(const Ctx &c, int nrhs) {
+    const size_t es = c.precision == CS_FP64 ? sizeof(double) : sizeof(float);
+    auto up = [](size_t v) { return (v + 255) / 256 * 256; };
+    size_t tot = 0;
+    for (const Level &L : c.lv) {
+        tot += 4 * up((size_t)L.n * nrhs * es);
+        if (L.ovl_m) tot += up((size_t)L.ovl_nblk * L.ovl_m * nrhs * es);
+    }
+    return tot;
+}
+
+// x = V b with the level workspace carved out of `scratch` (device memory of
+// at least vcycle_workspace_bytes): the same kernels as vcycle_apply, no
+// allocation, no event tracing, no synchronisation.  The context's own
+// buffers are restored by the next ensure_workspace.
+void vcycle_apply_scratch(Ctx &c, const double *b, double *x, int nrhs, unsigned char *scratch) {
+    const size_t es = c.precision == CS_FP64 ? sizeof(double) : sizeof(float);
+    auto up = [](size_t v) { return (v + 255) / 256 * 256; };
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        unsigned char *p = scratch + off;
+        off += up(bytes);
+        return p;
+    };
+    for (Level &L : c.lv) {
+        const size_t bytes = (size_t)L.n * nrhs * es;
+        L.w_xb = reinterpret_cast<char *>(take(bytes));
+        L.w_xt = reinterpret_cast<char *>(take(bytes));
+        L.w_bb = reinterpret_cast<char *>(take(bytes));
+        L.w_rr = reinterpret_cast<char *>(take(bytes));
+        L.w_ovl = L.ovl_m ? take((size_t)L.ovl_nblk * L.ovl_m * nrhs * es) : nullptr;
+    }
+    c.ws_scratch = true;
+    c.gen++;   // no captured graph may keep these addresses
+    const bool tr = c.tr.on;
+    c.tr.on = false;
+    try {
+        vcycle_run(c, b, x, nrhs);
+    } catch (...) {
+        c.tr.on = tr;
+        throw;
+    }
+    c.tr.on = tr;
 }
 
 // Sweep launch schedules per level, picked by measurement: one application of
@@ -1717,8 +1788,8 @@ void autotune(Ctx &c, int nrhs, double *ms) {
                     if (ms) ms[l] = 0.0;
                     if (L.depth <= 0 || L.n_active == 0 || l + 1 == c.lv.size()) continue;
                     const int64_t n = L.n * R;
-                    T *b = reinterpret_cast<T *>(L.bb.get()), *x = reinterpret_cast<T *>(L.xb.get()),
-                      *alt = reinterpret_cast<T *>(L.xt.get());
+                    T *b = reinterpret_cast<T *>(L.w_bb), *x = reinterpret_cast<T *>(L.w_xb),
+                      *alt = reinterpret_cast<T *>(L.w_xt);
                     hipLaunchKernelGGL(k_zero<T>, dim3(grid_for(n)), dim3(WG), 0, c.stream, n, b);
                     hipLaunchKernelGGL(k_zero<T>, dim3(grid_for(n)), dim3(WG), 0, c.stream, n, x);
                     CS_LAUNCH_CHECK();
@@ -1771,9 +1842,9 @@ void smooth_apply(Ctx &c, int level, bool reverse, const double *b, double *x, i
     const int64_t n = L.n * nrhs;
     dispatch_prec(c.precision, [&](auto tp) {
         using T = std::remove_pointer_t<decltype(tp)>;
-        T *bb = reinterpret_cast<T *>(L.bb.get());
-        T *xb = reinterpret_cast<T *>(L.xb.get());
-        T *xt = reinterpret_cast<T *>(L.xt.get());
+        T *bb = reinterpret_cast<T *>(L.w_bb);
+        T *xb = reinterpret_cast<T *>(L.w_xb);
+        T *xt = reinterpret_cast<T *>(L.w_xt);
         hipLaunchKernelGGL((k_convert<double, T>), dim3(grid_for(n)), dim3(WG), 0, c.stream, n, b, bb);
         hipLaunchKernelGGL((k_convert<double, T>), dim3(grid_for(n)), dim3(WG), 0, c.stream, n, (const double *)x, xb);
         T *res = nullptr;
@@ -1923,7 +1994,7 @@ void solve_ir(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
             };
             auto residual = [&]() {
                 const int slot = trace_begin(c, CS_TRACE_REFINE, ir_bytes);
-                norms(x, reinterpret_cast<T *>(L0.bb.get()), c.ir_norm.get());
+                norms(x, reinterpret_cast<T *>(L0.w_bb), c.ir_norm.get());
                 trace_end(c, slot);
             };
             // one refinement iteration after the check: d = V r, x += d, r = b - A x
@@ -1931,7 +2002,7 @@ void solve_ir(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
                 vcycle_level<T, R>(c, 0);
                 const int slot = trace_begin(c, CS_TRACE_REFINE, up_bytes);
                 hipLaunchKernelGGL((k_add_to64<T>), dim3(grid_for(n)), dim3(WG), 0, c.stream, n,
-                                   reinterpret_cast<const T *>(L0.xb.get()), x);
+                                   reinterpret_cast<const T *>(L0.w_xb), x);
                 CS_LAUNCH_CHECK();
                 trace_end(c, slot);
                 residual();
@@ -2033,8 +2104,8 @@ void solve_cg(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
         using T = std::remove_pointer_t<decltype(tp)>;
         dispatch_r(nrhs, [&](auto rc) {
             constexpr int R = decltype(rc)::value;
-            T *rt = reinterpret_cast<T *>(L0.bb.get());
-            const T *z = reinterpret_cast<const T *>(L0.xb.get());
+            T *rt = reinterpret_cast<T *>(L0.w_bb);
+            const T *z = reinterpret_cast<const T *>(L0.w_xb);
             // reduce partial sums of W values per row into out[nsys][W]
             auto reduce = [&](int W, double *out) {
                 if (batch)
@@ -2258,8 +2329,8 @@ void solve_gmres(Ctx &c, const double *b, double *x, int nrhs, double rtol, int 
         using T = std::remove_pointer_t<decltype(tp)>;
         dispatch_r(nrhs, [&](auto rc) {
             constexpr int R = decltype(rc)::value;
-            T *bb = reinterpret_cast<T *>(L0.bb.get());
-            const T *xb = reinterpret_cast<const T *>(L0.xb.get());
+            T *bb = reinterpret_cast<T *>(L0.w_bb);
+            const T *xb = reinterpret_cast<const T *>(L0.w_xb);
             auto reduce = [&](int W, double *out) {
                 hipLaunchKernelGGL(k_gm_reduce, dim3((unsigned)ceil_div(W, 64), (unsigned)nsys), dim3(1024), 0,
                                    c.stream, W, Gp, sys_wg, part, out);
