@@ -34,6 +34,9 @@ Readings taken where the paper leaves a choice open
 * Truncation (Alg. 2, optional step): keep the alpha blocks of largest
   Frobenius norm in each updated block row of E; ties go to the lower block
   column.
+* Regularised fit (an extension, not in the paper; ridge = 0 is the paper's
+  fit): Lambda_i (G_i + ridge tr(G_i)/n I) = H_i, the Tikhonov-regularised
+  least squares, used to fit cascades that are applied in reduced precision.
 """
 from typing import Dict, List, Optional, Sequence
 
@@ -140,12 +143,29 @@ def prescale(A: sp.spmatrix, kind: Optional[np.ndarray] = None, norm: str = "max
     return w, (W @ A @ W).tocsr()
 
 
-def least_squares_blocks(H: np.ndarray, G: np.ndarray) -> np.ndarray:
+def regularised_gram(G: np.ndarray, ridge: float) -> np.ndarray:
+    """G_i + tau_i I with tau_i = ridge * trace(G_i) / n: the normal-equation
+    matrices of the Tikhonov-regularised fit (ridge = 0: G itself)."""
+    if not ridge:
+        return G
+    n = G.shape[1]
+    tau = ridge * np.trace(G, axis1=1, axis2=2) / n
+    return G + tau[:, None, None] * np.eye(n)[None, :, :]
+
+
+def least_squares_blocks(H: np.ndarray, G: np.ndarray, ridge: float = 0.0) -> np.ndarray:
     """Minimum-norm solution Lambda_i of Lambda_i M_i = E_i via its normal
-    equations Lambda_i G_i = H_i (Alg. 2, least-squares step)."""
+    equations Lambda_i G_i = H_i (Alg. 2, least-squares step).
+
+    ridge > 0 (a precision-aware reading, not in the paper): minimise
+    ||E_i - Lambda_i M_i||_F^2 + tau_i ||Lambda_i||_F^2, tau_i = ridge tr(G_i)/n,
+    i.e. Lambda_i (G_i + tau_i I) = H_i.  It bounds the blocks whose fit
+    amplifies the nearly dependent directions of M_i, which a reduced-precision
+    application would otherwise turn into large errors."""
+    Gr = regularised_gram(G, ridge)
     out = np.empty_like(H)
     for i in range(G.shape[0]):
-        out[i] = H[i] @ np.linalg.pinv(G[i], rcond=PINV_RCOND, hermitian=True)
+        out[i] = H[i] @ np.linalg.pinv(Gr[i], rcond=PINV_RCOND, hermitian=True)
     return out
 
 
@@ -197,7 +217,7 @@ def unscale(lam_t: np.ndarray, w: np.ndarray) -> np.ndarray:
 
 
 def fit_additive(A: sp.spmatrix, n: int, depth: int, alpha: Optional[int] = None,
-                 kind: Optional[np.ndarray] = None, norm: str = "max") -> Dict:
+                 kind: Optional[np.ndarray] = None, norm: str = "max", ridge: float = 0.0) -> Dict:
     """Depth-nu additive cascade (Sec. 2.1, Alg. 2).
 
     Lambda_l = argmin_{Lambda block-diagonal} ||(I - Lambda A~) E_{l-1}||_F,
@@ -217,8 +237,8 @@ def fit_additive(A: sp.spmatrix, n: int, depth: int, alpha: Optional[int] = None
         M = (At @ E).tocsr()
         G = blockdiag_of_product(M, M, n)
         H = blockdiag_of_product(E, M, n)
-        Lt = least_squares_blocks(H, G)
-        cond.append(gram_condition(G))
+        Lt = least_squares_blocks(H, G, ridge)
+        cond.append(gram_condition(regularised_gram(G, ridge)))
         lam_t.append(Lt)
         if ell < depth:
             E = (E - blockdiag(Lt) @ M).tocsr()
@@ -231,7 +251,8 @@ def fit_additive(A: sp.spmatrix, n: int, depth: int, alpha: Optional[int] = None
 
 
 def fit_multiplicative(A: sp.spmatrix, n: int, depth: int, colours: np.ndarray,
-                       alpha: Optional[int] = None, kind: Optional[np.ndarray] = None, norm: str = "max") -> Dict:
+                       alpha: Optional[int] = None, kind: Optional[np.ndarray] = None, norm: str = "max",
+                       ridge: float = 0.0) -> Dict:
     """Depth-nu multicoloured cascade (Sec. 2.2).
 
     For l = 1..nu and colours k in ascending order,
@@ -261,9 +282,9 @@ def fit_multiplicative(A: sp.spmatrix, n: int, depth: int, colours: np.ndarray,
             Mk, Ek = M[sel], E[sel]
             G = blockdiag_of_product(Mk, Mk, n)
             H = blockdiag_of_product(Ek, Mk, n)
-            Lt = least_squares_blocks(H, G)
+            Lt = least_squares_blocks(H, G, ridge)
             lam_t[ell - 1][blocks] = Lt
-            cond[ell - 1][blocks] = gram_condition(G)
+            cond[ell - 1][blocks] = gram_condition(regularised_gram(G, ridge))
             if ell < depth or k < chi - 1:
                 D = np.zeros((B, n, n))
                 D[blocks] = Lt
@@ -401,11 +422,11 @@ def smooth_overlapping(A: sp.spmatrix, sm: Dict, x: np.ndarray, b: np.ndarray) -
     return x
 
 
-def fit(A, n, depth, mode="additive", colours=None, alpha=None, kind=None, norm="max") -> Dict:
+def fit(A, n, depth, mode="additive", colours=None, alpha=None, kind=None, norm="max", ridge=0.0) -> Dict:
     if mode == "additive":
-        return fit_additive(A, n, depth, alpha, kind, norm)
+        return fit_additive(A, n, depth, alpha, kind, norm, ridge)
     if mode == "multiplicative":
-        return fit_multiplicative(A, n, depth, colours, alpha, kind, norm)
+        return fit_multiplicative(A, n, depth, colours, alpha, kind, norm, ridge)
     raise ValueError(mode)
 
 
@@ -471,7 +492,8 @@ def smooth(A: sp.spmatrix, sm: Dict, x: np.ndarray, b: np.ndarray, reverse: bool
     return x
 
 
-def setup_hierarchy(levels, depth: int, mode: str = "additive", alpha=None, norm: str = "max") -> List[Dict]:
+def setup_hierarchy(levels, depth: int, mode: str = "additive", alpha=None, norm: str = "max",
+                    ridge: float = 0.0) -> List[Dict]:
     """Fit a cascade on every level except the coarsest (Sec. 2.5); a level
     with a `kind` array (velocity / pressure per unknown) is prescaled as a
     Stokes problem (Sec. 2.3.2) with the given constraint-row norm."""
@@ -480,7 +502,7 @@ def setup_hierarchy(levels, depth: int, mode: str = "additive", alpha=None, norm
         colours = lv.colour
         if mode == "multiplicative" and colours is None:
             colours = greedy_colour(block_pattern(lv.A, lv.block_size))
-        out.append(fit(lv.A, lv.block_size, depth, mode, colours, alpha, getattr(lv, "kind", None), norm))
+        out.append(fit(lv.A, lv.block_size, depth, mode, colours, alpha, getattr(lv, "kind", None), norm, ridge))
     return out
 
 
@@ -694,7 +716,7 @@ def block_ball(Apat: sp.csr_matrix, centre: int, radius: int) -> np.ndarray:
 
 def fit_local(A: sp.spmatrix, n: int, depth: int, centres: Sequence[int], mode: str = "additive",
               colours: Optional[np.ndarray] = None, radius: Optional[int] = None,
-              with_cond: bool = False):
+              with_cond: bool = False, ridge: float = 0.0):
     """Lambda_{l,i} for selected blocks i, each fitted on the sub-matrix of A
     over the blocks within block-graph distance `radius` of i.
 
@@ -713,7 +735,7 @@ def fit_local(A: sp.spmatrix, n: int, depth: int, centres: Sequence[int], mode: 
         sel = block_rows(S, n)
         sub = A[sel][:, sel]
         pos = int(np.searchsorted(S, c))
-        res = fit(sub, n, depth, mode, None if colours is None else np.asarray(colours)[S])
+        res = fit(sub, n, depth, mode, None if colours is None else np.asarray(colours)[S], ridge=ridge)
         out[int(c)] = [L[pos] for L in res["lam"]]
         conds[int(c)] = [float(np.max(g)) for g in res["gram_cond"]]
     return (out, conds) if with_cond else out

@@ -48,10 +48,12 @@ def random_block_matrix(B, n, seed, extra_edges=2, symmetric=False):
     return A
 
 
-def brute_force_cascade(A, n, depth, colours=None):
+def brute_force_cascade(A, n, depth, colours=None, ridge=0.0):
     """Solve every Frobenius problem of the cascade as ONE dense least-squares
     problem over all block-diagonal unknowns at once (SVD lstsq), without any
-    per-block decoupling, normal equations or sparse products."""
+    per-block decoupling, normal equations or sparse products.  ridge > 0 adds
+    the Tikhonov term tau_i ||Lambda_i||_F^2, tau_i = ridge * (squared norm of
+    block i's rows of M) / n, as extra rows sqrt(tau_i) e_(i,r,s) with target 0."""
     N = A.shape[0]
     B = N // n
     w = 1.0 / np.sqrt(np.diag(A))
@@ -71,7 +73,12 @@ def brute_force_cascade(A, n, depth, colours=None):
                         Z[i * n + r, :] = M[i * n + s, :]
                         cols.append(Z.ravel())
             D = np.stack(cols, axis=1)
-            sol = np.linalg.lstsq(D, E.ravel(), rcond=None)[0]
+            rhs = E.ravel()
+            if ridge:
+                tau = np.repeat([ridge * np.sum(M[i * n:(i + 1) * n] ** 2) / n for i in blocks], n * n)
+                D = np.vstack([D, np.diag(np.sqrt(tau))])
+                rhs = np.concatenate([rhs, np.zeros(len(tau))])
+            sol = np.linalg.lstsq(D, rhs, rcond=None)[0]
             Lfull = np.zeros((N, N))
             t = 0
             for i in blocks:
@@ -224,6 +231,33 @@ def test_multiplicative_vs_brute_force(B, n, depth, chi, seed):
     got = O.fit_multiplicative(sp.csr_matrix(A), n, depth, colours)["lam_tilde"]
     for l in range(depth):
         np.testing.assert_allclose(got[l], want[l], rtol=1e-9, atol=1e-11)
+
+
+@pytest.mark.parametrize("mode,B,n,depth,seed", [("additive", 10, 1, 3, 21), ("additive", 6, 3, 2, 22),
+                                                  ("multiplicative", 8, 2, 2, 23)])
+def test_ridge_fit_vs_brute_force(mode, B, n, depth, seed):
+    """The Tikhonov-regularised fit against the whole regularised objective as
+    one dense least-squares problem (augmented rows)."""
+    A = random_block_matrix(B, n, seed)
+    colours = None if mode == "additive" else np.arange(B) % 2
+    for ridge in (1e-3, 0.5):
+        want = brute_force_cascade(A, n, depth, colours, ridge=ridge)
+        got = O.fit(sp.csr_matrix(A), n, depth, mode, colours, ridge=ridge)["lam_tilde"]
+        for l in range(depth):
+            np.testing.assert_allclose(got[l], want[l], rtol=1e-9, atol=1e-11)
+
+
+def test_ridge_first_level_closed_form():
+    """Point blocks, E_0 = I: lambda~_i = a~_ii / ((1 + ridge) sum_j a~_ij^2)."""
+    p = fd.poisson2d(32)
+    A = p.levels[0].A
+    C = sp.coo_matrix(A)
+    dg = A.diagonal()
+    at = C.data / np.sqrt(dg[C.row] * dg[C.col])
+    s2 = np.bincount(C.row, weights=at ** 2, minlength=A.shape[0])
+    for ridge in (1e-3, 0.25):
+        res = O.fit_additive(A, 1, 2, ridge=ridge)
+        np.testing.assert_allclose(res["lam_tilde"][0][:, 0, 0], 1.0 / ((1.0 + ridge) * s2), rtol=1e-14)
 
 
 def test_first_order_optimality():
