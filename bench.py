@@ -122,14 +122,24 @@ def bench_batch(precision: str):
     b = torch.as_tensor(bt.rhs, device="cuda").contiguous()
     dof = bt.levels[0].n * 4
     out = dict(dof=int(bt.levels[0].n), nrhs=4, systems=64, setup_ms=None)
+    # launch schedules per level and eager vs graph replay, picked by measurement
+    sched = s.autotune(4)
+    on, e_ms, g_ms = s.graphs()
+    out["autotune"] = dict(rows_per_workgroup=[int(w) for w, _, _ in sched],
+                           workgroup_cap=[int(g) for _, g, _ in sched],
+                           vcycle_ms_eager=round(e_ms, 3), vcycle_ms_graph=round(g_ms, 3), graph_replay=on)
     for method, maxit in (("cg", 300), ("ir", 1000)):
-        infos = [s.solve(b, rtol=1e-10, maxit=maxit, method=method, raise_on_noconv=False)[1] for _ in range(2)]
-        its, rels = s.system_stats()
-        i = infos[-1]
-        out[method] = dict(solve_ms=round(i["solve_ms"], 2), iterations=i["iterations"],
-                           converged_systems=int((rels <= 1e-10).sum()), dof_per_s=dof / (i["solve_ms"] * 1e-3),
-                           per_system_iterations=[int(np.min(its)), int(np.median(its)), int(np.max(its))])
+        for replay in (False, True):
+            s.set_graphs(replay)
+            infos = [s.solve(b, rtol=1e-10, maxit=maxit, method=method, raise_on_noconv=False)[1] for _ in range(2)]
+            its, rels = s.system_stats()
+            i = infos[-1]
+            out[method + ("_graph" if replay else "_eager")] = dict(
+                solve_ms=round(i["solve_ms"], 2), iterations=i["iterations"],
+                converged_systems=int((rels <= 1e-10).sum()), dof_per_s=dof / (i["solve_ms"] * 1e-3),
+                per_system_iterations=[int(np.min(its)), int(np.median(its)), int(np.max(its))])
         out["setup_ms"] = round(i["setup_ms"], 2)
+    s.set_graphs(on)
     # sketched construction (64 Rademacher modes per level) instead of the exact fit
     for _ in range(2):
         s.setup_sketched(width=64, seed=0, depth=3, precision=precision)
@@ -187,8 +197,12 @@ def bench_stokes(precision: str):
 def bench_dg():
     """SIPG Q3 on a jittered 256^2 quadrilateral mesh (16 x 16 element blocks,
     1,048,576 unknowns, 1 RHS), depth-3 four-colour multiplicative FF cascade,
-    V(1,1); FP64 V-cycle (reduced precision diverges for this cascade) in
-    flexible CG and in the stationary iteration."""
+    V(1,1).  The configuration: BF16 blocks of A and Lambda on the matrix cores
+    (FP32 accumulation, FP32 vectors and restricted residual) inside FP64
+    iterative refinement, with the Tikhonov-regularised fit (ridge 1e-3) that
+    keeps the depth-3 blocks small enough for BF16.  Beside it: the same fit in
+    FP32 and FP64, the paper's plain fit in FP64 (the plain FP64 V-cycle), and
+    flexible GMRES(30) around each (the FF V-cycle is not symmetric)."""
     import time as _t
     import torch
     from paper_2606_12577_amd import cascade
@@ -198,14 +212,42 @@ def bench_dg():
     gen_s = _t.perf_counter() - t
     s = cascade.Solver(p.levels)
     b = torch.as_tensor(p.rhs, device="cuda").contiguous()
-    out = dict(dof=int(p.n), nrhs=1, generation_s=round(gen_s, 1))
+    out = dict(dof=int(p.n), nrhs=1, generation_s=round(gen_s, 1), ridge=1e-3)
+
+    def solve(method):
+        i = [s.solve(b, rtol=1e-10, maxit=400, method=method, raise_on_noconv=False)[1] for _ in range(2)][-1]
+        return dict(solve_ms=round(i["solve_ms"], 2), iterations=i["iterations"], rho=round(i["rho"], 4),
+                    rel_res=i["rel_res"], precision=i["precision"],
+                    setup_ms=round(i["setup_ms"], 2), dof_per_s=p.n / (i["solve_ms"] * 1e-3))
+
+    opts = dict(depth=3, mode="multiplicative", order="FF")
     for _ in range(2):
-        s.setup(depth=3, mode="multiplicative", order="FF", precision="fp64")
-    for method in ("cg", "ir"):
-        i = [s.solve(b, rtol=1e-10, maxit=300, method=method, raise_on_noconv=False)[1] for _ in range(2)][-1]
-        out[method] = dict(solve_ms=round(i["solve_ms"], 2), iterations=i["iterations"], rho=round(i["rho"], 4),
-                           rel_res=i["rel_res"], setup_ms=round(i["setup_ms"], 2),
-                           dof_per_s=p.n / (i["solve_ms"] * 1e-3))
+        s.setup(**opts, precision="fp64")
+    out["fp64_plain_fit"] = {m: solve(m) for m in ("ir", "fgmres")}
+    for _ in range(2):
+        s.setup(**opts, precision="bf16", ridge=1e-3)
+    out["bf16_ridge"] = {m: solve(m) for m in ("ir", "fgmres")}
+    # kernel timing of the finest level's BF16 colour sweeps in one more (traced) refinement solve
+    s.trace(("sweep",), period=1)
+    s.solve(b, rtol=1e-10, maxit=400, method="ir", raise_on_noconv=False)
+    tr = s.trace_read()["sweep"]
+    s.trace(())
+    for prec in ("fp32", "fp64"):
+        s.set_precision(prec)
+        out[f"{prec}_ridge"] = {m: solve(m) for m in ("ir", "fgmres")}
+    if tr["launches"]:
+        avg_s = tr["ms"] / tr["launches"] * 1e-3
+        per = tr["bytes"] / tr["launches"]
+        out["roofline_bsr16_sweep"] = dict(
+            kernel="k_bsr16_sweep<false> (one colour of the finest level, BF16 blocks on MFMA)", bound="hbm",
+            launches=tr["launches"], avg_us=round(avg_s * 1e6, 2), algorithmic_bytes_per_launch=int(per),
+            achieved=round(per / avg_s / 1e9, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+            frac=round(per / avg_s / 1e9 / HBM_PEAK_GBS, 4))
+    bir, fir, pir = out["bf16_ridge"]["ir"], out["fp64_ridge"]["ir"], out["fp64_plain_fit"]["ir"]
+    out["bf16_ir_vs_fp64_ir_same_fit"] = dict(speedup=round(fir["solve_ms"] / bir["solve_ms"], 3),
+                                              rho_ratio=round(bir["rho"] / fir["rho"], 4))
+    out["bf16_ir_vs_plain_fp64_ir"] = dict(speedup=round(pir["solve_ms"] / bir["solve_ms"], 3),
+                                           rho_ratio=round(bir["rho"] / pir["rho"], 4))
     s.close()
     return out
 
@@ -395,6 +437,12 @@ def main():
         info = step()
         log(f"warmup {w}: setup {info['setup_ms']:.1f} ms, solve {info['solve_ms']:.1f} ms, "
             f"{info['iterations']} it, rho {info['rho']:.4f}")
+    # launch schedules per level and eager vs graph replay, by measurement (kept across setups)
+    sched = s.autotune(args.nrhs)
+    replay, vc_eager, vc_graph = s.graphs()
+    tuned = dict(rows_per_workgroup=[w for w, _, _ in sched], workgroup_cap=[g for _, g, _ in sched],
+                 vcycle_ms_eager=round(vc_eager, 3), vcycle_ms_graph=round(vc_graph, 3), graph_replay=replay)
+    log(f"autotune: V-cycle {vc_eager:.3f} ms eager, {vc_graph:.3f} ms replayed")
     torch.cuda.synchronize()
     if not args.no_trace:
         s.trace(("sweep",), period=args.trace_period)
@@ -446,6 +494,12 @@ def main():
     for method in ("ir", "cg", "gmres", "fgmres"):
         if method != args.solver:
             extra[f"{args.precision}_{method}"] = run(method, args.precision)
+    # the same solves with every outer iteration replayed from a captured graph (untraced)
+    s.set_graphs(True)
+    for method in ("ir", "cg"):
+        extra[f"{args.precision}_{method}_graph_replay"] = run(method, args.precision + "_graph")
+    s.set_graphs(replay)
+    extra["autotune"] = tuned
     if not args.no_fp64_baseline and args.precision != "fp64":
         # the plain FP64 V-cycle (every kernel in FP64) under the same outer methods
         s.set_precision("fp64")

@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define CS_ABI_VERSION 2
+#define CS_ABI_VERSION 3
 
 typedef struct cs_ctx_s *cs_ctx;
 
@@ -60,8 +60,11 @@ typedef enum { CS_ADDITIVE = 0, CS_MULTIPLICATIVE = 1 } cs_mode;   /* Sec. 2.1 /
 typedef enum { CS_FF = 0, CS_RF = 1 } cs_order;   /* pre-smoother forward / reverse; post is forward (Sec. 2.4) */
 /* V-cycle working precision.  CS_BF16: FP32 vectors and arithmetic, with A and
  * Lambda of 16x16-block levels stored in BF16 and applied on the matrix cores
- * (FP32 accumulation) in the multicoloured sweeps and the residual when the
- * solve has one right-hand side; everything else as CS_FP32. */
+ * (FP32 accumulation) in the multicoloured sweeps when the solve has one
+ * right-hand side; everything else, including the residual restricted to the
+ * coarse level (FP32 A), as CS_FP32.  Cascades whose blocks cancel nearly
+ * dependent directions need the regularised fit (cs_options.ridge) to converge
+ * with BF16 blocks. */
 typedef enum { CS_FP64 = 0, CS_FP32 = 1, CS_BF16 = 2 } cs_precision;
 
 /* One level of the geometric hierarchy (Sec. 2.4); levels[0] is the finest and
@@ -97,6 +100,15 @@ typedef struct {
     int32_t n_pre, n_post;      /* cascade applications before / after the coarse correction (>= 1) */
     int32_t trunc_alpha;        /* keep the alpha largest blocks per row of E (Alg. 2 optional step); 0 = keep all */
     int32_t precision;          /* cs_precision of the V-cycle */
+    /* Tikhonov-regularised fit (an extension for reduced-precision cascades,
+     * not in the paper): every block solves Lambda~_i (G_i + tau_i I) = H_i with
+     * tau_i = ridge * trace(G_i) / n, i.e. it minimises
+     * ||E_i - Lambda~_i M_i||_F^2 + tau_i ||Lambda~_i||_F^2 (Alg. 2 least-squares
+     * step).  0 = the paper's fit.  Bounds the blocks that cancel nearly
+     * dependent directions of M_i, which BF16 application would amplify.
+     * Exact fits only (cs_setup, the coarse levels of cs_setup_learned); must
+     * be 0 for cs_setup_sketched and for levels with overlapping blocks. */
+    double ridge;
 } cs_options;
 
 typedef struct {
@@ -293,9 +305,24 @@ cs_status cs_get_lattice_stats(cs_ctx ctx, int32_t level, int64_t *fitted, int32
  * solves, until the level is replaced.  Results are identical under every
  * schedule.  Outputs per level (host arrays of n_levels, each may be NULL):
  * rows per workgroup (0 for a level without sweeps), workgroup cap (0 = none)
- * and the best time in ms.  The workspace vectors of every level are
- * overwritten. */
+ * and the best time in ms.  Then one V-cycle is timed eagerly and replayed
+ * from a graph, and graph replay of the outer iterations is switched on when
+ * it is faster (cs_set_graphs / cs_get_graphs).  The workspace vectors of
+ * every level are overwritten. */
 cs_status cs_autotune(cs_ctx ctx, int32_t nrhs, int32_t *wgs, int64_t *grid, double *ms);
+
+/* Graph replay of the outer iterations.  With on = 1, cs_solve and
+ * cs_solve_cg issue the device work of every iteration after the first (the
+ * V-cycle and the vector updates; the batch's per-system norms included) as
+ * one launch of a HIP graph captured on first use, on the context's own
+ * stream (ordered after and before the caller's).  The graph is recaptured
+ * when the vectors, right-hand-side count, precision, method or device buffers
+ * change.  Results are identical to eager launches.  Solves with event
+ * tracing on (cs_trace) run eagerly.  cs_autotune decides it by measurement
+ * (one V-cycle eager vs replayed); cs_get_graphs reports the setting and, after
+ * cs_autotune, both V-cycle times in ms (0 before). */
+cs_status cs_set_graphs(cs_ctx ctx, int32_t on);
+cs_status cs_get_graphs(cs_ctx ctx, int32_t *on, double *eager_ms, double *graph_ms);
 
 /* Device timing of kernel classes with HIP events recorded on the context's
  * stream around every launch of the class (for measurement; adds one event pair

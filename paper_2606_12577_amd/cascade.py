@@ -46,7 +46,7 @@ class cs_level(ctypes.Structure):
 class cs_options(ctypes.Structure):
     _fields_ = [("depth", ctypes.c_int32), ("mode", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("n_pre", ctypes.c_int32), ("n_post", ctypes.c_int32), ("trunc_alpha", ctypes.c_int32),
-                ("precision", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("ridge", ctypes.c_double)]
 
 
 class cs_info(ctypes.Structure):
@@ -74,6 +74,8 @@ SIGNATURES = {
     "cs_smooth": (_I32, [_VP, _I32, _I32, _VP, _VP, _I32]),
     "cs_vcycle": (_I32, [_VP, _VP, _VP, _I32]),
     "cs_vcycle_noalloc": (_I32, [_VP, _VP, _VP, _I32]),
+    "cs_set_graphs": (_I32, [_VP, _I32]),
+    "cs_get_graphs": (_I32, [_VP, _p(_I32), _p(_D), _p(_D)]),
     "cs_solve": (_I32, [_VP, _VP, _VP, _I32, _D, _I32, _p(cs_info), _p(_D)]),
     "cs_solve_cg": (_I32, [_VP, _VP, _VP, _I32, _D, _I32, _p(cs_info), _p(_D)]),
     "cs_solve_gmres": (_I32, [_VP, _VP, _VP, _I32, _D, _I32, _I32, _I32, _p(cs_info), _p(_D)]),
@@ -282,8 +284,8 @@ class Solver:
         return (fitted, rep) if classes else fitted
 
     def setup(self, depth: int = 3, mode: str = "additive", order: str = "RF", n_pre: int = 1,
-              n_post: int = 1, alpha: int = 0, precision: str = "fp64"):
-        o = cs_options(depth, _MODES[mode], _ORDERS[order], n_pre, n_post, alpha, _PRECS[precision])
+              n_post: int = 1, alpha: int = 0, precision: str = "fp64", ridge: float = 0.0):
+        o = cs_options(depth, _MODES[mode], _ORDERS[order], n_pre, n_post, alpha, _PRECS[precision], ridge)
         self.depth = depth
         self._check(self._lib.cs_setup(self._h, ctypes.byref(o)))
 
@@ -445,6 +447,16 @@ class Solver:
         wgs, grid, ms = np.zeros(L, np.int32), np.zeros(L, np.int64), np.zeros(L)
         self._check(self._lib.cs_autotune(self._h, nrhs, _ptr(wgs, _I32), _ptr(grid, _I64), _ptr(ms, _D)))
         return [(int(w), int(g), float(t)) for w, g, t in zip(wgs, grid, ms)]
+
+    def set_graphs(self, on: bool):
+        """Replay the outer iterations of refinement / CG solves from a graph."""
+        self._check(self._lib.cs_set_graphs(self._h, int(bool(on))))
+
+    def graphs(self):
+        """(replay on?, V-cycle ms eager, V-cycle ms replayed) - the times of the last autotune."""
+        on, e, g = ctypes.c_int32(), ctypes.c_double(), ctypes.c_double()
+        self._check(self._lib.cs_get_graphs(self._h, ctypes.byref(on), ctypes.byref(e), ctypes.byref(g)))
+        return bool(on.value), e.value, g.value
 
     def trace(self, classes=("sweep",), period: int = 1):
         """Start (clearing the counters) event timing of every period-th launch

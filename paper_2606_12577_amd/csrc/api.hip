@@ -190,7 +190,7 @@ unsigned char *device_scratch(int device) {
 }
 
 const uint64_t SAVE_MAGIC = 0x3150555445535343ull;  // "CSSETUP1"
-const int32_t SAVE_VERSION = 2;
+const int32_t SAVE_VERSION = 3;
 
 }  // namespace
 
@@ -335,10 +335,12 @@ cs_status cs_setup(cs_ctx ctx, const cs_options *opt) {
         need(opt->trunc_alpha >= 0, "trunc_alpha must be >= 0");
         need(opt->precision == CS_FP64 || opt->precision == CS_FP32 || opt->precision == CS_BF16,
              "precision must be FP64, FP32 or BF16");
+        need(opt->ridge >= 0.0 && opt->ridge < 1e6, "ridge must be in [0, 1e6)");
         bool ovl = false;
         for (const Level &L : c.lv) ovl |= L.ovl_m > 0;
         need(!ovl || (opt->mode == CS_ADDITIVE && opt->order == CS_FF && opt->trunc_alpha == 0),
              "overlapping blocks take additive cascades applied forward (FF), without truncation");
+        need(!ovl || opt->ridge == 0.0, "the regularised fit does not apply to overlapping blocks");
         c.have_setup = false;
         c.opt = *opt;
         c.precision = opt->precision;
@@ -358,6 +360,7 @@ cs_status cs_setup_sketched(cs_ctx ctx, const cs_options *opt, int32_t s, const 
         need(opt->order == CS_FF || opt->order == CS_RF, "order must be FF or RF");
         need(opt->n_pre >= 1 && opt->n_post >= 0, "need n_pre >= 1 and n_post >= 0");
         need(opt->trunc_alpha == 0, "truncation applies to the exact fit only");
+        need(opt->ridge == 0.0, "the regularised fit applies to the exact fit only");
         int64_t nbmax = 1;
         for (const Level &L : c.lv) nbmax = std::max<int64_t>(nbmax, L.nb);
         // with s <= n the first level fits every sketch column exactly: T_1 = 0
@@ -387,6 +390,7 @@ cs_status cs_setup_learned(cs_ctx ctx, const cs_options *opt, cs_mlp mlp, const 
         need(opt != nullptr && mlp != nullptr && X != nullptr, "options, network or features missing");
         need(opt->depth >= 1 && opt->depth <= 16, "depth must be in [1, 16]");
         need(opt->mode == CS_ADDITIVE, "the learned setup fits additive cascades");
+        need(opt->ridge >= 0.0 && opt->ridge < 1e6, "ridge must be in [0, 1e6)");
         need(opt->order == CS_FF || opt->order == CS_RF, "order must be FF or RF");
         need(opt->n_pre >= 1 && opt->n_post >= 0, "need n_pre >= 1 and n_post >= 0");
         need(opt->precision == CS_FP64 || opt->precision == CS_FP32 || opt->precision == CS_BF16,
@@ -687,6 +691,26 @@ cs_status cs_autotune(cs_ctx ctx, int32_t nrhs, int32_t *wgs, int64_t *grid, dou
             if (wgs) wgs[l] = c.lv[l].tune_wgs;
             if (grid) grid[l] = c.lv[l].tune_grid;
         }
+        double e = 0.0, g = 0.0;
+        cs::tune_graphs(c, nrhs, &e, &g);
+        c.tune_vcycle_ms[0] = e;
+        c.tune_vcycle_ms[1] = g;
+    });
+}
+
+cs_status cs_set_graphs(cs_ctx ctx, int32_t on) {
+    return guarded(ctx, [&](Ctx &c) {
+        need(on == 0 || on == 1, "graph replay is 0 (off) or 1 (on)");
+        c.use_graphs = on != 0;
+    });
+}
+
+cs_status cs_get_graphs(cs_ctx ctx, int32_t *on, double *eager_ms, double *graph_ms) {
+    return guarded(ctx, [&](Ctx &c) {
+        need(on != nullptr, "null output");
+        *on = c.use_graphs ? 1 : 0;
+        if (eager_ms) *eager_ms = c.tune_vcycle_ms[0];
+        if (graph_ms) *graph_ms = c.tune_vcycle_ms[1];
     });
 }
 
@@ -806,16 +830,6 @@ int trace_begin(Ctx &c, int cls, double bytes) {
     Trace &t = c.tr;
     if (!t.on || !((t.mask >> cls) & 1)) return -1;
     if (t.seen[cls]++ % t.period != 0) return -1;
-    if (t.capturing) {
-        // graph slot g is returned as -(g + 2); its events come from the pool
-        // created before the capture began
-        const int g = (int)t.gcls.size();
-        if (2 * (size_t)g + 2 > t.gev.size()) fail(CS_EDEVICE, "trace event pool exhausted during graph capture");
-        t.gcls.push_back(cls);
-        t.gbytes.push_back(bytes);
-        CS_HIP(hipEventRecordWithFlags(t.gev[2 * g], c.stream, hipEventRecordExternal));
-        return -(g + 2);
-    }
     if (2 * t.used + 2 > t.ev.size()) {
         hipEvent_t a, b;
         CS_HIP(hipEventCreate(&a));
@@ -835,7 +849,6 @@ int trace_begin(Ctx &c, int cls, double bytes) {
 int trace_begin_launch(Ctx &c, int cls, double bytes, hipEvent_t *start, hipEvent_t *stop) {
     *start = *stop = nullptr;
     Trace &t = c.tr;
-    if (t.capturing) return trace_begin(c, cls, bytes);   // event nodes around the launch
     if (!t.on || !((t.mask >> cls) & 1)) return -1;
     if (t.seen[cls]++ % t.period != 0) return -1;
     if (2 * t.used + 2 > t.ev.size()) {
@@ -857,23 +870,7 @@ int trace_begin_launch(Ctx &c, int cls, double bytes, hipEvent_t *start, hipEven
 
 void trace_end(Ctx &c, int slot) {
     if (slot == -1) return;
-    if (slot <= -2) {
-        const int g = -slot - 2;
-        CS_HIP(hipEventRecordWithFlags(c.tr.gev[2 * g + 1], c.stream, hipEventRecordExternal));
-        return;
-    }
     CS_HIP(hipEventRecord(c.tr.ev[2 * slot + 1], c.stream));
-}
-
-void trace_graph_accumulate(Ctx &c) {
-    Trace &t = c.tr;
-    for (size_t g = 0; g < t.gcls.size(); ++g) {
-        float ms = 0;
-        CS_HIP(hipEventElapsedTime(&ms, t.gev[2 * g], t.gev[2 * g + 1]));
-        t.ms[t.gcls[g]] += ms;
-        t.count[t.gcls[g]] += 1;
-        t.bytes[t.gcls[g]] += t.gbytes[g];
-    }
 }
 
 void graph_release(Ctx &c) {
@@ -881,17 +878,7 @@ void graph_release(Ctx &c) {
     if (c.graph) (void)hipGraphDestroy(c.graph);
     c.gexec = nullptr;
     c.graph = nullptr;
-    c.tr.gcls.clear();
-    c.tr.gbytes.clear();
     c.gkey = Ctx::GraphKey{};
-}
-
-void trace_graph_pool(Ctx &c, size_t slots) {
-    while (c.tr.gev.size() < 2 * slots) {
-        hipEvent_t e;
-        CS_HIP(hipEventCreate(&e));
-        c.tr.gev.push_back(e);
-    }
 }
 
 void trace_flush(Ctx &c) {
@@ -909,8 +896,6 @@ void trace_flush(Ctx &c) {
 }
 
 void trace_release(Ctx &c) {
-    for (hipEvent_t e : c.tr.gev) (void)hipEventDestroy(e);
-    c.tr.gev.clear();
     for (hipEvent_t e : c.tr.ev) (void)hipEventDestroy(e);
     c.tr.ev.clear();
     c.tr.cls.clear();

@@ -103,24 +103,6 @@ __global__ __launch_bounds__(WG) void k_bsr16_sweep(int64_t nblk, const int32_t 
     }
 }
 
-// r = A x - b on block rows 0..nblk-1
-__global__ __launch_bounds__(WG) void k_bsr16_residual(int64_t nblk, const int32_t *__restrict__ bptr,
-                                                       const int32_t *__restrict__ bcol,
-                                                       const unsigned short *__restrict__ aval,
-                                                       const float *__restrict__ b, const float *__restrict__ x,
-                                                       float *__restrict__ r) {
-    const int lane = threadIdx.x & 63;
-    const int64_t i = (int64_t)blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
-    if (i >= nblk) return;
-    const int kg = lane >> 4;
-    const f32x4 acc = block_row_product((int)i, lane, bptr, bcol, aval, x);
-    if ((lane & 15) == 0) {
-        const float4 bv = *reinterpret_cast<const float4 *>(b + i * 16 + kg * 4);
-        *reinterpret_cast<float4 *>(r + i * 16 + kg * 4) =
-            float4{acc[0] - bv.x, acc[1] - bv.y, acc[2] - bv.z, acc[3] - bv.w};
-    }
-}
-
 __device__ __forceinline__ int64_t op_pos(int i, int k) { return 4 * (i + 16 * (k >> 2)) + (k & 3); }
 
 // BF16 copy of A's 16x16 blocks in operand order (blocks of the block-CSR
@@ -223,13 +205,6 @@ void bf16_sweep(Ctx &c, const Level &L, int ell, int colour, bool reverse, bool 
                            L.cblk.get() + k0, L.bsr_ptr.get(), L.bsr_col.get(), L.a16.get(), lam, b, x);
     CS_LAUNCH_CHECK();
     trace_end(c, slot);
-}
-
-void bf16_residual(Ctx &c, const Level &L, const float *b, const float *x, float *r) {
-    const int64_t nblk = L.n_active / 16;
-    hipLaunchKernelGGL(k_bsr16_residual, dim3(gdim(nblk, WG / 64)), dim3(WG), 0, c.stream, nblk, L.bsr_ptr.get(),
-                       L.bsr_col.get(), L.a16.get(), b, x, r);
-    CS_LAUNCH_CHECK();
 }
 
 }  // namespace cs

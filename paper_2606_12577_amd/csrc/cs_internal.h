@@ -193,12 +193,6 @@ struct Trace {
     std::vector<int> cls;
     std::vector<double> cls_bytes;       // per recorded launch
     size_t used = 0;
-    // launches recorded while a graph is captured: external event-record
-    // nodes, read back after every replay
-    bool capturing = false;
-    std::vector<hipEvent_t> gev;
-    std::vector<int> gcls;
-    std::vector<double> gbytes;
     double ms[CS_TRACE_NCLASS] = {0};
     int64_t count[CS_TRACE_NCLASS] = {0};
     double bytes[CS_TRACE_NCLASS] = {0};
@@ -230,7 +224,7 @@ struct Ctx {
     // solve workspace
     DBuf<double> ir_partial, ir_norm;
     DBuf<double> cg_r, cg_p, cg_q;      // conjugate-gradient vectors [n][R] (FP64)
-    DBuf<double> cg_zq, cg_pq[2];       // per (system, RHS): (z, q_prev); (p, q) and (p, r), ping-pong
+    DBuf<double> cg_zq, cg_pq;          // per (system, RHS): (z, q_prev); (p, q) and (p, r)
     DBuf<int32_t> cg_sys_wg;            // batch: first workgroup of every system in the flat kernels
     DBuf<double> cg_partial;            // batch: flat-kernel partial sums [workgroups][R]
     double *h_norm = nullptr;           // pinned host copy of ir_norm
@@ -247,8 +241,10 @@ struct Ctx {
     int64_t sweep_grid = int64_t(1) << 40;   // cap on workgroups of the tiled kernels (multiple of 8)
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     Trace tr;
-    // graph replay of one refinement iteration (on the internal work stream)
-    bool use_graphs = false;            // measured no faster than eager launches; CS_GRAPHS=1 enables
+    // graph replay of the outer iterations of cs_solve / cs_solve_cg (on the
+    // internal work stream; cs_set_graphs, cs_autotune or CS_GRAPHS=1)
+    bool use_graphs = false;
+    double tune_vcycle_ms[2] = {0.0, 0.0};   // last cs_autotune: V-cycle eager, replayed
     uint64_t gen = 0;                   // bumped whenever device buffers the graph uses change
     hipStream_t work = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -263,22 +259,21 @@ struct Ctx {
         const void *b = nullptr, *x = nullptr;
         int nrhs = 0, prec = -1, mask = 0;
         uint64_t gen = 0;
+        int method = -1;                // 0 refinement, 1 conjugate gradients
         bool operator==(const GraphKey &o) const {
-            return b == o.b && x == o.x && nrhs == o.nrhs && prec == o.prec && mask == o.mask && gen == o.gen;
+            return b == o.b && x == o.x && nrhs == o.nrhs && prec == o.prec && mask == o.mask && gen == o.gen &&
+                   method == o.method;
         }
     } gkey;
 };
 
 void graph_release(Ctx &c);
-void trace_graph_accumulate(Ctx &c);
-void trace_graph_pool(Ctx &c, size_t slots);   // pre-create events for `slots` traced launches
 
 // tracing helpers (api.hip)
 int trace_begin(Ctx &c, int cls, double bytes);   // returns slot or -1
 // For one launch that records its own start and end (hipExtLaunchKernelGGL with
 // *start / *stop, null when the launch is not sampled): the kernel's duration
-// without event-packet overhead.  Under graph capture it falls back to event
-// nodes, and the caller then ends the slot with trace_end (slot <= -2).
+// without event-packet overhead.  (Solves replayed from graphs are not traced.)
 int trace_begin_launch(Ctx &c, int cls, double bytes, hipEvent_t *start, hipEvent_t *stop);
 void trace_end(Ctx &c, int slot);
 void trace_flush(Ctx &c);
@@ -301,7 +296,6 @@ void build_bf16_level(Ctx &c, Level &L);
 void build_bf16_smoother(Ctx &c, Level &L);
 bool use_bf16(const Ctx &c, const Level &L);
 void bf16_sweep(Ctx &c, const Level &L, int ell, int colour, bool reverse, bool zero, const float *b, float *x);
-void bf16_residual(Ctx &c, const Level &L, const float *b, const float *x, float *r);
 
 // solve.hip
 void ensure_workspace(Ctx &c, int nrhs);
@@ -314,6 +308,7 @@ void solve_ir(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
 void solve_cg(Ctx &c, const double *b, double *x, int nrhs, double rtol, int maxit, cs_info *info,
               double *history, cs_status *st);
 void autotune(Ctx &c, int nrhs, double *ms_out);
+void tune_graphs(Ctx &c, int nrhs, double *eager_ms, double *graph_ms);
 void solve_gmres(Ctx &c, const double *b, double *x, int nrhs, double rtol, int maxit, int restart, bool flexible,
                  cs_info *info, double *history, cs_status *st);
 

@@ -570,13 +570,18 @@ __global__ __launch_bounds__(WG) void k_rowprod_nb(const int32_t *__restrict__ l
     }
 }
 
-// Lambda~ G = H for one block (G, H: nb x nb in LDS, row-major), by the whole
-// workgroup; Lc and V are LDS scratch of MAXNB^2 doubles.  Writes Lambda~ to out
-// and, from thread 0, whether G was (numerically) singular to *singular.
+// Lambda~ (G + tau I) = H for one block (G, H: nb x nb in LDS, row-major), by
+// the whole workgroup, tau = ridge tr(G) / nb (ridge = 0: the plain normal
+// equations; ridge > 0: the Tikhonov-regularised fit).  Lc and V are LDS
+// scratch of MAXNB^2 doubles.  Writes Lambda~ to out and, from thread 0,
+// whether the matrix was (numerically) singular to *singular.
 __device__ void normal_solve(const double *G, const double *H, double *Lc, double *V, int nb,
-                             double *__restrict__ out, int32_t *__restrict__ singular) {
+                             double *__restrict__ out, int32_t *__restrict__ singular, double ridge) {
     const int t = threadIdx.x;
     const int nb2 = nb * nb;
+    double trace = 0.0;
+    for (int q = 0; q < nb; ++q) trace += G[q * nb + q];
+    const double tau = ridge > 0.0 ? ridge * trace / nb : 0.0;
     // Lambda~ G = H.  Regular G: Gauss-Jordan inverse of [G | I] (G is SPD:
     // no pivoting; the pivots are the Cholesky pivots squared, with the same
     // cut-off), one thread per entry, two barriers per step.  A pivot below
@@ -585,11 +590,11 @@ __device__ void normal_solve(const double *G, const double *H, double *Lc, doubl
     __shared__ double Aug[MAXNB * 2 * MAXNB];
     const int w2 = 2 * nb;
     double dmax = 0.0;
-    for (int q = 0; q < nb; ++q) dmax = fmax(dmax, G[q * nb + q]);
+    for (int q = 0; q < nb; ++q) dmax = fmax(dmax, G[q * nb + q] + tau);
     bool bad = !(dmax > 0.0);
     for (int e = t; e < nb * w2; e += WG) {
         const int r = e / w2, c = e % w2;
-        Aug[e] = c < nb ? G[r * nb + c] : (c - nb == r ? 1.0 : 0.0);
+        Aug[e] = c < nb ? G[r * nb + c] + (r == c ? tau : 0.0) : (c - nb == r ? 1.0 : 0.0);
     }
     __syncthreads();
     constexpr int PER = (MAXNB * 2 * MAXNB + WG - 1) / WG;
@@ -632,7 +637,7 @@ __device__ void normal_solve(const double *G, const double *H, double *Lc, doubl
     __shared__ double rc_s[MAXNB / 2], rs_s[MAXNB / 2], off_s[WG], dia_s[WG];
     for (int e = t; e < m * m; e += WG) {
         const int r = e / m, c = e % m;
-        Lc[e] = (r < nb && c < nb) ? G[r * nb + c] : 0.0;
+        Lc[e] = (r < nb && c < nb) ? G[r * nb + c] + (r == c ? tau : 0.0) : 0.0;
         V[e] = r == c ? 1.0 : 0.0;
     }
     __syncthreads();
@@ -744,7 +749,8 @@ __global__ __launch_bounds__(WG) void k_gram_solve(const int32_t *__restrict__ l
                                                    const int32_t *__restrict__ mptr, const int32_t *__restrict__ mcol,
                                                    const double *__restrict__ mval, const int32_t *__restrict__ eptr,
                                                    const int32_t *__restrict__ ecol, const double *__restrict__ eval,
-                                                   double *__restrict__ lamt, int32_t *__restrict__ singular) {
+                                                   double *__restrict__ lamt, int32_t *__restrict__ singular,
+                                                   double ridge) {
     __shared__ double G[MAXNB * MAXNB], H[MAXNB * MAXNB], Lc[MAXNB * MAXNB], V[MAXNB * MAXNB];
     __shared__ int32_t epos[UNION_CAP];   // position in pattern(M_i) of every block of E_i
     const int li = blockIdx.x;
@@ -824,7 +830,7 @@ __global__ __launch_bounds__(WG) void k_gram_solve(const int32_t *__restrict__ l
         }
     }
     __syncthreads();
-    normal_solve(G, H, Lc, V, nb, lamt + (int64_t)i * nb2, singular + li);
+    normal_solve(G, H, Lc, V, nb, lamt + (int64_t)i * nb2, singular + li, ridge);
 }
 
 // G = M M^T and H = E M^T on the matrix cores (FP64 MFMA 16x16x4) for 16x16
@@ -841,7 +847,8 @@ __global__ __launch_bounds__(WG) void k_gram_mfma(const int32_t *__restrict__ li
                                                   const int32_t *__restrict__ mptr, const int32_t *__restrict__ mcol,
                                                   const double *__restrict__ mval, const int32_t *__restrict__ eptr,
                                                   const int32_t *__restrict__ ecol, const double *__restrict__ eval,
-                                                  double *__restrict__ lamt, int32_t *__restrict__ singular) {
+                                                  double *__restrict__ lamt, int32_t *__restrict__ singular,
+                                                  double ridge) {
     constexpr int NBT = 16, NB2 = NBT * NBT, QCAP = 4096;
     __shared__ double G[MAXNB * MAXNB], H[MAXNB * MAXNB], Lc[MAXNB * MAXNB], V[MAXNB * MAXNB];
     __shared__ double part[WG / 64][2][16][16];
@@ -889,7 +896,7 @@ __global__ __launch_bounds__(WG) void k_gram_mfma(const int32_t *__restrict__ li
         H[e] = h;
     }
     __syncthreads();
-    normal_solve(G, H, Lc, V, NBT, lamt + (int64_t)i * NB2, singular + li);
+    normal_solve(G, H, Lc, V, NBT, lamt + (int64_t)i * NB2, singular + li, ridge);
 }
 
 // Point blocks (n = 1): one wavefront per list row, four rows per workgroup.
@@ -926,7 +933,8 @@ __global__ __launch_bounds__(WG) void k_gram_point(int nl, const int32_t *__rest
                                                    const int32_t *__restrict__ mptr, const int32_t *__restrict__ mcol,
                                                    const double *__restrict__ mval, const int32_t *__restrict__ eptr,
                                                    const int32_t *__restrict__ ecol, const double *__restrict__ eval,
-                                                   double *__restrict__ lamt, int32_t *__restrict__ singular) {
+                                                   double *__restrict__ lamt, int32_t *__restrict__ singular,
+                                                   double ridge) {
     const int w = blockIdx.x * (WG / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (w >= nl) return;
     const int i = list[w];
@@ -946,7 +954,7 @@ __global__ __launch_bounds__(WG) void k_gram_point(int nl, const int32_t *__rest
     if (lane == 0) {
         const bool bad = !(g > 0.0);
         singular[w] = bad ? 1 : 0;
-        lamt[i] = bad ? 0.0 : h / g;
+        lamt[i] = bad ? 0.0 : h / (g + (ridge > 0.0 ? ridge * g : 0.0));   // tr(G_i) / 1 = g
     }
 }
 
@@ -1046,7 +1054,7 @@ __global__ __launch_bounds__(WG) void k_sk_gram(int nl, const int32_t *__restric
 // Lambda~_i G_i = H_i per list block (the exact fit's solve), one workgroup each
 __global__ __launch_bounds__(WG) void k_sk_solve(const int32_t *__restrict__ list, int nb,
                                                  const double *__restrict__ gh, double *__restrict__ lamt,
-                                                 int32_t *__restrict__ singular) {
+                                                 int32_t *__restrict__ singular, double ridge) {
     __shared__ double G[MAXNB * MAXNB], H[MAXNB * MAXNB], Lc[MAXNB * MAXNB], V[MAXNB * MAXNB];
     const int wi = blockIdx.x, nb2 = nb * nb;
     const double *src = gh + (int64_t)wi * 2 * nb2;
@@ -1055,7 +1063,7 @@ __global__ __launch_bounds__(WG) void k_sk_solve(const int32_t *__restrict__ lis
         H[e] = src[nb2 + e];
     }
     __syncthreads();
-    normal_solve(G, H, Lc, V, nb, lamt + (int64_t)list[wi] * nb2, singular + wi);
+    normal_solve(G, H, Lc, V, nb, lamt + (int64_t)list[wi] * nb2, singular + wi, ridge);
 }
 
 // ---- overlapping blocks (Sec. 3.6.2), sketched form -------------------------
@@ -2664,13 +2672,13 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
             if (nb == 1)
                 hipLaunchKernelGGL(k_gram_point, dim3((unsigned)ceil_div(nl, WG / 64)), dim3(WG), 0, s, nl,
                                    dlist, mp.ptr.get(), mp.col.get(), mval.get(), E.pat.ptr.get(),
-                                   E.pat.col.get(), E.val.get(), lam_l, sing.get());
+                                   E.pat.col.get(), E.val.get(), lam_l, sing.get(), o.ridge);
             else {
                 auto go = [&](auto nbc) {
                     constexpr int NBT = decltype(nbc)::value;
                     hipLaunchKernelGGL((k_gram_solve<NBT>), dim3(nl), dim3(WG), 0, s, dlist, nb, mp.ptr.get(),
                                        mp.col.get(), mval.get(), E.pat.ptr.get(), E.pat.col.get(), E.val.get(),
-                                       lam_l, sing.get());
+                                       lam_l, sing.get(), o.ridge);
                 };
                 switch (nb) {
                     case 2: go(std::integral_constant<int, 2>{}); break;
@@ -2679,7 +2687,7 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
                     case 16:
                         hipLaunchKernelGGL(k_gram_mfma, dim3(nl), dim3(WG), 0, s, dlist, mp.ptr.get(),
                                            mp.col.get(), mval.get(), E.pat.ptr.get(), E.pat.col.get(),
-                                           E.val.get(), lam_l, sing.get());
+                                           E.val.get(), lam_l, sing.get(), o.ridge);
                         break;
                     default: go(std::integral_constant<int, 0>{}); break;
                 }
@@ -2831,7 +2839,7 @@ void fit_level_overlap_exact(Ctx &c, Level &L, const cs_options &o) {
         hipLaunchKernelGGL(k_ovl_gram_sparse, gb, dim3(WG), 0, s, nblk, m, L.ovl_nodes.get(), mp.ptr.get(),
                            mp.col.get(), mval.get(), E.pat.ptr.get(), E.pat.col.get(), E.val.get(), gh.get());
         hipLaunchKernelGGL(k_sk_solve, dim3((unsigned)nblk), dim3(WG), 0, s, list.get(), m, (const double *)gh.get(),
-                           lam_l, sing.get());
+                           lam_l, sing.get(), 0.0);
         CS_LAUNCH_CHECK();
         L.singular += reduce_i32(c, sing.get(), nblk, true);
         if (ell == depth) break;
@@ -2894,7 +2902,7 @@ void fit_level_overlap_sketched(Ctx &c, Level &L, const cs_options &o, const dou
             hipLaunchKernelGGL(k_ovl_gram<MB>, gb, dim3(WG), 0, s, nblk, m, L.ovl_nodes.get(), sk,
                                (const double *)M.get(), (const double *)T.get(), gh.get());
             hipLaunchKernelGGL(k_sk_solve, dim3((unsigned)nblk), dim3(WG), 0, s, list.get(), m,
-                               (const double *)gh.get(), lam_l, sing.get());
+                               (const double *)gh.get(), lam_l, sing.get(), 0.0);
             if (ell < depth) {
                 hipLaunchKernelGGL(k_ovl_y<MB>, gb, dim3(WG), 0, s, nblk, m, L.ovl_nodes.get(), sk,
                                    (const double *)lam_l, (const double *)M.get(), Y.get());
@@ -2966,7 +2974,7 @@ void fit_level_sketched(Ctx &c, Level &L, const cs_options &o, const double *S, 
                     hipLaunchKernelGGL(k_sk_gram<NB>, gw, dim3(WG), 0, s, nl, list, L.a_ptr.get(), L.a_col.get(),
                                        L.a_val.get(), L.w.get(), sk, (const double *)Tin, Mb.get(), gh.get());
                     hipLaunchKernelGGL(k_sk_solve, dim3((unsigned)nl), dim3(WG), 0, s, list, nb,
-                                       (const double *)gh.get(), lam_l, sing.get());
+                                       (const double *)gh.get(), lam_l, sing.get(), 0.0);
                     hipLaunchKernelGGL(k_sk_update<NB>, gw, dim3(WG), 0, s, nl, list, sk, (const double *)lam_l,
                                        (const double *)Mb.get(), Tin);
                 };

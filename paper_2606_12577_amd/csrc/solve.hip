@@ -1389,7 +1389,6 @@ void launch_sweep(Ctx &c, const Level &L, const Sell &S, bool rowmap, bool zero,
 #undef CS_SWEEP
     });
     CS_LAUNCH_CHECK();
-    if (slot <= -2) trace_end(c, slot);
 }
 
 // Overlapping blocks (Sec. 3.6.2): y = Lambda_l Theta r over the replicated
@@ -1595,15 +1594,13 @@ void vcycle_level(Ctx &c, int l) {
                                reinterpret_cast<T *>(C.w_bb));
         });
     } else {
-        bool bf16 = false;
-        if constexpr (std::is_same<T, float>::value && R == 1) {
-            bf16 = use_bf16(c, L);
-            if (bf16) bf16_residual(c, L, bb, x, rr);
-        }
-        if (!bf16)
-            hipLaunchKernelGGL((k_residual<T, R>), dim3(tile_grid(c, L.act_slices)), dim3(WG), 0, c.stream, na,
-                               L.act_slices, L.sell.slice_ptr.get(), L.sell.slice_len.get(), L.sell.col.get(),
-                               sell_val<T>(L.sell), bb, x, rr);
+        // the residual that the coarse level sees is formed in the working
+        // precision's vector type with the FP32/FP64 copy of A, also when the
+        // sweeps run in BF16: BF16 rounding of A here would corrupt the smooth
+        // error components that the coarse-grid correction must remove
+        hipLaunchKernelGGL((k_residual<T, R>), dim3(tile_grid(c, L.act_slices)), dim3(WG), 0, c.stream, na,
+                           L.act_slices, L.sell.slice_ptr.get(), L.sell.slice_len.get(), L.sell.col.get(),
+                           sell_val<T>(L.sell), bb, x, rr);
         hipLaunchKernelGGL((k_restrict_sell<T, R>), dim3(tile_grid(c, L.ptsell.nslices)), dim3(WG), 0, c.stream,
                            L.nc, L.ptsell.nslices, L.ptsell.slice_ptr.get(), L.ptsell.slice_len.get(),
                            L.ptsell.col.get(), sell_val<T>(L.ptsell), (T)L.r_scale, rr,
@@ -1928,6 +1925,130 @@ struct Monitor {
 
 }  // namespace
 
+namespace {
+
+// With graph replay the solve runs on the context's own non-blocking stream
+// (capture needs one), ordered after the caller's stream on entry and before
+// it on exit.  Replay is off while event tracing is on.
+struct SolveStream {
+    Ctx &c;
+    hipStream_t user;
+    bool on;
+    SolveStream(Ctx &cc, bool enable) : c(cc), user(cc.stream), on(enable) {
+        if (!on) return;
+        if (!c.work) CS_HIP(hipStreamCreateWithFlags(&c.work, hipStreamNonBlocking));
+        CS_HIP(hipEventRecord(c.ev_in, user));
+        CS_HIP(hipStreamWaitEvent(c.work, c.ev_in, 0));
+        c.stream = c.work;
+    }
+    ~SolveStream() {
+        if (!on) return;
+        (void)hipEventRecord(c.ev_out, c.stream);
+        (void)hipStreamWaitEvent(user, c.ev_out, 0);
+        c.stream = user;
+    }
+};
+
+// The device work of one outer iteration after the host's convergence check:
+// issued eagerly, or replayed as one graph launch (captured on first use and
+// whenever the key changes: other vectors, right-hand-side count, precision,
+// method, or device buffers).  Replays issue exactly the captured launches,
+// so both forms give identical results.
+template <class F>
+void run_iteration(Ctx &c, bool graphs, const Ctx::GraphKey &key, F &&body) {
+    if (!graphs) {
+        body();
+        return;
+    }
+    if (!c.gexec || !(key == c.gkey)) {
+        graph_release(c);
+        CS_HIP(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
+        try {
+            body();
+        } catch (...) {
+            hipGraph_t junk = nullptr;
+            (void)hipStreamEndCapture(c.stream, &junk);
+            if (junk) (void)hipGraphDestroy(junk);
+            throw;
+        }
+        CS_HIP(hipStreamEndCapture(c.stream, &c.graph));
+        CS_HIP(hipGraphInstantiate(&c.gexec, c.graph, nullptr, nullptr, 0));
+        c.gkey = key;
+    }
+    CS_HIP(hipGraphLaunch(c.gexec, c.stream));
+}
+
+// however a solve loop ends, no later V-cycle skips its first sweep
+struct SpecReset {
+    Ctx &c;
+    ~SpecReset() { c.spec_pending = false; }
+};
+
+}  // namespace
+
+// Eager launches or graph replay for the outer iterations, by measurement:
+// one V-cycle issued eagerly and the same V-cycle replayed from a captured
+// graph are each timed five times on the work stream (median); replay is kept
+// when it is faster.  Returns the two medians in ms (eager, graph).
+void tune_graphs(Ctx &c, int nrhs, double *eager_ms, double *graph_ms) {
+    ensure_workspace(c, nrhs);
+    const bool tr = c.tr.on;
+    c.tr.on = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    auto cleanup = [&]() {
+        if (ge) (void)hipGraphExecDestroy(ge);
+        if (g) (void)hipGraphDestroy(g);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        c.tr.on = tr;
+    };
+    try {
+        SolveStream ss(c, true);
+        CS_HIP(hipEventCreate(&e0));
+        CS_HIP(hipEventCreate(&e1));
+        dispatch_prec(c.precision, [&](auto tp) {
+            using T = std::remove_pointer_t<decltype(tp)>;
+            dispatch_r(nrhs, [&](auto rc) {
+                constexpr int R = decltype(rc)::value;
+                auto median = [&](auto &&issue) {
+                    issue();   // warm-up
+                    std::vector<float> t(5);
+                    for (float &v : t) {
+                        CS_HIP(hipEventRecord(e0, c.stream));
+                        issue();
+                        CS_HIP(hipEventRecord(e1, c.stream));
+                        CS_HIP(hipEventSynchronize(e1));
+                        CS_HIP(hipEventElapsedTime(&v, e0, e1));
+                    }
+                    std::sort(t.begin(), t.end());
+                    return (double)t[2];
+                };
+                *eager_ms = median([&]() { vcycle_level<T, R>(c, 0); });
+                CS_HIP(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
+                try {
+                    vcycle_level<T, R>(c, 0);
+                } catch (...) {
+                    hipGraph_t junk = nullptr;
+                    (void)hipStreamEndCapture(c.stream, &junk);
+                    if (junk) (void)hipGraphDestroy(junk);
+                    throw;
+                }
+                CS_HIP(hipStreamEndCapture(c.stream, &g));
+                CS_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+                *graph_ms = median([&]() { CS_HIP(hipGraphLaunch(ge, c.stream)); });
+            });
+        });
+        CS_HIP(hipStreamSynchronize(c.stream));
+    } catch (...) {
+        cleanup();
+        throw;
+    }
+    cleanup();
+    c.use_graphs = *graph_ms < *eager_ms;
+}
+
 void solve_ir(Ctx &c, const double *b, double *x, int nrhs, double rtol, int maxit, cs_info *info,
               double *history, cs_status *st) {
     ensure_workspace(c, nrhs);
@@ -1938,28 +2059,8 @@ void solve_ir(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
     const int nsys = c.sys_ptr.empty() ? 1 : (int)c.sys_ptr.size() - 1;
     const double *hn = c.h_norm;
     *st = CS_OK;
-    // With graphs the solve runs on the context's own (capturable) stream,
-    // ordered after the caller's stream and followed by it.
-    // (event tracing runs eagerly: timing nodes are not available in graphs here)
     const bool graphs = c.use_graphs && !c.tr.on;
-    const hipStream_t user = c.stream;
-    if (graphs) {
-        if (!c.work) CS_HIP(hipStreamCreateWithFlags(&c.work, hipStreamNonBlocking));
-        CS_HIP(hipEventRecord(c.ev_in, user));
-        CS_HIP(hipStreamWaitEvent(c.work, c.ev_in, 0));
-        c.stream = c.work;
-    }
-    struct Restore {
-        Ctx &c;
-        hipStream_t user;
-        bool on;
-        ~Restore() {
-            if (!on) return;
-            (void)hipEventRecord(c.ev_out, c.stream);
-            (void)hipStreamWaitEvent(user, c.ev_out, 0);
-            c.stream = user;
-        }
-    } restore{c, user, graphs};
+    SolveStream ss(c, graphs);
     CS_HIP(hipEventRecord(c.ev0, c.stream));
     dispatch_prec(c.precision, [&](auto tp) {
         using T = std::remove_pointer_t<decltype(tp)>;
@@ -2014,11 +2115,18 @@ void solve_ir(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
             residual();
             Monitor mon(c, nsys, R, rtol);
             int it = 0;
+            if (!c.ev_norm) CS_HIP(hipEventCreateWithFlags(&c.ev_norm, hipEventDisableTiming));
+            SpecReset spec_reset{c};
+            const Ctx::GraphKey key{b, x, R, c.precision, 0, c.gen, 0};
             for (;; ++it) {
                 CS_HIP(hipMemcpyAsync(c.h_norm, c.ir_norm.get(), 2 * nsys * R * sizeof(double),
                                       hipMemcpyDeviceToHost, c.stream));
-                CS_HIP(hipStreamSynchronize(c.stream));
-                if (graphs && it > 0) trace_graph_accumulate(c);
+                CS_HIP(hipEventRecord(c.ev_norm, c.stream));
+                // the next V-cycle's first sweep reads only r and Lambda: issued
+                // while the host waits for the norms (one wasted sweep when this
+                // check ends the solve)
+                if (it < maxit) issue_first_sweep<T, R>(c);
+                CS_HIP(hipEventSynchronize(c.ev_norm));
                 const double rel = mon.record(it, hn);
                 if (std::isnan(rel)) {
                     *st = CS_ENAN;
@@ -2029,38 +2137,8 @@ void solve_ir(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
                     *st = CS_ENOCONV;
                     break;
                 }
-                if (graphs) {
-                    const Ctx::GraphKey key{b, x, R, c.precision, c.tr.on ? c.tr.mask : 0, c.gen};
-                    if (!c.gexec || !(key == c.gkey)) {
-                        trace_flush(c);
-                        graph_release(c);
-                        if (c.tr.on) {
-                            size_t bound = 8;
-                            for (const Level &L : c.lv)
-                                bound += (size_t)(c.opt.n_pre + c.opt.n_post) * std::max(L.depth, 1) *
-                                             std::max(L.chi, 1) + 4;
-                            trace_graph_pool(c, bound);
-                        }
-                        c.tr.capturing = true;
-                        CS_HIP(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
-                        try {
-                            iteration();
-                        } catch (...) {
-                            hipGraph_t junk = nullptr;
-                            (void)hipStreamEndCapture(c.stream, &junk);
-                            if (junk) (void)hipGraphDestroy(junk);
-                            c.tr.capturing = false;
-                            throw;
-                        }
-                        c.tr.capturing = false;
-                        CS_HIP(hipStreamEndCapture(c.stream, &c.graph));
-                        CS_HIP(hipGraphInstantiate(&c.gexec, c.graph, nullptr, nullptr, 0));
-                        c.gkey = key;
-                    }
-                    CS_HIP(hipGraphLaunch(c.gexec, c.stream));
-                } else {
-                    iteration();
-                }
+                run_iteration(c, graphs, key, iteration);
+                c.spec_pending = false;
             }
             trace_flush(c);
             CS_HIP(hipEventRecord(c.ev1, c.stream));
@@ -2088,17 +2166,23 @@ void solve_cg(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
     const int64_t G = std::min<int64_t>(ceil_div(S.nslices, 4), IR_GRID);
     const int nsys = c.sys_ptr.empty() ? 1 : (int)c.sys_ptr.size() - 1;
     const bool batch = nsys > 1;
+    // grown only: a release would synchronise the device (the pool waits as
+    // hipFree does); a new buffer makes a captured iteration stale
     if (c.cg_r.n < (size_t)n) {
         c.cg_r.alloc(n);
         c.cg_p.alloc(n);
         c.cg_q.alloc(n);
+        c.gen++;
     }
-    // grown only: a release would synchronise the device (the pool waits as hipFree does)
-    if (c.cg_zq.n < (size_t)nsys * nrhs) c.cg_zq.alloc((size_t)nsys * nrhs);
-    for (auto &pq : c.cg_pq)
-        if (pq.n < (size_t)nsys * 2 * nrhs) pq.alloc((size_t)nsys * 2 * nrhs);
+    if (c.cg_zq.n < (size_t)nsys * nrhs || c.cg_pq.n < (size_t)nsys * 2 * nrhs) {
+        c.cg_zq.alloc((size_t)nsys * nrhs);
+        c.cg_pq.alloc((size_t)nsys * 2 * nrhs);
+        c.gen++;
+    }
     double *r = c.cg_r.get(), *p = c.cg_p.get(), *q = c.cg_q.get();
     *st = CS_OK;
+    const bool graphs = c.use_graphs && !c.tr.on;
+    SolveStream ss(c, graphs);
     CS_HIP(hipEventRecord(c.ev0, c.stream));
     dispatch_prec(c.precision, [&](auto tp) {
         using T = std::remove_pointer_t<decltype(tp)>;
@@ -2159,33 +2243,16 @@ void solve_cg(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
             CS_LAUNCH_CHECK();
             Monitor mon(c, nsys, R, rtol);
             int it = 0;
-            int cur = 0;
             if (!c.ev_norm) CS_HIP(hipEventCreateWithFlags(&c.ev_norm, hipEventDisableTiming));
-            struct SpecReset {   // however the loop ends, no later V-cycle skips its first sweep
-                Ctx &c;
-                ~SpecReset() { c.spec_pending = false; }
-            } spec_reset{c};
-            for (;; ++it) {
-                CS_HIP(hipMemcpyAsync(c.h_norm, c.ir_norm.get(), 2 * nsys * R * sizeof(double),
-                                      hipMemcpyDeviceToHost, c.stream));
-                CS_HIP(hipEventRecord(c.ev_norm, c.stream));
-                if (it < maxit) issue_first_sweep<T, R>(c);   // wasted (one sweep) when this check ends the solve
-                CS_HIP(hipEventSynchronize(c.ev_norm));
-                const double rel = mon.record(it, c.h_norm);
-                if (std::isnan(rel)) {
-                    *st = CS_ENAN;
-                    break;
-                }
-                if (rel <= rtol) break;
-                if (it == maxit) {
-                    *st = CS_ENOCONV;
-                    break;
-                }
+            SpecReset spec_reset{c};
+            // (p_prev, q_prev) is read by the direction update before this
+            // iteration's (p, q) overwrites it: one buffer serves both
+            double *pq = c.cg_pq.get();
+            // one CG iteration after the check (first: p = z, no projection)
+            auto iteration = [&](bool first) {
                 vcycle_level<T, R>(c, 0);   // z = V r
-                const double *pq_prev = c.cg_pq[cur ^ 1].get();
-                double *pq = c.cg_pq[cur].get();
-                int slot = trace_begin(c, CS_TRACE_REFINE, it ? vec + L0.n * R * sizeof(T) : 0.0);
-                if (it) {
+                int slot = trace_begin(c, CS_TRACE_REFINE, first ? 0.0 : vec + L0.n * R * sizeof(T));
+                if (!first) {
                     if (flat) {
                         hipLaunchKernelGGL((k_cg_zq_flat<T, R>), dim3(Gf), dim3(WG), 0, c.stream, npairs, nsys, sys_wg,
                                            c.sys_ptr_d.get(), z, q, fpart);
@@ -2206,10 +2273,10 @@ void solve_cg(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
                 }
                 if (!flat)
                     hipLaunchKernelGGL((k_cg_p<T, R>), dim3(grid_for(L0.n)), dim3(WG), 0, c.stream, L0.n, nsys,
-                                       c.sys_ptr_d.get(), z, c.cg_zq.get(), pq_prev, p, it == 0 ? 1 : 0);
+                                       c.sys_ptr_d.get(), z, c.cg_zq.get(), pq, p, first ? 1 : 0);
                 else
                     hipLaunchKernelGGL((k_cg_p_flat<T, R>), dim3(Gf), dim3(WG), 0, c.stream, npairs, nsys, sys_wg,
-                                       c.sys_ptr_d.get(), z, c.cg_zq.get(), pq_prev, p, it == 0 ? 1 : 0);
+                                       c.sys_ptr_d.get(), z, c.cg_zq.get(), pq, p, first ? 1 : 0);
                 CS_LAUNCH_CHECK();
                 trace_end(c, slot);
                 slot = trace_begin(c, CS_TRACE_REFINE, S.nnz * 12.0 + 3.0 * vec);
@@ -2251,7 +2318,27 @@ void solve_cg(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
                     reduce(R, c.ir_norm.get());
                 }
                 trace_end(c, slot);
-                cur ^= 1;
+            };
+            const Ctx::GraphKey key{b, x, R, c.precision, 0, c.gen, 1};
+            for (;; ++it) {
+                CS_HIP(hipMemcpyAsync(c.h_norm, c.ir_norm.get(), 2 * nsys * R * sizeof(double),
+                                      hipMemcpyDeviceToHost, c.stream));
+                CS_HIP(hipEventRecord(c.ev_norm, c.stream));
+                if (it < maxit) issue_first_sweep<T, R>(c);   // wasted (one sweep) when this check ends the solve
+                CS_HIP(hipEventSynchronize(c.ev_norm));
+                const double rel = mon.record(it, c.h_norm);
+                if (std::isnan(rel)) {
+                    *st = CS_ENAN;
+                    break;
+                }
+                if (rel <= rtol) break;
+                if (it == maxit) {
+                    *st = CS_ENOCONV;
+                    break;
+                }
+                if (it == 0) iteration(true);
+                else run_iteration(c, graphs, key, [&]() { iteration(false); });
+                c.spec_pending = false;
             }
             trace_flush(c);
             CS_HIP(hipEventRecord(c.ev1, c.stream));

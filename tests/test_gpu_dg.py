@@ -97,9 +97,9 @@ def test_bf16_sweep_matches_rounded_oracle(gpu_lib, dg16):
 def test_bf16_solve_depth1_and_escalation(gpu_lib, dg16):
     """A depth-1 multicoloured cascade (block Gauss-Seidel type) tolerates
     BF16 A and Lambda: the BF16 solve converges as the FP64 one does.  The
-    depth-3 Frobenius cascade does not (an FP64 emulation of the BF16
-    rounding diverges with rho ~ 10): the solve detects the divergence and
-    finishes in FP32."""
+    depth-3 plain Frobenius cascade does not (tests/test_oracle_precision.py:
+    its large, cancelling blocks amplify BF16 rounding): the solve detects the
+    divergence and finishes in FP32."""
     p, _ = dg16
     s = gpu_lib.Solver(p.levels)
     s.setup(depth=1, mode="multiplicative", order="FF", precision="fp64")
@@ -114,3 +114,43 @@ def test_bf16_solve_depth1_and_escalation(gpu_lib, dg16):
     s.setup(depth=3, mode="multiplicative", order="FF", precision="bf16")
     x, e = s.solve(p.rhs, rtol=1e-10, maxit=200)
     assert e["precision"] == "fp32" and e["rel_res"] <= 1e-10
+
+
+@pytest.fixture(scope="module")
+def dg16_ridge():
+    p = dg.sipg_q3(16)
+    return p, O.setup_hierarchy(p.levels, 3, "multiplicative", ridge=1e-3)
+
+
+def test_ridge_fit_parity_fp64(gpu_lib, dg16_ridge):
+    """The Tikhonov-regularised fit (ridge 1e-3) against the oracle's: the
+    regularised normal equations are far better conditioned, so the per-block
+    bounds from their condition numbers are tight."""
+    p, sm = dg16_ridge
+    s = gpu_lib.Solver(p.levels)
+    s.setup(depth=3, mode="multiplicative", order="FF", ridge=1e-3)
+    for l in range(len(p.levels) - 1):
+        check_level_smoothers(s, sm[l], l, 3, "sipg_q3_16 ridge 1e-3")
+    expect = O.vcycle(p.levels, sm, p.rhs, "FF", 1, 1)
+    check_vec(s.vcycle(p.rhs).cpu().numpy(), expect, VCYCLE_TOL, "sipg_q3_16 ridge FF FP64 V-cycle, own setup")
+
+
+def test_bf16_blocks_with_ridge_fit_converge_at_depth_3(gpu_lib, dg16_ridge):
+    """BF16 blocks on the matrix cores (FP32 restricted residual) with the
+    regularised depth-3 fit: the FP64 refinement reaches 1e-10 in BF16, with
+    the convergence factor within 5% of the FP64 V-cycle's on the same fit."""
+    p, sm = dg16_ridge
+    s = gpu_lib.Solver(p.levels)
+    s.setup(depth=3, mode="multiplicative", order="FF", precision="fp64", ridge=1e-3)
+    _, f64 = s.solve(p.rhs, rtol=1e-10, maxit=200)
+    s.set_precision("bf16")
+    x, b16 = s.solve(p.rhs, rtol=1e-10, maxit=200)
+    print(f"depth 3 ridge: rho fp64 {f64['rho']:.4f} ({f64['iterations']} it), "
+          f"bf16 {b16['rho']:.4f} ({b16['iterations']} it)")
+    assert b16["precision"] == "bf16"
+    r = p.rhs - p.levels[0].A @ x.cpu().numpy()
+    assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(p.rhs)
+    assert b16["rho"] <= 1.05 * f64["rho"]
+    # the oracle's FP64 refinement with the same fit converges at the FP64 rate
+    _, hist = O.solve(p.levels, sm, p.rhs, 1e-10, 200, "FF", 1, 1)
+    assert abs(f64["iterations"] - (len(hist) - 1)) <= 1

@@ -66,6 +66,25 @@ def test_dg_fullsize_solve(full):
     assert info["rho"] < ir["rho"] < 1.0
 
 
+def test_dg_fullsize_bf16_ridge_refinement(gpu_lib, full):
+    """The configuration bench.py times: the regularised fit (ridge 1e-3), BF16
+    blocks on the matrix cores inside FP64 refinement, to 1e-10, at most 5%
+    above the FP64 V-cycle's convergence factor on the same fit."""
+    p, _ = full
+    s = gpu_lib.Solver(p.levels)
+    s.setup(depth=DEPTH, mode="multiplicative", order="FF", precision="fp64", ridge=1e-3)
+    _, f64 = s.solve(p.rhs, rtol=1e-10, maxit=400)
+    s.set_precision("bf16")
+    x, b16 = s.solve(p.rhs, rtol=1e-10, maxit=400)
+    print(f"[fullsize-dg] ridge 1e-3 refinement: fp64 {f64['iterations']} it rho {f64['rho']:.4f}, "
+          f"bf16 {b16['iterations']} it rho {b16['rho']:.4f}", flush=True)
+    assert b16["precision"] == "bf16" and b16["rel_res"] <= 1e-10
+    r = p.rhs - p.levels[0].A @ x.cpu().numpy()
+    assert np.linalg.norm(r) / np.linalg.norm(p.rhs) <= 1.5e-10
+    assert b16["rho"] <= 1.05 * f64["rho"]
+    s.close()
+
+
 def test_dg_fullsize_vcycle_injected_smoothers(full):
     """Runs last: replaces the fitted smoothers."""
     p, s = full

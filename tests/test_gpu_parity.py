@@ -333,3 +333,32 @@ def test_autotuned_schedules_give_identical_results(gpu_lib, mode):
     x1, i1 = s.solve(p.rhs, rtol=1e-10, maxit=100, method="cg")
     assert i1["iterations"] == i0["iterations"]
     np.testing.assert_array_equal(x1.cpu().numpy(), x0)
+
+
+@pytest.mark.parametrize("case,ridge", [("poisson32_points", 0.25), ("interface16_blocks8", 1e-3)])
+def test_ridge_fit_parity(gpu_lib, case, ridge):
+    """The Tikhonov-regularised fit (point blocks: the scalar kernel; 8x8
+    blocks: the blocked normal equations) against the oracle's, and its
+    V-cycle with the GPU's own setup."""
+    p = fd.poisson2d(32) if case == "poisson32_points" else fd.interface3d(16, nrhs=2)
+    sm = O.setup_hierarchy(p.levels, 3, ridge=ridge)
+    s = gpu_solver(gpu_lib, p, depth=3, ridge=ridge)
+    check_smoothers(s, sm, p, 3, f"{p.name} ridge {ridge:g}")
+    check_patterns(s, sm, p)
+    o = O.vcycle(p.levels, sm, p.rhs, "RF")
+    check_vec(s.vcycle(p.rhs).cpu().numpy(), o, VCYCLE_TOL, f"{p.name} ridge {ridge:g} RF V-cycle, own setup")
+
+
+def test_ridge_is_refused_where_it_does_not_apply(gpu_lib):
+    p = fd.poisson2d(16)
+    s = gpu_lib.Solver(p.levels)
+    with pytest.raises(gpu_lib.CascadeError) as e:
+        s.setup(depth=2, ridge=-1.0)
+    assert e.value.status == -1
+    import ctypes
+
+    import torch
+    S = torch.ones((sum(lv.n for lv in p.levels[:-1]), 8), dtype=torch.float64, device="cuda")
+    o = gpu_lib.cs_options(2, 0, 1, 1, 1, 0, 0, 1e-3)
+    st = s._lib.cs_setup_sketched(s._h, ctypes.byref(o), 8, ctypes.c_void_p(S.data_ptr()))
+    assert st == -1 and "exact fit only" in s._lib.cs_last_error(s._h).decode()
