@@ -123,13 +123,15 @@ __device__ __forceinline__ void vload_nt(const T *p, T (&o)[R]) {
 }
 
 // x_in at unknown j, minus the interpolated coarse correction when PROL:
-// x_in[j] - x_c[j / agg_k]  (contiguous unit aggregation).
+// x_in[j] - x_c[j / agg_k]  (contiguous unit aggregation; agg_k divides 64, so
+// the division is a shift - a 64-bit division per gathered entry would cost
+// more than the gather).
 template <typename T, int R, bool PROL>
 __device__ __forceinline__ void load_x(const T *xin, const T *xc, int agg_k, int64_t j, T (&o)[R]) {
     vload<T, R>(xin + j * R, o);
     if constexpr (PROL) {
         T cv[R];
-        vload<T, R>(xc + (j / agg_k) * R, cv);
+        vload<T, R>(xc + (j >> __builtin_ctz((unsigned)agg_k)) * R, cv);
 #pragma unroll
         for (int k = 0; k < R; ++k) o[k] -= cv[k];
     }
@@ -195,11 +197,15 @@ __device__ __forceinline__ void spmv_row(const int32_t *__restrict__ scol, const
 //           interpolation step of Alg. 1 fused into the first post-sweep)
 //   WGS:    workgroup size; 256 (4 slices) on large levels, 64 (one slice per
 //           workgroup, more workgroups in flight) on small ones
-// SpMV of a natural-order row of an NB-block level (NB a power of two, so a
-// block's rows sit in NB consecutive lanes of the slice): entries inside the
-// row's own block take x from the lanes that hold those rows (shuffles of the
-// x rows they loaded anyway), only the others are gathered.  For the 7-point
-// stencil on 2x2x2 blocks this removes four of the seven gathers per row.
+// SpMV of a natural-order row of an NB-block level (row = 64 slice + lane, so
+// a block's rows sit in NB consecutive lanes and the slice's 64 rows in its 64
+// lanes): entries whose column lies in the row's own slice take x from the
+// lane that holds that row (a shuffle of the x row every lane loads for its
+// own row anyway), only the others are gathered.  With the Morton numbering a
+// slice is a 4x4x4 cube of cells, so for the 7-point stencil about 1.5 of the
+// 7 entries per row are gathered (3 when only the own 2x2x2 block was served
+// this way).  Every active lane of the slice holds its row's x: a valid row
+// couples only to valid rows, which run the same code.
 template <typename T, int R, bool PROL, int NB, int L>
 __device__ __forceinline__ void spmv_fixed_blk(const int32_t *__restrict__ scol, const T *__restrict__ sval,
                                                int64_t off, const T *xin, const T *xc, int agg_k, int64_t row,
@@ -216,15 +222,15 @@ __device__ __forceinline__ void spmv_fixed_blk(const int32_t *__restrict__ scol,
             aa[u] = __builtin_nontemporal_load(sval + off + (int64_t)u * 64);
         }
     }
-    const int64_t blk = row / NB;
-    const int lbase = lane & ~(NB - 1);
+    const int64_t first = row - lane;   // the slice's first row
     T xv[L][R];
 #pragma unroll
     for (int u = 0; u < L; ++u) {
-        const int src = lbase | (cc[u] & (NB - 1));
+        const int64_t d = (int64_t)cc[u] - first;
+        const int src = (int)(d & 63);
 #pragma unroll
         for (int k = 0; k < R; ++k) xv[u][k] = __shfl(xo[k], src, 64);
-        if ((int64_t)(cc[u] / NB) != blk) load_x<T, R, PROL>(xin, xc, agg_k, cc[u], xv[u]);
+        if (d < 0 || d >= 64) load_x<T, R, PROL>(xin, xc, agg_k, cc[u], xv[u]);
     }
 #pragma unroll
     for (int u = 0; u < L; ++u) {
@@ -1355,8 +1361,10 @@ void launch_sweep(Ctx &c, const Level &L, const Sell &S, bool rowmap, bool zero,
     if (L.tune_grid > 0 && (int64_t)G > L.tune_grid) G = (unsigned)L.tune_grid;
     if (G == 0) return;
     const bool prol = xc != nullptr;
+    // trace classes by level size (not by the launch shape the autotuner picks)
+    const bool large = nslices >= SMALL_SLICES;
     const int cls = zero ? CS_TRACE_SWEEP_ZERO
-                         : (xc ? CS_TRACE_SWEEP_PROLONG : (small ? CS_TRACE_SWEEP_SMALL : CS_TRACE_SWEEP));
+                         : (xc ? CS_TRACE_SWEEP_PROLONG : (large ? CS_TRACE_SWEEP : CS_TRACE_SWEEP_SMALL));
     const double es = sizeof(T);
     const double bytes = (zero ? 0.0 : nnz * (es + 4.0)) + (double)nrows * L.nb * es +
                          (double)nrows * R * es * 2.0 + (zero ? 0.0 : (rowmap ? L.n : nrows) * R * es) +
