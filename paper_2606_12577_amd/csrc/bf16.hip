@@ -1,7 +1,7 @@
 // BF16 block kernels for 16x16 blocks (tensor Q3 DG elements): the
-// multicoloured cascade sweep and the residual with A and Lambda stored in
-// BF16 and applied on the matrix cores (v_mfma_f32_16x16x16bf16) with FP32
-// accumulation; vectors FP32.
+// multicoloured cascade sweep with A and Lambda stored in BF16 and applied on
+// the matrix cores (v_mfma_f32_16x16x16bf16) with FP32 accumulation; vectors
+// FP32.
 //
 // A block product y = M v (16x16 times a 16-vector) is one MFMA whose B
 // operand holds v in every column: lane l supplies M[l%16][4(l/16)+t] and
@@ -47,22 +47,39 @@ __device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
-// acc = sum over the blocks of row i of A_ij x_j (rows 4 kg .. 4 kg + 3)
+// acc = sum over the blocks of row i of A_ij x_j (rows 4 kg .. 4 kg + 3).
+// Blocks are taken four at a time: their block and x loads are all issued
+// before the first MFMA (a wavefront then waits once per four blocks instead
+// of once per block); the products are summed in block order.
 __device__ __forceinline__ f32x4 block_row_product(int i, int lane, const int32_t *__restrict__ bptr,
                                                    const int32_t *__restrict__ bcol,
                                                    const unsigned short *__restrict__ aval,
                                                    const float *__restrict__ x) {
+    constexpr int CH = 4;
     const int kg = lane >> 4;
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int e = bptr[i]; e < bptr[i + 1]; ++e) {
-        const int64_t j = bcol[e];
-        const bf16x4 a = *reinterpret_cast<const bf16x4 *>(aval + (int64_t)e * 256 + lane * 4);
-        const float4 xv = *reinterpret_cast<const float4 *>(x + j * 16 + kg * 4);
-        const float v[4] = {xv.x, xv.y, xv.z, xv.w};
-        bf16x4 hi, lo;
-        split(v, hi, lo);
-        acc = mfma(a, hi, acc);
-        acc = mfma(a, lo, acc);
+    const int e1 = bptr[i + 1];
+    for (int e = bptr[i]; e < e1; e += CH) {
+        bf16x4 a[CH];
+        float4 xv[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            if (e + c < e1) {   // uniform per wavefront
+                const int64_t j = bcol[e + c];
+                a[c] = *reinterpret_cast<const bf16x4 *>(aval + (int64_t)(e + c) * 256 + lane * 4);
+                xv[c] = *reinterpret_cast<const float4 *>(x + j * 16 + kg * 4);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            if (e + c < e1) {
+                const float v[4] = {xv[c].x, xv[c].y, xv[c].z, xv[c].w};
+                bf16x4 hi, lo;
+                split(v, hi, lo);
+                acc = mfma(a[c], hi, acc);
+                acc = mfma(a[c], lo, acc);
+            }
+        }
     }
     return acc;
 }
@@ -82,13 +99,14 @@ __global__ __launch_bounds__(WG) void k_bsr16_sweep(int64_t nblk, const int32_t 
     if (w >= nblk) return;   // whole wavefront
     const int i = blist[w];
     const int kg = lane >> 4;
+    // b and Lambda_i do not depend on the product: their loads go out first
+    const float4 bv = *reinterpret_cast<const float4 *>(b + (int64_t)i * 16 + kg * 4);
+    const bf16x4 l = *reinterpret_cast<const bf16x4 *>(lam + (int64_t)i * 256 + lane * 4);
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
     if constexpr (!ZERO) acc = block_row_product(i, lane, bptr, bcol, aval, x);
-    const float4 bv = *reinterpret_cast<const float4 *>(b + (int64_t)i * 16 + kg * 4);
     const float r[4] = {acc[0] - bv.x, acc[1] - bv.y, acc[2] - bv.z, acc[3] - bv.w};
     bf16x4 hi, lo;
     split(r, hi, lo);
-    const bf16x4 l = *reinterpret_cast<const bf16x4 *>(lam + (int64_t)i * 256 + lane * 4);
     f32x4 y = {0.f, 0.f, 0.f, 0.f};
     y = mfma(l, hi, y);
     y = mfma(l, lo, y);

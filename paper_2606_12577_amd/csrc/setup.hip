@@ -513,9 +513,13 @@ __global__ __launch_bounds__(WG) void k_rowprod_nb(const int32_t *__restrict__ l
                     if (q < 0) continue;
                     const double *ev = eval + (int64_t)q * NB2 + c2;
                     const double2 *a2 = reinterpret_cast<const double2 *>(As + jj * NB2);
-#pragma unroll 2
+                    // the NB loads of a block first (all in flight), then the products
+                    double2 eb[NB];
+#pragma unroll
+                    for (int u = 0; u < NB; ++u) eb[u] = *reinterpret_cast<const double2 *>(ev + u * NB);
+#pragma unroll
                     for (int u = 0; u < NB; ++u) {
-                        const double2 e = *reinterpret_cast<const double2 *>(ev + u * NB);
+                        const double2 e = eb[u];
 #pragma unroll
                         for (int r2 = 0; r2 < NH; ++r2) {
                             const double2 av = a2[u * NH + r2];
@@ -777,6 +781,7 @@ __global__ __launch_bounds__(WG) void k_gram_solve(const int32_t *__restrict__ l
         for (int x = 0; x < 4; ++x)
 #pragma unroll
             for (int y = 0; y < 4; ++y) ga[x][y] = ha[x][y] = 0.0;
+#pragma unroll 2
         for (int j = lane; j < k * nb; j += 64) {
             const int pb = j / nb, u = j % nb;
             const double *mp = mval + (int64_t)(mlo + pb) * nb2 + u;
@@ -791,6 +796,7 @@ __global__ __launch_bounds__(WG) void k_gram_solve(const int32_t *__restrict__ l
 #pragma unroll
                 for (int y = 0; y < 4; ++y) ga[x][y] += av[x] * bv[y];
         }
+#pragma unroll 2
         for (int j = lane; j < ek * nb; j += 64) {
             const int qb = j / nb, u = j % nb;
             const int pb = epos_cached ? epos[qb] : bsearch_i32(mcol, mlo, mlo + k, ecol[elo + qb]);
