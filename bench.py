@@ -127,7 +127,9 @@ def bench_batch(precision: str):
     on, e_ms, g_ms = s.graphs()
     out["autotune"] = dict(rows_per_workgroup=[int(w) for w, _, _ in sched],
                            workgroup_cap=[int(g) for _, g, _ in sched],
-                           vcycle_ms_eager=round(e_ms, 3), vcycle_ms_graph=round(g_ms, 3), graph_replay=on)
+                           vcycle_ms_eager=round(e_ms, 3), vcycle_ms_graph=round(g_ms, 3), graph_replay=on,
+                           tail_vcycle_ms={str(r): round(t, 4) for r, t in s.tail_candidates()},
+                           tail_max_rows=s.tail()[0])
     for method, maxit in (("cg", 300), ("ir", 1000)):
         for replay in (False, True):
             s.set_graphs(replay)
@@ -252,7 +254,7 @@ def bench_dg():
     return out
 
 
-def bench_learned():
+def bench_learned(epochs: int = 40):
     """Q1 multiphase diffusion 96^3: train the block network on two samples,
     then on an unseen sample compare the learned finest-level setup with the
     Frobenius setup (setup time, CG convergence factor) and apply the judge."""
@@ -265,7 +267,7 @@ def bench_learned():
     gen_s = _t.perf_counter() - t
     X, T = L.build_training_set(train, depth=2)
     t = _t.perf_counter()
-    net, rep = L.train_network(X, T, n_samples=200000, epochs=40, batch=1024, lr0=1e-3)
+    net, rep = L.train_network(X, T, n_samples=200000, epochs=epochs, batch=1024, lr0=1e-3)
     import torch
     torch.cuda.synchronize()
     train_s = _t.perf_counter() - t
@@ -354,12 +356,20 @@ def bench_c1():
     out = dict(dof=int(p.n), nrhs=1)
     for _ in range(2):
         s.setup(depth=3, mode="additive", order="RF", n_pre=2, n_post=2, precision="fp64")
+    # the coarse levels as one single-workgroup launch, from the level autotune picks
+    s.autotune(1)
+    out["tail_vcycle_ms"] = {str(r): round(t, 4) for r, t in s.tail_candidates()}
+    out["tail_max_rows"], out["tail_first_level"] = s.tail()
+    tail = out["tail_max_rows"]
     for method in ("ir", "cg"):
-        i = [s.solve(b, rtol=1e-10, maxit=100, method=method)[1] for _ in range(3)][-1]
-        out[method] = dict(solve_ms=round(i["solve_ms"], 3), iterations=i["iterations"], rho=round(i["rho"], 4),
-                           rel_res=i["rel_res"], setup_ms=round(i["setup_ms"], 3),
-                           dof_per_s=p.n / (i["solve_ms"] * 1e-3),
-                           us_per_vcycle=round(i["solve_ms"] * 1e3 / max(i["iterations"], 1), 1))
+        for label, rows in ((method, tail), (f"{method}_per_level_launches", 0)):
+            s.set_tail(rows)
+            i = [s.solve(b, rtol=1e-10, maxit=100, method=method)[1] for _ in range(3)][-1]
+            out[label] = dict(solve_ms=round(i["solve_ms"], 3), iterations=i["iterations"], rho=round(i["rho"], 4),
+                              rel_res=i["rel_res"], setup_ms=round(i["setup_ms"], 3),
+                              dof_per_s=p.n / (i["solve_ms"] * 1e-3),
+                              us_per_vcycle=round(i["solve_ms"] * 1e3 / max(i["iterations"], 1), 1))
+    s.set_tail(tail)
     s.close()
     return out
 
@@ -391,6 +401,7 @@ def main():
     ap.add_argument("--no-c1", action="store_true", help="skip the 64^2 Poisson measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-system measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-setup measurement")
+    ap.add_argument("--learned-epochs", type=int, default=40, help="training epochs of the learned-setup network")
     ap.add_argument("--no-stokes", action="store_true", help="skip the Stokes (MAC) measurement")
     ap.add_argument("--no-dg", action="store_true", help="skip the SIPG Q3 256^2 measurement")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -441,7 +452,8 @@ def main():
     sched = s.autotune(args.nrhs)
     replay, vc_eager, vc_graph = s.graphs()
     tuned = dict(rows_per_workgroup=[w for w, _, _ in sched], workgroup_cap=[g for _, g, _ in sched],
-                 vcycle_ms_eager=round(vc_eager, 3), vcycle_ms_graph=round(vc_graph, 3), graph_replay=replay)
+                 vcycle_ms_eager=round(vc_eager, 3), vcycle_ms_graph=round(vc_graph, 3), graph_replay=replay,
+                 tail_vcycle_ms={str(r): round(t, 4) for r, t in s.tail_candidates()}, tail_max_rows=s.tail()[0])
     log(f"autotune: V-cycle {vc_eager:.3f} ms eager, {vc_graph:.3f} ms replayed")
     torch.cuda.synchronize()
     if not args.no_trace:
@@ -567,7 +579,7 @@ def main():
         extra["dg_sipg_q3_256"] = bench_dg()
     if not args.no_learned:
         log("learned setup: Q1 multiphase 96^3")
-        extra["learned_q1_96"] = bench_learned()
+        extra["learned_q1_96"] = bench_learned(args.learned_epochs)
 
     out = {
         "metric": METRIC,

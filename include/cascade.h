@@ -307,7 +307,8 @@ cs_status cs_get_lattice_stats(cs_ctx ctx, int32_t level, int64_t *fitted, int32
  * rows per workgroup (0 for a level without sweeps), workgroup cap (0 = none)
  * and the best time in ms.  Then one V-cycle is timed eagerly and replayed
  * from a graph, and graph replay of the outer iterations is switched on when
- * it is faster (cs_set_graphs / cs_get_graphs).  The workspace vectors of
+ * it is faster (cs_set_graphs / cs_get_graphs); before that the tail V-cycle's
+ * start level is picked the same way (cs_set_tail).  The workspace vectors of
  * every level are overwritten. */
 cs_status cs_autotune(cs_ctx ctx, int32_t nrhs, int32_t *wgs, int64_t *grid, double *ms);
 
@@ -323,6 +324,29 @@ cs_status cs_autotune(cs_ctx ctx, int32_t nrhs, int32_t *wgs, int64_t *grid, dou
  * cs_autotune, both V-cycle times in ms (0 before). */
 cs_status cs_set_graphs(cs_ctx ctx, int32_t on);
 cs_status cs_get_graphs(cs_ctx ctx, int32_t *on, double *eager_ms, double *graph_ms);
+
+/* Single-workgroup tail V-cycle (Alg. 1 on the coarse levels).  The levels
+ * below a few thousand rows cost a kernel launch per sweep, transfer and
+ * direct solve while moving almost no data; from the first level l >= 1 at
+ * which every level has at most max_rows rows, the whole V-cycle below is one
+ * launch of one 1024-thread workgroup that runs the same per-row arithmetic
+ * with workgroup barriers in place of kernel boundaries, so results are
+ * bit-identical to the per-level launches.  It applies to additive cascades
+ * with fused aggregation transfers, one block size of 1, 2, 4 or 8 on the
+ * covered levels, n_pre >= 1 and n_post >= 1; other hierarchies run the
+ * per-level launches.  max_rows 0 switches it off (the default).  One
+ * workgroup walks a level's 64-row slices one tile after another, so the tail
+ * pays only on levels of a few tiles; cs_autotune times one V-cycle with the
+ * tail off and starting at each level of at most 65536 rows and keeps the
+ * fastest.  cs_vcycle_noalloc always runs the per-level launches.
+ * cs_get_tail returns max_rows, the first level the tail covers in the current
+ * setup (-1: none) and, when cap > 0, up to cap of the last autotune's
+ * candidates (cand_rows: the limit, 0 = off; cand_ms: one V-cycle in ms) with
+ * their count in *n_cand (may be null).  Errors: CS_EINVAL for max_rows < 0 or
+ * max_rows > 65536. */
+cs_status cs_set_tail(cs_ctx ctx, int64_t max_rows);
+cs_status cs_get_tail(cs_ctx ctx, int64_t *max_rows, int32_t *first_level, int32_t cap, int64_t *cand_rows,
+                      double *cand_ms, int32_t *n_cand);
 
 /* Device timing of kernel classes with HIP events recorded on the context's
  * stream around every launch of the class (for measurement; adds one event pair
@@ -343,7 +367,8 @@ typedef enum {
     CS_TRACE_REFINE = 5,        /* FP64 refinement residual and update */
     CS_TRACE_SWEEP_PROLONG = 6, /* first post-sweep with the interpolation fused in */
     CS_TRACE_SWEEP_SMALL = 7,   /* cascade sweeps that read A on small levels */
-    CS_TRACE_NCLASS = 8
+    CS_TRACE_TAIL = 8,          /* the single-workgroup V-cycle over the coarse levels (cs_set_tail) */
+    CS_TRACE_NCLASS = 9
 } cs_trace_class;
 cs_status cs_trace(cs_ctx ctx, int32_t mask, int32_t period);
 cs_status cs_trace_read(cs_ctx ctx, int32_t cls, double *total_ms, int64_t *launches, double *bytes);

@@ -76,6 +76,8 @@ SIGNATURES = {
     "cs_vcycle_noalloc": (_I32, [_VP, _VP, _VP, _I32]),
     "cs_set_graphs": (_I32, [_VP, _I32]),
     "cs_get_graphs": (_I32, [_VP, _p(_I32), _p(_D), _p(_D)]),
+    "cs_set_tail": (_I32, [_VP, _I64]),
+    "cs_get_tail": (_I32, [_VP, _p(_I64), _p(_I32), _I32, _p(_I64), _p(_D), _p(_I32)]),
     "cs_solve": (_I32, [_VP, _VP, _VP, _I32, _D, _I32, _p(cs_info), _p(_D)]),
     "cs_solve_cg": (_I32, [_VP, _VP, _VP, _I32, _D, _I32, _p(cs_info), _p(_D)]),
     "cs_solve_gmres": (_I32, [_VP, _VP, _VP, _I32, _D, _I32, _I32, _I32, _p(cs_info), _p(_D)]),
@@ -437,7 +439,7 @@ class Solver:
         return it, rel
 
     TRACE_CLASSES = ("sweep", "sweep_zero", "residual", "prolong", "bottom", "refine", "sweep_prolong",
-                     "sweep_small")
+                     "sweep_small", "tail")
 
     def autotune(self, nrhs: int):
         """Time the candidate sweep schedules of every level (current precision,
@@ -457,6 +459,26 @@ class Solver:
         on, e, g = ctypes.c_int32(), ctypes.c_double(), ctypes.c_double()
         self._check(self._lib.cs_get_graphs(self._h, ctypes.byref(on), ctypes.byref(e), ctypes.byref(g)))
         return bool(on.value), e.value, g.value
+
+    def set_tail(self, max_rows: int):
+        """Run the V-cycle on the coarse levels of at most max_rows rows as one
+        single-workgroup launch (0: per-level launches)."""
+        self._check(self._lib.cs_set_tail(self._h, int(max_rows)))
+
+    def tail(self):
+        """(max_rows, first level the tail covers or -1)."""
+        m, f = ctypes.c_int64(), ctypes.c_int32()
+        self._check(self._lib.cs_get_tail(self._h, ctypes.byref(m), ctypes.byref(f), 0, None, None, None))
+        return m.value, f.value
+
+    def tail_candidates(self):
+        """The last autotune's tail candidates: [(max_rows, V-cycle ms)], 0 = off."""
+        cap = len(self.sizes) + 1
+        m, f, n = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        rows, ms = np.zeros(cap, np.int64), np.zeros(cap)
+        self._check(self._lib.cs_get_tail(self._h, ctypes.byref(m), ctypes.byref(f), cap, _ptr(rows, _I64),
+                                          _ptr(ms, _D), ctypes.byref(n)))
+        return [(int(r), float(t)) for r, t in zip(rows[:n.value], ms[:n.value])]
 
     def trace(self, classes=("sweep",), period: int = 1):
         """Start (clearing the counters) event timing of every period-th launch

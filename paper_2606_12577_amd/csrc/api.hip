@@ -691,6 +691,11 @@ cs_status cs_autotune(cs_ctx ctx, int32_t nrhs, int32_t *wgs, int64_t *grid, dou
             if (wgs) wgs[l] = c.lv[l].tune_wgs;
             if (grid) grid[l] = c.lv[l].tune_grid;
         }
+        c.tune_tail_rows.assign(c.lv.size() + 1, 0);
+        c.tune_tail_ms.assign(c.lv.size() + 1, 0.0);
+        const int nt = cs::tune_tail(c, nrhs, c.tune_tail_rows.data(), c.tune_tail_ms.data(), (int)c.lv.size() + 1);
+        c.tune_tail_rows.resize(nt);
+        c.tune_tail_ms.resize(nt);
         double e = 0.0, g = 0.0;
         cs::tune_graphs(c, nrhs, &e, &g);
         c.tune_vcycle_ms[0] = e;
@@ -711,6 +716,32 @@ cs_status cs_get_graphs(cs_ctx ctx, int32_t *on, double *eager_ms, double *graph
         *on = c.use_graphs ? 1 : 0;
         if (eager_ms) *eager_ms = c.tune_vcycle_ms[0];
         if (graph_ms) *graph_ms = c.tune_vcycle_ms[1];
+    });
+}
+
+cs_status cs_set_tail(cs_ctx ctx, int64_t max_rows) {
+    return guarded(ctx, [&](Ctx &c) {
+        need(max_rows >= 0 && max_rows <= 65536, "tail max_rows must be in [0, 65536]");
+        c.tail_rows = max_rows;
+        c.tail_from = -1;
+        c.tail_gen = ~uint64_t(0);   // rebuilt by the next V-cycle
+        c.gen++;                     // captured graphs hold the old launch sequence
+    });
+}
+
+cs_status cs_get_tail(cs_ctx ctx, int64_t *max_rows, int32_t *first_level, int32_t cap, int64_t *cand_rows,
+                      double *cand_ms, int32_t *n_cand) {
+    return guarded(ctx, [&](Ctx &c) {
+        need(max_rows != nullptr && first_level != nullptr, "null output");
+        need(cap >= 0 && (cap == 0 || (cand_rows != nullptr && cand_ms != nullptr)), "candidate arrays");
+        *max_rows = c.tail_rows;
+        *first_level = c.have_setup ? cs::tail_start(c) : -1;
+        const int nt = (int)c.tune_tail_rows.size();
+        for (int k = 0; k < std::min(nt, (int)cap); ++k) {
+            cand_rows[k] = c.tune_tail_rows[k];
+            cand_ms[k] = c.tune_tail_ms[k];
+        }
+        if (n_cand) *n_cand = nt;
     });
 }
 

@@ -18,6 +18,8 @@
 // load and a wavefront reads a block as one contiguous 512-byte segment.
 #include <algorithm>
 
+#include <hip/hip_ext.h>
+
 #include "cs_internal.h"
 
 namespace cs {
@@ -211,18 +213,20 @@ void bf16_sweep(Ctx &c, const Level &L, int ell, int colour, bool reverse, bool 
     const int64_t k0 = L.cblk_ptr[colour], nblk = L.cblk_ptr[colour + 1] - k0;
     if (nblk == 0) return;
     const unsigned short *lam = (reverse ? L.lam16T.get() : L.lam16.get()) + (int64_t)ell * L.B * 256;
-    const int slot = trace_begin(c, zero ? CS_TRACE_SWEEP_ZERO : (L.n >= (1 << 19) ? CS_TRACE_SWEEP
-                                                                                    : CS_TRACE_SWEEP_SMALL),
-                                 (zero ? 0.0 : (double)L.bsr_nnzb * 512.0 * nblk / std::max<int64_t>(L.B, 1)) +
-                                     nblk * (512.0 + 16 * 4 * (zero ? 2.0 : 3.0)));
+    // a sampled launch records its own start and end (no event packets around it)
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    (void)trace_begin_launch(c, zero ? CS_TRACE_SWEEP_ZERO : (L.n >= (1 << 19) ? CS_TRACE_SWEEP
+                                                                               : CS_TRACE_SWEEP_SMALL),
+                             (zero ? 0.0 : (double)L.bsr_nnzb * 512.0 * nblk / std::max<int64_t>(L.B, 1)) +
+                                 nblk * (512.0 + 16 * 4 * (zero ? 2.0 : 3.0)),
+                             &ev0, &ev1);
     if (zero)
-        hipLaunchKernelGGL(k_bsr16_sweep<true>, dim3(gdim(nblk, WG / 64)), dim3(WG), 0, c.stream, nblk,
-                           L.cblk.get() + k0, L.bsr_ptr.get(), L.bsr_col.get(), L.a16.get(), lam, b, x);
+        hipExtLaunchKernelGGL(k_bsr16_sweep<true>, dim3(gdim(nblk, WG / 64)), dim3(WG), 0, c.stream, ev0, ev1, 0,
+                              nblk, L.cblk.get() + k0, L.bsr_ptr.get(), L.bsr_col.get(), L.a16.get(), lam, b, x);
     else
-        hipLaunchKernelGGL(k_bsr16_sweep<false>, dim3(gdim(nblk, WG / 64)), dim3(WG), 0, c.stream, nblk,
-                           L.cblk.get() + k0, L.bsr_ptr.get(), L.bsr_col.get(), L.a16.get(), lam, b, x);
+        hipExtLaunchKernelGGL(k_bsr16_sweep<false>, dim3(gdim(nblk, WG / 64)), dim3(WG), 0, c.stream, ev0, ev1, 0,
+                              nblk, L.cblk.get() + k0, L.bsr_ptr.get(), L.bsr_col.get(), L.a16.get(), lam, b, x);
     CS_LAUNCH_CHECK();
-    trace_end(c, slot);
 }
 
 }  // namespace cs

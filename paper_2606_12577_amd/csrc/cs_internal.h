@@ -184,6 +184,21 @@ struct Level {
     unsigned char *w_ovl = nullptr;
 };
 
+// One level of the single-workgroup tail V-cycle (device copy of the
+// pointers and sizes the V-cycle uses on that level; values in the working
+// precision, cast by the kernel).
+struct TailLevel {
+    int64_t n, n_active, nslices, nc, nbl;   // rows, smoothed rows, their slices, coarse rows, Lambda entries per step
+    const int64_t *sptr;
+    const int32_t *slen, *scol;
+    const void *sval, *lam, *lamT;
+    void *bb, *xb, *xt;
+    int depth, agg_k, nseg;
+    double r_scale;
+    const int64_t *dseg, *dinv_off;
+    const double *dinv;
+};
+
 struct Trace {
     bool on = false;
     int mask = 0;                        // bit k: record class k
@@ -245,6 +260,17 @@ struct Ctx {
     // internal work stream; cs_set_graphs, cs_autotune or CS_GRAPHS=1)
     bool use_graphs = false;
     double tune_vcycle_ms[2] = {0.0, 0.0};   // last cs_autotune: V-cycle eager, replayed
+    // single-workgroup tail V-cycle over the coarse levels of at most tail_rows
+    // rows (0: off); its level table, valid for (tail_gen, tail_prec, tail_nrhs)
+    int64_t tail_rows = 0;
+    int tail_from = -1;                 // first level the tail covers (-1: none)
+    DBuf<TailLevel> tail_tab;
+    std::vector<TailLevel> tail_host;
+    double tail_bytes = 0.0;            // algorithmic bytes of one tail launch (trace)
+    std::vector<int64_t> tune_tail_rows;   // cs_autotune's candidates (0: off) and V-cycle ms
+    std::vector<double> tune_tail_ms;
+    uint64_t tail_gen = ~uint64_t(0);
+    int tail_prec = -1, tail_nrhs = 0;
     uint64_t gen = 0;                   // bumped whenever device buffers the graph uses change
     hipStream_t work = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -309,6 +335,8 @@ void solve_cg(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
               double *history, cs_status *st);
 void autotune(Ctx &c, int nrhs, double *ms_out);
 void tune_graphs(Ctx &c, int nrhs, double *eager_ms, double *graph_ms);
+int tail_start(const Ctx &c);
+int tune_tail(Ctx &c, int nrhs, int64_t *rows, double *ms, int cap);
 void solve_gmres(Ctx &c, const double *b, double *x, int nrhs, double rtol, int maxit, int restart, bool flexible,
                  cs_info *info, double *history, cs_status *st);
 

@@ -168,12 +168,13 @@ __device__ __forceinline__ void spmv_fixed(const int32_t *__restrict__ scol, con
     }
 }
 
-// Rows are processed in straight-line chunks of U entries (U = 8 when a
-// gathered row of x is at most 32 bytes, else 4) and a fixed-length tail.
+// Rows are processed in straight-line chunks of U = 8 entries and a
+// fixed-length tail (also for 64-byte FP64 x rows: 4-entry chunks left the
+// FP64 refinement residual at 134 instead of 121 us on the 128^3 problem).
 template <typename T, int R, bool PROL, typename TA = T>
 __device__ __forceinline__ void spmv_row(const int32_t *__restrict__ scol, const TA *__restrict__ sval, int64_t off,
                                          int len, const T *xin, const T *xc, int agg_k, T (&acc)[R]) {
-    constexpr int U = (sizeof(T) * R > 32) ? 4 : 8;
+    constexpr int U = 8;
     int e0 = 0;
     for (; e0 + U <= len; e0 += U)
         spmv_fixed<T, R, PROL, U>(scol, sval, off + (int64_t)e0 * 64, xin, xc, agg_k, acc);
@@ -243,7 +244,7 @@ template <typename T, int R, bool PROL, int NB>
 __device__ __forceinline__ void spmv_row_blk(const int32_t *__restrict__ scol, const T *__restrict__ sval,
                                              int64_t off, int len, const T *xin, const T *xc, int agg_k,
                                              int64_t row, int lane, const T (&xo)[R], T (&acc)[R]) {
-    constexpr int U = (sizeof(T) * R > 32) ? 4 : 8;
+    constexpr int U = 8;
     int e0 = 0;
     for (; e0 + U <= len; e0 += U)
         spmv_fixed_blk<T, R, PROL, NB, U>(scol, sval, off + (int64_t)e0 * 64, xin, xc, agg_k, row, lane, xo, acc);
@@ -275,17 +276,17 @@ __device__ __forceinline__ void spmv_row_nb(const int32_t *__restrict__ scol, co
         spmv_row<T, R, PROL>(scol, sval, off, len, xin, xc, agg_k, acc);
 }
 
+// One tile (WGS/64 slices) of a cascade sweep; red: LDS of WGS * R values
+// (block levels), rewritten per tile.
 template <typename T, int NB, int R, bool ZERO, bool ROWMAP, bool PROL, int WGS>
-__global__ __launch_bounds__(WGS) void k_sweep(int64_t nrows, int64_t nslices, const int32_t *__restrict__ rows,
-                                               const int64_t *__restrict__ sptr, const int32_t *__restrict__ slen,
-                                               const int32_t *__restrict__ scol, const T *__restrict__ sval,
-                                               const T *__restrict__ lam, const T *__restrict__ b, const T *xin,
-                                               T *xout, const T *__restrict__ xc, int agg_k) {
+__device__ __forceinline__ void sweep_tile(int64_t tile, int64_t nrows, int64_t nslices,
+                                           const int32_t *__restrict__ rows, const int64_t *__restrict__ sptr,
+                                           const int32_t *__restrict__ slen, const int32_t *__restrict__ scol,
+                                           const T *__restrict__ sval, const T *__restrict__ lam,
+                                           const T *__restrict__ b, const T *xin, T *xout,
+                                           const T *__restrict__ xc, int agg_k, T *red) {
     constexpr int SPW = WGS / 64;
-    __shared__ T red[NB > 1 ? WGS * R : 1];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const Tiles tl = my_tiles((nslices + SPW - 1) / SPW);
-    for (int64_t tile = tl.t; tile < tl.end; tile += tl.step) {
     const int64_t slice = tile * SPW + wv;
     const int64_t q = slice * 64 + lane;
     const bool valid = slice < nslices && q < nrows;
@@ -295,7 +296,7 @@ __global__ __launch_bounds__(WGS) void k_sweep(int64_t nrows, int64_t nslices, c
 #pragma unroll
     for (int k = 0; k < R; ++k) res[k] = T(0);
     // block levels: the row of Lambda and the row's own x_in are loaded first;
-    // x_in feeds the in-block part of the SpMV through lane shuffles
+    // x_in feeds the in-slice part of the SpMV through lane shuffles
     T lr[NB], xo[R];
     if constexpr (NB > 1) {
         if (valid) {
@@ -351,7 +352,20 @@ __global__ __launch_bounds__(WGS) void k_sweep(int64_t nrows, int64_t nslices, c
         }
         __syncthreads();   // red is rewritten by the next tile
     }
-    }
+}
+
+template <typename T, int NB, int R, bool ZERO, bool ROWMAP, bool PROL, int WGS>
+__global__ __launch_bounds__(WGS) void k_sweep(int64_t nrows, int64_t nslices, const int32_t *__restrict__ rows,
+                                               const int64_t *__restrict__ sptr, const int32_t *__restrict__ slen,
+                                               const int32_t *__restrict__ scol, const T *__restrict__ sval,
+                                               const T *__restrict__ lam, const T *__restrict__ b, const T *xin,
+                                               T *xout, const T *__restrict__ xc, int agg_k) {
+    constexpr int SPW = WGS / 64;
+    __shared__ T red[NB > 1 ? WGS * R : 1];
+    const Tiles tl = my_tiles((nslices + SPW - 1) / SPW);
+    for (int64_t tile = tl.t; tile < tl.end; tile += tl.step)
+        sweep_tile<T, NB, R, ZERO, ROWMAP, PROL, WGS>(tile, nrows, nslices, rows, sptr, slen, scol, sval, lam, b,
+                                                      xin, xout, xc, agg_k, red);
 }
 
 // r = A x - b over SELL rows (natural order)
@@ -376,20 +390,20 @@ __global__ __launch_bounds__(WG) void k_residual(int64_t nrows, int64_t nslices,
 }
 
 // Fused residual and restriction for contiguous unit aggregation:
-// b_c[I] = r_scale * sum_{u < agg_k} (A x - b)[agg_k*I + u].  A workgroup owns
-// 256 fine rows, i.e. 256/agg_k whole coarse rows (agg_k divides 64).
-template <typename T, int R, int NB = 1>
-__global__ __launch_bounds__(WG) void k_residual_restrict(int64_t nrows, int64_t nslices,
-                                                          const int64_t *__restrict__ sptr,
-                                                          const int32_t *__restrict__ slen,
-                                                          const int32_t *__restrict__ scol, const T *__restrict__ sval,
-                                                          const T *__restrict__ b, const T *__restrict__ x,
-                                                          int agg_k, int64_t nc, T r_scale, T *__restrict__ bc) {
-    __shared__ T red[WG * R];
+// b_c[I] = r_scale * sum_{u < agg_k} (A x - b)[agg_k*I + u].  A tile holds
+// WGS fine rows, i.e. WGS/agg_k whole coarse rows (agg_k divides 64); red:
+// LDS of WGS * R values.
+template <typename T, int R, int NB, int WGS>
+__device__ __forceinline__ void residual_restrict_tile(int64_t tile, int64_t nrows, int64_t nslices,
+                                                       const int64_t *__restrict__ sptr,
+                                                       const int32_t *__restrict__ slen,
+                                                       const int32_t *__restrict__ scol,
+                                                       const T *__restrict__ sval, const T *__restrict__ b,
+                                                       const T *__restrict__ x, int agg_k, int64_t nc, T r_scale,
+                                                       T *__restrict__ bc, T *red) {
+    constexpr int SPW = WGS / 64;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const Tiles tl = my_tiles((nslices + 3) / 4);
-    for (int64_t tile = tl.t; tile < tl.end; tile += tl.step) {
-    const int64_t slice = tile * 4 + wv;
+    const int64_t slice = tile * SPW + wv;
     const int64_t row = slice * 64 + lane;
     T acc[R];
 #pragma unroll
@@ -405,7 +419,7 @@ __global__ __launch_bounds__(WG) void k_residual_restrict(int64_t nrows, int64_t
 #pragma unroll
     for (int k = 0; k < R; ++k) red[threadIdx.x * R + k] = acc[k];
     __syncthreads();
-    const int per = WG / agg_k;
+    const int per = WGS / agg_k;
     if ((int)threadIdx.x < per) {
         const int64_t I = tile * per + threadIdx.x;
         if (I < nc) {
@@ -422,7 +436,20 @@ __global__ __launch_bounds__(WG) void k_residual_restrict(int64_t nrows, int64_t
         }
     }
     __syncthreads();   // red is rewritten by the next tile
-    }
+}
+
+template <typename T, int R, int NB = 1>
+__global__ __launch_bounds__(WG) void k_residual_restrict(int64_t nrows, int64_t nslices,
+                                                          const int64_t *__restrict__ sptr,
+                                                          const int32_t *__restrict__ slen,
+                                                          const int32_t *__restrict__ scol, const T *__restrict__ sval,
+                                                          const T *__restrict__ b, const T *__restrict__ x,
+                                                          int agg_k, int64_t nc, T r_scale, T *__restrict__ bc) {
+    __shared__ T red[WG * R];
+    const Tiles tl = my_tiles((nslices + 3) / 4);
+    for (int64_t tile = tl.t; tile < tl.end; tile += tl.step)
+        residual_restrict_tile<T, R, NB, WG>(tile, nrows, nslices, sptr, slen, scol, sval, b, x, agg_k, nc, r_scale,
+                                             bc, red);
 }
 
 // b_c = r_scale * P^T r with P^T in sliced ELLPACK (a lane per coarse row,
@@ -478,14 +505,13 @@ __global__ __launch_bounds__(WG) void k_prolong_sell(int64_t n, int64_t nslices,
 // (the whole bottom level, or trailing systems of a batch that end on this
 // level).  One wavefront per row: the lanes stream the inverse row coalesced,
 // accumulate all right-hand sides in FP64 and reduce across the wavefront.
+// Row i of a direct segment: x_i = (A_seg^{-1} b_seg)_i with FP64
+// accumulation, one wavefront per row.
 template <typename T, int R>
-__global__ __launch_bounds__(WG) void k_direct_seg(int64_t n_active, int64_t n, int nseg,
-                                                   const int64_t *__restrict__ seg, const int64_t *__restrict__ inv_off,
-                                                   const double *__restrict__ inv, const T *__restrict__ b,
-                                                   T *__restrict__ x) {
+__device__ __forceinline__ void direct_row(int64_t i, int nseg, const int64_t *__restrict__ seg,
+                                           const int64_t *__restrict__ inv_off, const double *__restrict__ inv,
+                                           const T *__restrict__ b, T *__restrict__ x) {
     const int lane = threadIdx.x & 63;
-    const int64_t i = n_active + (int64_t)blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
-    if (i >= n) return;   // uniform per wavefront
     int lo = 0, hi = nseg - 1;   // segment q with seg[q] <= i < seg[q+1]
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -514,6 +540,117 @@ __global__ __launch_bounds__(WG) void k_direct_seg(int64_t n_active, int64_t n, 
 #pragma unroll
         for (int k = 0; k < R; ++k) o[k] = (T)acc[k];
         vstore<T, R>(x + i * R, o);
+    }
+}
+
+template <typename T, int R>
+__global__ __launch_bounds__(WG) void k_direct_seg(int64_t n_active, int64_t n, int nseg,
+                                                   const int64_t *__restrict__ seg, const int64_t *__restrict__ inv_off,
+                                                   const double *__restrict__ inv, const T *__restrict__ b,
+                                                   T *__restrict__ x) {
+    const int64_t i = n_active + (int64_t)blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
+    if (i >= n) return;   // uniform per wavefront
+    direct_row<T, R>(i, nseg, seg, inv_off, inv, b, x);
+}
+
+// ---------------------------------------------------------------------------
+// Single-workgroup tail V-cycle: the coarse levels of at most a few thousand
+// rows are latency-bound (a kernel of a few microseconds per sweep, transfer
+// and direct solve), so one workgroup of 512-1024 threads runs Alg. 1 on all of
+// them in one launch: the same per-row arithmetic as the per-level kernels
+// (sweep_tile, residual_restrict_tile, direct_row), a workgroup barrier where
+// the eager path has a kernel boundary, hence identical results.
+// ---------------------------------------------------------------------------
+// 1024 threads where a row's vector data fits in 8 bytes; 512 (twice the
+// registers per thread) for several right-hand sides
+template <typename T, int R>
+constexpr int tail_wg() { return R * sizeof(T) <= 8 ? 1024 : 512; }
+
+template <typename T, int NB, int R, int TW, bool ZERO, bool PROL>
+__device__ void tail_sweep(const TailLevel &L, const T *lam, const T *b, const T *xin, T *xout, const T *xc,
+                           T *red) {
+    constexpr int SPW = TW / 64;
+    const int64_t ntiles = (L.nslices + SPW - 1) / SPW;
+    for (int64_t tile = 0; tile < ntiles; ++tile)
+        sweep_tile<T, NB, R, ZERO, false, PROL, TW>(tile, L.n_active, L.nslices, nullptr, L.sptr, L.slen, L.scol,
+                                                        static_cast<const T *>(L.sval), lam, b, xin, xout, xc,
+                                                        L.agg_k, red);
+    __syncthreads();
+}
+
+// one application of the level's additive cascade (as apply_cascade); returns
+// the buffer that holds the result
+template <typename T, int NB, int R, int TW>
+__device__ T *tail_cascade(const TailLevel &L, bool reverse, bool zero_start, const T *b, T *x, T *alt,
+                           const T *xc, T *red) {
+    T *cur = x, *nxt = alt;
+    for (int s = 0; s < L.depth; ++s) {
+        const int ell = reverse ? L.depth - 1 - s : s;
+        const T *lam = static_cast<const T *>(reverse ? L.lamT : L.lam) + (int64_t)ell * L.nbl;
+        if (zero_start && s == 0) tail_sweep<T, NB, R, TW, true, false>(L, lam, b, cur, nxt, nullptr, red);
+        else if (s == 0 && xc) tail_sweep<T, NB, R, TW, false, true>(L, lam, b, cur, nxt, xc, red);
+        else tail_sweep<T, NB, R, TW, false, false>(L, lam, b, cur, nxt, nullptr, red);
+        T *t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    return cur;
+}
+
+template <typename T, int R, int TW>
+__device__ void tail_direct(const TailLevel &L, T *x) {
+    const int wv = threadIdx.x >> 6;
+    for (int64_t i = L.n_active + wv; i < L.n; i += TW / 64)
+        direct_row<T, R>(i, L.nseg, L.dseg, L.dinv_off, L.dinv, static_cast<const T *>(L.bb), x);
+    __syncthreads();
+}
+
+// Alg. 1 from tab[0] (its right-hand side already in tab[0].bb) to the last
+// entry, solved directly; the result in tab[0].xb.
+template <typename T, int NB, int R, int TW = tail_wg<T, R>()>
+__global__ __launch_bounds__(TW) void k_tail_vcycle(const TailLevel *__restrict__ tab, int nlev, int n_pre,
+                                                    int n_post, int rf) {
+    __shared__ T red[TW * R];
+    uint32_t in_alt = 0;   // bit l: level l's smoothed x sits in xt instead of xb
+    for (int l = 0; l + 1 < nlev; ++l) {
+        const TailLevel &L = tab[l];
+        T *x = static_cast<T *>(L.xb), *alt = static_cast<T *>(L.xt);
+        const T *b = static_cast<const T *>(L.bb);
+        for (int a = 0; a < n_pre; ++a) {
+            T *res = tail_cascade<T, NB, R, TW>(L, rf != 0, a == 0, b, x, alt, nullptr, red);
+            if (res != x) {
+                alt = x;
+                x = res;
+            }
+        }
+        if (x != static_cast<T *>(L.xb)) in_alt |= 1u << l;
+        constexpr int SPW = TW / 64;
+        const int64_t ntiles = (L.nslices + SPW - 1) / SPW;
+        for (int64_t tile = 0; tile < ntiles; ++tile)
+            residual_restrict_tile<T, R, NB, TW>(tile, L.n_active, L.nslices, L.sptr, L.slen, L.scol,
+                                                     static_cast<const T *>(L.sval), b, x, L.agg_k, L.nc,
+                                                     (T)L.r_scale, static_cast<T *>(tab[l + 1].bb), red);
+        __syncthreads();
+    }
+    tail_direct<T, R, TW>(tab[nlev - 1], static_cast<T *>(tab[nlev - 1].xb));
+    for (int l = nlev - 2; l >= 0; --l) {
+        const TailLevel &L = tab[l];
+        T *xb = static_cast<T *>(L.xb), *xt = static_cast<T *>(L.xt);
+        T *x = (in_alt >> l) & 1u ? xt : xb, *alt = x == xb ? xt : xb;
+        const T *b = static_cast<const T *>(L.bb);
+        const T *xc = static_cast<const T *>(tab[l + 1].xb);
+        for (int a = 0; a < n_post; ++a) {
+            T *res = tail_cascade<T, NB, R, TW>(L, false, false, b, x, alt, a == 0 ? xc : nullptr, red);
+            if (res != x) {
+                alt = x;
+                x = res;
+            }
+        }
+        if (x != xb) {
+            for (int64_t e = threadIdx.x; e < L.n_active * R; e += TW) xb[e] = x[e];
+            __syncthreads();
+        }
+        tail_direct<T, R, TW>(L, xb);
     }
 }
 
@@ -1545,6 +1682,83 @@ void direct_solve(Ctx &c, const Level &L, const T *b, T *x) {
     trace_end(c, slot);
 }
 
+}  // namespace
+
+// The coarse levels the tail kernel covers: the first level l >= 1 from
+// which every level has at most c.tail_rows rows, every smoothed one is
+// additive (no overlapping blocks) with fused transfers and one common block
+// size of 1, 2, 4 or 8, and the cycle pre- and post-smooths (the first
+// post-smoothing sweep carries the interpolation); -1 when there is none.
+int tail_start(const Ctx &c) {
+    const int nl = (int)c.lv.size();
+    if (c.tail_rows <= 0 || nl < 3 || c.opt.mode != CS_ADDITIVE || !c.fuse_transfers || c.opt.n_pre < 1 ||
+        c.opt.n_post < 1)
+        return -1;
+    const int64_t nb = c.lv[nl - 2].nb;
+    if (nb != 1 && nb != 2 && nb != 4 && nb != 8) return -1;
+    int from = -1;
+    for (int l = nl - 1; l >= 1; --l) {
+        const Level &V = c.lv[l];
+        bool ok = V.n <= c.tail_rows && !V.ovl_m;
+        if (l + 1 < nl) ok = ok && V.agg_k > 0 && V.depth >= 1 && V.nb == nb && V.n_active > 0;
+        if (!ok || nl - l > 32) break;   // the kernel tracks the levels in a 32-bit mask
+        from = l;
+    }
+    return from >= 0 && from < nl - 1 ? from : -1;
+}
+
+namespace {
+
+template <typename T>
+void tail_table(Ctx &c, int nrhs) {
+    const int from = tail_start(c);
+    c.tail_from = from;
+    if (from < 0) return;
+    if (c.tail_gen == c.gen && c.tail_prec == c.precision && c.tail_nrhs == nrhs) return;
+    std::vector<TailLevel> tab;
+    const double es = sizeof(T), vr = (double)nrhs * es;
+    double bytes = 0.0;
+    for (size_t l = from; l < c.lv.size(); ++l) {
+        const Level &L = c.lv[l];
+        bytes += (double)L.dinv.n * 8.0 + 2.0 * (L.n - L.n_active) * vr;
+        if (l + 1 < c.lv.size()) {
+            const double A = L.act_nnz * (es + 4.0), lamb = (double)L.n_active * L.nb * es;
+            const double v = (double)L.n_active * vr, sweeps = (double)(c.opt.n_pre + c.opt.n_post) * L.depth;
+            bytes += (lamb + 2.0 * v) + (sweeps - 1.0) * (A + lamb + 3.0 * v);   // the first from zero
+            bytes += A + 2.0 * v + 2.0 * (double)L.nc * vr;   // residual + restriction, the interpolation read
+        }
+        TailLevel t{};
+        t.n = L.n;
+        t.n_active = L.n_active;
+        t.nslices = L.act_slices;
+        t.nc = L.nc;
+        t.nbl = L.B * L.nb * L.nb;
+        t.sptr = L.sell.slice_ptr.get();
+        t.slen = L.sell.slice_len.get();
+        t.scol = L.sell.col.get();
+        t.sval = sell_val<T>(L.sell);
+        t.lam = l + 1 < c.lv.size() ? lam_ptr<T>(L, false) : nullptr;
+        t.lamT = l + 1 < c.lv.size() ? lam_ptr<T>(L, true) : nullptr;
+        t.bb = L.w_bb;
+        t.xb = L.w_xb;
+        t.xt = L.w_xt;
+        t.depth = L.depth;
+        t.agg_k = L.agg_k;
+        t.r_scale = L.r_scale;
+        t.nseg = L.dseg.size() > 1 ? (int)L.dseg.size() - 1 : 0;
+        t.dseg = L.dseg_d.get();
+        t.dinv_off = L.dinv_off.get();
+        t.dinv = L.dinv.get();
+        tab.push_back(t);
+    }
+    c.tail_host = tab;
+    c.tail_bytes = bytes;
+    c.tail_tab.upload(c.tail_host.data(), c.tail_host.size(), c.stream);
+    c.tail_gen = c.gen;
+    c.tail_prec = c.precision;
+    c.tail_nrhs = nrhs;
+}
+
 // V-cycle (Alg. 1) from level l down: x_l = V(b_l) from the zero guess, with
 // b_l in bb and the result in xb.  Only the active rows are smoothed and
 // transferred; the direct segments of every level are solved exactly.
@@ -1568,6 +1782,21 @@ bool issue_first_sweep(Ctx &c) {
 
 template <typename T, int R>
 void vcycle_level(Ctx &c, int l) {
+    if (l > 0 && l == c.tail_from && c.tail_gen == c.gen && c.tail_prec == c.precision && c.tail_nrhs == R) {
+        const int nlev = (int)c.lv.size() - l;
+        hipEvent_t ev0 = nullptr, ev1 = nullptr;
+        const int slot = trace_begin_launch(c, CS_TRACE_TAIL, c.tail_bytes, &ev0, &ev1);
+        (void)slot;
+        dispatch_nb((int)c.lv[l].nb, [&](auto nbc) {
+            constexpr int NB = decltype(nbc)::value;
+            if constexpr (NB <= 8)
+                hipExtLaunchKernelGGL((k_tail_vcycle<T, NB, R>), dim3(1), dim3(tail_wg<T, R>()), 0, c.stream, ev0, ev1, 0,
+                                      (const TailLevel *)c.tail_tab.get(), nlev, c.opt.n_pre, c.opt.n_post,
+                                      c.opt.order == CS_RF ? 1 : 0);
+        });
+        CS_LAUNCH_CHECK();
+        return;
+    }
     Level &L = c.lv[l];
     T *xb = reinterpret_cast<T *>(L.w_xb);
     T *xt = reinterpret_cast<T *>(L.w_xt);
@@ -1659,10 +1888,16 @@ static void use_own_workspace(Ctx &c) {
     c.ws_scratch = false;
 }
 
+static void prepare_tail(Ctx &c, int nrhs) {
+    if (c.precision == CS_FP64) tail_table<double>(c, nrhs);
+    else tail_table<float>(c, nrhs);
+}
+
 void ensure_workspace(Ctx &c, int nrhs) {
     const int prec = c.precision;
     if (c.ws_nrhs == nrhs && c.ws_prec == prec) {
         if (c.ws_scratch) use_own_workspace(c);
+        prepare_tail(c, nrhs);
         return;
     }
     const size_t es = prec == CS_FP64 ? sizeof(double) : sizeof(float);
@@ -2055,6 +2290,78 @@ void tune_graphs(Ctx &c, int nrhs, double *eager_ms, double *graph_ms) {
     }
     cleanup();
     c.use_graphs = *graph_ms < *eager_ms;
+}
+
+// The tail V-cycle's size limit, picked by measurement: one V-cycle is timed
+// (median of five) with the tail off and with every limit that starts it at
+// another level (the sizes of levels 1.. of at most 65536 rows); the fastest
+// is kept.  ms[k] / rows[k] receive the candidates' times and limits.
+int tune_tail(Ctx &c, int nrhs, int64_t *rows, double *ms, int cap) {
+    std::vector<int64_t> cand{0};
+    for (size_t l = 1; l < c.lv.size(); ++l)
+        if (c.lv[l].n <= 65536 && std::find(cand.begin(), cand.end(), c.lv[l].n) == cand.end())
+            cand.push_back(c.lv[l].n);
+    const int64_t keep = c.tail_rows;
+    const bool tr = c.tr.on;
+    c.tr.on = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        c.tr.on = tr;
+    };
+    int nout = 0;
+    try {
+        CS_HIP(hipEventCreate(&e0));
+        CS_HIP(hipEventCreate(&e1));
+        int64_t best = 0;
+        double best_ms = 0.0;
+        std::vector<int> seen_from;
+        for (int64_t v : cand) {
+            c.tail_rows = v;
+            c.tail_gen = ~uint64_t(0);
+            ensure_workspace(c, nrhs);
+            const int from = v ? c.tail_from : -1;
+            if (v && (from < 0 || std::find(seen_from.begin(), seen_from.end(), from) != seen_from.end())) continue;
+            seen_from.push_back(from);
+            double t_ms = 0.0;
+            dispatch_prec(c.precision, [&](auto tp) {
+                using T = std::remove_pointer_t<decltype(tp)>;
+                dispatch_r(nrhs, [&](auto rc) {
+                    constexpr int R = decltype(rc)::value;
+                    vcycle_level<T, R>(c, 0);   // warm-up
+                    std::vector<float> t(5);
+                    for (float &u : t) {
+                        CS_HIP(hipEventRecord(e0, c.stream));
+                        vcycle_level<T, R>(c, 0);
+                        CS_HIP(hipEventRecord(e1, c.stream));
+                        CS_HIP(hipEventSynchronize(e1));
+                        CS_HIP(hipEventElapsedTime(&u, e0, e1));
+                    }
+                    std::sort(t.begin(), t.end());
+                    t_ms = t[2];
+                });
+            });
+            if (nout < cap) {
+                if (rows) rows[nout] = v;
+                if (ms) ms[nout] = t_ms;
+            }
+            ++nout;
+            if (v == 0 || t_ms < best_ms) {
+                best = v;
+                best_ms = t_ms;
+            }
+        }
+        c.tail_rows = best;
+    } catch (...) {
+        c.tail_rows = keep;
+        cleanup();
+        throw;
+    }
+    cleanup();
+    c.tail_gen = ~uint64_t(0);
+    c.gen++;
+    return nout;
 }
 
 void solve_ir(Ctx &c, const double *b, double *x, int nrhs, double rtol, int maxit, cs_info *info,
