@@ -240,11 +240,15 @@ def bench_dg():
     if tr["launches"]:
         avg_s = tr["ms"] / tr["launches"] * 1e-3
         per = tr["bytes"] / tr["launches"]
+        rp = _summary_values(DG_PROFILE_FILE, "bsr16")
+        rp_us = float(rp["avg_us"]) if rp.get("source") == bf16_source_digest() else None
         out["roofline_bsr16_sweep"] = dict(
             kernel="k_bsr16_sweep<false> (one colour of the finest level, BF16 blocks on MFMA)", bound="hbm",
+            timing="live: one HIP event pair around each run of consecutive colour sweeps of the finest level",
             launches=tr["launches"], avg_us=round(avg_s * 1e6, 2), algorithmic_bytes_per_launch=int(per),
             achieved=round(per / avg_s / 1e9, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-            frac=round(per / avg_s / 1e9 / HBM_PEAK_GBS, 4))
+            frac=round(per / avg_s / 1e9 / HBM_PEAK_GBS, 4), rocprof_avg_us=rp_us,
+            frac_rocprof=round(per / (rp_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4) if rp_us else None)
     bir, fir, pir = out["bf16_ridge"]["ir"], out["fp64_ridge"]["ir"], out["fp64_plain_fit"]["ir"]
     out["bf16_ir_vs_fp64_ir_same_fit"] = dict(speedup=round(fir["solve_ms"] / bir["solve_ms"], 3),
                                               rho_ratio=round(bir["rho"] / fir["rho"], 4))
@@ -303,6 +307,14 @@ def kernel_source_digest() -> str:
 
 
 PROFILE_FILE = os.path.join(ROOT, "profiles", "k_sweep_interface3d_128.md")
+DG_PROFILE_FILE = os.path.join(ROOT, "profiles", "dg_sipg_q3_256.md")
+
+
+def bf16_source_digest() -> str:
+    """Digest of the BF16 block-sweep source (kernel and launcher)."""
+    import hashlib
+    return hashlib.sha256(open(os.path.join(ROOT, "paper_2606_12577_amd", "csrc", "bf16.hip"), "rb").read()
+                          ).hexdigest()[:16]
 
 
 def _summary_values(path: str, tag: str) -> dict:
@@ -340,6 +352,65 @@ def rocprof_average_us(args):
     if not _default_workload(args) or vals.get("source") != kernel_source_digest():
         return None
     return float(vals["avg_us"])
+
+
+def _short_kernel(name: str) -> str:
+    """Kernel name without namespace and parameter list (template arguments kept)."""
+    for pre in ("void ", "cs::(anonymous namespace)::", "cs::"):
+        if name.startswith(pre):
+            name = name[len(pre):]
+    name = name.replace("cs::(anonymous namespace)::", "")
+    depth = 0
+    for i, ch in enumerate(name):
+        depth += ch == "<"
+        depth -= ch == ">"
+        if ch == "(" and depth == 0:
+            return name[:i]
+    return name
+
+
+def summarize_rocprof(path: str, top: int = 40) -> str:
+    """Markdown summary of a rocprofv3 CSV: a kernel trace (per kernel and grid:
+    calls, average / min / max duration, total, share) or a counter collection
+    (per kernel, grid and counter: dispatches, mean and sum of the counter, and
+    the mean dispatch duration).  Reads only the CSV."""
+    import csv
+    from collections import defaultdict
+    with open(path, newline="") as f:
+        rows = list(csv.DictReader(f))
+    if not rows:
+        return f"{path}: empty\n"
+    out = []
+    if "Counter_Name" in rows[0]:
+        acc = defaultdict(lambda: [0, 0.0, 0.0])
+        dur = defaultdict(list)
+        for r in rows:
+            key = (_short_kernel(r["Kernel_Name"]), int(r["Grid_Size"]))
+            a = acc[key + (r["Counter_Name"],)]
+            v = float(r["Counter_Value"])
+            a[0] += 1
+            a[1] += v
+            a[2] = max(a[2], v)
+            dur[key + (r["Counter_Name"],)].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+        out.append("| kernel | grid | counter | dispatches | mean per dispatch | max per dispatch | sum | mean us |")
+        out.append("|---|---|---|---|---|---|---|---|")
+        for (k, g, c), (n, tot, mx) in sorted(acc.items(), key=lambda kv: (kv[0][0], kv[0][1], kv[0][2])):
+            d = dur[(k, g, c)]
+            out.append(f"| `{k}` | {g} | {c} | {n} | {tot / n:.6g} | {mx:.6g} | {tot:.6g} | {sum(d) / len(d):.2f} |")
+    else:
+        acc = defaultdict(list)
+        for r in rows:
+            if r.get("Kind", "KERNEL_DISPATCH") != "KERNEL_DISPATCH":
+                continue
+            key = (_short_kernel(r["Kernel_Name"]), int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]))
+            acc[key].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+        total = sum(sum(v) for v in acc.values())
+        out.append("| kernel | grid (threads) | calls | avg us | min us | max us | total ms | % |")
+        out.append("|---|---|---|---|---|---|---|---|")
+        for (k, g), d in sorted(acc.items(), key=lambda kv: -sum(kv[1]))[:top]:
+            out.append(f"| `{k}` | {g} | {len(d)} | {sum(d) / len(d):.2f} | {min(d):.2f} | {max(d):.2f} | "
+                       f"{sum(d) * 1e-3:.2f} | {100 * sum(d) / total:.2f} |")
+    return "\n".join(out) + "\n"
 
 
 def bench_c1():
@@ -406,7 +477,14 @@ def main():
     ap.add_argument("--no-dg", action="store_true", help="skip the SIPG Q3 256^2 measurement")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
+    ap.add_argument("--summarize", nargs="+", metavar="CSV",
+                    help="print a markdown summary of rocprofv3 kernel-trace or counter CSVs and exit")
     args = ap.parse_args()
+    if args.summarize:
+        for path in args.summarize:
+            print(f"### {os.path.basename(os.path.dirname(path))}/{os.path.basename(path)}\n")
+            print(summarize_rocprof(path))
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -448,7 +526,10 @@ def main():
         info = step()
         log(f"warmup {w}: setup {info['setup_ms']:.1f} ms, solve {info['solve_ms']:.1f} ms, "
             f"{info['iterations']} it, rho {info['rho']:.4f}")
-    # launch schedules per level and eager vs graph replay, by measurement (kept across setups)
+    # launch schedules per level, the tail V-cycle and eager vs graph replay, by
+    # measurement on the setup's own operators (kept across setups)
+    if args.warmup == 0:
+        s.setup(**opts)
     sched = s.autotune(args.nrhs)
     replay, vc_eager, vc_graph = s.graphs()
     tuned = dict(rows_per_workgroup=[w for w, _, _ in sched], workgroup_cap=[g for _, g, _ in sched],
@@ -487,7 +568,8 @@ def main():
             frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(args),
             kernel=(f"k_sweep<{'float' if args.precision == 'fp32' else 'double'}, 8, {args.nrhs}, "
                     "false, false, false, 256> (cascade sweep reading A, large levels)"),
-            timing="live: HIP events around every sampled launch on the library's stream",
+            timing=("live: one HIP event pair around every sampled run of consecutive sweeps of the fine level "
+                    "on the library's stream; the average over the run's launches includes the gaps between them"),
             launches=sw["launches"], avg_us=round(avg_ms * 1e3, 2),
             algorithmic_bytes_per_launch=int(bytes_per_launch),
             rocprof_avg_us=rp_us,

@@ -857,10 +857,9 @@ cs_status cs_load_setup(cs_ctx ctx, const char *path) {
 // ---------------------------------------------------------------------------
 namespace cs {
 
-int trace_begin(Ctx &c, int cls, double bytes) {
-    Trace &t = c.tr;
-    if (!t.on || !((t.mask >> cls) & 1)) return -1;
-    if (t.seen[cls]++ % t.period != 0) return -1;
+// A free event pair for one recorded interval of class cls covering
+// `launches` launches and `bytes` algorithmic bytes.
+static int trace_slot(Trace &t, int cls, double bytes, int launches) {
     if (2 * t.used + 2 > t.ev.size()) {
         hipEvent_t a, b;
         CS_HIP(hipEventCreate(&a));
@@ -868,11 +867,25 @@ int trace_begin(Ctx &c, int cls, double bytes) {
         t.ev.push_back(a);
         t.ev.push_back(b);
         t.cls.push_back(0);
+        t.cls_n.push_back(0);
         t.cls_bytes.push_back(0.0);
     }
     const int slot = (int)t.used++;
     t.cls[slot] = cls;
+    t.cls_n[slot] = launches;
     t.cls_bytes[slot] = bytes;
+    return slot;
+}
+
+static bool trace_sampled(Trace &t, int cls) {
+    if (!t.on || !((t.mask >> cls) & 1) || cls == t.run_cls) return false;
+    return t.seen[cls]++ % t.period == 0;
+}
+
+int trace_begin(Ctx &c, int cls, double bytes) {
+    Trace &t = c.tr;
+    if (!trace_sampled(t, cls)) return -1;
+    const int slot = trace_slot(t, cls, bytes, 1);
     CS_HIP(hipEventRecord(t.ev[2 * slot], c.stream));
     return slot;
 }
@@ -880,23 +893,26 @@ int trace_begin(Ctx &c, int cls, double bytes) {
 int trace_begin_launch(Ctx &c, int cls, double bytes, hipEvent_t *start, hipEvent_t *stop) {
     *start = *stop = nullptr;
     Trace &t = c.tr;
-    if (!t.on || !((t.mask >> cls) & 1)) return -1;
-    if (t.seen[cls]++ % t.period != 0) return -1;
-    if (2 * t.used + 2 > t.ev.size()) {
-        hipEvent_t a, b;
-        CS_HIP(hipEventCreate(&a));
-        CS_HIP(hipEventCreate(&b));
-        t.ev.push_back(a);
-        t.ev.push_back(b);
-        t.cls.push_back(0);
-        t.cls_bytes.push_back(0.0);
-    }
-    const int slot = (int)t.used++;
-    t.cls[slot] = cls;
-    t.cls_bytes[slot] = bytes;
+    if (!trace_sampled(t, cls)) return -1;
+    const int slot = trace_slot(t, cls, bytes, 1);
     *start = t.ev[2 * slot];
     *stop = t.ev[2 * slot + 1];
     return slot;
+}
+
+int trace_begin_run(Ctx &c, int cls, double bytes, int launches) {
+    Trace &t = c.tr;
+    if (launches <= 0 || !trace_sampled(t, cls)) return -1;
+    t.run_cls = cls;   // the launches inside are not sampled one by one
+    const int slot = trace_slot(t, cls, bytes, launches);
+    CS_HIP(hipEventRecord(t.ev[2 * slot], c.stream));
+    return slot;
+}
+
+void trace_end_run(Ctx &c, int slot) {
+    if (slot == -1) return;
+    CS_HIP(hipEventRecord(c.tr.ev[2 * slot + 1], c.stream));
+    c.tr.run_cls = -1;
 }
 
 void trace_end(Ctx &c, int slot) {
@@ -920,7 +936,7 @@ void trace_flush(Ctx &c) {
         float ms = 0;
         CS_HIP(hipEventElapsedTime(&ms, t.ev[2 * k], t.ev[2 * k + 1]));
         t.ms[t.cls[k]] += ms;
-        t.count[t.cls[k]] += 1;
+        t.count[t.cls[k]] += t.cls_n[k];
         t.bytes[t.cls[k]] += t.cls_bytes[k];
     }
     t.used = 0;
@@ -930,7 +946,9 @@ void trace_release(Ctx &c) {
     for (hipEvent_t e : c.tr.ev) (void)hipEventDestroy(e);
     c.tr.ev.clear();
     c.tr.cls.clear();
+    c.tr.cls_n.clear();
     c.tr.cls_bytes.clear();
+    c.tr.run_cls = -1;
     c.tr.used = 0;
 }
 
@@ -944,6 +962,7 @@ cs_status cs_trace(cs_ctx ctx, int32_t mask, int32_t period) {
         cs::trace_flush(c);
         c.tr.mask = mask;
         c.tr.period = period;
+        c.tr.run_cls = -1;
         const int32_t enable = mask;
         if (enable) {
             for (int k = 0; k < CS_TRACE_NCLASS; ++k) {

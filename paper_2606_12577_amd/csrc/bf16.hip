@@ -209,6 +209,14 @@ bool use_bf16(const Ctx &c, const Level &L) {
     return c.precision == CS_BF16 && L.nb == 16 && L.a16.get() != nullptr;
 }
 
+// Algorithmic bytes of one colour sweep: the colour's share of A's BF16
+// blocks (from a zero guess none), its Lambda blocks, b, x (read and written).
+double bf16_sweep_bytes(const Level &L, int colour, bool zero) {
+    const int64_t nblk = L.cblk_ptr[colour + 1] - L.cblk_ptr[colour];
+    return (zero ? 0.0 : (double)L.bsr_nnzb * 512.0 * nblk / std::max<int64_t>(L.B, 1)) +
+           nblk * (512.0 + 16 * 4 * (zero ? 2.0 : 3.0));
+}
+
 void bf16_sweep(Ctx &c, const Level &L, int ell, int colour, bool reverse, bool zero, const float *b, float *x) {
     const int64_t k0 = L.cblk_ptr[colour], nblk = L.cblk_ptr[colour + 1] - k0;
     if (nblk == 0) return;
@@ -217,9 +225,7 @@ void bf16_sweep(Ctx &c, const Level &L, int ell, int colour, bool reverse, bool 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     (void)trace_begin_launch(c, zero ? CS_TRACE_SWEEP_ZERO : (L.n >= (1 << 19) ? CS_TRACE_SWEEP
                                                                                : CS_TRACE_SWEEP_SMALL),
-                             (zero ? 0.0 : (double)L.bsr_nnzb * 512.0 * nblk / std::max<int64_t>(L.B, 1)) +
-                                 nblk * (512.0 + 16 * 4 * (zero ? 2.0 : 3.0)),
-                             &ev0, &ev1);
+                             bf16_sweep_bytes(L, colour, zero), &ev0, &ev1);
     if (zero)
         hipExtLaunchKernelGGL(k_bsr16_sweep<true>, dim3(gdim(nblk, WG / 64)), dim3(WG), 0, c.stream, ev0, ev1, 0,
                               nblk, L.cblk.get() + k0, L.bsr_ptr.get(), L.bsr_col.get(), L.a16.get(), lam, b, x);

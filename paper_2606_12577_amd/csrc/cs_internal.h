@@ -206,7 +206,9 @@ struct Trace {
     int64_t seen[CS_TRACE_NCLASS] = {0};
     std::vector<hipEvent_t> ev;          // pairs: ev[2k] start, ev[2k+1] end
     std::vector<int> cls;
-    std::vector<double> cls_bytes;       // per recorded launch
+    std::vector<int> cls_n;              // launches per recorded interval
+    std::vector<double> cls_bytes;       // per recorded interval
+    int run_cls = -1;                    // class being timed as a run of consecutive launches
     size_t used = 0;
     double ms[CS_TRACE_NCLASS] = {0};
     int64_t count[CS_TRACE_NCLASS] = {0};
@@ -301,6 +303,11 @@ int trace_begin(Ctx &c, int cls, double bytes);   // returns slot or -1
 // *start / *stop, null when the launch is not sampled): the kernel's duration
 // without event-packet overhead.  (Solves replayed from graphs are not traced.)
 int trace_begin_launch(Ctx &c, int cls, double bytes, hipEvent_t *start, hipEvent_t *stop);
+// One event pair around `launches` consecutive launches of class cls (their
+// summed algorithmic bytes): the launches inside are not timed one by one.
+int trace_begin_run(Ctx &c, int cls, double bytes, int launches);
+void trace_end_run(Ctx &c, int slot);
+double bf16_sweep_bytes(const Level &L, int colour, bool zero);
 void trace_end(Ctx &c, int slot);
 void trace_flush(Ctx &c);
 void trace_release(Ctx &c);

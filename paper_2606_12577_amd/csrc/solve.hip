@@ -1483,6 +1483,18 @@ const double *pval<double>(const Level &L, bool tr) { return tr ? L.pt_val64.get
 template <>
 const float *pval<float>(const Level &L, bool tr) { return tr ? L.pt_val32.get() : L.p_val32.get(); }
 
+// Algorithmic bytes of one sweep launch: A's entries with their column index
+// (none from a zero guess), the Lambda rows, b and x_out, x_in (all rows of x
+// for a colour), and x_c when the interpolation is fused in.
+template <typename T, int R>
+double sweep_bytes(const Level &L, const Sell &S, bool rowmap, bool zero, bool prol) {
+    const int64_t nrows = rowmap ? S.nrows : L.n_active;
+    const int64_t nnz = rowmap ? S.nnz : L.act_nnz;
+    const double es = sizeof(T);
+    return (zero ? 0.0 : nnz * (es + 4.0)) + (double)nrows * L.nb * es + (double)nrows * R * es * 2.0 +
+           (zero ? 0.0 : (rowmap ? L.n : nrows) * R * es) + (prol ? (double)L.nc * R * es : 0.0);
+}
+
 template <typename T, int R>
 void launch_sweep(Ctx &c, const Level &L, const Sell &S, bool rowmap, bool zero, const T *lam, const T *b,
                   const T *xin, T *xout, const T *xc = nullptr, int agg_k = 0) {
@@ -1502,12 +1514,8 @@ void launch_sweep(Ctx &c, const Level &L, const Sell &S, bool rowmap, bool zero,
     const bool large = nslices >= SMALL_SLICES;
     const int cls = zero ? CS_TRACE_SWEEP_ZERO
                          : (xc ? CS_TRACE_SWEEP_PROLONG : (large ? CS_TRACE_SWEEP : CS_TRACE_SWEEP_SMALL));
-    const double es = sizeof(T);
-    const double bytes = (zero ? 0.0 : nnz * (es + 4.0)) + (double)nrows * L.nb * es +
-                         (double)nrows * R * es * 2.0 + (zero ? 0.0 : (rowmap ? L.n : nrows) * R * es) +
-                         (prol ? (double)L.nc * R * es : 0.0);
     hipEvent_t ev0 = nullptr, ev1 = nullptr;   // set for a sampled launch: it times itself
-    const int slot = trace_begin_launch(c, cls, bytes, &ev0, &ev1);
+    const int slot = trace_begin_launch(c, cls, sweep_bytes<T, R>(L, S, rowmap, zero, prol), &ev0, &ev1);
     dispatch_nb(L.nb, [&](auto nbc) {
         constexpr int NB = decltype(nbc)::value;
 #define CS_SWEEP(Z, M, P, ROWS)                                                                                     \
@@ -1634,13 +1642,23 @@ T *apply_cascade(Ctx &c, const Level &L, bool reverse, bool zero_start, const T 
         // s_begin = 1: step 0 (from zero, into alt) is already on the stream
         T *cur = x, *nxt = alt;
         if (s_begin == 1) std::swap(cur, nxt);
+        // the consecutive A-reading sweeps of a large level are timed as one
+        // run (one event pair; a timed single launch pays an end-of-kernel
+        // release that the untimed ones do not)
+        const int s_run = (s_begin == 0 && (zero_start || xc)) ? 1 : s_begin;
+        int run = -1;
         for (int s = s_begin; s < depth; ++s) {
+            if (s == s_run && L.act_slices >= SMALL_SLICES)
+                run = trace_begin_run(c, CS_TRACE_SWEEP,
+                                      (depth - s_run) * sweep_bytes<T, R>(L, L.sell, false, false, false),
+                                      depth - s_run);
             const int ell = reverse ? depth - 1 - s : s;
             const T *lam = lam_ptr<T>(L, reverse) + (int64_t)ell * nbl;
             launch_sweep<T, R>(c, L, L.sell, false, zero_start && s == 0, lam, b, cur, nxt, s == 0 ? xc : nullptr,
                                L.agg_k);
             std::swap(cur, nxt);
         }
+        trace_end_run(c, run);
         return cur;
     }
     // multiplicative: flattened (l, k) sequence, in place
@@ -1652,7 +1670,28 @@ T *apply_cascade(Ctx &c, const Level &L, bool reverse, bool zero_start, const T 
     const int nsteps = depth * chi;
     bool bf16 = false;
     if constexpr (std::is_same<T, float>::value && R == 1) bf16 = use_bf16(c, L);
+    // the A-reading colour sweeps of a large level run back to back: timed
+    // as one run (as the additive sweeps)
+    const int s_run = zero_start ? 1 : 0;
+    bool large = bf16 ? L.n >= (1 << 19) : true;
+    double run_bytes = 0.0;
+    int run_n = 0;
+    for (int s = s_run; s < nsteps; ++s) {
+        const int k = (reverse ? nsteps - 1 - s : s) % chi;
+        if (bf16) {
+            if (L.cblk_ptr[k + 1] == L.cblk_ptr[k]) continue;
+            run_bytes += bf16_sweep_bytes(L, k, false);
+        } else {
+            const Sell &S = L.csell[k];
+            if (S.nrows == 0) continue;
+            large = large && S.nslices >= SMALL_SLICES;
+            run_bytes += sweep_bytes<T, R>(L, S, true, false, false);
+        }
+        ++run_n;
+    }
+    int run = -1;
     for (int s = 0; s < nsteps; ++s) {
+        if (s == s_run && large) run = trace_begin_run(c, CS_TRACE_SWEEP, run_bytes, run_n);
         const int f = reverse ? nsteps - 1 - s : s;
         const int ell = f / chi, k = f % chi;
         if constexpr (std::is_same<T, float>::value && R == 1) {
@@ -1666,6 +1705,7 @@ T *apply_cascade(Ctx &c, const Level &L, bool reverse, bool zero_start, const T 
         const T *lam = lam_ptr<T>(L, reverse) + (int64_t)ell * nbl;
         launch_sweep<T, R>(c, L, S, true, zero_start && s == 0, lam, b, x, x);
     }
+    trace_end_run(c, run);
     return x;
 }
 
