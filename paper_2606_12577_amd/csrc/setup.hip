@@ -747,17 +747,19 @@ __device__ void normal_solve(const double *G, const double *H, double *Lc, doubl
 }
 
 // Normal equations of one block row: G = M M^T, H = E M^T, Lambda~ = H G^{-1}
-// (Cholesky; pseudo-inverse fallback).  One workgroup per list row.
+// (Cholesky; pseudo-inverse fallback).  A workgroup per list row, striding
+// over the nl rows; with only != null just the rows li with only[li] != 0.
 template <int NBT>   // > 0: block size fixed at compile time; 0: nb_rt
-__global__ __launch_bounds__(WG) void k_gram_solve(const int32_t *__restrict__ list, int nb_rt,
+__global__ __launch_bounds__(WG) void k_gram_solve(int nl, const int32_t *__restrict__ list, int nb_rt,
                                                    const int32_t *__restrict__ mptr, const int32_t *__restrict__ mcol,
                                                    const double *__restrict__ mval, const int32_t *__restrict__ eptr,
                                                    const int32_t *__restrict__ ecol, const double *__restrict__ eval,
-                                                   double *__restrict__ lamt, int32_t *__restrict__ singular,
-                                                   double ridge) {
+                                                   double *__restrict__ lamt, int32_t *singular, double ridge,
+                                                   const int32_t *only) {   // only may alias singular
     __shared__ double G[MAXNB * MAXNB], H[MAXNB * MAXNB], Lc[MAXNB * MAXNB], V[MAXNB * MAXNB];
     __shared__ int32_t epos[UNION_CAP];   // position in pattern(M_i) of every block of E_i
-    const int li = blockIdx.x;
+  for (int li = blockIdx.x; li < nl; li += gridDim.x) {
+    if (only && only[li] == 0) continue;   // uniform per workgroup
     const int i = list[li];
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
@@ -837,6 +839,8 @@ __global__ __launch_bounds__(WG) void k_gram_solve(const int32_t *__restrict__ l
     }
     __syncthreads();
     normal_solve(G, H, Lc, V, nb, lamt + (int64_t)i * nb2, singular + li, ridge);
+    __syncthreads();   // G, H and epos are rewritten by the next row
+  }
 }
 
 // G = M M^T and H = E M^T on the matrix cores (FP64 MFMA 16x16x4) for 16x16
@@ -903,6 +907,120 @@ __global__ __launch_bounds__(WG) void k_gram_mfma(const int32_t *__restrict__ li
     }
     __syncthreads();
     normal_solve(G, H, Lc, V, NBT, lamt + (int64_t)i * NB2, singular + li, ridge);
+}
+
+// G = M M^T and H = E M^T for 8x8 blocks on the FP64 matrix cores, two block
+// rows per wavefront: operand rows 0-7 of a 16x16x4 product belong to the
+// first row, rows 8-15 to the second, so the two diagonal 8x8 blocks of the
+// 16x16 result are the two rows' Gram matrices (the off-diagonal blocks pair
+// columns of different rows and are discarded).  A step takes four columns of
+// each row's M, two steps per block; the shorter row is padded with zeros.
+// E_i's block at M_i's block p is found by a cursor that walks E_i's sorted
+// columns alongside M_i's (pattern(E_i) is contained in pattern(M_i)).  The
+// normal equations of the workgroup's eight rows are then solved together
+// with normal_solve's Gauss-Jordan elimination, pivot cut-off and product
+// order; a row that meets a pivot below the cut-off (or a non-positive
+// diagonal) is marked in redo[li] for k_gram_solve's minimum-norm path.
+__global__ __launch_bounds__(WG) void k_gram_mfma8(int nl, const int32_t *__restrict__ list,
+                                                   const int32_t *__restrict__ mptr, const int32_t *__restrict__ mcol,
+                                                   const double *__restrict__ mval, const int32_t *__restrict__ eptr,
+                                                   const int32_t *__restrict__ ecol, const double *__restrict__ eval,
+                                                   double *__restrict__ lamt, int32_t *__restrict__ redo,
+                                                   double ridge) {
+    constexpr int NB = 8, NB2 = 64, W2 = 2 * NB, ROWS = 2 * (WG / 64);
+    __shared__ double Gs[ROWS][NB2], Hs[ROWS][NB2], Aug[ROWS][NB * W2];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int r16 = lane & 15, cq = lane >> 4, half = r16 >> 3, rr = r16 & 7;
+    const int slot = 2 * wave + half;
+    const int li = blockIdx.x * ROWS + slot;
+    int mlo = 0, k = 0, elo = 0, ek = 0;
+    if (li < nl) {
+        const int i = list[li];
+        mlo = mptr[li];
+        k = mptr[li + 1] - mlo;
+        elo = eptr[i];
+        ek = eptr[i + 1] - elo;
+    }
+    const int kmax = max(__shfl(k, 0, 64), __shfl(k, 8, 64));   // wave-uniform trip count
+    d4_t dg = {0.0, 0.0, 0.0, 0.0}, dh = {0.0, 0.0, 0.0, 0.0};
+    int qc = 0;   // cursor in E_i's sorted block columns
+    for (int p = 0; p < kmax; ++p) {
+        double am0 = 0.0, am1 = 0.0, ae0 = 0.0, ae1 = 0.0;
+        if (p < k) {
+            const int col = mcol[mlo + p];
+            while (qc < ek && ecol[elo + qc] < col) ++qc;
+            const double *mb = mval + (int64_t)(mlo + p) * NB2 + rr * NB;
+            am0 = mb[cq];
+            am1 = mb[4 + cq];
+            if (qc < ek && ecol[elo + qc] == col) {
+                const double *eb = eval + (int64_t)(elo + qc) * NB2 + rr * NB;
+                ae0 = eb[cq];
+                ae1 = eb[4 + cq];
+            }
+        }
+        dg = __builtin_amdgcn_mfma_f64_16x16x4f64(am0, am0, dg, 0, 0, 0);
+        dh = __builtin_amdgcn_mfma_f64_16x16x4f64(ae0, am0, dh, 0, 0, 0);
+        dg = __builtin_amdgcn_mfma_f64_16x16x4f64(am1, am1, dg, 0, 0, 0);
+        dh = __builtin_amdgcn_mfma_f64_16x16x4f64(ae1, am1, dh, 0, 0, 0);
+    }
+    // result lane l, register x = D[4x + l/16][l%16]: this lane's half owns
+    // registers 2 half and 2 half + 1 of its own column
+    {
+        const double g0 = half ? dg[2] : dg[0], g1 = half ? dg[3] : dg[1];
+        const double h0 = half ? dh[2] : dh[0], h1 = half ? dh[3] : dh[1];
+        Gs[slot][cq * NB + rr] = g0;
+        Gs[slot][(4 + cq) * NB + rr] = g1;
+        Hs[slot][cq * NB + rr] = h0;
+        Hs[slot][(4 + cq) * NB + rr] = h1;
+    }
+    __syncthreads();
+    // eight rows, 32 threads each, four entries of [G + tau I | I] per thread
+    const int s = t >> 5, j = t & 31;
+    const int ls = blockIdx.x * ROWS + s;
+    const double *G = Gs[s];
+    double trace = 0.0, dmax = 0.0;
+    for (int q = 0; q < NB; ++q) trace += G[q * NB + q];
+    const double tau = ridge > 0.0 ? ridge * trace / NB : 0.0;
+    for (int q = 0; q < NB; ++q) dmax = fmax(dmax, G[q * NB + q] + tau);
+    bool bad = !(dmax > 0.0);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int e = j + 32 * m, r = e / W2, c = e % W2;
+        Aug[s][e] = c < NB ? G[r * NB + c] + (r == c ? tau : 0.0) : (c - NB == r ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    for (int q = 0; q < NB; ++q) {   // uniform: every slot takes all NB steps, a bad one without updates
+        const double piv = Aug[s][q * W2 + q];
+        if (!(piv > PIVOT_TOL * dmax)) bad = true;
+        double f[4], g[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int e = j + 32 * m;
+            f[m] = Aug[s][(e / W2) * W2 + q];
+            g[m] = Aug[s][q * W2 + e % W2];
+        }
+        __syncthreads();
+        if (!bad) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int e = j + 32 * m;
+                Aug[s][e] = (e / W2 == q) ? g[m] / piv : Aug[s][e] - f[m] * g[m] / piv;
+            }
+        }
+        __syncthreads();
+    }
+    if (ls >= nl) return;
+    if (j == 0) redo[ls] = bad ? 1 : 0;
+    if (bad) return;
+    const int i = list[ls];
+    const double *H = Hs[s];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const int e = j + 32 * m, r = e / NB, c = e % NB;
+        double acc = 0.0;
+        for (int u = 0; u < NB; ++u) acc += H[r * NB + u] * Aug[s][u * W2 + NB + c];
+        lamt[(int64_t)i * NB2 + e] = acc;
+    }
 }
 
 // Point blocks (n = 1): one wavefront per list row, four rows per workgroup.
@@ -2682,14 +2800,23 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
             else {
                 auto go = [&](auto nbc) {
                     constexpr int NBT = decltype(nbc)::value;
-                    hipLaunchKernelGGL((k_gram_solve<NBT>), dim3(nl), dim3(WG), 0, s, dlist, nb, mp.ptr.get(),
+                    hipLaunchKernelGGL((k_gram_solve<NBT>), dim3(nl), dim3(WG), 0, s, nl, dlist, nb, mp.ptr.get(),
                                        mp.col.get(), mval.get(), E.pat.ptr.get(), E.pat.col.get(), E.val.get(),
-                                       lam_l, sing.get(), o.ridge);
+                                       lam_l, sing.get(), o.ridge, (const int32_t *)nullptr);
                 };
                 switch (nb) {
                     case 2: go(std::integral_constant<int, 2>{}); break;
                     case 4: go(std::integral_constant<int, 4>{}); break;
-                    case 8: go(std::integral_constant<int, 8>{}); break;
+                    case 8:
+                        // matrix cores, then the rows they flag through the minimum-norm path
+                        hipLaunchKernelGGL(k_gram_mfma8, dim3((unsigned)ceil_div(nl, 8)), dim3(WG), 0, s, nl, dlist,
+                                           mp.ptr.get(), mp.col.get(), mval.get(), E.pat.ptr.get(),
+                                           E.pat.col.get(), E.val.get(), lam_l, sing.get(), o.ridge);
+                        hipLaunchKernelGGL((k_gram_solve<8>), dim3((unsigned)std::min<int64_t>(nl, 2048)), dim3(WG),
+                                           0, s, nl, dlist, nb, mp.ptr.get(), mp.col.get(), mval.get(),
+                                           E.pat.ptr.get(), E.pat.col.get(), E.val.get(), lam_l, sing.get(), o.ridge,
+                                           (const int32_t *)sing.get());
+                        break;
                     case 16:
                         hipLaunchKernelGGL(k_gram_mfma, dim3(nl), dim3(WG), 0, s, dlist, mp.ptr.get(),
                                            mp.col.get(), mval.get(), E.pat.ptr.get(), E.pat.col.get(),
