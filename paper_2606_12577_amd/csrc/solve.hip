@@ -93,18 +93,26 @@ __device__ __forceinline__ Tiles my_tiles(int64_t ntiles) {
     return Tiles{ntiles * xcd / 8 + j, ntiles * (xcd + 1) / 8, gx};
 }
 
-// Streaming (non-temporal) loads for the per-sweep data that is not worth
-// caching (Lambda, b), so that the caches keep the gathered x.  FP32 matrix
-// entries (column, value) are loaded normally: every sweep of a level reads
-// the same A, which then stays in the 256 MB last-level cache between sweeps
-// (128^3 interface sweep 74.8 -> 70.5 us; caching Lambda or b as well was
-// slower: 79 us).  FP64 matrices keep streaming loads: at these sizes they do
-// not fit beside the FP64 vectors (the 128^3 FP64 V-cycle was 6% slower).
+// Loads of the per-sweep streams that are read once (Lambda, b).  FP32 data
+// goes through streaming (non-temporal) loads, so that the caches keep the
+// gathered x and the matrix: FP32 matrix entries (column, value) are loaded
+// normally, every sweep of a level reads the same A, which then stays in the
+// 256 MB last-level cache between sweeps (128^3 interface sweep 74.8 -> 70.5
+// us; ordinary loads of Lambda and b as well: 76-79 us).  FP64 streams use
+// ordinary loads: measured on the 128^3 problem, the FP64 sweep with 8
+// right-hand sides takes 173 instead of 202 us, with one 66 instead of 87 us,
+// and the FP64 refinement residual 89 instead of 94 us.  FP64 matrices keep
+// streaming loads (ordinary ones were 2-6% slower: they do not fit beside the
+// FP64 vectors).
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 template <typename T, int R>
 __device__ __forceinline__ void vload_nt(const T *p, T (&o)[R]) {
+    if constexpr (sizeof(T) == 8) {
+        vload<T, R>(p, o);
+        return;
+    }
     constexpr int BYTES = (int)sizeof(T) * R;
     if constexpr (BYTES % 16 == 0) {
         const u32x4 *q = reinterpret_cast<const u32x4 *>(p);
