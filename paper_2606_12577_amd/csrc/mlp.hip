@@ -29,12 +29,35 @@ __device__ __forceinline__ float sigmoidf(float z) { return 1.0f / (1.0f + expf(
 // layout (16x16x4, one block): lane l supplies A[l%16][l/16] and
 // B[l/16][l%16] and receives D[4*(l/16) + r][l%16] in register r.
 template <int EPI>
+__device__ __forceinline__ void epilogue(float v, int gm, int gn, float *__restrict__ C, int64_t ldc,
+                                         const float *__restrict__ bias, float *__restrict__ aux, int64_t ldaux,
+                                         const float *__restrict__ scale, const float *__restrict__ shift) {
+    if constexpr (EPI == EPI_BIAS) {
+        v += bias[gn];
+    } else if constexpr (EPI == EPI_BIAS_SILU) {
+        v += bias[gn];
+        aux[(int64_t)gm * ldaux + gn] = v;
+        v = v * sigmoidf(v);
+    } else if constexpr (EPI == EPI_DSILU) {
+        const float z = aux[(int64_t)gm * ldaux + gn];
+        const float s = sigmoidf(z);
+        v *= s * (1.0f + z * (1.0f - s));
+    } else if constexpr (EPI == EPI_AFFINE) {
+        v = (v + bias[gn]) * scale[gn] + shift[gn];
+    }
+    C[(int64_t)gm * ldc + gn] = v;
+}
+
+// Split K: workgroup z of the grid's third dimension sums k in
+// [z kchunk, (z + 1) kchunk) and, with part given, stores its raw partial
+// C_z(m, n) at part[(z M + m) N + n] for k_splitk to sum and finish.
+template <int EPI>
 __global__ __launch_bounds__(WG) void k_gemm(int M, int N, int K, const float *__restrict__ A, int64_t sam,
                                              int64_t sak, const int32_t *__restrict__ ar, const float *__restrict__ B,
                                              int64_t sbk, int64_t sbn, const int32_t *__restrict__ br,
                                              float *__restrict__ C, int64_t ldc, const float *__restrict__ bias,
                                              float *__restrict__ aux, int64_t ldaux, const float *__restrict__ scale,
-                                             const float *__restrict__ shift) {
+                                             const float *__restrict__ shift, int kchunk, float *__restrict__ part) {
     __shared__ float As[TK][TM + 4];
     __shared__ float Bs[TK][TN + 4];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -47,7 +70,8 @@ __global__ __launch_bounds__(WG) void k_gemm(int M, int N, int K, const float *_
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const bool a_kfast = sak == 1;
     const bool b_nfast = sbn == 1;
-    for (int k0 = 0; k0 < K; k0 += TK) {
+    const int kbeg = (int)blockIdx.z * kchunk, kend = min(K, kbeg + kchunk);
+    for (int k0 = kbeg; k0 < kend; k0 += TK) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             int mm, kk;
@@ -60,7 +84,7 @@ __global__ __launch_bounds__(WG) void k_gemm(int M, int N, int K, const float *_
             }
             const int gm = m0 + mm, gk = k0 + kk;
             float v = 0.f;
-            if (gm < M && gk < K) {
+            if (gm < M && gk < kend) {
                 const int64_t r = ar ? (int64_t)ar[gm] : (int64_t)gm;
                 v = A[r * sam + (int64_t)gk * sak];
             }
@@ -78,7 +102,7 @@ __global__ __launch_bounds__(WG) void k_gemm(int M, int N, int K, const float *_
             }
             const int gk = k0 + kk, gn = n0 + nn;
             float v = 0.f;
-            if (gk < K && gn < N) {
+            if (gk < kend && gn < N) {
                 const int64_t r = br ? (int64_t)br[gk] : (int64_t)gk;
                 v = B[r * sbk + (int64_t)gn * sbn];
             }
@@ -109,24 +133,26 @@ __global__ __launch_bounds__(WG) void k_gemm(int M, int N, int K, const float *_
             for (int r = 0; r < 4; ++r) {
                 const int gm = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
                 if (gm >= M || gn >= N) continue;
-                float v = acc[i][j][r];
-                if constexpr (EPI == EPI_BIAS) {
-                    v += bias[gn];
-                } else if constexpr (EPI == EPI_BIAS_SILU) {
-                    v += bias[gn];
-                    aux[(int64_t)gm * ldaux + gn] = v;
-                    v = v * sigmoidf(v);
-                } else if constexpr (EPI == EPI_DSILU) {
-                    const float z = aux[(int64_t)gm * ldaux + gn];
-                    const float s = sigmoidf(z);
-                    v *= s * (1.0f + z * (1.0f - s));
-                } else if constexpr (EPI == EPI_AFFINE) {
-                    v = (v + bias[gn]) * scale[gn] + shift[gn];
-                }
-                C[(int64_t)gm * ldc + gn] = v;
+                if (part)
+                    part[((int64_t)blockIdx.z * M + gm) * N + gn] = acc[i][j][r];
+                else
+                    epilogue<EPI>(acc[i][j][r], gm, gn, C, ldc, bias, aux, ldaux, scale, shift);
             }
         }
     }
+}
+
+// C(m, n) = epilogue(sum_z part_z(m, n)), z in increasing order
+template <int EPI>
+__global__ __launch_bounds__(WG) void k_splitk(int M, int N, int S, const float *__restrict__ part,
+                                               float *__restrict__ C, int64_t ldc, const float *__restrict__ bias,
+                                               float *__restrict__ aux, int64_t ldaux, const float *__restrict__ scale,
+                                               const float *__restrict__ shift) {
+    const int64_t e = blockIdx.x * (int64_t)WG + threadIdx.x, mn = (int64_t)M * N;
+    if (e >= mn) return;
+    float v = 0.f;
+    for (int z = 0; z < S; ++z) v += part[z * mn + e];
+    epilogue<EPI>(v, (int)(e / N), (int)(e % N), C, ldc, bias, aux, ldaux, scale, shift);
 }
 
 // dY = 2 (y - t') / (n * n_out) with t' = (T[row] - mean) / std; per-workgroup
@@ -172,12 +198,36 @@ __global__ __launch_bounds__(1024) void k_sum(int64_t G, const double *__restric
 }
 
 // out[c] = sum_r D[r][c]
-__global__ void k_colsum(int64_t n, int ncols, const float *__restrict__ D, float *__restrict__ out) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncols) return;
+// Column sums of an n x ncols matrix (bias gradients): workgroup (x, y)
+// covers 64 columns and rows [y rpb, (y + 1) rpb), its four wavefronts every
+// fourth row; the four sums are added in order, then k_colsum_fin adds the
+// row blocks' partials in order (with one row block, directly into out).
+__global__ __launch_bounds__(WG) void k_colsum(int64_t n, int ncols, int64_t rpb, const float *__restrict__ D,
+                                               float *__restrict__ out) {
+    __shared__ float red[WG / 64][64];
+    const int t = threadIdx.x, g = t >> 6;
+    const int c = blockIdx.x * 64 + (t & 63);
+    const int64_t r0 = (int64_t)blockIdx.y * rpb, r1 = min(n, r0 + rpb);
     float s = 0.f;
-    for (int64_t r = 0; r < n; ++r) s += D[r * ncols + c];
-    out[c] = s;
+    if (c < ncols)
+        for (int64_t r = r0 + g; r < r1; r += WG / 64) s += D[r * ncols + c];
+    red[g][t & 63] = s;
+    __syncthreads();
+    if (g == 0 && c < ncols) {
+        float v = red[0][t];
+#pragma unroll
+        for (int q = 1; q < WG / 64; ++q) v += red[q][t];
+        out[(int64_t)blockIdx.y * ncols + c] = v;
+    }
+}
+
+__global__ __launch_bounds__(WG) void k_colsum_fin(int ncols, int nblk, const float *__restrict__ part,
+                                                   float *__restrict__ out) {
+    const int c = blockIdx.x * WG + threadIdx.x;
+    if (c >= ncols) return;
+    float v = 0.f;
+    for (int b = 0; b < nblk; ++b) v += part[(int64_t)b * ncols + c];
+    out[c] = v;
 }
 
 __global__ void k_adam(int64_t np, float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
@@ -278,14 +328,35 @@ __global__ __launch_bounds__(WG) void k_fe_features(int n, const double *__restr
 
 inline unsigned gdim(int64_t n, int wg = WG) { return (unsigned)ceil_div(n, wg); }
 
+// A product with fewer than SPLIT_TILES output tiles and a long k (the
+// training batch's weight gradients and layers) is split over k into up to
+// 8 slices of at least 64, so that it runs on enough workgroups; the partial
+// products go through m.kpart and k_splitk.
+constexpr int SPLIT_TILES = 128;
+
 template <int EPI>
-void gemm(hipStream_t s, int M, int N, int K, const float *A, int64_t sam, int64_t sak, const int32_t *ar,
+void gemm(Mlp &m, hipStream_t s, int M, int N, int K, const float *A, int64_t sam, int64_t sak, const int32_t *ar,
           const float *B, int64_t sbk, int64_t sbn, const int32_t *br, float *C, int64_t ldc,
           const float *bias = nullptr, float *aux = nullptr, int64_t ldaux = 0, const float *scale = nullptr,
           const float *shift = nullptr) {
     if (M <= 0 || N <= 0) return;
-    hipLaunchKernelGGL((k_gemm<EPI>), dim3(gdim(N, TN), gdim(M, TM)), dim3(WG), 0, s, M, N, K, A, sam, sak, ar, B,
-                       sbk, sbn, br, C, ldc, bias, aux, ldaux, scale, shift);
+    const int64_t tiles = (int64_t)gdim(N, TN) * gdim(M, TM);
+    int S = 1;
+    if (tiles < SPLIT_TILES && K >= 8 * TK)
+        S = (int)std::min<int64_t>({8, ceil_div(2 * SPLIT_TILES, tiles), K / (4 * TK)});
+    int kchunk = (int)ceil_div(ceil_div(K, S), TK) * TK;
+    S = (int)ceil_div(K, kchunk);
+    if (S > 1 && (int64_t)S * M * N > (int64_t)m.kpart.n) S = 1;
+    if (S <= 1) {
+        kchunk = std::max(K, 1);
+        hipLaunchKernelGGL((k_gemm<EPI>), dim3(gdim(N, TN), gdim(M, TM), 1), dim3(WG), 0, s, M, N, K, A, sam, sak,
+                           ar, B, sbk, sbn, br, C, ldc, bias, aux, ldaux, scale, shift, kchunk, (float *)nullptr);
+    } else {
+        hipLaunchKernelGGL((k_gemm<EPI>), dim3(gdim(N, TN), gdim(M, TM), S), dim3(WG), 0, s, M, N, K, A, sam, sak,
+                           ar, B, sbk, sbn, br, C, ldc, bias, aux, ldaux, scale, shift, kchunk, m.kpart.get());
+        hipLaunchKernelGGL((k_splitk<EPI>), dim3(gdim((int64_t)M * N)), dim3(WG), 0, s, M, N, S,
+                           (const float *)m.kpart.get(), C, ldc, bias, aux, ldaux, scale, shift);
+    }
     CS_LAUNCH_CHECK();
 }
 
@@ -301,6 +372,11 @@ void ensure_cap(Mlp &m, int64_t rows) {
     m.d2.alloc(rows * W);
     m.d1.alloc(rows * W);
     m.part.alloc(gdim(rows * O));
+    // split-k partials: up to 8 slices of the largest product that is split
+    // (fewer than SPLIT_TILES output tiles)
+    const int64_t split_rows = std::min<int64_t>(rows, (int64_t)SPLIT_TILES * TM);
+    m.kpart.alloc((size_t)8 * std::max<int64_t>({split_rows * (int64_t)std::max(W, O), (int64_t)W * m.n_in,
+                                                 (int64_t)W * (int64_t)W}));
     m.cap = rows;
 }
 
@@ -319,15 +395,15 @@ void ensure_acc(Mlp &m, size_t slots) {
 void forward(Mlp &m, hipStream_t s, const float *X, const int32_t *rows, int64_t n, bool affine, float *Y) {
     const float *p = m.p.get();
     const int W = m.width, I = m.n_in, O = m.n_out;
-    gemm<EPI_BIAS_SILU>(s, (int)n, W, I, X, I, 1, rows, p + m.off[0], 1, I, nullptr, m.h1.get(), W, p + m.off[1],
+    gemm<EPI_BIAS_SILU>(m, s, (int)n, W, I, X, I, 1, rows, p + m.off[0], 1, I, nullptr, m.h1.get(), W, p + m.off[1],
                         m.z1.get(), W);
-    gemm<EPI_BIAS_SILU>(s, (int)n, W, W, m.h1.get(), W, 1, nullptr, p + m.off[2], 1, W, nullptr, m.h2.get(), W,
+    gemm<EPI_BIAS_SILU>(m, s, (int)n, W, W, m.h1.get(), W, 1, nullptr, p + m.off[2], 1, W, nullptr, m.h2.get(), W,
                         p + m.off[3], m.z2.get(), W);
     if (affine)
-        gemm<EPI_AFFINE>(s, (int)n, O, W, m.h2.get(), W, 1, nullptr, p + m.off[4], 1, W, nullptr, Y, O, p + m.off[5],
+        gemm<EPI_AFFINE>(m, s, (int)n, O, W, m.h2.get(), W, 1, nullptr, p + m.off[4], 1, W, nullptr, Y, O, p + m.off[5],
                          nullptr, 0, m.std.get(), m.mean.get());
     else
-        gemm<EPI_BIAS>(s, (int)n, O, W, m.h2.get(), W, 1, nullptr, p + m.off[4], 1, W, nullptr, Y, O, p + m.off[5]);
+        gemm<EPI_BIAS>(m, s, (int)n, O, W, m.h2.get(), W, 1, nullptr, p + m.off[4], 1, W, nullptr, Y, O, p + m.off[5]);
 }
 
 // loss partials of the current y against T[rows] into acc[slot]; dY when grad
@@ -341,6 +417,20 @@ void mse(Mlp &m, hipStream_t s, const float *T, const int32_t *rows, int64_t n, 
     CS_LAUNCH_CHECK();
 }
 
+void colsum(Mlp &m, hipStream_t s, int64_t n, int ncols, const float *D, float *out) {
+    int64_t nblk = std::min<int64_t>(64, ceil_div(std::max<int64_t>(n, 1), 128));
+    if (nblk * ncols > (int64_t)m.kpart.n) nblk = 1;
+    const int64_t rpb = ceil_div(std::max<int64_t>(n, 1), nblk);
+    const dim3 grid(gdim(ncols, 64), (unsigned)nblk);
+    if (nblk == 1) {
+        hipLaunchKernelGGL(k_colsum, grid, dim3(WG), 0, s, n, ncols, rpb, D, out);
+    } else {
+        hipLaunchKernelGGL(k_colsum, grid, dim3(WG), 0, s, n, ncols, rpb, D, m.kpart.get());
+        hipLaunchKernelGGL(k_colsum_fin, dim3(gdim(ncols)), dim3(WG), 0, s, ncols, (int)nblk,
+                           (const float *)m.kpart.get(), out);
+    }
+}
+
 // gradient of the loss of the last forward (rows of X) into g
 void backward(Mlp &m, hipStream_t s, const float *X, const int32_t *rows, int64_t n) {
     const float *p = m.p.get();
@@ -348,18 +438,18 @@ void backward(Mlp &m, hipStream_t s, const float *X, const int32_t *rows, int64_
     const int W = m.width, I = m.n_in, O = m.n_out;
     const int N = (int)n;
     // layer 3: gW3 = dy^T h2, gb3 = colsum(dy), d2 = (dy W3) .* silu'(z2)
-    gemm<EPI_STORE>(s, O, W, N, m.dy.get(), 1, O, nullptr, m.h2.get(), W, 1, nullptr, g + m.off[4], W);
-    hipLaunchKernelGGL(k_colsum, dim3(gdim(O)), dim3(WG), 0, s, n, O, m.dy.get(), g + m.off[5]);
-    gemm<EPI_DSILU>(s, N, W, O, m.dy.get(), O, 1, nullptr, p + m.off[4], W, 1, nullptr, m.d2.get(), W, nullptr,
+    gemm<EPI_STORE>(m, s, O, W, N, m.dy.get(), 1, O, nullptr, m.h2.get(), W, 1, nullptr, g + m.off[4], W);
+    colsum(m, s, n, O, m.dy.get(), g + m.off[5]);
+    gemm<EPI_DSILU>(m, s, N, W, O, m.dy.get(), O, 1, nullptr, p + m.off[4], W, 1, nullptr, m.d2.get(), W, nullptr,
                     m.z2.get(), W);
     // layer 2
-    gemm<EPI_STORE>(s, W, W, N, m.d2.get(), 1, W, nullptr, m.h1.get(), W, 1, nullptr, g + m.off[2], W);
-    hipLaunchKernelGGL(k_colsum, dim3(gdim(W)), dim3(WG), 0, s, n, W, m.d2.get(), g + m.off[3]);
-    gemm<EPI_DSILU>(s, N, W, W, m.d2.get(), W, 1, nullptr, p + m.off[2], W, 1, nullptr, m.d1.get(), W, nullptr,
+    gemm<EPI_STORE>(m, s, W, W, N, m.d2.get(), 1, W, nullptr, m.h1.get(), W, 1, nullptr, g + m.off[2], W);
+    colsum(m, s, n, W, m.d2.get(), g + m.off[3]);
+    gemm<EPI_DSILU>(m, s, N, W, W, m.d2.get(), W, 1, nullptr, p + m.off[2], W, 1, nullptr, m.d1.get(), W, nullptr,
                     m.z1.get(), W);
     // layer 1
-    gemm<EPI_STORE>(s, W, I, N, m.d1.get(), 1, W, nullptr, X, I, 1, rows, g + m.off[0], I);
-    hipLaunchKernelGGL(k_colsum, dim3(gdim(W)), dim3(WG), 0, s, n, W, m.d1.get(), g + m.off[1]);
+    gemm<EPI_STORE>(m, s, W, I, N, m.d1.get(), 1, W, nullptr, X, I, 1, rows, g + m.off[0], I);
+    colsum(m, s, n, W, m.d1.get(), g + m.off[1]);
     CS_LAUNCH_CHECK();
 }
 

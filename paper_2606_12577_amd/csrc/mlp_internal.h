@@ -20,6 +20,7 @@ struct Mlp {
     int64_t cap = 0;
     DBuf<float> z1, h1, z2, h2, y, dy, d2, d1;
     DBuf<double> part, acc;               // loss partial sums
+    DBuf<float> kpart;                    // split-k partial products
     double *h_acc = nullptr;              // pinned readback
     size_t h_acc_cap = 0;
 };
