@@ -748,18 +748,19 @@ __device__ void normal_solve(const double *G, const double *H, double *Lc, doubl
 
 // Normal equations of one block row: G = M M^T, H = E M^T, Lambda~ = H G^{-1}
 // (Cholesky; pseudo-inverse fallback).  A workgroup per list row, striding
-// over the nl rows; with only != null just the rows li with only[li] != 0.
+// over the nl rows; with only != null over the only[0] list rows only[1..].
 template <int NBT>   // > 0: block size fixed at compile time; 0: nb_rt
 __global__ __launch_bounds__(WG) void k_gram_solve(int nl, const int32_t *__restrict__ list, int nb_rt,
                                                    const int32_t *__restrict__ mptr, const int32_t *__restrict__ mcol,
                                                    const double *__restrict__ mval, const int32_t *__restrict__ eptr,
                                                    const int32_t *__restrict__ ecol, const double *__restrict__ eval,
-                                                   double *__restrict__ lamt, int32_t *singular, double ridge,
-                                                   const int32_t *only) {   // only may alias singular
+                                                   double *__restrict__ lamt, int32_t *__restrict__ singular,
+                                                   double ridge, const int32_t *__restrict__ only) {
     __shared__ double G[MAXNB * MAXNB], H[MAXNB * MAXNB], Lc[MAXNB * MAXNB], V[MAXNB * MAXNB];
     __shared__ int32_t epos[UNION_CAP];   // position in pattern(M_i) of every block of E_i
-  for (int li = blockIdx.x; li < nl; li += gridDim.x) {
-    if (only && only[li] == 0) continue;   // uniform per workgroup
+  const int nrows = only ? only[0] : nl;
+  for (int idx = blockIdx.x; idx < nrows; idx += gridDim.x) {
+    const int li = only ? only[1 + idx] : idx;
     const int i = list[li];
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
@@ -915,45 +916,64 @@ __global__ __launch_bounds__(WG) void k_gram_mfma(const int32_t *__restrict__ li
 // 16x16 result are the two rows' Gram matrices (the off-diagonal blocks pair
 // columns of different rows and are discarded).  A step takes four columns of
 // each row's M, two steps per block; the shorter row is padded with zeros.
-// E_i's block at M_i's block p is found by a cursor that walks E_i's sorted
-// columns alongside M_i's (pattern(E_i) is contained in pattern(M_i)).  The
-// normal equations of the workgroup's eight rows are then solved together
-// with normal_solve's Gauss-Jordan elimination, pivot cut-off and product
-// order; a row that meets a pivot below the cut-off (or a non-positive
-// diagonal) is marked in redo[li] for k_gram_solve's minimum-norm path.
+// The position in E_i of every block of M_i is searched first, by the whole
+// workgroup, into LDS (rows of more than QCAP8 blocks search as they go), so
+// that the product loop's iterations are independent.  The normal equations
+// of the workgroup's eight rows are then solved together with normal_solve's
+// Gauss-Jordan elimination, pivot cut-off and product order; a row that meets
+// a pivot below the cut-off (or a non-positive diagonal) gets redo[li] = 1
+// and is appended to redo_list (count in redo_list[0], rows from index 1) for
+// k_gram_solve's minimum-norm path.
+constexpr int QCAP8 = 512;
+
 __global__ __launch_bounds__(WG) void k_gram_mfma8(int nl, const int32_t *__restrict__ list,
                                                    const int32_t *__restrict__ mptr, const int32_t *__restrict__ mcol,
                                                    const double *__restrict__ mval, const int32_t *__restrict__ eptr,
                                                    const int32_t *__restrict__ ecol, const double *__restrict__ eval,
                                                    double *__restrict__ lamt, int32_t *__restrict__ redo,
-                                                   double ridge) {
+                                                   int32_t *__restrict__ redo_list, double ridge) {
     constexpr int NB = 8, NB2 = 64, W2 = 2 * NB, ROWS = 2 * (WG / 64);
     __shared__ double Gs[ROWS][NB2], Hs[ROWS][NB2], Aug[ROWS][NB * W2];
+    __shared__ int32_t qpos[ROWS][QCAP8];
+    __shared__ int32_t rmlo[ROWS], rk[ROWS], relo[ROWS], rek[ROWS];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int r16 = lane & 15, cq = lane >> 4, half = r16 >> 3, rr = r16 & 7;
     const int slot = 2 * wave + half;
-    const int li = blockIdx.x * ROWS + slot;
-    int mlo = 0, k = 0, elo = 0, ek = 0;
-    if (li < nl) {
-        const int i = list[li];
-        mlo = mptr[li];
-        k = mptr[li + 1] - mlo;
-        elo = eptr[i];
-        ek = eptr[i + 1] - elo;
+    if (t < ROWS) {
+        const int lr = blockIdx.x * ROWS + t;
+        int a = 0, b = 0, c = 0, d = 0;
+        if (lr < nl) {
+            const int i = list[lr];
+            a = mptr[lr];
+            b = mptr[lr + 1] - a;
+            c = eptr[i];
+            d = eptr[i + 1] - c;
+        }
+        rmlo[t] = a;
+        rk[t] = b;
+        relo[t] = c;
+        rek[t] = d;
     }
-    const int kmax = max(__shfl(k, 0, 64), __shfl(k, 8, 64));   // wave-uniform trip count
+    __syncthreads();
+    for (int sr = 0; sr < ROWS; ++sr) {
+        const int kk = min(rk[sr], QCAP8);
+        for (int p = t; p < kk; p += WG)
+            qpos[sr][p] = bsearch_i32(ecol, relo[sr], relo[sr] + rek[sr], mcol[rmlo[sr] + p]);
+    }
+    __syncthreads();
+    const int mlo = rmlo[slot], k = rk[slot], elo = relo[slot], ek = rek[slot];
+    const int kmax = max(rk[2 * wave], rk[2 * wave + 1]);   // wave-uniform trip count
     d4_t dg = {0.0, 0.0, 0.0, 0.0}, dh = {0.0, 0.0, 0.0, 0.0};
-    int qc = 0;   // cursor in E_i's sorted block columns
+#pragma unroll 2
     for (int p = 0; p < kmax; ++p) {
         double am0 = 0.0, am1 = 0.0, ae0 = 0.0, ae1 = 0.0;
         if (p < k) {
-            const int col = mcol[mlo + p];
-            while (qc < ek && ecol[elo + qc] < col) ++qc;
+            const int q = p < QCAP8 ? qpos[slot][p] : bsearch_i32(ecol, elo, elo + ek, mcol[mlo + p]);
             const double *mb = mval + (int64_t)(mlo + p) * NB2 + rr * NB;
             am0 = mb[cq];
             am1 = mb[4 + cq];
-            if (qc < ek && ecol[elo + qc] == col) {
-                const double *eb = eval + (int64_t)(elo + qc) * NB2 + rr * NB;
+            if (q >= 0) {
+                const double *eb = eval + (int64_t)q * NB2 + rr * NB;
                 ae0 = eb[cq];
                 ae1 = eb[4 + cq];
             }
@@ -1010,7 +1030,10 @@ __global__ __launch_bounds__(WG) void k_gram_mfma8(int nl, const int32_t *__rest
         __syncthreads();
     }
     if (ls >= nl) return;
-    if (j == 0) redo[ls] = bad ? 1 : 0;
+    if (j == 0) {
+        redo[ls] = bad ? 1 : 0;
+        if (bad) redo_list[1 + atomicAdd(redo_list, 1)] = ls;
+    }
     if (bad) return;
     const int i = list[ls];
     const double *H = Hs[s];
@@ -2741,7 +2764,7 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
     keep_pattern(E.pat);
     DBuf<double> lamt((size_t)depth * B * nb2);
     CS_HIP(hipMemsetAsync(lamt.get(), 0, lamt.bytes(), s));   // rows of direct segments get no smoother
-    DBuf<int32_t> pos(B), sing, cnt, err(B);
+    DBuf<int32_t> pos(B), sing, cnt, err(B), redo;
     DBuf<int64_t> tot(1);
     const int maxdeg = max_span(c, B, 1, ap.ptr.get());
     int32_t emax = 1;   // longest block row of E (E_0 = I)
@@ -2809,13 +2832,14 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
                     case 4: go(std::integral_constant<int, 4>{}); break;
                     case 8:
                         // matrix cores, then the rows they flag through the minimum-norm path
+                        redo.alloc((size_t)nl + 1);
+                        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(WG), 0, s, redo.get(), (int64_t)1, 0);
                         hipLaunchKernelGGL(k_gram_mfma8, dim3((unsigned)ceil_div(nl, 8)), dim3(WG), 0, s, nl, dlist,
                                            mp.ptr.get(), mp.col.get(), mval.get(), E.pat.ptr.get(),
-                                           E.pat.col.get(), E.val.get(), lam_l, sing.get(), o.ridge);
-                        hipLaunchKernelGGL((k_gram_solve<8>), dim3((unsigned)std::min<int64_t>(nl, 2048)), dim3(WG),
-                                           0, s, nl, dlist, nb, mp.ptr.get(), mp.col.get(), mval.get(),
-                                           E.pat.ptr.get(), E.pat.col.get(), E.val.get(), lam_l, sing.get(), o.ridge,
-                                           (const int32_t *)sing.get());
+                                           E.pat.col.get(), E.val.get(), lam_l, sing.get(), redo.get(), o.ridge);
+                        hipLaunchKernelGGL((k_gram_solve<8>), dim3(256), dim3(WG), 0, s, nl, dlist, nb, mp.ptr.get(),
+                                           mp.col.get(), mval.get(), E.pat.ptr.get(), E.pat.col.get(), E.val.get(),
+                                           lam_l, sing.get(), o.ridge, (const int32_t *)redo.get());
                         break;
                     case 16:
                         hipLaunchKernelGGL(k_gram_mfma, dim3(nl), dim3(WG), 0, s, dlist, mp.ptr.get(),
