@@ -2838,7 +2838,7 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
                     case 4: go(std::integral_constant<int, 4>{}); break;
                     case 8:
                         // matrix cores, then the rows they flag through the minimum-norm path
-                        redo.alloc((size_t)nl + 1);
+                        if (redo.n < (size_t)nl + 1) redo.alloc((size_t)nl + 1);   // grow only: a free syncs
                         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(WG), 0, s, redo.get(), (int64_t)1, 0);
                         hipLaunchKernelGGL(k_gram_mfma8, dim3((unsigned)ceil_div(nl, 8)), dim3(WG), 0, s, nl, dlist,
                                            mp.ptr.get(), mp.col.get(), mval.get(), E.pat.ptr.get(),
