@@ -325,13 +325,13 @@ cs_status cs_autotune(cs_ctx ctx, int32_t nrhs, int32_t *wgs, int64_t *grid, dou
 cs_status cs_set_graphs(cs_ctx ctx, int32_t on);
 cs_status cs_get_graphs(cs_ctx ctx, int32_t *on, double *eager_ms, double *graph_ms);
 
-/* Single-workgroup tail V-cycle (Alg. 1 on the coarse levels).  The levels
- * below a few thousand rows cost a kernel launch per sweep, transfer and
- * direct solve while moving almost no data; from the first level l >= 1 at
- * which every level has at most max_rows rows, the whole V-cycle below is one
- * launch of one 1024-thread workgroup that runs the same per-row arithmetic
- * with workgroup barriers in place of kernel boundaries, so results are
- * bit-identical to the per-level launches.  It applies to additive cascades
+/* Single-workgroup tail V-cycle (Alg. 1 on the small levels).  Levels below a
+ * few thousand rows cost a kernel launch per sweep, transfer and direct solve
+ * while moving almost no data; from the first level (the finest included) at
+ * which every level has at most max_rows rows, the V-cycle from there down is
+ * one launch of one workgroup of 512-1024 threads that runs the same per-row
+ * arithmetic with workgroup barriers in place of kernel boundaries, so results
+ * are bit-identical to the per-level launches.  It applies to additive cascades
  * with fused aggregation transfers, one block size of 1, 2, 4 or 8 on the
  * covered levels, n_pre >= 1 and n_post >= 1; other hierarchies run the
  * per-level launches.  max_rows 0 switches it off (the default).  One

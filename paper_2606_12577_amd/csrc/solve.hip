@@ -1732,20 +1732,20 @@ void direct_solve(Ctx &c, const Level &L, const T *b, T *x) {
 
 }  // namespace
 
-// The coarse levels the tail kernel covers: the first level l >= 1 from
-// which every level has at most c.tail_rows rows, every smoothed one is
+// The levels the tail kernel covers: the first level l (the finest included)
+// from which every level has at most c.tail_rows rows, every smoothed one is
 // additive (no overlapping blocks) with fused transfers and one common block
 // size of 1, 2, 4 or 8, and the cycle pre- and post-smooths (the first
 // post-smoothing sweep carries the interpolation); -1 when there is none.
 int tail_start(const Ctx &c) {
     const int nl = (int)c.lv.size();
-    if (c.tail_rows <= 0 || nl < 3 || c.opt.mode != CS_ADDITIVE || !c.fuse_transfers || c.opt.n_pre < 1 ||
+    if (c.tail_rows <= 0 || nl < 2 || c.opt.mode != CS_ADDITIVE || !c.fuse_transfers || c.opt.n_pre < 1 ||
         c.opt.n_post < 1)
         return -1;
     const int64_t nb = c.lv[nl - 2].nb;
     if (nb != 1 && nb != 2 && nb != 4 && nb != 8) return -1;
     int from = -1;
-    for (int l = nl - 1; l >= 1; --l) {
+    for (int l = nl - 1; l >= 0; --l) {
         const Level &V = c.lv[l];
         bool ok = V.n <= c.tail_rows && !V.ovl_m;
         if (l + 1 < nl) ok = ok && V.agg_k > 0 && V.depth >= 1 && V.nb == nb && V.n_active > 0;
@@ -1817,6 +1817,7 @@ void tail_table(Ctx &c, int nrhs) {
 template <typename T, int R>
 bool issue_first_sweep(Ctx &c) {
     if (c.lv.size() < 2 || c.opt.mode != CS_ADDITIVE || c.opt.n_pre < 1) return false;
+    if (c.tail_from == 0) return false;   // the whole V-cycle is one tail launch
     Level &L = c.lv[0];
     if (L.ovl_m || L.depth < 1) return false;
     const bool reverse = c.opt.order == CS_RF;
@@ -1830,7 +1831,7 @@ bool issue_first_sweep(Ctx &c) {
 
 template <typename T, int R>
 void vcycle_level(Ctx &c, int l) {
-    if (l > 0 && l == c.tail_from && c.tail_gen == c.gen && c.tail_prec == c.precision && c.tail_nrhs == R) {
+    if (l == c.tail_from && c.tail_gen == c.gen && c.tail_prec == c.precision && c.tail_nrhs == R) {
         const int nlev = (int)c.lv.size() - l;
         hipEvent_t ev0 = nullptr, ev1 = nullptr;
         const int slot = trace_begin_launch(c, CS_TRACE_TAIL, c.tail_bytes, &ev0, &ev1);
@@ -1980,6 +1981,7 @@ void ensure_workspace(Ctx &c, int nrhs) {
     c.ws_nrhs = nrhs;
     c.gen++;
     c.ws_prec = prec;
+    prepare_tail(c, nrhs);
 }
 
 static void vcycle_run(Ctx &c, const double *b, double *x, int nrhs) {
@@ -2342,11 +2344,11 @@ void tune_graphs(Ctx &c, int nrhs, double *eager_ms, double *graph_ms) {
 
 // The tail V-cycle's size limit, picked by measurement: one V-cycle is timed
 // (median of five) with the tail off and with every limit that starts it at
-// another level (the sizes of levels 1.. of at most 65536 rows); the fastest
+// another level (the sizes of the levels of at most 65536 rows); the fastest
 // is kept.  ms[k] / rows[k] receive the candidates' times and limits.
 int tune_tail(Ctx &c, int nrhs, int64_t *rows, double *ms, int cap) {
     std::vector<int64_t> cand{0};
-    for (size_t l = 1; l < c.lv.size(); ++l)
+    for (size_t l = 0; l < c.lv.size(); ++l)
         if (c.lv[l].n <= 65536 && std::find(cand.begin(), cand.end(), c.lv[l].n) == cand.end())
             cand.push_back(c.lv[l].n);
     const int64_t keep = c.tail_rows;

@@ -23,7 +23,7 @@ def _vcycle(s, b, tail):
 def _check_vcycle(s, b, label):
     s.set_tail(4096)
     m, first = s.tail()
-    assert m == 4096 and first >= 1, (label, first)   # the tail is in use
+    assert m == 4096 and first >= 0, (label, first)   # the tail is in use
     x0 = _vcycle(s, b, 0)
     x1 = _vcycle(s, b, 4096)
     x2 = _vcycle(s, b, 4096)   # the table is reused
@@ -47,10 +47,22 @@ def test_tail_vcycle_blocks8_3d(gpu_lib, precision, nrhs):
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_tail_vcycle_points_2d(gpu_lib, precision):
-    p = fd.poisson2d(64, nrhs=2)
+    p = fd.poisson2d(64, nrhs=2)   # levels of 4096, 1024, 256, 64 and 16 rows
     s = gpu_lib.Solver(p.levels)
     s.setup(depth=3, precision=precision)
-    _check_vcycle(s, p.rhs, f"poisson2d_64 {precision}")
+    assert _check_vcycle(s, p.rhs, f"poisson2d_64 {precision}") == 0   # the whole V-cycle in one launch
+    s.set_tail(1024)
+    assert s.tail()[1] == 1
+    x0 = _vcycle(s, p.rhs, 0)
+    np.testing.assert_array_equal(_vcycle(s, p.rhs, 1024), x0)
+    for method in ("ir", "cg"):   # with the tail from level 0 the refinement issues no early sweep
+        s.set_tail(0)
+        xa, ia = s.solve(p.rhs, rtol=1e-10, maxit=100, method=method)
+        s.set_tail(4096)
+        xb, ib = s.solve(p.rhs, rtol=1e-10, maxit=100, method=method)
+        assert ib["iterations"] == ia["iterations"]
+        np.testing.assert_array_equal(xb.cpu().numpy(), xa.cpu().numpy())
+        np.testing.assert_array_equal(ib["history"], ia["history"])
     s.close()
 
 
