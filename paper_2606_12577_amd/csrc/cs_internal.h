@@ -172,6 +172,10 @@ struct Level {
     int64_t dseg_max = 0;
     // BF16 block copies for 16x16 blocks (MFMA operand order), block-CSR of A
     DBuf<int32_t> bsr_ptr, bsr_col;
+    std::vector<int32_t> h_bsr_ptr;   // host copy of bsr_ptr
+    // per active block in colour order (cblk): {block row, first block, end
+    // block, 0}, so a colour sweep reads one 16-byte record per block row
+    DBuf<int32_t> bmeta;
     int64_t bsr_nnzb = 0;
     DBuf<unsigned short> a16, lam16, lam16T;
     DBuf<int32_t> cblk;               // active blocks grouped by colour
@@ -308,6 +312,7 @@ int trace_begin_launch(Ctx &c, int cls, double bytes, hipEvent_t *start, hipEven
 int trace_begin_run(Ctx &c, int cls, double bytes, int launches);
 void trace_end_run(Ctx &c, int slot);
 double bf16_sweep_bytes(const Level &L, int colour, bool zero);
+void build_bf16_meta(Ctx &c, Level &L, const std::vector<int32_t> &act);
 void trace_end(Ctx &c, int slot);
 void trace_flush(Ctx &c);
 void trace_release(Ctx &c);

@@ -2472,6 +2472,7 @@ void build_colour_layout(Ctx &c, Level &L) {
         L.cblk_ptr[k + 1] = (int64_t)act.size();
     }
     L.cblk.upload(act.data(), act.size(), c.stream);
+    build_bf16_meta(c, L, act);
     for (int k = 0; k < chi; ++k) {
         std::vector<int32_t> rows;
         rows.reserve((L.cptr[k + 1] - L.cptr[k]) * L.nb);
