@@ -28,6 +28,16 @@ struct Error {
 
 #define CS_LAUNCH_CHECK() CS_HIP(hipGetLastError())
 
+// Map the hardware workgroup id (of G) to a logical index so that each of the
+// 8 XCDs (which receive workgroups round-robin) works through one contiguous
+// range: neighbouring rows, which read the same gathered data, then run on the
+// same XCD and share its L2.  A bijection of [0, G).
+__device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t G) {
+    const int64_t xcd = bid & 7, idx = bid >> 3;
+    const int64_t per = G >> 3, rem = G & 7;
+    return xcd * per + (xcd < rem ? xcd : rem) + idx;
+}
+
 // Device memory cache (pool.hip): blocks are reused across allocations; a
 // freed block is released to the cache after a device synchronisation.
 void *pool_alloc(size_t bytes);   // throws CS_ENOMEM

@@ -128,7 +128,7 @@ __global__ __launch_bounds__(WG) void k_union(const int32_t *__restrict__ list, 
     __shared__ int32_t offs[257];
     __shared__ int32_t part[WG + 1];
     __shared__ int32_t total_s;
-    const int li = blockIdx.x;
+    const int li = (int)xcd_tile(blockIdx.x, gridDim.x);   // rows of a range share the XCD's L2
     if (li >= nlist) return;
     const int i = list ? list[li] : li;
     const int t = threadIdx.x;
@@ -238,7 +238,7 @@ __global__ __launch_bounds__(WG) void k_union_wave(const int32_t *__restrict__ l
     constexpr int P = 64 * K;
     __shared__ int32_t offs_s[WG / 64][65], start_s[WG / 64][64];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int li = blockIdx.x * (WG / 64) + wv;
+    const int li = (int)xcd_tile(blockIdx.x, gridDim.x) * (WG / 64) + wv;   // see k_union
     const bool live = li < nlist;
     const int i = live ? (list ? list[li] : li) : 0;
     int total = 0, lo = 0, deg = 0;
@@ -420,7 +420,7 @@ __global__ __launch_bounds__(WG) void k_rowprod(const int32_t *__restrict__ list
                                                 const int32_t *__restrict__ mptr, const int32_t *__restrict__ mcol,
                                                 double *__restrict__ mval) {
     __shared__ int32_t match[MATCH_CAP];
-    const int li = blockIdx.x;
+    const int li = (int)xcd_tile(blockIdx.x, gridDim.x);   // see k_rowprod_nb
     const int i = list[li];
     const int t = threadIdx.x;
     const int alo = abptr[i], deg = abptr[i + 1] - alo;
@@ -460,7 +460,10 @@ __global__ __launch_bounds__(WG) void k_rowprod(const int32_t *__restrict__ list
 // E entry is read from memory once per (p, j) instead of NB times, and the
 // A~ values come from LDS as wavefront broadcasts.
 constexpr int AS_CAP = 2048;   // doubles of A~ staged per row (deg * NB^2)
-constexpr int MATCH_NB = 4096; // (column, neighbour) matches cached per row
+constexpr int MATCH_NB = 2048; // (column, neighbour) matches cached per row
+constexpr int ECOL_CAP = 1920; // column indices of the neighbours' E rows staged per row
+constexpr int DEG_CAP = 32;    // neighbours whose E column lists are staged
+// (LDS per workgroup within 32 KB: five workgroups per CU, as the registers allow)
 
 template <int NB>
 __global__ __launch_bounds__(WG) void k_rowprod_nb(const int32_t *__restrict__ list,
@@ -473,25 +476,61 @@ __global__ __launch_bounds__(WG) void k_rowprod_nb(const int32_t *__restrict__ l
     constexpr int NB2 = NB * NB;
     __shared__ int32_t match[MATCH_NB];
     __shared__ __align__(16) double As[AS_CAP];
-    const int li = blockIdx.x;
+    // consecutive rows on one XCD: the E_j rows gathered by a row are gathered
+    // again by its neighbours, which then find them in that XCD's L2 (with the
+    // hardware's round-robin order neighbours ran on different XCDs; the
+    // 128^3 problem's largest launch fetched 44.5 GB against 8.5 GB of E)
+    const int li = (int)xcd_tile(blockIdx.x, gridDim.x);
     const int i = list[li];
     const int t = threadIdx.x;
     const int alo = abptr[i], deg = abptr[i + 1] - alo;
     const int mlo = mptr[li], k = mptr[li + 1] - mlo;
     const bool cached = (int64_t)k * deg <= MATCH_NB;   // uniform per workgroup
     const bool staged = deg * NB2 <= AS_CAP;
-    if (cached)
-        for (int e = t; e < k * deg; e += WG) {
-            const int p = e / deg, jj = e % deg;
-            const int j = abcol[alo + jj];
-            match[e] = bsearch_i32(ecol, eptr[j], eptr[j + 1], mcol[mlo + p]);
-        }
     // staged blocks are stored transposed (column u of A~_ij contiguous), so one
     // 16-byte LDS read feeds two rows of the product
     if (staged)
         for (int e = t; e < deg * NB2; e += WG) {
             const int jj = e / NB2, rs = e % NB2;
             As[jj * NB2 + (rs % NB) * NB + rs / NB] = abval[(int64_t)alo * NB2 + e];
+        }
+    // The neighbours' E column lists, concatenated in LDS with one coalesced
+    // read, so that the k * deg searches of the matches run in LDS instead of
+    // as chains of dependent global loads (the same positions either way).
+    __shared__ int32_t ecs[ECOL_CAP];
+    __shared__ int32_t eoff[DEG_CAP + 1], elo_s[DEG_CAP];
+    bool ecols = false;   // uniform
+    if (cached && deg <= DEG_CAP) {
+        if (t < deg) {
+            const int j = abcol[alo + t];
+            elo_s[t] = eptr[j];
+            eoff[t + 1] = eptr[j + 1] - eptr[j];
+        }
+        if (t == 0) eoff[0] = 0;
+        __syncthreads();
+        if (t == 0)
+            for (int jj = 0; jj < deg; ++jj) eoff[jj + 1] += eoff[jj];
+        __syncthreads();
+        const int tot = eoff[deg];
+        ecols = tot <= ECOL_CAP;
+        if (ecols)
+            for (int e = t; e < tot; e += WG) {
+                int jj = 0;
+                while (eoff[jj + 1] <= e) ++jj;
+                ecs[e] = ecol[elo_s[jj] + e - eoff[jj]];
+            }
+        __syncthreads();
+    }
+    if (cached)
+        for (int e = t; e < k * deg; e += WG) {
+            const int p = e / deg, jj = e % deg;
+            if (ecols) {
+                const int r = bsearch_i32(ecs, eoff[jj], eoff[jj + 1], mcol[mlo + p]);
+                match[e] = r < 0 ? -1 : elo_s[jj] + (r - eoff[jj]);
+            } else {
+                const int j = abcol[alo + jj];
+                match[e] = bsearch_i32(ecol, eptr[j], eptr[j + 1], mcol[mlo + p]);
+            }
         }
     __syncthreads();
     if constexpr (NB % 2 == 0) {
@@ -931,6 +970,7 @@ __global__ __launch_bounds__(WG) void k_gram_mfma(const int32_t *__restrict__ li
 // and is appended to redo_list (count in redo_list[0], rows from index 1) for
 // k_gram_solve's minimum-norm path.
 constexpr int QCAP8 = 512;
+constexpr int ECAP8 = 128;   // E_i column lists staged per row in k_gram_mfma8
 
 __global__ __launch_bounds__(WG) void k_gram_mfma8(int nl, const int32_t *__restrict__ list,
                                                    const int32_t *__restrict__ mptr, const int32_t *__restrict__ mcol,
@@ -961,10 +1001,33 @@ __global__ __launch_bounds__(WG) void k_gram_mfma8(int nl, const int32_t *__rest
         rek[t] = d;
     }
     __syncthreads();
-    for (int sr = 0; sr < ROWS; ++sr) {
-        const int kk = min(rk[sr], QCAP8);
-        for (int p = t; p < kk; p += WG)
-            qpos[sr][p] = bsearch_i32(ecol, relo[sr], relo[sr] + rek[sr], mcol[rmlo[sr] + p]);
+    // The positions of M_i's block columns in E_i, for the eight rows at once:
+    // E_i's column lists are staged in LDS with coalesced reads, so the
+    // searches run in LDS instead of as chains of dependent global loads.
+    __shared__ int32_t ecs8[ROWS][ECAP8];
+    __shared__ int32_t qoff[ROWS + 1];
+    for (int e = t; e < ROWS * ECAP8; e += WG) {
+        const int sr = e / ECAP8, q = e % ECAP8;
+        if (q < rek[sr] && rek[sr] <= ECAP8) ecs8[sr][q] = ecol[relo[sr] + q];
+    }
+    if (t == 0) {
+        qoff[0] = 0;
+        for (int sr = 0; sr < ROWS; ++sr) qoff[sr + 1] = qoff[sr] + min(rk[sr], QCAP8);
+    }
+    __syncthreads();
+    for (int e = t; e < qoff[ROWS]; e += WG) {
+        int sr = 0;
+        while (qoff[sr + 1] <= e) ++sr;
+        const int p = e - qoff[sr];
+        const int key = mcol[rmlo[sr] + p];
+        int q;
+        if (rek[sr] <= ECAP8) {
+            q = bsearch_i32(ecs8[sr], 0, rek[sr], key);
+            if (q >= 0) q += relo[sr];
+        } else {
+            q = bsearch_i32(ecol, relo[sr], relo[sr] + rek[sr], key);
+        }
+        qpos[sr][p] = q;
     }
     __syncthreads();
     const int mlo = rmlo[slot], k = rk[slot], elo = relo[slot], ek = rek[slot];
@@ -1065,7 +1128,8 @@ __global__ __launch_bounds__(WG) void k_rowprod_point(int nl, const int32_t *__r
                                                       const double *__restrict__ eval,
                                                       const int32_t *__restrict__ mptr,
                                                       const int32_t *__restrict__ mcol, double *__restrict__ mval) {
-    const int w = blockIdx.x * (WG / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    // see k_rowprod_nb for the order of the rows
+    const int w = (int)xcd_tile(blockIdx.x, gridDim.x) * (WG / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (w >= nl) return;
     const int i = list[w];
     const int alo = abptr[i], deg = abptr[i + 1] - alo;

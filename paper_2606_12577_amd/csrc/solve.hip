@@ -70,15 +70,6 @@ __device__ __forceinline__ void vstore(T *p, const T (&o)[R]) {
     }
 }
 
-// Map the hardware workgroup id to a logical tile so that each of the 8 XCDs
-// (which receive workgroups round-robin) works on one contiguous range of
-// rows, keeping gathered x in that XCD's L2.
-__device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t G) {
-    const int64_t xcd = bid & 7, idx = bid >> 3;
-    const int64_t per = G >> 3, rem = G & 7;
-    return xcd * per + (xcd < rem ? xcd : rem) + idx;
-}
-
 // Tiles (256 rows each) handled by this workgroup.  With a workgroup per tile
 // the hardware id is remapped by xcd_tile; with fewer workgroups (a multiple
 // of 8, resident all at once) each XCD sweeps one contiguous range of tiles
