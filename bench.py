@@ -445,6 +445,19 @@ def bench_c1():
     return out
 
 
+def stream_reference(s, nbytes=1 << 30, reps=10):
+    """GB/s of plain streaming kernels on this device (cs_stream_bandwidth, 1 GiB
+    per array): the rate HBM gives without the method's arithmetic, beside the
+    published peak.  4r1w reads four arrays per one written, the cascade sweep's
+    mix (it reads about 4.7 bytes per byte it writes)."""
+    out = {}
+    for name, (nr, nw) in (("read", (1, 0)), ("write", (0, 1)), ("copy", (1, 1)), ("4r1w", (4, 1))):
+        out[name] = round(s.stream_bandwidth(nr, nw, nbytes, reps)[0], 1)
+    out["unit"] = "GB/s"
+    out["arrays_bytes"] = nbytes
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -459,6 +472,8 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-baseline", action="store_true")
+    ap.add_argument("--no-stream-reference", action="store_true",
+                    help="skip the streaming-bandwidth reference reported beside the roofline")
     ap.add_argument("--no-trace", action="store_true", help="do not time the sweep kernel with events")
     ap.add_argument("--trace-period", type=int, default=8,
                     help="time every n-th launch of the sweep kernel with HIP events")
@@ -574,6 +589,9 @@ def main():
             algorithmic_bytes_per_launch=int(bytes_per_launch),
             rocprof_avg_us=rp_us,
             frac_rocprof=(round(bytes_per_launch / (rp_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4) if rp_us else None))
+        if not args.no_stream_reference:
+            roofline["attainable"] = stream_reference(s)
+            roofline["frac_of_attainable"] = round(achieved / roofline["attainable"]["4r1w"], 4)
 
     extra = {}
     runs = {}   # (precision, method) -> info of the last of two solves on the same setup

@@ -373,6 +373,20 @@ typedef enum {
 cs_status cs_trace(cs_ctx ctx, int32_t mask, int32_t period);
 cs_status cs_trace_read(cs_ctx ctx, int32_t cls, double *total_ms, int64_t *launches, double *bytes);
 
+/* Streaming reference for the roofline figures above: the HBM rate that plain
+ * kernels reach on this device when they only stream arrays (no arithmetic of
+ * the method).  Allocates n_read + n_write arrays of `bytes` bytes each on the
+ * context's device (freed before returning), fills them, then times `reps`
+ * launches on the context's stream that read n_read arrays (0-4) and write
+ * n_write (0 or 1) of them, one 16-byte element per thread.  Outputs (host,
+ * each may be NULL): *gbps = bytes * (n_read + n_write) / average launch time,
+ * in GB/s; *us = the average launch time in microseconds.  Synchronises the
+ * device.  Errors: CS_EINVAL for counts out of range, bytes not a positive
+ * multiple of 16 or above 64 GiB, reps < 1; CS_EDEVICE when the arrays do not
+ * fit in device memory. */
+cs_status cs_stream_bandwidth(cs_ctx ctx, int32_t n_read, int32_t n_write, int64_t bytes, int32_t reps,
+                              double *gbps, double *us);
+
 /* Independent systems sharing one hierarchy (a batch): row_ptr[0..nsys] cuts
  * the finest level into the systems' row ranges (host array, increasing, 0 to
  * n).  cs_solve then measures every (system, right-hand side) residual

@@ -78,6 +78,7 @@ SIGNATURES = {
     "cs_get_graphs": (_I32, [_VP, _p(_I32), _p(_D), _p(_D)]),
     "cs_set_tail": (_I32, [_VP, _I64]),
     "cs_get_tail": (_I32, [_VP, _p(_I64), _p(_I32), _I32, _p(_I64), _p(_D), _p(_I32)]),
+    "cs_stream_bandwidth": (_I32, [_VP, _I32, _I32, _I64, _I32, _p(_D), _p(_D)]),
     "cs_solve": (_I32, [_VP, _VP, _VP, _I32, _D, _I32, _p(cs_info), _p(_D)]),
     "cs_solve_cg": (_I32, [_VP, _VP, _VP, _I32, _D, _I32, _p(cs_info), _p(_D)]),
     "cs_solve_gmres": (_I32, [_VP, _VP, _VP, _I32, _D, _I32, _I32, _I32, _p(cs_info), _p(_D)]),
@@ -479,6 +480,14 @@ class Solver:
         self._check(self._lib.cs_get_tail(self._h, ctypes.byref(m), ctypes.byref(f), cap, _ptr(rows, _I64),
                                           _ptr(ms, _D), ctypes.byref(n)))
         return [(int(r), float(t)) for r, t in zip(rows[:n.value], ms[:n.value])]
+
+    def stream_bandwidth(self, n_read: int, n_write: int, nbytes: int, reps: int = 20):
+        """Streaming reference: (GB/s, us per launch) of plain kernels that read
+        n_read and write n_write arrays of nbytes each on this device."""
+        g, u = ctypes.c_double(), ctypes.c_double()
+        self._check(self._lib.cs_stream_bandwidth(self._h, n_read, n_write, int(nbytes), reps, ctypes.byref(g),
+                                                  ctypes.byref(u)))
+        return g.value, u.value
 
     def trace(self, classes=("sweep",), period: int = 1):
         """Start (clearing the counters) event timing of every period-th launch

@@ -745,6 +745,11 @@ cs_status cs_get_tail(cs_ctx ctx, int64_t *max_rows, int32_t *first_level, int32
     });
 }
 
+cs_status cs_stream_bandwidth(cs_ctx ctx, int32_t n_read, int32_t n_write, int64_t bytes, int32_t reps,
+                              double *gbps, double *us) {
+    return guarded(ctx, [&](Ctx &c) { cs::stream_bandwidth(c, n_read, n_write, bytes, reps, gbps, us); });
+}
+
 cs_status cs_solve_gmres(cs_ctx ctx, const double *b, double *x, int32_t nrhs, double rtol, int32_t maxit,
                          int32_t restart, int32_t flexible, cs_info *info, double *history) {
     return solve_escalating(ctx, b, x, maxit, rtol, info, [&](Ctx &c, cs_status *st) {

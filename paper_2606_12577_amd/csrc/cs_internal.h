@@ -359,6 +359,7 @@ void autotune(Ctx &c, int nrhs, double *ms_out);
 void tune_graphs(Ctx &c, int nrhs, double *eager_ms, double *graph_ms);
 int tail_start(const Ctx &c);
 int tune_tail(Ctx &c, int nrhs, int64_t *rows, double *ms, int cap);
+void stream_bandwidth(Ctx &c, int n_read, int n_write, int64_t bytes, int reps, double *gbps, double *us);
 void solve_gmres(Ctx &c, const double *b, double *x, int nrhs, double rtol, int maxit, int restart, bool flexible,
                  cs_info *info, double *history, cs_status *st);
 
