@@ -458,6 +458,50 @@ def stream_reference(s, nbytes=1 << 30, reps=10):
     return out
 
 
+SOLVE_KERNELS = ("k_sweep", "k_ir_residual", "k_tail_vcycle", "k_residual_restrict", "k_cg_")
+
+
+def summarize_setups(path: str, first: int = 1, count: int = 3, top: int = 16) -> str:
+    """Per-kernel time inside the setups of a rocprofv3 kernel trace.  A setup is
+    the stretch from a k_prescale_w launch (the first kernel of a setup) to the
+    last kernel before the next solve kernel; the table averages setups
+    first .. first + count - 1 (0-based; the default skips the warm-up's)."""
+    import csv
+    from collections import Counter, defaultdict
+    with open(path, newline="") as f:
+        rows = [r for r in csv.DictReader(f) if r.get("Kind", "KERNEL_DISPATCH") == "KERNEL_DISPATCH"]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    wins, cur, last_end = [], None, 0
+    for r in rows:
+        name = _short_kernel(r["Kernel_Name"])
+        if cur is None:
+            if not name.startswith("k_prescale_w"):
+                continue
+            cur = dict(t0=int(r["Start_Timestamp"]), ms=defaultdict(float), calls=Counter())
+        elif name.startswith(SOLVE_KERNELS):
+            cur["t1"] = last_end
+            wins.append(cur)
+            cur = None
+            continue
+        cur["ms"][name] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6
+        cur["calls"][name] += 1
+        last_end = int(r["End_Timestamp"])
+    sel = wins[first:first + count]
+    if not sel:
+        return f"{path}: {len(wins)} setups, none selected\n"
+    tot = defaultdict(float)
+    for w in sel:
+        for k, v in w["ms"].items():
+            tot[k] += v / len(sel)
+    span = sum((w["t1"] - w["t0"]) * 1e-6 for w in sel) / len(sel)
+    out = [f"{len(wins)} setups in the trace; setups {first}-{first + len(sel) - 1}: span {span:.2f} ms, "
+           f"kernel time {sum(tot.values()):.2f} ms per setup", "",
+           "| kernel | calls per setup | ms per setup |", "|---|---|---|"]
+    for k, v in sorted(tot.items(), key=lambda kv: -kv[1])[:top]:
+        out.append(f"| `{k}` | {sel[0]['calls'][k]} | {v:.2f} |")
+    return "\n".join(out) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -492,9 +536,14 @@ def main():
     ap.add_argument("--no-dg", action="store_true", help="skip the SIPG Q3 256^2 measurement")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
+    ap.add_argument("--summarize-setups", metavar="CSV",
+                    help="print the per-kernel time inside the setups of a rocprofv3 kernel trace and exit")
     ap.add_argument("--summarize", nargs="+", metavar="CSV",
                     help="print a markdown summary of rocprofv3 kernel-trace or counter CSVs and exit")
     args = ap.parse_args()
+    if args.summarize_setups:
+        print(summarize_setups(args.summarize_setups))
+        return
     if args.summarize:
         for path in args.summarize:
             print(f"### {os.path.basename(os.path.dirname(path))}/{os.path.basename(path)}\n")

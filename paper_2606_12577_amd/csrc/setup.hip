@@ -1033,24 +1033,36 @@ __global__ __launch_bounds__(WG) void k_gram_mfma8(int nl, const int32_t *__rest
     const int mlo = rmlo[slot], k = rk[slot], elo = relo[slot], ek = rek[slot];
     const int kmax = max(rk[2 * wave], rk[2 * wave + 1]);   // wave-uniform trip count
     d4_t dg = {0.0, 0.0, 0.0, 0.0}, dh = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 2
-    for (int p = 0; p < kmax; ++p) {
-        double am0 = 0.0, am1 = 0.0, ae0 = 0.0, ae1 = 0.0;
-        if (p < k) {
-            const int q = p < QCAP8 ? qpos[slot][p] : bsearch_i32(ecol, elo, elo + ek, mcol[mlo + p]);
-            const double *mb = mval + (int64_t)(mlo + p) * NB2 + rr * NB;
-            am0 = mb[cq];
-            am1 = mb[4 + cq];
-            if (q >= 0) {
-                const double *eb = eval + (int64_t)q * NB2 + rr * NB;
-                ae0 = eb[cq];
-                ae1 = eb[4 + cq];
+    // PB block columns per pass: their M and E loads are all issued before the
+    // first product (one memory round trip per pass instead of per column); the
+    // products run in column order as one at a time would
+    constexpr int PB = 8;
+    for (int p0 = 0; p0 < kmax; p0 += PB) {
+        double am0[PB], am1[PB], ae0[PB], ae1[PB];
+#pragma unroll
+        for (int u = 0; u < PB; ++u) {
+            const int p = p0 + u;
+            am0[u] = am1[u] = ae0[u] = ae1[u] = 0.0;
+            if (p < k) {
+                const int q = p < QCAP8 ? qpos[slot][p] : bsearch_i32(ecol, elo, elo + ek, mcol[mlo + p]);
+                const double *mb = mval + (int64_t)(mlo + p) * NB2 + rr * NB;
+                am0[u] = mb[cq];
+                am1[u] = mb[4 + cq];
+                if (q >= 0) {
+                    const double *eb = eval + (int64_t)q * NB2 + rr * NB;
+                    ae0[u] = eb[cq];
+                    ae1[u] = eb[4 + cq];
+                }
             }
         }
-        dg = __builtin_amdgcn_mfma_f64_16x16x4f64(am0, am0, dg, 0, 0, 0);
-        dh = __builtin_amdgcn_mfma_f64_16x16x4f64(ae0, am0, dh, 0, 0, 0);
-        dg = __builtin_amdgcn_mfma_f64_16x16x4f64(am1, am1, dg, 0, 0, 0);
-        dh = __builtin_amdgcn_mfma_f64_16x16x4f64(ae1, am1, dh, 0, 0, 0);
+#pragma unroll
+        for (int u = 0; u < PB; ++u) {
+            if (p0 + u >= kmax) break;   // wave-uniform
+            dg = __builtin_amdgcn_mfma_f64_16x16x4f64(am0[u], am0[u], dg, 0, 0, 0);
+            dh = __builtin_amdgcn_mfma_f64_16x16x4f64(ae0[u], am0[u], dh, 0, 0, 0);
+            dg = __builtin_amdgcn_mfma_f64_16x16x4f64(am1[u], am1[u], dg, 0, 0, 0);
+            dh = __builtin_amdgcn_mfma_f64_16x16x4f64(ae1[u], am1[u], dh, 0, 0, 0);
+        }
     }
     // result lane l, register x = D[4x + l/16][l%16]: this lane's half owns
     // registers 2 half and 2 half + 1 of its own column
@@ -1641,10 +1653,25 @@ __global__ __launch_bounds__(WG) void k_eupdate(int B, int nb_rt, const int32_t 
         return;
     }
     const int mlo = mptr[li], k = mptr[li + 1] - mlo;
+    // E_i's column list staged in LDS (one coalesced read), so that the k
+    // position searches run in LDS instead of as chains of global loads
+    constexpr int ECAP_U = NBT == 1 ? 64 : 512;
+    __shared__ int32_t ecs[ECAP_U];
+    const bool ecols = ek <= ECAP_U;   // uniform
+    if (ecols)
+        for (int q = t; q < ek; q += WG) ecs[q] = ecol[elo + q];
+    __syncthreads();
     for (int p = t; p < k; p += WG) {
         const int32_t c = mcol[mlo + p];
         ncol[nlo + p] = c;
-        if (k <= QCAP) qpos[p] = bsearch_i32(ecol, elo, elo + ek, c);
+        if (k <= QCAP) {
+            if (ecols) {
+                const int r = bsearch_i32(ecs, 0, ek, c);
+                qpos[p] = r < 0 ? -1 : elo + r;
+            } else {
+                qpos[p] = bsearch_i32(ecol, elo, elo + ek, c);
+            }
+        }
     }
     __syncthreads();
     const double *L = lamt + (int64_t)i * nb2;

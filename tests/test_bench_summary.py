@@ -70,3 +70,30 @@ def test_counter_summary_means_max_and_sums(tmp_path):
     assert abs(float(sweep[8]) - 65.0) < 1e-9
     copy = [l for l in body if "copyBuffer" in l][0].split("|")
     assert copy[6].strip() == "524320"
+
+
+def test_setup_windows(tmp_path):
+    # three setups (prescale ... E update) each followed by a solve kernel
+    rows, t = [], 0
+
+    def add(name, dt):
+        nonlocal t
+        rows.append(dict(Kind="KERNEL_DISPATCH", Kernel_Name=f"void cs::(anonymous namespace)::{name}(int)",
+                         Start_Timestamp=t, End_Timestamp=t + dt, Grid_Size_X=256, Grid_Size_Y=1, Grid_Size_Z=1))
+        t += dt + 1000
+
+    add("k_sweep<float, 8, 8, false, false, false, 256>", 5000)   # before any setup: ignored
+    for k in range(3):
+        add("k_prescale_w", 1000)
+        add("k_rowprod_nb<8>", 10000 * (k + 1))
+        add("k_eupdate<8>", 2000)
+        add("k_sweep<float, 8, 8, true, false, false, 256>", 5000)
+    p = tmp_path / "run_kernel_trace.csv"
+    _write(p, TRACE_COLS, rows)
+    out = bench.summarize_setups(str(p), first=1, count=2)
+    assert out.startswith("3 setups in the trace; setups 1-2:")
+    body = [l for l in out.splitlines() if l.startswith("| `")]
+    assert body[0] == "| `k_rowprod_nb<8>` | 1 | 0.03 |"     # (20 + 30) / 2 us -> 0.025 ms
+    assert "| `k_eupdate<8>` | 1 | 0.00 |" in body
+    # span: prescale start to E update end = 1000 + 1000 + rowprod + 1000 + 2000
+    assert "span 0.03 ms" in out
