@@ -631,7 +631,7 @@ def main():
             bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
             frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(args),
             kernel=(f"k_sweep<{'float' if args.precision == 'fp32' else 'double'}, 8, {args.nrhs}, "
-                    "false, false, false, 256> (cascade sweep reading A, large levels)"),
+                    "false, false, false, 256, false> (cascade sweep reading A, large levels)"),
             timing=("live: one HIP event pair around every sampled run of consecutive sweeps of the fine level "
                     "on the library's stream; the average over the run's launches includes the gaps between them"),
             launches=sw["launches"], avg_us=round(avg_ms * 1e3, 2),

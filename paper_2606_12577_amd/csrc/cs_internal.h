@@ -276,6 +276,10 @@ struct Ctx {
     // internal work stream; cs_set_graphs, cs_autotune or CS_GRAPHS=1)
     bool use_graphs = false;
     double tune_vcycle_ms[2] = {0.0, 0.0};   // last cs_autotune: V-cycle eager, replayed
+    // set around a refinement V-cycle: its last fine-level sweep adds x_0 into
+    // this FP64 vector (acc_done then true) instead of writing it
+    double *acc_x64 = nullptr;
+    bool acc_done = false;
     // single-workgroup tail V-cycle over the coarse levels of at most tail_rows
     // rows (0: off); its level table, valid for (tail_gen, tail_prec, tail_nrhs)
     int64_t tail_rows = 0;

@@ -275,15 +275,32 @@ __device__ __forceinline__ void spmv_row_nb(const int32_t *__restrict__ scol, co
         spmv_row<T, R, PROL>(scol, sval, off, len, xin, xc, agg_k, acc);
 }
 
+// The sweep's result for a row: stored as x_out, or with ACC added into the
+// FP64 vector acc instead (x_out is not written): the update x += d of an
+// outer refinement folded into the V-cycle's last fine-level sweep, with the
+// same FP64 addition as a separate pass.
+template <typename T, int R, bool ACC>
+__device__ __forceinline__ void sweep_store(T *xout, double *acc, int64_t row, const T (&xo)[R]) {
+    if constexpr (ACC) {
+        double ax[R];
+        vload<double, R>(acc + row * R, ax);
+#pragma unroll
+        for (int k = 0; k < R; ++k) ax[k] += (double)xo[k];
+        vstore<double, R>(acc + row * R, ax);
+    } else {
+        vstore<T, R>(xout + row * R, xo);
+    }
+}
+
 // One tile (WGS/64 slices) of a cascade sweep; red: LDS of WGS * R values
 // (block levels), rewritten per tile.
-template <typename T, int NB, int R, bool ZERO, bool ROWMAP, bool PROL, int WGS>
+template <typename T, int NB, int R, bool ZERO, bool ROWMAP, bool PROL, int WGS, bool ACC = false>
 __device__ __forceinline__ void sweep_tile(int64_t tile, int64_t nrows, int64_t nslices,
                                            const int32_t *__restrict__ rows, const int64_t *__restrict__ sptr,
                                            const int32_t *__restrict__ slen, const int32_t *__restrict__ scol,
                                            const T *__restrict__ sval, const T *__restrict__ lam,
                                            const T *__restrict__ b, const T *xin, T *xout,
-                                           const T *__restrict__ xc, int agg_k, T *red) {
+                                           const T *__restrict__ xc, int agg_k, T *red, double *acc = nullptr) {
     constexpr int SPW = WGS / 64;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t slice = tile * SPW + wv;
@@ -333,7 +350,7 @@ __device__ __forceinline__ void sweep_tile(int64_t tile, int64_t nrows, int64_t 
             }
 #pragma unroll
             for (int k = 0; k < R; ++k) xo[k] -= l * res[k];
-            vstore<T, R>(xout + row * R, xo);
+            sweep_store<T, R, ACC>(xout, acc, row, xo);
         }
     } else {
 #pragma unroll
@@ -347,24 +364,24 @@ __device__ __forceinline__ void sweep_tile(int64_t tile, int64_t nrows, int64_t 
 #pragma unroll
                 for (int k = 0; k < R; ++k) xo[k] -= lr[cc] * red[(base + cc) * R + k];
             }
-            vstore<T, R>(xout + row * R, xo);
+            sweep_store<T, R, ACC>(xout, acc, row, xo);
         }
         __syncthreads();   // red is rewritten by the next tile
     }
 }
 
-template <typename T, int NB, int R, bool ZERO, bool ROWMAP, bool PROL, int WGS>
+template <typename T, int NB, int R, bool ZERO, bool ROWMAP, bool PROL, int WGS, bool ACC = false>
 __global__ __launch_bounds__(WGS) void k_sweep(int64_t nrows, int64_t nslices, const int32_t *__restrict__ rows,
                                                const int64_t *__restrict__ sptr, const int32_t *__restrict__ slen,
                                                const int32_t *__restrict__ scol, const T *__restrict__ sval,
                                                const T *__restrict__ lam, const T *__restrict__ b, const T *xin,
-                                               T *xout, const T *__restrict__ xc, int agg_k) {
+                                               T *xout, const T *__restrict__ xc, int agg_k, double *acc) {
     constexpr int SPW = WGS / 64;
     __shared__ T red[NB > 1 ? WGS * R : 1];
     const Tiles tl = my_tiles((nslices + SPW - 1) / SPW);
     for (int64_t tile = tl.t; tile < tl.end; tile += tl.step)
-        sweep_tile<T, NB, R, ZERO, ROWMAP, PROL, WGS>(tile, nrows, nslices, rows, sptr, slen, scol, sval, lam, b,
-                                                      xin, xout, xc, agg_k, red);
+        sweep_tile<T, NB, R, ZERO, ROWMAP, PROL, WGS, ACC>(tile, nrows, nslices, rows, sptr, slen, scol, sval, lam,
+                                                           b, xin, xout, xc, agg_k, red, acc);
 }
 
 // r = A x - b over SELL rows (natural order)
@@ -1494,9 +1511,12 @@ double sweep_bytes(const Level &L, const Sell &S, bool rowmap, bool zero, bool p
            (zero ? 0.0 : (rowmap ? L.n : nrows) * R * es) + (prol ? (double)L.nc * R * es : 0.0);
 }
 
+// acc (natural order, not from zero, no interpolation): the result is added
+// into that FP64 vector instead of written to xout (sweep_store).
 template <typename T, int R>
 void launch_sweep(Ctx &c, const Level &L, const Sell &S, bool rowmap, bool zero, const T *lam, const T *b,
-                  const T *xin, T *xout, const T *xc = nullptr, int agg_k = 0) {
+                  const T *xin, T *xout, const T *xc = nullptr, int agg_k = 0, double *acc = nullptr) {
+    if (acc && (rowmap || zero || xc)) fail(CS_EINVAL, "accumulating sweep: natural order, not from zero");
     // the natural-order layout is swept over the active rows only (rows of
     // direct segments are solved exactly after the sweeps)
     const int64_t nrows = rowmap ? S.nrows : L.n_active;
@@ -1511,24 +1531,31 @@ void launch_sweep(Ctx &c, const Level &L, const Sell &S, bool rowmap, bool zero,
     const bool prol = xc != nullptr;
     // trace classes by level size (not by the launch shape the autotuner picks)
     const bool large = nslices >= SMALL_SLICES;
-    const int cls = zero ? CS_TRACE_SWEEP_ZERO
-                         : (xc ? CS_TRACE_SWEEP_PROLONG : (large ? CS_TRACE_SWEEP : CS_TRACE_SWEEP_SMALL));
+    const int cls = acc ? CS_TRACE_REFINE   // it carries the refinement's update
+                        : zero ? CS_TRACE_SWEEP_ZERO
+                               : (xc ? CS_TRACE_SWEEP_PROLONG : (large ? CS_TRACE_SWEEP : CS_TRACE_SWEEP_SMALL));
     hipEvent_t ev0 = nullptr, ev1 = nullptr;   // set for a sampled launch: it times itself
-    const int slot = trace_begin_launch(c, cls, sweep_bytes<T, R>(L, S, rowmap, zero, prol), &ev0, &ev1);
+    // an accumulating sweep writes no x_out but reads and writes the FP64 rows
+    const double acc_bytes = acc ? (double)nrows * R * (16.0 - sizeof(T)) : 0.0;
+    const int slot = trace_begin_launch(c, cls, sweep_bytes<T, R>(L, S, rowmap, zero, prol) + acc_bytes, &ev0, &ev1);
     dispatch_nb(L.nb, [&](auto nbc) {
         constexpr int NB = decltype(nbc)::value;
-#define CS_SWEEP(Z, M, P, ROWS)                                                                                     \
-    do {                                                                                                            \
-        if (small)                                                                                                  \
-            hipExtLaunchKernelGGL((k_sweep<T, NB, R, Z, M, P, 64>), dim3(G), dim3(64), 0, c.stream, ev0, ev1, 0,   \
-                                  nrows, nslices, ROWS, S.slice_ptr.get(), S.slice_len.get(), S.col.get(),         \
-                                  sell_val<T>(S), lam, b, xin, xout, xc, agg_k);                                   \
-        else                                                                                                        \
-            hipExtLaunchKernelGGL((k_sweep<T, NB, R, Z, M, P, WG>), dim3(G), dim3(WG), 0, c.stream, ev0, ev1, 0,   \
-                                  nrows, nslices, ROWS, S.slice_ptr.get(), S.slice_len.get(), S.col.get(),         \
-                                  sell_val<T>(S), lam, b, xin, xout, xc, agg_k);                                   \
+#define CS_SWEEP_ACC(Z, M, P, ROWS, A)                                                                                 \
+    do {                                                                                                               \
+        if (small)                                                                                                     \
+            hipExtLaunchKernelGGL((k_sweep<T, NB, R, Z, M, P, 64, A>), dim3(G), dim3(64), 0, c.stream, ev0, ev1, 0,   \
+                                  nrows, nslices, ROWS, S.slice_ptr.get(), S.slice_len.get(), S.col.get(),            \
+                                  sell_val<T>(S), lam, b, xin, xout, xc, agg_k, acc);                                 \
+        else                                                                                                           \
+            hipExtLaunchKernelGGL((k_sweep<T, NB, R, Z, M, P, WG, A>), dim3(G), dim3(WG), 0, c.stream, ev0, ev1, 0,   \
+                                  nrows, nslices, ROWS, S.slice_ptr.get(), S.slice_len.get(), S.col.get(),            \
+                                  sell_val<T>(S), lam, b, xin, xout, xc, agg_k, acc);                                 \
     } while (0)
-        if (rowmap) {
+#define CS_SWEEP(Z, M, P, ROWS) CS_SWEEP_ACC(Z, M, P, ROWS, false)
+        if (acc) {
+            if constexpr (std::is_same<T, double>::value) CS_SWEEP_ACC(false, false, false, nullptr, true);
+            else fail(CS_EINVAL, "accumulating sweep: FP64 working precision only");
+        } else if (rowmap) {
             if (zero) CS_SWEEP(true, true, false, S.rows.get());
             else CS_SWEEP(false, true, false, S.rows.get());
         } else if (zero) {
@@ -1539,6 +1566,7 @@ void launch_sweep(Ctx &c, const Level &L, const Sell &S, bool rowmap, bool zero,
             CS_SWEEP(false, false, false, nullptr);
         }
 #undef CS_SWEEP
+#undef CS_SWEEP_ACC
     });
     CS_LAUNCH_CHECK();
 }
@@ -1601,10 +1629,12 @@ __global__ void k_ovl_fuse(int64_t n, const int32_t *__restrict__ iptr, const in
 
 // One application of the cascade of level L: x <- S(x, b).  Returns the buffer
 // holding the result (additive sweeps alternate between x and alt).  With xc
-// given (additive only), the first sweep reads x - P x_c instead of x.
+// given (additive only), the first sweep reads x - P x_c instead of x.  With
+// acc64 (additive, at least two steps, or one that is neither from zero nor
+// interpolating) the last sweep adds its result into that FP64 vector instead.
 template <typename T, int R>
 T *apply_cascade(Ctx &c, const Level &L, bool reverse, bool zero_start, const T *b, T *x, T *alt,
-                 const T *xc = nullptr, int s_begin = 0) {
+                 const T *xc = nullptr, int s_begin = 0, double *acc64 = nullptr) {
     const int64_t nbl = L.B * L.nb * L.nb;
     const int depth = L.depth;
     if (L.ovl_m) {
@@ -1645,16 +1675,21 @@ T *apply_cascade(Ctx &c, const Level &L, bool reverse, bool zero_start, const T 
         // run (one event pair; a timed single launch pays an end-of-kernel
         // release that the untimed ones do not)
         const int s_run = (s_begin == 0 && (zero_start || xc)) ? 1 : s_begin;
+        const int s_end = acc64 ? depth - 1 : depth;   // an accumulating last sweep is timed on its own
         int run = -1;
         for (int s = s_begin; s < depth; ++s) {
-            if (s == s_run && L.act_slices >= SMALL_SLICES)
+            if (s == s_run && s_run < s_end && L.act_slices >= SMALL_SLICES)
                 run = trace_begin_run(c, CS_TRACE_SWEEP,
-                                      (depth - s_run) * sweep_bytes<T, R>(L, L.sell, false, false, false),
-                                      depth - s_run);
+                                      (s_end - s_run) * sweep_bytes<T, R>(L, L.sell, false, false, false),
+                                      s_end - s_run);
+            if (s == s_end) {
+                trace_end_run(c, run);
+                run = -1;
+            }
             const int ell = reverse ? depth - 1 - s : s;
             const T *lam = lam_ptr<T>(L, reverse) + (int64_t)ell * nbl;
             launch_sweep<T, R>(c, L, L.sell, false, zero_start && s == 0, lam, b, cur, nxt, s == 0 ? xc : nullptr,
-                               L.agg_k);
+                               L.agg_k, s == depth - 1 ? acc64 : nullptr);
             std::swap(cur, nxt);
         }
         trace_end_run(c, run);
@@ -1896,9 +1931,21 @@ void vcycle_level(Ctx &c, int l) {
         CS_LAUNCH_CHECK();
         trace_end(c, slot);
     }
+    // the outer refinement's x += x_0 folded into the last fine-level sweep
+    // (c.acc_x64): only where that sweep is the V-cycle's last write on level
+    // 0 - additive, not the interpolating first post-sweep, no direct segments
+    double *acc = nullptr;
+    if (l == 0 && c.acc_x64 && c.opt.mode == CS_ADDITIVE && !L.ovl_m && L.depth >= 1 && L.dseg.size() <= 1 &&
+        c.opt.n_post >= 1 && !(fuse_prol && c.opt.n_post == 1 && L.depth == 1))
+        acc = c.acc_x64;
     for (int a = 0; a < c.opt.n_post; ++a) {
-        T *res = apply_cascade<T, R>(c, L, false, false, bb, x, alt, (fuse_prol && a == 0) ? xc : nullptr);
+        T *res = apply_cascade<T, R>(c, L, false, false, bb, x, alt, (fuse_prol && a == 0) ? xc : nullptr, 0,
+                                     a == c.opt.n_post - 1 ? acc : nullptr);
         if (res != x) std::swap(x, alt);
+    }
+    if (acc) {
+        c.acc_done = true;   // x_0 is in c.acc_x64, not in xb
+        return;
     }
     if (x != xb) {
         CS_HIP(hipMemcpyAsync(xb, x, na * R * sizeof(T), hipMemcpyDeviceToDevice, c.stream));
@@ -2456,12 +2503,26 @@ void solve_ir(Ctx &c, const double *b, double *x, int nrhs, double rtol, int max
             };
             // one refinement iteration after the check: d = V r, x += d, r = b - A x
             auto iteration = [&]() {
+                // in FP64 the V-cycle's last fine sweep adds d into x where it can
+                // (128^3, 8 RHS: 52.2 -> 49.9 ms); in FP32 the accumulating
+                // sweep holds more registers than the plain one (three waves per
+                // SIMD instead of four) and the solve gained nothing (24.35 vs
+                // 24.39 ms), so FP32 keeps the separate pass
+                struct AccScope {
+                    Ctx &c;
+                    ~AccScope() { c.acc_x64 = nullptr; }   // also when a launch fails
+                } scope{c};
+                c.acc_x64 = std::is_same<T, double>::value ? x : nullptr;
+                c.acc_done = false;
                 vcycle_level<T, R>(c, 0);
-                const int slot = trace_begin(c, CS_TRACE_REFINE, up_bytes);
-                hipLaunchKernelGGL((k_add_to64<T>), dim3(grid_for(n)), dim3(WG), 0, c.stream, n,
-                                   reinterpret_cast<const T *>(L0.w_xb), x);
-                CS_LAUNCH_CHECK();
-                trace_end(c, slot);
+                c.acc_x64 = nullptr;
+                if (!c.acc_done) {
+                    const int slot = trace_begin(c, CS_TRACE_REFINE, up_bytes);
+                    hipLaunchKernelGGL((k_add_to64<T>), dim3(grid_for(n)), dim3(WG), 0, c.stream, n,
+                                       reinterpret_cast<const T *>(L0.w_xb), x);
+                    CS_LAUNCH_CHECK();
+                    trace_end(c, slot);
+                }
                 residual();
             };
             // ||b||^2, x = 0, first residual
