@@ -382,8 +382,9 @@ cs_status cs_trace_read(cs_ctx ctx, int32_t cls, double *total_ms, int64_t *laun
  * each may be NULL): *gbps = bytes * (n_read + n_write) / average launch time,
  * in GB/s; *us = the average launch time in microseconds.  Synchronises the
  * device.  Errors: CS_EINVAL for counts out of range, bytes not a positive
- * multiple of 16 or above 64 GiB, reps < 1; CS_EDEVICE when the arrays do not
- * fit in device memory. */
+ * multiple of 16 or above 64 GiB, reps < 1; CS_ENOMEM when the arrays do not
+ * fit in device memory (they come from, and return to, the context's device
+ * memory cache). */
 cs_status cs_stream_bandwidth(cs_ctx ctx, int32_t n_read, int32_t n_write, int64_t bytes, int32_t reps,
                               double *gbps, double *us);
 
