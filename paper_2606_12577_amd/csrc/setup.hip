@@ -969,7 +969,7 @@ __global__ __launch_bounds__(WG) void k_gram_mfma(const int32_t *__restrict__ li
 // a pivot below the cut-off (or a non-positive diagonal) gets redo[li] = 1
 // and is appended to redo_list (count in redo_list[0], rows from index 1) for
 // k_gram_solve's minimum-norm path.
-constexpr int QCAP8 = 512;
+constexpr int QCAP8 = 256;
 constexpr int ECAP8 = 128;   // E_i column lists staged per row in k_gram_mfma8
 
 __global__ __launch_bounds__(WG) void k_gram_mfma8(int nl, const int32_t *__restrict__ list,
@@ -1035,8 +1035,10 @@ __global__ __launch_bounds__(WG) void k_gram_mfma8(int nl, const int32_t *__rest
     d4_t dg = {0.0, 0.0, 0.0, 0.0}, dh = {0.0, 0.0, 0.0, 0.0};
     // PB block columns per pass: their M and E loads are all issued before the
     // first product (one memory round trip per pass instead of per column); the
-    // products run in column order as one at a time would
-    constexpr int PB = 8;
+    // products run in column order as one at a time would.  Four (72 VGPRs, and
+    // with 256 positions per row 29 KB of LDS: five waves per SIMD) measured
+    // faster than eight (104 VGPRs, four waves): 128^3 setup 54.8 -> 54.1 ms
+    constexpr int PB = 4;
     for (int p0 = 0; p0 < kmax; p0 += PB) {
         double am0[PB], am1[PB], ae0[PB], ae1[PB];
 #pragma unroll

@@ -139,6 +139,18 @@ def test_interface_setup_parity(gpu_lib, iface32):
     check_patterns(s, sm, p)
 
 
+def test_deep_cascade_long_rows(gpu_lib):
+    """A depth-6 cascade on 16^3 cells (8^3 blocks of 2x2x2): the deepest
+    steps' rows hold up to 302 blocks, more than the 8x8 normal equations keep
+    positions for in LDS (256) and more matches than the row product caches
+    (302 x 7 > 2048), so both search as they go."""
+    p = fd.interface3d(16, nrhs=1)
+    sm = oracle_setup(p, 6)
+    s = gpu_solver(gpu_lib, p, depth=6)
+    check_smoothers(s, sm, p, 6)
+    s.close()
+
+
 @pytest.mark.parametrize("order", ["RF", "FF"])
 def test_interface_vcycle_fp64_and_fp32(gpu_lib, iface32, order):
     p, sm = iface32
