@@ -459,23 +459,31 @@ __global__ __launch_bounds__(WG) void k_rowprod(const int32_t *__restrict__ list
 // thread per (block column p, column s) of M_i computing all NB rows: every
 // E entry is read from memory once per (p, j) instead of NB times, and the
 // A~ values come from LDS as wavefront broadcasts.
-constexpr int AS_CAP = 2048;   // doubles of A~ staged per row (deg * NB^2)
-constexpr int MATCH_NB = 2048; // (column, neighbour) matches cached per row
-constexpr int ECOL_CAP = 1920; // column indices of the neighbours' E rows staged per row
+constexpr int AS_CAP = 2048;   // at most this many doubles of A~ staged per row (deg * NB^2)
+constexpr int MATCH_NB = 1024; // (column, neighbour) matches cached per row
+constexpr int ECOL_CAP = 1024; // column indices of the neighbours' E rows staged per row
 constexpr int DEG_CAP = 32;    // neighbours whose E column lists are staged
-// (LDS per workgroup within 32 KB: five workgroups per CU, as the registers allow)
+// LDS and registers sized for eight waves per SIMD with blocks of up to 8x8:
+// the staging buffer of A~ is sized at launch from the level's largest block
+// row (a 7-point stencil's 7 blocks of 8x8: 3.5 KB), the rest is 8.3 KB; 62
+// VGPRs.  128^3 setup 53.6 -> 50.6 ms against five waves (92 VGPRs, 32 KB).
 
+// as_n: doubles of the dynamic LDS buffer that stages A~ (a row is staged
+// when deg * NB^2 <= as_n).
 template <int NB>
-__global__ __launch_bounds__(WG) void k_rowprod_nb(const int32_t *__restrict__ list,
-                                                   const int32_t *__restrict__ abptr,
-                                                   const int32_t *__restrict__ abcol,
-                                                   const double *__restrict__ abval,
-                                                   const int32_t *__restrict__ eptr, const int32_t *__restrict__ ecol,
-                                                   const double *__restrict__ eval, const int32_t *__restrict__ mptr,
-                                                   const int32_t *__restrict__ mcol, double *__restrict__ mval) {
+__global__ __launch_bounds__(WG, NB <= 8 ? 6 : 1) void k_rowprod_nb(const int32_t *__restrict__ list,
+                                                                    const int32_t *__restrict__ abptr,
+                                                                    const int32_t *__restrict__ abcol,
+                                                                    const double *__restrict__ abval,
+                                                                    const int32_t *__restrict__ eptr,
+                                                                    const int32_t *__restrict__ ecol,
+                                                                    const double *__restrict__ eval,
+                                                                    const int32_t *__restrict__ mptr,
+                                                                    const int32_t *__restrict__ mcol,
+                                                                    double *__restrict__ mval, int as_n) {
     constexpr int NB2 = NB * NB;
     __shared__ int32_t match[MATCH_NB];
-    __shared__ __align__(16) double As[AS_CAP];
+    extern __shared__ __align__(16) double As[];
     // consecutive rows on one XCD: the E_j rows gathered by a row are gathered
     // again by its neighbours, which then find them in that XCD's L2 (with the
     // hardware's round-robin order neighbours ran on different XCDs; the
@@ -486,7 +494,7 @@ __global__ __launch_bounds__(WG) void k_rowprod_nb(const int32_t *__restrict__ l
     const int alo = abptr[i], deg = abptr[i + 1] - alo;
     const int mlo = mptr[li], k = mptr[li + 1] - mlo;
     const bool cached = (int64_t)k * deg <= MATCH_NB;   // uniform per workgroup
-    const bool staged = deg * NB2 <= AS_CAP;
+    const bool staged = deg * NB2 <= as_n;
     // staged blocks are stored transposed (column u of A~_ij contiguous), so one
     // 16-byte LDS read feeds two rows of the product
     if (staged)
@@ -2664,13 +2672,16 @@ void greedy_colouring(Ctx &c, Level &L, const BPattern &ap) {
         if (v < 0) fail(CS_EINVAL, "greedy colouring needs more than 64 colours");
 }
 
-// register-blocked M = A~ E for the common block sizes; false: use k_rowprod
+// register-blocked M = A~ E for the common block sizes; false: use k_rowprod.
+// maxdeg: the most blocks in a block row of A~ (sizes the staging buffer).
 bool rowprod_nb(hipStream_t s, int nb, int nl, const int32_t *list, const BPattern &ap, const double *abval,
-                const EMat &E, const BPattern &mp, double *mval) {
+                const EMat &E, const BPattern &mp, double *mval, int maxdeg) {
     auto go = [&](auto nbc) {
         constexpr int NB = decltype(nbc)::value;
-        hipLaunchKernelGGL((k_rowprod_nb<NB>), dim3(nl), dim3(WG), 0, s, list, ap.ptr.get(), ap.col.get(), abval,
-                           E.pat.ptr.get(), E.pat.col.get(), E.val.get(), mp.ptr.get(), mp.col.get(), mval);
+        const int as_n = (int)std::min<int64_t>((int64_t)std::max(maxdeg, 0) * NB * NB, AS_CAP);
+        hipLaunchKernelGGL((k_rowprod_nb<NB>), dim3(nl), dim3(WG), (size_t)as_n * sizeof(double), s, list,
+                           ap.ptr.get(), ap.col.get(), abval, E.pat.ptr.get(), E.pat.col.get(), E.val.get(),
+                           mp.ptr.get(), mp.col.get(), mval, as_n);
         return true;
     };
     switch (nb) {
@@ -2909,7 +2920,7 @@ void fit_level(Ctx &c, Level &L, const cs_options &o) {
                 hipLaunchKernelGGL(k_rowprod_point, dim3((unsigned)ceil_div(nl, WG / 64)), dim3(WG), 0, s, nl,
                                    dlist, ap.ptr.get(), ap.col.get(), abval.get(), E.pat.ptr.get(),
                                    E.pat.col.get(), E.val.get(), mp.ptr.get(), mp.col.get(), mval.get());
-            else if (!rowprod_nb(s, nb, nl, dlist, ap, abval.get(), E, mp, mval.get()))
+            else if (!rowprod_nb(s, nb, nl, dlist, ap, abval.get(), E, mp, mval.get(), maxdeg))
                 hipLaunchKernelGGL(k_rowprod, dim3(nl), dim3(WG), 0, s, dlist, nb, ap.ptr.get(), ap.col.get(),
                                    abval.get(), E.pat.ptr.get(), E.pat.col.get(), E.val.get(), mp.ptr.get(),
                                    mp.col.get(), mval.get());
