@@ -980,15 +980,24 @@ __global__ __launch_bounds__(WG) void k_gram_mfma(const int32_t *__restrict__ li
 constexpr int QCAP8 = 256;
 constexpr int ECAP8 = 128;   // E_i column lists staged per row in k_gram_mfma8
 
-__global__ __launch_bounds__(WG) void k_gram_mfma8(int nl, const int32_t *__restrict__ list,
+__global__ __launch_bounds__(WG, 8) void k_gram_mfma8(int nl, const int32_t *__restrict__ list,
                                                    const int32_t *__restrict__ mptr, const int32_t *__restrict__ mcol,
                                                    const double *__restrict__ mval, const int32_t *__restrict__ eptr,
                                                    const int32_t *__restrict__ ecol, const double *__restrict__ eval,
                                                    double *__restrict__ lamt, int32_t *__restrict__ redo,
                                                    int32_t *__restrict__ redo_list, double ridge) {
     constexpr int NB = 8, NB2 = 64, W2 = 2 * NB, ROWS = 2 * (WG / 64);
-    __shared__ double Gs[ROWS][NB2], Hs[ROWS][NB2], Aug[ROWS][NB * W2];
-    __shared__ int32_t qpos[ROWS][QCAP8];
+    // one LDS buffer for the two phases: the positions and E_i's column lists
+    // while the products run, then G, H and [G + tau I | I] (16 KB instead of
+    // 28 KB: more workgroups per CU)
+    constexpr size_t P1 = sizeof(int32_t) * ROWS * (QCAP8 + ECAP8);
+    constexpr size_t P2 = sizeof(double) * ROWS * (2 * NB2 + NB * W2);
+    __shared__ __align__(16) unsigned char lds[P1 > P2 ? P1 : P2];
+    int32_t(*qpos)[QCAP8] = reinterpret_cast<int32_t(*)[QCAP8]>(lds);
+    int32_t(*ecs8)[ECAP8] = reinterpret_cast<int32_t(*)[ECAP8]>(lds + sizeof(int32_t) * ROWS * QCAP8);
+    double(*Gs)[NB2] = reinterpret_cast<double(*)[NB2]>(lds);
+    double(*Hs)[NB2] = Gs + ROWS;
+    double(*Aug)[NB * W2] = reinterpret_cast<double(*)[NB * W2]>(lds + sizeof(double) * ROWS * 2 * NB2);
     __shared__ int32_t rmlo[ROWS], rk[ROWS], relo[ROWS], rek[ROWS];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int r16 = lane & 15, cq = lane >> 4, half = r16 >> 3, rr = r16 & 7;
@@ -1012,7 +1021,6 @@ __global__ __launch_bounds__(WG) void k_gram_mfma8(int nl, const int32_t *__rest
     // The positions of M_i's block columns in E_i, for the eight rows at once:
     // E_i's column lists are staged in LDS with coalesced reads, so the
     // searches run in LDS instead of as chains of dependent global loads.
-    __shared__ int32_t ecs8[ROWS][ECAP8];
     __shared__ int32_t qoff[ROWS + 1];
     for (int e = t; e < ROWS * ECAP8; e += WG) {
         const int sr = e / ECAP8, q = e % ECAP8;
@@ -1043,10 +1051,11 @@ __global__ __launch_bounds__(WG) void k_gram_mfma8(int nl, const int32_t *__rest
     d4_t dg = {0.0, 0.0, 0.0, 0.0}, dh = {0.0, 0.0, 0.0, 0.0};
     // PB block columns per pass: their M and E loads are all issued before the
     // first product (one memory round trip per pass instead of per column); the
-    // products run in column order as one at a time would.  Four (72 VGPRs, and
-    // with 256 positions per row 29 KB of LDS: five waves per SIMD) measured
-    // faster than eight (104 VGPRs, four waves): 128^3 setup 54.8 -> 54.1 ms
-    constexpr int PB = 4;
+    // products run in column order as one at a time would.  Two columns, with
+    // the accumulators in ordinary registers (56 VGPRs) and the two-phase LDS
+    // (16.5 KB), run eight waves per SIMD; on the 128^3 setup that measured
+    // faster than four columns at five waves (51.1 -> 50.1 ms) and eight at four
+    constexpr int PB = 2;
     for (int p0 = 0; p0 < kmax; p0 += PB) {
         double am0[PB], am1[PB], ae0[PB], ae1[PB];
 #pragma unroll
@@ -1074,6 +1083,7 @@ __global__ __launch_bounds__(WG) void k_gram_mfma8(int nl, const int32_t *__rest
             dh = __builtin_amdgcn_mfma_f64_16x16x4f64(ae1[u], am1[u], dh, 0, 0, 0);
         }
     }
+    __syncthreads();   // every wave is done with the positions (phase 1 of lds)
     // result lane l, register x = D[4x + l/16][l%16]: this lane's half owns
     // registers 2 half and 2 half + 1 of its own column
     {
