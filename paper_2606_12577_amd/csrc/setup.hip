@@ -469,9 +469,11 @@ constexpr int DEG_CAP = 32;    // neighbours whose E column lists are staged
 // VGPRs.  128^3 setup 53.6 -> 50.6 ms against five waves (92 VGPRs, 32 KB).
 
 // as_n: doubles of the dynamic LDS buffer that stages A~ (a row is staged
-// when deg * NB^2 <= as_n).
-template <int NB>
-__global__ __launch_bounds__(WG, NB <= 8 ? 6 : 1) void k_rowprod_nb(const int32_t *__restrict__ list,
+// when deg * NB^2 <= as_n).  WGS: threads per row (one workgroup per row); 64
+// for the early steps whose short rows leave most of 256 threads idle (the
+// match and column tables shrink with it, so four times the rows run per CU).
+template <int NB, int WGS = WG>
+__global__ __launch_bounds__(WGS, NB <= 8 ? 6 * (WG / WGS) : 1) void k_rowprod_nb(const int32_t *__restrict__ list,
                                                                     const int32_t *__restrict__ abptr,
                                                                     const int32_t *__restrict__ abcol,
                                                                     const double *__restrict__ abval,
@@ -482,7 +484,8 @@ __global__ __launch_bounds__(WG, NB <= 8 ? 6 : 1) void k_rowprod_nb(const int32_
                                                                     const int32_t *__restrict__ mcol,
                                                                     double *__restrict__ mval, int as_n) {
     constexpr int NB2 = NB * NB;
-    __shared__ int32_t match[MATCH_NB];
+    constexpr int MATCH_W = MATCH_NB * WGS / WG, ECOL_W = ECOL_CAP * WGS / WG;
+    __shared__ int32_t match[MATCH_W];
     extern __shared__ __align__(16) double As[];
     // consecutive rows on one XCD: the E_j rows gathered by a row are gathered
     // again by its neighbours, which then find them in that XCD's L2 (with the
@@ -493,19 +496,19 @@ __global__ __launch_bounds__(WG, NB <= 8 ? 6 : 1) void k_rowprod_nb(const int32_
     const int t = threadIdx.x;
     const int alo = abptr[i], deg = abptr[i + 1] - alo;
     const int mlo = mptr[li], k = mptr[li + 1] - mlo;
-    const bool cached = (int64_t)k * deg <= MATCH_NB;   // uniform per workgroup
+    const bool cached = (int64_t)k * deg <= MATCH_W;   // uniform per workgroup
     const bool staged = deg * NB2 <= as_n;
     // staged blocks are stored transposed (column u of A~_ij contiguous), so one
     // 16-byte LDS read feeds two rows of the product
     if (staged)
-        for (int e = t; e < deg * NB2; e += WG) {
+        for (int e = t; e < deg * NB2; e += WGS) {
             const int jj = e / NB2, rs = e % NB2;
             As[jj * NB2 + (rs % NB) * NB + rs / NB] = abval[(int64_t)alo * NB2 + e];
         }
     // The neighbours' E column lists, concatenated in LDS with one coalesced
     // read, so that the k * deg searches of the matches run in LDS instead of
     // as chains of dependent global loads (the same positions either way).
-    __shared__ int32_t ecs[ECOL_CAP];
+    __shared__ int32_t ecs[ECOL_W];
     __shared__ int32_t eoff[DEG_CAP + 1], elo_s[DEG_CAP];
     bool ecols = false;   // uniform
     if (cached && deg <= DEG_CAP) {
@@ -520,9 +523,9 @@ __global__ __launch_bounds__(WG, NB <= 8 ? 6 : 1) void k_rowprod_nb(const int32_
             for (int jj = 0; jj < deg; ++jj) eoff[jj + 1] += eoff[jj];
         __syncthreads();
         const int tot = eoff[deg];
-        ecols = tot <= ECOL_CAP;
+        ecols = tot <= ECOL_W;
         if (ecols)
-            for (int e = t; e < tot; e += WG) {
+            for (int e = t; e < tot; e += WGS) {
                 int jj = 0;
                 while (eoff[jj + 1] <= e) ++jj;
                 ecs[e] = ecol[elo_s[jj] + e - eoff[jj]];
@@ -530,7 +533,7 @@ __global__ __launch_bounds__(WG, NB <= 8 ? 6 : 1) void k_rowprod_nb(const int32_
         __syncthreads();
     }
     if (cached)
-        for (int e = t; e < k * deg; e += WG) {
+        for (int e = t; e < k * deg; e += WGS) {
             const int p = e / deg, jj = e % deg;
             if (ecols) {
                 const int r = bsearch_i32(ecs, eoff[jj], eoff[jj + 1], mcol[mlo + p]);
@@ -544,7 +547,7 @@ __global__ __launch_bounds__(WG, NB <= 8 ? 6 : 1) void k_rowprod_nb(const int32_
     if constexpr (NB % 2 == 0) {
         if (staged) {   // two adjacent columns of M per thread (same summation order per entry)
             constexpr int NH = NB / 2;
-            for (int w = t; w < k * NH; w += WG) {
+            for (int w = t; w < k * NH; w += WGS) {
                 const int p = w / NH, c2 = (w % NH) * 2;
                 double a0[NB], a1[NB];
 #pragma unroll
@@ -590,7 +593,7 @@ __global__ __launch_bounds__(WG, NB <= 8 ? 6 : 1) void k_rowprod_nb(const int32_
             return;
         }
     }
-    for (int w = t; w < k * NB; w += WG) {
+    for (int w = t; w < k * NB; w += WGS) {
         const int p = w / NB, sc = w % NB;
         double acc[NB];
 #pragma unroll
@@ -2689,6 +2692,18 @@ bool rowprod_nb(hipStream_t s, int nb, int nl, const int32_t *list, const BPatte
     auto go = [&](auto nbc) {
         constexpr int NB = decltype(nbc)::value;
         const int as_n = (int)std::min<int64_t>((int64_t)std::max(maxdeg, 0) * NB * NB, AS_CAP);
+        // one wavefront per row while the average row needs at most two of its
+        // passes (the first cascade steps: 7 and 25 blocks per row on a 7-point
+        // stencil; 128^3 setup 50.1 -> 49.6 ms)
+        const int64_t items = (nl > 0 ? mp.nnzb / nl : 0) * (NB % 2 == 0 ? NB / 2 : NB);
+        if constexpr (NB <= 8) {
+            if (items <= 128) {
+                hipLaunchKernelGGL((k_rowprod_nb<NB, 64>), dim3(nl), dim3(64), (size_t)as_n * sizeof(double), s,
+                                   list, ap.ptr.get(), ap.col.get(), abval, E.pat.ptr.get(), E.pat.col.get(),
+                                   E.val.get(), mp.ptr.get(), mp.col.get(), mval, as_n);
+                return true;
+            }
+        }
         hipLaunchKernelGGL((k_rowprod_nb<NB>), dim3(nl), dim3(WG), (size_t)as_n * sizeof(double), s, list,
                            ap.ptr.get(), ap.col.get(), abval, E.pat.ptr.get(), E.pat.col.get(), E.val.get(),
                            mp.ptr.get(), mp.col.get(), mval, as_n);
