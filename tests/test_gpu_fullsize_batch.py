@@ -90,3 +90,27 @@ def test_batch_fullsize_solve(full):
     _, hist = O.fcg(p.levels[0].A, lambda r: O.vcycle(p.levels, sm, r, "RF", 1, 1), p.rhs, 1e-10, 300)
     pos = int(np.flatnonzero(np.asarray(bt.order) == q)[0])   # stats are in the stacked order
     assert abs(int(its[pos]) - (len(hist) - 1)) <= 1, (its[pos], len(hist) - 1)
+
+
+def test_batch_fullsize_refinement_fp32_vs_fp64(full, gpu_lib):
+    """The configured outer loop: FP64 refinement around the FP32 V-cycle brings
+    every system to 1e-10, in the V-cycles the plain FP64 V-cycle needs on the
+    same systems (the stationary iteration's rate is the V-cycle's convergence
+    factor, so equal counts mean equal factors up to the last step; the
+    slowest system, rho ~ 0.98, needs about 1,100)."""
+    probs, bt, s = full
+    _, info = s.solve(bt.rhs, rtol=1e-10, maxit=2000, method="ir")
+    its32, rels32 = s.system_stats()
+    s64 = gpu_lib.Solver(bt.levels)
+    s64.setup(depth=DEPTH, precision="fp64")
+    s64.set_systems(bt.sys_ptr)
+    _, info64 = s64.solve(bt.rhs, rtol=1e-10, maxit=2000, method="ir")
+    its64, rels64 = s64.system_stats()
+    s64.close()
+    print(f"[fullsize-batch] refinement: FP32 V-cycle {info['iterations']} (max), {info['solve_ms']:.1f} ms; "
+          f"FP64 V-cycle {info64['iterations']}, {info64['solve_ms']:.1f} ms", flush=True)
+    assert np.all(rels32 <= 1e-10) and np.all(rels64 <= 1e-10)
+    for q in range(len(probs)):
+        d = abs(int(its32[q]) - int(its64[q]))
+        bound = 1 + 0.02 * int(its64[q])
+        assert record(f"batch64 system {q} refinement V-cycles FP32 vs FP64", d, bound) <= 1.0, (q, its32[q], its64[q])

@@ -210,6 +210,46 @@ def test_first_level_closed_form_dirichlet():
     np.testing.assert_allclose(res["lam"][0][inner, 0, 0] * dg[inner], 0.8, rtol=1e-14)
 
 
+@pytest.mark.parametrize("nu", [1, 2])
+def test_depth_one_vcycle_is_the_weighted_jacobi_textbook_vcycle(nu):
+    """Alg. 1 with a depth-1 point cascade is the textbook V-cycle with the
+    weighted Jacobi smoother x <- x + w_i (b - A x)_i, w_i = 1 / sum_j
+    (a_ij^2 / a_jj) (the level-1 closed form above, unscaled; 4/5 of 1/a_ii on
+    interior rows of the 5-point Laplacian, Sec. 3.2): written here in the
+    error-correction form,
+    with dense matrices, restriction r_scale P^T of the residual b - A x,
+    correction x + P e_c and an exact bottom solve, independently of the
+    oracle's setup and of its sign convention."""
+    p = fd.poisson2d(32)
+    lv = p.levels
+
+    def weights(A):
+        C = sp.coo_matrix(A)
+        return 1.0 / np.bincount(C.row, weights=C.data ** 2 / A.diagonal()[C.col], minlength=A.shape[0])
+
+    def textbook(l, b):
+        A = lv[l].A.toarray()
+        if l == len(lv) - 1:
+            return np.linalg.solve(A, b)
+        w = weights(lv[l].A)[:, None]
+        x = np.zeros_like(b)
+        for _ in range(nu):
+            x = x + w * (b - A @ x)
+        P = lv[l].P.toarray()
+        e = textbook(l + 1, lv[l].r_scale * (P.T @ (b - A @ x)))
+        x = x + P @ e
+        for _ in range(nu):
+            x = x + w * (b - A @ x)
+        return x
+
+    b = stream(0, TEST, 19).uniform(-1, 1, size=(p.n, 2))
+    sm = O.setup_hierarchy(lv, 1)
+    want = textbook(0, b)
+    for order in ("RF", "FF"):   # a single point level: forward and reverse coincide
+        got = O.vcycle(lv, sm, b, order, nu, nu)
+        assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max(), order
+
+
 # ---------------------------------------------------------------------------
 # Brute-force Frobenius minimisation on tiny matrices
 # ---------------------------------------------------------------------------
