@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define CS_ABI_VERSION 3
+#define CS_ABI_VERSION 4
 
 typedef struct cs_ctx_s *cs_ctx;
 
@@ -66,6 +66,14 @@ typedef enum { CS_FF = 0, CS_RF = 1 } cs_order;   /* pre-smoother forward / reve
  * dependent directions need the regularised fit (cs_options.ridge) to converge
  * with BF16 blocks. */
 typedef enum { CS_FP64 = 0, CS_FP32 = 1, CS_BF16 = 2 } cs_precision;
+/* Where cs_setup takes the smoother of every level from.  CS_SRC_FROBENIUS:
+ * the cascade fit of Alg. 2 (the paper's method).  CS_SRC_JACOBI: the
+ * reference smoother the cascade is measured against (Sec. 2.1, Sec. 3.2):
+ * every cascade level Lambda_l = jacobi_omega * A_ii^{-1}, i.e. nu damped
+ * block Jacobi steps (additive) or block Gauss-Seidel / SOR steps over the
+ * colours (multiplicative).  The learned source has its own entry point,
+ * cs_setup_learned (cascade_learned.h). */
+typedef enum { CS_SRC_FROBENIUS = 0, CS_SRC_JACOBI = 1 } cs_source;
 
 /* One level of the geometric hierarchy (Sec. 2.4); levels[0] is the finest and
  * the last level is solved directly.  All pointers are host pointers. */
@@ -109,6 +117,8 @@ typedef struct {
      * Exact fits only (cs_setup, the coarse levels of cs_setup_learned); must
      * be 0 for cs_setup_sketched and for levels with overlapping blocks. */
     double ridge;
+    int32_t source;             /* cs_source; cs_setup_sketched and cs_setup_learned take CS_SRC_FROBENIUS only */
+    double jacobi_omega;        /* damping of CS_SRC_JACOBI, in (0, 2]; ignored for the fit */
 } cs_options;
 
 typedef struct {
@@ -119,6 +129,8 @@ typedef struct {
     double solve_ms;            /* device time of this solve */
     int32_t singular_blocks;    /* blocks solved by the pseudo-inverse fallback in the last setup */
     int32_t precision;          /* cs_precision the solve finished in (raised on divergence) */
+    double rho_geo;             /* geometric mean rate (r_K / r_0)^(1/K) over the K iterations */
+    double eta;                 /* iterations per decade of residual reduction, log 0.1 / log rho (Sec. 3.1) */
 } cs_info;
 
 /* Library identity. */

@@ -19,6 +19,7 @@ FP64, FP32, BF16 = 0, 1, 2
 _MODES = {"additive": ADDITIVE, "multiplicative": MULTIPLICATIVE}
 _ORDERS = {"FF": FF, "RF": RF}
 _PRECS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
+_SOURCES = {"frobenius": 0, "jacobi": 1}   # cs_source
 
 STATUS = {0: "CS_OK", -1: "CS_EINVAL", -2: "CS_ENOMEM", -3: "CS_EDEVICE", -4: "CS_ESINGULAR",
           -5: "CS_ECOLOR", -6: "CS_ENOCONV", -7: "CS_ESTATE", -8: "CS_ENAN", -9: "CS_EVERSION",
@@ -46,13 +47,15 @@ class cs_level(ctypes.Structure):
 class cs_options(ctypes.Structure):
     _fields_ = [("depth", ctypes.c_int32), ("mode", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("n_pre", ctypes.c_int32), ("n_post", ctypes.c_int32), ("trunc_alpha", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("ridge", ctypes.c_double)]
+                ("precision", ctypes.c_int32), ("ridge", ctypes.c_double),
+                ("source", ctypes.c_int32), ("jacobi_omega", ctypes.c_double)]
 
 
 class cs_info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("rel_res", ctypes.c_double), ("rho", ctypes.c_double),
                 ("setup_ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
-                ("singular_blocks", ctypes.c_int32), ("precision", ctypes.c_int32)]
+                ("singular_blocks", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("rho_geo", ctypes.c_double), ("eta", ctypes.c_double)]
 
 
 # every symbol declared in include/cascade.h, with its ctypes signature
@@ -287,8 +290,12 @@ class Solver:
         return (fitted, rep) if classes else fitted
 
     def setup(self, depth: int = 3, mode: str = "additive", order: str = "RF", n_pre: int = 1,
-              n_post: int = 1, alpha: int = 0, precision: str = "fp64", ridge: float = 0.0):
-        o = cs_options(depth, _MODES[mode], _ORDERS[order], n_pre, n_post, alpha, _PRECS[precision], ridge)
+              n_post: int = 1, alpha: int = 0, precision: str = "fp64", ridge: float = 0.0,
+              source: str = "frobenius", omega: float = 1.0):
+        """source "frobenius": the cascade fit; "jacobi": every cascade level
+        omega * blockdiag(A)^-1 (the reference smoother)."""
+        o = cs_options(depth, _MODES[mode], _ORDERS[order], n_pre, n_post, alpha, _PRECS[precision], ridge,
+                       _SOURCES[source], omega)
         self.depth = depth
         self._check(self._lib.cs_setup(self._h, ctypes.byref(o)))
 
@@ -398,7 +405,8 @@ class Solver:
         if st != 0 and not (st == -6 and not raise_on_noconv):
             self._check(st)
         k = info.iterations
-        return x, dict(iterations=k, rel_res=info.rel_res, rho=info.rho, setup_ms=info.setup_ms,
+        return x, dict(iterations=k, rel_res=info.rel_res, rho=info.rho, rho_geo=info.rho_geo, eta=info.eta,
+                       setup_ms=info.setup_ms,
                        solve_ms=info.solve_ms, singular_blocks=info.singular_blocks,
                        precision={v: k for k, v in _PRECS.items()}.get(info.precision),
                        history=hist[:k + 1].copy(), status=st)

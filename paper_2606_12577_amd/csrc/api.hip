@@ -190,7 +190,7 @@ unsigned char *device_scratch(int device) {
 }
 
 const uint64_t SAVE_MAGIC = 0x3150555445535343ull;  // "CSSETUP1"
-const int32_t SAVE_VERSION = 3;
+const int32_t SAVE_VERSION = 4;   // 4: cs_options gained source and jacobi_omega
 
 }  // namespace
 
@@ -336,8 +336,14 @@ cs_status cs_setup(cs_ctx ctx, const cs_options *opt) {
         need(opt->precision == CS_FP64 || opt->precision == CS_FP32 || opt->precision == CS_BF16,
              "precision must be FP64, FP32 or BF16");
         need(opt->ridge >= 0.0 && opt->ridge < 1e6, "ridge must be in [0, 1e6)");
+        need(opt->source == CS_SRC_FROBENIUS || opt->source == CS_SRC_JACOBI, "source must be FROBENIUS or JACOBI");
         bool ovl = false;
         for (const Level &L : c.lv) ovl |= L.ovl_m > 0;
+        if (opt->source == CS_SRC_JACOBI) {
+            need(opt->jacobi_omega > 0.0 && opt->jacobi_omega <= 2.0, "jacobi_omega must be in (0, 2]");
+            need(!ovl, "the block Jacobi reference smoother takes disjoint blocks");
+            need(opt->trunc_alpha == 0 && opt->ridge == 0.0, "truncation and ridge apply to the fit only");
+        }
         need(!ovl || (opt->mode == CS_ADDITIVE && opt->order == CS_FF && opt->trunc_alpha == 0),
              "overlapping blocks take additive cascades applied forward (FF), without truncation");
         need(!ovl || opt->ridge == 0.0, "the regularised fit does not apply to overlapping blocks");
@@ -361,6 +367,7 @@ cs_status cs_setup_sketched(cs_ctx ctx, const cs_options *opt, int32_t s, const 
         need(opt->n_pre >= 1 && opt->n_post >= 0, "need n_pre >= 1 and n_post >= 0");
         need(opt->trunc_alpha == 0, "truncation applies to the exact fit only");
         need(opt->ridge == 0.0, "the regularised fit applies to the exact fit only");
+        need(opt->source == CS_SRC_FROBENIUS, "the sketched construction is a Frobenius fit");
         int64_t nbmax = 1;
         for (const Level &L : c.lv) nbmax = std::max<int64_t>(nbmax, L.nb);
         // with s <= n the first level fits every sketch column exactly: T_1 = 0
@@ -390,6 +397,7 @@ cs_status cs_setup_learned(cs_ctx ctx, const cs_options *opt, cs_mlp mlp, const 
         need(opt != nullptr && mlp != nullptr && X != nullptr, "options, network or features missing");
         need(opt->depth >= 1 && opt->depth <= 16, "depth must be in [1, 16]");
         need(opt->mode == CS_ADDITIVE, "the learned setup fits additive cascades");
+        need(opt->source == CS_SRC_FROBENIUS, "the learned setup's coarse levels are Frobenius fits");
         need(opt->ridge >= 0.0 && opt->ridge < 1e6, "ridge must be in [0, 1e6)");
         need(opt->order == CS_FF || opt->order == CS_RF, "order must be FF or RF");
         need(opt->n_pre >= 1 && opt->n_post >= 0, "need n_pre >= 1 and n_post >= 0");

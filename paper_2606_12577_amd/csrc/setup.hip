@@ -1937,6 +1937,89 @@ __global__ void k_ecount(int B, const int32_t *__restrict__ pos, const int32_t *
     cnt[i] = q >= 0 ? mptr[q + 1] - mptr[q] : eptr[i + 1] - eptr[i];
 }
 
+// Reference smoother of Sec. 2.1 (damped block Jacobi; block Gauss-Seidel in
+// multiplicative mode): Lambda_l = omega A_ii^{-1} for every cascade level l.
+// One wavefront per block (four per workgroup): [A_ii | I] in LDS, gathered
+// from the scalar CSR rows of the block, then Gauss-Jordan elimination with
+// partial pivoting (the row of the largest |a_rk| at or below the pivot, the
+// first on ties); the right half ends as the inverse.  A zero or non-finite
+// pivot flags the block (bad[i] = 1, its Lambda zero).  Blocks at or beyond
+// B_act (rows solved directly) get zero Lambda and are not checked.
+__global__ __launch_bounds__(WG) void k_block_jacobi(int64_t B, int64_t B_act, int nb, int depth, double omega,
+                                                     const int32_t *__restrict__ a_ptr,
+                                                     const int32_t *__restrict__ a_col,
+                                                     const double *__restrict__ a_val, double *__restrict__ lam,
+                                                     int32_t *__restrict__ bad) {
+    __shared__ double m[WG / 64][MAXNB * 2 * MAXNB];
+    __shared__ double fac[WG / 64][MAXNB];
+    __shared__ int piv[WG / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t i = (int64_t)blockIdx.x * (WG / 64) + wv;
+    const bool act = i < B_act;   // uniform per wavefront; inactive ones still reach every barrier
+    const int w2 = 2 * nb;
+    double *a = m[wv];
+    for (int e = lane; e < nb * w2; e += 64) {
+        const int r = e / w2, q = e % w2;
+        a[e] = (q - nb == r) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    if (act && lane < nb) {
+        const int64_t row = i * nb + lane;
+        for (int e = a_ptr[row]; e < a_ptr[row + 1]; ++e) {
+            const int64_t cj = (int64_t)a_col[e] - i * nb;
+            if (cj >= 0 && cj < nb) a[lane * w2 + cj] += a_val[e];
+        }
+    }
+    __syncthreads();
+    bool ok = act;
+    for (int k = 0; k < nb; ++k) {
+        if (lane == 0) {
+            int p = k;
+            double best = fabs(a[k * w2 + k]);
+            for (int r = k + 1; r < nb; ++r) {
+                const double v = fabs(a[r * w2 + k]);
+                if (v > best) {
+                    best = v;
+                    p = r;
+                }
+            }
+            piv[wv] = p;
+        }
+        __syncthreads();
+        const int p = piv[wv];
+        const double pv = a[p * w2 + k];
+        ok = ok && pv != 0.0 && isfinite(pv);
+        const double inv = (pv != 0.0 && isfinite(pv)) ? 1.0 / pv : 0.0;
+        double tk = 0.0, tp = 0.0;
+        if (lane < w2) {   // swap rows k and p, scale the pivot row
+            tk = a[k * w2 + lane];
+            tp = a[p * w2 + lane];
+        }
+        __syncthreads();
+        if (lane < w2) {
+            a[p * w2 + lane] = tk;
+            a[k * w2 + lane] = tp * inv;
+        }
+        __syncthreads();
+        if (lane < nb) fac[wv][lane] = a[lane * w2 + k];
+        __syncthreads();
+        for (int e = lane; e < nb * w2; e += 64) {
+            const int r = e / w2, q = e % w2;
+            if (r != k) a[e] -= fac[wv][r] * a[k * w2 + q];
+        }
+        __syncthreads();
+    }
+    if (i < B) {
+        if (act && !ok && lane == 0) bad[i] = 1;
+        const int64_t nb2 = (int64_t)nb * nb;
+        for (int e = lane; e < nb * nb; e += 64) {
+            const int r = e / nb, q = e % nb;
+            const double v = (act && ok) ? omega * a[r * w2 + nb + q] : 0.0;
+            for (int ell = 0; ell < depth; ++ell) lam[((int64_t)ell * B + i) * nb2 + e] = v;
+        }
+    }
+}
+
 __global__ void k_unscale(int64_t B, int nb, const double *__restrict__ w, const double *__restrict__ lamt,
                           double *__restrict__ lam) {
     int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -3372,11 +3455,37 @@ void build_working_copies(Ctx &c) {
     CS_HIP(hipStreamSynchronize(c.stream));
 }
 
+// Every cascade level of L is omega A_ii^{-1} (cs_options.source =
+// CS_SRC_JACOBI): no fit; the prescaling, colouring and layouts as for a fit.
+void jacobi_level(Ctx &c, Level &L, const cs_options &o) {
+    hipStream_t s = c.stream;
+    BPattern ap;
+    FitLists fl;
+    prepare_level(c, L, o, false, ap, fl);
+    L.patterns.clear();
+    L.lat_fitted.clear();
+    L.lat_rep.release();
+    L.singular = 0;
+    L.depth = o.depth;
+    const int64_t B = L.B, B_act = L.n_active / L.nb;
+    L.lam64.alloc((size_t)o.depth * B * L.nb * L.nb);
+    DBuf<int32_t> bad(std::max<int64_t>(B, 1));
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(std::max<int64_t>(B, 1))), dim3(WG), 0, s, bad.get(),
+                       std::max<int64_t>(B, 1), 0);
+    hipLaunchKernelGGL(k_block_jacobi, dim3((unsigned)((B + WG / 64 - 1) / (WG / 64))), dim3(WG), 0, s, B, B_act,
+                       (int)L.nb, o.depth, o.jacobi_omega, L.a_ptr.get(), L.a_col.get(), L.a_val.get(),
+                       L.lam64.get(), bad.get());
+    CS_LAUNCH_CHECK();
+    if (reduce_i32(c, bad.get(), std::max<int64_t>(B, 1), false))
+        fail(CS_ESINGULAR, "block Jacobi: a diagonal block of A is singular");
+}
+
 void run_setup(Ctx &c, const cs_options &o) {
     CS_HIP(hipEventRecord(c.ev0, c.stream));
     c.singular = 0;
     for (size_t l = 0; l + 1 < c.lv.size(); ++l) {
-        fit_level(c, c.lv[l], o);
+        if (o.source == CS_SRC_JACOBI) jacobi_level(c, c.lv[l], o);
+        else fit_level(c, c.lv[l], o);
         c.singular += c.lv[l].singular;
     }
     for (Level &L : c.lv) factor_direct(c, L);

@@ -2251,6 +2251,9 @@ struct Monitor {
             rho = hist[1] / hist[0];
         }
         info->rho = rho;
+        // geometric mean rate over the whole history, and eta of the regression rate
+        info->rho_geo = K >= 1 ? std::pow(hist[K] / hist[0], 1.0 / K) : NAN;
+        info->eta = std::log(0.1) / std::log(rho);
     }
 };
 

@@ -38,7 +38,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_identity_and_status_strings(lib):
-    assert lib.cs_abi_version() == 3
+    assert lib.cs_abi_version() == 4
     assert lib.cs_status_string(0) == b"ok"
     assert lib.cs_status_string(-5) == b"improper colouring"
     assert lib.cs_status_string(12345) == b"unknown status"
