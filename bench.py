@@ -721,6 +721,26 @@ def main():
             fitted_fraction_per_step=[[round(f / n, 4) for f in fl] for fl, n in zip(fitted, nblk)])
         for l in range(len(nblk)):
             s.set_lattice(l, None)
+    # the reference smoother (Sec. 2.1, 3.2): depth-many damped block Jacobi
+    # steps, Lambda_l = omega A_ii^-1, same V-cycle, precision and outer loops;
+    # omega from a small sweep under CG, the best then also under refinement
+    jac = {}
+    for w in (0.7, 0.8, 0.9, 1.0):
+        s.setup(**dict(opts, source="jacobi", omega=w))
+        i = [s.solve(b, rtol=args.rtol, maxit=500, method="cg", raise_on_noconv=False)[1] for _ in range(2)][-1]
+        jac[w] = i
+    wbest = min(jac, key=lambda w: jac[w]["solve_ms"] if jac[w]["rel_res"] <= args.rtol else float("inf"))
+    s.setup(**dict(opts, source="jacobi", omega=wbest))
+    ji = [s.solve(b, rtol=args.rtol, maxit=2000, method="ir", raise_on_noconv=False)[1] for _ in range(2)][-1]
+    extra["block_jacobi_reference"] = dict(
+        omega=wbest,
+        cg={str(w): dict(solve_ms=round(i["solve_ms"], 3), iterations=i["iterations"], rho=round(i["rho"], 4),
+                         eta=round(i["eta"], 3), rel_res=i["rel_res"]) for w, i in jac.items()},
+        ir=dict(solve_ms=round(ji["solve_ms"], 3), iterations=ji["iterations"], rho=round(ji["rho"], 4),
+                eta=round(ji["eta"], 3), rel_res=ji["rel_res"]),
+        cascade_speedup=dict(
+            ir=round(ji["solve_ms"] / runs[(args.precision, "ir")]["solve_ms"], 3),
+            cg=round(jac[wbest]["solve_ms"] / runs[(args.precision, "cg")]["solve_ms"], 3)))
     if args.copy_mib:
         nel = args.copy_mib * 1024 * 1024 // 4
         src = torch.ones(nel, device=dev, dtype=torch.float32)
