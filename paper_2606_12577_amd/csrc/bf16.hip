@@ -49,16 +49,15 @@ __device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
-// acc = sum over the blocks [e0, e1) of a row of A_ij x_j (rows 4 kg .. 4 kg + 3).
+// acc + sum over the blocks [e0, e1) of a row of A_ij x_j (rows 4 kg .. 4 kg + 3).
 // Blocks are taken four at a time: their block and x loads are all issued
 // before the first MFMA (a wavefront then waits once per four blocks instead
 // of once per block); the products are summed in block order.
 __device__ __forceinline__ f32x4 block_row_product(int e0, int e1, int lane, const int32_t *__restrict__ bcol,
                                                    const unsigned short *__restrict__ aval,
-                                                   const float *__restrict__ x) {
+                                                   const float *__restrict__ x, f32x4 acc) {
     constexpr int CH = 4;
     const int kg = lane >> 4;
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
     for (int e = e0; e < e1; e += CH) {
         bf16x4 a[CH];
         float4 xv[CH];
@@ -84,13 +83,47 @@ __device__ __forceinline__ f32x4 block_row_product(int e0, int e1, int lane, con
     return acc;
 }
 
+// The row's first META_COLS blocks, whose block columns the row record holds:
+// their block and x loads all go out at once, before the first MFMA; the
+// products are summed in block order, as block_row_product does.
+constexpr int META_COLS = 5;
+__device__ __forceinline__ f32x4 block_row_head(int e0, int ne, const int (&col)[META_COLS], int lane,
+                                                const unsigned short *__restrict__ aval,
+                                                const float *__restrict__ x) {
+    const int kg = lane >> 4;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    bf16x4 a[META_COLS];
+    float4 xv[META_COLS];
+#pragma unroll
+    for (int c = 0; c < META_COLS; ++c) {
+        if (c < ne) {   // uniform per wavefront
+            a[c] = *reinterpret_cast<const bf16x4 *>(aval + (int64_t)(e0 + c) * 256 + lane * 4);
+            xv[c] = *reinterpret_cast<const float4 *>(x + (int64_t)col[c] * 16 + kg * 4);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < META_COLS; ++c) {
+        if (c < ne) {
+            const float v[4] = {xv[c].x, xv[c].y, xv[c].z, xv[c].w};
+            bf16x4 hi, lo;
+            split(v, hi, lo);
+            acc = mfma(a[c], hi, acc);
+            acc = mfma(a[c], lo, acc);
+        }
+    }
+    return acc;
+}
+
 // Multiplicative cascade step on one colour's nblk active block rows:
 // x_i <- x_i - Lambda_i (sum_j A_ij x_j - b_i), in place; ZERO: x = 0 before
 // the step, so x_i = Lambda_i b_i.  One wavefront per block row, read from a
-// 16-byte record {row, first block, end block} (one load where the colour
-// list and the block-row pointers were two dependent ones: 16.1 -> 15.6 us
-// per finest-level colour of the 256^2 SIPG problem; two rows per wavefront
-// with their loads interleaved measured 22 us).
+// 32-byte record {row, first block, end block, c0 | c1, c2, c3, c4} that also
+// holds the block columns of the row's first five blocks (the rest come from
+// bcol): the x gathers of a row then wait on one load instead of two
+// dependent ones.  (The 16-byte record without the columns replaced the
+// colour list and the block-row pointers: 16.1 -> 15.6 us per finest-level
+// colour of the 256^2 SIPG problem; two rows per wavefront with their loads
+// interleaved measured 22 us.)
 template <bool ZERO>
 __global__ __launch_bounds__(WG) void k_bsr16_sweep(int64_t nblk, const int4 *__restrict__ meta,
                                                     const int32_t *__restrict__ bcol,
@@ -100,13 +133,20 @@ __global__ __launch_bounds__(WG) void k_bsr16_sweep(int64_t nblk, const int4 *__
     const int lane = threadIdx.x & 63, kg = lane >> 4;
     const int64_t w = (int64_t)blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
     if (w >= nblk) return;   // whole wavefront
-    const int4 m = meta[w];
+    const int4 m = meta[2 * w];
+    const int4 m2 = meta[2 * w + 1];
     const int i = m.x;
     // b and Lambda_i do not depend on the product: their loads go out first
     const float4 bv = *reinterpret_cast<const float4 *>(b + (int64_t)i * 16 + kg * 4);
     const bf16x4 l = *reinterpret_cast<const bf16x4 *>(lam + (int64_t)i * 256 + lane * 4);
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    if constexpr (!ZERO) acc = block_row_product(m.y, m.z, lane, bcol, aval, x);
+    if constexpr (!ZERO) {
+        const int col[META_COLS] = {m.w, m2.x, m2.y, m2.z, m2.w};
+        const int ne = m.z - m.y;
+        acc = block_row_head(m.y, ne < META_COLS ? ne : META_COLS, col, lane, aval, x);
+        if (ne > META_COLS)   // uniform per wavefront
+            acc = block_row_product(m.y + META_COLS, m.z, lane, bcol, aval, x, acc);
+    }
     const float r[4] = {acc[0] - bv.x, acc[1] - bv.y, acc[2] - bv.z, acc[3] - bv.w};
     bf16x4 hi, lo;
     split(r, hi, lo);
@@ -200,13 +240,19 @@ void build_bf16_level(Ctx &c, Level &L) {
 void build_bf16_meta(Ctx &c, Level &L, const std::vector<int32_t> &act) {
     L.bmeta.release();
     if (L.nb != 16 || L.h_bsr_ptr.empty() || act.empty()) return;
-    std::vector<int32_t> m(4 * act.size());
+    // per row {row, first block, end block, c0 | c1, c2, c3, c4}: the block
+    // columns of the row's first META_COLS blocks, -1 where the row is shorter
+    std::vector<int32_t> cols(L.bsr_nnzb);
+    L.bsr_col.download(cols.data(), cols.size(), c.stream);
+    CS_HIP(hipStreamSynchronize(c.stream));
+    std::vector<int32_t> m(8 * act.size());
     for (size_t q = 0; q < act.size(); ++q) {
         const int32_t i = act[q];
-        m[4 * q] = i;
-        m[4 * q + 1] = L.h_bsr_ptr[i];
-        m[4 * q + 2] = L.h_bsr_ptr[i + 1];
-        m[4 * q + 3] = 0;
+        const int32_t e0 = L.h_bsr_ptr[i], e1 = L.h_bsr_ptr[i + 1];
+        m[8 * q] = i;
+        m[8 * q + 1] = e0;
+        m[8 * q + 2] = e1;
+        for (int k = 0; k < META_COLS; ++k) m[8 * q + 3 + k] = e0 + k < e1 ? cols[e0 + k] : -1;
     }
     L.bmeta.upload(m.data(), m.size(), c.stream);
     CS_HIP(hipStreamSynchronize(c.stream));   // the host vector goes out of scope
@@ -246,7 +292,7 @@ void bf16_sweep(Ctx &c, const Level &L, int ell, int colour, bool reverse, bool 
     (void)trace_begin_launch(c, zero ? CS_TRACE_SWEEP_ZERO : (L.n >= (1 << 19) ? CS_TRACE_SWEEP
                                                                                : CS_TRACE_SWEEP_SMALL),
                              bf16_sweep_bytes(L, colour, zero), &ev0, &ev1);
-    const int4 *meta = reinterpret_cast<const int4 *>(L.bmeta.get()) + k0;
+    const int4 *meta = reinterpret_cast<const int4 *>(L.bmeta.get()) + 2 * k0;   // two int4 per row
     if (zero)
         hipExtLaunchKernelGGL(k_bsr16_sweep<true>, dim3(gdim(nblk, WG / 64)), dim3(WG), 0, c.stream, ev0, ev1, 0,
                               nblk, meta, L.bsr_col.get(), L.a16.get(), lam, b, x);
