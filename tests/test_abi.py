@@ -66,3 +66,32 @@ def test_library_is_gfx950_only():
     path = os.path.join(ROOT, "paper_2606_12577_amd", "libcascade.so")
     data = open(path, "rb").read()
     assert b"gfx950" in data
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes structures of the binding have the C layout of the header:
+    a host program compiled from include/cascade.h prints size and field
+    offsets of cs_level, cs_options and cs_info (gcc, no GPU)."""
+    import shutil
+    import subprocess
+    from paper_2606_12577_amd import cascade
+    cc = shutil.which("gcc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {name: getattr(cascade, name) for name in ("cs_level", "cs_options", "cs_info")}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "cascade.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for name, cls in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert got[(name, field)] == getattr(cls, field).offset, (name, field)
