@@ -130,7 +130,7 @@ typedef struct {
     int32_t singular_blocks;    /* blocks solved by the pseudo-inverse fallback in the last setup */
     int32_t precision;          /* cs_precision the solve finished in (raised on divergence) */
     double rho_geo;             /* geometric mean rate (r_K / r_0)^(1/K) over the K iterations */
-    double eta;                 /* iterations per decade of residual reduction, log 0.1 / log rho (Sec. 3.1) */
+    double eta;                 /* iterations per decade of residual reduction, log 0.1 / log rho (Sec. 3.1); +inf for rho >= 1 */
 } cs_info;
 
 /* Library identity. */

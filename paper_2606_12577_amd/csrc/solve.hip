@@ -2253,7 +2253,8 @@ struct Monitor {
         info->rho = rho;
         // geometric mean rate over the whole history, and eta of the regression rate
         info->rho_geo = K >= 1 ? std::pow(hist[K] / hist[0], 1.0 / K) : NAN;
-        info->eta = std::log(0.1) / std::log(rho);
+        // no decade is ever reached at rho >= 1: eta is infinite there
+        info->eta = (rho > 0.0 && rho < 1.0) ? std::log(0.1) / std::log(rho) : (rho >= 1.0 ? INFINITY : NAN);
     }
 };
 
