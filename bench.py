@@ -557,6 +557,8 @@ def main():
                     help="print the per-kernel time inside the setups of a rocprofv3 kernel trace and exit")
     ap.add_argument("--summarize", nargs="+", metavar="CSV",
                     help="print a markdown summary of rocprofv3 kernel-trace or counter CSVs and exit")
+    ap.add_argument("--summarize-top", type=int, default=40, metavar="N",
+                    help="rows (kernel, grid and counter groups) kept by --summarize")
     args = ap.parse_args()
     if args.summarize_setups:
         print(summarize_setups(args.summarize_setups))
@@ -564,7 +566,7 @@ def main():
     if args.summarize:
         for path in args.summarize:
             print(f"### {os.path.basename(os.path.dirname(path))}/{os.path.basename(path)}\n")
-            print(summarize_rocprof(path))
+            print(summarize_rocprof(path, top=args.summarize_top))
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
