@@ -250,6 +250,26 @@ def test_depth_one_vcycle_is_the_weighted_jacobi_textbook_vcycle(nu):
         assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max(), order
 
 
+def test_jacobi_reference_smoother():
+    """The reference smoother of Sec. 3.2: every level omega A_ii^-1.  Its blocks
+    times the diagonal blocks of a non-symmetric A give omega I (a transposed or
+    undamped inverse fails), and with point blocks on the periodic 5-point
+    Laplacian and omega = 4/5 it is the depth-1 cascade fit (Table 1), reached by
+    the least-squares route instead of the inverse."""
+    n, B = 3, 7
+    A = random_block_matrix(B, n, 5, symmetric=False)
+    sm = O.jacobi_smoother(sp.csr_matrix(A), n, 2, omega=0.7)
+    assert len(sm["lam"]) == 2 and sm["colours"] is None
+    for L in sm["lam"]:
+        for i in range(B):
+            Aii = A[i * n:(i + 1) * n, i * n:(i + 1) * n]
+            np.testing.assert_allclose(L[i] @ Aii, 0.7 * np.eye(n), atol=1e-13)
+    P = fd.periodic_laplacian(12, 2)
+    fit = O.fit_additive(P, 1, 1)["lam"][0]
+    jac = O.jacobi_smoother(P, 1, 1, omega=0.8)["lam"][0]
+    np.testing.assert_allclose(jac, fit, rtol=1e-13)
+
+
 # ---------------------------------------------------------------------------
 # Brute-force Frobenius minimisation on tiny matrices
 # ---------------------------------------------------------------------------
