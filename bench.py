@@ -743,6 +743,12 @@ def main():
         cascade_speedup=dict(
             ir=round(ji["solve_ms"] / runs[(args.precision, "ir")]["solve_ms"], 3),
             cg=round(jac[wbest]["solve_ms"] / runs[(args.precision, "cg")]["solve_ms"], 3)))
+    # the paper's work model of the stationary iteration (Sec. 3.1), in 3D:
+    # C_3 = eta (1 + (2 nu + 1) / (1 - 2^-3)), nu cascade steps or Jacobi steps alike
+    def work(eta):
+        return round(eta * (1.0 + (2 * args.depth + 1) / (1.0 - 2.0 ** -3)), 3)
+    extra["block_jacobi_reference"]["work_model_c3"] = dict(
+        cascade=work(runs[(args.precision, "ir")]["eta"]), block_jacobi=work(ji["eta"]))
     if args.copy_mib:
         nel = args.copy_mib * 1024 * 1024 // 4
         src = torch.ones(nel, device=dev, dtype=torch.float32)
@@ -798,6 +804,7 @@ def main():
         "setup_plus_solve_dof_per_s": dof / ((solve_ms + setup_ms) * 1e-3),
         "iterations": last["iterations"],
         "rho": round(last["rho"], 4),
+        "eta": round(last["eta"], 3),
         "rel_res": last["rel_res"],
         "roofline": roofline,
         "cpu_baseline": cpu,
